@@ -1,0 +1,171 @@
+"""p-multigrid V(1,1) cycle and preconditioned CG (oracle; test infrastructure).
+
+Sec. 4.3 (eq. asm-afw: coarse space V_{h,1}, A_0 the form rediscretised at p=1,
+R_0 the restriction), Sec. 5 (hybrid multigrid/Schwarz: additive within a level,
+multiplicative across levels in a V(1,1) cycle; CG from a zero guess).
+
+Readings of the paper (it fixes none of these):
+  * prolongation: the natural embedding V_{h,1} in V_{h,p} written in FDM DoFs
+    (per P-axis the (p+1)x2 matrix of the linear hats; per DP-axis r_0 -> r_0);
+    restriction is its transpose;
+  * smoothing: one damped step z += omega M^{-1} (r - A z) before and after the
+    coarse correction, omega = 2 / (0.1 lam + 1.1 lam) with lam an estimate of
+    the largest eigenvalue of M^{-1} A (first-degree Chebyshev on [0.1, 1.1] lam);
+  * stop when the 2-norm of the residual drops by the relative tolerance (1e-8),
+    the true residual b - A x being checked at exit;
+  * Dirichlet rows act as the identity.
+"""
+import numpy as np
+import scipy.linalg
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .tables1d import Element1D, p1_embedding
+from .lattice import Lattice
+
+
+def prolongation(lat_f: Lattice, lat_c: Lattice):
+    """Sparse (ndofs_f x ndofs_c) embedding of the p=1 space in the degree-p space;
+    rows and columns of Dirichlet DoFs are zero."""
+    assert lat_c.p == 1 and lat_f.space == lat_c.space
+    el = Element1D(lat_f.p)
+    E = p1_embedding(el)
+    ED = np.zeros((lat_f.p, 1))
+    ED[0, 0] = 1.0
+    cdf = lat_f.cell_dofs()
+    cdc = lat_c.cell_dofs()
+    owner = -np.ones(lat_f.ndofs, dtype=np.int64)
+    for k in range(cdf.shape[0]):
+        new = owner[cdf[k]] < 0
+        owner[cdf[k][new]] = k
+    rows, cols, vals = [], [], []
+    nloc_f = [int(np.prod(lat_f.local_shape(m))) for m in range(len(lat_f.kinds))]
+    nloc_c = [int(np.prod(lat_c.local_shape(m))) for m in range(len(lat_c.kinds))]
+    of = np.cumsum([0] + nloc_f)
+    oc = np.cumsum([0] + nloc_c)
+    for m, kind in enumerate(lat_f.kinds):
+        mats = [E if k == "P" else ED for k in kind]
+        Pm = np.kron(mats[2], np.kron(mats[1], mats[0]))       # local fine x local coarse
+        r_, c_ = np.nonzero(np.abs(Pm) > 0)
+        for k in range(cdf.shape[0]):
+            gf = cdf[k, of[m] + r_]
+            sel = owner[gf] == k
+            rows.append(gf[sel])
+            cols.append(cdc[k, oc[m] + c_[sel]])
+            vals.append(Pm[r_[sel], c_[sel]])
+    Pr = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                       shape=(lat_f.ndofs, lat_c.ndofs))
+    kf = sp.diags((~lat_f.dirichlet_mask()).astype(np.float64))
+    kc = sp.diags((~lat_c.dirichlet_mask()).astype(np.float64))
+    return sp.csr_matrix(kf @ Pr @ kc)
+
+
+class CoarseSolver:
+    """A_0^{-1} on the free coarse DoFs by Cholesky (dense or sparse LU)."""
+
+    def __init__(self, lat_c: Lattice, A0):
+        self.free = np.where(~lat_c.dirichlet_mask())[0]
+        A0f = sp.csr_matrix(A0)[self.free][:, self.free]
+        self.n = lat_c.ndofs
+        if self.free.size <= 4000:
+            self.chol = scipy.linalg.cho_factor(A0f.toarray(), lower=True)
+            self.lu = None
+        else:
+            self.chol = None
+            self.lu = spla.splu(sp.csc_matrix(A0f))
+
+    def solve(self, r):
+        out = np.zeros(self.n)
+        rf = r[self.free]
+        out[self.free] = scipy.linalg.cho_solve(self.chol, rf) if self.chol is not None else self.lu.solve(rf)
+        return out
+
+
+class VCycle:
+    """Hybrid V(1,1): z = w M r; z += P A0^{-1} P^T (r - A z); z += w M (r - A z)."""
+
+    def __init__(self, lat: Lattice, A, relax, Pr, coarse, omega):
+        self.A = sp.csr_matrix(A)
+        self.relax = relax
+        self.Pr = Pr
+        self.coarse = coarse
+        self.omega = omega
+        self.dmask = lat.dirichlet_mask()
+
+    def __call__(self, r):
+        r = np.where(self.dmask, 0.0, r)
+        w = self.omega
+        z = w * np.where(self.dmask, 0.0, self.relax.apply(r))
+        r1 = r - self.A @ z
+        r1[self.dmask] = 0.0
+        z = z + self.Pr @ self.coarse.solve(self.Pr.T @ r1)
+        r2 = r - self.A @ z
+        r2[self.dmask] = 0.0
+        z = z + w * np.where(self.dmask, 0.0, self.relax.apply(r2))
+        return z
+
+
+def lanczos_lambda_max(A, Minv, v0, steps=10):
+    """Largest eigenvalue of M^{-1} A estimated from ``steps`` preconditioned CG
+    iterations on A x = v0 (Lanczos tridiagonal from the CG coefficients)."""
+    x = np.zeros_like(v0)
+    r = v0.copy()
+    z = Minv(r)
+    p = z.copy()
+    rz = r @ z
+    alphas, betas = [], []
+    for _ in range(steps):
+        Ap = A @ p
+        a = rz / (p @ Ap)
+        x += a * p
+        r -= a * Ap
+        z = Minv(r)
+        rz_new = r @ z
+        b = rz_new / rz
+        alphas.append(a)
+        betas.append(b)
+        rz = rz_new
+        p = z + b * p
+    k = len(alphas)
+    T = np.zeros((k, k))
+    for j in range(k):
+        T[j, j] = 1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0)
+        if j + 1 < k:
+            T[j, j + 1] = T[j + 1, j] = np.sqrt(betas[j]) / alphas[j]
+    return float(np.linalg.eigvalsh(T).max())
+
+
+def omega_from_lambda(lam):
+    return 2.0 / (0.1 * lam + 1.1 * lam)
+
+
+def pcg(A, b, M, rtol=1e-8, maxit=500):
+    """Preconditioned CG from x0 = 0.  Returns x, iterations, residual 2-norm history."""
+    A = sp.csr_matrix(A)
+    x = np.zeros_like(b)
+    r = b.copy()
+    nb = np.linalg.norm(b)
+    hist = [np.linalg.norm(r)]
+    if nb == 0:
+        return x, 0, hist
+    z = M(r)
+    p = z.copy()
+    rz = r @ z
+    it = 0
+    while it < maxit:
+        Ap = A @ p
+        a = rz / (p @ Ap)
+        x += a * p
+        r -= a * Ap
+        it += 1
+        hist.append(np.linalg.norm(r))
+        if hist[-1] <= rtol * nb:
+            rtrue = b - A @ x
+            if np.linalg.norm(rtrue) <= rtol * nb:
+                break
+            r = rtrue
+        z = M(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, it, hist
