@@ -1,0 +1,182 @@
+/*
+ * rz.h -- C ABI of the MI355X library for the p-multigrid solvers of the Riesz
+ * maps of the L2 de Rham complex (Brubeck & Farrell, "Multigrid solvers for the
+ * de Rham complex with optimal complexity in polynomial degree").
+ *
+ * Problem (Sec. 1, eqs. hgrad/hcurl/hdiv; Sec. 2.1, eq. common_weak_formulation):
+ *   find u_h in V^k_{h,p} with a^k(v,u) = (v, beta u) + (d^k v, alpha d^k u) = F(v)
+ *   for k = 0 (H(grad), Q_p), 1 (H(curl), NCE_p), 2 (H(div), NCF_p) on a structured
+ *   nx*ny*nz hexahedral mesh, homogeneous Dirichlet traces on the faces selected
+ *   by a bit mask.
+ *
+ * Degrees of freedom are coefficients in the FDM bases of Sec. 2.2-2.4 and sit on
+ * a lattice (x fastest).  Q_p: index X + Nx*(Y + Ny*Z), Nx = nx*p + 1.  NCE_p /
+ * NCF_p: three component blocks one after the other; component m has extent
+ * n_a*p along its broken (DP) axes and n_a*p+1 along its continuous axes.
+ * Vectors hold every lattice DoF; Dirichlet rows act as the identity (outputs copy
+ * the input there, inputs there are read as zero elsewhere).
+ *
+ * Ownership: the caller owns every vector (device pointers, e.g. the data of a
+ * torch tensor on the library's device).  The library owns tables, factors and
+ * workspace, all allocated in rz_setup and released by rz_free.  Host arrays
+ * passed to rz_setup are copied before it returns.
+ *
+ * Ordering / synchronisation: calls are stream-ordered on the stream given to
+ * rz_create (NULL = the legacy default stream).  rz_setup, rz_solve and
+ * rz_export return after the device work they need has finished.
+ *
+ * Errors: every call returns an rz_status; rz_last_error(ctx) gives a message.
+ * Nothing throws across this boundary.  One host thread per context at a time.
+ */
+#ifndef RZ_H
+#define RZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rz_ctx rz_ctx;
+typedef struct rz_problem rz_problem;
+
+typedef enum { RZ_GRAD = 0, RZ_CURL = 1, RZ_DIV = 2 } rz_space;
+
+typedef enum {
+  RZ_OK = 0,
+  RZ_ERR_ARG = -1,           /* invalid argument or unsupported combination     */
+  RZ_ERR_OOM = -2,           /* device or host allocation failed                */
+  RZ_ERR_BREAKDOWN = -3,     /* incomplete Cholesky pivot <= 0, or CG p.Ap <= 0  */
+  RZ_ERR_NOT_CONVERGED = -4, /* maxit reached before the tolerance              */
+  RZ_ERR_HIP = -5,           /* a HIP runtime call failed                        */
+  RZ_ERR_SINGULAR = -6,      /* coarse factorisation met a non-positive pivot   */
+  RZ_ERR_NODEVICE = -7       /* compute call on a host-only context             */
+} rz_status;
+
+typedef enum { RZ_F64 = 0, RZ_F32 = 1 } rz_dtype;
+
+/* Mesh: structured nx*ny*nz hexahedra.  vertex_xyz: host array of
+ * (nx+1)(ny+1)(nz+1) points (x,y,z), vertex vx + (nx+1)*(vy + (ny+1)*vz);
+ * NULL = uniform mesh of the unit cube.  dirichlet_faces: bit 0 x=0, 1 x=1,
+ * 2 y=0, 3 y=1, 4 z=0, 5 z=1 (0x3F = whole boundary). */
+typedef struct {
+  int32_t nx, ny, nz;
+  const double *vertex_xyz;
+  uint32_t dirichlet_faces;
+} rz_mesh;
+
+/* Coefficients alpha, beta > 0 of a^k.  RZ_COEF_CONST: alpha[0], beta[0].
+ * RZ_COEF_CELL: one value per cell (cells cx + nx*(cy + ny*cz)), constant on the
+ * cell.  Host arrays. */
+enum { RZ_COEF_CONST = 0, RZ_COEF_CELL = 1 };
+typedef struct {
+  int32_t kind;
+  const double *alpha;
+  const double *beta;
+} rz_coef;
+
+/* Precision protocols of the solve. */
+enum {
+  RZ_PREC_F64 = 0,   /* FP64 apply, relaxation, coarse solve and Krylov            */
+  RZ_PREC_MIXED = 1  /* FP64 apply/coarse/Krylov, FP32 relaxation, flexible CG     */
+};
+
+typedef struct {
+  int32_t space;       /* rz_space                                                  */
+  int32_t p;           /* polynomial degree, 1 <= p <= 12                           */
+  int32_t precision;   /* RZ_PREC_*                                                 */
+  int32_t maxit;       /* CG iteration cap (default 200)                            */
+  double rtol;         /* relative tolerance on the 2-norm residual (default 1e-8)   */
+  double omega;        /* smoother damping; 0 = 2/(1.2*lambda_max) with lambda_max  *
+                        * estimated by 10 Lanczos steps on M^{-1}A                   */
+  uint64_t lanczos_seed; /* SplitMix64 seed of the Lanczos start vector (default 99) */
+} rz_opts;
+
+/* Results of rz_solve. */
+typedef struct {
+  int32_t iters;          /* CG iterations                                            */
+  int32_t status;         /* rz_status of the solve                                   */
+  double rel_res;         /* true ||b - A x||_2 / ||b||_2 at exit                     */
+  double omega;           /* smoother damping that was used                           */
+  double t_solve_ms;      /* device time of the solve (hipEvents on the stream)       */
+} rz_solve_info;
+
+/* Fill *o with defaults (space grad, p = 4, FP64, maxit 200, rtol 1e-8, omega 0). */
+void rz_opts_default(rz_opts *o);
+
+/* Create a context on HIP device `device` and stream `stream` (a hipStream_t, may
+ * be NULL).  device = -1 creates a host-only context: rz_setup then builds only
+ * the host-side data (numbering, 1-D tables, patch layout, IC pattern) for
+ * rz_export, and every compute call returns RZ_ERR_NODEVICE. */
+rz_status rz_create(rz_ctx **ctx, int device, void *stream);
+rz_status rz_destroy(rz_ctx *ctx);
+const char *rz_last_error(const rz_ctx *ctx);
+
+/* Build everything a solve needs (Sec. 3.2 auxiliary operator, Sec. 4.4 static
+ * condensation, Sec. 4.5 incomplete Cholesky of every vertex-star interface
+ * patch on the static-condensation pattern, the p=1 coarse problem of eq.
+ * asm-afw and its factorisation).  Requires a Cartesian mesh (axis-aligned
+ * boxes).  Returns RZ_ERR_BREAKDOWN if an IC pivot is not positive and
+ * RZ_ERR_SINGULAR if the coarse factorisation fails. */
+rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *coef,
+                   const rz_opts *opts, rz_problem **out);
+rz_status rz_free(rz_problem *h);
+
+/* sizes[0] lattice DoFs, [1] free DoFs, [2] cells, [3] vertex-patch slots,
+ * [4] coarse (p=1) lattice DoFs, [5] nonzeros of one patch factor (lower),
+ * [6] rows of one patch, [7] non-empty patches. */
+rz_status rz_sizes(const rz_problem *h, int64_t sizes[8]);
+
+/* y = A x (eq. sum-factorization: matrix-free, per-cell tensor contractions).
+ * x, y: device arrays of sizes[0] elements of type t; x and y must not overlap. */
+rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t);
+
+/* z = M^{-1} r, one application of the statically condensed additive Schwarz
+ * relaxation on the auxiliary operator (eqs. schur, sc-asm-afw): cell-interior
+ * solves, vertex-star interface patch solves with the IC factors, harmonic
+ * extension.  Device arrays of type t (RZ_F32 uses FP32 factors). */
+rz_status rz_relax(rz_problem *h, const void *r, void *z, rz_dtype t);
+
+/* Transfers between the degree-p lattice and the p=1 lattice (sizes[4]):
+ * xf += P xc (prolongation, the embedding V_{h,1} in V_{h,p}) and rc = P^T rf.
+ * FP64 device arrays; Dirichlet entries of the output are zero (prolong adds 0). */
+rz_status rz_prolong_add(rz_problem *h, const double *xc, double *xf);
+rz_status rz_restrict(rz_problem *h, const double *rf, double *rc);
+
+/* xc = A_0^{-1} rc on the free p=1 DoFs (FP64 block-tridiagonal LDL^T); Dirichlet
+ * entries of xc are zero. */
+rz_status rz_coarse_solve(rz_problem *h, const double *rc, double *xc);
+
+/* z = V(r): hybrid V(1,1) cycle (damped relaxation, coarse correction, damped
+ * relaxation), FP64 device arrays. */
+rz_status rz_vcycle(rz_problem *h, const double *r, double *z);
+
+/* Solve A x = b by CG preconditioned with the V-cycle from x = 0, until the true
+ * ||b - A x||_2 <= rtol ||b||_2.  b, x: FP64 device arrays of sizes[0].  info may
+ * be NULL.  Returns RZ_ERR_NOT_CONVERGED if maxit is reached (x holds the last
+ * iterate). */
+rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *info);
+
+/* Export host copies of setup products for parity checks.  If buf is NULL, *bytes
+ * receives the size needed.  what:
+ *   RZ_EXPORT_DOFMAP     int64 (ncells, ncell_dofs) cell -> lattice index
+ *   RZ_EXPORT_PATCH      int64 lattice indices of non-empty patch `index`
+ *                        (in patch order), preceded by its vertex id
+ *   RZ_EXPORT_IC_PATTERN int32 pairs (row, col), row >= col, of non-empty patch
+ *                        `index` in patch-local numbering, row-major order
+ *   RZ_EXPORT_IC_FACTOR  double values matching RZ_EXPORT_IC_PATTERN (FP64 factor)
+ *   RZ_EXPORT_TABLES1D   double: lambda (p-1), B (p+1)^2, A (p+1)^2, D p*(p+1),
+ *                        E (p+1)*2 (p=1 embedding), all row-major
+ *   RZ_EXPORT_AUXCOEF    double (ncells, 6) separable auxiliary weights
+ *   RZ_EXPORT_OMEGA      double: the smoother damping of rz_vcycle / rz_solve   */
+enum {
+  RZ_EXPORT_DOFMAP = 0, RZ_EXPORT_PATCH = 1, RZ_EXPORT_IC_PATTERN = 2,
+  RZ_EXPORT_IC_FACTOR = 3, RZ_EXPORT_TABLES1D = 4, RZ_EXPORT_AUXCOEF = 5,
+  RZ_EXPORT_OMEGA = 6
+};
+rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RZ_H */

@@ -1,0 +1,88 @@
+// Host-side launchers of the HIP kernels (gfx950).  All launches are
+// asynchronous on the given stream; pointers are device pointers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rz {
+
+// Lattice description passed to kernels by value.
+struct LatDev {
+  int p, nx, ny, nz;   // degree and cells per axis
+  int Nx, Ny, Nz;      // Q_p lattice extents (n*p + 1)
+  unsigned dir;        // Dirichlet face bits
+};
+
+// Symbolic patch data on the device.
+struct PatchDev {
+  int nrows, nnz;
+  int nflev, nblev;
+  const int *off;                  // 3*nrows offsets
+  const int *rowptr, *col;         // lower CSR (diagonal last)
+  const int *erow;                 // row of every CSR entry
+  const int *uptr, *urow, *upos;   // column access of the lower factor
+  const int *flev_ptr, *flev_rows, *blev_ptr, *blev_rows;
+};
+
+// ---- vectors ------------------------------------------------------------------
+void launch_fill(double *y, double v, int64_t n, hipStream_t s);
+void launch_cast_d2f(const double *x, float *y, int64_t n, hipStream_t s);
+void launch_cast_f2d(const float *x, double *y, int64_t n, hipStream_t s);
+// y = a*x + y ; y = x + b*y ; z = x - y
+void launch_axpy(double a, const double *x, double *y, int64_t n, hipStream_t s);
+void launch_xpby(const double *x, double b, double *y, int64_t n, hipStream_t s);
+void launch_sub(const double *x, const double *y, double *z, int64_t n, hipStream_t s);
+void launch_scale_copy(double a, const double *x, double *y, int64_t n, hipStream_t s);
+// Deterministic two-pass dot products: out[k] = <x_k, y_k> for up to 3 pairs.
+void launch_dots(int npairs, const double *const *xs, const double *const *ys, int64_t n,
+                 double *partials, double *out, hipStream_t s);
+int dots_partials_size();
+
+// ---- H(grad) operator and relaxation ----------------------------------------------
+template <typename T>
+void launch_apply_grad(const LatDev &L, const T *coef, const T *B, const T *A, const T *x, T *y,
+                       hipStream_t s);
+template <typename T>
+void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r,
+                          T *rt, hipStream_t s);
+template <typename T>
+void launch_patch_solve(const LatDev &L, const PatchDev &P, const T *factor, const T *rt, T *zbuf,
+                        hipStream_t s);
+template <typename T>
+void launch_expand_grad(const LatDev &L, const PatchDev &P, const T *coef, const T *A,
+                        const T *lam, const T *r, const T *zbuf, T *z, hipStream_t s);
+
+// IC factorisation of every vertex patch (FP64) on the static-condensation
+// pattern; writes the FP64 factor and an FP32 copy; *status = 0 or the first
+// failing patch + 1 (pivot <= 0).
+void launch_patch_factor(const LatDev &L, const PatchDev &P, const double *coef, const double *B,
+                         const double *A, const double *lam, double *f64, float *f32, int *status,
+                         hipStream_t s);
+
+// z_D = r_D on Dirichlet rows of the Q_p lattice (r == nullptr: z_D = 0).
+void launch_dirichlet_copy(const LatDev &L, const double *r, double *z, hipStream_t s);
+
+// ---- p-transfer (Q_1 <-> Q_p) -------------------------------------------------------
+void launch_prolong_add_grad(const LatDev &L, const double *E, const double *xc, double *xf,
+                             hipStream_t s);
+void launch_restrict_grad(const LatDev &L, const double *E, const double *rf, double *rc,
+                          hipStream_t s);
+
+// ---- coarse block-tridiagonal LDL^T ---------------------------------------------------
+// Dense m x m blocks, row-major; C and Ct are m x 9 stencil couplings to the
+// previous / next plane (entry j couples to in-plane offset (j%3-1, j/3-1)).
+void launch_schur_update(int m, int mx, const double *Wprev, const double *C, const double *Akk,
+                         double *Dk, hipStream_t s);
+void launch_sweep_inverse(int m, double *W, double *tmp, int *status, hipStream_t s);
+void launch_coarse_fwd(int m, int mx, const double *W, const double *C, const double *r,
+                       const double *vprev, double *v, hipStream_t s);
+void launch_coarse_bwd(int m, int mx, const double *W, const double *Ct, const double *v,
+                       const double *xnext, double *x, hipStream_t s);
+// gather / scatter between the coarse lattice and the free-box block vector
+void launch_coarse_gather(int nfree, int bx0, int by0, int bz0, int mx, int my, int NX, int NY,
+                          const double *rc, double *blk, hipStream_t s);
+void launch_coarse_scatter(int ncoarse, int bx0, int by0, int bz0, int mx, int my, int mz, int NX,
+                           int NY, const double *blk, double *xc, hipStream_t s);
+
+}  // namespace rz

@@ -1,0 +1,904 @@
+// C ABI (include/rz.h): problem setup on the host and the device, and the
+// stream-ordered compute calls that drive the HIP kernels.
+#include "../../include/rz.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lattice.hpp"
+#include "patch.hpp"
+#include "tables1d.hpp"
+
+struct rz_ctx {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  std::string err;
+};
+
+namespace {
+
+using namespace rz;
+
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct rz_problem {
+  rz_ctx *ctx = nullptr;
+  rz_opts opts{};
+  int p = 0, nx = 0, ny = 0, nz = 0;
+  unsigned dir = 0;
+  int Nx = 0, Ny = 0, Nz = 0;
+  int64_t ndofs = 0, nfree = 0, ncells = 0, nvert = 0, ncoarse = 0;
+  Tables1D t, t1;
+  PatchSymbolic ps;
+  std::vector<double> coef;       // ncells * 6
+  std::vector<int> erow;          // row of every pattern entry
+  std::vector<int64_t> patch_vids;  // non-empty patches (vertex ids)
+  double omega = 0.0;
+  // device
+  LatDev L{};
+  PatchDev P{};
+  std::vector<void *> allocs;
+  double *coef64 = nullptr, *B64 = nullptr, *A64 = nullptr, *lam64 = nullptr, *E64 = nullptr;
+  float *coef32 = nullptr, *B32 = nullptr, *A32 = nullptr, *lam32 = nullptr;
+  double *f64 = nullptr;
+  float *f32 = nullptr;
+  double *rt64 = nullptr, *zb64 = nullptr;
+  float *rt32 = nullptr, *zb32 = nullptr, *r32 = nullptr, *z32 = nullptr;
+  double *vt = nullptr, *vaz = nullptr, *vr = nullptr, *rc = nullptr, *xc = nullptr;
+  // coarse
+  int cm = 0, cmx = 0, cmy = 0, cmz = 0, cbx0 = 0, cby0 = 0, cbz0 = 0, cNX = 0, cNY = 0, cNZ = 0;
+  double *cW = nullptr, *cC = nullptr, *cCt = nullptr, *cr = nullptr, *cv = nullptr, *cx = nullptr;
+  // krylov
+  double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kAp = nullptr, *kro = nullptr;
+  double *partials = nullptr, *dots = nullptr;
+  int *status = nullptr;
+};
+
+namespace {
+
+rz_status fail(rz_ctx *ctx, rz_status st, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+#define HIPCALL(h, expr)                                                                   \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((h)->ctx, RZ_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+rz_status dalloc(rz_problem *h, T **ptr, size_t count) {
+  void *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&p, sizeof(T) * count);
+  if (e != hipSuccess) return fail(h->ctx, RZ_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  h->allocs.push_back(p);
+  *ptr = static_cast<T *>(p);
+  return RZ_OK;
+}
+
+template <typename T>
+rz_status upload(rz_problem *h, T **ptr, const std::vector<T> &v) {
+  rz_status st = dalloc(h, ptr, v.size());
+  if (st != RZ_OK) return st;
+  HIPCALL(h, hipMemcpyAsync(*ptr, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, h->ctx->stream));
+  return RZ_OK;
+}
+
+bool lat_dirichlet_h(const rz_problem *h, int X, int Y, int Z) {
+  return ((h->dir & 1u) && X == 0) || ((h->dir & 2u) && X == h->Nx - 1) || ((h->dir & 4u) && Y == 0) ||
+         ((h->dir & 8u) && Y == h->Ny - 1) || ((h->dir & 16u) && Z == 0) || ((h->dir & 32u) && Z == h->Nz - 1);
+}
+
+bool patch_row_present(const rz_problem *h, int64_t vid, int k, int G[3]) {
+  const int nvx = h->nx + 1, nvy = h->ny + 1;
+  const int V[3] = {(int)(vid % nvx), (int)((vid / nvx) % nvy), (int)(vid / ((int64_t)nvx * nvy))};
+  const int Nd[3] = {h->Nx, h->Ny, h->Nz};
+  for (int d = 0; d < 3; ++d) {
+    G[d] = V[d] * h->p + h->ps.off[3 * k + d];
+    if (G[d] < 0 || G[d] >= Nd[d]) return false;
+  }
+  return !lat_dirichlet_h(h, G[0], G[1], G[2]);
+}
+
+// Entry (r, c) of a patch pattern is kept for slot vid iff some existing cell of the
+// star holds both DoFs and couples them (same rule as the device factorisation).
+bool patch_entry_allowed(const rz_problem *h, int64_t vid, const int Gr[3], const int Gc[3]) {
+  const int nvx = h->nx + 1, nvy = h->ny + 1;
+  const int V[3] = {(int)(vid % nvx), (int)((vid / nvx) % nvy), (int)(vid / ((int64_t)nvx * nvy))};
+  const int nc[3] = {h->nx, h->ny, h->nz};
+  for (int cell = 0; cell < 8; ++cell) {
+    int u[3], w[3];
+    bool in = true;
+    for (int d = 0; d < 3; ++d) {
+      int cc = V[d] - 1 + ((cell >> d) & 1);
+      u[d] = Gr[d] - cc * h->p;
+      w[d] = Gc[d] - cc * h->p;
+      in = in && cc >= 0 && cc < nc[d] && u[d] >= 0 && u[d] <= h->p && w[d] >= 0 && w[d] <= h->p;
+    }
+    if (in && cell_schur_coupled(h->p, u, w)) return true;
+  }
+  return false;
+}
+
+uint64_t splitmix_next(uint64_t &s) {
+  s += 0x9E3779B97F4A7C15ull;
+  uint64_t z = s;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------------------
+// operator pieces on the device
+// ---------------------------------------------------------------------------------------
+rz_status do_apply64(rz_problem *h, const double *x, double *y) {
+  launch_apply_grad<double>(h->L, h->coef64, h->B64, h->A64, x, y, h->ctx->stream);
+  return RZ_OK;
+}
+
+rz_status do_relax64(rz_problem *h, const double *r, double *z) {
+  hipStream_t s = h->ctx->stream;
+  launch_condense_grad<double>(h->L, h->coef64, h->A64, h->lam64, r, h->rt64, s);
+  launch_patch_solve<double>(h->L, h->P, h->f64, h->rt64, h->zb64, s);
+  launch_expand_grad<double>(h->L, h->P, h->coef64, h->A64, h->lam64, r, h->zb64, z, s);
+  return RZ_OK;
+}
+
+rz_status do_relax32(rz_problem *h, const float *r, float *z) {
+  hipStream_t s = h->ctx->stream;
+  launch_condense_grad<float>(h->L, h->coef32, h->A32, h->lam32, r, h->rt32, s);
+  launch_patch_solve<float>(h->L, h->P, h->f32, h->rt32, h->zb32, s);
+  launch_expand_grad<float>(h->L, h->P, h->coef32, h->A32, h->lam32, r, h->zb32, z, s);
+  return RZ_OK;
+}
+
+// fine relaxation on FP64 vectors in the precision of the problem's protocol
+rz_status do_relax_prec(rz_problem *h, const double *r, double *z) {
+  if (h->opts.precision == RZ_PREC_MIXED) {
+    launch_cast_d2f(r, h->r32, h->ndofs, h->ctx->stream);
+    do_relax32(h, h->r32, h->z32);
+    launch_cast_f2d(h->z32, z, h->ndofs, h->ctx->stream);
+    return RZ_OK;
+  }
+  return do_relax64(h, r, z);
+}
+
+rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv) {
+  hipStream_t s = h->ctx->stream;
+  const int m = h->cm, nb = h->cmz;
+  const size_t mm = (size_t)m * m;
+  launch_coarse_gather(m * nb, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cNX, h->cNY, rcv, h->cr, s);
+  for (int k = 0; k < nb; ++k)
+    launch_coarse_fwd(m, h->cmx, h->cW + k * mm, h->cC + (size_t)k * m * 9, h->cr + (size_t)k * m,
+                      k ? h->cv + (size_t)(k - 1) * m : nullptr, h->cv + (size_t)k * m, s);
+  for (int k = nb - 1; k >= 0; --k)
+    launch_coarse_bwd(m, h->cmx, h->cW + k * mm, h->cCt + (size_t)k * m * 9, h->cv + (size_t)k * m,
+                      k < nb - 1 ? h->cx + (size_t)(k + 1) * m : nullptr, h->cx + (size_t)k * m, s);
+  launch_coarse_scatter((int)h->ncoarse, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cmz, h->cNX, h->cNY,
+                        h->cx, xcv, s);
+  return RZ_OK;
+}
+
+rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
+  hipStream_t s = h->ctx->stream;
+  const int64_t n = h->ndofs;
+  const double w = h->omega;
+  do_relax_prec(h, r, h->vt);
+  launch_scale_copy(w, h->vt, z, n, s);            // z = w M r
+  do_apply64(h, z, h->vaz);
+  launch_sub(r, h->vaz, h->vr, n, s);              // r1 = r - A z
+  launch_restrict_grad(h->L, h->E64, h->vr, h->rc, s);
+  do_coarse(h, h->rc, h->xc);
+  launch_prolong_add_grad(h->L, h->E64, h->xc, z, s);   // z += P A0^{-1} P^T r1
+  do_apply64(h, z, h->vaz);
+  launch_sub(r, h->vaz, h->vr, n, s);              // r2 = r - A z
+  do_relax_prec(h, h->vr, h->vt);
+  launch_axpy(w, h->vt, z, n, s);                  // z += w M r2
+  launch_dirichlet_copy(h->L, r, z, s);
+  return RZ_OK;
+}
+
+rz_status dots_host(rz_problem *h, int np, const double *const *xs, const double *const *ys, double *out) {
+  launch_dots(np, xs, ys, h->ndofs, h->partials, h->dots, h->ctx->stream);
+  HIPCALL(h, hipMemcpyAsync(out, h->dots, sizeof(double) * np, hipMemcpyDeviceToHost, h->ctx->stream));
+  HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+  return RZ_OK;
+}
+
+// largest eigenvalue of T (k x k symmetric tridiagonal) by bisection on Sturm counts
+double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b) {
+  const int k = (int)a.size();
+  double lo = 0, hi = 0;
+  for (int i = 0; i < k; ++i) {
+    double r = std::fabs(i > 0 ? b[i - 1] : 0.0) + std::fabs(i + 1 < k ? b[i] : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double d = 1.0;
+    for (int i = 0; i < k; ++i) {
+      d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= k) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// 10 preconditioned CG steps on A x = v0 with M = fine relaxation; Lanczos estimate
+rz_status estimate_lambda(rz_problem *h, double *lam_out) {
+  hipStream_t s = h->ctx->stream;
+  const int64_t n = h->ndofs;
+  std::vector<double> v0(n);
+  uint64_t st = h->opts.lanczos_seed;
+  for (int64_t g = 0; g < n; ++g) {
+    double u = (double)(splitmix_next(st) >> 11) * 0x1.0p-53;
+    int X = g % h->Nx, Y = (g / h->Nx) % h->Ny, Z = g / ((int64_t)h->Nx * h->Ny);
+    v0[g] = lat_dirichlet_h(h, X, Y, Z) ? 0.0 : 2.0 * u - 1.0;
+  }
+  HIPCALL(h, hipMemcpyAsync(h->kr, v0.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  do_relax_prec(h, h->kr, h->kz);
+  HIPCALL(h, hipMemcpyAsync(h->kp, h->kz, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  double rz_;
+  {
+    const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
+    rz_status e = dots_host(h, 1, xs, ys, &rz_);
+    if (e) return e;
+  }
+  std::vector<double> al, be;
+  for (int it = 0; it < 10; ++it) {
+    do_apply64(h, h->kp, h->kAp);
+    double pAp;
+    const double *xs[1] = {h->kp}, *ys[1] = {h->kAp};
+    rz_status e = dots_host(h, 1, xs, ys, &pAp);
+    if (e) return e;
+    if (!(pAp > 0)) break;
+    double a = rz_ / pAp;
+    launch_axpy(-a, h->kAp, h->kr, n, s);
+    do_relax_prec(h, h->kr, h->kz);
+    double rzn;
+    const double *xs2[1] = {h->kr}, *ys2[1] = {h->kz};
+    e = dots_host(h, 1, xs2, ys2, &rzn);
+    if (e) return e;
+    double b = rzn / rz_;
+    al.push_back(a);
+    be.push_back(b);
+    rz_ = rzn;
+    launch_xpby(h->kz, b, h->kp, n, s);
+    if (!(rzn > 0)) break;
+  }
+  const int k = (int)al.size();
+  if (k == 0) return fail(h->ctx, RZ_ERR_BREAKDOWN, "Lanczos estimate failed");
+  std::vector<double> d(k), off(k > 1 ? k - 1 : 1, 0.0);
+  for (int j = 0; j < k; ++j) {
+    d[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j + 1 < k) off[j] = std::sqrt(be[j]) / al[j];
+  }
+  *lam_out = tridiag_max_eig(d, off);
+  return RZ_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// coarse problem: Q_1 rediscretisation with the same per-cell weights; plane-wise
+// block-tridiagonal LDL^T with dense inverse diagonal blocks.
+// ---------------------------------------------------------------------------------------
+rz_status setup_coarse(rz_problem *h) {
+  hipStream_t s = h->ctx->stream;
+  const int NX = h->nx + 1, NY = h->ny + 1, NZ = h->nz + 1;
+  h->cNX = NX;
+  h->cNY = NY;
+  h->cNZ = NZ;
+  h->ncoarse = (int64_t)NX * NY * NZ;
+  int lo[3], hi[3];
+  const int Nd[3] = {NX, NY, NZ};
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = (h->dir & (1u << (2 * d))) ? 1 : 0;
+    hi[d] = (h->dir & (1u << (2 * d + 1))) ? Nd[d] - 2 : Nd[d] - 1;
+    if (hi[d] < lo[d]) return fail(h->ctx, RZ_ERR_ARG, "coarse problem has no free DoF along an axis");
+  }
+  h->cbx0 = lo[0];
+  h->cby0 = lo[1];
+  h->cbz0 = lo[2];
+  h->cmx = hi[0] - lo[0] + 1;
+  h->cmy = hi[1] - lo[1] + 1;
+  h->cmz = hi[2] - lo[2] + 1;
+  const int m = h->cmx * h->cmy, nb = h->cmz;
+  h->cm = m;
+  if (m > 4096) return fail(h->ctx, RZ_ERR_ARG, "coarse plane too large for the dense-block coarse solver");
+  // 27-point stencil of every free coarse DoF from the p=1 cell matrices
+  const Tables1D &t1 = h->t1;
+  auto B1 = [&](int a, int b) { return t1.B[a * 2 + b]; };
+  auto A1 = [&](int a, int b) { return t1.A[a * 2 + b]; };
+  const int64_t nfree = (int64_t)m * nb;
+  std::vector<double> st(nfree * 27, 0.0);
+  for (int64_t c = 0; c < h->ncells; ++c) {
+    int cx = c % h->nx, cy = (c / h->nx) % h->ny, cz = c / ((int64_t)h->nx * h->ny);
+    const double *w = &h->coef[6 * c];
+    for (int i = 0; i < 8; ++i) {
+      int ia[3] = {i & 1, (i >> 1) & 1, i >> 2};
+      int Vi[3] = {cx + ia[0], cy + ia[1], cz + ia[2]};
+      bool fi = true;
+      for (int d = 0; d < 3; ++d) fi = fi && Vi[d] >= lo[d] && Vi[d] <= hi[d];
+      if (!fi) continue;
+      int64_t row = (Vi[0] - lo[0]) + h->cmx * ((Vi[1] - lo[1]) + (int64_t)h->cmy * (Vi[2] - lo[2]));
+      for (int j = 0; j < 8; ++j) {
+        int ja[3] = {j & 1, (j >> 1) & 1, j >> 2};
+        double v = w[0] * A1(ia[0], ja[0]) * B1(ia[1], ja[1]) * B1(ia[2], ja[2]) +
+                   w[1] * B1(ia[0], ja[0]) * A1(ia[1], ja[1]) * B1(ia[2], ja[2]) +
+                   w[2] * B1(ia[0], ja[0]) * B1(ia[1], ja[1]) * A1(ia[2], ja[2]) +
+                   w[3] * B1(ia[0], ja[0]) * B1(ia[1], ja[1]) * B1(ia[2], ja[2]);
+        int off = (ja[0] - ia[0] + 1) + 3 * (ja[1] - ia[1] + 1) + 9 * (ja[2] - ia[2] + 1);
+        st[row * 27 + off] += v;
+      }
+    }
+  }
+  // device blocks
+  rz_status e;
+  if ((e = dalloc(h, &h->cW, (size_t)nb * m * m))) return e;
+  std::vector<double> C((size_t)nb * m * 9, 0.0), Ct((size_t)nb * m * 9, 0.0);
+  for (int k = 0; k < nb; ++k)
+    for (int a = 0; a < m; ++a)
+      for (int j = 0; j < 9; ++j) {
+        C[((size_t)k * m + a) * 9 + j] = k > 0 ? st[((int64_t)k * m + a) * 27 + j] : 0.0;
+        Ct[((size_t)k * m + a) * 9 + j] = k < nb - 1 ? st[((int64_t)k * m + a) * 27 + 18 + j] : 0.0;
+      }
+  if ((e = upload(h, &h->cC, C))) return e;
+  if ((e = upload(h, &h->cCt, Ct))) return e;
+  double *Akk = nullptr, *tmp = nullptr;
+  if ((e = dalloc(h, &Akk, (size_t)m * m))) return e;
+  if ((e = dalloc(h, &tmp, (size_t)m * m))) return e;
+  std::vector<double> Ah((size_t)m * m);
+  for (int k = 0; k < nb; ++k) {
+    std::fill(Ah.begin(), Ah.end(), 0.0);
+    for (int a = 0; a < m; ++a) {
+      int ax = a % h->cmx, ay = a / h->cmx;
+      for (int j = 0; j < 9; ++j) {
+        int bx = ax + j % 3 - 1, by = ay + j / 3 - 1;
+        if (bx < 0 || bx >= h->cmx || by < 0 || by >= h->cmy) continue;
+        Ah[(size_t)a * m + bx + h->cmx * by] = st[((int64_t)k * m + a) * 27 + 9 + j];
+      }
+    }
+    HIPCALL(h, hipMemcpyAsync(Akk, Ah.data(), sizeof(double) * m * m, hipMemcpyHostToDevice, s));
+    double *Wk = h->cW + (size_t)k * m * m;
+    if (k == 0) {
+      HIPCALL(h, hipMemcpyAsync(Wk, Akk, sizeof(double) * m * m, hipMemcpyDeviceToDevice, s));
+    } else {
+      launch_schur_update(m, h->cmx, h->cW + (size_t)(k - 1) * m * m, h->cC + (size_t)k * m * 9, Akk, Wk, s);
+    }
+    launch_sweep_inverse(m, Wk, tmp, h->status, s);
+    HIPCALL(h, hipStreamSynchronize(s));  // Ah is reused for the next plane
+  }
+  int stv = 0;
+  HIPCALL(h, hipMemcpy(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost));
+  if (stv) return fail(h->ctx, RZ_ERR_SINGULAR, "coarse factorisation: non-positive pivot");
+  if ((e = dalloc(h, &h->cr, nfree))) return e;
+  if ((e = dalloc(h, &h->cv, nfree))) return e;
+  if ((e = dalloc(h, &h->cx, nfree))) return e;
+  return RZ_OK;
+}
+
+void release(rz_problem *h) {
+  for (void *p : h->allocs) hipFree(p);
+  h->allocs.clear();
+}
+
+rz_status require_device(const rz_problem *h) {
+  if (!h) return RZ_ERR_ARG;
+  if (h->ctx->device < 0) return fail(h->ctx, RZ_ERR_NODEVICE, "host-only context");
+  return RZ_OK;
+}
+
+}  // namespace
+
+// =========================================================================================
+// public API
+// =========================================================================================
+extern "C" {
+
+void rz_opts_default(rz_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->space = RZ_GRAD;
+  o->p = 4;
+  o->precision = RZ_PREC_F64;
+  o->maxit = 200;
+  o->rtol = 1e-8;
+  o->omega = 0.0;
+  o->lanczos_seed = 99;
+}
+
+rz_status rz_create(rz_ctx **ctx, int device, void *stream) {
+  if (!ctx) return RZ_ERR_ARG;
+  rz_ctx *c = new rz_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (device >= 0) {
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) {
+      delete c;
+      return RZ_ERR_HIP;
+    }
+  }
+  *ctx = c;
+  return RZ_OK;
+}
+
+rz_status rz_destroy(rz_ctx *ctx) {
+  delete ctx;
+  return RZ_OK;
+}
+
+const char *rz_last_error(const rz_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz_opts *opts, rz_problem **out) {
+  if (!ctx || !mesh || !cf || !opts || !out) return RZ_ERR_ARG;
+  *out = nullptr;
+  if (opts->space != RZ_GRAD) return fail(ctx, RZ_ERR_ARG, "only the H(grad) space is available");
+  if (opts->p < 1 || opts->p > 9) return fail(ctx, RZ_ERR_ARG, "p must be in 1..9");
+  if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(ctx, RZ_ERR_ARG, "bad mesh size");
+  if (mesh->dirichlet_faces > 0x3F) return fail(ctx, RZ_ERR_ARG, "bad Dirichlet mask");
+  if (cf->kind != RZ_COEF_CONST && cf->kind != RZ_COEF_CELL) return fail(ctx, RZ_ERR_ARG, "bad coefficient kind");
+  if (!cf->alpha || !cf->beta) return fail(ctx, RZ_ERR_ARG, "missing coefficients");
+  if (opts->precision != RZ_PREC_F64 && opts->precision != RZ_PREC_MIXED)
+    return fail(ctx, RZ_ERR_ARG, "bad precision");
+  rz_problem *h = new rz_problem();
+  h->ctx = ctx;
+  h->opts = *opts;
+  if (h->opts.maxit <= 0) h->opts.maxit = 200;
+  if (!(h->opts.rtol > 0)) h->opts.rtol = 1e-8;
+  const int p = opts->p;
+  h->p = p;
+  h->nx = mesh->nx;
+  h->ny = mesh->ny;
+  h->nz = mesh->nz;
+  h->dir = mesh->dirichlet_faces;
+  h->Nx = h->nx * p + 1;
+  h->Ny = h->ny * p + 1;
+  h->Nz = h->nz * p + 1;
+  h->ndofs = (int64_t)h->Nx * h->Ny * h->Nz;
+  h->ncells = (int64_t)h->nx * h->ny * h->nz;
+  h->nvert = (int64_t)(h->nx + 1) * (h->ny + 1) * (h->nz + 1);
+  // geometry: a tensor grid of axis-aligned boxes
+  const int nvx = h->nx + 1, nvy = h->ny + 1, nvz = h->nz + 1;
+  std::vector<double> gx(nvx), gy(nvy), gz(nvz);
+  for (int i = 0; i < nvx; ++i) gx[i] = (double)i / h->nx;
+  for (int i = 0; i < nvy; ++i) gy[i] = (double)i / h->ny;
+  for (int i = 0; i < nvz; ++i) gz[i] = (double)i / h->nz;
+  if (mesh->vertex_xyz) {
+    const double *v = mesh->vertex_xyz;
+    for (int i = 0; i < nvx; ++i) gx[i] = v[3 * i];
+    for (int i = 0; i < nvy; ++i) gy[i] = v[3 * (i * nvx) + 1];
+    for (int i = 0; i < nvz; ++i) gz[i] = v[3 * (i * nvx * nvy) + 2];
+    for (int64_t k = 0; k < h->nvert; ++k) {
+      int vx = k % nvx, vy = (k / nvx) % nvy, vz = k / ((int64_t)nvx * nvy);
+      if (v[3 * k] != gx[vx] || v[3 * k + 1] != gy[vy] || v[3 * k + 2] != gz[vz]) {
+        delete h;
+        return fail(ctx, RZ_ERR_ARG, "mesh is not Cartesian (axis-aligned boxes required)");
+      }
+    }
+  }
+  h->coef.assign(6 * h->ncells, 0.0);
+  for (int64_t c = 0; c < h->ncells; ++c) {
+    int cx = c % h->nx, cy = (c / h->nx) % h->ny, cz = c / ((int64_t)h->nx * h->ny);
+    double hs[3] = {gx[cx + 1] - gx[cx], gy[cy + 1] - gy[cy], gz[cz + 1] - gz[cz]};
+    if (!(hs[0] > 0 && hs[1] > 0 && hs[2] > 0)) {
+      delete h;
+      return fail(ctx, RZ_ERR_ARG, "cells must have positive extent");
+    }
+    double al = cf->kind == RZ_COEF_CONST ? cf->alpha[0] : cf->alpha[c];
+    double be = cf->kind == RZ_COEF_CONST ? cf->beta[0] : cf->beta[c];
+    if (!(al > 0 && be > 0)) {
+      delete h;
+      return fail(ctx, RZ_ERR_ARG, "alpha and beta must be positive");
+    }
+    double V = hs[0] * hs[1] * hs[2];
+    for (int d = 0; d < 3; ++d) h->coef[6 * c + d] = al * V / (2.0 * hs[d] * hs[d]);
+    for (int d = 0; d < 3; ++d) h->coef[6 * c + 3 + d] = be * V / 8.0;
+  }
+  if (!build_tables1d(p, h->t) || !build_tables1d(1, h->t1)) {
+    delete h;
+    return fail(ctx, RZ_ERR_ARG, "1-D tables failed");
+  }
+  build_patch_symbolic(p, h->ps);
+  h->erow.resize(h->ps.nnz);
+  for (int r = 0; r < h->ps.nrows; ++r)
+    for (int k = h->ps.rowptr[r]; k < h->ps.rowptr[r + 1]; ++k) h->erow[k] = r;
+  // free DoFs and non-empty patches
+  int64_t nd = 0;
+  for (int64_t g = 0; g < h->ndofs; ++g) {
+    int X = g % h->Nx, Y = (g / h->Nx) % h->Ny, Z = g / ((int64_t)h->Nx * h->Ny);
+    nd += lat_dirichlet_h(h, X, Y, Z);
+  }
+  h->nfree = h->ndofs - nd;
+  for (int64_t v = 0; v < h->nvert; ++v) {
+    int G[3];
+    for (int k = 0; k < h->ps.nrows; ++k)
+      if (patch_row_present(h, v, k, G)) {
+        h->patch_vids.push_back(v);
+        break;
+      }
+  }
+  h->L = LatDev{p, h->nx, h->ny, h->nz, h->Nx, h->Ny, h->Nz, h->dir};
+  if (ctx->device < 0) {
+    *out = h;
+    return RZ_OK;
+  }
+  // ---- device data ----------------------------------------------------------------------
+  hipStream_t s = ctx->stream;
+  rz_status e;
+  auto bail = [&](rz_status st) {
+    hipStreamSynchronize(s);
+    release(h);
+    delete h;
+    return st;
+  };
+  const int n1 = p + 1;
+  std::vector<double> lamf(n1, 0.0);
+  for (int i = 1; i < p; ++i) lamf[i] = h->t.lam[i - 1];
+  std::vector<float> c32(h->coef.begin(), h->coef.end()), B32(h->t.B.begin(), h->t.B.end()),
+      A32(h->t.A.begin(), h->t.A.end()), l32(lamf.begin(), lamf.end());
+  if ((e = dalloc(h, &h->status, 1))) return bail(e);
+  if (hipMemsetAsync(h->status, 0, sizeof(int), s) != hipSuccess) return bail(fail(ctx, RZ_ERR_HIP, "memset"));
+  if ((e = upload(h, &h->coef64, h->coef)) || (e = upload(h, &h->B64, h->t.B)) || (e = upload(h, &h->A64, h->t.A)) ||
+      (e = upload(h, &h->lam64, lamf)) || (e = upload(h, &h->E64, h->t.E)) || (e = upload(h, &h->coef32, c32)) ||
+      (e = upload(h, &h->B32, B32)) || (e = upload(h, &h->A32, A32)) || (e = upload(h, &h->lam32, l32)))
+    return bail(e);
+  // symbolic patch arrays
+  const PatchSymbolic &ps = h->ps;
+  std::vector<int> sym;
+  auto push = [&](const std::vector<int> &v) {
+    size_t o = sym.size();
+    sym.insert(sym.end(), v.begin(), v.end());
+    return o;
+  };
+  size_t o_off = push(ps.off), o_rp = push(ps.rowptr), o_col = push(ps.col), o_er = push(h->erow),
+         o_up = push(ps.uptr), o_ur = push(ps.urow), o_upos = push(ps.upos), o_fp = push(ps.flev_ptr),
+         o_fr = push(ps.flev_rows), o_bp = push(ps.blev_ptr), o_br = push(ps.blev_rows);
+  int *dsym = nullptr;
+  if ((e = upload(h, &dsym, sym))) return bail(e);
+  h->P = PatchDev{ps.nrows, ps.nnz, (int)ps.flev_ptr.size() - 1, (int)ps.blev_ptr.size() - 1,
+                  dsym + o_off, dsym + o_rp, dsym + o_col, dsym + o_er, dsym + o_up, dsym + o_ur, dsym + o_upos,
+                  dsym + o_fp, dsym + o_fr, dsym + o_bp, dsym + o_br};
+  const size_t nf = (size_t)h->nvert * ps.nnz, nzb = (size_t)h->nvert * ps.nrows;
+  if ((e = dalloc(h, &h->f64, nf)) || (e = dalloc(h, &h->f32, nf)) || (e = dalloc(h, &h->zb64, nzb)) ||
+      (e = dalloc(h, &h->zb32, nzb)) || (e = dalloc(h, &h->rt64, h->ndofs)) || (e = dalloc(h, &h->rt32, h->ndofs)) ||
+      (e = dalloc(h, &h->r32, h->ndofs)) || (e = dalloc(h, &h->z32, h->ndofs)) || (e = dalloc(h, &h->vt, h->ndofs)) ||
+      (e = dalloc(h, &h->vaz, h->ndofs)) || (e = dalloc(h, &h->vr, h->ndofs)) || (e = dalloc(h, &h->kr, h->ndofs)) ||
+      (e = dalloc(h, &h->kz, h->ndofs)) || (e = dalloc(h, &h->kp, h->ndofs)) || (e = dalloc(h, &h->kAp, h->ndofs)) ||
+      (e = dalloc(h, &h->kro, h->ndofs)) || (e = dalloc(h, &h->partials, dots_partials_size())) ||
+      (e = dalloc(h, &h->dots, 4)))
+    return bail(e);
+  // the workspace of the vertex patches: keep rows of empty slots well defined
+  launch_fill(h->zb64, 0.0, (int64_t)nzb, s);
+  launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, h->f64, h->f32, h->status, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(ctx, RZ_ERR_HIP, "patch factorisation failed"));
+  int stv = 0;
+  if (hipMemcpy(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    return bail(fail(ctx, RZ_ERR_HIP, "status read"));
+  if (stv) {
+    char msg[128];
+    std::snprintf(msg, sizeof msg, "incomplete Cholesky breakdown in vertex patch %d", stv - 1);
+    return bail(fail(ctx, RZ_ERR_BREAKDOWN, msg));
+  }
+  if ((e = dalloc(h, &h->rc, (size_t)(h->nx + 1) * (h->ny + 1) * (h->nz + 1))) ||
+      (e = dalloc(h, &h->xc, (size_t)(h->nx + 1) * (h->ny + 1) * (h->nz + 1))))
+    return bail(e);
+  if ((e = setup_coarse(h))) return bail(e);
+  if (opts->omega > 0) {
+    h->omega = opts->omega;
+  } else {
+    double lam = 0;
+    if ((e = estimate_lambda(h, &lam))) return bail(e);
+    h->omega = 2.0 / (1.2 * lam);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(ctx, RZ_ERR_HIP, "setup failed"));
+  *out = h;
+  return RZ_OK;
+}
+
+rz_status rz_free(rz_problem *h) {
+  if (!h) return RZ_OK;
+  if (h->ctx && h->ctx->device >= 0) hipStreamSynchronize(h->ctx->stream);
+  release(h);
+  delete h;
+  return RZ_OK;
+}
+
+rz_status rz_sizes(const rz_problem *h, int64_t sizes[8]) {
+  if (!h || !sizes) return RZ_ERR_ARG;
+  sizes[0] = h->ndofs;
+  sizes[1] = h->nfree;
+  sizes[2] = h->ncells;
+  sizes[3] = h->nvert;
+  sizes[4] = (int64_t)(h->nx + 1) * (h->ny + 1) * (h->nz + 1);
+  sizes[5] = h->ps.nnz;
+  sizes[6] = h->ps.nrows;
+  sizes[7] = (int64_t)h->patch_vids.size();
+  return RZ_OK;
+}
+
+rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  if (!x || !y || x == y) return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad vectors");
+  if (t == RZ_F64) return do_apply64(h, static_cast<const double *>(x), static_cast<double *>(y));
+  if (t == RZ_F32) {
+    launch_apply_grad<float>(h->L, h->coef32, h->B32, h->A32, static_cast<const float *>(x), static_cast<float *>(y),
+                             h->ctx->stream);
+    return RZ_OK;
+  }
+  return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad dtype");
+}
+
+rz_status rz_relax(rz_problem *h, const void *r, void *z, rz_dtype t) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  if (!r || !z || r == z) return fail(h->ctx, RZ_ERR_ARG, "rz_relax: bad vectors");
+  if (t == RZ_F64) return do_relax64(h, static_cast<const double *>(r), static_cast<double *>(z));
+  if (t == RZ_F32) return do_relax32(h, static_cast<const float *>(r), static_cast<float *>(z));
+  return fail(h->ctx, RZ_ERR_ARG, "rz_relax: bad dtype");
+}
+
+rz_status rz_prolong_add(rz_problem *h, const double *xc, double *xf) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  if (!xc || !xf) return fail(h->ctx, RZ_ERR_ARG, "rz_prolong_add: bad vectors");
+  launch_prolong_add_grad(h->L, h->E64, xc, xf, h->ctx->stream);
+  return RZ_OK;
+}
+
+rz_status rz_restrict(rz_problem *h, const double *rf, double *rcv) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  if (!rf || !rcv) return fail(h->ctx, RZ_ERR_ARG, "rz_restrict: bad vectors");
+  launch_restrict_grad(h->L, h->E64, rf, rcv, h->ctx->stream);
+  return RZ_OK;
+}
+
+rz_status rz_coarse_solve(rz_problem *h, const double *rcv, double *xcv) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  if (!rcv || !xcv || rcv == xcv) return fail(h->ctx, RZ_ERR_ARG, "rz_coarse_solve: bad vectors");
+  return do_coarse(h, rcv, xcv);
+}
+
+rz_status rz_vcycle(rz_problem *h, const double *r, double *z) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  if (!r || !z || r == z) return fail(h->ctx, RZ_ERR_ARG, "rz_vcycle: bad vectors");
+  return do_vcycle(h, r, z);
+}
+
+rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *info) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  if (!b || !x || b == x) return fail(h->ctx, RZ_ERR_ARG, "rz_solve: bad vectors");
+  hipStream_t s = h->ctx->stream;
+  const int64_t n = h->ndofs;
+  const bool flexible = h->opts.precision == RZ_PREC_MIXED;
+  hipEvent_t ev0, ev1;
+  HIPCALL(h, hipEventCreate(&ev0));
+  HIPCALL(h, hipEventCreate(&ev1));
+  HIPCALL(h, hipEventRecord(ev0, s));
+  // r = b with Dirichlet rows zero, x = 0
+  launch_fill(x, 0.0, n, s);
+  launch_scale_copy(1.0, b, h->kr, n, s);
+  launch_dirichlet_copy(h->L, nullptr, h->kr, s);
+  double bb;
+  {
+    const double *xs[1] = {h->kr}, *ys[1] = {h->kr};
+    if ((e = dots_host(h, 1, xs, ys, &bb))) return e;
+  }
+  const double nb = std::sqrt(bb), tol = h->opts.rtol * nb;
+  int it = 0;
+  rz_status result = RZ_OK;
+  double relres = 0.0;
+  if (nb > 0) {
+    do_vcycle(h, h->kr, h->kz);
+    launch_scale_copy(1.0, h->kz, h->kp, n, s);
+    double rz_;
+    {
+      const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
+      if ((e = dots_host(h, 1, xs, ys, &rz_))) return e;
+    }
+    result = RZ_ERR_NOT_CONVERGED;
+    while (it < h->opts.maxit) {
+      do_apply64(h, h->kp, h->kAp);
+      double pAp;
+      {
+        const double *xs[1] = {h->kp}, *ys[1] = {h->kAp};
+        if ((e = dots_host(h, 1, xs, ys, &pAp))) return e;
+      }
+      if (!(pAp > 0)) {
+        result = fail(h->ctx, RZ_ERR_BREAKDOWN, "CG breakdown: p.Ap <= 0");
+        break;
+      }
+      const double a = rz_ / pAp;
+      launch_axpy(a, h->kp, x, n, s);
+      if (flexible) launch_scale_copy(1.0, h->kr, h->kro, n, s);
+      launch_axpy(-a, h->kAp, h->kr, n, s);
+      ++it;
+      double rr;
+      {
+        const double *xs[1] = {h->kr}, *ys[1] = {h->kr};
+        if ((e = dots_host(h, 1, xs, ys, &rr))) return e;
+      }
+      if (std::sqrt(rr) <= tol) {
+        // true residual check
+        do_apply64(h, x, h->vaz);
+        launch_sub(b, h->vaz, h->vr, n, s);
+        launch_dirichlet_copy(h->L, nullptr, h->vr, s);
+        double tr;
+        const double *xs[1] = {h->vr}, *ys[1] = {h->vr};
+        if ((e = dots_host(h, 1, xs, ys, &tr))) return e;
+        if (std::sqrt(tr) <= tol) {
+          result = RZ_OK;
+          break;
+        }
+        launch_scale_copy(1.0, h->vr, h->kr, n, s);
+      }
+      do_vcycle(h, h->kr, h->kz);
+      double d2[2];
+      if (flexible) {
+        const double *xs[2] = {h->kr, h->kro}, *ys[2] = {h->kz, h->kz};
+        if ((e = dots_host(h, 2, xs, ys, d2))) return e;
+      } else {
+        const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
+        if ((e = dots_host(h, 1, xs, ys, d2))) return e;
+        d2[1] = 0.0;
+      }
+      const double beta = (d2[0] - d2[1]) / rz_;
+      rz_ = d2[0];
+      launch_xpby(h->kz, beta, h->kp, n, s);
+    }
+  }
+  // final true residual
+  do_apply64(h, x, h->vaz);
+  launch_sub(b, h->vaz, h->vr, n, s);
+  launch_dirichlet_copy(h->L, nullptr, h->vr, s);
+  {
+    double tr;
+    const double *xs[1] = {h->vr}, *ys[1] = {h->vr};
+    if ((e = dots_host(h, 1, xs, ys, &tr))) return e;
+    relres = nb > 0 ? std::sqrt(tr) / nb : 0.0;
+  }
+  HIPCALL(h, hipEventRecord(ev1, s));
+  HIPCALL(h, hipEventSynchronize(ev1));
+  float ms = 0;
+  hipEventElapsedTime(&ms, ev0, ev1);
+  hipEventDestroy(ev0);
+  hipEventDestroy(ev1);
+  if (info) {
+    info->iters = it;
+    info->status = result;
+    info->rel_res = relres;
+    info->omega = h->omega;
+    info->t_solve_ms = ms;
+  }
+  if (result == RZ_ERR_NOT_CONVERGED) fail(h->ctx, result, "maximum number of iterations reached");
+  return result;
+}
+
+rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *bytes) {
+  if (!h || !bytes) return RZ_ERR_ARG;
+  const int p = h->p, n1 = p + 1;
+  std::vector<unsigned char> out;
+  auto put = [&](const void *src, size_t nb) {
+    size_t o = out.size();
+    out.resize(o + nb);
+    std::memcpy(out.data() + o, src, nb);
+  };
+  switch (what) {
+    case RZ_EXPORT_DOFMAP: {
+      for (int64_t c = 0; c < h->ncells; ++c) {
+        int cx = c % h->nx, cy = (c / h->nx) % h->ny, cz = c / ((int64_t)h->nx * h->ny);
+        for (int l = 0; l < n1; ++l)
+          for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+              int64_t g = (int64_t)(cx * p + i) + (int64_t)h->Nx * ((cy * p + j) + (int64_t)h->Ny * (cz * p + l));
+              put(&g, sizeof g);
+            }
+      }
+      break;
+    }
+    case RZ_EXPORT_PATCH:
+    case RZ_EXPORT_IC_PATTERN:
+    case RZ_EXPORT_IC_FACTOR: {
+      if (index < 0 || index >= (int64_t)h->patch_vids.size()) return fail(h->ctx, RZ_ERR_ARG, "bad patch index");
+      const int64_t vid = h->patch_vids[index];
+      std::vector<int> loc(h->ps.nrows, -1);
+      std::vector<std::array<int, 3>> G(h->ps.nrows);
+      int cnt = 0;
+      for (int k = 0; k < h->ps.nrows; ++k) {
+        int g3[3];
+        if (patch_row_present(h, vid, k, g3)) {
+          loc[k] = cnt++;
+          G[k] = {g3[0], g3[1], g3[2]};
+        }
+      }
+      if (what == RZ_EXPORT_PATCH) {
+        put(&vid, sizeof vid);
+        for (int k = 0; k < h->ps.nrows; ++k)
+          if (loc[k] >= 0) {
+            int64_t g = (int64_t)G[k][0] + (int64_t)h->Nx * (G[k][1] + (int64_t)h->Ny * G[k][2]);
+            put(&g, sizeof g);
+          }
+        break;
+      }
+      std::vector<double> vals;
+      if (what == RZ_EXPORT_IC_FACTOR) {
+        rz_status e = require_device(h);
+        if (e) return e;
+        vals.resize(h->ps.nnz);
+        HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+        HIPCALL(h, hipMemcpy(vals.data(), h->f64 + vid * (int64_t)h->ps.nnz, sizeof(double) * h->ps.nnz,
+                             hipMemcpyDeviceToHost));
+      }
+      for (int r = 0; r < h->ps.nrows; ++r) {
+        if (loc[r] < 0) continue;
+        for (int k = h->ps.rowptr[r]; k < h->ps.rowptr[r + 1]; ++k) {
+          int c = h->ps.col[k];
+          if (loc[c] < 0) continue;
+          if (r != c && !patch_entry_allowed(h, vid, G[r].data(), G[c].data())) continue;
+          if (what == RZ_EXPORT_IC_PATTERN) {
+            int pr[2] = {loc[r], loc[c]};
+            put(pr, sizeof pr);
+          } else {
+            put(&vals[k], sizeof(double));
+          }
+        }
+      }
+      break;
+    }
+    case RZ_EXPORT_TABLES1D: {
+      std::vector<double> v(h->t.lam);
+      v.insert(v.end(), h->t.B.begin(), h->t.B.end());
+      v.insert(v.end(), h->t.A.begin(), h->t.A.end());
+      v.insert(v.end(), h->t.D.begin(), h->t.D.end());
+      v.insert(v.end(), h->t.E.begin(), h->t.E.end());
+      put(v.data(), sizeof(double) * v.size());
+      break;
+    }
+    case RZ_EXPORT_AUXCOEF:
+      put(h->coef.data(), sizeof(double) * h->coef.size());
+      break;
+    case RZ_EXPORT_OMEGA:
+      put(&h->omega, sizeof(double));
+      break;
+    default:
+      return fail(h->ctx, RZ_ERR_ARG, "bad export kind");
+  }
+  if (!buf) {
+    *bytes = (int64_t)out.size();
+    return RZ_OK;
+  }
+  if (*bytes < (int64_t)out.size()) return fail(h->ctx, RZ_ERR_ARG, "export buffer too small");
+  std::memcpy(buf, out.data(), out.size());
+  *bytes = (int64_t)out.size();
+  return RZ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,247 @@
+"""ctypes binding of ``librz.so`` (include/rz.h).  Argument marshalling only: every
+step of the computation runs in the library's HIP kernels.  Device vectors are
+passed as torch tensors (their data pointers) on the context's stream.
+
+There is no fallback: if the shared library is missing, importing this module
+raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librz.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2211_14284_amd.build`")
+lib = ctypes.CDLL(LIB_PATH)
+
+GRAD, CURL, DIV = 0, 1, 2
+SPACES = {"grad": GRAD, "curl": CURL, "div": DIV}
+F64, F32 = 0, 1
+COEF_CONST, COEF_CELL = 0, 1
+PREC_F64, PREC_MIXED = 0, 1
+EXPORT_DOFMAP, EXPORT_PATCH, EXPORT_IC_PATTERN, EXPORT_IC_FACTOR = 0, 1, 2, 3
+EXPORT_TABLES1D, EXPORT_AUXCOEF, EXPORT_OMEGA = 4, 5, 6
+STATUS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_OOM", -3: "RZ_ERR_BREAKDOWN",
+          -4: "RZ_ERR_NOT_CONVERGED", -5: "RZ_ERR_HIP", -6: "RZ_ERR_SINGULAR", -7: "RZ_ERR_NODEVICE"}
+
+
+class RzError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("vertex_xyz", ctypes.POINTER(ctypes.c_double)), ("dirichlet_faces", ctypes.c_uint32)]
+
+
+class Coef(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("alpha", ctypes.POINTER(ctypes.c_double)),
+                ("beta", ctypes.POINTER(ctypes.c_double))]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("space", ctypes.c_int32), ("p", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double), ("omega", ctypes.c_double),
+                ("lanczos_seed", ctypes.c_uint64)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_res", ctypes.c_double),
+                ("omega", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_proto = {
+    "rz_opts_default": (None, [ctypes.POINTER(Opts)]),
+    "rz_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _vp]),
+    "rz_destroy": (ctypes.c_int, [_vp]),
+    "rz_last_error": (ctypes.c_char_p, [_vp]),
+    "rz_setup": (ctypes.c_int, [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Coef), ctypes.POINTER(Opts),
+                                ctypes.POINTER(_vp)]),
+    "rz_free": (ctypes.c_int, [_vp]),
+    "rz_sizes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)]),
+    "rz_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+    "rz_relax": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+    "rz_prolong_add": (ctypes.c_int, [_vp, _vp, _vp]),
+    "rz_restrict": (ctypes.c_int, [_vp, _vp, _vp]),
+    "rz_coarse_solve": (ctypes.c_int, [_vp, _vp, _vp]),
+    "rz_vcycle": (ctypes.c_int, [_vp, _vp, _vp]),
+    "rz_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(SolveInfo)]),
+    "rz_export": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_int64)]),
+}
+for _name, (_res, _args) in _proto.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+class Context:
+    """A library context on one HIP device (device=-1: host-only, symbolic setup)."""
+
+    def __init__(self, device=0, stream=None):
+        self.handle = _vp()
+        sp = None
+        if device >= 0 and stream is not None:
+            sp = stream if isinstance(stream, int) else stream.cuda_stream
+        code = lib.rz_create(ctypes.byref(self.handle), device, sp)
+        if code != 0:
+            raise RzError(code, "rz_create failed")
+        self.device = device
+
+    def error(self):
+        return lib.rz_last_error(self.handle).decode()
+
+    def check(self, code):
+        if code != 0:
+            raise RzError(code, self.error())
+
+    def close(self):
+        if self.handle:
+            lib.rz_destroy(self.handle)
+            self.handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_opts(**kw):
+    o = Opts()
+    lib.rz_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "space" and isinstance(v, str):
+            v = SPACES[v]
+        setattr(o, k, v)
+    return o
+
+
+class Problem:
+    """One discretised Riesz map: ``Problem(ctx, n, p, alpha, beta, ...)``.
+
+    n: cells per axis (int or 3-tuple); alpha, beta: scalars (constant) or arrays of
+    one value per cell; vertices: optional (n_vertices, 3) array of a Cartesian grid.
+    """
+
+    def __init__(self, ctx, n, p, alpha=1.0, beta=1.0, space="grad", vertices=None,
+                 dirichlet=0x3F, **opts):
+        self.ctx = ctx
+        nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+        self._keep = []
+        vp = None
+        if vertices is not None:
+            v = np.ascontiguousarray(vertices, dtype=np.float64).ravel()
+            self._keep.append(v)
+            vp = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        mesh = Mesh(nx, ny, nz, vp, dirichlet)
+        a = np.ascontiguousarray(np.atleast_1d(alpha), dtype=np.float64)
+        b = np.ascontiguousarray(np.atleast_1d(beta), dtype=np.float64)
+        kind = COEF_CONST if (a.size == 1 and b.size == 1) else COEF_CELL
+        if kind == COEF_CELL:
+            a = np.ascontiguousarray(np.broadcast_to(a, (nx * ny * nz,)))
+            b = np.ascontiguousarray(np.broadcast_to(b, (nx * ny * nz,)))
+        self._keep += [a, b]
+        coef = Coef(kind, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        o = default_opts(space=space, p=p, **opts)
+        self.handle = _vp()
+        ctx.check(lib.rz_setup(ctx.handle, ctypes.byref(mesh), ctypes.byref(coef), ctypes.byref(o),
+                               ctypes.byref(self.handle)))
+        s = (ctypes.c_int64 * 8)()
+        ctx.check(lib.rz_sizes(self.handle, s))
+        (self.ndofs, self.nfree, self.ncells, self.nslots, self.ncoarse, self.nnz, self.nrows,
+         self.npatches) = list(s)
+        self.n = (nx, ny, nz)
+        self.p = p
+
+    # ---- compute (device tensors) -------------------------------------------------
+    def apply(self, x, y, dtype=F64):
+        self.ctx.check(lib.rz_apply(self.handle, _ptr(x), _ptr(y), dtype))
+
+    def relax(self, r, z, dtype=F64):
+        self.ctx.check(lib.rz_relax(self.handle, _ptr(r), _ptr(z), dtype))
+
+    def prolong_add(self, xc, xf):
+        self.ctx.check(lib.rz_prolong_add(self.handle, _ptr(xc), _ptr(xf)))
+
+    def restrict(self, rf, rc):
+        self.ctx.check(lib.rz_restrict(self.handle, _ptr(rf), _ptr(rc)))
+
+    def coarse_solve(self, rc, xc):
+        self.ctx.check(lib.rz_coarse_solve(self.handle, _ptr(rc), _ptr(xc)))
+
+    def vcycle(self, r, z):
+        self.ctx.check(lib.rz_vcycle(self.handle, _ptr(r), _ptr(z)))
+
+    def solve(self, b, x, check=True):
+        info = SolveInfo()
+        code = lib.rz_solve(self.handle, _ptr(b), _ptr(x), ctypes.byref(info))
+        if check:
+            self.ctx.check(code)
+        return info
+
+    # ---- exports (host numpy arrays) ----------------------------------------------
+    def _export(self, what, index=0, dtype=np.float64):
+        nb = ctypes.c_int64(0)
+        self.ctx.check(lib.rz_export(self.handle, what, index, None, ctypes.byref(nb)))
+        buf = np.empty(nb.value // np.dtype(dtype).itemsize, dtype=dtype)
+        self.ctx.check(lib.rz_export(self.handle, what, index, buf.ctypes.data_as(_vp), ctypes.byref(nb)))
+        return buf
+
+    def dofmap(self):
+        m = self._export(EXPORT_DOFMAP, dtype=np.int64)
+        return m.reshape(self.ncells, -1)
+
+    def patch(self, k):
+        v = self._export(EXPORT_PATCH, k, dtype=np.int64)
+        return int(v[0]), v[1:]
+
+    def ic_pattern(self, k):
+        return self._export(EXPORT_IC_PATTERN, k, dtype=np.int32).reshape(-1, 2)
+
+    def ic_factor(self, k):
+        return self._export(EXPORT_IC_FACTOR, k)
+
+    def tables1d(self):
+        p = self.p
+        v = self._export(EXPORT_TABLES1D)
+        n1 = p + 1
+        o = 0
+        out = {}
+        for name, size, shape in (("lam", p - 1, (p - 1,)), ("B", n1 * n1, (n1, n1)), ("A", n1 * n1, (n1, n1)),
+                                  ("D", p * n1, (p, n1)), ("E", n1 * 2, (n1, 2))):
+            out[name] = v[o:o + size].reshape(shape)
+            o += size
+        return out
+
+    def aux_coefficients(self):
+        return self._export(EXPORT_AUXCOEF).reshape(self.ncells, 6)
+
+    def omega(self):
+        return float(self._export(EXPORT_OMEGA)[0])
+
+    def close(self):
+        if self.handle:
+            lib.rz_free(self.handle)
+            self.handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

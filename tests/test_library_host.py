@@ -1,0 +1,104 @@
+"""Host-side checks of the C-ABI library (no GPU): the shared library loads and
+exports every entry point of include/rz.h; the numbering, the vertex-star
+patches, the static-condensation IC pattern and the 1-D tables of a host-only
+context match the oracle bit-exactly (integers) or to 1e-13 (tables)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.lattice import Mesh, Lattice
+from oracle.tables1d import Element1D, p1_embedding
+from oracle import schwarz
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _rz():
+    from paper_2211_14284_amd import rz
+    return rz
+
+
+def test_exports_every_declared_symbol():
+    rz = _rz()
+    header = open(os.path.join(ROOT, "include", "rz.h")).read()
+    names = set(re.findall(r"\b(rz_[a-z_]+)\s*\(", header))
+    assert len(names) >= 15
+    for name in sorted(names):
+        assert hasattr(rz.lib, name), name
+
+
+def test_host_only_context_refuses_compute():
+    rz = _rz()
+    ctx = rz.Context(-1)
+    pb = rz.Problem(ctx, 2, 3)
+    with pytest.raises(rz.RzError) as e:
+        pb.apply(1, 2)
+    assert e.value.code == -7
+
+
+@pytest.mark.parametrize("n,p", [((2, 3, 2), 3), ((4, 4, 4), 4), ((2, 2, 2), 7)])
+def test_dofmap_bit_exact(n, p):
+    rz = _rz()
+    pb = rz.Problem(rz.Context(-1), n, p)
+    lat = Lattice(Mesh(*n), "grad", p)
+    assert np.array_equal(pb.dofmap(), lat.cell_dofs())
+    assert pb.ndofs == lat.ndofs
+    assert pb.nfree == int((~lat.dirichlet_mask()).sum())
+
+
+@pytest.mark.parametrize("n,p,dirichlet", [((4, 4, 4), 4, 0x3F), ((3, 2, 3), 3, 0x3F), ((3, 3, 2), 2, 0x15)])
+def test_patches_and_ic_pattern_bit_exact(n, p, dirichlet):
+    rz = _rz()
+    pb = rz.Problem(rz.Context(-1), n, p, dirichlet=dirichlet)
+    m = Mesh(*n, dirichlet=dirichlet)
+    lat = Lattice(m, "grad", p)
+    ref = schwarz.vertex_patches_grad(lat)
+    assert pb.npatches == len(ref)
+    pat = schwarz.symbolic_schur_pattern_grad(lat)
+    for k, (vid, dofs) in enumerate(ref):
+        v, d = pb.patch(k)
+        assert v == vid
+        assert np.array_equal(d, dofs)
+        pv = pat[dofs][:, dofs].toarray().astype(bool)
+        r, c = np.nonzero(np.tril(pv))
+        order = np.lexsort((c, r))
+        got = pb.ic_pattern(k)
+        assert np.array_equal(got, np.stack([r[order], c[order]], 1))
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 7, 9])
+def test_tables1d_match_oracle(p):
+    rz = _rz()
+    pb = rz.Problem(rz.Context(-1), 2, p)
+    t = pb.tables1d()
+    e = Element1D(p)
+    sc = max(1.0, np.abs(e.A).max())
+    assert np.allclose(t["lam"], e.lam, rtol=1e-13, atol=0)
+    assert np.abs(t["B"] - e.B).max() < 1e-14
+    assert np.abs(t["A"] - e.A).max() < 1e-13 * sc
+    assert np.abs(t["D"] - e.D).max() < 1e-13 * np.sqrt(sc)
+    assert np.abs(t["E"] - p1_embedding(e)).max() < 1e-14
+
+
+def test_aux_coefficients_cartesian():
+    rz = _rz()
+    from oracle import auxop
+    m = Mesh(3, 2, 2)
+    m.vertices[:, 0] *= 1.5
+    alpha = np.linspace(0.5, 2, 12)
+    beta = np.linspace(3, 1, 12)
+    pb = rz.Problem(rz.Context(-1), (3, 2, 2), 3, alpha, beta, vertices=m.vertices)
+    ref = auxop.cartesian_coefficient_array(Lattice(m, "grad", 3), alpha, beta)
+    assert np.allclose(pb.aux_coefficients(), ref, rtol=1e-14)
+
+
+def test_rejects_non_cartesian_mesh():
+    rz = _rz()
+    m = Mesh(2, 2, 2)
+    v = m.vertices.copy()
+    v[13] += 0.05
+    with pytest.raises(rz.RzError) as e:
+        rz.Problem(rz.Context(-1), 2, 3, vertices=v)
+    assert e.value.code == -1
