@@ -1,0 +1,212 @@
+#!/usr/bin/env python
+"""Benchmark of the H(grad) hot path on one MI355X.
+
+Workload (default): Q_7 on a uniform 32^3 hexahedral mesh of the unit cube
+(225^3 = 11,390,625 lattice DoFs), cellwise-constant alpha, beta log-uniform in
+[1e-2, 1e2) (SplitMix64 seeds 1, 2), U[-1,1) right-hand side (seed 0), homogeneous
+Dirichlet boundary.
+
+One step = one PCG solve from x = 0 to a true relative residual of 1e-8 with the
+p-multigrid V(1,1) preconditioner (statically condensed vertex-star relaxation
+with IC patch factors, p=1 coarse solve), all vectors resident in HBM; setup is
+done once before the timed region and reported separately.  Printed: one JSON
+line with the FP64 solve throughput as `value`, plus the mixed-precision solve,
+the operator-apply throughput, per-kernel times and the roofline of the dominant
+kernel (HIP events on the library stream over the timed region), and the CPU
+oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GDoF/s sum-factorized apply; PCG time-to-1e-8, FP64 vs mixed, H(grad) p=7"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(n, p):
+    import synth
+    nc = n ** 3
+    alpha = synth.cell_coefficients(nc, 1)
+    beta = synth.cell_coefficients(nc, 2)
+    ndofs = (n * p + 1) ** 3
+    b = synth.rhs_values(ndofs, 0)
+    return alpha, beta, b
+
+
+def kernel_bytes(pb, sz, n):
+    """Algorithmic HBM bytes of one launch of each timed kernel group (element size sz)."""
+    nd, ns, nnz, nrows, nc, p = pb.ndofs, pb.nslots, pb.nnz, pb.nrows, pb.ncells, pb.p
+    niface = nd - nc * (p - 1) ** 3
+    return {
+        # x read once, y written once, 6 weights per cell
+        "apply": 2 * nd * sz + 6 * nc * sz,
+        # r read once, interface right-hand side written once
+        "condense": (nd + niface) * sz,
+        # every slot: its factor (nnz values) once, its interface vector in and out
+        "patch": ns * (nnz + 2 * nrows) * sz,
+        # patch solutions read once, r read once, z written once
+        "expand": (ns * nrows + 2 * nd) * sz,
+        # dense inverse diagonal blocks of the coarse LDL^T, read in both sweeps
+        "coarse": 2 * (n - 1) * ((n - 1) ** 2) ** 2 * 8,
+    }
+
+
+def time_solves(torch, pb, bt, x, steps, warmup):
+    for _ in range(warmup):
+        pb.solve(bt, x)
+    torch.cuda.synchronize()
+    pb.timing(True)
+    pb.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [pb.solve(bt, x) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = pb.timing_read()
+    pb.timing(False)
+    return (t1 - t0) * 1e3 / steps, infos, kt
+
+
+def time_apply(torch, pb, dtype_t, code, reps=50, warm=10):
+    x = torch.rand(pb.ndofs, dtype=dtype_t, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(warm):
+        pb.apply(x, y, code)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record(s)
+        pb.apply(x, y, code)
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def cpu_baseline(n=4, p=7):
+    """The oracle's FP64 PCG (same method, same recipe) on a bounded sample."""
+    from threadpoolctl import threadpool_limits
+    import synth
+    from oracle.lattice import Mesh, Lattice
+    from oracle import assemble as asm, auxop, schwarz, pmg
+    with threadpool_limits(limits=1):
+        al = synth.cell_coefficients(n ** 3, 1)
+        be = synth.cell_coefficients(n ** 3, 2)
+        m = Mesh(n, n, n)
+        lat, latc = Lattice(m, "grad", p), Lattice(m, "grad", 1)
+        A = asm.with_dirichlet(lat, asm.cartesian_operator(lat, al, be))
+        co = auxop.cartesian_coefficient_array(lat, al, be)
+        R = schwarz.SCRelaxGrad(lat, auxop.separable_operator(lat, co))
+        Pr = pmg.prolongation(lat, latc)
+        cs = pmg.CoarseSolver(latc, asm.with_dirichlet(latc, asm.cartesian_operator(latc, al, be)))
+        mask = lat.dirichlet_mask()
+        v0 = np.where(mask, 0.0, synth.uniform_pm1(99, lat.ndofs))
+        lam = pmg.lanczos_lambda_max(A, lambda r: np.where(mask, 0.0, R.apply(r)), v0)
+        V = pmg.VCycle(lat, A, R, Pr, cs, pmg.omega_from_lambda(lam))
+        b = np.where(mask, 0.0, synth.rhs_values(lat.ndofs, 0))
+        t0 = time.perf_counter()
+        x, it, _ = pmg.pcg(A, b, V)
+        t = time.perf_counter() - t0
+    return {"value": lat.ndofs / t / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle FP64 PCG to 1e-8 (same V(1,1)/IC/p-MG method and coefficient recipe), "
+                      f"Q_{p} on {n}^3 cells = {lat.ndofs} DoFs, {it} iterations, setup excluded, "
+                      f"{t:.2f} s on 1 host thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--p", type=int, default=7)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
+              "(multi-GPU sharding is a design in DESIGN.md, not built); rerun with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2211_14284_amd import rz
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    ctx = rz.Context(0, stream)
+    alpha, beta, b = workload(args.n, args.p)
+    log(f"setup FP64 problem n={args.n} p={args.p}")
+    t0 = time.perf_counter()
+    pb = rz.Problem(ctx, args.n, args.p, alpha, beta, precision=rz.PREC_F64)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"setup done in {setup_s:.2f} s; timing {args.steps} FP64 solves")
+    bt = torch.as_tensor(b, device="cuda:0")
+    x = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
+    ms, infos, kt = time_solves(torch, pb, bt, x, args.steps, args.warmup)
+    iters = infos[-1].iters
+    relres = max(i.rel_res for i in infos)
+    # dominant kernel and its roofline (algorithmic bytes / average launch time)
+    kb = kernel_bytes(pb, 8, args.n)
+    dom = max(kt, key=lambda k: kt[k][0])
+    per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}
+    roof = None
+    if dom in kb and kt[dom][1]:
+        ach = kb[dom] / (per_launch[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "avg_launch_ms": round(per_launch[dom], 4), "algorithmic_bytes_per_launch": kb[dom]}
+    log(f"FP64 solve {ms:.3f} ms, {iters} iterations; timing the apply")
+    apply64 = time_apply(torch, pb, torch.float64, rz.F64)
+    apply32 = time_apply(torch, pb, torch.float32, rz.F32)
+    out = {
+        "metric": METRIC, "value": round(pb.ndofs / (ms * 1e-3) / 1e9, 5), "unit": "GDoF/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"H(grad) Q_{args.p} on {args.n}^3 uniform hex mesh, cellwise log-uniform "
+                               f"alpha,beta in [1e-2,1e2), U[-1,1) RHS; PCG to rel. residual 1e-8",
+                   "ndofs": pb.ndofs, "nfree": pb.nfree, "cells": pb.ncells, "p": args.p},
+        "pcg_ms_f64": round(ms, 4), "iters_f64": iters, "rel_res_f64": relres,
+        "setup_s_f64": round(setup_s, 3), "omega": pb.omega(),
+        "apply_gdofs_f64": round(pb.ndofs / (apply64 * 1e-3) / 1e9, 2),
+        "apply_gdofs_f32": round(pb.ndofs / (apply32 * 1e-3) / 1e9, 2),
+        "apply_ms_f64": round(apply64, 4), "apply_ms_f32": round(apply32, 4),
+        "kernel_ms_per_step_f64": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
+        "kernel_launches_per_step_f64": {k: v[1] / args.steps for k, v in kt.items()},
+        "roofline": roof,
+    }
+    pb.close()
+    if not args.no_mixed:
+        log("setup mixed-precision problem")
+        t0 = time.perf_counter()
+        pm = rz.Problem(ctx, args.n, args.p, alpha, beta, precision=rz.PREC_MIXED)
+        torch.cuda.synchronize()
+        out["setup_s_mixed"] = round(time.perf_counter() - t0, 3)
+        msm, infm, ktm = time_solves(torch, pm, bt, x, args.steps, args.warmup)
+        out["pcg_ms_mixed"] = round(msm, 4)
+        out["iters_mixed"] = infm[-1].iters
+        out["rel_res_mixed"] = max(i.rel_res for i in infm)
+        out["kernel_ms_per_step_mixed"] = {k: round(v[0] / args.steps, 4) for k, v in ktm.items()}
+        out["speedup_mixed_vs_f64"] = round(ms / msm, 3)
+        pm.close()
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

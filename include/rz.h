@@ -176,6 +176,23 @@ enum {
 };
 rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *bytes);
 
+/* Per-kernel device timing for measurement.  While enabled, every launch of the
+ * kernels below is bracketed by hipEvents on the context stream; rz_timing_read
+ * synchronises, returns the accumulated milliseconds and launch counts per kernel
+ * (arrays of RZ_NKERNELS entries) and resets the accumulators. */
+enum {
+  RZ_K_APPLY = 0,        /* operator apply (init + cell kernel)                       */
+  RZ_K_CONDENSE = 1,     /* relaxation: interface right-hand side (R_Gamma r)        */
+  RZ_K_PATCH = 2,        /* relaxation: vertex-patch triangular solves               */
+  RZ_K_EXPAND = 3,       /* relaxation: patch sum + harmonic extension               */
+  RZ_K_TRANSFER = 4,     /* restriction + prolongation                               */
+  RZ_K_COARSE = 5,       /* coarse block-tridiagonal solve                            */
+  RZ_K_KRYLOV = 6,       /* vector updates and dot products                           */
+  RZ_NKERNELS = 7
+};
+rz_status rz_timing_enable(rz_problem *h, int on);
+rz_status rz_timing_read(rz_problem *h, double ms[RZ_NKERNELS], int64_t count[RZ_NKERNELS]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,6 +65,10 @@ struct rz_problem {
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kAp = nullptr, *kro = nullptr;
   double *partials = nullptr, *dots = nullptr;
   int *status = nullptr;
+  // per-kernel timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  std::vector<std::pair<int, size_t>> ev_used;  // (kernel id, pool index)
 };
 
 namespace {
@@ -145,26 +149,82 @@ uint64_t splitmix_next(uint64_t &s) {
 }
 
 // ---------------------------------------------------------------------------------------
+// per-kernel timing: events around launches while enabled
+// ---------------------------------------------------------------------------------------
+struct Timed {
+  rz_problem *h;
+  int id;
+  size_t slot = 0;
+  Timed(rz_problem *h_, int id_) : h(h_), id(id_) {
+    if (!h->timing) return;
+    slot = h->ev_used.size();
+    if (slot >= h->ev_pool.size()) {
+      hipEvent_t a, b;
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      h->ev_pool.push_back({a, b});
+    }
+    h->ev_used.push_back({id, slot});
+    hipEventRecord(h->ev_pool[slot].first, h->ctx->stream);
+  }
+  ~Timed() {
+    if (h->timing) hipEventRecord(h->ev_pool[slot].second, h->ctx->stream);
+  }
+};
+
+
+// vector updates of the Krylov method and the V-cycle (timed as one group)
+void v_axpy(rz_problem *h, double a, const double *x, double *y) {
+  Timed t(h, RZ_K_KRYLOV);
+  launch_axpy(a, x, y, h->ndofs, h->ctx->stream);
+}
+void v_xpby(rz_problem *h, const double *x, double b, double *y) {
+  Timed t(h, RZ_K_KRYLOV);
+  launch_xpby(x, b, y, h->ndofs, h->ctx->stream);
+}
+void v_sub(rz_problem *h, const double *x, const double *y, double *z) {
+  Timed t(h, RZ_K_KRYLOV);
+  launch_sub(x, y, z, h->ndofs, h->ctx->stream);
+}
+void v_scale_copy(rz_problem *h, double a, const double *x, double *y) {
+  Timed t(h, RZ_K_KRYLOV);
+  launch_scale_copy(a, x, y, h->ndofs, h->ctx->stream);
+}
+
+// ---------------------------------------------------------------------------------------
 // operator pieces on the device
 // ---------------------------------------------------------------------------------------
 rz_status do_apply64(rz_problem *h, const double *x, double *y) {
+  Timed t(h, RZ_K_APPLY);
   launch_apply_grad<double>(h->L, h->coef64, h->B64, h->A64, x, y, h->ctx->stream);
   return RZ_OK;
 }
 
-rz_status do_relax64(rz_problem *h, const double *r, double *z) {
+template <typename T>
+void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T *f, T *rt, T *zb, const T *r,
+                 T *z) {
   hipStream_t s = h->ctx->stream;
-  launch_condense_grad<double>(h->L, h->coef64, h->A64, h->lam64, r, h->rt64, s);
-  launch_patch_solve<double>(h->L, h->P, h->f64, h->rt64, h->zb64, s);
-  launch_expand_grad<double>(h->L, h->P, h->coef64, h->A64, h->lam64, r, h->zb64, z, s);
+  {
+    Timed t(h, RZ_K_CONDENSE);
+    launch_condense_grad<T>(h->L, coef, A, lam, r, rt, s);
+  }
+  {
+    Timed t(h, RZ_K_PATCH);
+    launch_patch_solve<T>(h->L, h->P, f, rt, zb, s);
+  }
+  {
+    Timed t(h, RZ_K_EXPAND);
+    launch_expand_grad<T>(h->L, h->P, coef, A, lam, r, zb, z, s);
+  }
+}
+
+rz_status do_relax64(rz_problem *h, const double *r, double *z) {
+  relax_steps<double>(h, h->coef64, h->A64, h->lam64, h->f64, h->rt64, h->zb64, r, z);
   return RZ_OK;
 }
 
 rz_status do_relax32(rz_problem *h, const float *r, float *z) {
-  hipStream_t s = h->ctx->stream;
-  launch_condense_grad<float>(h->L, h->coef32, h->A32, h->lam32, r, h->rt32, s);
-  launch_patch_solve<float>(h->L, h->P, h->f32, h->rt32, h->zb32, s);
-  launch_expand_grad<float>(h->L, h->P, h->coef32, h->A32, h->lam32, r, h->zb32, z, s);
+  relax_steps<float>(h, h->coef32, h->A32, h->lam32, h->f32, h->rt32, h->zb32, r, z);
   return RZ_OK;
 }
 
@@ -180,6 +240,7 @@ rz_status do_relax_prec(rz_problem *h, const double *r, double *z) {
 }
 
 rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv) {
+  Timed tm(h, RZ_K_COARSE);
   hipStream_t s = h->ctx->stream;
   const int m = h->cm, nb = h->cmz;
   const size_t mm = (size_t)m * m;
@@ -200,22 +261,31 @@ rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
   const int64_t n = h->ndofs;
   const double w = h->omega;
   do_relax_prec(h, r, h->vt);
-  launch_scale_copy(w, h->vt, z, n, s);            // z = w M r
+  v_scale_copy(h, w, h->vt, z);            // z = w M r
   do_apply64(h, z, h->vaz);
-  launch_sub(r, h->vaz, h->vr, n, s);              // r1 = r - A z
-  launch_restrict_grad(h->L, h->E64, h->vr, h->rc, s);
+  v_sub(h, r, h->vaz, h->vr);              // r1 = r - A z
+  {
+    Timed tm(h, RZ_K_TRANSFER);
+    launch_restrict_grad(h->L, h->E64, h->vr, h->rc, s);
+  }
   do_coarse(h, h->rc, h->xc);
-  launch_prolong_add_grad(h->L, h->E64, h->xc, z, s);   // z += P A0^{-1} P^T r1
+  {
+    Timed tm(h, RZ_K_TRANSFER);
+    launch_prolong_add_grad(h->L, h->E64, h->xc, z, s);   // z += P A0^{-1} P^T r1
+  }
   do_apply64(h, z, h->vaz);
-  launch_sub(r, h->vaz, h->vr, n, s);              // r2 = r - A z
+  v_sub(h, r, h->vaz, h->vr);              // r2 = r - A z
   do_relax_prec(h, h->vr, h->vt);
-  launch_axpy(w, h->vt, z, n, s);                  // z += w M r2
+  v_axpy(h, w, h->vt, z);                  // z += w M r2
   launch_dirichlet_copy(h->L, r, z, s);
   return RZ_OK;
 }
 
 rz_status dots_host(rz_problem *h, int np, const double *const *xs, const double *const *ys, double *out) {
-  launch_dots(np, xs, ys, h->ndofs, h->partials, h->dots, h->ctx->stream);
+  {
+    Timed tm(h, RZ_K_KRYLOV);
+    launch_dots(np, xs, ys, h->ndofs, h->partials, h->dots, h->ctx->stream);
+  }
   HIPCALL(h, hipMemcpyAsync(out, h->dots, sizeof(double) * np, hipMemcpyDeviceToHost, h->ctx->stream));
   HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
   return RZ_OK;
@@ -277,7 +347,7 @@ rz_status estimate_lambda(rz_problem *h, double *lam_out) {
     if (e) return e;
     if (!(pAp > 0)) break;
     double a = rz_ / pAp;
-    launch_axpy(-a, h->kAp, h->kr, n, s);
+    v_axpy(h, -a, h->kAp, h->kr);
     do_relax_prec(h, h->kr, h->kz);
     double rzn;
     const double *xs2[1] = {h->kr}, *ys2[1] = {h->kz};
@@ -287,7 +357,7 @@ rz_status estimate_lambda(rz_problem *h, double *lam_out) {
     al.push_back(a);
     be.push_back(b);
     rz_ = rzn;
-    launch_xpby(h->kz, b, h->kp, n, s);
+    v_xpby(h, h->kz, b, h->kp);
     if (!(rzn > 0)) break;
   }
   const int k = (int)al.size();
@@ -403,6 +473,12 @@ rz_status setup_coarse(rz_problem *h) {
 void release(rz_problem *h) {
   for (void *p : h->allocs) hipFree(p);
   h->allocs.clear();
+  for (auto &e : h->ev_pool) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
+  h->ev_pool.clear();
+  h->ev_used.clear();
 }
 
 rz_status require_device(const rz_problem *h) {
@@ -705,7 +781,7 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *inf
   HIPCALL(h, hipEventRecord(ev0, s));
   // r = b with Dirichlet rows zero, x = 0
   launch_fill(x, 0.0, n, s);
-  launch_scale_copy(1.0, b, h->kr, n, s);
+  v_scale_copy(h, 1.0, b, h->kr);
   launch_dirichlet_copy(h->L, nullptr, h->kr, s);
   double bb;
   {
@@ -718,7 +794,7 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *inf
   double relres = 0.0;
   if (nb > 0) {
     do_vcycle(h, h->kr, h->kz);
-    launch_scale_copy(1.0, h->kz, h->kp, n, s);
+    v_scale_copy(h, 1.0, h->kz, h->kp);
     double rz_;
     {
       const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
@@ -737,9 +813,9 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *inf
         break;
       }
       const double a = rz_ / pAp;
-      launch_axpy(a, h->kp, x, n, s);
-      if (flexible) launch_scale_copy(1.0, h->kr, h->kro, n, s);
-      launch_axpy(-a, h->kAp, h->kr, n, s);
+      v_axpy(h, a, h->kp, x);
+      if (flexible) v_scale_copy(h, 1.0, h->kr, h->kro);
+      v_axpy(h, -a, h->kAp, h->kr);
       ++it;
       double rr;
       {
@@ -749,7 +825,7 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *inf
       if (std::sqrt(rr) <= tol) {
         // true residual check
         do_apply64(h, x, h->vaz);
-        launch_sub(b, h->vaz, h->vr, n, s);
+        v_sub(h, b, h->vaz, h->vr);
         launch_dirichlet_copy(h->L, nullptr, h->vr, s);
         double tr;
         const double *xs[1] = {h->vr}, *ys[1] = {h->vr};
@@ -758,7 +834,7 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *inf
           result = RZ_OK;
           break;
         }
-        launch_scale_copy(1.0, h->vr, h->kr, n, s);
+        v_scale_copy(h, 1.0, h->vr, h->kr);
       }
       do_vcycle(h, h->kr, h->kz);
       double d2[2];
@@ -772,12 +848,12 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *inf
       }
       const double beta = (d2[0] - d2[1]) / rz_;
       rz_ = d2[0];
-      launch_xpby(h->kz, beta, h->kp, n, s);
+      v_xpby(h, h->kz, beta, h->kp);
     }
   }
   // final true residual
   do_apply64(h, x, h->vaz);
-  launch_sub(b, h->vaz, h->vr, n, s);
+  v_sub(h, b, h->vaz, h->vr);
   launch_dirichlet_copy(h->L, nullptr, h->vr, s);
   {
     double tr;
@@ -898,6 +974,31 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
   if (*bytes < (int64_t)out.size()) return fail(h->ctx, RZ_ERR_ARG, "export buffer too small");
   std::memcpy(buf, out.data(), out.size());
   *bytes = (int64_t)out.size();
+  return RZ_OK;
+}
+
+rz_status rz_timing_enable(rz_problem *h, int on) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  h->timing = on != 0;
+  return RZ_OK;
+}
+
+rz_status rz_timing_read(rz_problem *h, double ms[RZ_NKERNELS], int64_t count[RZ_NKERNELS]) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+  for (int k = 0; k < RZ_NKERNELS; ++k) {
+    if (ms) ms[k] = 0.0;
+    if (count) count[k] = 0;
+  }
+  for (auto &u : h->ev_used) {
+    float t = 0;
+    hipEventElapsedTime(&t, h->ev_pool[u.second].first, h->ev_pool[u.second].second);
+    if (ms) ms[u.first] += t;
+    if (count) count[u.first] += 1;
+  }
+  h->ev_used.clear();
   return RZ_OK;
 }
 

@@ -24,6 +24,7 @@ COEF_CONST, COEF_CELL = 0, 1
 PREC_F64, PREC_MIXED = 0, 1
 EXPORT_DOFMAP, EXPORT_PATCH, EXPORT_IC_PATTERN, EXPORT_IC_FACTOR = 0, 1, 2, 3
 EXPORT_TABLES1D, EXPORT_AUXCOEF, EXPORT_OMEGA = 4, 5, 6
+KERNELS = ("apply", "condense", "patch", "expand", "transfer", "coarse", "krylov")
 STATUS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_OOM", -3: "RZ_ERR_BREAKDOWN",
           -4: "RZ_ERR_NOT_CONVERGED", -5: "RZ_ERR_HIP", -6: "RZ_ERR_SINGULAR", -7: "RZ_ERR_NODEVICE"}
 
@@ -73,6 +74,8 @@ _proto = {
     "rz_vcycle": (ctypes.c_int, [_vp, _vp, _vp]),
     "rz_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(SolveInfo)]),
     "rz_export": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_int64)]),
+    "rz_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "rz_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
 for _name, (_res, _args) in _proto.items():
     _f = getattr(lib, _name)
@@ -194,6 +197,17 @@ class Problem:
         if check:
             self.ctx.check(code)
         return info
+
+    # ---- per-kernel device timing --------------------------------------------------
+    def timing(self, on=True):
+        self.ctx.check(lib.rz_timing_enable(self.handle, 1 if on else 0))
+
+    def timing_read(self):
+        """{kernel: (total ms, launches)} accumulated since the last read."""
+        ms = (ctypes.c_double * len(KERNELS))()
+        cnt = (ctypes.c_int64 * len(KERNELS))()
+        self.ctx.check(lib.rz_timing_read(self.handle, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNELS)}
 
     # ---- exports (host numpy arrays) ----------------------------------------------
     def _export(self, what, index=0, dtype=np.float64):
