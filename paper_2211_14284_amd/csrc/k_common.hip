@@ -138,66 +138,158 @@ __global__ void k_negate(double *W, int64_t n) {
     W[i] = -W[i];
 }
 
-// v = W (r - C vprev): every block rebuilds w in LDS, then each wavefront computes
-// whole rows of the dense matrix-vector product.
-constexpr int kRowsPerBlock = 16;
-__global__ void __launch_bounds__(256) k_coarse_fwd(int m, int mx, const double *__restrict__ W,
-                                                    const double *__restrict__ C, const double *__restrict__ r,
-                                                    const double *__restrict__ vprev, double *__restrict__ v) {
-  extern __shared__ double w[];
-  int my = m / mx;
-  for (int a = threadIdx.x; a < m; a += blockDim.x) {
-    double t = r[a];
-    if (vprev)
-      for (int j = 0; j < 9; ++j) {
-        int c = nbr(a, j, mx, my);
-        if (c >= 0) t -= C[a * 9 + j] * vprev[c];
-      }
-    w[a] = t;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int rr = wid; rr < kRowsPerBlock; rr += 4) {
-    int row = blockIdx.x * kRowsPerBlock + rr;
-    if (row >= m) break;
-    const double *Wr = W + (int64_t)row * m;
-    double acc = 0.0;
-    for (int c = lane; c < m; c += 64) acc += Wr[c] * w[c];
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-    if (lane == 0) v[row] = acc;
-  }
+// Cross-block data of the coarse sweeps (v, x) is written and read with
+// agent-scope relaxed atomics, which bypass the per-XCD L2, so the grid barrier
+// only has to order these accesses: every thread waits for its stores, one thread
+// per block arrives on the counter and polls the generation word.  No L2
+// write-back or invalidation is needed.  The wait is bounded: after ~2^26 polls
+// the block records status = -1 and continues, so a barrier cannot hang.
+__device__ __forceinline__ void st_agent(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const double *p) {
+  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// x = v - W (C^T xnext)   (xnext == nullptr: x = v)
-__global__ void __launch_bounds__(256) k_coarse_bwd(int m, int mx, const double *__restrict__ W,
-                                                    const double *__restrict__ Ct, const double *__restrict__ v,
-                                                    const double *__restrict__ xnext, double *__restrict__ x) {
-  extern __shared__ double w[];
-  int my = m / mx;
-  if (!xnext) {
-    for (int a = blockIdx.x * kRowsPerBlock + threadIdx.x; a < min(m, (int)(blockIdx.x + 1) * kRowsPerBlock);
-         a += blockDim.x)
-      x[a] = v[a];
-    return;
-  }
-  for (int a = threadIdx.x; a < m; a += blockDim.x) {
-    double t = 0.0;
-    for (int j = 0; j < 9; ++j) {
-      int c = nbr(a, j, mx, my);
-      if (c >= 0) t += Ct[a * 9 + j] * xnext[c];
+// Wait until this wave's outstanding vector memory operations (here: the result
+// store) have completed, before the block barrier lets thread 0 publish the flag.
+// A workgroup-scope fence does not wait for them, an agent-scope one would also
+// write back the whole L2.  s_waitcnt immediate: vmcnt 0, expcnt 7, lgkmcnt 15.
+__device__ __forceinline__ void store_done() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Flag barrier: block b publishes generation `gen` in its own word flags[4 b];
+// wavefront 0 of every block polls all words with one vector load per 64 blocks
+// and a wave vote.  No contended atomics, no L2 maintenance (agent-scope
+// accesses).  Generations only grow (differences are taken modulo 2^32).
+__device__ void grid_barrier(unsigned *flags, unsigned gen, int *status) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    if (threadIdx.x == 0) __hip_atomic_store(flags + 4 * blockIdx.x, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    while (true) {
+      bool ok = true;
+      for (unsigned b = threadIdx.x; b < gridDim.x; b += 64)
+        ok &= (int)(__hip_atomic_load(flags + 4 * b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - gen) >= 0;
+      if (__all(ok)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1l << 26)) {
+        if (threadIdx.x == 0) atomicCAS(status, 0, -1);
+        break;
+      }
     }
-    w[a] = t;
   }
   __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Whole coarse solve in one persistent cooperative launch: block forward sweep
+//   v_k = W_k (r_k - C_k v_{k-1}),
+// block backward sweep
+//   x_k = v_k - W_k (C_{k+1}^T x_{k+1}),
+// one grid barrier per plane.  Every block rebuilds the coupled right-hand side w
+// in LDS (in-plane neighbours from the table nb, -1 = none); one row of W per
+// wavefront (16 rows per block), the row of the next plane loaded into registers
+// before the barrier of the current plane.
+struct CoarseArgs {
+  int m, nb;
+  const double *W, *C, *Ct, *r;
+  const int *nbt;
+  double *v, *x;
+  unsigned *flags;
+  unsigned gen0;
+  int *status;
+};
+
+template <int MPL>
+__global__ void __launch_bounds__(1024) k_coarse_persistent(CoarseArgs a) {
+  extern __shared__ double w[];
+  const int m = a.m;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int rr = wid; rr < kRowsPerBlock; rr += 4) {
-    int row = blockIdx.x * kRowsPerBlock + rr;
-    if (row >= m) break;
-    const double *Wr = W + (int64_t)row * m;
+  const int row = blockIdx.x * 16 + wid;
+  const bool has_row = row < m;
+  double wr[MPL];
+  auto load_row = [&](int k) {
+    const double *Wr = a.W + (size_t)k * m * m + (size_t)(has_row ? row : 0) * m;
+#pragma unroll
+    for (int j = 0; j < MPL; ++j) {
+      const int c = lane + 64 * j;
+      wr[j] = (has_row && c < m) ? Wr[c] : 0.0;
+    }
+  };
+  auto row_dot = [&]() {
     double acc = 0.0;
-    for (int c = lane; c < m; c += 64) acc += Wr[c] * w[c];
+#pragma unroll
+    for (int j = 0; j < MPL; ++j) {
+      const int c = lane + 64 * j;
+      if (c < m) acc += wr[j] * w[c];
+    }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-    if (lane == 0) x[row] = v[row] - acc;
+    return acc;
+  };
+  load_row(0);
+  for (int k = 0; k < a.nb; ++k) {
+    const double *rk = a.r + (size_t)k * m;
+    const double *Ck = a.C + (size_t)k * m * 9;
+    const double *vp = k ? a.v + (size_t)(k - 1) * m : nullptr;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      double t = rk[i];
+      if (vp) {
+        // all nine loads issued unconditionally (a missing neighbour reads the row
+        // itself and is masked), so they are in flight together
+        int c[9];
+        double nv[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) c[j] = a.nbt[i * 9 + j];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) nv[j] = ld_agent(vp + (c[j] >= 0 ? c[j] : i));
+        double cc[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) cc[j] = Ck[i * 9 + j];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) t -= c[j] >= 0 ? cc[j] * nv[j] : 0.0;
+      }
+      w[i] = t;
+    }
+    __syncthreads();
+    const double acc = row_dot();
+    if (has_row && lane == 0) st_agent(a.v + (size_t)k * m + row, acc);
+    store_done();
+    load_row(k + 1 < a.nb ? k + 1 : a.nb - 1);
+    grid_barrier(a.flags, a.gen0 + 1 + k, a.status);
+  }
+  for (int k = a.nb - 1; k >= 0; --k) {
+    const double *vk = a.v + (size_t)k * m;
+    double *xk = a.x + (size_t)k * m;
+    if (k == a.nb - 1) {
+      if (has_row && lane == 0) st_agent(xk + row, ld_agent(vk + row));
+      store_done();
+      if (k > 0) load_row(k - 1);
+    } else {
+      const double *Ctk = a.Ct + (size_t)k * m * 9;
+      const double *xn = a.x + (size_t)(k + 1) * m;
+      for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        int c[9];
+        double nv[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) c[j] = a.nbt[i * 9 + j];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) nv[j] = ld_agent(xn + (c[j] >= 0 ? c[j] : i));
+        double cc[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) cc[j] = Ctk[i * 9 + j];
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) t += c[j] >= 0 ? cc[j] * nv[j] : 0.0;
+        w[i] = t;
+      }
+      __syncthreads();
+      const double acc = row_dot();
+      if (has_row && lane == 0) st_agent(xk + row, ld_agent(vk + row) - acc);
+      store_done();
+      if (k > 0) load_row(k - 1);
+    }
+    if (k > 0) grid_barrier(a.flags, a.gen0 + a.nb + (a.nb - k), a.status);
   }
 }
 
@@ -272,16 +364,23 @@ void launch_sweep_inverse(int m, double *W, double *tmp, int *status, hipStream_
   k_negate<<<nblk(n), kBS, 0, s>>>(W, n);
 }
 
-void launch_coarse_fwd(int m, int mx, const double *W, const double *C, const double *r, const double *vprev,
-                       double *v, hipStream_t s) {
-  unsigned nb = (unsigned)((m + kRowsPerBlock - 1) / kRowsPerBlock);
-  k_coarse_fwd<<<nb, 256, sizeof(double) * m, s>>>(m, mx, W, C, r, vprev, v);
-}
-
-void launch_coarse_bwd(int m, int mx, const double *W, const double *Ct, const double *v, const double *xnext,
-                       double *x, hipStream_t s) {
-  unsigned nb = (unsigned)((m + kRowsPerBlock - 1) / kRowsPerBlock);
-  k_coarse_bwd<<<nb, 256, sizeof(double) * m, s>>>(m, mx, W, Ct, v, xnext, x);
+int launch_coarse_solve(int m, int nb, const double *W, const double *C, const double *Ct, const int *nbt,
+                        const double *r, double *v, double *x, unsigned *flags, unsigned *gen, int *status,
+                        hipStream_t s) {
+  const int blocks = (m + 15) / 16;
+  CoarseArgs a{m, nb, W, C, Ct, r, nbt, v, x, flags, *gen, status};
+  *gen += 2 * (unsigned)nb;
+  void *args[] = {&a};
+  const void *fn;
+  const int mpl = (m + 63) / 64;
+  if (mpl <= 4) fn = (const void *)k_coarse_persistent<4>;
+  else if (mpl <= 8) fn = (const void *)k_coarse_persistent<8>;
+  else if (mpl <= 16) fn = (const void *)k_coarse_persistent<16>;
+  else if (mpl <= 32) fn = (const void *)k_coarse_persistent<32>;
+  else if (mpl <= 64) fn = (const void *)k_coarse_persistent<64>;
+  else return -1;
+  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(1024), args, sizeof(double) * m, s);
+  return e == hipSuccess ? 0 : -1;
 }
 
 void launch_coarse_gather(int nfree, int bx0, int by0, int bz0, int mx, int my, int NX, int NY, const double *rc,

@@ -32,92 +32,173 @@ __device__ __forceinline__ int ncells_axis(const LatDev &L, int a) {
   return a == 0 ? L.nx : (a == 1 ? L.ny : L.nz);
 }
 
-// 1-D FDM mass (diagonal + (0,p)) applied along one axis of a tile.
-template <typename T>
-__device__ __forceinline__ T mass1d(const T *B, int p, int m, const T *f, int stride) {
-  const int n1 = p + 1;
-  T v = B[m * n1 + m] * f[m * stride];
-  if (m == 0) v += B[p] * f[p * stride];
-  else if (m == p) v += B[p * n1] * f[0];
-  return v;
-}
-
-// 1-D FDM stiffness (diagonal + rows/columns 0, p) applied along one axis.
-template <typename T>
-__device__ __forceinline__ T stiff1d(const T *A, int p, int m, const T *f, int stride) {
-  const int n1 = p + 1;
-  if (m != 0 && m != p)
-    return A[m * n1 + m] * f[m * stride] + A[m * n1] * f[0] + A[m * n1 + p] * f[p * stride];
-  T v = 0;
-  for (int i = 0; i <= p; ++i) v += A[m * n1 + i] * f[i * stride];
-  return v;
-}
-
-template <typename T>
-__device__ __forceinline__ void atomic_add(T *addr, T v) {
-  atomicAdd(addr, v);
-}
-
 // ------------------------------------------------------------------------------------
 // y = A x: per cell, y_K = s1 (A x B x B) + s2 (B x A x B) + s3 (B x B x A) + mu (B x B x B)
-// applied as per-axis contractions of the (p+1)^3 tile staged in LDS (eq.
-// sum-factorization with the exact 1-D integrals of an axis-aligned cell).
-// Interface contributions are summed with atomics; cell-interior rows are owned.
+// (eq. sum-factorization with the exact 1-D integrals of an axis-aligned cell),
+// applied as per-axis contractions.  Compile-time degree P: one thread per tensor
+// line of a cell holds the line in registers; LDS is used only to turn x-lines
+// into z-lines, z-lines into y-lines and y-lines back into x-lines.  The 1-D
+// tables travel in the kernel arguments (scalar registers).  Cell-interior rows
+// are owned by the cell (plain store); interface rows are summed with atomics.
 // ------------------------------------------------------------------------------------
-template <typename T>
-__global__ void k_apply_grad(LatDev L, const T *__restrict__ coef, const T *__restrict__ Bg,
-                             const T *__restrict__ Ag, const T *__restrict__ x, T *__restrict__ y) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *sm = reinterpret_cast<T *>(smem_raw);
-  const int p = L.p, n1 = p + 1, n2 = n1 * n1, n3 = n2 * n1;
-  T *sB = sm, *sA = sB + n2, *xs = sA + n2, *t1 = xs + n3, *v = t1 + n3, *u = v + n3, *w = u + n3;
-  const int cell = blockIdx.x;
-  const int cx = cell % L.nx, cy = (cell / L.nx) % L.ny, cz = cell / (L.nx * L.ny);
-  for (int k = threadIdx.x; k < n2; k += blockDim.x) {
-    sB[k] = Bg[k];
-    sA[k] = Ag[k];
+template <int P, typename T>
+struct Tab1D {
+  T B[(P + 1) * (P + 1)];
+  T A[(P + 1) * (P + 1)];
+};
+
+template <int P, typename T>
+__device__ __forceinline__ void mass_line(const Tab1D<P, T> &t, const T *in, T *out) {
+  constexpr int N1 = P + 1;
+#pragma unroll
+  for (int m = 0; m <= P; ++m) out[m] = t.B[m * N1 + m] * in[m];
+  out[0] += t.B[P] * in[P];
+  out[P] += t.B[P * N1] * in[0];
+}
+
+template <int P, typename T>
+__device__ __forceinline__ void stiff_line(const Tab1D<P, T> &t, const T *in, T *out) {
+  constexpr int N1 = P + 1;
+#pragma unroll
+  for (int m = 1; m < P; ++m) out[m] = t.A[m * N1 + m] * in[m] + t.A[m * N1] * in[0] + t.A[m * N1 + P] * in[P];
+  T a0 = 0, aP = 0;
+#pragma unroll
+  for (int i = 0; i <= P; ++i) {
+    a0 += t.A[i] * in[i];
+    aP += t.A[P * N1 + i] * in[i];
   }
-  const T s1 = coef[6 * cell + 0], s2 = coef[6 * cell + 1], s3 = coef[6 * cell + 2];
-  const T mu = coef[6 * cell + 3];
-  for (int k = threadIdx.x; k < n3; k += blockDim.x) {
-    int a = k % n1, b = (k / n1) % n1, c = k / n2;
-    int X = cx * p + a, Y = cy * p + b, Z = cz * p + c;
-    xs[k] = lat_dirichlet(L, X, Y, Z) ? T(0) : x[lat_index(L, X, Y, Z)];
+  out[0] = a0;
+  out[P] = aP;
+}
+
+template <int P, typename T, int CPB>
+__global__ void __launch_bounds__(CPB *(P + 1) * (P + 1))
+    k_apply_kron(LatDev L, Tab1D<P, T> tb, const T *__restrict__ coef, const T *__restrict__ x, T *__restrict__ y,
+                 T *__restrict__ ebuf, int ncells) {
+  constexpr int N1 = P + 1, NL = N1 * N1, N3 = NL * N1;
+  __shared__ T S0[CPB * N3], S1[CPB * N3];
+  const int lc = threadIdx.x / NL, l = threadIdx.x % NL;
+  const int cell = blockIdx.x * CPB + lc;
+  const bool active = cell < ncells;
+  T *s0 = S0 + lc * N3, *s1 = S1 + lc * N3;
+  const int cc = active ? cell : 0;
+  const int cx = cc % L.nx, cy = (cc / L.nx) % L.ny, cz = cc / (L.nx * L.ny);
+  T s1c = 0, s2c = 0, s3c = 0, mu = 0;
+  if (active) {
+    s1c = coef[6 * cell];
+    s2c = coef[6 * cell + 1];
+    s3c = coef[6 * cell + 2];
+    mu = coef[6 * cell + 3];
+  }
+  T r0[N1], r1[N1], r2[N1];
+  {  // x-line (b, c) of x
+    const int b = l % N1, c = l / N1;
+    const int Y = cy * P + b, Z = cz * P + c;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+      const int X = cx * P + a;
+      r0[a] = (active && !lat_dirichlet(L, X, Y, Z)) ? x[lat_index(L, X, Y, Z)] : T(0);
+      s0[a + N1 * b + NL * c] = r0[a];
+    }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < n3; k += blockDim.x) {  // along z
-    int ab = k % n2, c = k / n2;
-    t1[k] = mass1d(sB, p, c, xs + ab, n2);
-    v[k] = stiff1d(sA, p, c, xs + ab, n2);
+  {  // z-line (a, b): t1 = B_z x, v = A_z x
+#pragma unroll
+    for (int c = 0; c <= P; ++c) r0[c] = s0[l + NL * c];
+    mass_line<P, T>(tb, r0, r1);
+    stiff_line<P, T>(tb, r0, r2);
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < n3; k += blockDim.x) {  // along y
-    int a = k % n1, b = (k / n1) % n1, c = k / n2;
-    int base = a + n2 * c;
-    T uu = mass1d(sB, p, b, t1 + base, n1);
-    u[k] = uu;
-    w[k] = mu * uu + s2 * stiff1d(sA, p, b, t1 + base, n1) + s3 * mass1d(sB, p, b, v + base, n1);
+#pragma unroll
+  for (int c = 0; c <= P; ++c) {
+    s0[l + NL * c] = r1[c];
+    s1[l + NL * c] = r2[c];
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < n3; k += blockDim.x) {  // along x, scatter
-    int a = k % n1, b = (k / n1) % n1, c = k / n2;
-    int base = n1 * (b + n1 * c);
-    T val = s1 * stiff1d(sA, p, a, u + base, 1) + mass1d(sB, p, a, w + base, 1);
-    int X = cx * p + a, Y = cy * p + b, Z = cz * p + c;
-    if (lat_dirichlet(L, X, Y, Z)) continue;
-    long g = lat_index(L, X, Y, Z);
-    bool own = (a != 0 && a != p && b != 0 && b != p && c != 0 && c != p);
-    if (own) y[g] = val;
-    else atomic_add(y + g, val);
+  {  // y-line (a, c): u = B_y t1, w = mu u + s2 A_y t1 + s3 B_y v
+    const int a = l % N1, c = l / N1;
+#pragma unroll
+    for (int b = 0; b <= P; ++b) {
+      r0[b] = s0[a + N1 * b + NL * c];
+      r1[b] = s1[a + N1 * b + NL * c];
+    }
+    T u[N1], t[N1];
+    mass_line<P, T>(tb, r0, u);
+    stiff_line<P, T>(tb, r0, t);
+    mass_line<P, T>(tb, r1, r2);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b <= P; ++b) {
+      s0[a + N1 * b + NL * c] = u[b];
+      s1[a + N1 * b + NL * c] = mu * u[b] + s2c * t[b] + s3c * r2[b];
+    }
+  }
+  __syncthreads();
+  {  // x-line (b, c): y = s1 A_x u + B_x w, scatter
+    const int b = l % N1, c = l / N1;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+      r0[a] = s0[a + N1 * b + NL * c];
+      r1[a] = s1[a + N1 * b + NL * c];
+    }
+    stiff_line<P, T>(tb, r0, r2);
+    mass_line<P, T>(tb, r1, r0);
+    if (!active) return;
+    const int Y = cy * P + b, Z = cz * P + c;
+    const bool line_int = (b != 0 && b != P && c != 0 && c != P);
+    T *eo = ebuf + (long)cell * N3 + N1 * l;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+      const T val = s1c * r2[a] + r0[a];
+      if (line_int && a != 0 && a != P) y[lat_index(L, cx * P + a, Y, Z)] = val;
+      else eo[a] = val;
+    }
   }
 }
 
+// Interface rows of y: sum of the contributions of the (up to 8) cells that hold the
+// DoF, read from the per-cell buffer in a fixed order (z, y, x of the cells);
+// Dirichlet rows copy x.  Rows interior to a cell were written by the cell kernel.
 template <typename T>
-__global__ void k_apply_init(LatDev L, const T *__restrict__ x, T *__restrict__ y, long n) {
+__global__ void k_apply_gather(LatDev L, const T *__restrict__ x, const T *__restrict__ ebuf, T *__restrict__ y,
+                               long n) {
   long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
-  int X = g % L.Nx, Y = (g / L.Nx) % L.Ny, Z = g / ((long)L.Nx * L.Ny);
-  y[g] = lat_dirichlet(L, X, Y, Z) ? x[g] : T(0);
+  const int p = L.p, n1 = p + 1, n3 = n1 * n1 * n1;
+  const int C[3] = {(int)(g % L.Nx), (int)((g / L.Nx) % L.Ny), (int)(g / ((long)L.Nx * L.Ny))};
+  if (C[0] % p != 0 && C[1] % p != 0 && C[2] % p != 0) return;
+  if (lat_dirichlet(L, C[0], C[1], C[2])) {
+    y[g] = x[g];
+    return;
+  }
+  int cl[3][2], lo[3][2], cnt[3];
+  for (int d = 0; d < 3; ++d) {
+    const int nc = ncells_axis(L, d);
+    cnt[d] = 0;
+    if (C[d] % p == 0) {
+      const int c = C[d] / p;
+      if (c - 1 >= 0) {
+        cl[d][cnt[d]] = c - 1;
+        lo[d][cnt[d]++] = p;
+      }
+      if (c < nc) {
+        cl[d][cnt[d]] = c;
+        lo[d][cnt[d]++] = 0;
+      }
+    } else {
+      cl[d][0] = C[d] / p;
+      lo[d][0] = C[d] % p;
+      cnt[d] = 1;
+    }
+  }
+  T acc = 0;
+  for (int k = 0; k < cnt[2]; ++k)
+    for (int j = 0; j < cnt[1]; ++j)
+      for (int i = 0; i < cnt[0]; ++i) {
+        const long cell = cl[0][i] + (long)L.nx * (cl[1][j] + (long)L.ny * cl[2][k]);
+        acc += ebuf[cell * n3 + lo[0][i] + n1 * (lo[1][j] + n1 * lo[2][k])];
+      }
+  y[g] = acc;
 }
 
 // ------------------------------------------------------------------------------------
@@ -171,50 +252,222 @@ __global__ void k_condense_grad(LatDev L, const T *__restrict__ coef, const T *_
 }
 
 // ------------------------------------------------------------------------------------
-// Relaxation step 2 (eq. sc-asm-afw): one workgroup per vertex slot; the IC factor
-// of the slot is staged in LDS, forward and backward substitution by level sets.
+// Relaxation step 2 (eq. sc-asm-afw): L_v L_v^T z_v = rt|_v for every vertex slot.
+// Persistent blocks; every thread keeps the same off-diagonal entries of the
+// factor (value and packed row/column/level) in registers for all its slots, and
+// owns up to four rows.  Forward and backward substitution run level by level
+// (a row only depends on rows of earlier levels); inside a level the entries act
+// in parallel through LDS atomics on the patch vector.
 // ------------------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) k_patch_solve(LatDev L, PatchDev P, const T *__restrict__ factor,
-                                                      const T *__restrict__ rt, T *__restrict__ zbuf) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *Ls = reinterpret_cast<T *>(smem_raw);
-  T *xs = Ls + P.nnz;
-  const int p = L.p;
-  const long vid = blockIdx.x;
+template <typename T, int BS, int KL>
+__global__ void __launch_bounds__(BS) k_patch_solve(LatDev L, PatchDev P, const T *__restrict__ factor,
+                                                     const T *__restrict__ rt, T *__restrict__ zbuf, long nslots) {
+  constexpr int RMAX = 2, NL = 4;  // rows per thread; levels 1..4 carry off-diagonal entries
+  __shared__ T x[RMAX * BS];
+  const int tid = threadIdx.x;
+  const int p = L.p, nrows = P.nrows, nnz = P.nnz, nlev = P.nlev;
+  // entries of level l+1: [elev[l+1], elev[l+2]), thread tid takes elev[l+1] + tid + BS k
+  int rc[NL][KL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l)
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const int e = P.elev[l + 1] + tid + BS * k;
+      rc[l][k] = (l + 1 < nlev && e < P.elev[l + 2]) ? P.rc[e] : -1;
+    }
+  int rlev[RMAX], ro[RMAX][3];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) {
+    const int i = tid + r * BS;
+    rlev[r] = i < nrows ? P.rlev[i] : -1;
+    for (int d = 0; d < 3; ++d) ro[r][d] = i < nrows ? P.off[3 * i + d] : 0;
+  }
   const int nvx = L.nx + 1, nvy = L.ny + 1;
-  const int vx = vid % nvx, vy = (vid / nvx) % nvy, vz = vid / ((long)nvx * nvy);
-  const T *f = factor + vid * (long)P.nnz;
-  for (int k = threadIdx.x; k < P.nnz; k += blockDim.x) Ls[k] = f[k];
-  for (int k = threadIdx.x; k < P.nrows; k += blockDim.x) {
-    int X = vx * p + P.off[3 * k], Y = vy * p + P.off[3 * k + 1], Z = vz * p + P.off[3 * k + 2];
-    bool in = X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
-    xs[k] = (in && !lat_dirichlet(L, X, Y, Z)) ? rt[lat_index(L, X, Y, Z)] : T(0);
-  }
-  __syncthreads();
-  for (int lv = 0; lv < P.nflev; ++lv) {
-    const int b = P.flev_ptr[lv], e = P.flev_ptr[lv + 1];
-    for (int t = b + threadIdx.x; t < e; t += blockDim.x) {
-      int i = P.flev_rows[t];
-      int rs = P.rowptr[i], re = P.rowptr[i + 1] - 1;
-      T s = xs[i];
-      for (int k = rs; k < re; ++k) s -= Ls[k] * xs[P.col[k]];
-      xs[i] = s / Ls[re];
+  for (long slot = blockIdx.x; slot < nslots; slot += gridDim.x) {
+    const T *f = factor + slot * (long)nnz;
+    T v[NL][KL], dg[RMAX];
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+#pragma unroll
+      for (int k = 0; k < KL; ++k)
+        v[l][k] = rc[l][k] >= 0 ? f[nrows + P.elev[l + 1] + tid + BS * k] : T(0);
+    const int vx = slot % nvx, vy = (slot / nvx) % nvy, vz = slot / ((long)nvx * nvy);
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      const int i = tid + r * BS;
+      if (rlev[r] < 0) continue;
+      dg[r] = f[i];
+      const int X = vx * p + ro[r][0], Y = vy * p + ro[r][1], Z = vz * p + ro[r][2];
+      const bool in = X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
+      x[i] = (in && !lat_dirichlet(L, X, Y, Z)) ? rt[lat_index(L, X, Y, Z)] : T(0);
     }
     __syncthreads();
-  }
-  for (int lv = 0; lv < P.nblev; ++lv) {
-    const int b = P.blev_ptr[lv], e = P.blev_ptr[lv + 1];
-    for (int t = b + threadIdx.x; t < e; t += blockDim.x) {
-      int i = P.blev_rows[t];
-      T s = xs[i];
-      for (int k = P.uptr[i]; k < P.uptr[i + 1]; ++k) s -= Ls[P.upos[k]] * xs[P.urow[k]];
-      xs[i] = s / Ls[P.rowptr[i + 1] - 1];
+    // forward: L y = b, level by level
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+      if (rlev[r] == 0) x[tid + r * BS] /= dg[r];
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      if (l + 1 >= nlev) break;
+      T xv[KL];
+#pragma unroll
+      for (int k = 0; k < KL; ++k) xv[k] = rc[l][k] >= 0 ? x[(rc[l][k] >> 10) & 1023] : T(0);
+#pragma unroll
+      for (int k = 0; k < KL; ++k)
+        if (rc[l][k] >= 0) atomicAdd(&x[rc[l][k] & 1023], -v[l][k] * xv[k]);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r)
+        if (rlev[r] == l + 1) x[tid + r * BS] /= dg[r];
+      __syncthreads();
     }
+    // backward: L^T z = y, levels in reverse
+#pragma unroll
+    for (int l = NL - 1; l >= 0; --l) {
+      if (l + 1 >= nlev) continue;
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r)
+        if (rlev[r] == l + 1) x[tid + r * BS] /= dg[r];
+      __syncthreads();
+      T xv[KL];
+#pragma unroll
+      for (int k = 0; k < KL; ++k) xv[k] = rc[l][k] >= 0 ? x[rc[l][k] & 1023] : T(0);
+#pragma unroll
+      for (int k = 0; k < KL; ++k)
+        if (rc[l][k] >= 0) atomicAdd(&x[(rc[l][k] >> 10) & 1023], -v[l][k] * xv[k]);
+      __syncthreads();
+    }
+    T *zo = zbuf + slot * (long)nrows;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+      if (rlev[r] >= 0) {
+        const int i = tid + r * BS;
+        if (rlev[r] == 0) x[i] /= dg[r];
+        zo[i] = x[i];
+      }
     __syncthreads();
   }
-  T *zo = zbuf + vid * (long)P.nrows;
-  for (int k = threadIdx.x; k < P.nrows; k += blockDim.x) zo[k] = xs[k];
+}
+
+// Gather form (no atomics, fixed summation order).  Persistent blocks keep the
+// symbolic lists in LDS (16-bit), stage each slot's factor in LDS and prefetch the
+// next slot's factor into registers while solving the current one (barriers
+// only order LDS, so the prefetch stays in flight).  In level l, G_l lanes work
+// on one row (forward) or one column (backward) and combine by shuffles.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T s, int G) {
+  for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  return s;
+}
+
+template <typename T, int BS, int PF>
+__global__ void __launch_bounds__(BS) k_patch_solve_g(LatDev L, PatchSolveDev S, const T *__restrict__ factor,
+                                                       const T *__restrict__ rt, T *__restrict__ zbuf, long nslots) {
+  constexpr int RMAX = 1024 / BS;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x;
+  const int p = L.p, nrows = S.nrows, nnz = S.nnz, noff = S.noff, nlev = S.nlev;
+  T *V = reinterpret_cast<T *>(smem_raw);
+  T *x = V + nnz;
+  unsigned *blist = reinterpret_cast<unsigned *>(x + nrows);
+  unsigned short *fcol = reinterpret_cast<unsigned short *>(blist + noff);
+  unsigned short *fptr = fcol + noff;
+  unsigned short *bptr = fptr + 2 * nrows;
+  unsigned short *lrows = bptr + nrows + 1;
+  for (int i = tid; i < noff; i += BS) {
+    blist[i] = (unsigned)S.blist[i];
+    fcol[i] = (unsigned short)S.fcol[i];
+  }
+  for (int i = tid; i < 2 * nrows; i += BS) fptr[i] = (unsigned short)S.fptr[i];
+  for (int i = tid; i <= nrows; i += BS) bptr[i] = (unsigned short)S.bptr[i];
+  for (int i = tid; i < nrows; i += BS) lrows[i] = (unsigned short)S.lrows[i];
+  int ro[RMAX][3];
+  bool own[RMAX];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) {
+    const int i = tid + r * BS;
+    own[r] = i < nrows;
+    for (int d = 0; d < 3; ++d) ro[r][d] = own[r] ? S.off[3 * i + d] : 0;
+  }
+  const int nvx = L.nx + 1, nvy = L.ny + 1;
+  T pf[PF], pb[RMAX];
+  // load (into registers) the factor and the gathered right-hand side of a slot
+  auto fetch = [&](long sl) {
+    const T *f = factor + sl * (long)nnz;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) pf[k] = (tid + BS * k < nnz) ? f[tid + BS * k] : T(0);
+    const int vx = sl % nvx, vy = (sl / nvx) % nvy, vz = sl / ((long)nvx * nvy);
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      const int X = vx * p + ro[r][0], Y = vy * p + ro[r][1], Z = vz * p + ro[r][2];
+      const bool in = own[r] && X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
+      pb[r] = (in && !lat_dirichlet(L, X, Y, Z)) ? rt[lat_index(L, X, Y, Z)] : T(0);
+    }
+  };
+  long slot = blockIdx.x;
+  if (slot < nslots) fetch(slot);
+  for (; slot < nslots; slot += gridDim.x) {
+#pragma unroll
+    for (int k = 0; k < PF; ++k)
+      if (tid + BS * k < nnz) V[tid + BS * k] = pf[k];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+      if (own[r]) x[tid + r * BS] = pb[r];
+    const long next = slot + gridDim.x;
+    if (next < nslots) fetch(next);
+    lds_barrier();
+    for (int lv = 0; lv < nlev; ++lv) {  // forward: L y = b
+      const int G = S.G[lv], q = tid & (G - 1), base = S.lptr[lv], nr = S.lptr[lv + 1] - base;
+      for (int gr = tid / G; gr < nr; gr += BS / G) {
+        const int i = lrows[base + gr];
+        T s = 0;
+        const int e1 = fptr[2 * i + 1];
+        int e = fptr[2 * i] + q;
+        for (; e + 3 * G < e1; e += 4 * G) {  // four independent entries per step
+          const int c0 = fcol[e], c1 = fcol[e + G], c2 = fcol[e + 2 * G], c3 = fcol[e + 3 * G];
+          s += V[nrows + e] * x[c0] + V[nrows + e + G] * x[c1] + V[nrows + e + 2 * G] * x[c2] +
+               V[nrows + e + 3 * G] * x[c3];
+        }
+        for (; e < e1; e += G) s += V[nrows + e] * x[fcol[e]];
+        s = group_sum(s, G);
+        if (q == 0) x[i] = (x[i] - s) / V[i];
+      }
+      lds_barrier();
+    }
+    for (int lv = nlev - 1; lv >= 0; --lv) {  // backward: L^T z = y
+      const int G = S.G[lv], q = tid & (G - 1), base = S.lptr[lv], nr = S.lptr[lv + 1] - base;
+      for (int gr = tid / G; gr < nr; gr += BS / G) {
+        const int i = lrows[base + gr];
+        T s = 0;
+        const int k1 = bptr[i + 1];
+        int k = bptr[i] + q;
+        for (; k + 3 * G < k1; k += 4 * G) {
+          const unsigned w0 = blist[k], w1 = blist[k + G], w2 = blist[k + 2 * G], w3 = blist[k + 3 * G];
+          s += V[nrows + (w0 & 0xFFFFu)] * x[w0 >> 16] + V[nrows + (w1 & 0xFFFFu)] * x[w1 >> 16] +
+               V[nrows + (w2 & 0xFFFFu)] * x[w2 >> 16] + V[nrows + (w3 & 0xFFFFu)] * x[w3 >> 16];
+        }
+        for (; k < k1; k += G) {
+          const unsigned w = blist[k];
+          s += V[nrows + (w & 0xFFFFu)] * x[w >> 16];
+        }
+        s = group_sum(s, G);
+        if (q == 0) x[i] = (x[i] - s) / V[i];
+      }
+      lds_barrier();
+    }
+    T *zo = zbuf + slot * (long)nrows;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+      if (own[r]) zo[tid + r * BS] = x[tid + r * BS];
+    lds_barrier();
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -431,8 +684,9 @@ __global__ void __launch_bounds__(256) k_patch_factor(LatDev L, PatchDev P, cons
   double *o64 = f64 + vid * (long)P.nnz;
   float *o32 = f32 + vid * (long)P.nnz;
   for (int k = threadIdx.x; k < P.nnz; k += blockDim.x) {
-    o64[k] = S[k];
-    o32[k] = (float)S[k];
+    int q = P.perm[k];
+    o64[q] = S[k];
+    o32[q] = (float)S[k];
   }
 }
 
@@ -472,49 +726,57 @@ __global__ void k_prolong_add_grad(LatDev L, const double *__restrict__ E, const
   xf[g] += acc;
 }
 
-__global__ void __launch_bounds__(256) k_restrict_grad(LatDev L, const double *__restrict__ E,
-                                                        const double *__restrict__ rf, double *__restrict__ rc) {
-  __shared__ double red[256];
-  const int p = L.p;
-  const int NC[3] = {L.nx + 1, L.ny + 1, L.nz + 1};
-  const long V = blockIdx.x;
-  const int VC[3] = {(int)(V % NC[0]), (int)((V / NC[0]) % NC[1]), (int)(V / ((long)NC[0] * NC[1]))};
-  bool dir = ((L.dir & 1u) && VC[0] == 0) || ((L.dir & 2u) && VC[0] == NC[0] - 1) ||
-             ((L.dir & 4u) && VC[1] == 0) || ((L.dir & 8u) && VC[1] == NC[1] - 1) ||
-             ((L.dir & 16u) && VC[2] == 0) || ((L.dir & 32u) && VC[2] == NC[2] - 1);
-  if (dir) {
-    if (threadIdx.x == 0) rc[V] = 0.0;
-    return;
-  }
-  const int Nd[3] = {L.Nx, L.Ny, L.Nz};
-  int lo[3], ext[3];
-  for (int d = 0; d < 3; ++d) {
-    lo[d] = VC[d] * p - (p - 1);
-    int hi = VC[d] * p + (p - 1);
-    if (lo[d] < 0) lo[d] = 0;
-    if (hi > Nd[d] - 1) hi = Nd[d] - 1;
-    ext[d] = hi - lo[d] + 1;
-  }
-  const int tot = ext[0] * ext[1] * ext[2];
+// Restriction rc = P^T rf as three 1-D passes (x, then y, then z); the weight of a
+// fine coordinate X for coarse vertex V is E[X - (V-1)p][1] left of V p, 1 at V p,
+// E[X - V p][0] right of it.  Fine Dirichlet entries are read as zero, coarse
+// Dirichlet outputs are zero.
+__device__ __forceinline__ double hat_weight(const double *E, int p, int off) {
+  return off < 0 ? E[2 * (off + p) + 1] : (off > 0 ? E[2 * off] : 1.0);
+}
+
+__global__ void k_restrict_x(LatDev L, const double *__restrict__ E, const double *__restrict__ rf,
+                             double *__restrict__ t1, long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p = L.p, NCX = L.nx + 1;
+  const int VX = i % NCX;
+  const long yz = i / NCX;
+  const int Y = yz % L.Ny, Z = yz / L.Ny;
+  const int lo = max(0, VX * p - (p - 1)), hi = min(L.Nx - 1, VX * p + (p - 1));
   double acc = 0.0;
-  for (int k = threadIdx.x; k < tot; k += blockDim.x) {
-    int G[3] = {lo[0] + k % ext[0], lo[1] + (k / ext[0]) % ext[1], lo[2] + k / (ext[0] * ext[1])};
-    if (lat_dirichlet(L, G[0], G[1], G[2])) continue;
-    double wt = 1.0;
-    for (int d = 0; d < 3; ++d) {
-      int off = G[d] - VC[d] * p;
-      if (off < 0) wt *= E[2 * (off + p) + 1];
-      else if (off > 0) wt *= E[2 * off];
-    }
-    acc += wt * rf[G[0] + (long)L.Nx * (G[1] + (long)L.Ny * G[2])];
+  for (int X = lo; X <= hi; ++X)
+    if (!lat_dirichlet(L, X, Y, Z)) acc += hat_weight(E, p, X - VX * p) * rf[X + (long)L.Nx * yz];
+  t1[i] = acc;
+}
+
+__global__ void k_restrict_y(LatDev L, const double *__restrict__ E, const double *__restrict__ t1,
+                             double *__restrict__ t2, long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p = L.p, NCX = L.nx + 1, NCY = L.ny + 1;
+  const int VX = i % NCX, VY = (i / NCX) % NCY;
+  const int Z = i / ((long)NCX * NCY);
+  const int lo = max(0, VY * p - (p - 1)), hi = min(L.Ny - 1, VY * p + (p - 1));
+  double acc = 0.0;
+  for (int Y = lo; Y <= hi; ++Y) acc += hat_weight(E, p, Y - VY * p) * t1[VX + (long)NCX * (Y + (long)L.Ny * Z)];
+  t2[i] = acc;
+}
+
+__global__ void k_restrict_z(LatDev L, const double *__restrict__ E, const double *__restrict__ t2,
+                             double *__restrict__ rc, long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p = L.p, NC[3] = {L.nx + 1, L.ny + 1, L.nz + 1};
+  const int VX = i % NC[0], VY = (i / NC[0]) % NC[1], VZ = i / ((long)NC[0] * NC[1]);
+  const bool dir = ((L.dir & 1u) && VX == 0) || ((L.dir & 2u) && VX == NC[0] - 1) ||
+                   ((L.dir & 4u) && VY == 0) || ((L.dir & 8u) && VY == NC[1] - 1) ||
+                   ((L.dir & 16u) && VZ == 0) || ((L.dir & 32u) && VZ == NC[2] - 1);
+  double acc = 0.0;
+  if (!dir) {
+    const int lo = max(0, VZ * p - (p - 1)), hi = min(L.Nz - 1, VZ * p + (p - 1));
+    for (int Z = lo; Z <= hi; ++Z) acc += hat_weight(E, p, Z - VZ * p) * t2[VX + (long)NC[0] * (VY + (long)NC[1] * Z)];
   }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) rc[V] = red[0];
+  rc[i] = acc;
 }
 
 __global__ void k_dirichlet_copy(LatDev L, const double *__restrict__ r, double *__restrict__ z, long n) {
@@ -531,15 +793,38 @@ inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 // ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
+template <int P, typename T>
+static void apply_kron(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x, T *y,
+                       T *ebuf, hipStream_t s) {
+  constexpr int NL = (P + 1) * (P + 1);
+  constexpr int CPB = NL >= 256 ? 1 : 256 / NL;
+  Tab1D<P, T> tb;
+  for (int i = 0; i < (P + 1) * (P + 1); ++i) {
+    tb.B[i] = (T)Bh[i];
+    tb.A[i] = (T)Ah[i];
+  }
+  const int ncells = L.nx * L.ny * L.nz;
+  const unsigned grid = (unsigned)((ncells + CPB - 1) / CPB);
+  k_apply_kron<P, T, CPB><<<grid, CPB * NL, 0, s>>>(L, tb, coef, x, y, ebuf, ncells);
+}
+
 template <typename T>
-void launch_apply_grad(const LatDev &L, const T *coef, const T *B, const T *A, const T *x, T *y,
-                       hipStream_t s) {
+void launch_apply_grad(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x, T *y,
+                       T *ebuf, hipStream_t s) {
+  switch (L.p) {
+    case 1: apply_kron<1, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
+    case 2: apply_kron<2, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
+    case 3: apply_kron<3, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
+    case 4: apply_kron<4, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
+    case 5: apply_kron<5, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
+    case 6: apply_kron<6, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
+    case 7: apply_kron<7, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
+    case 8: apply_kron<8, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
+    case 9: apply_kron<9, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
+    default: break;
+  }
   long n = (long)L.Nx * L.Ny * L.Nz;
-  k_apply_init<T><<<nblocks(n, 256), 256, 0, s>>>(L, x, y, n);
-  const int n1 = L.p + 1, n3 = n1 * n1 * n1;
-  int bs = n3 >= 256 ? 256 : (n3 >= 128 ? 128 : 64);
-  size_t shm = sizeof(T) * (2 * n1 * n1 + 5 * n3);
-  k_apply_grad<T><<<L.nx * L.ny * L.nz, bs, shm, s>>>(L, coef, B, A, x, y);
+  k_apply_gather<T><<<nblocks(n, 256), 256, 0, s>>>(L, x, ebuf, y, n);
 }
 
 template <typename T>
@@ -549,13 +834,83 @@ void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *l
   k_condense_grad<T><<<nblocks(n, 256), 256, 0, s>>>(L, coef, A, lam, r, rt, n);
 }
 
+int device_cu_count() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+template <typename T, int KL>
+static void patch_solve_k(const LatDev &L, const PatchDev &P, const T *factor, const T *rt, T *zbuf, long nv,
+                          hipStream_t s) {
+  constexpr int BS = 512;
+  long grid = (long)device_cu_count() * 2;
+  if (grid > nv) grid = nv;
+  k_patch_solve<T, BS, KL><<<(unsigned)grid, BS, 0, s>>>(L, P, factor, rt, zbuf, nv);
+}
+
+template <typename T, int BS, int PF>
+static void patch_solve_g(const LatDev &L, const PatchSolveDev &S0, const T *factor, const T *rt, T *zbuf, long nv,
+                          size_t shm, int per_cu, hipStream_t s) {
+  // lanes per row in each level: the largest power of two <= 64 that fits the block
+  PatchSolveDev S = S0;
+  for (int l = 0; l < 5; ++l) {
+    const int nr = l < S.nlev ? S.lptr[l + 1] - S.lptr[l] : 0;
+    int G = 1;
+    while (G < 64 && nr * (2 * G) <= BS) G *= 2;
+    S.G[l] = G;
+  }
+  if (shm > 65536)
+    hipFuncSetAttribute((const void *)k_patch_solve_g<T, BS, PF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  long grid = (long)device_cu_count() * per_cu;
+  if (grid > nv) grid = nv;
+  k_patch_solve_g<T, BS, PF><<<(unsigned)grid, BS, shm, s>>>(L, S, factor, rt, zbuf, nv);
+}
+
+size_t patch_solve_lds_bytes(const PatchSolveDev &S, size_t elem) {
+  return elem * (size_t)(S.nnz + S.nrows) + 4 * (size_t)S.noff + 2 * (size_t)S.noff + 4 * (size_t)S.nrows +
+         2 * (size_t)(S.nrows + 1) + 2 * (size_t)S.nrows;
+}
+
 template <typename T>
-void launch_patch_solve(const LatDev &L, const PatchDev &P, const T *factor, const T *rt, T *zbuf,
-                        hipStream_t s) {
+void launch_patch_solve(const LatDev &L, const PatchDev &P, const PatchSolveDev &S, const T *factor, const T *rt,
+                        T *zbuf, hipStream_t s) {
   long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
-  size_t shm = sizeof(T) * (P.nnz + P.nrows);
-  if (shm > 65536) hipFuncSetAttribute((const void *)k_patch_solve<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  k_patch_solve<T><<<(unsigned)nv, 256, shm, s>>>(L, P, factor, rt, zbuf);
+  const size_t shm = patch_solve_lds_bytes(S, sizeof(T));
+  if (shm <= 160 * 1024 - 1024 && S.nrows <= 1024) {
+    // one 1024-thread block per CU when a staged factor needs more than half the LDS
+    const bool big = shm > 78 * 1024;
+    const int per_cu = big ? 1 : 2;
+    const int pf = big ? (S.nnz + 1023) / 1024 : (S.nnz + 511) / 512;
+    if (big) {
+      if (pf <= 4) patch_solve_g<T, 1024, 4>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
+      else if (pf <= 8) patch_solve_g<T, 1024, 8>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
+      else patch_solve_g<T, 1024, 16>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
+    } else {
+      if (pf <= 4) patch_solve_g<T, 512, 4>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
+      else if (pf <= 8) patch_solve_g<T, 512, 8>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
+      else if (pf <= 16) patch_solve_g<T, 512, 16>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
+      else if (pf <= 24) patch_solve_g<T, 512, 24>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
+      else patch_solve_g<T, 512, 32>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
+    }
+    return;
+  }
+  // factors too large to stage in LDS: level-parallel form with register-resident entries
+  int mx = 0;
+  for (int l = 1; l < P.nlev; ++l) mx = mx > P.elev[l + 1] - P.elev[l] ? mx : P.elev[l + 1] - P.elev[l];
+  const int need = (mx + 511) / 512;
+  if (need <= 1) patch_solve_k<T, 1>(L, P, factor, rt, zbuf, nv, s);
+  else if (need <= 2) patch_solve_k<T, 2>(L, P, factor, rt, zbuf, nv, s);
+  else if (need <= 4) patch_solve_k<T, 4>(L, P, factor, rt, zbuf, nv, s);
+  else if (need <= 8) patch_solve_k<T, 8>(L, P, factor, rt, zbuf, nv, s);
+  else if (need <= 12) patch_solve_k<T, 12>(L, P, factor, rt, zbuf, nv, s);
+  else patch_solve_k<T, 20>(L, P, factor, rt, zbuf, nv, s);
 }
 
 template <typename T>
@@ -587,23 +942,27 @@ void launch_prolong_add_grad(const LatDev &L, const double *E, const double *xc,
   k_prolong_add_grad<<<nblocks(n, 256), 256, 0, s>>>(L, E, xc, xf, n);
 }
 
-void launch_restrict_grad(const LatDev &L, const double *E, const double *rf, double *rc, hipStream_t s) {
-  long nc = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
-  k_restrict_grad<<<(unsigned)nc, 256, 0, s>>>(L, E, rf, rc);
+void launch_restrict_grad(const LatDev &L, const double *E, const double *rf, double *rc, double *t1, double *t2,
+                          hipStream_t s) {
+  const long n1 = (long)(L.nx + 1) * L.Ny * L.Nz, n2 = (long)(L.nx + 1) * (L.ny + 1) * L.Nz,
+             n3 = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
+  k_restrict_x<<<nblocks(n1, 256), 256, 0, s>>>(L, E, rf, t1, n1);
+  k_restrict_y<<<nblocks(n2, 256), 256, 0, s>>>(L, E, t1, t2, n2);
+  k_restrict_z<<<nblocks(n3, 256), 256, 0, s>>>(L, E, t2, rc, n3);
 }
 
 template void launch_apply_grad<double>(const LatDev &, const double *, const double *, const double *,
-                                        const double *, double *, hipStream_t);
-template void launch_apply_grad<float>(const LatDev &, const float *, const float *, const float *,
-                                       const float *, float *, hipStream_t);
+                                        const double *, double *, double *, hipStream_t);
+template void launch_apply_grad<float>(const LatDev &, const float *, const double *, const double *,
+                                       const float *, float *, float *, hipStream_t);
 template void launch_condense_grad<double>(const LatDev &, const double *, const double *, const double *,
                                            const double *, double *, hipStream_t);
 template void launch_condense_grad<float>(const LatDev &, const float *, const float *, const float *,
                                           const float *, float *, hipStream_t);
-template void launch_patch_solve<double>(const LatDev &, const PatchDev &, const double *, const double *,
-                                         double *, hipStream_t);
-template void launch_patch_solve<float>(const LatDev &, const PatchDev &, const float *, const float *,
-                                        float *, hipStream_t);
+template void launch_patch_solve<double>(const LatDev &, const PatchDev &, const PatchSolveDev &, const double *,
+                                         const double *, double *, hipStream_t);
+template void launch_patch_solve<float>(const LatDev &, const PatchDev &, const PatchSolveDev &, const float *,
+                                        const float *, float *, hipStream_t);
 template void launch_expand_grad<double>(const LatDev &, const PatchDev &, const double *, const double *,
                                          const double *, const double *, const double *, double *,
                                          hipStream_t);

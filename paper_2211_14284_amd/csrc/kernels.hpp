@@ -23,6 +23,20 @@ struct PatchDev {
   const int *erow;                 // row of every CSR entry
   const int *uptr, *urow, *upos;   // column access of the lower factor
   const int *flev_ptr, *flev_rows, *blev_ptr, *blev_rows;
+  // level-sorted storage of the factor values (see PatchSymbolic)
+  int nlev, noff;
+  int elev[6];                     // off-diagonal entries of level l: [elev[l], elev[l+1]) (nlev <= 5)
+  const int *rc;                   // noff packed (row | col << 10 | level << 20)
+  const int *rlev;                 // forward level of every row
+  const int *perm;                 // CSR position -> storage position
+};
+
+// Gather form of the patch triangular solves (see PatchSymbolic).
+struct PatchSolveDev {
+  int nrows, nnz, noff, nlev;
+  int lptr[6];                     // rows of level l: lrows[lptr[l] .. lptr[l+1]-1]
+  int G[5];                        // lanes per row in level l (power of two <= 64)
+  const int *off, *fptr, *fcol, *bptr, *blist, *lrows;
 };
 
 // ---- vectors ------------------------------------------------------------------
@@ -40,15 +54,19 @@ void launch_dots(int npairs, const double *const *xs, const double *const *ys, i
 int dots_partials_size();
 
 // ---- H(grad) operator and relaxation ----------------------------------------------
+// Bh, Ah: host copies of the 1-D FDM mass and stiffness ((p+1)^2, row-major);
+// ebuf: per-cell scratch of ncells*(p+1)^3 values for the interface contributions
 template <typename T>
-void launch_apply_grad(const LatDev &L, const T *coef, const T *B, const T *A, const T *x, T *y,
-                       hipStream_t s);
+void launch_apply_grad(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x, T *y,
+                       T *ebuf, hipStream_t s);
 template <typename T>
 void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r,
                           T *rt, hipStream_t s);
 template <typename T>
-void launch_patch_solve(const LatDev &L, const PatchDev &P, const T *factor, const T *rt, T *zbuf,
-                        hipStream_t s);
+void launch_patch_solve(const LatDev &L, const PatchDev &P, const PatchSolveDev &S, const T *factor, const T *rt,
+                        T *zbuf, hipStream_t s);
+// number of compute units of the current device (cached), for persistent grids
+int device_cu_count();
 template <typename T>
 void launch_expand_grad(const LatDev &L, const PatchDev &P, const T *coef, const T *A,
                         const T *lam, const T *r, const T *zbuf, T *z, hipStream_t s);
@@ -66,8 +84,9 @@ void launch_dirichlet_copy(const LatDev &L, const double *r, double *z, hipStrea
 // ---- p-transfer (Q_1 <-> Q_p) -------------------------------------------------------
 void launch_prolong_add_grad(const LatDev &L, const double *E, const double *xc, double *xf,
                              hipStream_t s);
-void launch_restrict_grad(const LatDev &L, const double *E, const double *rf, double *rc,
-                          hipStream_t s);
+// t1: (nx+1)*Ny*Nz and t2: (nx+1)*(ny+1)*Nz scratch arrays
+void launch_restrict_grad(const LatDev &L, const double *E, const double *rf, double *rc, double *t1,
+                          double *t2, hipStream_t s);
 
 // ---- coarse block-tridiagonal LDL^T ---------------------------------------------------
 // Dense m x m blocks, row-major; C and Ct are m x 9 stencil couplings to the
@@ -75,10 +94,14 @@ void launch_restrict_grad(const LatDev &L, const double *E, const double *rf, do
 void launch_schur_update(int m, int mx, const double *Wprev, const double *C, const double *Akk,
                          double *Dk, hipStream_t s);
 void launch_sweep_inverse(int m, double *W, double *tmp, int *status, hipStream_t s);
-void launch_coarse_fwd(int m, int mx, const double *W, const double *C, const double *r,
-                       const double *vprev, double *v, hipStream_t s);
-void launch_coarse_bwd(int m, int mx, const double *W, const double *Ct, const double *v,
-                       const double *xnext, double *x, hipStream_t s);
+// Whole block-tridiagonal solve (forward and backward sweeps over nb planes) in
+// one cooperative launch; bar: two zero-initialised unsigned counters owned by
+// the problem; returns 0 on a successful launch.
+// nbt: m*9 in-plane neighbour table (-1 = outside the plane); flags: 4 words per
+// block (zero-initialised once); *gen: host-side generation counter of the flags
+int launch_coarse_solve(int m, int nb, const double *W, const double *C, const double *Ct, const int *nbt,
+                        const double *r, double *v, double *x, unsigned *flags, unsigned *gen, int *status,
+                        hipStream_t s);
 // gather / scatter between the coarse lattice and the free-box block vector
 void launch_coarse_gather(int nfree, int bx0, int by0, int bz0, int mx, int my, int NX, int NY,
                           const double *rc, double *blk, hipStream_t s);

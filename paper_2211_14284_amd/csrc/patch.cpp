@@ -6,6 +6,7 @@
 #include "patch.hpp"
 
 #include <algorithm>
+#include <array>
 
 #include "lattice.hpp"
 
@@ -82,6 +83,54 @@ void build_patch_symbolic(int p, PatchSymbolic &ps) {
   };
   group(flev, fmax, ps.flev_ptr, ps.flev_rows);
   group(blev, bmax, ps.blev_ptr, ps.blev_rows);
+  // storage order for the level-parallel solve
+  ps.nlev = fmax + 1;
+  ps.level = flev;
+  ps.noff = ps.nnz - n;
+  ps.perm.assign(ps.nnz, -1);
+  // off-diagonal entries sorted by (level of the row, row, column)
+  std::vector<std::array<int, 4>> offd;  // level, row, col, csr position
+  for (int r = 0; r < n; ++r)
+    for (int k = ps.rowptr[r]; k < ps.rowptr[r + 1]; ++k) {
+      int c = ps.col[k];
+      if (c == r) ps.perm[k] = r;
+      else offd.push_back({flev[r], r, c, k});
+    }
+  std::sort(offd.begin(), offd.end());
+  ps.rc.resize(offd.size());
+  ps.fcol.resize(offd.size());
+  ps.fptr.assign(n + 1, 0);
+  std::vector<std::vector<std::pair<int, int>>> colent(n);  // (j, storage index)
+  for (size_t e = 0; e < offd.size(); ++e) {
+    int r = offd[e][1], c = offd[e][2], k = offd[e][3];
+    ps.perm[k] = n + (int)e;
+    ps.rc[e] = r | (c << 10) | (flev[r] << 20);
+    ps.fcol[e] = c;
+    ps.fptr[r + 1]++;
+    colent[c].push_back({r, (int)e});
+  }
+  // rows of one level are contiguous and ordered, so the counts turn into offsets
+  // in level order; fptr is indexed by row
+  {
+    std::vector<int> start(n, 0);
+    for (size_t e = 0; e < offd.size(); ++e) {
+      int r = offd[e][1];
+      if (e == 0 || offd[e - 1][1] != r) start[r] = (int)e;
+    }
+    std::vector<int> cnt(ps.fptr.begin() + 1, ps.fptr.end());
+    ps.fptr.assign(2 * n, 0);  // (start, end) per row
+    for (int r = 0; r < n; ++r) {
+      ps.fptr[2 * r] = cnt[r] ? start[r] : 0;
+      ps.fptr[2 * r + 1] = ps.fptr[2 * r] + cnt[r];
+    }
+  }
+  ps.bptr.assign(n + 1, 0);
+  ps.blist.clear();
+  for (int i = 0; i < n; ++i) {
+    std::sort(colent[i].begin(), colent[i].end());
+    for (auto &pr : colent[i]) ps.blist.push_back(pr.second | (pr.first << 16));
+    ps.bptr[i + 1] = (int)ps.blist.size();
+  }
 }
 
 }  // namespace rz

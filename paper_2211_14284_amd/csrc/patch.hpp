@@ -17,7 +17,18 @@ struct PatchSymbolic {
   std::vector<int> uptr, urow, upos;
   // level schedules of the forward and backward triangular solves
   std::vector<int> flev_ptr, flev_rows, blev_ptr, blev_rows;
-  // for the IC factorisation: rows grouped by forward level (same as flev)
+  // Storage order of a slot's factor values: the nrows diagonal entries (row
+  // order), then the off-diagonal entries sorted by (forward level of the row,
+  // row, column).  perm[k] = storage position of CSR entry k.
+  int nlev = 0, noff = 0;
+  std::vector<int> level;          // forward level of every row
+  std::vector<int> perm;           // nnz
+  std::vector<int> rc;             // noff packed entries: row | col << 10 | level(row) << 20
+  // gather form of the two sweeps, in storage numbering of the off-diagonals:
+  // row i's entries (L_ij, j < i) are fptr[2i] .. fptr[2i+1]-1 with columns fcol;
+  // column i's entries (L_ji, j > i) are listed in blist[bptr[i] .. bptr[i+1]-1]
+  // as (storage index | j << 16), j ascending
+  std::vector<int> fptr, fcol, bptr, blist;
 };
 
 // Build the layout and the static-condensation pattern of a full (untruncated)

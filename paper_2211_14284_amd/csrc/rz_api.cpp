@@ -50,17 +50,21 @@ struct rz_problem {
   // device
   LatDev L{};
   PatchDev P{};
+  PatchSolveDev PS{};
   std::vector<void *> allocs;
   double *coef64 = nullptr, *B64 = nullptr, *A64 = nullptr, *lam64 = nullptr, *E64 = nullptr;
   float *coef32 = nullptr, *B32 = nullptr, *A32 = nullptr, *lam32 = nullptr;
-  double *f64 = nullptr;
-  float *f32 = nullptr;
+  double *f64 = nullptr, *eb64 = nullptr;
+  float *f32 = nullptr, *eb32 = nullptr;
   double *rt64 = nullptr, *zb64 = nullptr;
   float *rt32 = nullptr, *zb32 = nullptr, *r32 = nullptr, *z32 = nullptr;
-  double *vt = nullptr, *vaz = nullptr, *vr = nullptr, *rc = nullptr, *xc = nullptr;
+  double *vt = nullptr, *vaz = nullptr, *vr = nullptr, *rc = nullptr, *xc = nullptr, *rt1 = nullptr, *rt2 = nullptr;
   // coarse
   int cm = 0, cmx = 0, cmy = 0, cmz = 0, cbx0 = 0, cby0 = 0, cbz0 = 0, cNX = 0, cNY = 0, cNZ = 0;
   double *cW = nullptr, *cC = nullptr, *cCt = nullptr, *cr = nullptr, *cv = nullptr, *cx = nullptr;
+  unsigned *cbar = nullptr;
+  unsigned cgen = 0;
+  int *cnbt = nullptr;
   // krylov
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kAp = nullptr, *kro = nullptr;
   double *partials = nullptr, *dots = nullptr;
@@ -196,7 +200,7 @@ void v_scale_copy(rz_problem *h, double a, const double *x, double *y) {
 // ---------------------------------------------------------------------------------------
 rz_status do_apply64(rz_problem *h, const double *x, double *y) {
   Timed t(h, RZ_K_APPLY);
-  launch_apply_grad<double>(h->L, h->coef64, h->B64, h->A64, x, y, h->ctx->stream);
+  launch_apply_grad<double>(h->L, h->coef64, h->t.B.data(), h->t.A.data(), x, y, h->eb64, h->ctx->stream);
   return RZ_OK;
 }
 
@@ -210,7 +214,7 @@ void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T
   }
   {
     Timed t(h, RZ_K_PATCH);
-    launch_patch_solve<T>(h->L, h->P, f, rt, zb, s);
+    launch_patch_solve<T>(h->L, h->P, h->PS, f, rt, zb, s);
   }
   {
     Timed t(h, RZ_K_EXPAND);
@@ -245,12 +249,9 @@ rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv) {
   const int m = h->cm, nb = h->cmz;
   const size_t mm = (size_t)m * m;
   launch_coarse_gather(m * nb, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cNX, h->cNY, rcv, h->cr, s);
-  for (int k = 0; k < nb; ++k)
-    launch_coarse_fwd(m, h->cmx, h->cW + k * mm, h->cC + (size_t)k * m * 9, h->cr + (size_t)k * m,
-                      k ? h->cv + (size_t)(k - 1) * m : nullptr, h->cv + (size_t)k * m, s);
-  for (int k = nb - 1; k >= 0; --k)
-    launch_coarse_bwd(m, h->cmx, h->cW + k * mm, h->cCt + (size_t)k * m * 9, h->cv + (size_t)k * m,
-                      k < nb - 1 ? h->cx + (size_t)(k + 1) * m : nullptr, h->cx + (size_t)k * m, s);
+  (void)mm;
+  if (launch_coarse_solve(m, nb, h->cW, h->cC, h->cCt, h->cnbt, h->cr, h->cv, h->cx, h->cbar, &h->cgen, h->status, s))
+    return fail(h->ctx, RZ_ERR_HIP, "cooperative launch of the coarse solve failed");
   launch_coarse_scatter((int)h->ncoarse, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cmz, h->cNX, h->cNY,
                         h->cx, xcv, s);
   return RZ_OK;
@@ -266,7 +267,7 @@ rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
   v_sub(h, r, h->vaz, h->vr);              // r1 = r - A z
   {
     Timed tm(h, RZ_K_TRANSFER);
-    launch_restrict_grad(h->L, h->E64, h->vr, h->rc, s);
+    launch_restrict_grad(h->L, h->E64, h->vr, h->rc, h->rt1, h->rt2, s);
   }
   do_coarse(h, h->rc, h->xc);
   {
@@ -437,6 +438,15 @@ rz_status setup_coarse(rz_problem *h) {
       }
   if ((e = upload(h, &h->cC, C))) return e;
   if ((e = upload(h, &h->cCt, Ct))) return e;
+  {
+    std::vector<int> nbt((size_t)m * 9, -1);
+    for (int a_ = 0; a_ < m; ++a_)
+      for (int j = 0; j < 9; ++j) {
+        int bx = a_ % h->cmx + j % 3 - 1, by = a_ / h->cmx + j / 3 - 1;
+        if (bx >= 0 && bx < h->cmx && by >= 0 && by < h->cmy) nbt[(size_t)a_ * 9 + j] = bx + h->cmx * by;
+      }
+    if ((e = upload(h, &h->cnbt, nbt))) return e;
+  }
   double *Akk = nullptr, *tmp = nullptr;
   if ((e = dalloc(h, &Akk, (size_t)m * m))) return e;
   if ((e = dalloc(h, &tmp, (size_t)m * m))) return e;
@@ -467,6 +477,10 @@ rz_status setup_coarse(rz_problem *h) {
   if ((e = dalloc(h, &h->cr, nfree))) return e;
   if ((e = dalloc(h, &h->cv, nfree))) return e;
   if ((e = dalloc(h, &h->cx, nfree))) return e;
+  const size_t nflags = 4 * (size_t)((m + 15) / 16);
+  if ((e = dalloc(h, &h->cbar, nflags))) return e;
+  HIPCALL(h, hipMemsetAsync(h->cbar, 0, nflags * sizeof(unsigned), s));
+  HIPCALL(h, hipStreamSynchronize(s));
   return RZ_OK;
 }
 
@@ -652,14 +666,41 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
   };
   size_t o_off = push(ps.off), o_rp = push(ps.rowptr), o_col = push(ps.col), o_er = push(h->erow),
          o_up = push(ps.uptr), o_ur = push(ps.urow), o_upos = push(ps.upos), o_fp = push(ps.flev_ptr),
-         o_fr = push(ps.flev_rows), o_bp = push(ps.blev_ptr), o_br = push(ps.blev_rows);
+         o_fr = push(ps.flev_rows), o_bp = push(ps.blev_ptr), o_br = push(ps.blev_rows), o_rc = push(ps.rc),
+         o_lv = push(ps.level), o_pm = push(ps.perm), o_gfp = push(ps.fptr), o_gfc = push(ps.fcol),
+         o_gbp = push(ps.bptr), o_gbl = push(ps.blist);
   int *dsym = nullptr;
   if ((e = upload(h, &dsym, sym))) return bail(e);
   h->P = PatchDev{ps.nrows, ps.nnz, (int)ps.flev_ptr.size() - 1, (int)ps.blev_ptr.size() - 1,
                   dsym + o_off, dsym + o_rp, dsym + o_col, dsym + o_er, dsym + o_up, dsym + o_ur, dsym + o_upos,
-                  dsym + o_fp, dsym + o_fr, dsym + o_bp, dsym + o_br};
+                  dsym + o_fp, dsym + o_fr, dsym + o_bp, dsym + o_br, ps.nlev, ps.noff, {0, 0, 0, 0, 0, 0},
+                  dsym + o_rc, dsym + o_lv, dsym + o_pm};
+  if (ps.nlev > 5) return bail(fail(ctx, RZ_ERR_ARG, "patch level schedule deeper than 5"));
+  {
+    PatchSolveDev &S = h->PS;
+    S.nrows = ps.nrows;
+    S.nnz = ps.nnz;
+    S.noff = ps.noff;
+    S.nlev = ps.nlev;
+    for (int l = 0; l < 6; ++l) S.lptr[l] = l < (int)ps.flev_ptr.size() ? ps.flev_ptr[l] : ps.nrows;
+    for (int l = 0; l < 5; ++l) S.G[l] = 1;  // lane-group sizes are chosen by the launcher
+    S.off = dsym + o_off;
+    S.fptr = dsym + o_gfp;
+    S.fcol = dsym + o_gfc;
+    S.bptr = dsym + o_gbp;
+    S.blist = dsym + o_gbl;
+    S.lrows = dsym + o_fr;
+  }
+  for (int l = 0; l <= 5; ++l) {
+    int cnt = 0;
+    for (int v : ps.rc)
+      if ((v >> 20) < l) ++cnt;
+    h->P.elev[l] = cnt;
+  }
   const size_t nf = (size_t)h->nvert * ps.nnz, nzb = (size_t)h->nvert * ps.nrows;
-  if ((e = dalloc(h, &h->f64, nf)) || (e = dalloc(h, &h->f32, nf)) || (e = dalloc(h, &h->zb64, nzb)) ||
+  const size_t neb = (size_t)h->ncells * (p + 1) * (p + 1) * (p + 1);
+  if ((e = dalloc(h, &h->eb64, neb)) || (e = dalloc(h, &h->eb32, neb)) || (e = dalloc(h, &h->f64, nf)) ||
+      (e = dalloc(h, &h->f32, nf)) || (e = dalloc(h, &h->zb64, nzb)) ||
       (e = dalloc(h, &h->zb32, nzb)) || (e = dalloc(h, &h->rt64, h->ndofs)) || (e = dalloc(h, &h->rt32, h->ndofs)) ||
       (e = dalloc(h, &h->r32, h->ndofs)) || (e = dalloc(h, &h->z32, h->ndofs)) || (e = dalloc(h, &h->vt, h->ndofs)) ||
       (e = dalloc(h, &h->vaz, h->ndofs)) || (e = dalloc(h, &h->vr, h->ndofs)) || (e = dalloc(h, &h->kr, h->ndofs)) ||
@@ -679,7 +720,9 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
     std::snprintf(msg, sizeof msg, "incomplete Cholesky breakdown in vertex patch %d", stv - 1);
     return bail(fail(ctx, RZ_ERR_BREAKDOWN, msg));
   }
-  if ((e = dalloc(h, &h->rc, (size_t)(h->nx + 1) * (h->ny + 1) * (h->nz + 1))) ||
+  if ((e = dalloc(h, &h->rt1, (size_t)(h->nx + 1) * h->Ny * h->Nz)) ||
+      (e = dalloc(h, &h->rt2, (size_t)(h->nx + 1) * (h->ny + 1) * h->Nz)) ||
+      (e = dalloc(h, &h->rc, (size_t)(h->nx + 1) * (h->ny + 1) * (h->nz + 1))) ||
       (e = dalloc(h, &h->xc, (size_t)(h->nx + 1) * (h->ny + 1) * (h->nz + 1))))
     return bail(e);
   if ((e = setup_coarse(h))) return bail(e);
@@ -722,8 +765,9 @@ rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t) {
   if (!x || !y || x == y) return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad vectors");
   if (t == RZ_F64) return do_apply64(h, static_cast<const double *>(x), static_cast<double *>(y));
   if (t == RZ_F32) {
-    launch_apply_grad<float>(h->L, h->coef32, h->B32, h->A32, static_cast<const float *>(x), static_cast<float *>(y),
-                             h->ctx->stream);
+    Timed t(h, RZ_K_APPLY);
+    launch_apply_grad<float>(h->L, h->coef32, h->t.B.data(), h->t.A.data(), static_cast<const float *>(x),
+                             static_cast<float *>(y), h->eb32, h->ctx->stream);
     return RZ_OK;
   }
   return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad dtype");
@@ -750,7 +794,7 @@ rz_status rz_restrict(rz_problem *h, const double *rf, double *rcv) {
   rz_status e = require_device(h);
   if (e) return e;
   if (!rf || !rcv) return fail(h->ctx, RZ_ERR_ARG, "rz_restrict: bad vectors");
-  launch_restrict_grad(h->L, h->E64, rf, rcv, h->ctx->stream);
+  launch_restrict_grad(h->L, h->E64, rf, rcv, h->rt1, h->rt2, h->ctx->stream);
   return RZ_OK;
 }
 
@@ -943,7 +987,7 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
             int pr[2] = {loc[r], loc[c]};
             put(pr, sizeof pr);
           } else {
-            put(&vals[k], sizeof(double));
+            put(&vals[h->ps.perm[k]], sizeof(double));
           }
         }
       }
