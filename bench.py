@@ -53,8 +53,9 @@ def kernel_bytes(pb, sz, n):
         "apply": 2 * nd * sz + 6 * nc * sz,
         # r read once, interface right-hand side written once
         "condense": (nd + niface) * sz,
-        # every slot: its factor (nnz values) once, its interface vector in and out
-        "patch": ns * (nnz + 2 * nrows) * sz,
+        # every slot: the off-diagonal factor entries once per sweep (forward and
+        # backward), the diagonal once, its interface vector in and out
+        "patch": ns * (2 * (nnz - nrows) + 3 * nrows) * sz,
         # patch solutions read once, r read once, z written once
         "expand": (ns * nrows + 2 * nd) * sz,
         # dense inverse diagonal blocks of the coarse LDL^T, read in both sweeps

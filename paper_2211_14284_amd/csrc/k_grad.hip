@@ -253,220 +253,72 @@ __global__ void k_condense_grad(LatDev L, const T *__restrict__ coef, const T *_
 
 // ------------------------------------------------------------------------------------
 // Relaxation step 2 (eq. sc-asm-afw): L_v L_v^T z_v = rt|_v for every vertex slot.
-// Persistent blocks; every thread keeps the same off-diagonal entries of the
-// factor (value and packed row/column/level) in registers for all its slots, and
-// owns up to four rows.  Forward and backward substitution run level by level
-// (a row only depends on rows of earlier levels); inside a level the entries act
-// in parallel through LDS atomics on the patch vector.
+// One wavefront per slot, no block barriers: the passes of the wavefront schedule
+// (levels of the forward sweep, then of the backward sweep) run in program order
+// on the slot's vector in LDS, which only this wavefront touches.  The factor
+// values stream in ELL order, the next pass's values loaded while the current
+// pass computes.  The block shares the schedule's index tables in LDS.
 // ------------------------------------------------------------------------------------
-template <typename T, int BS, int KL>
-__global__ void __launch_bounds__(BS) k_patch_solve(LatDev L, PatchDev P, const T *__restrict__ factor,
-                                                     const T *__restrict__ rt, T *__restrict__ zbuf, long nslots) {
-  constexpr int RMAX = 2, NL = 4;  // rows per thread; levels 1..4 carry off-diagonal entries
-  __shared__ T x[RMAX * BS];
-  const int tid = threadIdx.x;
-  const int p = L.p, nrows = P.nrows, nnz = P.nnz, nlev = P.nlev;
-  // entries of level l+1: [elev[l+1], elev[l+2]), thread tid takes elev[l+1] + tid + BS k
-  int rc[NL][KL];
-#pragma unroll
-  for (int l = 0; l < NL; ++l)
-#pragma unroll
-    for (int k = 0; k < KL; ++k) {
-      const int e = P.elev[l + 1] + tid + BS * k;
-      rc[l][k] = (l + 1 < nlev && e < P.elev[l + 2]) ? P.rc[e] : -1;
-    }
-  int rlev[RMAX], ro[RMAX][3];
-#pragma unroll
-  for (int r = 0; r < RMAX; ++r) {
-    const int i = tid + r * BS;
-    rlev[r] = i < nrows ? P.rlev[i] : -1;
-    for (int d = 0; d < 3; ++d) ro[r][d] = i < nrows ? P.off[3 * i + d] : 0;
-  }
-  const int nvx = L.nx + 1, nvy = L.ny + 1;
-  for (long slot = blockIdx.x; slot < nslots; slot += gridDim.x) {
-    const T *f = factor + slot * (long)nnz;
-    T v[NL][KL], dg[RMAX];
-#pragma unroll
-    for (int l = 0; l < NL; ++l)
-#pragma unroll
-      for (int k = 0; k < KL; ++k)
-        v[l][k] = rc[l][k] >= 0 ? f[nrows + P.elev[l + 1] + tid + BS * k] : T(0);
-    const int vx = slot % nvx, vy = (slot / nvx) % nvy, vz = slot / ((long)nvx * nvy);
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      const int i = tid + r * BS;
-      if (rlev[r] < 0) continue;
-      dg[r] = f[i];
-      const int X = vx * p + ro[r][0], Y = vy * p + ro[r][1], Z = vz * p + ro[r][2];
-      const bool in = X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
-      x[i] = (in && !lat_dirichlet(L, X, Y, Z)) ? rt[lat_index(L, X, Y, Z)] : T(0);
-    }
-    __syncthreads();
-    // forward: L y = b, level by level
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-      if (rlev[r] == 0) x[tid + r * BS] /= dg[r];
-    __syncthreads();
-#pragma unroll
-    for (int l = 0; l < NL; ++l) {
-      if (l + 1 >= nlev) break;
-      T xv[KL];
-#pragma unroll
-      for (int k = 0; k < KL; ++k) xv[k] = rc[l][k] >= 0 ? x[(rc[l][k] >> 10) & 1023] : T(0);
-#pragma unroll
-      for (int k = 0; k < KL; ++k)
-        if (rc[l][k] >= 0) atomicAdd(&x[rc[l][k] & 1023], -v[l][k] * xv[k]);
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < RMAX; ++r)
-        if (rlev[r] == l + 1) x[tid + r * BS] /= dg[r];
-      __syncthreads();
-    }
-    // backward: L^T z = y, levels in reverse
-#pragma unroll
-    for (int l = NL - 1; l >= 0; --l) {
-      if (l + 1 >= nlev) continue;
-#pragma unroll
-      for (int r = 0; r < RMAX; ++r)
-        if (rlev[r] == l + 1) x[tid + r * BS] /= dg[r];
-      __syncthreads();
-      T xv[KL];
-#pragma unroll
-      for (int k = 0; k < KL; ++k) xv[k] = rc[l][k] >= 0 ? x[rc[l][k] & 1023] : T(0);
-#pragma unroll
-      for (int k = 0; k < KL; ++k)
-        if (rc[l][k] >= 0) atomicAdd(&x[(rc[l][k] >> 10) & 1023], -v[l][k] * xv[k]);
-      __syncthreads();
-    }
-    T *zo = zbuf + slot * (long)nrows;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-      if (rlev[r] >= 0) {
-        const int i = tid + r * BS;
-        if (rlev[r] == 0) x[i] /= dg[r];
-        zo[i] = x[i];
-      }
-    __syncthreads();
-  }
-}
-
-// Gather form (no atomics, fixed summation order).  Persistent blocks keep the
-// symbolic lists in LDS (16-bit), stage each slot's factor in LDS and prefetch the
-// next slot's factor into registers while solving the current one (barriers
-// only order LDS, so the prefetch stays in flight).  In level l, G_l lanes work
-// on one row (forward) or one column (backward) and combine by shuffles.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 template <typename T>
 __device__ __forceinline__ T group_sum(T s, int G) {
   for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   return s;
 }
 
-template <typename T, int BS, int PF>
-__global__ void __launch_bounds__(BS) k_patch_solve_g(LatDev L, PatchSolveDev S, const T *__restrict__ factor,
-                                                       const T *__restrict__ rt, T *__restrict__ zbuf, long nslots) {
-  constexpr int RMAX = 1024 / BS;
+template <typename T>
+__global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E, const T *__restrict__ factor,
+                                                         const T *__restrict__ rt, T *__restrict__ zbuf,
+                                                         long nslots) {
+  constexpr int KM = 8;  // at most kMaxSteps steps per pass
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int tid = threadIdx.x;
-  const int p = L.p, nrows = S.nrows, nnz = S.nnz, noff = S.noff, nlev = S.nlev;
-  T *V = reinterpret_cast<T *>(smem_raw);
-  T *x = V + nnz;
-  unsigned *blist = reinterpret_cast<unsigned *>(x + nrows);
-  unsigned short *fcol = reinterpret_cast<unsigned short *>(blist + noff);
-  unsigned short *fptr = fcol + noff;
-  unsigned short *bptr = fptr + 2 * nrows;
-  unsigned short *lrows = bptr + nrows + 1;
-  for (int i = tid; i < noff; i += BS) {
-    blist[i] = (unsigned)S.blist[i];
-    fcol[i] = (unsigned short)S.fcol[i];
-  }
-  for (int i = tid; i < 2 * nrows; i += BS) fptr[i] = (unsigned short)S.fptr[i];
-  for (int i = tid; i <= nrows; i += BS) bptr[i] = (unsigned short)S.bptr[i];
-  for (int i = tid; i < nrows; i += BS) lrows[i] = (unsigned short)S.lrows[i];
-  int ro[RMAX][3];
-  bool own[RMAX];
-#pragma unroll
-  for (int r = 0; r < RMAX; ++r) {
-    const int i = tid + r * BS;
-    own[r] = i < nrows;
-    for (int d = 0; d < 3; ++d) ro[r][d] = own[r] ? S.off[3 * i + d] : 0;
-  }
+  const int nrows = E.nrows, ne = E.ne, np = E.npass, p = L.p;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  T *xw = reinterpret_cast<T *>(smem_raw) + (size_t)w * 2 * nrows;  // this wavefront's vector
+  T *dw = xw + nrows;                                                  // and diagonal
+  int *off = reinterpret_cast<int *>(reinterpret_cast<T *>(smem_raw) + (size_t)nw * 2 * nrows);
+  unsigned short *ecol = reinterpret_cast<unsigned short *>(off + nrows);
+  unsigned short *erow = ecol + ne;
+  for (int i = tid; i < ne; i += blockDim.x) ecol[i] = (unsigned short)E.ecol[i];
+  for (int i = tid; i < np * 64; i += blockDim.x) erow[i] = (unsigned short)(E.erow[i] & 0xFFFF);
+  for (int i = tid; i < nrows; i += blockDim.x)
+    off[i] = (E.off[3 * i] + 64) | ((E.off[3 * i + 1] + 64) << 8) | ((E.off[3 * i + 2] + 64) << 16);
+  __syncthreads();
   const int nvx = L.nx + 1, nvy = L.ny + 1;
-  T pf[PF], pb[RMAX];
-  // load (into registers) the factor and the gathered right-hand side of a slot
-  auto fetch = [&](long sl) {
-    const T *f = factor + sl * (long)nnz;
-#pragma unroll
-    for (int k = 0; k < PF; ++k) pf[k] = (tid + BS * k < nnz) ? f[tid + BS * k] : T(0);
+  for (long sl = (long)blockIdx.x * nw + w; sl < nslots; sl += (long)gridDim.x * nw) {
+    const T *f = factor + sl * (long)E.stride;
+    const T *fe = f + nrows;
     const int vx = sl % nvx, vy = (sl / nvx) % nvy, vz = sl / ((long)nvx * nvy);
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      const int X = vx * p + ro[r][0], Y = vy * p + ro[r][1], Z = vz * p + ro[r][2];
-      const bool in = own[r] && X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
-      pb[r] = (in && !lat_dirichlet(L, X, Y, Z)) ? rt[lat_index(L, X, Y, Z)] : T(0);
+    for (int i = lane; i < nrows; i += 64) {
+      const int o = off[i];
+      const int X = vx * p + (o & 255) - 64, Y = vy * p + ((o >> 8) & 255) - 64, Z = vz * p + ((o >> 16) & 255) - 64;
+      const bool in = X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
+      xw[i] = (in && !lat_dirichlet(L, X, Y, Z)) ? rt[lat_index(L, X, Y, Z)] : T(0);
+      dw[i] = f[i];
     }
-  };
-  long slot = blockIdx.x;
-  if (slot < nslots) fetch(slot);
-  for (; slot < nslots; slot += gridDim.x) {
+    T cur[KM];
+    {
+      const int K = E.pass[1], base = E.pass[2];
 #pragma unroll
-    for (int k = 0; k < PF; ++k)
-      if (tid + BS * k < nnz) V[tid + BS * k] = pf[k];
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-      if (own[r]) x[tid + r * BS] = pb[r];
-    const long next = slot + gridDim.x;
-    if (next < nslots) fetch(next);
-    lds_barrier();
-    for (int lv = 0; lv < nlev; ++lv) {  // forward: L y = b
-      const int G = S.G[lv], q = tid & (G - 1), base = S.lptr[lv], nr = S.lptr[lv + 1] - base;
-      for (int gr = tid / G; gr < nr; gr += BS / G) {
-        const int i = lrows[base + gr];
-        T s = 0;
-        const int e1 = fptr[2 * i + 1];
-        int e = fptr[2 * i] + q;
-        for (; e + 3 * G < e1; e += 4 * G) {  // four independent entries per step
-          const int c0 = fcol[e], c1 = fcol[e + G], c2 = fcol[e + 2 * G], c3 = fcol[e + 3 * G];
-          s += V[nrows + e] * x[c0] + V[nrows + e + G] * x[c1] + V[nrows + e + 2 * G] * x[c2] +
-               V[nrows + e + 3 * G] * x[c3];
-        }
-        for (; e < e1; e += G) s += V[nrows + e] * x[fcol[e]];
-        s = group_sum(s, G);
-        if (q == 0) x[i] = (x[i] - s) / V[i];
-      }
-      lds_barrier();
+      for (int s = 0; s < KM; ++s) cur[s] = s < K ? fe[base + 64 * s + lane] : T(0);
     }
-    for (int lv = nlev - 1; lv >= 0; --lv) {  // backward: L^T z = y
-      const int G = S.G[lv], q = tid & (G - 1), base = S.lptr[lv], nr = S.lptr[lv + 1] - base;
-      for (int gr = tid / G; gr < nr; gr += BS / G) {
-        const int i = lrows[base + gr];
-        T s = 0;
-        const int k1 = bptr[i + 1];
-        int k = bptr[i] + q;
-        for (; k + 3 * G < k1; k += 4 * G) {
-          const unsigned w0 = blist[k], w1 = blist[k + G], w2 = blist[k + 2 * G], w3 = blist[k + 3 * G];
-          s += V[nrows + (w0 & 0xFFFFu)] * x[w0 >> 16] + V[nrows + (w1 & 0xFFFFu)] * x[w1 >> 16] +
-               V[nrows + (w2 & 0xFFFFu)] * x[w2 >> 16] + V[nrows + (w3 & 0xFFFFu)] * x[w3 >> 16];
-        }
-        for (; k < k1; k += G) {
-          const unsigned w = blist[k];
-          s += V[nrows + (w & 0xFFFFu)] * x[w >> 16];
-        }
-        s = group_sum(s, G);
-        if (q == 0) x[i] = (x[i] - s) / V[i];
-      }
-      lds_barrier();
-    }
-    T *zo = zbuf + slot * (long)nrows;
+    for (int t = 0; t < np; ++t) {
+      const int G = E.pass[3 * t], K = E.pass[3 * t + 1], base = E.pass[3 * t + 2];
+      T nxt[KM];
+      const int Kn = t + 1 < np ? E.pass[3 * t + 4] : 0, bn = t + 1 < np ? E.pass[3 * t + 5] : 0;
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-      if (own[r]) zo[tid + r * BS] = x[tid + r * BS];
-    lds_barrier();
+      for (int s = 0; s < KM; ++s) nxt[s] = s < Kn ? fe[bn + 64 * s + lane] : T(0);
+      T acc = 0;
+#pragma unroll
+      for (int s = 0; s < KM; ++s)
+        if (s < K) acc += cur[s] * xw[ecol[base + 64 * s + lane]];
+      acc = group_sum(acc, G);
+      const unsigned row = erow[64 * t + lane];
+      if ((lane & (G - 1)) == 0 && row != 0xFFFFu) xw[row] = (xw[row] - acc) / dw[row];
+#pragma unroll
+      for (int s = 0; s < KM; ++s) cur[s] = nxt[s];
+    }
+    T *zo = zbuf + sl * (long)nrows;
+    for (int i = lane; i < nrows; i += 64) zo[i] = xw[i];
   }
 }
 
@@ -681,12 +533,16 @@ __global__ void __launch_bounds__(256) k_patch_factor(LatDev L, PatchDev P, cons
     }
     __syncthreads();
   }
-  double *o64 = f64 + vid * (long)P.nnz;
-  float *o32 = f32 + vid * (long)P.nnz;
+  double *o64 = f64 + vid * (long)P.stride;
+  float *o32 = f32 + vid * (long)P.stride;
   for (int k = threadIdx.x; k < P.nnz; k += blockDim.x) {
-    int q = P.perm[k];
+    const int q = P.perm[k], q2 = P.perm2[k];
     o64[q] = S[k];
     o32[q] = (float)S[k];
+    if (q2 >= 0) {
+      o64[q2] = S[k];
+      o32[q2] = (float)S[k];
+    }
   }
 }
 
@@ -846,71 +702,25 @@ int device_cu_count() {
   return cus;
 }
 
-template <typename T, int KL>
-static void patch_solve_k(const LatDev &L, const PatchDev &P, const T *factor, const T *rt, T *zbuf, long nv,
-                          hipStream_t s) {
-  constexpr int BS = 512;
-  long grid = (long)device_cu_count() * 2;
-  if (grid > nv) grid = nv;
-  k_patch_solve<T, BS, KL><<<(unsigned)grid, BS, 0, s>>>(L, P, factor, rt, zbuf, nv);
-}
-
-template <typename T, int BS, int PF>
-static void patch_solve_g(const LatDev &L, const PatchSolveDev &S0, const T *factor, const T *rt, T *zbuf, long nv,
-                          size_t shm, int per_cu, hipStream_t s) {
-  // lanes per row in each level: the largest power of two <= 64 that fits the block
-  PatchSolveDev S = S0;
-  for (int l = 0; l < 5; ++l) {
-    const int nr = l < S.nlev ? S.lptr[l + 1] - S.lptr[l] : 0;
-    int G = 1;
-    while (G < 64 && nr * (2 * G) <= BS) G *= 2;
-    S.G[l] = G;
-  }
-  if (shm > 65536)
-    hipFuncSetAttribute((const void *)k_patch_solve_g<T, BS, PF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  long grid = (long)device_cu_count() * per_cu;
-  if (grid > nv) grid = nv;
-  k_patch_solve_g<T, BS, PF><<<(unsigned)grid, BS, shm, s>>>(L, S, factor, rt, zbuf, nv);
-}
-
-size_t patch_solve_lds_bytes(const PatchSolveDev &S, size_t elem) {
-  return elem * (size_t)(S.nnz + S.nrows) + 4 * (size_t)S.noff + 2 * (size_t)S.noff + 4 * (size_t)S.nrows +
-         2 * (size_t)(S.nrows + 1) + 2 * (size_t)S.nrows;
+size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves) {
+  return (size_t)waves * 2 * E.nrows * elem + 4 * (size_t)E.nrows + 2 * (size_t)E.ne + 2 * 64 * (size_t)E.npass;
 }
 
 template <typename T>
-void launch_patch_solve(const LatDev &L, const PatchDev &P, const PatchSolveDev &S, const T *factor, const T *rt,
-                        T *zbuf, hipStream_t s) {
-  long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
-  const size_t shm = patch_solve_lds_bytes(S, sizeof(T));
-  if (shm <= 160 * 1024 - 1024 && S.nrows <= 1024) {
-    // one 1024-thread block per CU when a staged factor needs more than half the LDS
-    const bool big = shm > 78 * 1024;
-    const int per_cu = big ? 1 : 2;
-    const int pf = big ? (S.nnz + 1023) / 1024 : (S.nnz + 511) / 512;
-    if (big) {
-      if (pf <= 4) patch_solve_g<T, 1024, 4>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
-      else if (pf <= 8) patch_solve_g<T, 1024, 8>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
-      else patch_solve_g<T, 1024, 16>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
-    } else {
-      if (pf <= 4) patch_solve_g<T, 512, 4>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
-      else if (pf <= 8) patch_solve_g<T, 512, 8>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
-      else if (pf <= 16) patch_solve_g<T, 512, 16>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
-      else if (pf <= 24) patch_solve_g<T, 512, 24>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
-      else patch_solve_g<T, 512, 32>(L, S, factor, rt, zbuf, nv, shm, per_cu, s);
-    }
-    return;
-  }
-  // factors too large to stage in LDS: level-parallel form with register-resident entries
-  int mx = 0;
-  for (int l = 1; l < P.nlev; ++l) mx = mx > P.elev[l + 1] - P.elev[l] ? mx : P.elev[l + 1] - P.elev[l];
-  const int need = (mx + 511) / 512;
-  if (need <= 1) patch_solve_k<T, 1>(L, P, factor, rt, zbuf, nv, s);
-  else if (need <= 2) patch_solve_k<T, 2>(L, P, factor, rt, zbuf, nv, s);
-  else if (need <= 4) patch_solve_k<T, 4>(L, P, factor, rt, zbuf, nv, s);
-  else if (need <= 8) patch_solve_k<T, 8>(L, P, factor, rt, zbuf, nv, s);
-  else if (need <= 12) patch_solve_k<T, 12>(L, P, factor, rt, zbuf, nv, s);
-  else patch_solve_k<T, 20>(L, P, factor, rt, zbuf, nv, s);
+int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf, hipStream_t s) {
+  const long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
+  constexpr size_t kLds = 160 * 1024;
+  int waves = 16;
+  while (waves > 1 && patch_solve_lds_bytes(E, sizeof(T), waves) > kLds) --waves;
+  const size_t shm = patch_solve_lds_bytes(E, sizeof(T), waves);
+  if (shm > kLds) return -1;
+  const int per_cu = 2 * shm <= kLds ? 2 : 1;
+  hipFuncSetAttribute((const void *)k_patch_solve_w<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  long grid = (long)device_cu_count() * per_cu;
+  const long need = (nv + waves - 1) / waves;
+  if (grid > need) grid = need;
+  k_patch_solve_w<T><<<(unsigned)grid, 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv);
+  return 0;
 }
 
 template <typename T>
@@ -959,9 +769,9 @@ template void launch_condense_grad<double>(const LatDev &, const double *, const
                                            const double *, double *, hipStream_t);
 template void launch_condense_grad<float>(const LatDev &, const float *, const float *, const float *,
                                           const float *, float *, hipStream_t);
-template void launch_patch_solve<double>(const LatDev &, const PatchDev &, const PatchSolveDev &, const double *,
+template int launch_patch_solve<double>(const LatDev &, const PatchEllDev &, const double *,
                                          const double *, double *, hipStream_t);
-template void launch_patch_solve<float>(const LatDev &, const PatchDev &, const PatchSolveDev &, const float *,
+template int launch_patch_solve<float>(const LatDev &, const PatchEllDev &, const float *,
                                         const float *, float *, hipStream_t);
 template void launch_expand_grad<double>(const LatDev &, const PatchDev &, const double *, const double *,
                                          const double *, const double *, const double *, double *,

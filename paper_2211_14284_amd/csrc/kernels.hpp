@@ -23,20 +23,19 @@ struct PatchDev {
   const int *erow;                 // row of every CSR entry
   const int *uptr, *urow, *upos;   // column access of the lower factor
   const int *flev_ptr, *flev_rows, *blev_ptr, *blev_rows;
-  // level-sorted storage of the factor values (see PatchSymbolic)
-  int nlev, noff;
-  int elev[6];                     // off-diagonal entries of level l: [elev[l], elev[l+1]) (nlev <= 5)
-  const int *rc;                   // noff packed (row | col << 10 | level << 20)
-  const int *rlev;                 // forward level of every row
-  const int *perm;                 // CSR position -> storage position
+  // slot layout of the factor values (see PatchSymbolic): stride values per slot,
+  // CSR entry k at perm[k] and, for off-diagonal entries, also at perm2[k]
+  int stride;
+  const int *perm, *perm2;
 };
 
-// Gather form of the patch triangular solves (see PatchSymbolic).
-struct PatchSolveDev {
-  int nrows, nnz, noff, nlev;
-  int lptr[6];                     // rows of level l: lrows[lptr[l] .. lptr[l+1]-1]
-  int G[5];                        // lanes per row in level l (power of two <= 64)
-  const int *off, *fptr, *fcol, *bptr, *blist, *lrows;
+// Wavefront schedule of the patch triangular solves (see PatchSymbolic).
+struct PatchEllDev {
+  int nrows, npass, ne, stride;
+  const int *pass;                 // 3*npass: lanes per row G, steps K, ELL offset
+  const int *ecol;                 // ne: x index read at every ELL position
+  const int *erow;                 // 64*npass: row solved by each lane's group (-1 none)
+  const int *off;                  // 3*nrows: lattice offsets of the patch rows
 };
 
 // ---- vectors ------------------------------------------------------------------
@@ -62,9 +61,10 @@ void launch_apply_grad(const LatDev &L, const T *coef, const double *Bh, const d
 template <typename T>
 void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r,
                           T *rt, hipStream_t s);
+// Returns non-zero when the schedule does not fit the LDS of one block.
+size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves);
 template <typename T>
-void launch_patch_solve(const LatDev &L, const PatchDev &P, const PatchSolveDev &S, const T *factor, const T *rt,
-                        T *zbuf, hipStream_t s);
+int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf, hipStream_t s);
 // number of compute units of the current device (cached), for persistent grids
 int device_cu_count();
 template <typename T>

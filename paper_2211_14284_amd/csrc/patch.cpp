@@ -83,54 +83,97 @@ void build_patch_symbolic(int p, PatchSymbolic &ps) {
   };
   group(flev, fmax, ps.flev_ptr, ps.flev_rows);
   group(blev, bmax, ps.blev_ptr, ps.blev_rows);
-  // storage order for the level-parallel solve
   ps.nlev = fmax + 1;
   ps.level = flev;
   ps.noff = ps.nnz - n;
-  ps.perm.assign(ps.nnz, -1);
-  // off-diagonal entries sorted by (level of the row, row, column)
-  std::vector<std::array<int, 4>> offd;  // level, row, col, csr position
-  for (int r = 0; r < n; ++r)
-    for (int k = ps.rowptr[r]; k < ps.rowptr[r + 1]; ++k) {
-      int c = ps.col[k];
-      if (c == r) ps.perm[k] = r;
-      else offd.push_back({flev[r], r, c, k});
+  build_wave_schedule(ps);
+}
+
+// Lay out one level's rows (forward) or columns (backward) in passes.  items:
+// (row, list of (CSR entry, x index)).  G is the power of two that minimises the
+// padded size with at most kMaxSteps steps per pass (ties: the smaller G).
+static void schedule_level(PatchSymbolic &ps, std::vector<std::pair<int, std::vector<std::pair<int, int>>>> items,
+                           bool forward) {
+  const int W = PatchSymbolic::kLanes, KM = PatchSymbolic::kMaxSteps;
+  std::stable_sort(items.begin(), items.end(),
+                   [](const auto &a, const auto &b) { return a.second.size() > b.second.size(); });
+  const int n = (int)items.size();
+  if (n == 0) return;
+  int bestG = -1;
+  long best = 0;
+  for (int G = 1; G <= W; G *= 2) {
+    const int R = W / G;
+    long tot = 0;
+    bool ok = true;
+    for (int t = 0; t < n; t += R) {
+      const int K = ((int)items[t].second.size() + G - 1) / G;
+      if (K > KM) ok = false;
+      tot += (long)W * K;
     }
-  std::sort(offd.begin(), offd.end());
-  ps.rc.resize(offd.size());
-  ps.fcol.resize(offd.size());
-  ps.fptr.assign(n + 1, 0);
-  std::vector<std::vector<std::pair<int, int>>> colent(n);  // (j, storage index)
-  for (size_t e = 0; e < offd.size(); ++e) {
-    int r = offd[e][1], c = offd[e][2], k = offd[e][3];
-    ps.perm[k] = n + (int)e;
-    ps.rc[e] = r | (c << 10) | (flev[r] << 20);
-    ps.fcol[e] = c;
-    ps.fptr[r + 1]++;
-    colent[c].push_back({r, (int)e});
-  }
-  // rows of one level are contiguous and ordered, so the counts turn into offsets
-  // in level order; fptr is indexed by row
-  {
-    std::vector<int> start(n, 0);
-    for (size_t e = 0; e < offd.size(); ++e) {
-      int r = offd[e][1];
-      if (e == 0 || offd[e - 1][1] != r) start[r] = (int)e;
-    }
-    std::vector<int> cnt(ps.fptr.begin() + 1, ps.fptr.end());
-    ps.fptr.assign(2 * n, 0);  // (start, end) per row
-    for (int r = 0; r < n; ++r) {
-      ps.fptr[2 * r] = cnt[r] ? start[r] : 0;
-      ps.fptr[2 * r + 1] = ps.fptr[2 * r] + cnt[r];
+    if (ok && (bestG < 0 || tot < best)) {
+      bestG = G;
+      best = tot;
     }
   }
-  ps.bptr.assign(n + 1, 0);
-  ps.blist.clear();
-  for (int i = 0; i < n; ++i) {
-    std::sort(colent[i].begin(), colent[i].end());
-    for (auto &pr : colent[i]) ps.blist.push_back(pr.second | (pr.first << 16));
-    ps.bptr[i + 1] = (int)ps.blist.size();
+  const int G = bestG, R = W / G;
+  for (int t = 0; t < n; t += R) {
+    const int K = ((int)items[t].second.size() + G - 1) / G;
+    const int base = (int)ps.ecol.size();
+    ps.pass_g.push_back(G);
+    ps.pass_k.push_back(K);
+    ps.pass_base.push_back(base);
+    ps.ecol.resize(base + (size_t)W * K, 0);
+    const size_t r0 = ps.erow.size();
+    ps.erow.resize(r0 + W, -1);
+    for (int j = 0; j < R && t + j < n; ++j) {
+      const auto &it = items[t + j];
+      for (int q = 0; q < G; ++q) ps.erow[r0 + j * G + q] = it.first;
+      for (int m = 0; m < (int)it.second.size(); ++m) {
+        const int pos = base + (m / G) * W + j * G + (m % G);
+        ps.ecol[pos] = it.second[m].second;
+        (forward ? ps.pos1 : ps.pos2)[it.second[m].first] = ps.nrows + pos;
+      }
+    }
   }
+}
+
+void build_wave_schedule(PatchSymbolic &ps) {
+  const int n = ps.nrows;
+  ps.pos1.assign(ps.nnz, -1);
+  ps.pos2.assign(ps.nnz, -1);
+  ps.pass_g.clear();
+  ps.pass_k.clear();
+  ps.pass_base.clear();
+  ps.ecol.clear();
+  ps.erow.clear();
+  for (int r = 0; r < n; ++r) ps.pos1[ps.rowptr[r + 1] - 1] = r;  // diagonal
+  // forward: row i gathers L_ij x_j, j < i
+  for (int l = 0; l < ps.nlev; ++l) {
+    std::vector<std::pair<int, std::vector<std::pair<int, int>>>> items;
+    for (int r = 0; r < n; ++r)
+      if (ps.level[r] == l) {
+        std::vector<std::pair<int, int>> e;
+        for (int k = ps.rowptr[r]; k < ps.rowptr[r + 1] - 1; ++k) e.push_back({k, ps.col[k]});
+        items.push_back({r, e});
+      }
+    schedule_level(ps, items, true);
+  }
+  ps.nfpass = (int)ps.pass_g.size();
+  ps.ef = (int)ps.ecol.size();
+  // backward: column i gathers L_ji x_j, j > i, levels in reverse
+  for (int l = ps.nlev - 1; l >= 0; --l) {
+    std::vector<std::pair<int, std::vector<std::pair<int, int>>>> items;
+    for (int i = 0; i < n; ++i)
+      if (ps.level[i] == l) {
+        std::vector<std::pair<int, int>> e;
+        for (int t = ps.uptr[i]; t < ps.uptr[i + 1]; ++t) e.push_back({ps.upos[t], ps.urow[t]});
+        items.push_back({i, e});
+      }
+    schedule_level(ps, items, false);
+  }
+  ps.npass = (int)ps.pass_g.size();
+  ps.eb = (int)ps.ecol.size() - ps.ef;
+  ps.stride = n + ps.ef + ps.eb;
 }
 
 }  // namespace rz

@@ -17,22 +17,28 @@ struct PatchSymbolic {
   std::vector<int> uptr, urow, upos;
   // level schedules of the forward and backward triangular solves
   std::vector<int> flev_ptr, flev_rows, blev_ptr, blev_rows;
-  // Storage order of a slot's factor values: the nrows diagonal entries (row
-  // order), then the off-diagonal entries sorted by (forward level of the row,
-  // row, column).  perm[k] = storage position of CSR entry k.
-  int nlev = 0, noff = 0;
+  int nlev = 0, noff = 0;          // forward levels, off-diagonal entries
   std::vector<int> level;          // forward level of every row
-  std::vector<int> perm;           // nnz
-  std::vector<int> rc;             // noff packed entries: row | col << 10 | level(row) << 20
-  // gather form of the two sweeps, in storage numbering of the off-diagonals:
-  // row i's entries (L_ij, j < i) are fptr[2i] .. fptr[2i+1]-1 with columns fcol;
-  // column i's entries (L_ji, j > i) are listed in blist[bptr[i] .. bptr[i+1]-1]
-  // as (storage index | j << 16), j ascending
-  std::vector<int> fptr, fcol, bptr, blist;
+
+  // Wavefront schedule of the two sweeps (one 64-lane wavefront per patch).  A
+  // pass works on up to 64/G rows (forward) or columns (backward) of one level,
+  // G lanes each; lane j*G+q takes entries q, q+G, ... of its row, so step s of
+  // the pass reads ELL position base + 64 s + lane.  A slot's factor values are
+  // [diagonal (nrows)] [forward ELL (ef)] [backward ELL (eb)], padding zero, so
+  // each sweep streams its values once, coalesced.
+  static constexpr int kLanes = 64, kMaxSteps = 8;
+  int npass = 0, nfpass = 0, ef = 0, eb = 0, stride = 0;
+  std::vector<int> pass_g, pass_k, pass_base;  // per pass: lanes per row, steps, ELL offset
+  std::vector<int> ecol;   // ef + eb: index of the x entry read at each ELL position (padding 0)
+  std::vector<int> erow;   // npass*64: row solved by the lane's group (-1: none)
+  std::vector<int> pos1;   // nnz: CSR entry -> value position in the slot (diagonal or forward ELL)
+  std::vector<int> pos2;   // nnz: CSR entry -> backward ELL value position (-1 for the diagonal)
 };
 
 // Build the layout and the static-condensation pattern of a full (untruncated)
 // interior vertex patch on a Cartesian mesh.
 void build_patch_symbolic(int p, PatchSymbolic &ps);
+// The wavefront schedule (called by build_patch_symbolic).
+void build_wave_schedule(PatchSymbolic &ps);
 
 }  // namespace rz

@@ -50,7 +50,7 @@ struct rz_problem {
   // device
   LatDev L{};
   PatchDev P{};
-  PatchSolveDev PS{};
+  PatchEllDev PE{};
   std::vector<void *> allocs;
   double *coef64 = nullptr, *B64 = nullptr, *A64 = nullptr, *lam64 = nullptr, *E64 = nullptr;
   float *coef32 = nullptr, *B32 = nullptr, *A32 = nullptr, *lam32 = nullptr;
@@ -214,7 +214,7 @@ void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T
   }
   {
     Timed t(h, RZ_K_PATCH);
-    launch_patch_solve<T>(h->L, h->P, h->PS, f, rt, zb, s);
+    launch_patch_solve<T>(h->L, h->PE, f, rt, zb, s);
   }
   {
     Timed t(h, RZ_K_EXPAND);
@@ -664,40 +664,26 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
     sym.insert(sym.end(), v.begin(), v.end());
     return o;
   };
+  std::vector<int> passes;
+  for (int t = 0; t < ps.npass; ++t) {
+    passes.push_back(ps.pass_g[t]);
+    passes.push_back(ps.pass_k[t]);
+    passes.push_back(ps.pass_base[t]);
+  }
   size_t o_off = push(ps.off), o_rp = push(ps.rowptr), o_col = push(ps.col), o_er = push(h->erow),
          o_up = push(ps.uptr), o_ur = push(ps.urow), o_upos = push(ps.upos), o_fp = push(ps.flev_ptr),
-         o_fr = push(ps.flev_rows), o_bp = push(ps.blev_ptr), o_br = push(ps.blev_rows), o_rc = push(ps.rc),
-         o_lv = push(ps.level), o_pm = push(ps.perm), o_gfp = push(ps.fptr), o_gfc = push(ps.fcol),
-         o_gbp = push(ps.bptr), o_gbl = push(ps.blist);
+         o_fr = push(ps.flev_rows), o_bp = push(ps.blev_ptr), o_br = push(ps.blev_rows), o_p1 = push(ps.pos1),
+         o_p2 = push(ps.pos2), o_pass = push(passes), o_ecol = push(ps.ecol), o_erow = push(ps.erow);
   int *dsym = nullptr;
   if ((e = upload(h, &dsym, sym))) return bail(e);
   h->P = PatchDev{ps.nrows, ps.nnz, (int)ps.flev_ptr.size() - 1, (int)ps.blev_ptr.size() - 1,
                   dsym + o_off, dsym + o_rp, dsym + o_col, dsym + o_er, dsym + o_up, dsym + o_ur, dsym + o_upos,
-                  dsym + o_fp, dsym + o_fr, dsym + o_bp, dsym + o_br, ps.nlev, ps.noff, {0, 0, 0, 0, 0, 0},
-                  dsym + o_rc, dsym + o_lv, dsym + o_pm};
-  if (ps.nlev > 5) return bail(fail(ctx, RZ_ERR_ARG, "patch level schedule deeper than 5"));
-  {
-    PatchSolveDev &S = h->PS;
-    S.nrows = ps.nrows;
-    S.nnz = ps.nnz;
-    S.noff = ps.noff;
-    S.nlev = ps.nlev;
-    for (int l = 0; l < 6; ++l) S.lptr[l] = l < (int)ps.flev_ptr.size() ? ps.flev_ptr[l] : ps.nrows;
-    for (int l = 0; l < 5; ++l) S.G[l] = 1;  // lane-group sizes are chosen by the launcher
-    S.off = dsym + o_off;
-    S.fptr = dsym + o_gfp;
-    S.fcol = dsym + o_gfc;
-    S.bptr = dsym + o_gbp;
-    S.blist = dsym + o_gbl;
-    S.lrows = dsym + o_fr;
-  }
-  for (int l = 0; l <= 5; ++l) {
-    int cnt = 0;
-    for (int v : ps.rc)
-      if ((v >> 20) < l) ++cnt;
-    h->P.elev[l] = cnt;
-  }
-  const size_t nf = (size_t)h->nvert * ps.nnz, nzb = (size_t)h->nvert * ps.nrows;
+                  dsym + o_fp, dsym + o_fr, dsym + o_bp, dsym + o_br, ps.stride, dsym + o_p1, dsym + o_p2};
+  h->PE = PatchEllDev{ps.nrows, ps.npass, ps.ef + ps.eb, ps.stride, dsym + o_pass, dsym + o_ecol, dsym + o_erow,
+                      dsym + o_off};
+  if (patch_solve_lds_bytes(h->PE, sizeof(double), 1) > 160 * 1024)
+    return bail(fail(ctx, RZ_ERR_ARG, "patch schedule does not fit the LDS"));
+  const size_t nf = (size_t)h->nvert * ps.stride, nzb = (size_t)h->nvert * ps.nrows;
   const size_t neb = (size_t)h->ncells * (p + 1) * (p + 1) * (p + 1);
   if ((e = dalloc(h, &h->eb64, neb)) || (e = dalloc(h, &h->eb32, neb)) || (e = dalloc(h, &h->f64, nf)) ||
       (e = dalloc(h, &h->f32, nf)) || (e = dalloc(h, &h->zb64, nzb)) ||
@@ -710,6 +696,10 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
     return bail(e);
   // the workspace of the vertex patches: keep rows of empty slots well defined
   launch_fill(h->zb64, 0.0, (int64_t)nzb, s);
+  // ELL padding of the factors must read as zero
+  if (hipMemsetAsync(h->f64, 0, nf * sizeof(double), s) != hipSuccess ||
+      hipMemsetAsync(h->f32, 0, nf * sizeof(float), s) != hipSuccess)
+    return bail(fail(ctx, RZ_ERR_HIP, "memset"));
   launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, h->f64, h->f32, h->status, s);
   if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(ctx, RZ_ERR_HIP, "patch factorisation failed"));
   int stv = 0;
@@ -972,9 +962,9 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
       if (what == RZ_EXPORT_IC_FACTOR) {
         rz_status e = require_device(h);
         if (e) return e;
-        vals.resize(h->ps.nnz);
+        vals.resize(h->ps.stride);
         HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
-        HIPCALL(h, hipMemcpy(vals.data(), h->f64 + vid * (int64_t)h->ps.nnz, sizeof(double) * h->ps.nnz,
+        HIPCALL(h, hipMemcpy(vals.data(), h->f64 + vid * (int64_t)h->ps.stride, sizeof(double) * h->ps.stride,
                              hipMemcpyDeviceToHost));
       }
       for (int r = 0; r < h->ps.nrows; ++r) {
@@ -987,7 +977,7 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
             int pr[2] = {loc[r], loc[c]};
             put(pr, sizeof pr);
           } else {
-            put(&vals[h->ps.perm[k]], sizeof(double));
+            put(&vals[h->ps.pos1[k]], sizeof(double));
           }
         }
       }
