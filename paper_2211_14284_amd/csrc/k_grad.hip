@@ -35,11 +35,13 @@ __device__ __forceinline__ int ncells_axis(const LatDev &L, int a) {
 // ------------------------------------------------------------------------------------
 // y = A x: per cell, y_K = s1 (A x B x B) + s2 (B x A x B) + s3 (B x B x A) + mu (B x B x B)
 // (eq. sum-factorization with the exact 1-D integrals of an axis-aligned cell),
-// applied as per-axis contractions.  Compile-time degree P: one thread per tensor
-// line of a cell holds the line in registers; LDS is used only to turn x-lines
-// into z-lines, z-lines into y-lines and y-lines back into x-lines.  The 1-D
-// tables travel in the kernel arguments (scalar registers).  Cell-interior rows
-// are owned by the cell (plain store); interface rows are summed with atomics.
+// applied as per-axis contractions.  In the FDM basis B is diagonal plus the (0,p)
+// pair and A an arrowhead, so each 1-D factor costs O(p) per line.  Compile-time
+// degree P: one thread per tensor line of a cell, lines exchanged through LDS
+// (x to z, z to y, y to x); tiles are loaded and stored with lanes running along x
+// across the block's x-adjacent cells.  The 1-D tables travel in the kernel
+// arguments (scalar registers).  Cell-interior rows are owned by the cell (plain
+// store); interface rows go to a per-cell buffer summed by k_apply_gather.
 // ------------------------------------------------------------------------------------
 template <int P, typename T>
 struct Tab1D {
@@ -81,8 +83,6 @@ __global__ void __launch_bounds__(CPB *(P + 1) * (P + 1))
   const int cell = blockIdx.x * CPB + lc;
   const bool active = cell < ncells;
   T *s0 = S0 + lc * N3, *s1 = S1 + lc * N3;
-  const int cc = active ? cell : 0;
-  const int cx = cc % L.nx, cy = (cc / L.nx) % L.ny, cz = cc / (L.nx * L.ny);
   T s1c = 0, s2c = 0, s3c = 0, mu = 0;
   if (active) {
     s1c = coef[6 * cell];
@@ -91,15 +91,19 @@ __global__ void __launch_bounds__(CPB *(P + 1) * (P + 1))
     mu = coef[6 * cell + 3];
   }
   T r0[N1], r1[N1], r2[N1];
-  {  // x-line (b, c) of x
-    const int b = l % N1, c = l / N1;
-    const int Y = cy * P + b, Z = cz * P + c;
-#pragma unroll
-    for (int a = 0; a <= P; ++a) {
-      const int X = cx * P + a;
-      r0[a] = (active && !lat_dirichlet(L, X, Y, Z)) ? x[lat_index(L, X, Y, Z)] : T(0);
-      s0[a + N1 * b + NL * c] = r0[a];
+  // the block's CPB cells are consecutive along x: load their tiles with lanes
+  // running along x across the cells (a fastest, then cell, then b, c)
+  const long cell0 = (long)blockIdx.x * CPB;
+  for (int k = threadIdx.x; k < CPB * N3; k += CPB * NL) {
+    const int a = k % N1, lk = (k / N1) % CPB, bc = k / (N1 * CPB), b = bc % N1, cq = bc / N1;
+    const long ce = cell0 + lk;
+    T v = 0;
+    if (ce < ncells) {
+      const int ex = ce % L.nx, ey = (ce / L.nx) % L.ny, ez = ce / ((long)L.nx * L.ny);
+      const int X = ex * P + a, Y = ey * P + b, Z = ez * P + cq;
+      if (!lat_dirichlet(L, X, Y, Z)) v = x[lat_index(L, X, Y, Z)];
     }
+    S0[lk * N3 + a + N1 * b + NL * cq] = v;
   }
   __syncthreads();
   {  // z-line (a, b): t1 = B_z x, v = A_z x
@@ -134,7 +138,7 @@ __global__ void __launch_bounds__(CPB *(P + 1) * (P + 1))
     }
   }
   __syncthreads();
-  {  // x-line (b, c): y = s1 A_x u + B_x w, scatter
+  {  // x-line (b, c): y = s1 A_x u + B_x w
     const int b = l % N1, c = l / N1;
 #pragma unroll
     for (int a = 0; a <= P; ++a) {
@@ -143,15 +147,22 @@ __global__ void __launch_bounds__(CPB *(P + 1) * (P + 1))
     }
     stiff_line<P, T>(tb, r0, r2);
     mass_line<P, T>(tb, r1, r0);
-    if (!active) return;
-    const int Y = cy * P + b, Z = cz * P + c;
-    const bool line_int = (b != 0 && b != P && c != 0 && c != P);
-    T *eo = ebuf + (long)cell * N3 + N1 * l;
+    __syncthreads();
 #pragma unroll
-    for (int a = 0; a <= P; ++a) {
-      const T val = s1c * r2[a] + r0[a];
-      if (line_int && a != 0 && a != P) y[lat_index(L, cx * P + a, Y, Z)] = val;
-      else eo[a] = val;
+    for (int a = 0; a <= P; ++a) s0[a + N1 * b + NL * c] = s1c * r2[a] + r0[a];
+  }
+  __syncthreads();
+  // cell-interior rows to y, interface rows to the per-cell buffer, lanes along x
+  for (int k = threadIdx.x; k < CPB * N3; k += CPB * NL) {
+    const int a = k % N1, lk = (k / N1) % CPB, bc = k / (N1 * CPB), b = bc % N1, cq = bc / N1;
+    const long ce = cell0 + lk;
+    if (ce >= ncells) continue;
+    const T val = S0[lk * N3 + a + N1 * b + NL * cq];
+    if (a != 0 && a != P && b != 0 && b != P && cq != 0 && cq != P) {
+      const int ex = ce % L.nx, ey = (ce / L.nx) % L.ny, ez = ce / ((long)L.nx * L.ny);
+      y[lat_index(L, ex * P + a, ey * P + b, ez * P + cq)] = val;
+    } else {
+      ebuf[ce * N3 + a + N1 * b + NL * cq] = val;
     }
   }
 }
@@ -206,46 +217,67 @@ __global__ void k_apply_gather(LatDev L, const T *__restrict__ x, const T *__res
 // face DoFs (exactly one lattice coordinate on a vertex plane) couple to cell
 // interiors: along their normal line in each of the two cells.
 // ------------------------------------------------------------------------------------
-template <typename T>
-__global__ void k_condense_grad(LatDev L, const T *__restrict__ coef, const T *__restrict__ Ag,
-                                const T *__restrict__ lam, const T *__restrict__ r, T *__restrict__ rt,
-                                long n) {
-  long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const int p = L.p, n1 = p + 1;
-  int C[3] = {(int)(g % L.Nx), (int)((g / L.Nx) % L.Ny), (int)(g / ((long)L.Nx * L.Ny))};
-  int onv[3] = {C[0] % p == 0, C[1] % p == 0, C[2] % p == 0};
-  int nb = onv[0] + onv[1] + onv[2];
-  if (nb == 0) return;
-  if (lat_dirichlet(L, C[0], C[1], C[2])) {
+// Work item: one lattice point of a vertex plane normal to axis `a` (plane k,
+// coordinates u, v along the other two axes b < c, u fastest).  A point that lies
+// on several vertex planes (edge, vertex) is handled by its lowest such axis.
+struct PlanePoint {
+  int C[3];
+  bool face, owner;
+};
+
+template <int P>
+__device__ __forceinline__ bool plane_point(const LatDev &L, int a, long idx, PlanePoint &q) {
+  const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+  const int Nd[3] = {L.Nx, L.Ny, L.Nz};
+  const int nd[3] = {L.nx, L.ny, L.nz};
+  const long Nb = Nd[b], Nc = Nd[c];
+  if (idx >= (long)(nd[a] + 1) * Nb * Nc) return false;
+  const int u = idx % Nb, v = (idx / Nb) % Nc, k = idx / (Nb * Nc);
+  q.C[a] = k * P;
+  q.C[b] = u;
+  q.C[c] = v;
+  const bool ob = u % P == 0, oc = v % P == 0;
+  q.face = !ob && !oc;
+  q.owner = !((b < a && ob) || (c < a && oc));
+  return true;
+}
+
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_condense_plane(LatDev L, int a, const T *__restrict__ coef,
+                                                         const T *__restrict__ Ag, const T *__restrict__ lam,
+                                                         const T *__restrict__ r, T *__restrict__ rt) {
+  constexpr int N1 = P + 1;
+  PlanePoint q;
+  if (!plane_point<P>(L, a, (long)blockIdx.x * blockDim.x + threadIdx.x, q) || !q.owner) return;
+  const long g = lat_index(L, q.C[0], q.C[1], q.C[2]);
+  if (lat_dirichlet(L, q.C[0], q.C[1], q.C[2])) {
     rt[g] = T(0);
     return;
   }
   T val = r[g];
-  if (nb == 1 && p >= 2) {
-    int a = onv[0] ? 0 : (onv[1] ? 1 : 2);
-    long stride = a == 0 ? 1 : (a == 1 ? (long)L.Nx : (long)L.Nx * L.Ny);
+  if (q.face && P >= 2) {
+    const long stride = a == 0 ? 1 : (a == 1 ? (long)L.Nx : (long)L.Nx * L.Ny);
+    const int na = ncells_axis(L, a);
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
       int cell[3];
-      for (int d = 0; d < 3; ++d) cell[d] = C[d] / p;
-      cell[a] = C[a] / p - 1 + side;
-      if (cell[a] < 0 || cell[a] >= ncells_axis(L, a)) continue;
-      int e = side == 0 ? p : 0;
-      int cid = cell[0] + L.nx * (cell[1] + L.ny * cell[2]);
-      T s[3] = {coef[6 * cid], coef[6 * cid + 1], coef[6 * cid + 2]};
-      T mu = coef[6 * cid + 3];
-      int loc[3];
-      for (int d = 0; d < 3; ++d) loc[d] = C[d] - cell[d] * p;
-      T part = 0;
-      T base = mu;
+      for (int d = 0; d < 3; ++d) cell[d] = q.C[d] / P;
+      cell[a] = q.C[a] / P - 1 + side;
+      if (cell[a] < 0 || cell[a] >= na) continue;
+      const int e = side == 0 ? P : 0;
+      const int cid = cell[0] + L.nx * (cell[1] + L.ny * cell[2]);
+      const T sa = coef[6 * cid + a];
+      T base = coef[6 * cid + 3];
       for (int d = 0; d < 3; ++d)
-        if (d != a) base += s[d] * lam[loc[d]];
-      long g0 = g - (long)loc[a] * stride;  // lattice index of local coordinate 0 on axis a
-      for (int i = 1; i < p; ++i) {
-        T dd = base + s[a] * lam[i];
-        part += Ag[e * n1 + i] * r[g0 + i * stride] / dd;
-      }
-      val -= s[a] * part;
+        if (d != a) base += coef[6 * cid + d] * lam[q.C[d] - cell[d] * P];
+      const long g0 = g + (long)(cell[a] * P - q.C[a]) * stride;  // local coordinate 0 on axis a
+      T rr[P + 1];
+#pragma unroll
+      for (int i = 1; i < P; ++i) rr[i] = r[g0 + i * stride];
+      T part = 0;
+#pragma unroll
+      for (int i = 1; i < P; ++i) part += Ag[e * N1 + i] * rr[i] / (base + sa * lam[i]);
+      val -= sa * part;
     }
   }
   rt[g] = val;
@@ -327,67 +359,63 @@ __global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E,
 // vertex id) of the patch solutions; Dirichlet rows copy r.
 // Step 4 (harmonic extension, R_Gamma^T): z_I = P_II^{-1} (r_I - P_IG z_G).
 // ------------------------------------------------------------------------------------
-template <typename T>
-__global__ void k_expand_iface(LatDev L, int nrows, const T *__restrict__ r, const T *__restrict__ zbuf,
-                               T *__restrict__ z, long n) {
-  long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const int p = L.p;
-  int C[3] = {(int)(g % L.Nx), (int)((g / L.Nx) % L.Ny), (int)(g / ((long)L.Nx * L.Ny))};
-  int lo[3], hi[3], nb = 0;
-  for (int d = 0; d < 3; ++d) {
-    if (C[d] % p == 0) {
-      lo[d] = hi[d] = C[d] / p;
-      ++nb;
-    } else {
-      lo[d] = C[d] / p;
-      hi[d] = lo[d] + 1;
-    }
-  }
-  if (nb == 0) return;
-  if (lat_dirichlet(L, C[0], C[1], C[2])) {
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_expand_plane(LatDev L, int a, const T *__restrict__ r,
+                                                       const T *__restrict__ zbuf, T *__restrict__ z) {
+  PlanePoint q;
+  if (!plane_point<P>(L, a, (long)blockIdx.x * blockDim.x + threadIdx.x, q) || !q.owner) return;
+  const long g = lat_index(L, q.C[0], q.C[1], q.C[2]);
+  if (lat_dirichlet(L, q.C[0], q.C[1], q.C[2])) {
     z[g] = r[g];
     return;
+  }
+  constexpr int NR = 1 + 6 * (P - 1) + 12 * (P - 1) * (P - 1);
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = q.C[d] / P;
+    hi[d] = (q.C[d] % P == 0) ? lo[d] : lo[d] + 1;
   }
   const int nvx = L.nx + 1, nvy = L.ny + 1;
   T acc = 0;
   for (int vz = lo[2]; vz <= hi[2]; ++vz)
     for (int vy = lo[1]; vy <= hi[1]; ++vy)
       for (int vx = lo[0]; vx <= hi[0]; ++vx) {
-        int k = patch_local_index(p, C[0] - vx * p, C[1] - vy * p, C[2] - vz * p);
-        long vid = vx + (long)nvx * (vy + (long)nvy * vz);
-        acc += zbuf[vid * nrows + k];
+        const int k = patch_local_index(P, q.C[0] - vx * P, q.C[1] - vy * P, q.C[2] - vz * P);
+        const long vid = vx + (long)nvx * (vy + (long)nvy * vz);
+        acc += zbuf[vid * NR + k];
       }
   z[g] = acc;
 }
 
-template <typename T>
-__global__ void k_expand_interior(LatDev L, const T *__restrict__ coef, const T *__restrict__ Ag,
-                                  const T *__restrict__ lam, const T *__restrict__ r, T *__restrict__ z,
-                                  long n) {
-  long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const int p = L.p, n1 = p + 1;
-  int C[3] = {(int)(g % L.Nx), (int)((g / L.Nx) % L.Ny), (int)(g / ((long)L.Nx * L.Ny))};
-  if (C[0] % p == 0 || C[1] % p == 0 || C[2] % p == 0) return;
-  int cell[3], loc[3];
-  for (int d = 0; d < 3; ++d) {
-    cell[d] = C[d] / p;
-    loc[d] = C[d] - cell[d] * p;
-  }
-  int cid = cell[0] + L.nx * (cell[1] + L.ny * cell[2]);
-  T s[3] = {coef[6 * cid], coef[6 * cid + 1], coef[6 * cid + 2]};
+// Interior DoFs only: lattice points with no coordinate on a vertex plane,
+// enumerated so that consecutive threads run along x.
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_expand_interior(LatDev L, const T *__restrict__ coef,
+                                                          const T *__restrict__ Ag, const T *__restrict__ lam,
+                                                          const T *__restrict__ r, T *__restrict__ z, long n) {
+  constexpr int N1 = P + 1, Q = P - 1;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const long mx = (long)L.nx * Q, my = (long)L.ny * Q;
+  const int ix = t % mx, iy = (t / mx) % my, iz = t / (mx * my);
+  const int cell[3] = {ix / Q, iy / Q, iz / Q};
+  const int loc[3] = {1 + ix % Q, 1 + iy % Q, 1 + iz % Q};
+  const int C[3] = {cell[0] * P + loc[0], cell[1] * P + loc[1], cell[2] * P + loc[2]};
+  const long g = lat_index(L, C[0], C[1], C[2]);
+  const int cid = cell[0] + L.nx * (cell[1] + L.ny * cell[2]);
+  const T s[3] = {coef[6 * cid], coef[6 * cid + 1], coef[6 * cid + 2]};
   T dd = coef[6 * cid + 3];
   T val = r[g];
-  for (int a = 0; a < 3; ++a) {
-    dd += s[a] * lam[loc[a]];
-    for (int side = 0; side < 2; ++side) {
-      int e = side ? p : 0;
-      int F[3] = {C[0], C[1], C[2]};
-      F[a] = cell[a] * p + e;
-      T zf = lat_dirichlet(L, F[0], F[1], F[2]) ? T(0) : z[lat_index(L, F[0], F[1], F[2])];
-      val -= s[a] * Ag[loc[a] * n1 + e] * zf;
-    }
+  const long stride[3] = {1, (long)L.Nx, (long)L.Nx * L.Ny};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    dd += s[d] * lam[loc[d]];
+    const int Fl[3] = {d == 0 ? cell[0] * P : C[0], d == 1 ? cell[1] * P : C[1], d == 2 ? cell[2] * P : C[2]};
+    const int Fh[3] = {d == 0 ? cell[0] * P + P : C[0], d == 1 ? cell[1] * P + P : C[1],
+                       d == 2 ? cell[2] * P + P : C[2]};
+    const T zl = lat_dirichlet(L, Fl[0], Fl[1], Fl[2]) ? T(0) : z[g - (long)loc[d] * stride[d]];
+    const T zh = lat_dirichlet(L, Fh[0], Fh[1], Fh[2]) ? T(0) : z[g + (long)(P - loc[d]) * stride[d]];
+    val -= s[d] * (Ag[loc[d] * N1] * zl + Ag[loc[d] * N1 + P] * zh);
   }
   z[g] = val / dd;
 }
@@ -683,11 +711,46 @@ void launch_apply_grad(const LatDev &L, const T *coef, const double *Bh, const d
   k_apply_gather<T><<<nblocks(n, 256), 256, 0, s>>>(L, x, ebuf, y, n);
 }
 
+static long plane_points(const LatDev &L, int a) {
+  const long Nd[3] = {L.Nx, L.Ny, L.Nz}, nd[3] = {L.nx, L.ny, L.nz};
+  return (nd[a] + 1) * Nd[a == 0 ? 1 : 0] * Nd[a == 2 ? 1 : 2];
+}
+
+template <int P, typename T>
+static void condense_p(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *rt, hipStream_t s) {
+  for (int a = 0; a < 3; ++a)
+    k_condense_plane<P, T><<<nblocks(plane_points(L, a), 256), 256, 0, s>>>(L, a, coef, A, lam, r, rt);
+}
+
+template <int P, typename T>
+static void expand_p(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, const T *zbuf, T *z,
+                     hipStream_t s) {
+  for (int a = 0; a < 3; ++a)
+    k_expand_plane<P, T><<<nblocks(plane_points(L, a), 256), 256, 0, s>>>(L, a, r, zbuf, z);
+  const long ni = (long)L.nx * L.ny * L.nz * (P - 1) * (P - 1) * (P - 1);
+  if (ni > 0) k_expand_interior<P, T><<<nblocks(ni, 256), 256, 0, s>>>(L, coef, A, lam, r, z, ni);
+}
+
+#define RZ_DISPATCH_P(p, call) \
+  switch (p) {                 \
+    case 1: call(1); break;    \
+    case 2: call(2); break;    \
+    case 3: call(3); break;    \
+    case 4: call(4); break;    \
+    case 5: call(5); break;    \
+    case 6: call(6); break;    \
+    case 7: call(7); break;    \
+    case 8: call(8); break;    \
+    case 9: call(9); break;    \
+    default: break;            \
+  }
+
 template <typename T>
 void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *rt,
                           hipStream_t s) {
-  long n = (long)L.Nx * L.Ny * L.Nz;
-  k_condense_grad<T><<<nblocks(n, 256), 256, 0, s>>>(L, coef, A, lam, r, rt, n);
+#define RZ_CALL(P) condense_p<P, T>(L, coef, A, lam, r, rt, s)
+  RZ_DISPATCH_P(L.p, RZ_CALL)
+#undef RZ_CALL
 }
 
 int device_cu_count() {
@@ -726,9 +789,9 @@ int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, c
 template <typename T>
 void launch_expand_grad(const LatDev &L, const PatchDev &P, const T *coef, const T *A, const T *lam,
                         const T *r, const T *zbuf, T *z, hipStream_t s) {
-  long n = (long)L.Nx * L.Ny * L.Nz;
-  k_expand_iface<T><<<nblocks(n, 256), 256, 0, s>>>(L, P.nrows, r, zbuf, z, n);
-  k_expand_interior<T><<<nblocks(n, 256), 256, 0, s>>>(L, coef, A, lam, r, z, n);
+#define RZ_CALL(Q) expand_p<Q, T>(L, coef, A, lam, r, zbuf, z, s)
+  RZ_DISPATCH_P(L.p, RZ_CALL)
+#undef RZ_CALL
 }
 
 void launch_patch_factor(const LatDev &L, const PatchDev &P, const double *coef, const double *B,
