@@ -182,16 +182,33 @@ def reference_values(el, space, xq):
     raise ValueError(space)
 
 
-def quadrature_cell_matrix(el, space, corners, alpha, beta, q):
-    """Dense cell matrix on a trilinear cell with q Gauss-Legendre points per axis.
-    alpha, beta: scalars or callables of physical points (nq, 3)."""
-    xq, wq = gauss_legendre(q)
+def _cell_coef(c, X, xq):
+    """Coefficient values at the tensor points: scalar, callable of physical points,
+    or 27 reference samples of the cell (triquadratic interpolation)."""
+    if callable(c):
+        return c(X)
+    c = np.asarray(c, dtype=np.float64)
+    if c.size == 27:
+        from .quadrature import sampled_values
+        return sampled_values(c[None, :], xq)[0]
+    return np.full(X.shape[0], float(c))
+
+
+def quadrature_cell_matrix(el, space, corners, alpha, beta, q, kind="gl"):
+    """Dense cell matrix on a trilinear cell with q points per axis (Gauss-Legendre,
+    or Gauss-Lobatto-Legendre for kind="gll").  alpha, beta: scalars, callables of
+    physical points (nq, 3), or 27 reference samples."""
+    if kind == "gl":
+        xq, wq = gauss_legendre(q)
+    else:
+        from .quadrature import rule
+        xq, wq = rule(q, kind)
     W = np.einsum("z,y,x->zyx", wq, wq, wq).ravel()
     X, J = trilinear_jacobian(corners, xq)
     det = np.linalg.det(J)
     Jinv = np.linalg.inv(J)
-    a = alpha(X) if callable(alpha) else np.full(X.shape[0], float(alpha))
-    b = beta(X) if callable(beta) else np.full(X.shape[0], float(beta))
+    a = _cell_coef(alpha, X, xq)
+    b = _cell_coef(beta, X, xq)
     val, dval = reference_values(el, space, xq)
     if space == "grad":
         phys_v = val                                              # identity
@@ -247,16 +264,22 @@ def cartesian_operator(lat: Lattice, alpha, beta):
     return assemble(lat, mats)
 
 
-def quadrature_operator(lat: Lattice, alpha, beta, q=None):
+def quadrature_operator(lat: Lattice, alpha, beta, q=None, kind="gl"):
     """Global matrix by per-cell quadrature (any trilinear mesh).  alpha, beta:
-    scalar, per-cell array, or callable of physical points."""
+    scalar, per-cell array (ncells,), per-cell samples (ncells, 27), or callable of
+    physical points."""
     mesh = lat.mesh
     el = Element1D(lat.p)
     q = q or (lat.p + 2)
     cv = mesh.cell_vertices()
+
+    def pick(c, k):
+        if callable(c) or np.isscalar(c):
+            return c
+        c = np.asarray(c)
+        return c[k] if c.ndim == 2 else float(c[k])
+
     mats = []
     for k in range(mesh.ncells):
-        a = alpha if (callable(alpha) or np.isscalar(alpha)) else float(alpha[k])
-        b = beta if (callable(beta) or np.isscalar(beta)) else float(beta[k])
-        mats.append(quadrature_cell_matrix(el, lat.space, cv[k], a, b, q))
+        mats.append(quadrature_cell_matrix(el, lat.space, cv[k], pick(alpha, k), pick(beta, k), q, kind))
     return assemble(lat, mats)

@@ -41,13 +41,18 @@ def cell_geometry(mesh, xq, cells):
     return np.array(Js), np.array(Xs)
 
 
-def apply(lat: Lattice, x, alpha, beta, q=None, chunk=2048):
-    """y = A x by sum factorisation.  alpha, beta: scalar, per-cell array, or callable
-    of physical points (n, 3)."""
+def apply(lat: Lattice, x, alpha, beta, q=None, chunk=2048, kind="gl"):
+    """y = A x by sum factorisation.  alpha, beta: scalar, per-cell array (ncells,),
+    per-cell reference samples (ncells, 27), or callable of physical points (n, 3).
+    q points per axis, Gauss-Legendre (kind "gl") or Gauss-Lobatto-Legendre ("gll")."""
     mesh, p, space = lat.mesh, lat.p, lat.space
     el = Element1D(p)
     q = q or (p + 2)
-    xq, wq = gauss_legendre(q)
+    if kind == "gl":
+        xq, wq = gauss_legendre(q)
+    else:
+        from .quadrature import rule
+        xq, wq = rule(q, kind)
     W = np.einsum("z,y,x->zyx", wq, wq, wq)
     tabs = _axis_tables(el, xq)
     kinds = component_kinds(space, p)
@@ -65,8 +70,8 @@ def apply(lat: Lattice, x, alpha, beta, q=None, chunk=2048):
         det = np.linalg.det(J)
         Jinv = np.linalg.inv(J)
         Xf = X.reshape(-1, 3)
-        a = _coef(alpha, cells, Xf, q)
-        b = _coef(beta, cells, Xf, q)
+        a = _coef(alpha, cells, Xf, q, xq)
+        b = _coef(beta, cells, Xf, q, xq)
         wdet = (W.ravel()[None, :] * det)
         tiles = [xf[cd[cells, off[m]:off[m + 1]]].reshape((nc,) + lat.local_shape(m)[::-1])
                  for m in range(ncomp)]
@@ -130,11 +135,14 @@ def apply(lat: Lattice, x, alpha, beta, q=None, chunk=2048):
     return y
 
 
-def _coef(c, cells, Xf, q):
+def _coef(c, cells, Xf, q, xq):
     n = cells.size
     if callable(c):
         return c(Xf).reshape(n, q ** 3)
     c = np.asarray(c, dtype=np.float64)
     if c.ndim == 0:
         return np.full((n, q ** 3), float(c))
+    if c.ndim == 2:
+        from .quadrature import sampled_values
+        return sampled_values(c[cells], xq)
     return np.repeat(c[cells][:, None], q ** 3, axis=1)
