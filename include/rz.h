@@ -67,8 +67,18 @@ typedef struct {
 
 /* Coefficients alpha, beta > 0 of a^k.  RZ_COEF_CONST: alpha[0], beta[0].
  * RZ_COEF_CELL: one value per cell (cells cx + nx*(cy + ny*cz)), constant on the
- * cell.  Host arrays. */
-enum { RZ_COEF_CONST = 0, RZ_COEF_CELL = 1 };
+ * cell.  RZ_COEF_SAMPLES: 27 values per cell, the coefficient at the images of the
+ * reference points {-1,0,1}^3 (x fastest) under the cell's trilinear map; the
+ * coefficient is their triquadratic interpolant on the reference cell.  Host
+ * arrays.
+ *
+ * Cartesian meshes with RZ_COEF_CONST / RZ_COEF_CELL use the exact Kronecker cell
+ * matrices (Sec. 3.2 closed form).  Any other mesh (trilinear cells) or
+ * RZ_COEF_SAMPLES integrates with q = ceil(3(p+1)/2) Gauss-Lobatto-Legendre points
+ * per axis (Sec. 5); the relaxation then uses separable per-cell weights from cell
+ * averages of the coefficient-weighted metric, and the p=1 coarse operator is
+ * integrated with 3 points per axis. */
+enum { RZ_COEF_CONST = 0, RZ_COEF_CELL = 1, RZ_COEF_SAMPLES = 2 };
 typedef struct {
   int32_t kind;
   const double *alpha;
@@ -83,7 +93,7 @@ enum {
 
 typedef struct {
   int32_t space;       /* rz_space                                                  */
-  int32_t p;           /* polynomial degree, 1 <= p <= 12                           */
+  int32_t p;           /* polynomial degree, 1 <= p <= 9                            */
   int32_t precision;   /* RZ_PREC_*                                                 */
   int32_t maxit;       /* CG iteration cap (default 200)                            */
   double rtol;         /* relative tolerance on the 2-norm residual (default 1e-8)   */
@@ -115,9 +125,10 @@ const char *rz_last_error(const rz_ctx *ctx);
 /* Build everything a solve needs (Sec. 3.2 auxiliary operator, Sec. 4.4 static
  * condensation, Sec. 4.5 incomplete Cholesky of every vertex-star interface
  * patch on the static-condensation pattern, the p=1 coarse problem of eq.
- * asm-afw and its factorisation).  Requires a Cartesian mesh (axis-aligned
- * boxes).  Returns RZ_ERR_BREAKDOWN if an IC pivot is not positive and
- * RZ_ERR_SINGULAR if the coarse factorisation fails. */
+ * asm-afw and its factorisation).  Cells must have a positive Jacobian
+ * determinant at every quadrature point (RZ_ERR_ARG otherwise).  Returns
+ * RZ_ERR_BREAKDOWN if an IC pivot is not positive and RZ_ERR_SINGULAR if the
+ * coarse factorisation fails. */
 rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *coef,
                    const rz_opts *opts, rz_problem **out);
 rz_status rz_free(rz_problem *h);

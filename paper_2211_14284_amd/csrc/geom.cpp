@@ -1,0 +1,115 @@
+// Host geometry of trilinear cells (see geom.hpp).
+#include "geom.hpp"
+
+#include <cmath>
+
+namespace rz {
+
+void build_quad_tables(const Tables1D &t, int q, QuadTables &Q) {
+  Q.p = t.p;
+  Q.q = q;
+  gll_rule(q, Q.xq, Q.wq);
+  fdm_eval(t, Q.xq, Q.Bq, Q.Dq);
+  Q.Lq.assign(3 * q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    const double x = Q.xq[i];
+    Q.Lq[3 * i] = 0.5 * x * (x - 1.0);
+    Q.Lq[3 * i + 1] = 1.0 - x * x;
+    Q.Lq[3 * i + 2] = 0.5 * x * (x + 1.0);
+  }
+}
+
+double trilinear_jacobian(const double *c, const double xi[3], double J[9]) {
+  for (int e = 0; e < 9; ++e) J[e] = 0.0;
+  for (int k = 0; k < 8; ++k) {
+    double sg[3], f[3];
+    for (int a = 0; a < 3; ++a) {
+      sg[a] = ((k >> a) & 1) ? 1.0 : -1.0;
+      f[a] = 0.5 * (1.0 + sg[a] * xi[a]);
+    }
+    const double dN[3] = {0.5 * sg[0] * f[1] * f[2], 0.5 * sg[1] * f[0] * f[2], 0.5 * sg[2] * f[0] * f[1]};
+    for (int r = 0; r < 3; ++r)
+      for (int s = 0; s < 3; ++s) J[3 * r + s] += dN[s] * c[3 * k + r];
+  }
+  return J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) + J[2] * (J[3] * J[7] - J[4] * J[6]);
+}
+
+static void inverse3(const double J[9], double det, double Ji[9]) {
+  Ji[0] = (J[4] * J[8] - J[5] * J[7]) / det;
+  Ji[1] = (J[2] * J[7] - J[1] * J[8]) / det;
+  Ji[2] = (J[1] * J[5] - J[2] * J[4]) / det;
+  Ji[3] = (J[5] * J[6] - J[3] * J[8]) / det;
+  Ji[4] = (J[0] * J[8] - J[2] * J[6]) / det;
+  Ji[5] = (J[2] * J[3] - J[0] * J[5]) / det;
+  Ji[6] = (J[3] * J[7] - J[4] * J[6]) / det;
+  Ji[7] = (J[1] * J[6] - J[0] * J[7]) / det;
+  Ji[8] = (J[0] * J[4] - J[1] * J[3]) / det;
+}
+
+static double interp27(const double *s, const QuadTables &Q, int i, int j, int k) {
+  double v = 0.0;
+  for (int c = 0; c < 3; ++c)
+    for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < 3; ++a) v += s[a + 3 * b + 9 * c] * Q.Lq[3 * i + a] * Q.Lq[3 * j + b] * Q.Lq[3 * k + c];
+  return v;
+}
+
+bool averaged_weights(const double *corners, const double *as, const double *bs, const QuadTables &Q,
+                      double out[6]) {
+  const int q = Q.q;
+  double sig[3] = {0, 0, 0}, mu = 0;
+  for (int k = 0; k < q; ++k)
+    for (int j = 0; j < q; ++j)
+      for (int i = 0; i < q; ++i) {
+        const double xi[3] = {Q.xq[i], Q.xq[j], Q.xq[k]};
+        double J[9], Ji[9];
+        const double det = trilinear_jacobian(corners, xi, J);
+        if (!(det > 0)) return false;
+        inverse3(J, det, Ji);
+        const double al = interp27(as, Q, i, j, k), be = interp27(bs, Q, i, j, k);
+        if (!(al > 0) || !(be > 0)) return false;
+        const double w = Q.wq[i] * Q.wq[j] * Q.wq[k] * det;
+        for (int s = 0; s < 3; ++s)
+          sig[s] += w * al * (Ji[3 * s] * Ji[3 * s] + Ji[3 * s + 1] * Ji[3 * s + 1] + Ji[3 * s + 2] * Ji[3 * s + 2]);
+        mu += w * be;
+      }
+  for (int s = 0; s < 3; ++s) out[s] = 0.125 * sig[s];
+  for (int s = 0; s < 3; ++s) out[3 + s] = 0.125 * mu;
+  return true;
+}
+
+bool q1_cell_matrix(const double *corners, const double *as, const double *bs, const QuadTables &Q,
+                    double K[64]) {
+  const int q = Q.q;
+  for (int e = 0; e < 64; ++e) K[e] = 0.0;
+  for (int k = 0; k < q; ++k)
+    for (int j = 0; j < q; ++j)
+      for (int i = 0; i < q; ++i) {
+        const double xi[3] = {Q.xq[i], Q.xq[j], Q.xq[k]};
+        double J[9], Ji[9];
+        const double det = trilinear_jacobian(corners, xi, J);
+        if (!(det > 0)) return false;
+        inverse3(J, det, Ji);
+        const double al = interp27(as, Q, i, j, k), be = interp27(bs, Q, i, j, k);
+        const double w = Q.wq[i] * Q.wq[j] * Q.wq[k] * det;
+        double N[8], gx[8][3];
+        for (int n = 0; n < 8; ++n) {
+          double sg[3], f[3];
+          for (int a = 0; a < 3; ++a) {
+            sg[a] = ((n >> a) & 1) ? 1.0 : -1.0;
+            f[a] = 0.5 * (1.0 + sg[a] * xi[a]);
+          }
+          N[n] = f[0] * f[1] * f[2];
+          const double g[3] = {0.5 * sg[0] * f[1] * f[2], 0.5 * sg[1] * f[0] * f[2], 0.5 * sg[2] * f[0] * f[1]};
+          // physical gradient J^-T g: component r = sum_s Ji[s][r] g_s
+          for (int r = 0; r < 3; ++r) gx[n][r] = Ji[r] * g[0] + Ji[3 + r] * g[1] + Ji[6 + r] * g[2];
+        }
+        for (int a = 0; a < 8; ++a)
+          for (int b = 0; b < 8; ++b)
+            K[8 * a + b] += w * (al * (gx[a][0] * gx[b][0] + gx[a][1] * gx[b][1] + gx[a][2] * gx[b][2]) +
+                                 be * N[a] * N[b]);
+      }
+  return true;
+}
+
+}  // namespace rz

@@ -707,6 +707,11 @@ void launch_apply_grad(const LatDev &L, const T *coef, const double *Bh, const d
     case 9: apply_kron<9, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
     default: break;
   }
+  launch_apply_gather<T>(L, x, ebuf, y, s);
+}
+
+template <typename T>
+void launch_apply_gather(const LatDev &L, const T *x, const T *ebuf, T *y, hipStream_t s) {
   long n = (long)L.Nx * L.Ny * L.Nz;
   k_apply_gather<T><<<nblocks(n, 256), 256, 0, s>>>(L, x, ebuf, y, n);
 }
@@ -828,6 +833,8 @@ template void launch_apply_grad<double>(const LatDev &, const double *, const do
                                         const double *, double *, double *, hipStream_t);
 template void launch_apply_grad<float>(const LatDev &, const float *, const double *, const double *,
                                        const float *, float *, float *, hipStream_t);
+template void launch_apply_gather<double>(const LatDev &, const double *, const double *, double *, hipStream_t);
+template void launch_apply_gather<float>(const LatDev &, const float *, const float *, float *, hipStream_t);
 template void launch_condense_grad<double>(const LatDev &, const double *, const double *, const double *,
                                            const double *, double *, hipStream_t);
 template void launch_condense_grad<float>(const LatDev &, const float *, const float *, const float *,

@@ -38,6 +38,16 @@ struct PatchEllDev {
   const int *off;                  // 3*nrows: lattice offsets of the patch rows
 };
 
+// Trilinear cells with sampled coefficients: vertex coordinates (nvertices x 3,
+// FP64), 27 coefficient samples per cell, and the quadrature tabulations of
+// QuadTables (Bq, Dq: Q x (p+1); wq, xq: Q; Lq: Q x 3) in the compute precision.
+template <typename T>
+struct QuadDev {
+  const double *vert;
+  const T *as, *bs;
+  const T *Bq, *Dq, *wq, *xq, *Lq;
+};
+
 // ---- vectors ------------------------------------------------------------------
 void launch_fill(double *y, double v, int64_t n, hipStream_t s);
 void launch_cast_d2f(const double *x, float *y, int64_t n, hipStream_t s);
@@ -65,6 +75,13 @@ void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *l
 size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves);
 template <typename T>
 int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf, hipStream_t s);
+// Cell phase of y = A x on trilinear cells (interior rows to y, interface rows to
+// ebuf); the interface rows are then summed by launch_apply_gather.  Returns
+// non-zero for an unsupported degree.
+template <typename T>
+int launch_apply_quad_cells(const LatDev &L, const QuadDev<T> &G, const T *x, T *y, T *ebuf, hipStream_t s);
+template <typename T>
+void launch_apply_gather(const LatDev &L, const T *x, const T *ebuf, T *y, hipStream_t s);
 // number of compute units of the current device (cached), for persistent grids
 int device_cu_count();
 template <typename T>

@@ -14,6 +14,7 @@
 
 #include "kernels.hpp"
 #include "lattice.hpp"
+#include "geom.hpp"
 #include "patch.hpp"
 #include "tables1d.hpp"
 
@@ -54,6 +55,13 @@ struct rz_problem {
   std::vector<void *> allocs;
   double *coef64 = nullptr, *B64 = nullptr, *A64 = nullptr, *lam64 = nullptr, *E64 = nullptr;
   float *coef32 = nullptr, *B32 = nullptr, *A32 = nullptr, *lam32 = nullptr;
+  // trilinear / sampled-coefficient path
+  bool quad = false;
+  QuadTables qt;
+  std::vector<double> vert, asmp, bsmp;  // vertices (nvert x 3), 27 samples per cell
+  std::vector<double> cellA1;            // p=1 cell matrices (ncells x 64)
+  QuadDev<double> Q64{};
+  QuadDev<float> Q32{};
   double *f64 = nullptr, *eb64 = nullptr;
   float *f32 = nullptr, *eb32 = nullptr;
   double *rt64 = nullptr, *zb64 = nullptr;
@@ -200,7 +208,12 @@ void v_scale_copy(rz_problem *h, double a, const double *x, double *y) {
 // ---------------------------------------------------------------------------------------
 rz_status do_apply64(rz_problem *h, const double *x, double *y) {
   Timed t(h, RZ_K_APPLY);
-  launch_apply_grad<double>(h->L, h->coef64, h->t.B.data(), h->t.A.data(), x, y, h->eb64, h->ctx->stream);
+  if (h->quad) {
+    launch_apply_quad_cells<double>(h->L, h->Q64, x, y, h->eb64, h->ctx->stream);
+    launch_apply_gather<double>(h->L, x, h->eb64, y, h->ctx->stream);
+  } else {
+    launch_apply_grad<double>(h->L, h->coef64, h->t.B.data(), h->t.A.data(), x, y, h->eb64, h->ctx->stream);
+  }
   return RZ_OK;
 }
 
@@ -417,10 +430,11 @@ rz_status setup_coarse(rz_problem *h) {
       int64_t row = (Vi[0] - lo[0]) + h->cmx * ((Vi[1] - lo[1]) + (int64_t)h->cmy * (Vi[2] - lo[2]));
       for (int j = 0; j < 8; ++j) {
         int ja[3] = {j & 1, (j >> 1) & 1, j >> 2};
-        double v = w[0] * A1(ia[0], ja[0]) * B1(ia[1], ja[1]) * B1(ia[2], ja[2]) +
-                   w[1] * B1(ia[0], ja[0]) * A1(ia[1], ja[1]) * B1(ia[2], ja[2]) +
-                   w[2] * B1(ia[0], ja[0]) * B1(ia[1], ja[1]) * A1(ia[2], ja[2]) +
-                   w[3] * B1(ia[0], ja[0]) * B1(ia[1], ja[1]) * B1(ia[2], ja[2]);
+        double v = h->quad ? h->cellA1[64 * c + 8 * i + j]
+                           : w[0] * A1(ia[0], ja[0]) * B1(ia[1], ja[1]) * B1(ia[2], ja[2]) +
+                                 w[1] * B1(ia[0], ja[0]) * A1(ia[1], ja[1]) * B1(ia[2], ja[2]) +
+                                 w[2] * B1(ia[0], ja[0]) * B1(ia[1], ja[1]) * A1(ia[2], ja[2]) +
+                                 w[3] * B1(ia[0], ja[0]) * B1(ia[1], ja[1]) * B1(ia[2], ja[2]);
         int off = (ja[0] - ia[0] + 1) + 3 * (ja[1] - ia[1] + 1) + 9 * (ja[2] - ia[2] + 1);
         st[row * 27 + off] += v;
       }
@@ -550,7 +564,8 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
   if (opts->p < 1 || opts->p > 9) return fail(ctx, RZ_ERR_ARG, "p must be in 1..9");
   if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(ctx, RZ_ERR_ARG, "bad mesh size");
   if (mesh->dirichlet_faces > 0x3F) return fail(ctx, RZ_ERR_ARG, "bad Dirichlet mask");
-  if (cf->kind != RZ_COEF_CONST && cf->kind != RZ_COEF_CELL) return fail(ctx, RZ_ERR_ARG, "bad coefficient kind");
+  if (cf->kind != RZ_COEF_CONST && cf->kind != RZ_COEF_CELL && cf->kind != RZ_COEF_SAMPLES)
+    return fail(ctx, RZ_ERR_ARG, "bad coefficient kind");
   if (!cf->alpha || !cf->beta) return fail(ctx, RZ_ERR_ARG, "missing coefficients");
   if (opts->precision != RZ_PREC_F64 && opts->precision != RZ_PREC_MIXED)
     return fail(ctx, RZ_ERR_ARG, "bad precision");
@@ -571,46 +586,85 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
   h->ndofs = (int64_t)h->Nx * h->Ny * h->Nz;
   h->ncells = (int64_t)h->nx * h->ny * h->nz;
   h->nvert = (int64_t)(h->nx + 1) * (h->ny + 1) * (h->nz + 1);
-  // geometry: a tensor grid of axis-aligned boxes
-  const int nvx = h->nx + 1, nvy = h->ny + 1, nvz = h->nz + 1;
-  std::vector<double> gx(nvx), gy(nvy), gz(nvz);
-  for (int i = 0; i < nvx; ++i) gx[i] = (double)i / h->nx;
-  for (int i = 0; i < nvy; ++i) gy[i] = (double)i / h->ny;
-  for (int i = 0; i < nvz; ++i) gz[i] = (double)i / h->nz;
-  if (mesh->vertex_xyz) {
-    const double *v = mesh->vertex_xyz;
-    for (int i = 0; i < nvx; ++i) gx[i] = v[3 * i];
-    for (int i = 0; i < nvy; ++i) gy[i] = v[3 * (i * nvx) + 1];
-    for (int i = 0; i < nvz; ++i) gz[i] = v[3 * (i * nvx * nvy) + 2];
-    for (int64_t k = 0; k < h->nvert; ++k) {
-      int vx = k % nvx, vy = (k / nvx) % nvy, vz = k / ((int64_t)nvx * nvy);
-      if (v[3 * k] != gx[vx] || v[3 * k + 1] != gy[vy] || v[3 * k + 2] != gz[vz]) {
-        delete h;
-        return fail(ctx, RZ_ERR_ARG, "mesh is not Cartesian (axis-aligned boxes required)");
-      }
-    }
-  }
-  h->coef.assign(6 * h->ncells, 0.0);
-  for (int64_t c = 0; c < h->ncells; ++c) {
-    int cx = c % h->nx, cy = (c / h->nx) % h->ny, cz = c / ((int64_t)h->nx * h->ny);
-    double hs[3] = {gx[cx + 1] - gx[cx], gy[cy + 1] - gy[cy], gz[cz + 1] - gz[cz]};
-    if (!(hs[0] > 0 && hs[1] > 0 && hs[2] > 0)) {
-      delete h;
-      return fail(ctx, RZ_ERR_ARG, "cells must have positive extent");
-    }
-    double al = cf->kind == RZ_COEF_CONST ? cf->alpha[0] : cf->alpha[c];
-    double be = cf->kind == RZ_COEF_CONST ? cf->beta[0] : cf->beta[c];
-    if (!(al > 0 && be > 0)) {
-      delete h;
-      return fail(ctx, RZ_ERR_ARG, "alpha and beta must be positive");
-    }
-    double V = hs[0] * hs[1] * hs[2];
-    for (int d = 0; d < 3; ++d) h->coef[6 * c + d] = al * V / (2.0 * hs[d] * hs[d]);
-    for (int d = 0; d < 3; ++d) h->coef[6 * c + 3 + d] = be * V / 8.0;
-  }
   if (!build_tables1d(p, h->t) || !build_tables1d(1, h->t1)) {
     delete h;
     return fail(ctx, RZ_ERR_ARG, "1-D tables failed");
+  }
+  // geometry: vertices (uniform unit cube by default); a tensor grid of
+  // axis-aligned boxes with cellwise-constant coefficients takes the Kronecker path
+  const int nvx = h->nx + 1, nvy = h->ny + 1, nvz = h->nz + 1;
+  h->vert.resize(3 * h->nvert);
+  for (int64_t k = 0; k < h->nvert; ++k) {
+    const int vx = k % nvx, vy = (k / nvx) % nvy, vz = k / ((int64_t)nvx * nvy);
+    if (mesh->vertex_xyz) {
+      for (int r = 0; r < 3; ++r) h->vert[3 * k + r] = mesh->vertex_xyz[3 * k + r];
+    } else {
+      h->vert[3 * k] = (double)vx / h->nx;
+      h->vert[3 * k + 1] = (double)vy / h->ny;
+      h->vert[3 * k + 2] = (double)vz / h->nz;
+    }
+  }
+  bool cartesian = true;
+  for (int64_t k = 0; k < h->nvert && cartesian; ++k) {
+    const int vx = k % nvx, vy = (k / nvx) % nvy, vz = k / ((int64_t)nvx * nvy);
+    cartesian = h->vert[3 * k] == h->vert[3 * vx] && h->vert[3 * k + 1] == h->vert[3 * (vy * nvx) + 1] &&
+                h->vert[3 * k + 2] == h->vert[3 * (vz * nvx * nvy) + 2];
+  }
+  h->quad = !cartesian || cf->kind == RZ_COEF_SAMPLES;
+  h->coef.assign(6 * h->ncells, 0.0);
+  if (!h->quad) {
+    for (int64_t c = 0; c < h->ncells; ++c) {
+      int cx = c % h->nx, cy = (c / h->nx) % h->ny, cz = c / ((int64_t)h->nx * h->ny);
+      // axis-aligned boxes: extents from the first row of vertices along each axis
+      const double hs[3] = {h->vert[3 * (cx + 1)] - h->vert[3 * cx],
+                            h->vert[3 * ((cy + 1) * nvx) + 1] - h->vert[3 * (cy * nvx) + 1],
+                            h->vert[3 * ((int64_t)(cz + 1) * nvx * nvy) + 2] -
+                                h->vert[3 * ((int64_t)cz * nvx * nvy) + 2]};
+      if (!(hs[0] > 0 && hs[1] > 0 && hs[2] > 0)) {
+        delete h;
+        return fail(ctx, RZ_ERR_ARG, "cells must have positive extent");
+      }
+      double al = cf->kind == RZ_COEF_CONST ? cf->alpha[0] : cf->alpha[c];
+      double be = cf->kind == RZ_COEF_CONST ? cf->beta[0] : cf->beta[c];
+      if (!(al > 0 && be > 0)) {
+        delete h;
+        return fail(ctx, RZ_ERR_ARG, "alpha and beta must be positive");
+      }
+      double V = hs[0] * hs[1] * hs[2];
+      for (int d = 0; d < 3; ++d) h->coef[6 * c + d] = al * V / (2.0 * hs[d] * hs[d]);
+      for (int d = 0; d < 3; ++d) h->coef[6 * c + 3 + d] = be * V / 8.0;
+    }
+  } else {
+    h->asmp.resize(27 * h->ncells);
+    h->bsmp.resize(27 * h->ncells);
+    for (int64_t c = 0; c < h->ncells; ++c)
+      for (int k = 0; k < 27; ++k) {
+        h->asmp[27 * c + k] = cf->kind == RZ_COEF_CONST ? cf->alpha[0]
+                              : cf->kind == RZ_COEF_CELL ? cf->alpha[c] : cf->alpha[27 * c + k];
+        h->bsmp[27 * c + k] = cf->kind == RZ_COEF_CONST ? cf->beta[0]
+                              : cf->kind == RZ_COEF_CELL ? cf->beta[c] : cf->beta[27 * c + k];
+        if (!(h->asmp[27 * c + k] > 0 && h->bsmp[27 * c + k] > 0)) {
+          delete h;
+          return fail(ctx, RZ_ERR_ARG, "coefficient samples must be positive");
+        }
+      }
+    build_quad_tables(h->t, default_quad_points(p), h->qt);
+    QuadTables q1;
+    build_quad_tables(h->t1, default_quad_points(1), q1);
+    h->cellA1.resize(64 * h->ncells);
+    for (int64_t c = 0; c < h->ncells; ++c) {
+      int cx = c % h->nx, cy = (c / h->nx) % h->ny, cz = c / ((int64_t)h->nx * h->ny);
+      double corners[24];
+      for (int k = 0; k < 8; ++k) {
+        const int64_t vid = (cx + (k & 1)) + nvx * ((cy + ((k >> 1) & 1)) + (int64_t)nvy * (cz + (k >> 2)));
+        for (int r = 0; r < 3; ++r) corners[3 * k + r] = h->vert[3 * vid + r];
+      }
+      if (!averaged_weights(corners, &h->asmp[27 * c], &h->bsmp[27 * c], h->qt, &h->coef[6 * c]) ||
+          !q1_cell_matrix(corners, &h->asmp[27 * c], &h->bsmp[27 * c], q1, &h->cellA1[64 * c])) {
+        delete h;
+        return fail(ctx, RZ_ERR_ARG, "non-positive Jacobian determinant or coefficient at a quadrature point");
+      }
+    }
   }
   build_patch_symbolic(p, h->ps);
   h->erow.resize(h->ps.nnz);
@@ -656,6 +710,21 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
       (e = upload(h, &h->lam64, lamf)) || (e = upload(h, &h->E64, h->t.E)) || (e = upload(h, &h->coef32, c32)) ||
       (e = upload(h, &h->B32, B32)) || (e = upload(h, &h->A32, A32)) || (e = upload(h, &h->lam32, l32)))
     return bail(e);
+  if (h->quad) {
+    auto to32 = [](const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); };
+    const QuadTables &qt = h->qt;
+    double *dv = nullptr, *a64 = nullptr, *b64 = nullptr, *qB = nullptr, *qD = nullptr, *qw = nullptr, *qx = nullptr,
+           *qL = nullptr;
+    float *a32 = nullptr, *b32 = nullptr, *fB = nullptr, *fD = nullptr, *fw = nullptr, *fx = nullptr, *fL = nullptr;
+    if ((e = upload(h, &dv, h->vert)) || (e = upload(h, &a64, h->asmp)) || (e = upload(h, &b64, h->bsmp)) ||
+        (e = upload(h, &qB, qt.Bq)) || (e = upload(h, &qD, qt.Dq)) || (e = upload(h, &qw, qt.wq)) ||
+        (e = upload(h, &qx, qt.xq)) || (e = upload(h, &qL, qt.Lq)) || (e = upload(h, &a32, to32(h->asmp))) ||
+        (e = upload(h, &b32, to32(h->bsmp))) || (e = upload(h, &fB, to32(qt.Bq))) || (e = upload(h, &fD, to32(qt.Dq))) ||
+        (e = upload(h, &fw, to32(qt.wq))) || (e = upload(h, &fx, to32(qt.xq))) || (e = upload(h, &fL, to32(qt.Lq))))
+      return bail(e);
+    h->Q64 = QuadDev<double>{dv, a64, b64, qB, qD, qw, qx, qL};
+    h->Q32 = QuadDev<float>{dv, a32, b32, fB, fD, fw, fx, fL};
+  }
   // symbolic patch arrays
   const PatchSymbolic &ps = h->ps;
   std::vector<int> sym;
@@ -756,8 +825,14 @@ rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t) {
   if (t == RZ_F64) return do_apply64(h, static_cast<const double *>(x), static_cast<double *>(y));
   if (t == RZ_F32) {
     Timed t(h, RZ_K_APPLY);
-    launch_apply_grad<float>(h->L, h->coef32, h->t.B.data(), h->t.A.data(), static_cast<const float *>(x),
-                             static_cast<float *>(y), h->eb32, h->ctx->stream);
+    const float *xf = static_cast<const float *>(x);
+    float *yf = static_cast<float *>(y);
+    if (h->quad) {
+      launch_apply_quad_cells<float>(h->L, h->Q32, xf, yf, h->eb32, h->ctx->stream);
+      launch_apply_gather<float>(h->L, xf, h->eb32, yf, h->ctx->stream);
+    } else {
+      launch_apply_grad<float>(h->L, h->coef32, h->t.B.data(), h->t.A.data(), xf, yf, h->eb32, h->ctx->stream);
+    }
     return RZ_OK;
   }
   return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad dtype");

@@ -132,6 +132,16 @@ static void gll_nodes(int p, std::vector<double> &xi) {
   std::sort(xi.begin(), xi.end());
 }
 
+void gll_rule(int q, std::vector<double> &x, std::vector<double> &w) {
+  gll_nodes(q - 1, x);
+  w.assign(q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    double P, dP;
+    legendre(q - 1, x[i], P, dP);
+    w[i] = 2.0 / (q * (q - 1.0) * P * P);
+  }
+}
+
 bool build_tables1d(int p, Tables1D &t) {
   if (p < 1 || p > 16) return false;
   const int n = p + 1;

@@ -21,6 +21,9 @@ bool build_tables1d(int p, Tables1D &t);
 // Gauss-Legendre rule with n points on [-1,1].
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
 
+// Gauss-Lobatto-Legendre rule with q >= 2 points on [-1,1] (exact to degree 2q-3).
+void gll_rule(int q, std::vector<double> &x, std::vector<double> &w);
+
 // Values and derivatives of the FDM basis s_0..s_p at points x (n points):
 // val[k*(p+1)+j] = s_j(x_k), der likewise.
 void fdm_eval(const Tables1D &t, const std::vector<double> &x, std::vector<double> &val,

@@ -20,7 +20,7 @@ lib = ctypes.CDLL(LIB_PATH)
 GRAD, CURL, DIV = 0, 1, 2
 SPACES = {"grad": GRAD, "curl": CURL, "div": DIV}
 F64, F32 = 0, 1
-COEF_CONST, COEF_CELL = 0, 1
+COEF_CONST, COEF_CELL, COEF_SAMPLES = 0, 1, 2
 PREC_F64, PREC_MIXED = 0, 1
 EXPORT_DOFMAP, EXPORT_PATCH, EXPORT_IC_PATTERN, EXPORT_IC_FACTOR = 0, 1, 2, 3
 EXPORT_TABLES1D, EXPORT_AUXCOEF, EXPORT_OMEGA = 4, 5, 6
@@ -137,8 +137,9 @@ def default_opts(**kw):
 class Problem:
     """One discretised Riesz map: ``Problem(ctx, n, p, alpha, beta, ...)``.
 
-    n: cells per axis (int or 3-tuple); alpha, beta: scalars (constant) or arrays of
-    one value per cell; vertices: optional (n_vertices, 3) array of a Cartesian grid.
+    n: cells per axis (int or 3-tuple); alpha, beta: scalars (constant), arrays of
+    one value per cell, or (ncells, 27) arrays of reference samples; vertices:
+    optional (n_vertices, 3) array (any trilinear mesh).
     """
 
     def __init__(self, ctx, n, p, alpha=1.0, beta=1.0, space="grad", vertices=None,
@@ -154,10 +155,19 @@ class Problem:
         mesh = Mesh(nx, ny, nz, vp, dirichlet)
         a = np.ascontiguousarray(np.atleast_1d(alpha), dtype=np.float64)
         b = np.ascontiguousarray(np.atleast_1d(beta), dtype=np.float64)
-        kind = COEF_CONST if (a.size == 1 and b.size == 1) else COEF_CELL
-        if kind == COEF_CELL:
-            a = np.ascontiguousarray(np.broadcast_to(a, (nx * ny * nz,)))
-            b = np.ascontiguousarray(np.broadcast_to(b, (nx * ny * nz,)))
+        nc = nx * ny * nz
+        if a.ndim == 2 or b.ndim == 2:
+            # 27 samples per cell (reference points {-1,0,1}^3, x fastest)
+            kind = COEF_SAMPLES
+            a = np.ascontiguousarray(np.broadcast_to(a.reshape(-1, 27) if a.ndim == 2 else a[:, None],
+                                                     (nc, 27))).ravel()
+            b = np.ascontiguousarray(np.broadcast_to(b.reshape(-1, 27) if b.ndim == 2 else b[:, None],
+                                                     (nc, 27))).ravel()
+        else:
+            kind = COEF_CONST if (a.size == 1 and b.size == 1) else COEF_CELL
+            if kind == COEF_CELL:
+                a = np.ascontiguousarray(np.broadcast_to(a, (nc,)))
+                b = np.ascontiguousarray(np.broadcast_to(b, (nc,)))
         self._keep += [a, b]
         coef = Coef(kind, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                     b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))

@@ -94,11 +94,42 @@ def test_aux_coefficients_cartesian():
     assert np.allclose(pb.aux_coefficients(), ref, rtol=1e-14)
 
 
-def test_rejects_non_cartesian_mesh():
+@pytest.mark.parametrize("p", [1, 3, 8])
+def test_aux_coefficients_trilinear_sampled(p):
+    # cell-averaged separable weights on a perturbed mesh with sampled coefficients
+    import synth
+    from oracle.quadrature import averaged_coefficients, sample_function, default_points
+    rz = _rz()
+    m = Mesh(3, 2, 2)
+    m = Mesh(3, 2, 2, vertices=_perturb(m.vertices, (3, 2, 2), 7))
+    f = lambda X: np.exp(0.5 * np.sin(2 * np.pi * X[:, 0]) * np.sin(2 * np.pi * X[:, 1]) *
+                         np.sin(2 * np.pi * X[:, 2]))
+    a = sample_function(m, f)
+    b = sample_function(m, lambda X: 1.0 + X[:, 0] ** 2)
+    pb = rz.Problem(rz.Context(-1), (3, 2, 2), p, a, b, vertices=m.vertices)
+    ref = averaged_coefficients(m, a, b, default_points(p))
+    assert np.allclose(pb.aux_coefficients(), ref, rtol=1e-13, atol=0)
+
+
+def _perturb(v, n, seed):
+    """Move interior vertices by up to 0.15 h per coordinate (seeded)."""
+    import synth
+    nx, ny, nz = n
+    v = v.copy()
+    u = synth.uniform_pm1(seed, v.size).reshape(v.shape)
+    k = np.arange(v.shape[0])
+    ix, iy, iz = k % (nx + 1), (k // (nx + 1)) % (ny + 1), k // ((nx + 1) * (ny + 1))
+    inner = (ix > 0) & (ix < nx) & (iy > 0) & (iy < ny) & (iz > 0) & (iz < nz)
+    h = np.array([1.0 / nx, 1.0 / ny, 1.0 / nz])
+    v[inner] += 0.15 * h * u[inner]
+    return v
+
+
+def test_rejects_inverted_cell():
     rz = _rz()
     m = Mesh(2, 2, 2)
     v = m.vertices.copy()
-    v[13] += 0.05
+    v[13] += 0.6          # the centre vertex beyond the opposite corner: det J < 0
     with pytest.raises(rz.RzError) as e:
         rz.Problem(rz.Context(-1), 2, 3, vertices=v)
     assert e.value.code == -1
