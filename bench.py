@@ -96,6 +96,41 @@ def time_apply(torch, pb, dtype_t, code, reps=50, warm=10):
     return float(np.median(ts))
 
 
+def bench_c5(torch, rz, ctx, steps, warmup, n=24, p=8):
+    """Q_8 on a 24^3 mesh with interior vertices perturbed by up to 0.15 h (seed 3),
+    alpha = exp(0.5 sin 2pi x sin 2pi y sin 2pi z) sampled at 27 reference points per
+    cell, beta = 1, U[-1,1) RHS (seed 0): PCG with the cell-averaged separable
+    auxiliary in the relaxation, FP64 and mixed."""
+    import synth
+    v = synth.perturbed_vertices(n, 3)
+    a = synth.c5_coefficient_samples(v, n)
+    out = {"workload": f"H(grad) Q_{p} on a perturbed {n}^3 mesh (trilinear cells, interior vertices "
+                       f"+-0.15h), alpha=exp(0.5 sin sin sin) sampled 27/cell, beta=1; "
+                       f"cell-averaged separable auxiliary"}
+    for prec, name in ((rz.PREC_F64, "f64"), (rz.PREC_MIXED, "mixed")):
+        log(f"C5 setup ({name})")
+        t0 = time.perf_counter()
+        pb = rz.Problem(ctx, n, p, a, 1.0, vertices=v, precision=prec)
+        torch.cuda.synchronize()
+        out[f"setup_s_{name}"] = round(time.perf_counter() - t0, 3)
+        b = torch.as_tensor(synth.rhs_values(pb.ndofs, 0), device="cuda:0")
+        x = torch.empty_like(b)
+        ms, infos, kt = time_solves(torch, pb, b, x, steps, warmup)
+        out["ndofs"] = pb.ndofs
+        out[f"pcg_ms_{name}"] = round(ms, 4)
+        out[f"iters_{name}"] = infos[-1].iters
+        out[f"rel_res_{name}"] = max(i.rel_res for i in infos)
+        out[f"kernel_ms_per_step_{name}"] = {k: round(v_[0] / steps, 4) for k, v_ in kt.items()}
+        if prec == rz.PREC_F64:
+            out["gdofs_f64"] = round(pb.ndofs / (ms * 1e-3) / 1e9, 5)
+            out["apply_ms_f64"] = round(time_apply(torch, pb, torch.float64, rz.F64), 4)
+            out["apply_ms_f32"] = round(time_apply(torch, pb, torch.float32, rz.F32), 4)
+            out["apply_gdofs_f64"] = round(pb.ndofs / (out["apply_ms_f64"] * 1e-3) / 1e9, 2)
+            out["apply_gdofs_f32"] = round(pb.ndofs / (out["apply_ms_f32"] * 1e-3) / 1e9, 2)
+        pb.close()
+    return out
+
+
 def cpu_baseline(n=4, p=7):
     """The oracle's FP64 PCG (same method, same recipe) on a bounded sample."""
     from threadpoolctl import threadpool_limits
@@ -135,6 +170,7 @@ def main():
     ap.add_argument("--p", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-c5", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -203,6 +239,8 @@ def main():
         out["kernel_ms_per_step_mixed"] = {k: round(v[0] / args.steps, 4) for k, v in ktm.items()}
         out["speedup_mixed_vs_f64"] = round(ms / msm, 3)
         pm.close()
+    if not args.no_c5:
+        out["c5"] = bench_c5(torch, rz, ctx, max(1, args.steps // 2), 1)
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()

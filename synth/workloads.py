@@ -49,6 +49,40 @@ def cell_coefficients(n_cells: int, seed: int, lo: float = 1e-2, hi: float = 1e2
     return log_uniform(seed, n_cells, lo, hi)
 
 
+def c5_alpha(X: np.ndarray, amplitude: float = 0.5) -> np.ndarray:
+    """The smooth coefficient exp(a sin(2 pi x) sin(2 pi y) sin(2 pi z)) at points X (n, 3)."""
+    return np.exp(amplitude * np.sin(2 * np.pi * X[:, 0]) * np.sin(2 * np.pi * X[:, 1]) *
+                  np.sin(2 * np.pi * X[:, 2]))
+
+
+def reference_sample_points(vertices: np.ndarray, nx: int, ny: int, nz: int) -> np.ndarray:
+    """Physical images (ncells, 27, 3) of the reference points {-1,0,1}^3 (x fastest)
+    under each cell's trilinear map (corner k = kx + 2 ky + 4 kz)."""
+    v = np.asarray(vertices, dtype=np.float64).reshape(-1, 3)
+    c = np.arange(nx * ny * nz)
+    cx, cy, cz = c % nx, (c // nx) % ny, c // (nx * ny)
+    corners = np.zeros((c.size, 8, 3))
+    for k in range(8):
+        vid = (cx + (k & 1)) + (nx + 1) * ((cy + ((k >> 1) & 1)) + (ny + 1) * (cz + (k >> 2)))
+        corners[:, k] = v[vid]
+    t = np.array([-1.0, 0.0, 1.0])
+    out = np.zeros((c.size, 27, 3))
+    for m in range(27):
+        xi = (t[m % 3], t[(m // 3) % 3], t[m // 9])
+        for k in range(8):
+            w = 1.0
+            for a in range(3):
+                w *= 0.5 * (1.0 + (1.0 if (k >> a) & 1 else -1.0) * xi[a])
+            out[:, m] += w * corners[:, k]
+    return out
+
+
+def c5_coefficient_samples(vertices: np.ndarray, n: int, amplitude: float = 0.5) -> np.ndarray:
+    """(n^3, 27) samples of c5_alpha at each cell's reference points."""
+    X = reference_sample_points(vertices, n, n, n)
+    return c5_alpha(X.reshape(-1, 3), amplitude).reshape(-1, 27)
+
+
 def rhs_values(n_dofs: int, seed: int) -> np.ndarray:
     """One U[-1,1) right-hand side of length n_dofs from stream ``seed``."""
     return uniform_pm1(seed, n_dofs)

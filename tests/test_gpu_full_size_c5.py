@@ -1,0 +1,134 @@
+"""Parity at the full size of the trilinear workload: Q_8 on a 24^3 mesh with
+interior vertices perturbed by up to 0.15 h (seed 3), alpha = exp(0.5 sin sin sin)
+sampled 27 times per cell, beta = 1 (7,189,057 DoFs).
+
+As for the Cartesian workload, the oracle computes sampled outputs exactly from
+3x3x3 windows of cells: the apply at the DoFs of the window's centre cell (only
+the cells sharing a DoF with it contribute), the relaxation there (only the stars
+of its 8 vertices and its own interior solves contribute, all strictly inside the
+window), and sampled components of the solve's true residual.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.lattice import Mesh, Lattice
+from oracle import auxop, schwarz, matfree
+from oracle.quadrature import averaged_coefficients, default_points
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+NC, P = 24, 8
+NX = NC * P + 1
+Q = default_points(P)
+CELLS = [(0, 0, 0), (23, 23, 23), (1, 1, 1), (11, 12, 13), (23, 0, 7), (4, 20, 3)]
+
+
+def _window(c0, verts):
+    lo = [max(c - 1, 0) for c in c0]
+    hi = [min(c + 1, NC - 1) for c in c0]
+    nw = [h - l + 1 for l, h in zip(lo, hi)]
+    vz, vy, vx = np.meshgrid(np.arange(lo[2], hi[2] + 2), np.arange(lo[1], hi[1] + 2),
+                             np.arange(lo[0], hi[0] + 2), indexing="ij")
+    wv = verts[(vx + (NC + 1) * (vy + (NC + 1) * vz)).ravel()]
+    bits = 0
+    for a in range(3):
+        if lo[a] == 0:
+            bits |= 1 << (2 * a)
+        if hi[a] == NC - 1:
+            bits |= 1 << (2 * a + 1)
+    cz, cy, cx = np.meshgrid(np.arange(lo[2], hi[2] + 1), np.arange(lo[1], hi[1] + 1),
+                             np.arange(lo[0], hi[0] + 1), indexing="ij")
+    cells = (cx + NC * (cy + NC * cz)).ravel()
+    nl = [n * P + 1 for n in nw]
+    Zl, Yl, Xl = np.meshgrid(np.arange(nl[2]) + lo[2] * P, np.arange(nl[1]) + lo[1] * P,
+                             np.arange(nl[0]) + lo[0] * P, indexing="ij")
+    dofs = (Xl + NX * (Yl + NX * Zl)).ravel()
+    r = [np.arange((c0[a] - lo[a]) * P, (c0[a] - lo[a]) * P + P + 1) for a in range(3)]
+    Rz, Ry, Rx = np.meshgrid(r[2], r[1], r[0], indexing="ij")
+    own = (Rx + nl[0] * (Ry + nl[1] * Rz)).ravel()
+    return nw, wv, bits, cells, dofs, own
+
+
+def _global_dirichlet(g):
+    X, Y, Z = g % NX, (g // NX) % NX, g // (NX * NX)
+    return (X == 0) | (X == NX - 1) | (Y == 0) | (Y == NX - 1) | (Z == 0) | (Z == NX - 1)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_14284_amd import rz
+    ctx = rz.Context(0, torch.cuda.current_stream())
+    v = synth.perturbed_vertices(NC, 3)
+    a = synth.c5_coefficient_samples(v, NC)
+    b = np.ones_like(a)
+    pb = rz.Problem(ctx, NC, P, a, b, vertices=v)
+    yield rz, ctx, pb, v, a, b
+    pb.close()
+
+
+def _oracle_apply(c0, x, v, a, b):
+    nw, wv, bits, cells, dofs, own = _window(c0, v)
+    lat = Lattice(Mesh(*nw, vertices=wv, dirichlet=bits), "grad", P)
+    y = matfree.apply(lat, x[dofs], a[cells], b[cells], Q, kind="gll")
+    return dofs[own], y[own]
+
+
+def _oracle_relax(c0, r, v, a, b):
+    nw, wv, bits, cells, dofs, own = _window(c0, v)
+    m = Mesh(*nw, vertices=wv, dirichlet=0x3F)
+    lat = Lattice(m, "grad", P)
+    co = averaged_coefficients(m, a[cells], b[cells], Q)
+    R = schwarz.SCRelaxGrad(lat, auxop.separable_operator(lat, co))
+    z = R.apply(np.where(lat.dirichlet_mask(), 0.0, r[dofs]))
+    return dofs[own], z[own]
+
+
+def test_c5_apply_sampled(setup):
+    rz, ctx, pb, v, a, b = setup
+    assert pb.ndofs == NX ** 3
+    x = synth.uniform_pm1(81, pb.ndofs)
+    xt = torch.as_tensor(x, device="cuda:0")
+    y = torch.empty_like(xt)
+    pb.apply(xt, y)
+    y32 = torch.empty(pb.ndofs, dtype=torch.float32, device="cuda:0")
+    pb.apply(xt.float(), y32, rz.F32)
+    torch.cuda.synchronize()
+    yh, y32h = y.cpu().numpy(), y32.double().cpu().numpy()
+    for c0 in CELLS:
+        g, yr = _oracle_apply(c0, x, v, a, b)
+        assert np.linalg.norm(yh[g] - yr) < 1e-12 * np.linalg.norm(yr), c0
+        assert np.linalg.norm(y32h[g] - yr) < 1e-5 * np.linalg.norm(yr), c0
+
+
+def test_c5_relax_sampled(setup):
+    rz, ctx, pb, v, a, b = setup
+    r = synth.uniform_pm1(82, pb.ndofs)
+    rt = torch.as_tensor(r, device="cuda:0")
+    z = torch.empty_like(rt)
+    pb.relax(rt, z)
+    torch.cuda.synchronize()
+    zh = z.cpu().numpy()
+    for c0 in CELLS[:4]:
+        g, zr = _oracle_relax(c0, r, v, a, b)
+        free = ~_global_dirichlet(g)
+        assert np.linalg.norm(zh[g[free]] - zr[free]) < 1e-12 * np.linalg.norm(zr[free]), c0
+
+
+def test_c5_solve_residual(setup):
+    rz, ctx, pb, v, a, b = setup
+    bb = np.where(_global_dirichlet(np.arange(pb.ndofs)), 0.0, synth.rhs_values(pb.ndofs, 0))
+    bt = torch.as_tensor(bb, device="cuda:0")
+    x = torch.empty_like(bt)
+    info = pb.solve(bt, x)
+    xh = x.cpu().numpy()
+    bound = 1e-8 * np.linalg.norm(bb)
+    assert info.rel_res <= 1e-8
+    for c0 in CELLS:
+        g, y = _oracle_apply(c0, xh, v, a, b)
+        free = ~_global_dirichlet(g)
+        assert np.abs(bb[g[free]] - y[free]).max() <= bound, c0
