@@ -18,6 +18,8 @@ Modules
   schwarz   -- static condensation, vertex-star patches, incomplete Cholesky on
                the static-condensation pattern, patch relaxation (Sec. 4.3-4.5)
   pmg       -- p-transfer, coarse problem, V(1,1) cycle and PCG (Sec. 4.3, 5)
+  learned   -- least-squares separable fit to the broken diagonals, per-cell
+               features, a hand-written NumPy MLP (forward, backward, Adam)
   quadrature-- Gauss-Lobatto rules, sampled (triquadratic) coefficients and the
                cell-averaged separable auxiliary weights for trilinear cells
 
