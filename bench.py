@@ -96,6 +96,56 @@ def time_apply(torch, pb, dtype_t, code, reps=50, warm=10):
     return float(np.median(ts))
 
 
+def c5_aux_variants(torch, rz, ctx, pb, b, x, n, p, train_seeds=(10, 11, 12, 13)):
+    """FP64 PCG on the C5 problem with three separable auxiliaries: cell averages
+    (default), the least-squares fit to the broken diagonals, and an MLP trained on
+    meshes with other perturbation seeds (features -> log(fit / average))."""
+    import synth
+    res = {}
+    t_fit, feats, base = pb.aux_data()
+
+    def run(coef, name):
+        pb.set_aux(coef)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = pb.solve(b, x)
+        torch.cuda.synchronize()
+        res[name] = {"iters": info.iters, "pcg_ms": round((time.perf_counter() - t0) * 1e3, 3),
+                     "rel_res": info.rel_res, "omega": pb.omega()}
+
+    run(base, "cell_average")
+    run(t_fit, "lsq_fit")
+    log("C5: MLP training data from meshes with seeds " + str(list(train_seeds)))
+    t0 = time.perf_counter()
+    Xs, Ys = [], []
+    for s in train_seeds:
+        v = synth.perturbed_vertices(n, s)
+        hp = rz.Problem(rz.Context(-1), n, p, synth.c5_coefficient_samples(v, n), 1.0, vertices=v)
+        t, f, bs = hp.aux_data()
+        hp.close()
+        Xs.append(f.astype(np.float32))
+        Ys.append(np.log(t / bs).astype(np.float32))
+    X = torch.as_tensor(np.concatenate(Xs), device="cuda:0")
+    Y = torch.as_tensor(np.concatenate(Ys), device="cuda:0")
+    t_data = time.perf_counter() - t0
+    mlp = rz.MLP(ctx, 51, 64, 6, seed=1)
+    t0 = time.perf_counter()
+    loss = mlp.train(X, Y, epochs=20, batch=512, lr=2e-3, seed=11)
+    t_train = time.perf_counter() - t0
+    Xt = torch.as_tensor(feats.astype(np.float32), device="cuda:0")
+    out = torch.empty((pb.ncells, 6), dtype=torch.float32, device="cuda:0")
+    mlp.predict(Xt, out)
+    pred = out.cpu().numpy().astype(np.float64)
+    mlp.close()
+    res["mlp_rms_log_error"] = float(np.sqrt(np.mean((pred - np.log(t_fit / base)) ** 2)))
+    res["cell_average_rms_log_error"] = float(np.sqrt(np.mean(np.log(t_fit / base) ** 2)))
+    run(base * np.exp(pred), "mlp")
+    res["mlp_train"] = {"cells": int(X.shape[0]), "data_s": round(t_data, 2), "train_s": round(t_train, 2),
+                        "final_loss": loss}
+    pb.set_aux(base)
+    return res
+
+
 def bench_c5(torch, rz, ctx, steps, warmup, n=24, p=8):
     """Q_8 on a 24^3 mesh with interior vertices perturbed by up to 0.15 h (seed 3),
     alpha = exp(0.5 sin 2pi x sin 2pi y sin 2pi z) sampled at 27 reference points per
@@ -122,6 +172,7 @@ def bench_c5(torch, rz, ctx, steps, warmup, n=24, p=8):
         out[f"rel_res_{name}"] = max(i.rel_res for i in infos)
         out[f"kernel_ms_per_step_{name}"] = {k: round(v_[0] / steps, 4) for k, v_ in kt.items()}
         if prec == rz.PREC_F64:
+            out["aux"] = c5_aux_variants(torch, rz, ctx, pb, b, x, n, p)
             out["gdofs_f64"] = round(pb.ndofs / (ms * 1e-3) / 1e9, 5)
             out["apply_ms_f64"] = round(time_apply(torch, pb, torch.float64, rz.F64), 4)
             out["apply_ms_f32"] = round(time_apply(torch, pb, torch.float32, rz.F32), 4)

@@ -204,6 +204,53 @@ enum {
 rz_status rz_timing_enable(rz_problem *h, int on);
 rz_status rz_timing_read(rz_problem *h, double ms[RZ_NKERNELS], int64_t count[RZ_NKERNELS]);
 
+/* ---- learned auxiliary weights (trilinear cells) ----------------------------------
+ * The separable auxiliary of the relaxation uses per-cell weights c = (sigma_1..3,
+ * mu, mu, mu).  The least-squares fit of c to the broken diagonals of the paper's
+ * auxiliary operator (eq. sum-factorization_approx) is their mean, computed with
+ * the quadrature of the operator (Christoffel-factorised).  A small MLP (FP32,
+ * nin -> nhid tanh -> nhid tanh -> nout, squared-error loss, Adam) learns
+ * log(c_fit / c_avg) from dimensionless per-cell features; c_avg are the default
+ * cell-averaged weights. */
+
+/* Host arrays of ncells rows: targets (6) = the least-squares fit, features (51) =
+ * corner offsets from the centroid over the mean edge length minus those of a cube
+ * (24) and log alpha samples minus their mean (27), base (6) = the cell-averaged
+ * weights in use.  Any pointer may be NULL.  Requires the quadrature path
+ * (trilinear cells or sampled coefficients); works on host-only contexts. */
+rz_status rz_aux_data(const rz_problem *h, double *targets, double *features, double *base);
+
+/* Replace the auxiliary weights (host array ncells x 6, all > 0) and rebuild what
+ * depends on them: the patch IC factors and, unless omega was fixed, omega.
+ * Synchronous.  RZ_ERR_BREAKDOWN if an IC pivot is not positive. */
+rz_status rz_set_aux(rz_problem *h, const double *coef6);
+
+typedef struct rz_mlp rz_mlp;   /* opaque; parameters on the device of ctx */
+
+/* Create an MLP on ctx's device and stream: Glorot-uniform weights from the
+ * SplitMix64 stream `seed` (W1, W2, W3 in turn, row-major out x in), zero biases.
+ * Parameters are packed W1 (nhid x nin), b1, W2 (nhid x nhid), b2, W3 (nout x nhid), b3. */
+rz_status rz_mlp_create(rz_ctx *ctx, int32_t nin, int32_t nhid, int32_t nout, uint64_t seed, rz_mlp **out);
+rz_status rz_mlp_free(rz_mlp *m);
+const char *rz_mlp_last_error(const rz_mlp *m);
+int64_t rz_mlp_nparams(const rz_mlp *m);
+/* Copy the packed parameters to (set = 0) or from (set = 1) a host array; setting
+ * restarts the Adam step count. */
+rz_status rz_mlp_params(rz_mlp *m, float *host, int32_t set);
+/* Y (n x nout) = network(X (n x nin)); device pointers, stream-ordered. */
+rz_status rz_mlp_predict(rz_mlp *m, const float *X, float *Y, int64_t n);
+/* Loss (mean over rows and outputs of the squared error) and its gradient with
+ * respect to the packed parameters (host array of rz_mlp_nparams floats, may be
+ * NULL); X, Y device pointers.  Synchronous. */
+rz_status rz_mlp_loss_grad(rz_mlp *m, const float *X, const float *Y, int64_t n, double *loss, float *grad_host);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the full batch X, Y. */
+rz_status rz_mlp_adam_step(rz_mlp *m, const float *X, const float *Y, int64_t n, float lr);
+/* Minibatch Adam: `epochs` passes over the n rows in an order shuffled by the
+ * SplitMix64 stream `seed`, floor(n / batch) steps per epoch; *final_loss = the
+ * loss of the last batch.  Synchronous. */
+rz_status rz_mlp_train(rz_mlp *m, const float *X, const float *Y, int64_t n, int32_t epochs, int32_t batch,
+                       float lr, uint64_t seed, double *final_loss);
+
 #ifdef __cplusplus
 }
 #endif

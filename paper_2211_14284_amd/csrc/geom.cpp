@@ -112,4 +112,103 @@ bool q1_cell_matrix(const double *corners, const double *as, const double *bs, c
   return true;
 }
 
+void christoffel(const Tables1D &t, const QuadTables &Q, std::vector<double> &kP, std::vector<double> &kD) {
+  const int p = t.p, n = p + 1, q = Q.q;
+  // inverse of the broken transformation G (Gauss-Jordan with partial pivoting)
+  std::vector<double> G(t.G), Gi(n * n, 0.0);
+  for (int i = 0; i < n; ++i) Gi[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(G[r * n + c]) > std::fabs(G[piv * n + c])) piv = r;
+    for (int k = 0; k < n; ++k) {
+      std::swap(G[c * n + k], G[piv * n + k]);
+      std::swap(Gi[c * n + k], Gi[piv * n + k]);
+    }
+    const double d = G[c * n + c];
+    for (int k = 0; k < n; ++k) {
+      G[c * n + k] /= d;
+      Gi[c * n + k] /= d;
+    }
+    for (int r = 0; r < n; ++r)
+      if (r != c) {
+        const double f = G[r * n + c];
+        for (int k = 0; k < n; ++k) {
+          G[r * n + k] -= f * G[c * n + k];
+          Gi[r * n + k] -= f * Gi[c * n + k];
+        }
+      }
+  }
+  kP.assign(q, 0.0);
+  kD.assign(q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    // broken functions: values s(x) G^-1
+    for (int k = 0; k < n; ++k) {
+      double v = 0.0;
+      for (int j = 0; j < n; ++j) v += Q.Bq[i * n + j] * Gi[j * n + k];
+      kP[i] += v * v;
+    }
+    kP[i] /= n;
+    // L2 basis of degree p-1: r_0 = 2^-1/2, r_k = lambda_k^-1/2 s_k'
+    double s = 0.5;
+    for (int k = 1; k < p; ++k) {
+      const double r = Q.Dq[i * n + k] / std::sqrt(t.lam[k - 1]);
+      s += r * r;
+    }
+    kD[i] = s / p;
+  }
+}
+
+bool fit_targets(const double *corners, const double *as, const double *bs, const QuadTables &Q,
+                 const std::vector<double> &kP, const std::vector<double> &kD, double out[6]) {
+  const int q = Q.q;
+  double sig[3] = {0, 0, 0}, mu = 0;
+  for (int k = 0; k < q; ++k)
+    for (int j = 0; j < q; ++j)
+      for (int i = 0; i < q; ++i) {
+        const double xi[3] = {Q.xq[i], Q.xq[j], Q.xq[k]};
+        double J[9], Ji[9];
+        const double det = trilinear_jacobian(corners, xi, J);
+        if (!(det > 0)) return false;
+        inverse3(J, det, Ji);
+        const double al = interp27(as, Q, i, j, k), be = interp27(bs, Q, i, j, k);
+        const double w = Q.wq[i] * Q.wq[j] * Q.wq[k] * det;
+        const double kp[3] = {kP[i], kP[j], kP[k]}, kd[3] = {kD[i], kD[j], kD[k]};
+        for (int s = 0; s < 3; ++s) {
+          double kw = kd[s];
+          for (int a = 0; a < 3; ++a)
+            if (a != s) kw *= kp[a];
+          sig[s] += w * al * kw *
+                    (Ji[3 * s] * Ji[3 * s] + Ji[3 * s + 1] * Ji[3 * s + 1] + Ji[3 * s + 2] * Ji[3 * s + 2]);
+        }
+        mu += w * be * kp[0] * kp[1] * kp[2];
+      }
+  for (int s = 0; s < 3; ++s) out[s] = sig[s];
+  for (int s = 0; s < 3; ++s) out[3 + s] = mu;
+  return true;
+}
+
+void cell_features(const double *corners, const double *as, double out[51]) {
+  double cen[3] = {0, 0, 0};
+  for (int k = 0; k < 8; ++k)
+    for (int r = 0; r < 3; ++r) cen[r] += corners[3 * k + r] / 8.0;
+  static const int E[12][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3},
+                               {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
+  double h = 0;
+  for (auto &e : E) {
+    double d2 = 0;
+    for (int r = 0; r < 3; ++r) {
+      const double d = corners[3 * e[1] + r] - corners[3 * e[0] + r];
+      d2 += d * d;
+    }
+    h += std::sqrt(d2) / 12.0;
+  }
+  for (int k = 0; k < 8; ++k)
+    for (int r = 0; r < 3; ++r)
+      out[3 * k + r] = (corners[3 * k + r] - cen[r]) / h - (((k >> r) & 1) ? 0.5 : -0.5);
+  double m = 0;
+  for (int k = 0; k < 27; ++k) m += std::log(as[k]) / 27.0;
+  for (int k = 0; k < 27; ++k) out[24 + k] = std::log(as[k]) - m;
+}
+
 }  // namespace rz

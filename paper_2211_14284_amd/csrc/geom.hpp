@@ -35,4 +35,17 @@ bool averaged_weights(const double *corners, const double *as, const double *bs,
 bool q1_cell_matrix(const double *corners, const double *as, const double *bs, const QuadTables &Q,
                     double K[64]);
 
+// Christoffel functions of the 1-D bases at the points Q.xq: kP = mean over the
+// broken degree-p basis of its squares, kD = the same for the degree-(p-1) L2 basis.
+void christoffel(const Tables1D &t, const QuadTables &Q, std::vector<double> &kP, std::vector<double> &kD);
+
+// Least-squares separable fit to the broken diagonals of the auxiliary operator
+// (the mean of each diagonal), Christoffel-factorised: out = (sigma_1..3, mu x3).
+bool fit_targets(const double *corners, const double *as, const double *bs, const QuadTables &Q,
+                 const std::vector<double> &kP, const std::vector<double> &kD, double out[6]);
+
+// 51 dimensionless features of a cell: corner offsets from the centroid over the
+// mean edge length minus those of a cube (24), log alpha samples minus their mean (27).
+void cell_features(const double *corners, const double *as, double out[51]);
+
 }  // namespace rz

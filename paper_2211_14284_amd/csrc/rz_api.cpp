@@ -24,6 +24,10 @@ struct rz_ctx {
   std::string err;
 };
 
+namespace rz {
+void *ctx_stream(const rz_ctx *ctx) { return ctx ? (void *)ctx->stream : nullptr; }
+}  // namespace rz
+
 namespace {
 
 using namespace rz;
@@ -985,6 +989,57 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *inf
   }
   if (result == RZ_ERR_NOT_CONVERGED) fail(h->ctx, result, "maximum number of iterations reached");
   return result;
+}
+
+rz_status rz_aux_data(const rz_problem *h, double *targets, double *features, double *base) {
+  if (!h) return RZ_ERR_ARG;
+  if (!h->quad) return fail(h->ctx, RZ_ERR_ARG, "rz_aux_data: needs trilinear cells or sampled coefficients");
+  std::vector<double> kP, kD;
+  christoffel(h->t, h->qt, kP, kD);
+  const int nvx = h->nx + 1, nvy = h->ny + 1;
+  for (int64_t c = 0; c < h->ncells; ++c) {
+    int cx = c % h->nx, cy = (c / h->nx) % h->ny, cz = c / ((int64_t)h->nx * h->ny);
+    double corners[24];
+    for (int k = 0; k < 8; ++k) {
+      const int64_t vid = (cx + (k & 1)) + nvx * ((cy + ((k >> 1) & 1)) + (int64_t)nvy * (cz + (k >> 2)));
+      for (int r = 0; r < 3; ++r) corners[3 * k + r] = h->vert[3 * vid + r];
+    }
+    if (targets && !fit_targets(corners, &h->asmp[27 * c], &h->bsmp[27 * c], h->qt, kP, kD, targets + 6 * c))
+      return fail(h->ctx, RZ_ERR_ARG, "non-positive Jacobian determinant");
+    if (features) cell_features(corners, &h->asmp[27 * c], features + 51 * c);
+    if (base)
+      for (int k = 0; k < 6; ++k) base[6 * c + k] = h->coef[6 * c + k];
+  }
+  return RZ_OK;
+}
+
+rz_status rz_set_aux(rz_problem *h, const double *coef6) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  if (!coef6) return fail(h->ctx, RZ_ERR_ARG, "rz_set_aux: null weights");
+  for (int64_t k = 0; k < 6 * h->ncells; ++k)
+    if (!(coef6[k] > 0)) return fail(h->ctx, RZ_ERR_ARG, "rz_set_aux: weights must be positive");
+  hipStream_t s = h->ctx->stream;
+  h->coef.assign(coef6, coef6 + 6 * h->ncells);
+  std::vector<float> c32(h->coef.begin(), h->coef.end());
+  HIPCALL(h, hipMemcpyAsync(h->coef64, h->coef.data(), sizeof(double) * h->coef.size(), hipMemcpyHostToDevice, s));
+  HIPCALL(h, hipMemcpyAsync(h->coef32, c32.data(), sizeof(float) * c32.size(), hipMemcpyHostToDevice, s));
+  const size_t nf = (size_t)h->nvert * h->ps.stride;
+  HIPCALL(h, hipMemsetAsync(h->f64, 0, nf * sizeof(double), s));
+  HIPCALL(h, hipMemsetAsync(h->f32, 0, nf * sizeof(float), s));
+  HIPCALL(h, hipMemsetAsync(h->status, 0, sizeof(int), s));
+  launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, h->f64, h->f32, h->status, s);
+  int stv = 0;
+  HIPCALL(h, hipMemcpyAsync(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCALL(h, hipStreamSynchronize(s));
+  if (stv) return fail(h->ctx, RZ_ERR_BREAKDOWN, "incomplete Cholesky breakdown after rz_set_aux");
+  if (!(h->opts.omega > 0)) {
+    double lam = 0;
+    if ((e = estimate_lambda(h, &lam))) return e;
+    h->omega = 2.0 / (1.2 * lam);
+  }
+  HIPCALL(h, hipStreamSynchronize(s));
+  return RZ_OK;
 }
 
 rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *bytes) {

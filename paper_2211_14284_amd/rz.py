@@ -76,6 +76,19 @@ _proto = {
     "rz_export": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "rz_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "rz_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "rz_aux_data": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "rz_set_aux": (ctypes.c_int, [_vp, _vp]),
+    "rz_mlp_create": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                     ctypes.POINTER(_vp)]),
+    "rz_mlp_free": (ctypes.c_int, [_vp]),
+    "rz_mlp_last_error": (ctypes.c_char_p, [_vp]),
+    "rz_mlp_nparams": (ctypes.c_int64, [_vp]),
+    "rz_mlp_params": (ctypes.c_int, [_vp, _vp, ctypes.c_int32]),
+    "rz_mlp_predict": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64]),
+    "rz_mlp_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), _vp]),
+    "rz_mlp_adam_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_float]),
+    "rz_mlp_train": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                    ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),
 }
 for _name, (_res, _args) in _proto.items():
     _f = getattr(lib, _name)
@@ -256,6 +269,19 @@ class Problem:
     def aux_coefficients(self):
         return self._export(EXPORT_AUXCOEF).reshape(self.ncells, 6)
 
+    def aux_data(self):
+        """(targets, features, base): the least-squares fit of the separable weights
+        to the broken diagonals, the 51 per-cell features and the weights in use."""
+        t = np.zeros((self.ncells, 6))
+        f = np.zeros((self.ncells, 51))
+        b = np.zeros((self.ncells, 6))
+        self.ctx.check(lib.rz_aux_data(self.handle, t.ctypes.data, f.ctypes.data, b.ctypes.data))
+        return t, f, b
+
+    def set_aux(self, coef6):
+        c = np.ascontiguousarray(coef6, dtype=np.float64).reshape(self.ncells, 6)
+        self.ctx.check(lib.rz_set_aux(self.handle, c.ctypes.data))
+
     def omega(self):
         return float(self._export(EXPORT_OMEGA)[0])
 
@@ -263,6 +289,63 @@ class Problem:
         if self.handle:
             lib.rz_free(self.handle)
             self.handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """The library's small MLP (FP32 on the context's device): nin -> nhid (tanh) ->
+    nhid (tanh) -> nout.  Arrays passed to predict/train are torch tensors on the
+    device; parameters move as packed host float32 arrays."""
+
+    def __init__(self, ctx, nin=51, nhid=64, nout=6, seed=1234):
+        self.ctx = ctx
+        self.handle = _vp()
+        self._check(lib.rz_mlp_create(ctx.handle, nin, nhid, nout, seed, ctypes.byref(self.handle)))
+        self.nin, self.nhid, self.nout = nin, nhid, nout
+        self.nparams = int(lib.rz_mlp_nparams(self.handle))
+
+    def _check(self, code):
+        if code != 0:
+            msg = lib.rz_mlp_last_error(self.handle).decode() if getattr(self, "handle", None) else ""
+            raise RzError(code, msg)
+
+    def params(self):
+        p = np.zeros(self.nparams, dtype=np.float32)
+        self._check(lib.rz_mlp_params(self.handle, p.ctypes.data, 0))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.nparams
+        self._check(lib.rz_mlp_params(self.handle, p.ctypes.data, 1))
+
+    def predict(self, X, Y):
+        self._check(lib.rz_mlp_predict(self.handle, _ptr(X), _ptr(Y), X.shape[0]))
+
+    def loss_grad(self, X, Y):
+        loss = ctypes.c_double()
+        g = np.zeros(self.nparams, dtype=np.float32)
+        self._check(lib.rz_mlp_loss_grad(self.handle, _ptr(X), _ptr(Y), X.shape[0], ctypes.byref(loss), g.ctypes.data))
+        return loss.value, g
+
+    def adam_step(self, X, Y, lr):
+        self._check(lib.rz_mlp_adam_step(self.handle, _ptr(X), _ptr(Y), X.shape[0], lr))
+
+    def train(self, X, Y, epochs, batch, lr, seed=7):
+        loss = ctypes.c_double()
+        self._check(lib.rz_mlp_train(self.handle, _ptr(X), _ptr(Y), X.shape[0], epochs, batch, lr, seed,
+                                     ctypes.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.rz_mlp_free(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

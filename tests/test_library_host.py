@@ -133,3 +133,20 @@ def test_rejects_inverted_cell():
     with pytest.raises(rz.RzError) as e:
         rz.Problem(rz.Context(-1), 2, 3, vertices=v)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("p", [2, 5, 8])
+def test_aux_fit_targets_and_features(p):
+    # least-squares separable fit to the broken diagonals and the MLP features
+    import synth
+    from oracle import learned
+    rz = _rz()
+    v = synth.perturbed_vertices(3, 3)
+    m = Mesh(3, 3, 3, vertices=v)
+    a = synth.c5_coefficient_samples(v, 3)
+    b = np.repeat(synth.cell_coefficients(27, 4, 0.5, 2.0)[:, None], 27, 1)
+    pb = rz.Problem(rz.Context(-1), 3, p, a, b, vertices=v)
+    t, f, base = pb.aux_data()
+    assert np.allclose(t, learned.diagonal_targets(m, a, b, p), rtol=1e-12, atol=0)
+    assert np.abs(f - learned.features(m, a)).max() < 1e-13
+    assert np.array_equal(base, pb.aux_coefficients())
