@@ -80,6 +80,7 @@ struct rz_problem {
   // krylov
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kAp = nullptr, *kro = nullptr;
   double *partials = nullptr, *dots = nullptr;
+  double *hdots = nullptr;  // pinned host copy of the dot products (4 values)
   int *status = nullptr;
   // per-kernel timing
   bool timing = false;
@@ -505,6 +506,8 @@ rz_status setup_coarse(rz_problem *h) {
 void release(rz_problem *h) {
   for (void *p : h->allocs) hipFree(p);
   h->allocs.clear();
+  if (h->hdots) hipHostFree(h->hdots);
+  h->hdots = nullptr;
   for (auto &e : h->ev_pool) {
     hipEventDestroy(e.first);
     hipEventDestroy(e.second);
@@ -524,6 +527,177 @@ rz_status require_device(const rz_problem *h) {
 // =========================================================================================
 // public API
 // =========================================================================================
+namespace {
+
+// PCG (Sec. 5) as a state machine: each step enqueues stream-ordered work and the
+// dot products it needs (copied asynchronously to pinned host memory); the caller
+// waits for the stream and hands the values to the next step.  rz_solve runs one
+// instance; rz_solve_batched advances instances of several problems in lockstep,
+// so their streams overlap on the device.  Both issue the same kernels in the same
+// order, so their results are identical.
+struct PcgRun {
+  rz_problem *h = nullptr;
+  const double *b = nullptr;
+  double *x = nullptr;
+  enum Phase { INIT, GOT_BB, GOT_RZ0, GOT_PAP, GOT_RR, GOT_TR, GOT_D2, GOT_FINAL, DONE } phase = INIT;
+  int it = 0, ndots = 0;
+  double nb = 0, tol = 0, rz = 0, relres = 0;
+  rz_status result = RZ_OK;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+rz_status pcg_dots(PcgRun &R, int np, const double *const *xs, const double *const *ys) {
+  rz_problem *h = R.h;
+  {
+    Timed tm(h, RZ_K_KRYLOV);
+    launch_dots(np, xs, ys, h->ndofs, h->partials, h->dots, h->ctx->stream);
+  }
+  HIPCALL(h, hipMemcpyAsync(h->hdots, h->dots, sizeof(double) * np, hipMemcpyDeviceToHost, h->ctx->stream));
+  R.ndots = np;
+  return RZ_OK;
+}
+
+rz_status pcg_final(PcgRun &R) {
+  rz_problem *h = R.h;
+  do_apply64(h, R.x, h->vaz);
+  v_sub(h, R.b, h->vaz, h->vr);
+  launch_dirichlet_copy(h->L, nullptr, h->vr, h->ctx->stream);
+  const double *xs[1] = {h->vr};
+  R.phase = PcgRun::GOT_FINAL;
+  return pcg_dots(R, 1, xs, xs);
+}
+
+rz_status pcg_precondition(PcgRun &R) {
+  rz_problem *h = R.h;
+  do_vcycle(h, h->kr, h->kz);
+  R.phase = PcgRun::GOT_D2;
+  if (h->opts.precision == RZ_PREC_MIXED) {
+    const double *xs[2] = {h->kr, h->kro}, *ys[2] = {h->kz, h->kz};
+    return pcg_dots(R, 2, xs, ys);
+  }
+  const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
+  return pcg_dots(R, 1, xs, ys);
+}
+
+rz_status pcg_search(PcgRun &R) {
+  rz_problem *h = R.h;
+  if (R.it >= h->opts.maxit) {
+    R.result = RZ_ERR_NOT_CONVERGED;
+    return pcg_final(R);
+  }
+  do_apply64(h, h->kp, h->kAp);
+  const double *xs[1] = {h->kp}, *ys[1] = {h->kAp};
+  R.phase = PcgRun::GOT_PAP;
+  return pcg_dots(R, 1, xs, ys);
+}
+
+// Advance one step with the dot products of the previous step in h->hdots.
+rz_status pcg_step(PcgRun &R) {
+  rz_problem *h = R.h;
+  hipStream_t s = h->ctx->stream;
+  const int64_t n = h->ndofs;
+  const double *d = h->hdots;
+  switch (R.phase) {
+    case PcgRun::INIT: {
+      HIPCALL(h, hipEventCreate(&R.ev0));
+      HIPCALL(h, hipEventCreate(&R.ev1));
+      HIPCALL(h, hipEventRecord(R.ev0, s));
+      launch_fill(R.x, 0.0, n, s);  // x = 0, r = b with Dirichlet rows zero
+      v_scale_copy(h, 1.0, R.b, h->kr);
+      launch_dirichlet_copy(h->L, nullptr, h->kr, s);
+      const double *xs[1] = {h->kr};
+      R.phase = PcgRun::GOT_BB;
+      return pcg_dots(R, 1, xs, xs);
+    }
+    case PcgRun::GOT_BB: {
+      R.nb = std::sqrt(d[0]);
+      R.tol = h->opts.rtol * R.nb;
+      if (!(R.nb > 0)) return pcg_final(R);
+      do_vcycle(h, h->kr, h->kz);
+      v_scale_copy(h, 1.0, h->kz, h->kp);
+      const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
+      R.phase = PcgRun::GOT_RZ0;
+      return pcg_dots(R, 1, xs, ys);
+    }
+    case PcgRun::GOT_RZ0:
+      R.rz = d[0];
+      return pcg_search(R);
+    case PcgRun::GOT_PAP: {
+      const double pAp = d[0];
+      if (!(pAp > 0)) {
+        R.result = fail(h->ctx, RZ_ERR_BREAKDOWN, "CG breakdown: p.Ap <= 0");
+        return pcg_final(R);
+      }
+      const double a = R.rz / pAp;
+      v_axpy(h, a, h->kp, R.x);
+      if (h->opts.precision == RZ_PREC_MIXED) v_scale_copy(h, 1.0, h->kr, h->kro);
+      v_axpy(h, -a, h->kAp, h->kr);
+      ++R.it;
+      const double *xs[1] = {h->kr};
+      R.phase = PcgRun::GOT_RR;
+      return pcg_dots(R, 1, xs, xs);
+    }
+    case PcgRun::GOT_RR: {
+      if (std::sqrt(d[0]) <= R.tol) {  // recurrence converged: check the true residual
+        do_apply64(h, R.x, h->vaz);
+        v_sub(h, R.b, h->vaz, h->vr);
+        launch_dirichlet_copy(h->L, nullptr, h->vr, s);
+        const double *xs[1] = {h->vr};
+        R.phase = PcgRun::GOT_TR;
+        return pcg_dots(R, 1, xs, xs);
+      }
+      return pcg_precondition(R);
+    }
+    case PcgRun::GOT_TR: {
+      if (std::sqrt(d[0]) <= R.tol) {
+        R.result = RZ_OK;
+        R.relres = R.nb > 0 ? std::sqrt(d[0]) / R.nb : 0.0;
+        R.phase = PcgRun::DONE;
+        return RZ_OK;
+      }
+      v_scale_copy(h, 1.0, h->vr, h->kr);
+      return pcg_precondition(R);
+    }
+    case PcgRun::GOT_D2: {
+      const double d1 = h->opts.precision == RZ_PREC_MIXED ? d[1] : 0.0;
+      const double beta = (d[0] - d1) / R.rz;
+      R.rz = d[0];
+      v_xpby(h, h->kz, beta, h->kp);
+      return pcg_search(R);
+    }
+    case PcgRun::GOT_FINAL:
+      R.relres = R.nb > 0 ? std::sqrt(d[0]) / R.nb : 0.0;
+      R.phase = PcgRun::DONE;
+      return RZ_OK;
+    case PcgRun::DONE:
+      return RZ_OK;
+  }
+  return RZ_OK;
+}
+
+rz_status pcg_finish(PcgRun &R, rz_solve_info *info) {
+  rz_problem *h = R.h;
+  float ms = 0;
+  if (R.ev0) {
+    HIPCALL(h, hipEventRecord(R.ev1, h->ctx->stream));
+    HIPCALL(h, hipEventSynchronize(R.ev1));
+    hipEventElapsedTime(&ms, R.ev0, R.ev1);
+    hipEventDestroy(R.ev0);
+    hipEventDestroy(R.ev1);
+    R.ev0 = R.ev1 = nullptr;
+  }
+  if (info) {
+    info->iters = R.it;
+    info->status = R.result;
+    info->rel_res = R.relres;
+    info->omega = h->omega;
+    info->t_solve_ms = ms;
+  }
+  return R.result;
+}
+
+}  // namespace
+
 extern "C" {
 
 void rz_opts_default(rz_opts *o) {
@@ -767,6 +941,8 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
       (e = dalloc(h, &h->kro, h->ndofs)) || (e = dalloc(h, &h->partials, dots_partials_size())) ||
       (e = dalloc(h, &h->dots, 4)))
     return bail(e);
+  if (hipHostMalloc((void **)&h->hdots, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return bail(fail(ctx, RZ_ERR_OOM, "pinned host buffer"));
   // the workspace of the vertex patches: keep rows of empty slots well defined
   launch_fill(h->zb64, 0.0, (int64_t)nzb, s);
   // ELL padding of the factors must read as zero
@@ -885,110 +1061,66 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *inf
   rz_status e = require_device(h);
   if (e) return e;
   if (!b || !x || b == x) return fail(h->ctx, RZ_ERR_ARG, "rz_solve: bad vectors");
-  hipStream_t s = h->ctx->stream;
-  const int64_t n = h->ndofs;
-  const bool flexible = h->opts.precision == RZ_PREC_MIXED;
-  hipEvent_t ev0, ev1;
-  HIPCALL(h, hipEventCreate(&ev0));
-  HIPCALL(h, hipEventCreate(&ev1));
-  HIPCALL(h, hipEventRecord(ev0, s));
-  // r = b with Dirichlet rows zero, x = 0
-  launch_fill(x, 0.0, n, s);
-  v_scale_copy(h, 1.0, b, h->kr);
-  launch_dirichlet_copy(h->L, nullptr, h->kr, s);
-  double bb;
-  {
-    const double *xs[1] = {h->kr}, *ys[1] = {h->kr};
-    if ((e = dots_host(h, 1, xs, ys, &bb))) return e;
+  PcgRun R;
+  R.h = h;
+  R.b = b;
+  R.x = x;
+  while (R.phase != PcgRun::DONE) {
+    if ((e = pcg_step(R))) return e;
+    if (R.phase != PcgRun::DONE) HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
   }
-  const double nb = std::sqrt(bb), tol = h->opts.rtol * nb;
-  int it = 0;
-  rz_status result = RZ_OK;
-  double relres = 0.0;
-  if (nb > 0) {
-    do_vcycle(h, h->kr, h->kz);
-    v_scale_copy(h, 1.0, h->kz, h->kp);
-    double rz_;
-    {
-      const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
-      if ((e = dots_host(h, 1, xs, ys, &rz_))) return e;
+  return pcg_finish(R, info);
+}
+
+rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const *b, double *const *x, int32_t nrhs,
+                           int32_t nthreads, rz_solve_info *infos) {
+  (void)nthreads;
+  if (!hs || !b || !x || n < 0 || nrhs < 1) return RZ_ERR_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i] || !b[i] || !x[i]) return RZ_ERR_ARG;
+    rz_status e = require_device(hs[i]);
+    if (e) return e;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(hs[i]->ctx, RZ_ERR_ARG, "rz_solve_batched: a problem appears twice");
+  }
+  // one running instance per problem (its right-hand sides one after another);
+  // every round enqueues one step of every running instance, then waits for each
+  std::vector<PcgRun> run(n);
+  std::vector<int> rhs(n, 0);
+  std::vector<rz_status> st(n, RZ_OK);
+  auto start = [&](int i) {
+    run[i] = PcgRun();
+    run[i].h = hs[i];
+    run[i].b = b[i] + (int64_t)rhs[i] * hs[i]->ndofs;
+    run[i].x = x[i] + (int64_t)rhs[i] * hs[i]->ndofs;
+  };
+  for (int i = 0; i < n; ++i) start(i);
+  int active = n;
+  while (active > 0) {
+    for (int i = 0; i < n; ++i)
+      if (rhs[i] < nrhs && st[i] == RZ_OK) {
+        rz_status e = pcg_step(run[i]);
+        if (e) st[i] = e;
+      }
+    for (int i = 0; i < n; ++i) {
+      if (rhs[i] >= nrhs || st[i] != RZ_OK) continue;
+      if (run[i].phase != PcgRun::DONE && hipStreamSynchronize(hs[i]->ctx->stream) != hipSuccess) {
+        st[i] = fail(hs[i]->ctx, RZ_ERR_HIP, "stream synchronisation");
+        continue;
+      }
+      if (run[i].phase == PcgRun::DONE) {
+        rz_solve_info inf{};
+        pcg_finish(run[i], &inf);
+        if (infos) infos[(int64_t)i * nrhs + rhs[i]] = inf;
+        if (++rhs[i] < nrhs) start(i);
+      }
     }
-    result = RZ_ERR_NOT_CONVERGED;
-    while (it < h->opts.maxit) {
-      do_apply64(h, h->kp, h->kAp);
-      double pAp;
-      {
-        const double *xs[1] = {h->kp}, *ys[1] = {h->kAp};
-        if ((e = dots_host(h, 1, xs, ys, &pAp))) return e;
-      }
-      if (!(pAp > 0)) {
-        result = fail(h->ctx, RZ_ERR_BREAKDOWN, "CG breakdown: p.Ap <= 0");
-        break;
-      }
-      const double a = rz_ / pAp;
-      v_axpy(h, a, h->kp, x);
-      if (flexible) v_scale_copy(h, 1.0, h->kr, h->kro);
-      v_axpy(h, -a, h->kAp, h->kr);
-      ++it;
-      double rr;
-      {
-        const double *xs[1] = {h->kr}, *ys[1] = {h->kr};
-        if ((e = dots_host(h, 1, xs, ys, &rr))) return e;
-      }
-      if (std::sqrt(rr) <= tol) {
-        // true residual check
-        do_apply64(h, x, h->vaz);
-        v_sub(h, b, h->vaz, h->vr);
-        launch_dirichlet_copy(h->L, nullptr, h->vr, s);
-        double tr;
-        const double *xs[1] = {h->vr}, *ys[1] = {h->vr};
-        if ((e = dots_host(h, 1, xs, ys, &tr))) return e;
-        if (std::sqrt(tr) <= tol) {
-          result = RZ_OK;
-          break;
-        }
-        v_scale_copy(h, 1.0, h->vr, h->kr);
-      }
-      do_vcycle(h, h->kr, h->kz);
-      double d2[2];
-      if (flexible) {
-        const double *xs[2] = {h->kr, h->kro}, *ys[2] = {h->kz, h->kz};
-        if ((e = dots_host(h, 2, xs, ys, d2))) return e;
-      } else {
-        const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
-        if ((e = dots_host(h, 1, xs, ys, d2))) return e;
-        d2[1] = 0.0;
-      }
-      const double beta = (d2[0] - d2[1]) / rz_;
-      rz_ = d2[0];
-      v_xpby(h, h->kz, beta, h->kp);
-    }
+    active = 0;
+    for (int i = 0; i < n; ++i) active += (rhs[i] < nrhs && st[i] == RZ_OK);
   }
-  // final true residual
-  do_apply64(h, x, h->vaz);
-  v_sub(h, b, h->vaz, h->vr);
-  launch_dirichlet_copy(h->L, nullptr, h->vr, s);
-  {
-    double tr;
-    const double *xs[1] = {h->vr}, *ys[1] = {h->vr};
-    if ((e = dots_host(h, 1, xs, ys, &tr))) return e;
-    relres = nb > 0 ? std::sqrt(tr) / nb : 0.0;
-  }
-  HIPCALL(h, hipEventRecord(ev1, s));
-  HIPCALL(h, hipEventSynchronize(ev1));
-  float ms = 0;
-  hipEventElapsedTime(&ms, ev0, ev1);
-  hipEventDestroy(ev0);
-  hipEventDestroy(ev1);
-  if (info) {
-    info->iters = it;
-    info->status = result;
-    info->rel_res = relres;
-    info->omega = h->omega;
-    info->t_solve_ms = ms;
-  }
-  if (result == RZ_ERR_NOT_CONVERGED) fail(h->ctx, result, "maximum number of iterations reached");
-  return result;
+  for (int i = 0; i < n; ++i)
+    if (st[i]) return st[i];
+  return RZ_OK;
 }
 
 rz_status rz_aux_data(const rz_problem *h, double *targets, double *features, double *base) {

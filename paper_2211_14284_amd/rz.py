@@ -6,6 +6,7 @@ There is no fallback: if the shared library is missing, importing this module
 raises.
 """
 import ctypes
+import sys
 import os
 
 import numpy as np
@@ -77,6 +78,9 @@ _proto = {
     "rz_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "rz_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "rz_aux_data": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "rz_solve_batched": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_vp),
+                                        ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(SolveInfo)]),
     "rz_set_aux": (ctypes.c_int, [_vp, _vp]),
     "rz_mlp_create": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                      ctypes.POINTER(_vp)]),
@@ -117,6 +121,8 @@ class Context:
         if code != 0:
             raise RzError(code, "rz_create failed")
         self.device = device
+        # the stream must outlive the context (and the problems, which hold the context)
+        self._stream = stream
 
     def error(self):
         return lib.rz_last_error(self.handle).decode()
@@ -131,6 +137,8 @@ class Context:
             self.handle = _vp()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -291,10 +299,28 @@ class Problem:
             self.handle = _vp()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
             pass
+
+
+def solve_batched(problems, bs, xs, nthreads=8, check=True):
+    """Batched solves: problems[i] solves the nrhs rows of the device tensor bs[i]
+    (shape nrhs x ndofs) into xs[i]; problems on different contexts run
+    concurrently.  Returns an (n, nrhs) list of SolveInfo."""
+    n = len(problems)
+    nrhs = bs[0].shape[0] if n else 1
+    H = (_vp * n)(*[p.handle for p in problems])
+    B = (_vp * n)(*[_ptr(b) for b in bs])
+    X = (_vp * n)(*[_ptr(x) for x in xs])
+    infos = (SolveInfo * max(1, n * nrhs))()
+    code = lib.rz_solve_batched(H, n, B, X, nrhs, nthreads, infos)
+    if check and code != 0:
+        raise RzError(code, "rz_solve_batched failed")
+    return [[infos[i * nrhs + r] for r in range(nrhs)] for i in range(n)]
 
 
 class MLP:
@@ -348,6 +374,8 @@ class MLP:
             self.handle = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

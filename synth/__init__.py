@@ -8,9 +8,9 @@ library receive the exact bytes produced here.
 from .splitmix import splitmix64_u64, uniform01, uniform_pm1, log_uniform
 from .workloads import (unit_cube_vertices, perturbed_vertices, cell_coefficients,
                         rhs_values, multi_rhs, c5_alpha, reference_sample_points,
-                        c5_coefficient_samples, WORKLOADS)
+                        c5_coefficient_samples, batch_spec, WORKLOADS)
 
 __all__ = ["splitmix64_u64", "uniform01", "uniform_pm1", "log_uniform",
            "unit_cube_vertices", "perturbed_vertices", "cell_coefficients",
            "rhs_values", "multi_rhs", "c5_alpha", "reference_sample_points",
-           "c5_coefficient_samples", "WORKLOADS"]
+           "c5_coefficient_samples", "batch_spec", "WORKLOADS"]

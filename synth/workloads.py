@@ -83,6 +83,15 @@ def c5_coefficient_samples(vertices: np.ndarray, n: int, amplitude: float = 0.5)
     return c5_alpha(X.reshape(-1, 3), amplitude).reshape(-1, 27)
 
 
+def batch_spec(i: int):
+    """Problem i of the batched workload: (space, n, p) from stream 1000 + i with
+    space uniform in (grad, curl, div), n uniform in 4..16 cells per axis, p uniform
+    in 3..9; its right-hand sides use seeds 4i .. 4i+3."""
+    u = uniform01(1000 + i, 3)
+    space = ("grad", "curl", "div")[min(2, int(3 * u[0]))]
+    return space, 4 + min(12, int(13 * u[1])), 3 + min(6, int(7 * u[2]))
+
+
 def rhs_values(n_dofs: int, seed: int) -> np.ndarray:
     """One U[-1,1) right-hand side of length n_dofs from stream ``seed``."""
     return uniform_pm1(seed, n_dofs)
