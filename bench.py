@@ -206,15 +206,22 @@ def bench_batched(torch, rz, nrhs=4, nctx=8, count=64):
     setup_s = time.perf_counter() - t0
     dofs_rhs = sum(pb.ndofs for pb in probs) * nrhs
     log("batched: sequential solves")
-    rz.solve_batched(probs, bs, xs, nthreads=1)   # warm-up
+
+    def sequential():
+        for pb, b, x in zip(probs, bs, xs):
+            for r in range(nrhs):
+                pb.solve(b[r], x[r])
+        torch.cuda.synchronize()
+
+    sequential()   # warm-up
+    rz.solve_batched(probs, bs, xs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    seq = rz.solve_batched(probs, bs, xs, nthreads=1)
-    torch.cuda.synchronize()
+    sequential()
     t_seq = time.perf_counter() - t0
     log("batched: concurrent solves")
     t0 = time.perf_counter()
-    con = rz.solve_batched(probs, bs, xs, nthreads=nctx)
+    con = rz.solve_batched(probs, bs, xs)
     torch.cuda.synchronize()
     t_con = time.perf_counter() - t0
     iters = [inf.iters for row in con for inf in row]
@@ -232,7 +239,7 @@ def bench_batched(torch, rz, nrhs=4, nctx=8, count=64):
     return out
 
 
-def cpu_baseline(n=4, p=7):
+def cpu_baseline(n=4, p=7, min_s=10.0):
     """The oracle's FP64 PCG (same method, same recipe) on a bounded sample."""
     from threadpoolctl import threadpool_limits
     import synth
@@ -253,13 +260,18 @@ def cpu_baseline(n=4, p=7):
         lam = pmg.lanczos_lambda_max(A, lambda r: np.where(mask, 0.0, R.apply(r)), v0)
         V = pmg.VCycle(lat, A, R, Pr, cs, pmg.omega_from_lambda(lam))
         b = np.where(mask, 0.0, synth.rhs_values(lat.ndofs, 0))
-        t0 = time.perf_counter()
-        x, it, _ = pmg.pcg(A, b, V)
-        t = time.perf_counter() - t0
+        # a bounded sample: repeat the solve until at least min_s seconds of CPU work
+        reps, t = 0, 0.0
+        while t < min_s:
+            t0 = time.perf_counter()
+            x, it, _ = pmg.pcg(A, b, V)
+            t += time.perf_counter() - t0
+            reps += 1
+        t /= reps
     return {"value": lat.ndofs / t / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle FP64 PCG to 1e-8 (same V(1,1)/IC/p-MG method and coefficient recipe), "
                       f"Q_{p} on {n}^3 cells = {lat.ndofs} DoFs, {it} iterations, setup excluded, "
-                      f"{t:.2f} s on 1 host thread"}
+                      f"{t:.3f} s per solve on 1 host thread, mean of {reps} repetitions"}
 
 
 def main():

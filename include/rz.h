@@ -169,14 +169,16 @@ rz_status rz_vcycle(rz_problem *h, const double *r, double *z);
 rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *info);
 
 /* Batch of independent solves (the batched workload of many Riesz maps of uneven
- * size and degree).  Problem i solves nrhs right-hand sides b[i] + r*ndofs_i into
- * x[i] + r*ndofs_i (device pointers, r = 0..nrhs-1), in order, with rz_solve.
- * Problems created on different contexts (hence different streams) run
- * concurrently from up to nthreads host threads (<= 0: 8); problems sharing a
- * context run one after another.  infos: n*nrhs results (may be NULL).
- * Synchronous; returns the first failing status, the other solves still run. */
+ * size and degree).  Problem i (each problem at most once) solves nrhs right-hand
+ * sides b[i] + r*ndofs_i into x[i] + r*ndofs_i (device pointers, r = 0..nrhs-1),
+ * one after another.  The PCG iterations of all problems advance in lockstep from
+ * the calling thread: each round enqueues one step of every running solve on its
+ * problem's stream, then waits for the streams, so problems created on different
+ * contexts (streams) overlap on the device.  Results equal those of rz_solve.
+ * infos: n*nrhs results (may be NULL).  Synchronous; returns the first failing
+ * status (the other solves still run to completion). */
 rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const *b, double *const *x,
-                           int32_t nrhs, int32_t nthreads, rz_solve_info *infos);
+                           int32_t nrhs, rz_solve_info *infos);
 
 /* Export host copies of setup products for parity checks.  If buf is NULL, *bytes
  * receives the size needed.  what:

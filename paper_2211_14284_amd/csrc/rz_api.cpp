@@ -1073,8 +1073,7 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *inf
 }
 
 rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const *b, double *const *x, int32_t nrhs,
-                           int32_t nthreads, rz_solve_info *infos) {
-  (void)nthreads;
+                           rz_solve_info *infos) {
   if (!hs || !b || !x || n < 0 || nrhs < 1) return RZ_ERR_ARG;
   for (int i = 0; i < n; ++i) {
     if (!hs[i] || !b[i] || !x[i]) return RZ_ERR_ARG;

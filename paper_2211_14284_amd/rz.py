@@ -79,8 +79,7 @@ _proto = {
     "rz_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "rz_aux_data": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "rz_solve_batched": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_vp),
-                                        ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32,
-                                        ctypes.POINTER(SolveInfo)]),
+                                        ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(SolveInfo)]),
     "rz_set_aux": (ctypes.c_int, [_vp, _vp]),
     "rz_mlp_create": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                      ctypes.POINTER(_vp)]),
@@ -307,7 +306,7 @@ class Problem:
             pass
 
 
-def solve_batched(problems, bs, xs, nthreads=8, check=True):
+def solve_batched(problems, bs, xs, check=True):
     """Batched solves: problems[i] solves the nrhs rows of the device tensor bs[i]
     (shape nrhs x ndofs) into xs[i]; problems on different contexts run
     concurrently.  Returns an (n, nrhs) list of SolveInfo."""
@@ -317,7 +316,7 @@ def solve_batched(problems, bs, xs, nthreads=8, check=True):
     B = (_vp * n)(*[_ptr(b) for b in bs])
     X = (_vp * n)(*[_ptr(x) for x in xs])
     infos = (SolveInfo * max(1, n * nrhs))()
-    code = lib.rz_solve_batched(H, n, B, X, nrhs, nthreads, infos)
+    code = lib.rz_solve_batched(H, n, B, X, nrhs, infos)
     if check and code != 0:
         raise RzError(code, "rz_solve_batched failed")
     return [[infos[i * nrhs + r] for r in range(nrhs)] for i in range(n)]

@@ -33,7 +33,7 @@ def test_batched_equals_single_solves():
         bs.append(torch.as_tensor(b, device="cuda:0"))
         xs.append(torch.zeros((nrhs, pb.ndofs), dtype=torch.float64, device="cuda:0"))
     torch.cuda.synchronize()
-    infos = rz.solve_batched(probs, bs, xs, nthreads=3)
+    infos = rz.solve_batched(probs, bs, xs)
     torch.cuda.synchronize()
     for i, pb in enumerate(probs):
         for r in range(nrhs):
