@@ -85,6 +85,26 @@ __global__ void __launch_bounds__(kBS) k_dot_final(int np, int nb, const double 
   }
 }
 
+// CG update fused with the next inner product: x += a p; (ro = r); r -= a Ap;
+// partial sums of r.r (same two-pass reduction as the dots)
+__global__ void __launch_bounds__(kBS) k_cg_update(double a, const double *__restrict__ p,
+                                                    const double *__restrict__ Ap, double *__restrict__ x,
+                                                    double *__restrict__ r, double *__restrict__ ro, int64_t n,
+                                                    double *partials) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += a * p[i];
+    const double ri = r[i];
+    if (ro) ro[i] = ri;
+    const double rn = ri - a * Ap[i];
+    r[i] = rn;
+    acc += rn * rn;
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
 // ---- coarse block-tridiagonal LDL^T ------------------------------------------------
 __device__ __forceinline__ int nbr(int a, int j, int mx, int my) {
   int ax = a % mx + (j % 3) - 1, ay = a / mx + (j / 3) - 1;
@@ -329,6 +349,12 @@ void launch_scale_copy(double a, const double *x, double *y, int64_t n, hipStrea
 }
 
 int dots_partials_size() { return 3 * kDotBlocks; }
+
+void launch_cg_update(double a, const double *p, const double *Ap, double *x, double *r, double *ro, int64_t n,
+                      double *partials, double *out, hipStream_t s) {
+  k_cg_update<<<kDotBlocks, kBS, 0, s>>>(a, p, Ap, x, r, ro, n, partials);
+  k_dot_final<<<1, kBS, 0, s>>>(1, kDotBlocks, partials, out);
+}
 
 void launch_dots(int npairs, const double *const *xs, const double *const *ys, int64_t n, double *partials,
                  double *out, hipStream_t s) {

@@ -242,11 +242,62 @@ __device__ __forceinline__ bool plane_point(const LatDev &L, int a, long idx, Pl
   return true;
 }
 
+// Pass 1, per cell (CPB cells along x per block): t = r_I / dd on the interior
+// (P_II is diagonal, dd = mu + sum_d sigma_d lambda_{i_d}), then for every axis a
+// and interior line along a the two face contributions
+//   fc[cell][a][side][u + Q w] = sigma_a sum_i A_{e,i} t_i,  e = 0 (side 0), P (side 1),
+// (u, w: interior coordinates along the other two axes, lower axis first).
+template <int P, typename T, int CPB>
+__global__ void __launch_bounds__(256) k_condense_cells(LatDev L, const T *__restrict__ coef, const T *__restrict__ Ag,
+                                                        const T *__restrict__ lam, const T *__restrict__ r,
+                                                        T *__restrict__ fc, int ncells) {
+  constexpr int N1 = P + 1, N2 = N1 * N1, N3 = N2 * N1, Q = P - 1, Q2 = Q * Q;
+  __shared__ T S[CPB * N3];
+  const long cell0 = (long)blockIdx.x * CPB;
+  for (int k = threadIdx.x; k < CPB * N3; k += blockDim.x) {
+    const int a = k % N1, lk = (k / N1) % CPB, bc = k / (N1 * CPB), b = bc % N1, cq = bc / N1;
+    const long ce = cell0 + lk;
+    T v = 0;
+    if (ce < ncells && a > 0 && a < P && b > 0 && b < P && cq > 0 && cq < P) {
+      const int ex = ce % L.nx, ey = (ce / L.nx) % L.ny, ez = ce / ((long)L.nx * L.ny);
+      const T *cf = coef + 6 * ce;
+      const T dd = cf[3] + cf[0] * lam[a] + cf[1] * lam[b] + cf[2] * lam[cq];
+      v = r[lat_index(L, ex * P + a, ey * P + b, ez * P + cq)] / dd;
+    }
+    S[lk * N3 + a + N1 * b + N2 * cq] = v;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < CPB * 3 * Q2; t += blockDim.x) {
+    const int uw = t % Q2, ax = (t / Q2) % 3, lk = t / (3 * Q2);
+    const long ce = cell0 + lk;
+    if (ce >= ncells) continue;
+    const int u = 1 + uw % Q, w = 1 + uw / Q;
+    // local coordinates (x, y, z) of point i on the line: axis ax varies, the
+    // lower remaining axis takes u, the higher one w
+    const int stride = ax == 0 ? 1 : (ax == 1 ? N1 : N2);
+    const int base = ax == 0 ? N1 * u + N2 * w : (ax == 1 ? u + N2 * w : u + N1 * w);
+    const T *s = S + lk * N3 + base;
+    T lo = 0, hi = 0;
+#pragma unroll
+    for (int i = 1; i < P; ++i) {
+      const T ti = s[i * stride];
+      lo += Ag[i] * ti;
+      hi += Ag[P * N1 + i] * ti;
+    }
+    const T sa = coef[6 * ce + ax];
+    T *o = fc + ((ce * 3 + ax) * 2) * Q2 + uw;
+    o[0] = sa * lo;
+    o[Q2] = sa * hi;
+  }
+}
+
+// Pass 2, per point of the vertex planes: rt_G = r_G - (contributions of the two
+// cells on either side of the face) for face DoFs, r for edge and vertex DoFs, 0 on
+// Dirichlet rows.
 template <int P, typename T>
-__global__ void __launch_bounds__(256) k_condense_plane(LatDev L, int a, const T *__restrict__ coef,
-                                                         const T *__restrict__ Ag, const T *__restrict__ lam,
+__global__ void __launch_bounds__(256) k_condense_plane(LatDev L, int a, const T *__restrict__ fc,
                                                          const T *__restrict__ r, T *__restrict__ rt) {
-  constexpr int N1 = P + 1;
+  constexpr int Q = P - 1, Q2 = Q * Q;
   PlanePoint q;
   if (!plane_point<P>(L, a, (long)blockIdx.x * blockDim.x + threadIdx.x, q) || !q.owner) return;
   const long g = lat_index(L, q.C[0], q.C[1], q.C[2]);
@@ -256,28 +307,20 @@ __global__ void __launch_bounds__(256) k_condense_plane(LatDev L, int a, const T
   }
   T val = r[g];
   if (q.face && P >= 2) {
-    const long stride = a == 0 ? 1 : (a == 1 ? (long)L.Nx : (long)L.Nx * L.Ny);
-    const int na = ncells_axis(L, a);
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      int cell[3];
-      for (int d = 0; d < 3; ++d) cell[d] = q.C[d] / P;
-      cell[a] = q.C[a] / P - 1 + side;
-      if (cell[a] < 0 || cell[a] >= na) continue;
-      const int e = side == 0 ? P : 0;
-      const int cid = cell[0] + L.nx * (cell[1] + L.ny * cell[2]);
-      const T sa = coef[6 * cid + a];
-      T base = coef[6 * cid + 3];
-      for (int d = 0; d < 3; ++d)
-        if (d != a) base += coef[6 * cid + d] * lam[q.C[d] - cell[d] * P];
-      const long g0 = g + (long)(cell[a] * P - q.C[a]) * stride;  // local coordinate 0 on axis a
-      T rr[P + 1];
-#pragma unroll
-      for (int i = 1; i < P; ++i) rr[i] = r[g0 + i * stride];
-      T part = 0;
-#pragma unroll
-      for (int i = 1; i < P; ++i) part += Ag[e * N1 + i] * rr[i] / (base + sa * lam[i]);
-      val -= sa * part;
+    const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+    const int uw = (q.C[b] % P - 1) + Q * (q.C[c] % P - 1);
+    int cell[3];
+    for (int d = 0; d < 3; ++d) cell[d] = q.C[d] / P;
+    const int ka = q.C[a] / P;
+    if (ka > 0) {  // the cell below: its face at local coordinate P (side 1)
+      cell[a] = ka - 1;
+      const long ce = cell[0] + (long)L.nx * (cell[1] + (long)L.ny * cell[2]);
+      val -= fc[((ce * 3 + a) * 2 + 1) * Q2 + uw];
+    }
+    if (ka < ncells_axis(L, a)) {  // the cell above: its face at local coordinate 0 (side 0)
+      cell[a] = ka;
+      const long ce = cell[0] + (long)L.nx * (cell[1] + (long)L.ny * cell[2]);
+      val -= fc[((ce * 3 + a) * 2) * Q2 + uw];
     }
   }
   rt[g] = val;
@@ -722,9 +765,13 @@ static long plane_points(const LatDev &L, int a) {
 }
 
 template <int P, typename T>
-static void condense_p(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *rt, hipStream_t s) {
+static void condense_p(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *fc, T *rt,
+                       hipStream_t s) {
+  constexpr int CPB = 4;
+  const long nc = (long)L.nx * L.ny * L.nz;
+  if (P >= 2) k_condense_cells<P, T, CPB><<<(unsigned)((nc + CPB - 1) / CPB), 256, 0, s>>>(L, coef, A, lam, r, fc, (int)nc);
   for (int a = 0; a < 3; ++a)
-    k_condense_plane<P, T><<<nblocks(plane_points(L, a), 256), 256, 0, s>>>(L, a, coef, A, lam, r, rt);
+    k_condense_plane<P, T><<<nblocks(plane_points(L, a), 256), 256, 0, s>>>(L, a, fc, r, rt);
 }
 
 template <int P, typename T>
@@ -751,9 +798,9 @@ static void expand_p(const LatDev &L, const T *coef, const T *A, const T *lam, c
   }
 
 template <typename T>
-void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *rt,
+void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *fc, T *rt,
                           hipStream_t s) {
-#define RZ_CALL(P) condense_p<P, T>(L, coef, A, lam, r, rt, s)
+#define RZ_CALL(P) condense_p<P, T>(L, coef, A, lam, r, fc, rt, s)
   RZ_DISPATCH_P(L.p, RZ_CALL)
 #undef RZ_CALL
 }
@@ -836,9 +883,9 @@ template void launch_apply_grad<float>(const LatDev &, const float *, const doub
 template void launch_apply_gather<double>(const LatDev &, const double *, const double *, double *, hipStream_t);
 template void launch_apply_gather<float>(const LatDev &, const float *, const float *, float *, hipStream_t);
 template void launch_condense_grad<double>(const LatDev &, const double *, const double *, const double *,
-                                           const double *, double *, hipStream_t);
+                                           const double *, double *, double *, hipStream_t);
 template void launch_condense_grad<float>(const LatDev &, const float *, const float *, const float *,
-                                          const float *, float *, hipStream_t);
+                                          const float *, float *, float *, hipStream_t);
 template int launch_patch_solve<double>(const LatDev &, const PatchEllDev &, const double *,
                                          const double *, double *, hipStream_t);
 template int launch_patch_solve<float>(const LatDev &, const PatchEllDev &, const float *,

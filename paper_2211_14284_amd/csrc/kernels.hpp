@@ -61,6 +61,9 @@ void launch_scale_copy(double a, const double *x, double *y, int64_t n, hipStrea
 void launch_dots(int npairs, const double *const *xs, const double *const *ys, int64_t n,
                  double *partials, double *out, hipStream_t s);
 int dots_partials_size();
+// x += a p; ro = r (if ro != nullptr); r -= a Ap; out[0] = r.r (two-pass, like launch_dots)
+void launch_cg_update(double a, const double *p, const double *Ap, double *x, double *r, double *ro, int64_t n,
+                      double *partials, double *out, hipStream_t s);
 
 // ---- H(grad) operator and relaxation ----------------------------------------------
 // Bh, Ah: host copies of the 1-D FDM mass and stiffness ((p+1)^2, row-major);
@@ -68,8 +71,9 @@ int dots_partials_size();
 template <typename T>
 void launch_apply_grad(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x, T *y,
                        T *ebuf, hipStream_t s);
+// fc: scratch of 6 (p-1)^2 values per cell (the per-cell face contributions)
 template <typename T>
-void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r,
+void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *fc,
                           T *rt, hipStream_t s);
 // Returns non-zero when the schedule does not fit the LDS of one block.
 size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves);

@@ -222,13 +222,15 @@ rz_status do_apply64(rz_problem *h, const double *x, double *y) {
   return RZ_OK;
 }
 
+// fc: the apply's per-cell buffer, free during a relaxation, holds the per-cell
+// face contributions of the condensation
 template <typename T>
-void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T *f, T *rt, T *zb, const T *r,
-                 T *z) {
+void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T *f, T *fc, T *rt, T *zb,
+                 const T *r, T *z) {
   hipStream_t s = h->ctx->stream;
   {
     Timed t(h, RZ_K_CONDENSE);
-    launch_condense_grad<T>(h->L, coef, A, lam, r, rt, s);
+    launch_condense_grad<T>(h->L, coef, A, lam, r, fc, rt, s);
   }
   {
     Timed t(h, RZ_K_PATCH);
@@ -241,12 +243,12 @@ void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T
 }
 
 rz_status do_relax64(rz_problem *h, const double *r, double *z) {
-  relax_steps<double>(h, h->coef64, h->A64, h->lam64, h->f64, h->rt64, h->zb64, r, z);
+  relax_steps<double>(h, h->coef64, h->A64, h->lam64, h->f64, h->eb64, h->rt64, h->zb64, r, z);
   return RZ_OK;
 }
 
 rz_status do_relax32(rz_problem *h, const float *r, float *z) {
-  relax_steps<float>(h, h->coef32, h->A32, h->lam32, h->f32, h->rt32, h->zb32, r, z);
+  relax_steps<float>(h, h->coef32, h->A32, h->lam32, h->f32, h->eb32, h->rt32, h->zb32, r, z);
   return RZ_OK;
 }
 
@@ -629,13 +631,16 @@ rz_status pcg_step(PcgRun &R) {
         return pcg_final(R);
       }
       const double a = R.rz / pAp;
-      v_axpy(h, a, h->kp, R.x);
-      if (h->opts.precision == RZ_PREC_MIXED) v_scale_copy(h, 1.0, h->kr, h->kro);
-      v_axpy(h, -a, h->kAp, h->kr);
+      {
+        Timed tm(h, RZ_K_KRYLOV);
+        launch_cg_update(a, h->kp, h->kAp, R.x, h->kr, h->opts.precision == RZ_PREC_MIXED ? h->kro : nullptr, n,
+                         h->partials, h->dots, s);
+      }
       ++R.it;
-      const double *xs[1] = {h->kr};
+      HIPCALL(h, hipMemcpyAsync(h->hdots, h->dots, sizeof(double), hipMemcpyDeviceToHost, s));
+      R.ndots = 1;
       R.phase = PcgRun::GOT_RR;
-      return pcg_dots(R, 1, xs, xs);
+      return RZ_OK;
     }
     case PcgRun::GOT_RR: {
       if (std::sqrt(d[0]) <= R.tol) {  // recurrence converged: check the true residual
