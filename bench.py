@@ -182,6 +182,20 @@ def bench_c5(torch, rz, ctx, steps, warmup, n=24, p=8):
     return out
 
 
+def bench_c3(torch, rz, ctx, n=16, p=6):
+    """H(curl) NCE_6 on a uniform 16^3 mesh, alpha = beta = 1: operator apply throughput
+    (the H(curl) relaxation is not built, so no solve)."""
+    pb = rz.Problem(ctx, n, p, 1.0, 1.0, space="curl")
+    out = {"workload": f"H(curl) NCE_{p} on {n}^3 uniform hex mesh, alpha=beta=1 (apply only)",
+           "ndofs": pb.ndofs, "nfree": pb.nfree}
+    for name, dt, code in (("f64", torch.float64, rz.F64), ("f32", torch.float32, rz.F32)):
+        ms = time_apply(torch, pb, dt, code)
+        out[f"apply_ms_{name}"] = round(ms, 4)
+        out[f"apply_gdofs_{name}"] = round(pb.ndofs / (ms * 1e-3) / 1e9, 2)
+    pb.close()
+    return out
+
+
 def bench_batched(torch, rz, nrhs=4, nctx=8, count=64):
     """The batched workload: 64 problems with (n, p) drawn per problem (n in 4..16,
     p in 3..9, streams 1000+i), 4 right-hand sides each (seeds 4i..4i+3), alpha =
@@ -285,6 +299,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-c3", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -355,6 +370,8 @@ def main():
         pm.close()
     if not args.no_c5:
         out["c5"] = bench_c5(torch, rz, ctx, max(1, args.steps // 2), 1)
+    if not args.no_c3:
+        out["c3"] = bench_c3(torch, rz, ctx)
     if not args.no_batched:
         out["batched"] = bench_batched(torch, rz)
     if not args.no_cpu_baseline:

@@ -14,6 +14,17 @@ struct LatDev {
   unsigned dir;        // Dirichlet face bits
 };
 
+// H(curl) / H(div) lattice (space 1 / 2): component m has extents ext[m][a] and
+// starts at off[m] (off[3] = all DoFs); cell_dofs = sum of the per-cell tile sizes.
+struct VecDev {
+  int p, nx, ny, nz;
+  unsigned dir;
+  int space;
+  int ext[3][3];
+  long off[4];
+  int cell_dofs;
+};
+
 // Symbolic patch data on the device.
 struct PatchDev {
   int nrows, nnz;
@@ -86,6 +97,11 @@ template <typename T>
 int launch_apply_quad_cells(const LatDev &L, const QuadDev<T> &G, const T *x, T *y, T *ebuf, hipStream_t s);
 template <typename T>
 void launch_apply_gather(const LatDev &L, const T *x, const T *ebuf, T *y, hipStream_t s);
+// y = A x in H(curl) / H(div) on axis-aligned cells (weights: 6 per cell, stiffness
+// part 0..2, mass part 3..5); ebuf: ncells * cell_dofs.  Non-zero for unsupported p.
+template <typename T>
+int launch_apply_vec(const VecDev &V, const T *coef, const T *B, const T *D, const T *x, T *y, T *ebuf,
+                     hipStream_t s);
 // number of compute units of the current device (cached), for persistent grids
 int device_cu_count();
 template <typename T>

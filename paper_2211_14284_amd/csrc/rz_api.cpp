@@ -59,6 +59,11 @@ struct rz_problem {
   std::vector<void *> allocs;
   double *coef64 = nullptr, *B64 = nullptr, *A64 = nullptr, *lam64 = nullptr, *E64 = nullptr;
   float *coef32 = nullptr, *B32 = nullptr, *A32 = nullptr, *lam32 = nullptr;
+  // H(curl) / H(div): apply only
+  int space = RZ_GRAD;
+  VecDev V{};
+  double *D64 = nullptr;
+  float *D32 = nullptr;
   // trilinear / sampled-coefficient path
   bool quad = false;
   QuadTables qt;
@@ -213,7 +218,10 @@ void v_scale_copy(rz_problem *h, double a, const double *x, double *y) {
 // ---------------------------------------------------------------------------------------
 rz_status do_apply64(rz_problem *h, const double *x, double *y) {
   Timed t(h, RZ_K_APPLY);
-  if (h->quad) {
+  if (h->space != RZ_GRAD) {
+    if (launch_apply_vec<double>(h->V, h->coef64, h->B64, h->D64, x, y, h->eb64, h->ctx->stream))
+      return fail(h->ctx, RZ_ERR_ARG, "unsupported degree");
+  } else if (h->quad) {
     launch_apply_quad_cells<double>(h->L, h->Q64, x, y, h->eb64, h->ctx->stream);
     launch_apply_gather<double>(h->L, x, h->eb64, y, h->ctx->stream);
   } else {
@@ -531,6 +539,107 @@ rz_status require_device(const rz_problem *h) {
 // =========================================================================================
 namespace {
 
+// H(curl) / H(div) problems: the cellwise-constant Cartesian cell matrices of the
+// closed form (Sec. 3.2 with the pullbacks of Sec. 3.1 on boxes), apply only.
+//   curl: stiffness weight of curl component n: alpha 2 h_n^2 / V, mass weight of
+//         component m: beta V / (2 h_m^2);
+//   div:  stiffness weight alpha 8 / V, mass weight of component m: beta 2 h_m^2 / V.
+rz_status setup_vector(rz_problem *h, const rz_coef *cf, rz_problem **out) {
+  rz_ctx *ctx = h->ctx;
+  const int p = h->p;
+  h->space = h->opts.space;
+  if (h->quad) {
+    delete h;
+    return fail(ctx, RZ_ERR_ARG, "H(curl)/H(div) need axis-aligned cells and cellwise-constant coefficients");
+  }
+  const int nvx = h->nx + 1, nvy = h->ny + 1;
+  for (int64_t c = 0; c < h->ncells; ++c) {
+    int cx = c % h->nx, cy = (c / h->nx) % h->ny, cz = c / ((int64_t)h->nx * h->ny);
+    const double hs[3] = {h->vert[3 * (cx + 1)] - h->vert[3 * cx],
+                          h->vert[3 * ((cy + 1) * nvx) + 1] - h->vert[3 * (cy * nvx) + 1],
+                          h->vert[3 * ((int64_t)(cz + 1) * nvx * nvy) + 2] - h->vert[3 * ((int64_t)cz * nvx * nvy) + 2]};
+    const double al = cf->kind == RZ_COEF_CONST ? cf->alpha[0] : cf->alpha[c];
+    const double be = cf->kind == RZ_COEF_CONST ? cf->beta[0] : cf->beta[c];
+    const double V = hs[0] * hs[1] * hs[2];
+    for (int d = 0; d < 3; ++d) {
+      if (h->space == RZ_CURL) {
+        h->coef[6 * c + d] = al * 2.0 * hs[d] * hs[d] / V;
+        h->coef[6 * c + 3 + d] = be * V / (2.0 * hs[d] * hs[d]);
+      } else {
+        h->coef[6 * c + d] = al * 8.0 / V;
+        h->coef[6 * c + 3 + d] = be * 2.0 * hs[d] * hs[d] / V;
+      }
+    }
+  }
+  VecDev &Vd = h->V;
+  Vd.p = p;
+  Vd.nx = h->nx;
+  Vd.ny = h->ny;
+  Vd.nz = h->nz;
+  Vd.dir = h->dir;
+  Vd.space = h->space;
+  const int nd[3] = {h->nx, h->ny, h->nz};
+  long off = 0;
+  Vd.cell_dofs = 0;
+  int64_t ndir = 0;
+  for (int m = 0; m < 3; ++m) {
+    int tile = 1;
+    bool P[3];
+    for (int a = 0; a < 3; ++a) {
+      P[a] = h->space == RZ_CURL ? a != m : a == m;
+      Vd.ext[m][a] = nd[a] * p + (P[a] ? 1 : 0);
+      tile *= P[a] ? p + 1 : p;
+    }
+    Vd.off[m] = off;
+    off += (long)Vd.ext[m][0] * Vd.ext[m][1] * Vd.ext[m][2];
+    Vd.cell_dofs += tile;
+    for (int64_t g = 0; g < (int64_t)Vd.ext[m][0] * Vd.ext[m][1] * Vd.ext[m][2]; ++g) {
+      const int C[3] = {(int)(g % Vd.ext[m][0]), (int)((g / Vd.ext[m][0]) % Vd.ext[m][1]),
+                        (int)(g / ((int64_t)Vd.ext[m][0] * Vd.ext[m][1]))};
+      bool d = false;
+      for (int a = 0; a < 3; ++a)
+        if (P[a] && (((h->dir >> (2 * a)) & 1u) && C[a] == 0 || ((h->dir >> (2 * a + 1)) & 1u) && C[a] == Vd.ext[m][a] - 1))
+          d = true;
+      ndir += d;
+    }
+  }
+  Vd.off[3] = off;
+  h->ndofs = off;
+  h->nfree = off - ndir;
+  if (ctx->device < 0) {
+    *out = h;
+    return RZ_OK;
+  }
+  hipStream_t s = ctx->stream;
+  rz_status e;
+  auto bail = [&](rz_status st) {
+    hipStreamSynchronize(s);
+    release(h);
+    delete h;
+    return st;
+  };
+  std::vector<float> c32(h->coef.begin(), h->coef.end()), B32(h->t.B.begin(), h->t.B.end()),
+      D32(h->t.D.begin(), h->t.D.end());
+  const size_t neb = (size_t)h->ncells * Vd.cell_dofs;
+  if ((e = upload(h, &h->coef64, h->coef)) || (e = upload(h, &h->coef32, c32)) || (e = upload(h, &h->B64, h->t.B)) ||
+      (e = upload(h, &h->B32, B32)) || (e = upload(h, &h->D64, h->t.D)) || (e = upload(h, &h->D32, D32)) ||
+      (e = dalloc(h, &h->eb64, neb)) || (e = dalloc(h, &h->eb32, neb)))
+    return bail(e);
+  if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(ctx, RZ_ERR_HIP, "setup failed"));
+  *out = h;
+  return RZ_OK;
+}
+
+rz_status require_grad(const rz_problem *h) {
+  if (h->space != RZ_GRAD)
+    return fail(h->ctx, RZ_ERR_ARG, "this call is available for H(grad) only (H(curl)/H(div): apply)");
+  return RZ_OK;
+}
+
+}  // namespace
+
+namespace {
+
 // PCG (Sec. 5) as a state machine: each step enqueues stream-ordered work and the
 // dot products it needs (copied asynchronously to pinned host memory); the caller
 // waits for the stream and hands the values to the next step.  rz_solve runs one
@@ -743,7 +852,8 @@ const char *rz_last_error(const rz_ctx *ctx) { return ctx ? ctx->err.c_str() : "
 rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz_opts *opts, rz_problem **out) {
   if (!ctx || !mesh || !cf || !opts || !out) return RZ_ERR_ARG;
   *out = nullptr;
-  if (opts->space != RZ_GRAD) return fail(ctx, RZ_ERR_ARG, "only the H(grad) space is available");
+  if (opts->space != RZ_GRAD && opts->space != RZ_CURL && opts->space != RZ_DIV)
+    return fail(ctx, RZ_ERR_ARG, "bad space");
   if (opts->p < 1 || opts->p > 9) return fail(ctx, RZ_ERR_ARG, "p must be in 1..9");
   if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(ctx, RZ_ERR_ARG, "bad mesh size");
   if (mesh->dirichlet_faces > 0x3F) return fail(ctx, RZ_ERR_ARG, "bad Dirichlet mask");
@@ -849,6 +959,7 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
       }
     }
   }
+  if (opts->space != RZ_GRAD) return setup_vector(h, cf, out);
   build_patch_symbolic(p, h->ps);
   h->erow.resize(h->ps.nnz);
   for (int r = 0; r < h->ps.nrows; ++r)
@@ -1012,7 +1123,10 @@ rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t) {
     Timed t(h, RZ_K_APPLY);
     const float *xf = static_cast<const float *>(x);
     float *yf = static_cast<float *>(y);
-    if (h->quad) {
+    if (h->space != RZ_GRAD) {
+      if (launch_apply_vec<float>(h->V, h->coef32, h->B32, h->D32, xf, yf, h->eb32, h->ctx->stream))
+        return fail(h->ctx, RZ_ERR_ARG, "unsupported degree");
+    } else if (h->quad) {
       launch_apply_quad_cells<float>(h->L, h->Q32, xf, yf, h->eb32, h->ctx->stream);
       launch_apply_gather<float>(h->L, xf, h->eb32, yf, h->ctx->stream);
     } else {
@@ -1026,6 +1140,7 @@ rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t) {
 rz_status rz_relax(rz_problem *h, const void *r, void *z, rz_dtype t) {
   rz_status e = require_device(h);
   if (e) return e;
+  if ((e = require_grad(h))) return e;
   if (!r || !z || r == z) return fail(h->ctx, RZ_ERR_ARG, "rz_relax: bad vectors");
   if (t == RZ_F64) return do_relax64(h, static_cast<const double *>(r), static_cast<double *>(z));
   if (t == RZ_F32) return do_relax32(h, static_cast<const float *>(r), static_cast<float *>(z));
@@ -1035,6 +1150,7 @@ rz_status rz_relax(rz_problem *h, const void *r, void *z, rz_dtype t) {
 rz_status rz_prolong_add(rz_problem *h, const double *xc, double *xf) {
   rz_status e = require_device(h);
   if (e) return e;
+  if ((e = require_grad(h))) return e;
   if (!xc || !xf) return fail(h->ctx, RZ_ERR_ARG, "rz_prolong_add: bad vectors");
   launch_prolong_add_grad(h->L, h->E64, xc, xf, h->ctx->stream);
   return RZ_OK;
@@ -1043,6 +1159,7 @@ rz_status rz_prolong_add(rz_problem *h, const double *xc, double *xf) {
 rz_status rz_restrict(rz_problem *h, const double *rf, double *rcv) {
   rz_status e = require_device(h);
   if (e) return e;
+  if ((e = require_grad(h))) return e;
   if (!rf || !rcv) return fail(h->ctx, RZ_ERR_ARG, "rz_restrict: bad vectors");
   launch_restrict_grad(h->L, h->E64, rf, rcv, h->rt1, h->rt2, h->ctx->stream);
   return RZ_OK;
@@ -1051,6 +1168,7 @@ rz_status rz_restrict(rz_problem *h, const double *rf, double *rcv) {
 rz_status rz_coarse_solve(rz_problem *h, const double *rcv, double *xcv) {
   rz_status e = require_device(h);
   if (e) return e;
+  if ((e = require_grad(h))) return e;
   if (!rcv || !xcv || rcv == xcv) return fail(h->ctx, RZ_ERR_ARG, "rz_coarse_solve: bad vectors");
   return do_coarse(h, rcv, xcv);
 }
@@ -1058,6 +1176,7 @@ rz_status rz_coarse_solve(rz_problem *h, const double *rcv, double *xcv) {
 rz_status rz_vcycle(rz_problem *h, const double *r, double *z) {
   rz_status e = require_device(h);
   if (e) return e;
+  if ((e = require_grad(h))) return e;
   if (!r || !z || r == z) return fail(h->ctx, RZ_ERR_ARG, "rz_vcycle: bad vectors");
   return do_vcycle(h, r, z);
 }
@@ -1065,6 +1184,7 @@ rz_status rz_vcycle(rz_problem *h, const double *r, double *z) {
 rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *info) {
   rz_status e = require_device(h);
   if (e) return e;
+  if ((e = require_grad(h))) return e;
   if (!b || !x || b == x) return fail(h->ctx, RZ_ERR_ARG, "rz_solve: bad vectors");
   PcgRun R;
   R.h = h;
@@ -1083,7 +1203,7 @@ rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const
   for (int i = 0; i < n; ++i) {
     if (!hs[i] || !b[i] || !x[i]) return RZ_ERR_ARG;
     rz_status e = require_device(hs[i]);
-    if (e) return e;
+    if (e || (e = require_grad(hs[i]))) return e;
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail(hs[i]->ctx, RZ_ERR_ARG, "rz_solve_batched: a problem appears twice");
   }
@@ -1152,6 +1272,7 @@ rz_status rz_aux_data(const rz_problem *h, double *targets, double *features, do
 rz_status rz_set_aux(rz_problem *h, const double *coef6) {
   rz_status e = require_device(h);
   if (e) return e;
+  if ((e = require_grad(h))) return e;
   if (!coef6) return fail(h->ctx, RZ_ERR_ARG, "rz_set_aux: null weights");
   for (int64_t k = 0; k < 6 * h->ncells; ++k)
     if (!(coef6[k] > 0)) return fail(h->ctx, RZ_ERR_ARG, "rz_set_aux: weights must be positive");
@@ -1189,6 +1310,24 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
   };
   switch (what) {
     case RZ_EXPORT_DOFMAP: {
+      if (h->space != RZ_GRAD) {
+        const VecDev &Vd = h->V;
+        for (int64_t c = 0; c < h->ncells; ++c) {
+          const int cc[3] = {(int)(c % h->nx), (int)((c / h->nx) % h->ny), (int)(c / ((int64_t)h->nx * h->ny))};
+          for (int m = 0; m < 3; ++m) {
+            int e3[3];
+            for (int a = 0; a < 3; ++a) e3[a] = (h->space == RZ_CURL ? a != m : a == m) ? p + 1 : p;
+            for (int l = 0; l < e3[2]; ++l)
+              for (int j = 0; j < e3[1]; ++j)
+                for (int i = 0; i < e3[0]; ++i) {
+                  const int64_t g = Vd.off[m] + (int64_t)(cc[0] * p + i) +
+                                    (int64_t)Vd.ext[m][0] * ((cc[1] * p + j) + (int64_t)Vd.ext[m][1] * (cc[2] * p + l));
+                  put(&g, sizeof g);
+                }
+          }
+        }
+        break;
+      }
       for (int64_t c = 0; c < h->ncells; ++c) {
         int cx = c % h->nx, cy = (c / h->nx) % h->ny, cz = c / ((int64_t)h->nx * h->ny);
         for (int l = 0; l < n1; ++l)

@@ -1,0 +1,107 @@
+"""GPU parity of the H(curl) (NCE_p) and H(div) (NCF_p) operator apply against the
+oracle's assembled Kronecker operator, through the C ABI; FP64 1e-12, FP32 1e-5
+relative over all DoFs.  Plus the workload C3 (NCE_6 on 16^3, 2,709,792 DoFs) at
+full size: outputs at the DoFs of sampled cells against the oracle on 3x3x3
+windows (only cells sharing a DoF with the centre cell contribute there)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.lattice import Mesh, Lattice
+from oracle import assemble as asm, matfree
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rz():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_14284_amd import rz as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(rz):
+    return rz.Context(0, torch.cuda.current_stream())
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+CASES = [("curl", (3, 2, 4), 3, 0x3F), ("curl", (2, 2, 2), 6, 0x15), ("curl", (3, 3, 2), 1, 0x3F),
+         ("curl", (2, 2, 2), 9, 0x3F), ("div", (3, 2, 4), 3, 0x3F), ("div", (2, 3, 2), 5, 0x2A),
+         ("div", (2, 2, 2), 9, 0x3F), ("div", (3, 2, 2), 1, 0x3F)]
+
+
+@pytest.mark.parametrize("space,n,p,dirichlet", CASES)
+def test_vec_apply_parity(rz, ctx, space, n, p, dirichlet):
+    m = Mesh(*n, dirichlet=dirichlet)
+    m.vertices[:, 2] *= 1.3   # anisotropic boxes
+    al = synth.cell_coefficients(m.ncells, 1)
+    be = synth.cell_coefficients(m.ncells, 2)
+    lat = Lattice(m, space, p)
+    A = asm.with_dirichlet(lat, asm.cartesian_operator(lat, al, be))
+    pb = rz.Problem(ctx, n, p, al, be, space=space, vertices=m.vertices, dirichlet=dirichlet)
+    x = synth.uniform_pm1(5, lat.ndofs)
+    y_ref = A @ np.where(lat.dirichlet_mask(), 0.0, x) + np.where(lat.dirichlet_mask(), x, 0.0)
+    xt = torch.as_tensor(x, device="cuda:0")
+    y = torch.empty_like(xt)
+    pb.apply(xt, y)
+    y32 = torch.empty(lat.ndofs, dtype=torch.float32, device="cuda:0")
+    pb.apply(xt.float(), y32, rz.F32)
+    torch.cuda.synchronize()
+    assert rel(y.cpu().numpy(), y_ref) < 1e-12
+    assert rel(y32.double().cpu().numpy(), y_ref) < 1e-5
+
+
+def _window(c0, NC, P, lat_full):
+    lo = [max(c - 1, 0) for c in c0]
+    hi = [min(c + 1, NC - 1) for c in c0]
+    nw = [h - l + 1 for l, h in zip(lo, hi)]
+    h = 1.0 / NC
+    xs = [(lo[a] + np.arange(nw[a] + 1)) * h for a in range(3)]
+    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    bits = 0
+    for a in range(3):
+        bits |= (1 << (2 * a)) if lo[a] == 0 else 0
+        bits |= (1 << (2 * a + 1)) if hi[a] == NC - 1 else 0
+    mw = Mesh(*nw, vertices=np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1), dirichlet=bits)
+    latw = Lattice(mw, lat_full.space, P)
+    co = latw.coords()                                            # (comp, X, Y, Z) window-local
+    g = np.zeros(latw.ndofs, dtype=np.int64)
+    for mcomp in range(3):
+        sel = co[:, 0] == mcomp
+        Ex, Ey, _ = lat_full.extents[mcomp]
+        Xg = co[sel, 1] + lo[0] * P
+        Yg = co[sel, 2] + lo[1] * P
+        Zg = co[sel, 3] + lo[2] * P
+        g[sel] = lat_full.offsets[mcomp] + Xg + Ex * (Yg + Ey * Zg)
+    cz, cy, cx = np.meshgrid(np.arange(lo[2], hi[2] + 1), np.arange(lo[1], hi[1] + 1),
+                             np.arange(lo[0], hi[0] + 1), indexing="ij")
+    cells = (cx + NC * (cy + NC * cz)).ravel()
+    ci = mw.cell_index()
+    centre = np.nonzero((ci[:, 0] == c0[0] - lo[0]) & (ci[:, 1] == c0[1] - lo[1]) & (ci[:, 2] == c0[2] - lo[2]))[0][0]
+    own = latw.cell_dofs()[centre]
+    return latw, g, cells, own
+
+
+def test_c3_full_size_sampled(rz, ctx):
+    NC, P = 16, 6
+    m = Mesh(NC, NC, NC)
+    lat = Lattice(m, "curl", P)
+    pb = rz.Problem(ctx, NC, P, 1.0, 1.0, space="curl")
+    assert pb.ndofs == lat.ndofs == 2709792 and pb.nfree == 2599200
+    x = synth.uniform_pm1(9, lat.ndofs)
+    xt = torch.as_tensor(x, device="cuda:0")
+    y = torch.empty_like(xt)
+    pb.apply(xt, y)
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy()
+    for c0 in [(0, 0, 0), (15, 15, 15), (7, 8, 9), (1, 14, 3), (15, 0, 6)]:
+        latw, g, cells, own = _window(c0, NC, P, lat)
+        yw = matfree.apply(latw, x[g], 1.0, 1.0)
+        assert np.linalg.norm(yh[g[own]] - yw[own]) < 1e-12 * np.linalg.norm(yw[own]), c0

@@ -150,3 +150,27 @@ def test_aux_fit_targets_and_features(p):
     assert np.allclose(t, learned.diagonal_targets(m, a, b, p), rtol=1e-12, atol=0)
     assert np.abs(f - learned.features(m, a)).max() < 1e-13
     assert np.array_equal(base, pb.aux_coefficients())
+
+
+@pytest.mark.parametrize("space", ["curl", "div"])
+@pytest.mark.parametrize("n,p,dirichlet", [((2, 3, 2), 3, 0x3F), ((3, 2, 2), 2, 0x15), ((2, 2, 2), 6, 0x3F)])
+def test_vector_space_numbering_and_weights(space, n, p, dirichlet):
+    from oracle import auxop
+    rz = _rz()
+    m = Mesh(*n, dirichlet=dirichlet)
+    m.vertices[:, 1] *= 0.7
+    al = np.linspace(0.5, 2.0, m.ncells)
+    be = np.linspace(3.0, 1.0, m.ncells)
+    pb = rz.Problem(rz.Context(-1), n, p, al, be, space=space, vertices=m.vertices, dirichlet=dirichlet)
+    lat = Lattice(m, space, p)
+    assert pb.ndofs == lat.ndofs
+    assert pb.nfree == int((~lat.dirichlet_mask()).sum())
+    assert np.array_equal(pb.dofmap(), lat.cell_dofs())
+    assert np.allclose(pb.aux_coefficients(), auxop.cartesian_coefficient_array(lat, al, be), rtol=1e-14)
+
+
+def test_vector_space_rejects_relaxation():
+    rz = _rz()
+    pb = rz.Problem(rz.Context(-1), 2, 3, space="curl")
+    with pytest.raises(rz.RzError):
+        pb.relax(1, 2)
