@@ -300,6 +300,9 @@ def main():
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="copy 1 GiB once before the solves (outside the timed region), a plain copy "
+                         "kernel of known size for scaling HBM byte counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -312,6 +315,12 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     ctx = rz.Context(0, stream)
+    if args.calib_copy:
+        src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     alpha, beta, b = workload(args.n, args.p)
     log(f"setup FP64 problem n={args.n} p={args.p}")
     t0 = time.perf_counter()
@@ -368,6 +377,15 @@ def main():
         out["kernel_ms_per_step_mixed"] = {k: round(v[0] / args.steps, 4) for k, v in ktm.items()}
         out["speedup_mixed_vs_f64"] = round(ms / msm, 3)
         pm.close()
+        log("setup defect-correction problem (FP32 operator)")
+        pd = rz.Problem(ctx, args.n, args.p, alpha, beta, precision=rz.PREC_DEFECT)
+        msd, infd, ktd = time_solves(torch, pd, bt, x, args.steps, args.warmup)
+        out["pcg_ms_defect"] = round(msd, 4)
+        out["iters_defect_inner"] = infd[-1].iters
+        out["rel_res_defect"] = max(i.rel_res for i in infd)
+        out["kernel_ms_per_step_defect"] = {k: round(v[0] / args.steps, 4) for k, v in ktd.items()}
+        out["speedup_defect_vs_f64"] = round(ms / msd, 3)
+        pd.close()
     if not args.no_c5:
         out["c5"] = bench_c5(torch, rz, ctx, max(1, args.steps // 2), 1)
     if not args.no_c3:

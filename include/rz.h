@@ -88,7 +88,10 @@ typedef struct {
 /* Precision protocols of the solve. */
 enum {
   RZ_PREC_F64 = 0,   /* FP64 apply, relaxation, coarse solve and Krylov            */
-  RZ_PREC_MIXED = 1  /* FP64 apply/coarse/Krylov, FP32 relaxation, flexible CG     */
+  RZ_PREC_MIXED = 1, /* FP64 apply/coarse/Krylov, FP32 relaxation, flexible CG     */
+  RZ_PREC_DEFECT = 2 /* defect correction: FP64 outer residuals and updates; inner  *
+                      * FP32 flexible CG (FP32 apply, FP32 V-cycle with FP64 coarse *
+                      * correction) to 1e-4 relative; iters = inner iterations      */
 };
 
 typedef struct {

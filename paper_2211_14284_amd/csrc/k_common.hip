@@ -52,6 +52,38 @@ struct DotArgs {
 };
 
 // wavefront (64 lanes) sum by shuffles, then across the 4 waves of the block
+// FP32 vectors of the inner solve of the defect-correction protocol (scalars and
+// inner products in FP64)
+__global__ void k_axpy_f(float a, const float *x, float *y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+__global__ void k_xpby_f(const float *x, float b, float *y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = x[i] + b * y[i];
+}
+__global__ void k_sub_f(const float *x, const float *y, float *z, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = x[i] - y[i];
+}
+__global__ void k_scale_copy_f(float a, const float *x, float *y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+__global__ void k_fill_f(float *y, float v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+// y64 += x32 ; z32 += t64
+__global__ void k_add_f2d(const float *x, double *y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += (double)x[i];
+}
+__global__ void k_add_d2f(const double *t, float *z, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] += (float)t[i];
+}
+
 __device__ __forceinline__ double block_sum(double v, double *red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -100,6 +132,40 @@ __global__ void __launch_bounds__(kBS) k_cg_update(double a, const double *__res
     const double rn = ri - a * Ap[i];
     r[i] = rn;
     acc += rn * rn;
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+struct DotArgsF {
+  const float *x[3];
+  const float *y[3];
+};
+
+__global__ void __launch_bounds__(kBS) k_dot_partial_f(int np, DotArgsF a, int64_t n, double *partials) {
+  __shared__ double red[16];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    for (int k = 0; k < np; ++k) acc[k] += (double)a.x[k][i] * (double)a.y[k][i];
+  for (int k = 0; k < np; ++k) {
+    double t = block_sum(acc[k], red);
+    if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kBS) k_cg_update_f(float a, const float *__restrict__ p,
+                                                      const float *__restrict__ Ap, float *__restrict__ x,
+                                                      float *__restrict__ r, float *__restrict__ ro, int64_t n,
+                                                      double *partials) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += a * p[i];
+    const float ri = r[i];
+    if (ro) ro[i] = ri;
+    const float rn = ri - a * Ap[i];
+    r[i] = rn;
+    acc += (double)rn * (double)rn;
   }
   const double t = block_sum(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -349,6 +415,40 @@ void launch_scale_copy(double a, const double *x, double *y, int64_t n, hipStrea
 }
 
 int dots_partials_size() { return 3 * kDotBlocks; }
+void launch_axpy_f(float a, const float *x, float *y, int64_t n, hipStream_t s) {
+  k_axpy_f<<<nblk(n), kBS, 0, s>>>(a, x, y, n);
+}
+void launch_xpby_f(const float *x, float b, float *y, int64_t n, hipStream_t s) {
+  k_xpby_f<<<nblk(n), kBS, 0, s>>>(x, b, y, n);
+}
+void launch_sub_f(const float *x, const float *y, float *z, int64_t n, hipStream_t s) {
+  k_sub_f<<<nblk(n), kBS, 0, s>>>(x, y, z, n);
+}
+void launch_scale_copy_f(float a, const float *x, float *y, int64_t n, hipStream_t s) {
+  k_scale_copy_f<<<nblk(n), kBS, 0, s>>>(a, x, y, n);
+}
+void launch_fill_f(float *y, float v, int64_t n, hipStream_t s) { k_fill_f<<<nblk(n), kBS, 0, s>>>(y, v, n); }
+void launch_add_f2d(const float *x, double *y, int64_t n, hipStream_t s) {
+  k_add_f2d<<<nblk(n), kBS, 0, s>>>(x, y, n);
+}
+void launch_add_d2f(const double *t, float *z, int64_t n, hipStream_t s) {
+  k_add_d2f<<<nblk(n), kBS, 0, s>>>(t, z, n);
+}
+void launch_dots_f(int npairs, const float *const *xs, const float *const *ys, int64_t n, double *partials,
+                   double *out, hipStream_t s) {
+  DotArgsF a{};
+  for (int k = 0; k < npairs; ++k) {
+    a.x[k] = xs[k];
+    a.y[k] = ys[k];
+  }
+  k_dot_partial_f<<<kDotBlocks, kBS, 0, s>>>(npairs, a, n, partials);
+  k_dot_final<<<1, kBS, 0, s>>>(npairs, kDotBlocks, partials, out);
+}
+void launch_cg_update_f(float a, const float *p, const float *Ap, float *x, float *r, float *ro, int64_t n,
+                        double *partials, double *out, hipStream_t s) {
+  k_cg_update_f<<<kDotBlocks, kBS, 0, s>>>(a, p, Ap, x, r, ro, n, partials);
+  k_dot_final<<<1, kBS, 0, s>>>(1, kDotBlocks, partials, out);
+}
 
 void launch_cg_update(double a, const double *p, const double *Ap, double *x, double *r, double *ro, int64_t n,
                       double *partials, double *out, hipStream_t s) {

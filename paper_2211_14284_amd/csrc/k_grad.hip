@@ -706,11 +706,12 @@ __global__ void k_restrict_z(LatDev L, const double *__restrict__ E, const doubl
   rc[i] = acc;
 }
 
-__global__ void k_dirichlet_copy(LatDev L, const double *__restrict__ r, double *__restrict__ z, long n) {
+template <typename T>
+__global__ void k_dirichlet_copy(LatDev L, const T *__restrict__ r, T *__restrict__ z, long n) {
   long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   int X = g % L.Nx, Y = (g / L.Nx) % L.Ny, Z = g / ((long)L.Nx * L.Ny);
-  if (lat_dirichlet(L, X, Y, Z)) z[g] = r ? r[g] : 0.0;
+  if (lat_dirichlet(L, X, Y, Z)) z[g] = r ? r[g] : T(0);
 }
 
 inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -858,7 +859,12 @@ void launch_patch_factor(const LatDev &L, const PatchDev &P, const double *coef,
 
 void launch_dirichlet_copy(const LatDev &L, const double *r, double *z, hipStream_t s) {
   long n = (long)L.Nx * L.Ny * L.Nz;
-  k_dirichlet_copy<<<nblocks(n, 256), 256, 0, s>>>(L, r, z, n);
+  k_dirichlet_copy<double><<<nblocks(n, 256), 256, 0, s>>>(L, r, z, n);
+}
+
+void launch_dirichlet_copy_f(const LatDev &L, const float *r, float *z, hipStream_t s) {
+  long n = (long)L.Nx * L.Ny * L.Nz;
+  k_dirichlet_copy<float><<<nblocks(n, 256), 256, 0, s>>>(L, r, z, n);
 }
 
 void launch_prolong_add_grad(const LatDev &L, const double *E, const double *xc, double *xf,

@@ -76,6 +76,20 @@ int dots_partials_size();
 void launch_cg_update(double a, const double *p, const double *Ap, double *x, double *r, double *ro, int64_t n,
                       double *partials, double *out, hipStream_t s);
 
+// FP32 vectors (inner solve of the defect-correction protocol); inner products
+// accumulate in FP64 into out[k] like launch_dots
+void launch_axpy_f(float a, const float *x, float *y, int64_t n, hipStream_t s);
+void launch_xpby_f(const float *x, float b, float *y, int64_t n, hipStream_t s);
+void launch_sub_f(const float *x, const float *y, float *z, int64_t n, hipStream_t s);
+void launch_scale_copy_f(float a, const float *x, float *y, int64_t n, hipStream_t s);
+void launch_fill_f(float *y, float v, int64_t n, hipStream_t s);
+void launch_add_f2d(const float *x, double *y, int64_t n, hipStream_t s);  // y += x
+void launch_add_d2f(const double *t, float *z, int64_t n, hipStream_t s);  // z += t
+void launch_dots_f(int npairs, const float *const *xs, const float *const *ys, int64_t n, double *partials,
+                   double *out, hipStream_t s);
+void launch_cg_update_f(float a, const float *p, const float *Ap, float *x, float *r, float *ro, int64_t n,
+                        double *partials, double *out, hipStream_t s);
+
 // ---- H(grad) operator and relaxation ----------------------------------------------
 // Bh, Ah: host copies of the 1-D FDM mass and stiffness ((p+1)^2, row-major);
 // ebuf: per-cell scratch of ncells*(p+1)^3 values for the interface contributions
@@ -116,6 +130,7 @@ void launch_patch_factor(const LatDev &L, const PatchDev &P, const double *coef,
                          hipStream_t s);
 
 // z_D = r_D on Dirichlet rows of the Q_p lattice (r == nullptr: z_D = 0).
+void launch_dirichlet_copy_f(const LatDev &L, const float *r, float *z, hipStream_t s);
 void launch_dirichlet_copy(const LatDev &L, const double *r, double *z, hipStream_t s);
 
 // ---- p-transfer (Q_1 <-> Q_p) -------------------------------------------------------

@@ -75,6 +75,9 @@ struct rz_problem {
   float *f32 = nullptr, *eb32 = nullptr;
   double *rt64 = nullptr, *zb64 = nullptr;
   float *rt32 = nullptr, *zb32 = nullptr, *r32 = nullptr, *z32 = nullptr;
+  // inner FP32 solve of the defect-correction protocol
+  float *kp32 = nullptr, *kAp32 = nullptr, *ko32 = nullptr, *ke32 = nullptr, *t32 = nullptr, *az32 = nullptr,
+        *vr32 = nullptr;
   double *vt = nullptr, *vaz = nullptr, *vr = nullptr, *rc = nullptr, *xc = nullptr, *rt1 = nullptr, *rt2 = nullptr;
   // coarse
   int cm = 0, cmx = 0, cmy = 0, cmz = 0, cbx0 = 0, cby0 = 0, cbz0 = 0, cNX = 0, cNY = 0, cNZ = 0;
@@ -261,8 +264,9 @@ rz_status do_relax32(rz_problem *h, const float *r, float *z) {
 }
 
 // fine relaxation on FP64 vectors in the precision of the problem's protocol
+// (FP32 relaxation for the mixed and defect-correction protocols)
 rz_status do_relax_prec(rz_problem *h, const double *r, double *z) {
-  if (h->opts.precision == RZ_PREC_MIXED) {
+  if (h->opts.precision != RZ_PREC_F64) {
     launch_cast_d2f(r, h->r32, h->ndofs, h->ctx->stream);
     do_relax32(h, h->r32, h->z32);
     launch_cast_f2d(h->z32, z, h->ndofs, h->ctx->stream);
@@ -310,6 +314,52 @@ rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
   return RZ_OK;
 }
 
+rz_status do_apply32(rz_problem *h, const float *x, float *y) {
+  Timed t(h, RZ_K_APPLY);
+  hipStream_t s = h->ctx->stream;
+  if (h->space != RZ_GRAD) {
+    if (launch_apply_vec<float>(h->V, h->coef32, h->B32, h->D32, x, y, h->eb32, s))
+      return fail(h->ctx, RZ_ERR_ARG, "unsupported degree");
+  } else if (h->quad) {
+    launch_apply_quad_cells<float>(h->L, h->Q32, x, y, h->eb32, s);
+    launch_apply_gather<float>(h->L, x, h->eb32, y, s);
+  } else {
+    launch_apply_grad<float>(h->L, h->coef32, h->t.B.data(), h->t.A.data(), x, y, h->eb32, s);
+  }
+  return RZ_OK;
+}
+
+// The V(1,1) cycle on FP32 vectors (inner solve of the defect-correction
+// protocol): FP32 apply and relaxation, the coarse correction in FP64.
+rz_status do_vcycle32(rz_problem *h, const float *r, float *z) {
+  hipStream_t s = h->ctx->stream;
+  const int64_t n = h->ndofs;
+  const float w = (float)h->omega;
+  do_relax32(h, r, h->t32);
+  launch_scale_copy_f(w, h->t32, z, n, s);      // z = w M r
+  do_apply32(h, z, h->az32);
+  launch_sub_f(r, h->az32, h->vr32, n, s);       // r1 = r - A z
+  launch_cast_f2d(h->vr32, h->vr, n, s);
+  {
+    Timed tm(h, RZ_K_TRANSFER);
+    launch_restrict_grad(h->L, h->E64, h->vr, h->rc, h->rt1, h->rt2, s);
+  }
+  rz_status e = do_coarse(h, h->rc, h->xc);
+  if (e) return e;
+  launch_fill(h->vt, 0.0, n, s);
+  {
+    Timed tm(h, RZ_K_TRANSFER);
+    launch_prolong_add_grad(h->L, h->E64, h->xc, h->vt, s);
+  }
+  launch_add_d2f(h->vt, z, n, s);                // z += P A0^{-1} P^T r1
+  do_apply32(h, z, h->az32);
+  launch_sub_f(r, h->az32, h->vr32, n, s);       // r2 = r - A z
+  do_relax32(h, h->vr32, h->t32);
+  launch_axpy_f(w, h->t32, z, n, s);             // z += w M r2
+  launch_dirichlet_copy_f(h->L, r, z, s);
+  return RZ_OK;
+}
+
 rz_status dots_host(rz_problem *h, int np, const double *const *xs, const double *const *ys, double *out) {
   {
     Timed tm(h, RZ_K_KRYLOV);
@@ -318,6 +368,111 @@ rz_status dots_host(rz_problem *h, int np, const double *const *xs, const double
   HIPCALL(h, hipMemcpyAsync(out, h->dots, sizeof(double) * np, hipMemcpyDeviceToHost, h->ctx->stream));
   HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
   return RZ_OK;
+}
+
+rz_status dots_host_f(rz_problem *h, int np, const float *const *xs, const float *const *ys, double *out) {
+  {
+    Timed tm(h, RZ_K_KRYLOV);
+    launch_dots_f(np, xs, ys, h->ndofs, h->partials, h->dots, h->ctx->stream);
+  }
+  HIPCALL(h, hipMemcpyAsync(out, h->dots, sizeof(double) * np, hipMemcpyDeviceToHost, h->ctx->stream));
+  HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+  return RZ_OK;
+}
+
+// Defect correction (not in the paper; the FP32 operator protocol): the outer loop
+// forms the true residual r = b - A x in FP64 and stops at ||r|| <= rtol ||b||; each
+// correction solves A e = r with FP32 flexible CG (FP32 apply, FP32 V-cycle,
+// Polak-Ribiere) to 1e-4 relative, and x += e in FP64.  iters counts the inner
+// iterations.
+rz_status defect_solve(rz_problem *h, const double *b, double *x, rz_solve_info *info) {
+  hipStream_t s = h->ctx->stream;
+  const int64_t n = h->ndofs;
+  rz_status e;
+  hipEvent_t ev0, ev1;
+  HIPCALL(h, hipEventCreate(&ev0));
+  HIPCALL(h, hipEventCreate(&ev1));
+  HIPCALL(h, hipEventRecord(ev0, s));
+  launch_fill(x, 0.0, n, s);
+  v_scale_copy(h, 1.0, b, h->kr);
+  launch_dirichlet_copy(h->L, nullptr, h->kr, s);
+  double bb;
+  {
+    const double *xs[1] = {h->kr};
+    if ((e = dots_host(h, 1, xs, xs, &bb))) return e;
+  }
+  const double nb = std::sqrt(bb), tol = h->opts.rtol * nb;
+  int it = 0;
+  rz_status result = RZ_ERR_NOT_CONVERGED;
+  double rr = bb;
+  for (int outer = 0; outer < 64; ++outer) {
+    if (outer > 0) {  // true residual of the current iterate
+      do_apply64(h, x, h->vaz);
+      v_sub(h, b, h->vaz, h->kr);
+      launch_dirichlet_copy(h->L, nullptr, h->kr, s);
+      const double *xs[1] = {h->kr};
+      if ((e = dots_host(h, 1, xs, xs, &rr))) return e;
+    }
+    if (std::sqrt(rr) <= tol) {
+      result = RZ_OK;
+      break;
+    }
+    if (it >= h->opts.maxit) break;
+    // inner FP32 flexible CG from e = 0
+    launch_cast_d2f(h->kr, h->r32, n, s);
+    launch_fill_f(h->ke32, 0.0f, n, s);
+    if ((e = do_vcycle32(h, h->r32, h->z32))) return e;
+    launch_scale_copy_f(1.0f, h->z32, h->kp32, n, s);
+    double rz;
+    {
+      const float *xs[1] = {h->r32}, *ys[1] = {h->z32};
+      if ((e = dots_host_f(h, 1, xs, ys, &rz))) return e;
+    }
+    const double tol_in = 1e-4 * std::sqrt(rr);
+    while (it < h->opts.maxit) {
+      if ((e = do_apply32(h, h->kp32, h->kAp32))) return e;
+      double pAp;
+      {
+        const float *xs[1] = {h->kp32}, *ys[1] = {h->kAp32};
+        if ((e = dots_host_f(h, 1, xs, ys, &pAp))) return e;
+      }
+      if (!(pAp > 0)) break;  // the FP64 outer loop decides
+      const double a = rz / pAp;
+      double rin;
+      {
+        Timed tm(h, RZ_K_KRYLOV);
+        launch_cg_update_f((float)a, h->kp32, h->kAp32, h->ke32, h->r32, h->ko32, n, h->partials, h->dots, s);
+      }
+      HIPCALL(h, hipMemcpyAsync(&rin, h->dots, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCALL(h, hipStreamSynchronize(s));
+      ++it;
+      if (std::sqrt(rin) <= tol_in) break;
+      if ((e = do_vcycle32(h, h->r32, h->z32))) return e;
+      double d[2];
+      {
+        const float *xs[2] = {h->r32, h->ko32}, *ys[2] = {h->z32, h->z32};
+        if ((e = dots_host_f(h, 2, xs, ys, d))) return e;
+      }
+      const double beta = (d[0] - d[1]) / rz;
+      rz = d[0];
+      launch_xpby_f(h->z32, (float)beta, h->kp32, n, s);
+    }
+    launch_add_f2d(h->ke32, x, n, s);
+  }
+  HIPCALL(h, hipEventRecord(ev1, s));
+  HIPCALL(h, hipEventSynchronize(ev1));
+  float ms = 0;
+  hipEventElapsedTime(&ms, ev0, ev1);
+  hipEventDestroy(ev0);
+  hipEventDestroy(ev1);
+  if (info) {
+    info->iters = it;
+    info->status = result;
+    info->rel_res = nb > 0 ? std::sqrt(rr) / nb : 0.0;
+    info->omega = h->omega;
+    info->t_solve_ms = ms;
+  }
+  return result;
 }
 
 // largest eigenvalue of T (k x k symmetric tridiagonal) by bisection on Sturm counts
@@ -860,7 +1015,7 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
   if (cf->kind != RZ_COEF_CONST && cf->kind != RZ_COEF_CELL && cf->kind != RZ_COEF_SAMPLES)
     return fail(ctx, RZ_ERR_ARG, "bad coefficient kind");
   if (!cf->alpha || !cf->beta) return fail(ctx, RZ_ERR_ARG, "missing coefficients");
-  if (opts->precision != RZ_PREC_F64 && opts->precision != RZ_PREC_MIXED)
+  if (opts->precision != RZ_PREC_F64 && opts->precision != RZ_PREC_MIXED && opts->precision != RZ_PREC_DEFECT)
     return fail(ctx, RZ_ERR_ARG, "bad precision");
   rz_problem *h = new rz_problem();
   h->ctx = ctx;
@@ -1059,6 +1214,12 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
     return bail(e);
   if (hipHostMalloc((void **)&h->hdots, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return bail(fail(ctx, RZ_ERR_OOM, "pinned host buffer"));
+  if (opts->precision == RZ_PREC_DEFECT &&
+      ((e = dalloc(h, &h->kp32, h->ndofs)) || (e = dalloc(h, &h->kAp32, h->ndofs)) ||
+       (e = dalloc(h, &h->ko32, h->ndofs)) || (e = dalloc(h, &h->ke32, h->ndofs)) ||
+       (e = dalloc(h, &h->t32, h->ndofs)) || (e = dalloc(h, &h->az32, h->ndofs)) ||
+       (e = dalloc(h, &h->vr32, h->ndofs))))
+    return bail(e);
   // the workspace of the vertex patches: keep rows of empty slots well defined
   launch_fill(h->zb64, 0.0, (int64_t)nzb, s);
   // ELL padding of the factors must read as zero
@@ -1119,21 +1280,7 @@ rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t) {
   if (e) return e;
   if (!x || !y || x == y) return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad vectors");
   if (t == RZ_F64) return do_apply64(h, static_cast<const double *>(x), static_cast<double *>(y));
-  if (t == RZ_F32) {
-    Timed t(h, RZ_K_APPLY);
-    const float *xf = static_cast<const float *>(x);
-    float *yf = static_cast<float *>(y);
-    if (h->space != RZ_GRAD) {
-      if (launch_apply_vec<float>(h->V, h->coef32, h->B32, h->D32, xf, yf, h->eb32, h->ctx->stream))
-        return fail(h->ctx, RZ_ERR_ARG, "unsupported degree");
-    } else if (h->quad) {
-      launch_apply_quad_cells<float>(h->L, h->Q32, xf, yf, h->eb32, h->ctx->stream);
-      launch_apply_gather<float>(h->L, xf, h->eb32, yf, h->ctx->stream);
-    } else {
-      launch_apply_grad<float>(h->L, h->coef32, h->t.B.data(), h->t.A.data(), xf, yf, h->eb32, h->ctx->stream);
-    }
-    return RZ_OK;
-  }
+  if (t == RZ_F32) return do_apply32(h, static_cast<const float *>(x), static_cast<float *>(y));
   return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad dtype");
 }
 
@@ -1186,6 +1333,7 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *inf
   if (e) return e;
   if ((e = require_grad(h))) return e;
   if (!b || !x || b == x) return fail(h->ctx, RZ_ERR_ARG, "rz_solve: bad vectors");
+  if (h->opts.precision == RZ_PREC_DEFECT) return defect_solve(h, b, x, info);
   PcgRun R;
   R.h = h;
   R.b = b;
@@ -1204,6 +1352,8 @@ rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const
     if (!hs[i] || !b[i] || !x[i]) return RZ_ERR_ARG;
     rz_status e = require_device(hs[i]);
     if (e || (e = require_grad(hs[i]))) return e;
+    if (hs[i]->opts.precision == RZ_PREC_DEFECT)
+      return fail(hs[i]->ctx, RZ_ERR_ARG, "rz_solve_batched: the defect-correction protocol is not batched");
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail(hs[i]->ctx, RZ_ERR_ARG, "rz_solve_batched: a problem appears twice");
   }

@@ -209,3 +209,23 @@ def test_solve_c1(rz, ctx):
     assert info.rel_res <= 1e-8
     assert rel(H(x), xs) < 1e-6
     assert 8 <= info.iters <= 16
+
+
+@pytest.mark.parametrize("n,p", [((4, 4, 4), 4), ((3, 3, 3), 7)])
+def test_solve_defect_correction(rz, ctx, n, p):
+    """FP32 operator protocol: FP64 outer residuals, FP32 inner flexible CG.  The
+    oracle has no FP32 path, so the check is the plain definition: the true residual
+    reaches 1e-8 and the solution matches the direct solve."""
+    al, be = coefs(n)
+    ref = Ref(n, p, al, be, relax=False)
+    pb = rz.Problem(ctx, n, p, al, be, precision=rz.PREC_DEFECT)
+    b = np.where(ref.mask, 0.0, synth.rhs_values(ref.lat.ndofs, 0))
+    x = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
+    info = pb.solve(T(b), x)
+    xg = H(x)
+    xs = spla.spsolve(ref.A.tocsc(), b)
+    assert info.rel_res <= 1e-8
+    assert np.linalg.norm(b - ref.A @ xg) <= 1.01e-8 * np.linalg.norm(b)
+    eA = np.sqrt((xg - xs) @ (ref.A @ (xg - xs)) / (xs @ (ref.A @ xs)))
+    assert eA < 1e-7
+    assert 5 <= info.iters <= 80
