@@ -27,6 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of a kernel group from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0, factors from a plain 1 GiB copy in the same run); the figure belongs
+# to the kernel version it was taken on (profiles/pmc_patch_solve_hgrad_q7_n32.md)
+MEASURED_TRAFFIC = {"patch": 4.401e9}
 METRIC = "GDoF/s sum-factorized apply; PCG time-to-1e-8, FP64 vs mixed, H(grad) p=7"
 
 
@@ -341,7 +345,9 @@ def main():
     if dom in kb and kt[dom][1]:
         ach = kb[dom] / (per_launch[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": MEASURED_TRAFFIC.get(dom) if args.p == 7 and args.n == 32 else None,
+                "kernel": dom,
                 "avg_launch_ms": round(per_launch[dom], 4), "algorithmic_bytes_per_launch": kb[dom]}
     log(f"FP64 solve {ms:.3f} ms, {iters} iterations; timing the apply")
     apply64 = time_apply(torch, pb, torch.float64, rz.F64)
