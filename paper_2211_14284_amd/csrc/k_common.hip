@@ -269,34 +269,50 @@ __device__ void grid_barrier(unsigned *flags, unsigned gen, int *status) {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Whole coarse solve in one persistent cooperative launch: block forward sweep
-//   v_k = W_k (r_k - C_k v_{k-1}),
-// block backward sweep
-//   x_k = v_k - W_k (C_{k+1}^T x_{k+1}),
-// one grid barrier per plane.  Every block rebuilds the coupled right-hand side w
-// in LDS (in-plane neighbours from the table nb, -1 = none); one row of W per
-// wavefront (16 rows per block), the row of the next plane loaded into registers
+// Coupling products of the block LDL^T: out = W_k Cs with Cs the 9-point in-plane
+// coupling of plane k to a neighbouring plane (C[a][j]: row a, neighbour j of a), so
+// out[i][b] = sum_j W_k[i][nbr_j(b)] C[nbr_j(b)][8 - j] (the offset of b seen from
+// nbr_j(b) is the reverse one, index 8 - j).
+__global__ void k_coarse_wc(int m, int mx, int my, const double *__restrict__ W, const double *__restrict__ C,
+                            double *__restrict__ out) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * m) return;
+  const int i = idx / m, b = idx % m;
+  double s = 0.0;
+  for (int j = 0; j < 9; ++j) {
+    const int a = nbr(b, j, mx, my);
+    if (a >= 0) s += W[(int64_t)i * m + a] * C[(int64_t)a * 9 + (8 - j)];
+  }
+  out[idx] = s;
+}
+
+// Whole coarse solve, one persistent cooperative launch, with M_k = W_k C_k and
+// N_k = W_k C_{k+1}^T precomputed:
+//   u_k = W_k r_k (all planes, no barrier: each wavefront owns its rows),
+//   v_0 = u_0, v_k = u_k - M_k v_{k-1},   x_{nb-1} = v_{nb-1}, x_k = v_k - N_k x_{k+1}.
+// One matrix row per wavefront (RPB rows per block); the neighbouring plane's vector
+// is staged in LDS once per block; the next matrix row is loaded into registers
 // before the barrier of the current plane.
-struct CoarseArgs {
+struct CoarseArgs2 {
   int m, nb;
-  const double *W, *C, *Ct, *r;
-  const int *nbt;
-  double *v, *x;
+  const double *W, *M, *N, *r;
+  double *u, *v, *x;
   unsigned *flags;
   unsigned gen0;
   int *status;
 };
 
-template <int MPL>
-__global__ void __launch_bounds__(1024) k_coarse_persistent(CoarseArgs a) {
-  extern __shared__ double w[];
-  const int m = a.m;
+template <int MPL, int RPB>
+__global__ void __launch_bounds__(64 * RPB) k_coarse_mn(CoarseArgs2 a) {
+  extern __shared__ double vl[];
+  const int m = a.m, nb = a.nb;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int row = blockIdx.x * 16 + wid;
+  const int row = blockIdx.x * RPB + wid;
   const bool has_row = row < m;
+  const size_t mm = (size_t)m * m;
   double wr[MPL];
-  auto load_row = [&](int k) {
-    const double *Wr = a.W + (size_t)k * m * m + (size_t)(has_row ? row : 0) * m;
+  auto load_row = [&](const double *mat) {
+    const double *Wr = mat + (size_t)(has_row ? row : 0) * m;
 #pragma unroll
     for (int j = 0; j < MPL; ++j) {
       const int c = lane + 64 * j;
@@ -308,74 +324,51 @@ __global__ void __launch_bounds__(1024) k_coarse_persistent(CoarseArgs a) {
 #pragma unroll
     for (int j = 0; j < MPL; ++j) {
       const int c = lane + 64 * j;
-      if (c < m) acc += wr[j] * w[c];
+      if (c < m) acc += wr[j] * vl[c];
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
     return acc;
   };
-  load_row(0);
-  for (int k = 0; k < a.nb; ++k) {
+  // phase 0: u_k = W_k r_k
+  load_row(a.W);
+  for (int k = 0; k < nb; ++k) {
     const double *rk = a.r + (size_t)k * m;
-    const double *Ck = a.C + (size_t)k * m * 9;
-    const double *vp = k ? a.v + (size_t)(k - 1) * m : nullptr;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-      double t = rk[i];
-      if (vp) {
-        // all nine loads issued unconditionally (a missing neighbour reads the row
-        // itself and is masked), so they are in flight together
-        int c[9];
-        double nv[9];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) c[j] = a.nbt[i * 9 + j];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) nv[j] = ld_agent(vp + (c[j] >= 0 ? c[j] : i));
-        double cc[9];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) cc[j] = Ck[i * 9 + j];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) t -= c[j] >= 0 ? cc[j] * nv[j] : 0.0;
-      }
-      w[i] = t;
-    }
+    for (int i = threadIdx.x; i < m; i += blockDim.x) vl[i] = rk[i];
     __syncthreads();
     const double acc = row_dot();
-    if (has_row && lane == 0) st_agent(a.v + (size_t)k * m + row, acc);
+    if (k + 1 < nb) load_row(a.W + (k + 1) * mm);
+    else if (nb > 1) load_row(a.M + mm);
+    if (has_row && lane == 0) a.u[(size_t)k * m + row] = acc;
+    __syncthreads();
+  }
+  // forward sweep
+  if (has_row && lane == 0) st_agent(a.v + row, a.u[row]);
+  store_done();
+  grid_barrier(a.flags, a.gen0 + 1, a.status);
+  for (int k = 1; k < nb; ++k) {
+    const double *vp = a.v + (size_t)(k - 1) * m;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) vl[i] = ld_agent(vp + i);
+    __syncthreads();
+    const double acc = row_dot();
+    if (k + 1 < nb) load_row(a.M + (k + 1) * mm);
+    else load_row(a.N + (nb - 2) * mm);
+    if (has_row && lane == 0) st_agent(a.v + (size_t)k * m + row, a.u[(size_t)k * m + row] - acc);
     store_done();
-    load_row(k + 1 < a.nb ? k + 1 : a.nb - 1);
     grid_barrier(a.flags, a.gen0 + 1 + k, a.status);
   }
-  for (int k = a.nb - 1; k >= 0; --k) {
-    const double *vk = a.v + (size_t)k * m;
-    double *xk = a.x + (size_t)k * m;
-    if (k == a.nb - 1) {
-      if (has_row && lane == 0) st_agent(xk + row, ld_agent(vk + row));
-      store_done();
-      if (k > 0) load_row(k - 1);
-    } else {
-      const double *Ctk = a.Ct + (size_t)k * m * 9;
-      const double *xn = a.x + (size_t)(k + 1) * m;
-      for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        int c[9];
-        double nv[9];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) c[j] = a.nbt[i * 9 + j];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) nv[j] = ld_agent(xn + (c[j] >= 0 ? c[j] : i));
-        double cc[9];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) cc[j] = Ctk[i * 9 + j];
-        double t = 0.0;
-#pragma unroll
-        for (int j = 0; j < 9; ++j) t += c[j] >= 0 ? cc[j] * nv[j] : 0.0;
-        w[i] = t;
-      }
-      __syncthreads();
-      const double acc = row_dot();
-      if (has_row && lane == 0) st_agent(xk + row, ld_agent(vk + row) - acc);
-      store_done();
-      if (k > 0) load_row(k - 1);
-    }
-    if (k > 0) grid_barrier(a.flags, a.gen0 + a.nb + (a.nb - k), a.status);
+  // backward sweep
+  if (has_row && lane == 0) st_agent(a.x + (size_t)(nb - 1) * m + row, ld_agent(a.v + (size_t)(nb - 1) * m + row));
+  store_done();
+  if (nb > 1) grid_barrier(a.flags, a.gen0 + nb + 1, a.status);
+  for (int k = nb - 2; k >= 0; --k) {
+    const double *xn = a.x + (size_t)(k + 1) * m;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) vl[i] = ld_agent(xn + i);
+    __syncthreads();
+    const double acc = row_dot();
+    if (k > 0) load_row(a.N + (k - 1) * mm);
+    if (has_row && lane == 0) st_agent(a.x + (size_t)k * m + row, ld_agent(a.v + (size_t)k * m + row) - acc);
+    store_done();
+    if (k > 0) grid_barrier(a.flags, a.gen0 + nb + 1 + (nb - 1 - k), a.status);
   }
 }
 
@@ -490,22 +483,32 @@ void launch_sweep_inverse(int m, double *W, double *tmp, int *status, hipStream_
   k_negate<<<nblk(n), kBS, 0, s>>>(W, n);
 }
 
-int launch_coarse_solve(int m, int nb, const double *W, const double *C, const double *Ct, const int *nbt,
-                        const double *r, double *v, double *x, unsigned *flags, unsigned *gen, int *status,
-                        hipStream_t s) {
-  const int blocks = (m + 15) / 16;
-  CoarseArgs a{m, nb, W, C, Ct, r, nbt, v, x, flags, *gen, status};
+void launch_coarse_wc(int m, int mx, int my, const double *W, const double *C, double *out, hipStream_t s) {
+  const int64_t n = (int64_t)m * m;
+  k_coarse_wc<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(m, mx, my, W, C, out);
+}
+
+int coarse_blocks(int m) { return m <= 1024 ? (m + 3) / 4 : (m + 15) / 16; }
+
+int launch_coarse_solve(int m, int nb, const double *W, const double *M, const double *N, const double *r, double *u,
+                        double *v, double *x, unsigned *flags, unsigned *gen, int *status, hipStream_t s) {
+  const bool small = m <= 1024;
+  const int blocks = coarse_blocks(m);
+  CoarseArgs2 a{m, nb, W, M, N, r, u, v, x, flags, *gen, status};
   *gen += 2 * (unsigned)nb;
   void *args[] = {&a};
   const void *fn;
   const int mpl = (m + 63) / 64;
-  if (mpl <= 4) fn = (const void *)k_coarse_persistent<4>;
-  else if (mpl <= 8) fn = (const void *)k_coarse_persistent<8>;
-  else if (mpl <= 16) fn = (const void *)k_coarse_persistent<16>;
-  else if (mpl <= 32) fn = (const void *)k_coarse_persistent<32>;
-  else if (mpl <= 64) fn = (const void *)k_coarse_persistent<64>;
-  else return -1;
-  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(1024), args, sizeof(double) * m, s);
+  if (small) {
+    if (mpl <= 4) fn = (const void *)k_coarse_mn<4, 4>;
+    else if (mpl <= 8) fn = (const void *)k_coarse_mn<8, 4>;
+    else fn = (const void *)k_coarse_mn<16, 4>;
+  } else {
+    if (mpl <= 32) fn = (const void *)k_coarse_mn<32, 16>;
+    else if (mpl <= 64) fn = (const void *)k_coarse_mn<64, 16>;
+    else return -1;
+  }
+  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(small ? 256 : 1024), args, sizeof(double) * m, s);
   return e == hipSuccess ? 0 : -1;
 }
 

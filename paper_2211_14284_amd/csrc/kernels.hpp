@@ -149,11 +149,14 @@ void launch_sweep_inverse(int m, double *W, double *tmp, int *status, hipStream_
 // Whole block-tridiagonal solve (forward and backward sweeps over nb planes) in
 // one cooperative launch; bar: two zero-initialised unsigned counters owned by
 // the problem; returns 0 on a successful launch.
-// nbt: m*9 in-plane neighbour table (-1 = outside the plane); flags: 4 words per
-// block (zero-initialised once); *gen: host-side generation counter of the flags
-int launch_coarse_solve(int m, int nb, const double *W, const double *C, const double *Ct, const int *nbt,
-                        const double *r, double *v, double *x, unsigned *flags, unsigned *gen, int *status,
-                        hipStream_t s);
+// out = W Cs for the 9-point coupling Cs (m*9, see launch_coarse_solve)
+void launch_coarse_wc(int m, int mx, int my, const double *W, const double *C, double *out, hipStream_t s);
+// cooperative blocks of the coarse solve for plane size m (4 flag words each)
+int coarse_blocks(int m);
+// M: nb m*m blocks W_k C_k (k >= 1), N: W_k C_{k+1}^T (k <= nb-2); u: nb*m scratch;
+// flags: 4 words per block (zero-initialised once); *gen: host-side generation counter
+int launch_coarse_solve(int m, int nb, const double *W, const double *M, const double *N, const double *r, double *u,
+                        double *v, double *x, unsigned *flags, unsigned *gen, int *status, hipStream_t s);
 // gather / scatter between the coarse lattice and the free-box block vector
 void launch_coarse_gather(int nfree, int bx0, int by0, int bz0, int mx, int my, int NX, int NY,
                           const double *rc, double *blk, hipStream_t s);

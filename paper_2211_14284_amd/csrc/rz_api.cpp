@@ -82,9 +82,9 @@ struct rz_problem {
   // coarse
   int cm = 0, cmx = 0, cmy = 0, cmz = 0, cbx0 = 0, cby0 = 0, cbz0 = 0, cNX = 0, cNY = 0, cNZ = 0;
   double *cW = nullptr, *cC = nullptr, *cCt = nullptr, *cr = nullptr, *cv = nullptr, *cx = nullptr;
+  double *cM = nullptr, *cN = nullptr, *cu = nullptr;
   unsigned *cbar = nullptr;
   unsigned cgen = 0;
-  int *cnbt = nullptr;
   // krylov
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kAp = nullptr, *kro = nullptr;
   double *partials = nullptr, *dots = nullptr;
@@ -282,7 +282,7 @@ rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv) {
   const size_t mm = (size_t)m * m;
   launch_coarse_gather(m * nb, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cNX, h->cNY, rcv, h->cr, s);
   (void)mm;
-  if (launch_coarse_solve(m, nb, h->cW, h->cC, h->cCt, h->cnbt, h->cr, h->cv, h->cx, h->cbar, &h->cgen, h->status, s))
+  if (launch_coarse_solve(m, nb, h->cW, h->cM, h->cN, h->cr, h->cu, h->cv, h->cx, h->cbar, &h->cgen, h->status, s))
     return fail(h->ctx, RZ_ERR_HIP, "cooperative launch of the coarse solve failed");
   launch_coarse_scatter((int)h->ncoarse, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cmz, h->cNX, h->cNY,
                         h->cx, xcv, s);
@@ -622,15 +622,6 @@ rz_status setup_coarse(rz_problem *h) {
       }
   if ((e = upload(h, &h->cC, C))) return e;
   if ((e = upload(h, &h->cCt, Ct))) return e;
-  {
-    std::vector<int> nbt((size_t)m * 9, -1);
-    for (int a_ = 0; a_ < m; ++a_)
-      for (int j = 0; j < 9; ++j) {
-        int bx = a_ % h->cmx + j % 3 - 1, by = a_ / h->cmx + j / 3 - 1;
-        if (bx >= 0 && bx < h->cmx && by >= 0 && by < h->cmy) nbt[(size_t)a_ * 9 + j] = bx + h->cmx * by;
-      }
-    if ((e = upload(h, &h->cnbt, nbt))) return e;
-  }
   double *Akk = nullptr, *tmp = nullptr;
   if ((e = dalloc(h, &Akk, (size_t)m * m))) return e;
   if ((e = dalloc(h, &tmp, (size_t)m * m))) return e;
@@ -658,10 +649,19 @@ rz_status setup_coarse(rz_problem *h) {
   int stv = 0;
   HIPCALL(h, hipMemcpy(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost));
   if (stv) return fail(h->ctx, RZ_ERR_SINGULAR, "coarse factorisation: non-positive pivot");
+  // coupling products for the solve: M_k = W_k C_k, N_k = W_k C_{k+1}^T
+  if ((e = dalloc(h, &h->cM, (size_t)nb * m * m)) || (e = dalloc(h, &h->cN, (size_t)nb * m * m))) return e;
+  for (int k = 0; k < nb; ++k) {
+    const double *Wk = h->cW + (size_t)k * m * m;
+    if (k > 0) launch_coarse_wc(m, h->cmx, h->cmy, Wk, h->cC + (size_t)k * m * 9, h->cM + (size_t)k * m * m, s);
+    if (k + 1 < nb)
+      launch_coarse_wc(m, h->cmx, h->cmy, Wk, h->cCt + (size_t)k * m * 9, h->cN + (size_t)k * m * m, s);
+  }
+  if ((e = dalloc(h, &h->cu, nfree))) return e;
   if ((e = dalloc(h, &h->cr, nfree))) return e;
   if ((e = dalloc(h, &h->cv, nfree))) return e;
   if ((e = dalloc(h, &h->cx, nfree))) return e;
-  const size_t nflags = 4 * (size_t)((m + 15) / 16);
+  const size_t nflags = 4 * (size_t)coarse_blocks(m);
   if ((e = dalloc(h, &h->cbar, nflags))) return e;
   HIPCALL(h, hipMemsetAsync(h->cbar, 0, nflags * sizeof(unsigned), s));
   HIPCALL(h, hipStreamSynchronize(s));
