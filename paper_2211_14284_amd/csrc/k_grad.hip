@@ -24,6 +24,12 @@ __device__ __forceinline__ bool lat_dirichlet(const LatDev &L, int X, int Y, int
          ((L.dir & 16u) && Z == 0) || ((L.dir & 32u) && Z == L.Nz - 1);
 }
 
+// Dirichlet test of one lattice coordinate along axis a (0: x, 1: y, 2: z)
+__device__ __forceinline__ bool lat_dirichlet_axis(const LatDev &L, int a, int v) {
+  const int N = a == 0 ? L.Nx : (a == 1 ? L.Ny : L.Nz);
+  return ((L.dir & (1u << (2 * a))) && v == 0) || ((L.dir & (2u << (2 * a))) && v == N - 1);
+}
+
 __device__ __forceinline__ long lat_index(const LatDev &L, int X, int Y, int Z) {
   return (long)X + (long)L.Nx * ((long)Y + (long)L.Ny * (long)Z);
 }
@@ -36,12 +42,18 @@ __device__ __forceinline__ int ncells_axis(const LatDev &L, int a) {
 // y = A x: per cell, y_K = s1 (A x B x B) + s2 (B x A x B) + s3 (B x B x A) + mu (B x B x B)
 // (eq. sum-factorization with the exact 1-D integrals of an axis-aligned cell),
 // applied as per-axis contractions.  In the FDM basis B is diagonal plus the (0,p)
-// pair and A an arrowhead, so each 1-D factor costs O(p) per line.  Compile-time
-// degree P: one thread per tensor line of a cell, lines exchanged through LDS
-// (x to z, z to y, y to x); tiles are loaded and stored with lanes running along x
-// across the block's x-adjacent cells.  The 1-D tables travel in the kernel
-// arguments (scalar registers).  Cell-interior rows are owned by the cell (plain
-// store); interface rows go to a per-cell buffer summed by k_apply_gather.
+// pair and A an arrowhead, so each 1-D factor costs O(p) per line.
+//
+// Pencil decomposition: one block per x-row of cells (fixed cell indices ey, ez),
+// walked in chunks of CPC cells.  Per chunk: one thread per tensor line of a cell,
+// lines exchanged through LDS (x to z, z to y, y to x).  The x-faces shared by two
+// cells of the row are summed in the block (the last cell's x = P face carries to
+// the next chunk), so every lattice row (Y, Z) strictly inside the row's y-z cross
+// section is complete when stored and goes to y directly, coalesced along x.  The
+// 4p rows of the cross section on its y- or z-faces go to a face-line buffer, one
+// x-line per (row of cells, face row), summed by k_apply_faces.  The next chunk's
+// x tile is loaded into registers while the current chunk computes.  With bsub
+// given the kernels store bsub - A x instead (the residual of the V-cycle).
 // ------------------------------------------------------------------------------------
 template <int P, typename T>
 struct Tab1D {
@@ -73,98 +85,176 @@ __device__ __forceinline__ void stiff_line(const Tab1D<P, T> &t, const T *in, T 
   out[P] = aP;
 }
 
-template <int P, typename T, int CPB>
-__global__ void __launch_bounds__(CPB *(P + 1) * (P + 1))
-    k_apply_kron(LatDev L, Tab1D<P, T> tb, const T *__restrict__ coef, const T *__restrict__ x, T *__restrict__ y,
-                 T *__restrict__ ebuf, int ncells) {
-  constexpr int N1 = P + 1, NL = N1 * N1, N3 = NL * N1;
-  __shared__ T S0[CPB * N3], S1[CPB * N3];
-  const int lc = threadIdx.x / NL, l = threadIdx.x % NL;
-  const int cell = blockIdx.x * CPB + lc;
-  const bool active = cell < ncells;
+// face-row index of (b, c) in a cell's y-z cross section (b or c on {0, P})
+template <int P>
+__device__ __forceinline__ int face_row(int b, int c) {
+  return c == 0 ? b : (c == P ? P + 1 + b : 2 * (P + 1) + 2 * (c - 1) + (b == P));
+}
+
+template <int P, typename T, int CPC>
+__global__ void __launch_bounds__(CPC *(P + 1) * (P + 1), 4)
+    k_apply_pencil(LatDev L, Tab1D<P, T> tb, const T *__restrict__ coef, const T *__restrict__ x,
+                   const T *__restrict__ bsub, T *__restrict__ y, T *__restrict__ fb) {
+  constexpr int N1 = P + 1, NL = N1 * N1, N3 = NL * N1, NT = CPC * NL, W = CPC * P + 1;
+  __shared__ T S0[CPC * N3], S1[CPC * N3], CR[2][NL];
+  const int tid = threadIdx.x, lc = tid / NL, l = tid % NL;
+  const int ey = blockIdx.x % L.ny, ez = blockIdx.x / L.ny;
+  const int nch = (L.nx + CPC - 1) / CPC;
   T *s0 = S0 + lc * N3, *s1 = S1 + lc * N3;
-  T s1c = 0, s2c = 0, s3c = 0, mu = 0;
-  if (active) {
-    s1c = coef[6 * cell];
-    s2c = coef[6 * cell + 1];
-    s3c = coef[6 * cell + 2];
-    mu = coef[6 * cell + 3];
-  }
-  T r0[N1], r1[N1], r2[N1];
-  // the block's CPB cells are consecutive along x: load their tiles with lanes
-  // running along x across the cells (a fastest, then cell, then b, c)
-  const long cell0 = (long)blockIdx.x * CPB;
-  for (int k = threadIdx.x; k < CPB * N3; k += CPB * NL) {
-    const int a = k % N1, lk = (k / N1) % CPB, bc = k / (N1 * CPB), b = bc % N1, cq = bc / N1;
-    const long ce = cell0 + lk;
-    T v = 0;
-    if (ce < ncells) {
-      const int ex = ce % L.nx, ey = (ce / L.nx) % L.ny, ez = ce / ((long)L.nx * L.ny);
-      const int X = ex * P + a, Y = ey * P + b, Z = ez * P + cq;
-      if (!lat_dirichlet(L, X, Y, Z)) v = x[lat_index(L, X, Y, Z)];
+  // x tile of chunk j: thread tid loads the z-column (a, lk, b) of the chunk's cells,
+  // a = tid % N1, lk = (tid / N1) % CPC, b = tid / (N1 CPC), c = 0..P (lanes along x);
+  // the loads stay in flight until the values go to LDS at the top of the next chunk
+  const int la = tid % N1, llk = (tid / N1) % CPC, lb = tid / (N1 * CPC);
+  const int Yl = ey * P + lb;
+  const long zst = (long)L.Nx * L.Ny;
+  unsigned zmask = 0;  // bit c: the point at Z = ez P + c is not on a Dirichlet z-face
+#pragma unroll
+  for (int i = 0; i < N1; ++i) zmask |= (unsigned)!lat_dirichlet_axis(L, 2, ez * P + i) << i;
+  if (lat_dirichlet_axis(L, 1, Yl)) zmask = 0;
+  T xv[N1];
+  unsigned okm = 0;  // bit c: xv[c] is a free DoF of the chunk (else it counts as 0)
+  auto load = [&](int j) {
+    const int X = (j * CPC + llk) * P + la;
+    const bool okx = j * CPC + llk < L.nx && !lat_dirichlet_axis(L, 0, X);
+    okm = okx ? zmask : 0u;
+    // always in bounds (x clamped to the lattice); masked values are never used
+    const T *xc = x + lat_index(L, min(X, L.Nx - 1), Yl, ez * P);
+#pragma unroll
+    for (int i = 0; i < N1; ++i) xv[i] = xc[i * zst];
+  };
+  load(0);
+  T *sx = S0 + llk * N3 + la + N1 * lb;
+  for (int j = 0; j < nch; ++j) {
+    const int nc = min(CPC, L.nx - j * CPC);
+#pragma unroll
+    for (int i = 0; i < N1; ++i) sx[NL * i] = ((okm >> i) & 1u) ? xv[i] : T(0);
+    // this chunk's weights first: the compute waits on them, not on the prefetch
+    const long cell = (j * CPC + min(lc, nc - 1)) + (long)L.nx * (ey + (long)L.ny * ez);
+    const T s1c = coef[6 * cell], s2c = coef[6 * cell + 1], s3c = coef[6 * cell + 2], mu = coef[6 * cell + 3];
+    load(min(j + 1, nch - 1));  // unconditional, so no branch merges the wait counts
+    T r0[N1], r1[N1], r2[N1];
+    __syncthreads();
+    {  // z-line (a, b): t1 = B_z x, v = A_z x
+#pragma unroll
+      for (int c = 0; c <= P; ++c) r0[c] = s0[l + NL * c];
+      mass_line<P, T>(tb, r0, r1);
+      stiff_line<P, T>(tb, r0, r2);
     }
-    S0[lk * N3 + a + N1 * b + NL * cq] = v;
-  }
-  __syncthreads();
-  {  // z-line (a, b): t1 = B_z x, v = A_z x
-#pragma unroll
-    for (int c = 0; c <= P; ++c) r0[c] = s0[l + NL * c];
-    mass_line<P, T>(tb, r0, r1);
-    stiff_line<P, T>(tb, r0, r2);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c <= P; ++c) {
-    s0[l + NL * c] = r1[c];
-    s1[l + NL * c] = r2[c];
-  }
-  __syncthreads();
-  {  // y-line (a, c): u = B_y t1, w = mu u + s2 A_y t1 + s3 B_y v
-    const int a = l % N1, c = l / N1;
-#pragma unroll
-    for (int b = 0; b <= P; ++b) {
-      r0[b] = s0[a + N1 * b + NL * c];
-      r1[b] = s1[a + N1 * b + NL * c];
-    }
-    T u[N1], t[N1];
-    mass_line<P, T>(tb, r0, u);
-    stiff_line<P, T>(tb, r0, t);
-    mass_line<P, T>(tb, r1, r2);
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b <= P; ++b) {
-      s0[a + N1 * b + NL * c] = u[b];
-      s1[a + N1 * b + NL * c] = mu * u[b] + s2c * t[b] + s3c * r2[b];
+    for (int c = 0; c <= P; ++c) {
+      s0[l + NL * c] = r1[c];
+      s1[l + NL * c] = r2[c];
     }
-  }
-  __syncthreads();
-  {  // x-line (b, c): y = s1 A_x u + B_x w
-    const int b = l % N1, c = l / N1;
-#pragma unroll
-    for (int a = 0; a <= P; ++a) {
-      r0[a] = s0[a + N1 * b + NL * c];
-      r1[a] = s1[a + N1 * b + NL * c];
-    }
-    stiff_line<P, T>(tb, r0, r2);
-    mass_line<P, T>(tb, r1, r0);
     __syncthreads();
+    {  // y-line (a, c): u = B_y t1, w = mu u + s2 A_y t1 + s3 B_y v
+      const int a = l % N1, c = l / N1;
 #pragma unroll
-    for (int a = 0; a <= P; ++a) s0[a + N1 * b + NL * c] = s1c * r2[a] + r0[a];
+      for (int b = 0; b <= P; ++b) {
+        r0[b] = s0[a + N1 * b + NL * c];
+        r1[b] = s1[a + N1 * b + NL * c];
+      }
+      T u[N1], t[N1];
+      mass_line<P, T>(tb, r0, u);
+      stiff_line<P, T>(tb, r0, t);
+      mass_line<P, T>(tb, r1, r2);
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b <= P; ++b) {
+        s0[a + N1 * b + NL * c] = u[b];
+        s1[a + N1 * b + NL * c] = mu * u[b] + s2c * t[b] + s3c * r2[b];
+      }
+    }
+    __syncthreads();
+    {  // x-line (b, c): y = s1 A_x u + B_x w
+      const int b = l % N1, c = l / N1;
+#pragma unroll
+      for (int a = 0; a <= P; ++a) {
+        r0[a] = s0[a + N1 * b + NL * c];
+        r1[a] = s1[a + N1 * b + NL * c];
+      }
+      stiff_line<P, T>(tb, r0, r2);
+      mass_line<P, T>(tb, r1, r0);
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a <= P; ++a) s0[a + N1 * b + NL * c] = s1c * r2[a] + r0[a];
+    }
+    __syncthreads();
+    // rows of the chunk, lanes along x: point xo of row (b, c) is local a = xo % P of
+    // cell xo / P plus, at a = 0, the x = P face of the cell before it
+    const bool last = j + 1 == nch;
+    for (int k = tid; k < NL * W; k += NT) {
+      const int xo = k % W, row = k / W;
+      T val;
+      if (xo < nc * P) {
+        const int lk = xo / P, a = xo % P;
+        val = S0[lk * N3 + a + N1 * row];
+        if (a == 0) val += lk > 0 ? S0[(lk - 1) * N3 + P + N1 * row] : (j > 0 ? CR[(j - 1) & 1][row] : T(0));
+      } else if (last && xo == nc * P) {
+        val = S0[(nc - 1) * N3 + P + N1 * row];
+      } else {
+        continue;
+      }
+      const int X = j * CPC * P + xo, b = row % N1, c = row / N1;
+      if (b > 0 && b < P && c > 0 && c < P) {
+        const long g = lat_index(L, X, ey * P + b, ez * P + c);
+        if (lat_dirichlet(L, X, ey * P + b, ez * P + c)) val = x[g];
+        y[g] = bsub ? bsub[g] - val : val;
+      } else {
+        fb[((long)blockIdx.x * 4 * P + face_row<P>(b, c)) * L.Nx + X] = val;
+      }
+    }
+    if (tid < NL) CR[j & 1][tid] = S0[(nc - 1) * N3 + P + N1 * tid];
+    __syncthreads();
   }
-  __syncthreads();
-  // cell-interior rows to y, interface rows to the per-cell buffer, lanes along x
-  for (int k = threadIdx.x; k < CPB * N3; k += CPB * NL) {
-    const int a = k % N1, lk = (k / N1) % CPB, bc = k / (N1 * CPB), b = bc % N1, cq = bc / N1;
-    const long ce = cell0 + lk;
-    if (ce >= ncells) continue;
-    const T val = S0[lk * N3 + a + N1 * b + NL * cq];
-    if (a != 0 && a != P && b != 0 && b != P && cq != 0 && cq != P) {
-      const int ex = ce % L.nx, ey = (ce / L.nx) % L.ny, ez = ce / ((long)L.nx * L.ny);
-      y[lat_index(L, ex * P + a, ey * P + b, ez * P + cq)] = val;
+}
+
+// Lattice rows (Y, Z) on a y- or z-vertex plane: the sum of the face-line buffer
+// rows of the (up to 4) rows of cells that hold them, in a fixed order (cell z, then
+// y, lower first); Dirichlet points take x.  Lines enumerated as: Y on a vertex
+// plane (any Z), then Z on a vertex plane with Y off them.
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_apply_faces(LatDev L, const T *__restrict__ x, const T *__restrict__ fb,
+                                                     const T *__restrict__ bsub, T *__restrict__ y, long n) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int X = g % L.Nx;
+  const long line = g / L.Nx, n1 = (long)(L.ny + 1) * L.Nz;
+  int Y, Z;
+  if (line < n1) {
+    Y = (int)(line / L.Nz) * P;
+    Z = line % L.Nz;
+  } else if constexpr (P > 1) {
+    const long m = line - n1, off = L.Ny - L.ny - 1;
+    Z = (int)(m / off) * P;
+    const int yn = m % off;
+    Y = (yn / (P - 1)) * P + 1 + yn % (P - 1);
+  } else {
+    return;  // P = 1: every lattice row lies on a y-vertex plane
+  }
+  const long gi = lat_index(L, X, Y, Z);
+  T val = 0;
+  if (lat_dirichlet(L, X, Y, Z)) {
+    val = x[gi];
+  } else {
+    int cy[2], by[2], ny = 0, cz[2], bz[2], nz = 0;
+    if (Y % P == 0) {
+      if (Y / P > 0) { cy[ny] = Y / P - 1; by[ny++] = P; }
+      if (Y / P < L.ny) { cy[ny] = Y / P; by[ny++] = 0; }
     } else {
-      ebuf[ce * N3 + a + N1 * b + NL * cq] = val;
+      cy[0] = Y / P; by[0] = Y % P; ny = 1;
     }
+    if (Z % P == 0) {
+      if (Z / P > 0) { cz[nz] = Z / P - 1; bz[nz++] = P; }
+      if (Z / P < L.nz) { cz[nz] = Z / P; bz[nz++] = 0; }
+    } else {
+      cz[0] = Z / P; bz[0] = Z % P; nz = 1;
+    }
+    for (int k = 0; k < nz; ++k)
+      for (int i = 0; i < ny; ++i)
+        val += fb[(((long)cy[i] + (long)L.ny * cz[k]) * 4 * P + face_row<P>(by[i], bz[k])) * L.Nx + X];
   }
+  y[gi] = bsub ? bsub[gi] - val : val;
 }
 
 // Interface rows of y: sum of the contributions of the (up to 8) cells that hold the
@@ -721,37 +811,42 @@ inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 // ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
+#define RZ_DISPATCH_P(p, call) \
+  switch (p) {                 \
+    case 1: call(1); break;    \
+    case 2: call(2); break;    \
+    case 3: call(3); break;    \
+    case 4: call(4); break;    \
+    case 5: call(5); break;    \
+    case 6: call(6); break;    \
+    case 7: call(7); break;    \
+    case 8: call(8); break;    \
+    case 9: call(9); break;    \
+    default: break;            \
+  }
+
 template <int P, typename T>
-static void apply_kron(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x, T *y,
-                       T *ebuf, hipStream_t s) {
+static void apply_pencil(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x,
+                         const T *bsub, T *y, T *fb, hipStream_t s) {
   constexpr int NL = (P + 1) * (P + 1);
-  constexpr int CPB = NL >= 256 ? 1 : 256 / NL;
+  constexpr int CPC = NL >= 256 ? 1 : 256 / NL;
   Tab1D<P, T> tb;
   for (int i = 0; i < (P + 1) * (P + 1); ++i) {
     tb.B[i] = (T)Bh[i];
     tb.A[i] = (T)Ah[i];
   }
-  const int ncells = L.nx * L.ny * L.nz;
-  const unsigned grid = (unsigned)((ncells + CPB - 1) / CPB);
-  k_apply_kron<P, T, CPB><<<grid, CPB * NL, 0, s>>>(L, tb, coef, x, y, ebuf, ncells);
+  k_apply_pencil<P, T, CPC><<<(unsigned)(L.ny * L.nz), CPC * NL, 0, s>>>(L, tb, coef, x, bsub, y, fb);
+  const long nlines = (long)(L.ny + 1) * L.Nz + (long)(L.nz + 1) * (L.Ny - L.ny - 1);
+  const long n = nlines * L.Nx;
+  k_apply_faces<P, T><<<nblocks(n, 256), 256, 0, s>>>(L, x, fb, bsub, y, n);
 }
 
 template <typename T>
-void launch_apply_grad(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x, T *y,
-                       T *ebuf, hipStream_t s) {
-  switch (L.p) {
-    case 1: apply_kron<1, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
-    case 2: apply_kron<2, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
-    case 3: apply_kron<3, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
-    case 4: apply_kron<4, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
-    case 5: apply_kron<5, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
-    case 6: apply_kron<6, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
-    case 7: apply_kron<7, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
-    case 8: apply_kron<8, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
-    case 9: apply_kron<9, T>(L, coef, Bh, Ah, x, y, ebuf, s); break;
-    default: break;
-  }
-  launch_apply_gather<T>(L, x, ebuf, y, s);
+void launch_apply_grad(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x,
+                       const T *bsub, T *y, T *fbuf, hipStream_t s) {
+#define RZ_CALL(Q) apply_pencil<Q, T>(L, coef, Bh, Ah, x, bsub, y, fbuf, s)
+  RZ_DISPATCH_P(L.p, RZ_CALL)
+#undef RZ_CALL
 }
 
 template <typename T>
@@ -783,20 +878,6 @@ static void expand_p(const LatDev &L, const T *coef, const T *A, const T *lam, c
   const long ni = (long)L.nx * L.ny * L.nz * (P - 1) * (P - 1) * (P - 1);
   if (ni > 0) k_expand_interior<P, T><<<nblocks(ni, 256), 256, 0, s>>>(L, coef, A, lam, r, z, ni);
 }
-
-#define RZ_DISPATCH_P(p, call) \
-  switch (p) {                 \
-    case 1: call(1); break;    \
-    case 2: call(2); break;    \
-    case 3: call(3); break;    \
-    case 4: call(4); break;    \
-    case 5: call(5); break;    \
-    case 6: call(6); break;    \
-    case 7: call(7); break;    \
-    case 8: call(8); break;    \
-    case 9: call(9); break;    \
-    default: break;            \
-  }
 
 template <typename T>
 void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *fc, T *rt,
@@ -883,9 +964,9 @@ void launch_restrict_grad(const LatDev &L, const double *E, const double *rf, do
 }
 
 template void launch_apply_grad<double>(const LatDev &, const double *, const double *, const double *,
-                                        const double *, double *, double *, hipStream_t);
+                                        const double *, const double *, double *, double *, hipStream_t);
 template void launch_apply_grad<float>(const LatDev &, const float *, const double *, const double *,
-                                       const float *, float *, float *, hipStream_t);
+                                       const float *, const float *, float *, float *, hipStream_t);
 template void launch_apply_gather<double>(const LatDev &, const double *, const double *, double *, hipStream_t);
 template void launch_apply_gather<float>(const LatDev &, const float *, const float *, float *, hipStream_t);
 template void launch_condense_grad<double>(const LatDev &, const double *, const double *, const double *,

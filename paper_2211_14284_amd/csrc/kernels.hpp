@@ -92,10 +92,11 @@ void launch_cg_update_f(float a, const float *p, const float *Ap, float *x, floa
 
 // ---- H(grad) operator and relaxation ----------------------------------------------
 // Bh, Ah: host copies of the 1-D FDM mass and stiffness ((p+1)^2, row-major);
-// ebuf: per-cell scratch of ncells*(p+1)^3 values for the interface contributions
+// y = A x, or y = bsub - A x when bsub is not null (y must not alias x or bsub);
+// fbuf: scratch of ny*nz*4p*Nx values (the face-line buffer)
 template <typename T>
-void launch_apply_grad(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x, T *y,
-                       T *ebuf, hipStream_t s);
+void launch_apply_grad(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x,
+                       const T *bsub, T *y, T *fbuf, hipStream_t s);
 // fc: scratch of 6 (p-1)^2 values per cell (the per-cell face contributions)
 template <typename T>
 void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *fc,

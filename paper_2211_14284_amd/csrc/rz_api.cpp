@@ -228,8 +228,22 @@ rz_status do_apply64(rz_problem *h, const double *x, double *y) {
     launch_apply_quad_cells<double>(h->L, h->Q64, x, y, h->eb64, h->ctx->stream);
     launch_apply_gather<double>(h->L, x, h->eb64, y, h->ctx->stream);
   } else {
-    launch_apply_grad<double>(h->L, h->coef64, h->t.B.data(), h->t.A.data(), x, y, h->eb64, h->ctx->stream);
+    launch_apply_grad<double>(h->L, h->coef64, h->t.B.data(), h->t.A.data(), x, nullptr, y, h->eb64,
+                              h->ctx->stream);
   }
+  return RZ_OK;
+}
+
+// out = b - A x (fused into the apply's stores for the sum-factorised H(grad) operator)
+rz_status do_residual64(rz_problem *h, const double *b, const double *x, double *out) {
+  if (h->space == RZ_GRAD && !h->quad) {
+    Timed t(h, RZ_K_APPLY);
+    launch_apply_grad<double>(h->L, h->coef64, h->t.B.data(), h->t.A.data(), x, b, out, h->eb64, h->ctx->stream);
+    return RZ_OK;
+  }
+  rz_status e = do_apply64(h, x, h->vaz);
+  if (e) return e;
+  v_sub(h, b, h->vaz, out);
   return RZ_OK;
 }
 
@@ -295,8 +309,7 @@ rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
   const double w = h->omega;
   do_relax_prec(h, r, h->vt);
   v_scale_copy(h, w, h->vt, z);            // z = w M r
-  do_apply64(h, z, h->vaz);
-  v_sub(h, r, h->vaz, h->vr);              // r1 = r - A z
+  do_residual64(h, r, z, h->vr);           // r1 = r - A z
   {
     Timed tm(h, RZ_K_TRANSFER);
     launch_restrict_grad(h->L, h->E64, h->vr, h->rc, h->rt1, h->rt2, s);
@@ -306,8 +319,7 @@ rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
     Timed tm(h, RZ_K_TRANSFER);
     launch_prolong_add_grad(h->L, h->E64, h->xc, z, s);   // z += P A0^{-1} P^T r1
   }
-  do_apply64(h, z, h->vaz);
-  v_sub(h, r, h->vaz, h->vr);              // r2 = r - A z
+  do_residual64(h, r, z, h->vr);           // r2 = r - A z
   do_relax_prec(h, h->vr, h->vt);
   v_axpy(h, w, h->vt, z);                  // z += w M r2
   launch_dirichlet_copy(h->L, r, z, s);
@@ -324,8 +336,20 @@ rz_status do_apply32(rz_problem *h, const float *x, float *y) {
     launch_apply_quad_cells<float>(h->L, h->Q32, x, y, h->eb32, s);
     launch_apply_gather<float>(h->L, x, h->eb32, y, s);
   } else {
-    launch_apply_grad<float>(h->L, h->coef32, h->t.B.data(), h->t.A.data(), x, y, h->eb32, s);
+    launch_apply_grad<float>(h->L, h->coef32, h->t.B.data(), h->t.A.data(), x, nullptr, y, h->eb32, s);
   }
+  return RZ_OK;
+}
+
+rz_status do_residual32(rz_problem *h, const float *b, const float *x, float *out) {
+  if (h->space == RZ_GRAD && !h->quad) {
+    Timed t(h, RZ_K_APPLY);
+    launch_apply_grad<float>(h->L, h->coef32, h->t.B.data(), h->t.A.data(), x, b, out, h->eb32, h->ctx->stream);
+    return RZ_OK;
+  }
+  rz_status e = do_apply32(h, x, h->az32);
+  if (e) return e;
+  launch_sub_f(b, h->az32, out, h->ndofs, h->ctx->stream);
   return RZ_OK;
 }
 
@@ -337,8 +361,7 @@ rz_status do_vcycle32(rz_problem *h, const float *r, float *z) {
   const float w = (float)h->omega;
   do_relax32(h, r, h->t32);
   launch_scale_copy_f(w, h->t32, z, n, s);      // z = w M r
-  do_apply32(h, z, h->az32);
-  launch_sub_f(r, h->az32, h->vr32, n, s);       // r1 = r - A z
+  do_residual32(h, r, z, h->vr32);              // r1 = r - A z
   launch_cast_f2d(h->vr32, h->vr, n, s);
   {
     Timed tm(h, RZ_K_TRANSFER);
@@ -352,8 +375,7 @@ rz_status do_vcycle32(rz_problem *h, const float *r, float *z) {
     launch_prolong_add_grad(h->L, h->E64, h->xc, h->vt, s);
   }
   launch_add_d2f(h->vt, z, n, s);                // z += P A0^{-1} P^T r1
-  do_apply32(h, z, h->az32);
-  launch_sub_f(r, h->az32, h->vr32, n, s);       // r2 = r - A z
+  do_residual32(h, r, z, h->vr32);              // r2 = r - A z
   do_relax32(h, h->vr32, h->t32);
   launch_axpy_f(w, h->t32, z, n, s);             // z += w M r2
   launch_dirichlet_copy_f(h->L, r, z, s);
@@ -407,8 +429,7 @@ rz_status defect_solve(rz_problem *h, const double *b, double *x, rz_solve_info 
   double rr = bb;
   for (int outer = 0; outer < 64; ++outer) {
     if (outer > 0) {  // true residual of the current iterate
-      do_apply64(h, x, h->vaz);
-      v_sub(h, b, h->vaz, h->kr);
+      do_residual64(h, b, x, h->kr);
       launch_dirichlet_copy(h->L, nullptr, h->kr, s);
       const double *xs[1] = {h->kr};
       if ((e = dots_host(h, 1, xs, xs, &rr))) return e;
@@ -825,8 +846,7 @@ rz_status pcg_dots(PcgRun &R, int np, const double *const *xs, const double *con
 
 rz_status pcg_final(PcgRun &R) {
   rz_problem *h = R.h;
-  do_apply64(h, R.x, h->vaz);
-  v_sub(h, R.b, h->vaz, h->vr);
+  do_residual64(h, R.b, R.x, h->vr);
   launch_dirichlet_copy(h->L, nullptr, h->vr, h->ctx->stream);
   const double *xs[1] = {h->vr};
   R.phase = PcgRun::GOT_FINAL;
@@ -908,8 +928,7 @@ rz_status pcg_step(PcgRun &R) {
     }
     case PcgRun::GOT_RR: {
       if (std::sqrt(d[0]) <= R.tol) {  // recurrence converged: check the true residual
-        do_apply64(h, R.x, h->vaz);
-        v_sub(h, R.b, h->vaz, h->vr);
+        do_residual64(h, R.b, R.x, h->vr);
         launch_dirichlet_copy(h->L, nullptr, h->vr, s);
         const double *xs[1] = {h->vr};
         R.phase = PcgRun::GOT_TR;
