@@ -421,17 +421,55 @@ __global__ void __launch_bounds__(256) k_condense_plane(LatDev L, int a, const T
 // One wavefront per slot, no block barriers: the passes of the wavefront schedule
 // (levels of the forward sweep, then of the backward sweep) run in program order
 // on the slot's vector in LDS, which only this wavefront touches.  The factor
-// values stream in ELL order, the next pass's values loaded while the current
-// pass computes.  The block shares the schedule's index tables in LDS.
+// values stream in ELL order; the block shares the schedule's index tables in LDS.
+// Two variants, chosen by measurement: FP32 streams the values into two register
+// buffers used in turn (pass t + 1 loads while pass t computes); FP64 keeps one
+// buffer loaded at the top of each pass, which measured faster for 8-byte values.
 // ------------------------------------------------------------------------------------
+// sum over the K steps of one lane in a pass of buf[s] * x[col(s)], K uniform: one
+// straight-line body per K so that the LDS reads batch without per-step branches
+template <int KM, typename T, int K = KM>
+__device__ __forceinline__ T pass_dot(int k, const T (&buf)[KM], const unsigned short *ec, const T *xw) {
+  if (k == K) {
+    int ix[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) ix[s] = ec[64 * s];
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < K; ++s) acc += buf[s] * xw[ix[s]];
+    return acc;
+  }
+  if constexpr (K > 1) {
+    return pass_dot<KM, T, K - 1>(k, buf, ec, xw);
+  } else {
+    return T(0);
+  }
+}
+
+// raw buffer loads (offsets in bytes; out-of-range offsets read 0)
+template <typename T>
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return __builtin_bit_cast(double, v);
+}
+template <>
+__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
 template <typename T>
 __device__ __forceinline__ T group_sum(T s, int G) {
   for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   return s;
 }
 
+// Single-buffer variant (FP64): the next pass's values are loaded at the top of
+// each pass, steps only up to K.
 template <typename T>
-__global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E, const T *__restrict__ factor,
+__global__ void __launch_bounds__(1024) k_patch_solve_s(LatDev L, PatchEllDev E, const T *__restrict__ factor,
                                                          const T *__restrict__ rt, T *__restrict__ zbuf,
                                                          long nslots) {
   constexpr int KM = 8;  // at most kMaxSteps steps per pass
@@ -481,6 +519,72 @@ __global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E,
       if ((lane & (G - 1)) == 0 && row != 0xFFFFu) xw[row] = (xw[row] - acc) / dw[row];
 #pragma unroll
       for (int s = 0; s < KM; ++s) cur[s] = nxt[s];
+    }
+    T *zo = zbuf + sl * (long)nrows;
+    for (int i = lane; i < nrows; i += 64) zo[i] = xw[i];
+  }
+}
+
+template <typename T, int KM>
+__global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E, const T *__restrict__ factor,
+                                                         const T *__restrict__ rt, T *__restrict__ zbuf,
+                                                         long nslots) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nrows = E.nrows, ne = E.ne, np = E.npass, p = L.p;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  T *xw = reinterpret_cast<T *>(smem_raw) + (size_t)w * 2 * nrows;  // this wavefront's vector
+  T *dw = xw + nrows;                                                  // and diagonal
+  int *off = reinterpret_cast<int *>(reinterpret_cast<T *>(smem_raw) + (size_t)nw * 2 * nrows);
+  unsigned short *ecol = reinterpret_cast<unsigned short *>(off + nrows);
+  unsigned short *erow = ecol + ne;
+  for (int i = tid; i < ne; i += blockDim.x) ecol[i] = (unsigned short)E.ecol[i];
+  for (int i = tid; i < np * 64; i += blockDim.x) erow[i] = (unsigned short)(E.erow[i] & 0xFFFF);
+  for (int i = tid; i < nrows; i += blockDim.x)
+    off[i] = (E.off[3 * i] + 64) | ((E.off[3 * i + 1] + 64) << 8) | ((E.off[3 * i + 2] + 64) << 16);
+  __syncthreads();
+  const int nvx = L.nx + 1, nvy = L.ny + 1;
+  // the wavefront index as a wave-uniform (scalar) value, so that slot addresses
+  // and the slot's buffer resource live in scalar registers
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  for (long sl = (long)blockIdx.x * nw + wu; sl < nslots; sl += (long)gridDim.x * nw) {
+    const T *f = factor + sl * (long)E.stride;
+    const int vx = sl % nvx, vy = (sl / nvx) % nvy, vz = sl / ((long)nvx * nvy);
+    for (int i = lane; i < nrows; i += 64) {
+      const int o = off[i];
+      const int X = vx * p + (o & 255) - 64, Y = vy * p + ((o >> 8) & 255) - 64, Z = vz * p + ((o >> 16) & 255) - 64;
+      const bool in = X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
+      xw[i] = (in && !lat_dirichlet(L, X, Y, Z)) ? rt[lat_index(L, X, Y, Z)] : T(0);
+      dw[i] = f[i];
+    }
+    // Factor values of pass t through a buffer resource spanning this slot: steps
+    // past K take an offset beyond the range, which reads 0 without a memory access,
+    // so the loads carry no branch and stay in flight across the other buffer's pass.
+    const __amdgpu_buffer_rsrc_t fr =
+        __builtin_amdgcn_make_buffer_rsrc((void *)f, (short)0, E.stride * (int)sizeof(T), 0x00020000);
+    auto load_pass = [&](T (&buf)[KM], int t) {
+      const int K = E.pass[3 * t + 1];
+      const unsigned o = (unsigned)(nrows + E.pass[3 * t + 2] + lane) * sizeof(T);
+#pragma unroll
+      for (int s = 0; s < KM; ++s) buf[s] = buffer_load<T>(fr, s < K ? o + 64 * s * sizeof(T) : 0x80000000u);
+    };
+    auto run_pass = [&](const T (&buf)[KM], int t) {
+      const int G = E.pass[3 * t], K = E.pass[3 * t + 1], base = E.pass[3 * t + 2];
+      T acc = 0;
+      if (K > 0) {
+        acc = pass_dot<KM, T>(K, buf, ecol + base + lane, xw);
+        acc = group_sum(acc, G);
+      }
+      const unsigned row = erow[64 * t + lane];
+      if ((lane & (G - 1)) == 0 && row != 0xFFFFu) xw[row] = (xw[row] - acc) / dw[row];
+    };
+    // two register buffers in turn: pass t computes while pass t + 1 loads
+    T ba[KM], bb[KM];
+    load_pass(ba, 0);
+    for (int t = 0; t < np; t += 2) {
+      load_pass(bb, min(t + 1, np - 1));
+      run_pass(ba, t);
+      load_pass(ba, min(t + 2, np - 1));
+      if (t + 1 < np) run_pass(bb, t + 1);
     }
     T *zo = zbuf + sl * (long)nrows;
     for (int i = lane; i < nrows; i += 64) zo[i] = xw[i];
@@ -711,36 +815,39 @@ __global__ void __launch_bounds__(256) k_patch_factor(LatDev L, PatchDev P, cons
 // p-transfer: the embedding of Q_1 in Q_p in FDM coefficients is the Kronecker
 // product of the (p+1)x2 hat matrix E per axis; restriction is its transpose.
 // ------------------------------------------------------------------------------------
-__global__ void k_prolong_add_grad(LatDev L, const double *__restrict__ E, const double *__restrict__ xc,
-                                   double *__restrict__ xf, long n) {
-  long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const int p = L.p;
-  int C[3] = {(int)(g % L.Nx), (int)((g / L.Nx) % L.Ny), (int)(g / ((long)L.Nx * L.Ny))};
-  if (lat_dirichlet(L, C[0], C[1], C[2])) return;
-  const int NC[3] = {L.nx + 1, L.ny + 1, L.nz + 1};
-  int c0[3];
-  double w[3][2];
+// One block row of 256 lanes along x per lattice row (Y, Z); the y and z weights
+// are uniform over the block.  Coarse Dirichlet vertices and fine Dirichlet rows
+// contribute nothing.
+template <int P>
+__global__ void __launch_bounds__(256) k_prolong_add_p(LatDev L, const double *__restrict__ E,
+                                                       const double *__restrict__ xc, double *__restrict__ xf,
+                                                       int nxb) {
+  const long row = blockIdx.x / nxb;
+  const int X = (blockIdx.x % nxb) * 256 + threadIdx.x;
+  if (X >= L.Nx) return;
+  const int Y = row % L.Ny, Z = row / L.Ny;
+  if (lat_dirichlet(L, X, Y, Z)) return;
+  int c[3];
+  double w0[3], w1[3];
+  bool m0[3], m1[3];
+  const int C[3] = {X, Y, Z}, n[3] = {L.nx, L.ny, L.nz};
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    int c = C[d] / p;
-    if (c >= NC[d] - 1) c = NC[d] - 2;
-    int a = C[d] - c * p;
-    c0[d] = c;
-    w[d][0] = E[2 * a];
-    w[d][1] = E[2 * a + 1];
+    c[d] = min(C[d] / P, n[d] - 1);
+    const int a = C[d] - c[d] * P;
+    w0[d] = E[2 * a];
+    w1[d] = E[2 * a + 1];
+    m0[d] = !((L.dir & (1u << (2 * d))) && c[d] == 0);
+    m1[d] = !((L.dir & (2u << (2 * d))) && c[d] + 1 == n[d]);
   }
-  double acc = 0.0;
-  for (int k = 0; k < 8; ++k) {
-    int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
-    double wt = w[0][kx] * w[1][ky] * w[2][kz];
-    if (wt == 0.0) continue;
-    int X = c0[0] + kx, Y = c0[1] + ky, Z = c0[2] + kz;
-    bool dir = ((L.dir & 1u) && X == 0) || ((L.dir & 2u) && X == NC[0] - 1) || ((L.dir & 4u) && Y == 0) ||
-               ((L.dir & 8u) && Y == NC[1] - 1) || ((L.dir & 16u) && Z == 0) || ((L.dir & 32u) && Z == NC[2] - 1);
-    if (dir) continue;
-    acc += wt * xc[X + (long)NC[0] * (Y + (long)NC[1] * Z)];
-  }
-  xf[g] += acc;
+  const long sy = L.nx + 1, sz = sy * (L.ny + 1);
+  const double *q = xc + c[0] + sy * c[1] + sz * c[2];
+  auto xline = [&](long o) {
+    return (m0[0] ? w0[0] * q[o] : 0.0) + (m1[0] ? w1[0] * q[o + 1] : 0.0);
+  };
+  const double a0 = (m0[1] ? w0[1] * xline(0) : 0.0) + (m1[1] ? w1[1] * xline(sy) : 0.0);
+  const double a1 = (m0[1] ? w0[1] * xline(sz) : 0.0) + (m1[1] ? w1[1] * xline(sz + sy) : 0.0);
+  xf[X + (long)L.Nx * row] += (m0[2] ? w0[2] * a0 : 0.0) + (m1[2] ? w1[2] * a1 : 0.0);
 }
 
 // Restriction rc = P^T rf as three 1-D passes (x, then y, then z); the weight of a
@@ -751,6 +858,37 @@ __device__ __forceinline__ double hat_weight(const double *E, int p, int off) {
   return off < 0 ? E[2 * (off + p) + 1] : (off > 0 ? E[2 * off] : 1.0);
 }
 
+// x pass: R lattice rows per block (64 lanes each), each row staged in LDS with
+// its Dirichlet entries zeroed, then one lane per coarse vertex sums its 2P - 1
+// fine neighbours (weights uniform over the lanes).
+template <int P>
+__global__ void __launch_bounds__(256) k_restrict_x_p(LatDev L, const double *__restrict__ E,
+                                                      const double *__restrict__ rf, double *__restrict__ t1,
+                                                      long nrows) {
+  extern __shared__ double srow[];
+  const int R = blockDim.x >> 6, r = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long row = (long)blockIdx.x * R + r;
+  const bool active = row < nrows;
+  const int Y = active ? row % L.Ny : 0, Z = active ? row / L.Ny : 0;
+  const bool rowdir = lat_dirichlet_axis(L, 1, Y) || lat_dirichlet_axis(L, 2, Z);
+  double *s = srow + (size_t)r * L.Nx;
+  for (int X = lane; X < L.Nx; X += 64)
+    s[X] = (active && !rowdir && !lat_dirichlet_axis(L, 0, X)) ? rf[X + (long)L.Nx * row] : 0.0;
+  __syncthreads();
+  if (!active) return;
+  for (int V = lane; V <= L.nx; V += 64) {
+    double acc = 0.0;
+#pragma unroll
+    for (int o = -(P - 1); o <= P - 1; ++o) {
+      const int X = V * P + o;
+      const double wt = o < 0 ? E[2 * (o + P) + 1] : (o > 0 ? E[2 * o] : 1.0);
+      if (X >= 0 && X < L.Nx) acc += wt * s[X];
+    }
+    t1[V + (long)(L.nx + 1) * row] = acc;
+  }
+}
+
+// x pass for rows too long to stage in LDS: one thread per (coarse vertex, row)
 __global__ void k_restrict_x(LatDev L, const double *__restrict__ E, const double *__restrict__ rf,
                              double *__restrict__ t1, long n) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -912,11 +1050,30 @@ int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, c
   const size_t shm = patch_solve_lds_bytes(E, sizeof(T), waves);
   if (shm > kLds) return -1;
   const int per_cu = 2 * shm <= kLds ? 2 : 1;
-  hipFuncSetAttribute((const void *)k_patch_solve_w<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   long grid = (long)device_cu_count() * per_cu;
   const long need = (nv + waves - 1) / waves;
   if (grid > need) grid = need;
-  k_patch_solve_w<T><<<(unsigned)grid, 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv);
+  if (sizeof(T) == 8) {  // FP64: the single-buffer kernel
+    hipFuncSetAttribute((const void *)k_patch_solve_s<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    k_patch_solve_s<T><<<(unsigned)grid, 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv);
+    return 0;
+  }
+#define RZ_CALL(KM)                                                                                          \
+  hipFuncSetAttribute((const void *)k_patch_solve_w<T, KM>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                      (int)shm);                                                                             \
+  k_patch_solve_w<T, KM><<<(unsigned)grid, 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv)
+  switch (E.kmax) {
+    case 1: RZ_CALL(1); break;
+    case 2: RZ_CALL(2); break;
+    case 3: RZ_CALL(3); break;
+    case 4: RZ_CALL(4); break;
+    case 5: RZ_CALL(5); break;
+    case 6: RZ_CALL(6); break;
+    case 7: RZ_CALL(7); break;
+    case 8: RZ_CALL(8); break;
+    default: return -1;
+  }
+#undef RZ_CALL
   return 0;
 }
 
@@ -950,15 +1107,29 @@ void launch_dirichlet_copy_f(const LatDev &L, const float *r, float *z, hipStrea
 
 void launch_prolong_add_grad(const LatDev &L, const double *E, const double *xc, double *xf,
                              hipStream_t s) {
-  long n = (long)L.Nx * L.Ny * L.Nz;
-  k_prolong_add_grad<<<nblocks(n, 256), 256, 0, s>>>(L, E, xc, xf, n);
+  const int nxb = (L.Nx + 255) / 256;
+  const unsigned grid = (unsigned)((long)nxb * L.Ny * L.Nz);
+#define RZ_CALL(Q) k_prolong_add_p<Q><<<grid, 256, 0, s>>>(L, E, xc, xf, nxb)
+  RZ_DISPATCH_P(L.p, RZ_CALL)
+#undef RZ_CALL
 }
 
 void launch_restrict_grad(const LatDev &L, const double *E, const double *rf, double *rc, double *t1, double *t2,
                           hipStream_t s) {
   const long n1 = (long)(L.nx + 1) * L.Ny * L.Nz, n2 = (long)(L.nx + 1) * (L.ny + 1) * L.Nz,
              n3 = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
-  k_restrict_x<<<nblocks(n1, 256), 256, 0, s>>>(L, E, rf, t1, n1);
+  const long rows = (long)L.Ny * L.Nz;
+  int R = 4;
+  while (R > 1 && (size_t)R * L.Nx * sizeof(double) > 64 * 1024) R >>= 1;
+  const size_t shm = (size_t)R * L.Nx * sizeof(double);
+  if (shm <= 64 * 1024) {
+    const unsigned grid = (unsigned)((rows + R - 1) / R);
+#define RZ_CALL(Q) k_restrict_x_p<Q><<<grid, 64 * R, shm, s>>>(L, E, rf, t1, rows)
+    RZ_DISPATCH_P(L.p, RZ_CALL)
+#undef RZ_CALL
+  } else {
+    k_restrict_x<<<nblocks(n1, 256), 256, 0, s>>>(L, E, rf, t1, n1);
+  }
   k_restrict_y<<<nblocks(n2, 256), 256, 0, s>>>(L, E, t1, t2, n2);
   k_restrict_z<<<nblocks(n3, 256), 256, 0, s>>>(L, E, t2, rc, n3);
 }

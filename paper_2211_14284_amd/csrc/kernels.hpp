@@ -43,6 +43,7 @@ struct PatchDev {
 // Wavefront schedule of the patch triangular solves (see PatchSymbolic).
 struct PatchEllDev {
   int nrows, npass, ne, stride;
+  int kmax;                        // largest step count K over the passes (1..8)
   const int *pass;                 // 3*npass: lanes per row G, steps K, ELL offset
   const int *ecol;                 // ne: x index read at every ELL position
   const int *erow;                 // 64*npass: row solved by each lane's group (-1 none)

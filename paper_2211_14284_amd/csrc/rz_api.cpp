@@ -1216,8 +1216,10 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
   h->P = PatchDev{ps.nrows, ps.nnz, (int)ps.flev_ptr.size() - 1, (int)ps.blev_ptr.size() - 1,
                   dsym + o_off, dsym + o_rp, dsym + o_col, dsym + o_er, dsym + o_up, dsym + o_ur, dsym + o_upos,
                   dsym + o_fp, dsym + o_fr, dsym + o_bp, dsym + o_br, ps.stride, dsym + o_p1, dsym + o_p2};
-  h->PE = PatchEllDev{ps.nrows, ps.npass, ps.ef + ps.eb, ps.stride, dsym + o_pass, dsym + o_ecol, dsym + o_erow,
-                      dsym + o_off};
+  int kmax = 1;
+  for (int k : ps.pass_k) kmax = std::max(kmax, k);
+  h->PE = PatchEllDev{ps.nrows, ps.npass, ps.ef + ps.eb, ps.stride, kmax, dsym + o_pass, dsym + o_ecol,
+                      dsym + o_erow, dsym + o_off};
   if (patch_solve_lds_bytes(h->PE, sizeof(double), 1) > 160 * 1024)
     return bail(fail(ctx, RZ_ERR_ARG, "patch schedule does not fit the LDS"));
   const size_t nf = (size_t)h->nvert * ps.stride, nzb = (size_t)h->nvert * ps.nrows;
