@@ -38,6 +38,37 @@ __device__ __forceinline__ int ncells_axis(const LatDev &L, int a) {
   return a == 0 ? L.nx : (a == 1 ? L.ny : L.nz);
 }
 
+// Lattice rows (Y, Z) along x, enumerated as: rows on a y- or z-vertex plane first
+// (Y on a vertex plane with any Z, then Z on a vertex plane with Y off them), then
+// the rows strictly inside a cell's y-z cross section.
+template <int P>
+__device__ __forceinline__ void plane_row(const LatDev &L, long line, int &Y, int &Z) {
+  const long n1 = (long)(L.ny + 1) * L.Nz;
+  if (line < n1) {
+    Y = (int)(line / L.Nz) * P;
+    Z = line % L.Nz;
+  } else if constexpr (P > 1) {
+    const long m = line - n1, off = (long)L.ny * (P - 1);
+    Z = (int)(m / off) * P;
+    const int yn = m % off;
+    Y = (yn / (P - 1)) * P + 1 + yn % (P - 1);
+  } else {
+    Y = Z = 0;
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void interior_row(const LatDev &L, long i, int &Y, int &Z) {
+  if constexpr (P > 1) {
+    const long my = (long)L.ny * (P - 1);
+    const int iy = i % my, iz = i / my;
+    Y = (iy / (P - 1)) * P + 1 + iy % (P - 1);
+    Z = (iz / (P - 1)) * P + 1 + iz % (P - 1);
+  } else {
+    Y = Z = 0;  // P = 1 has no interior rows
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // y = A x: per cell, y_K = s1 (A x B x B) + s2 (B x A x B) + s3 (B x B x A) + mu (B x B x B)
 // (eq. sum-factorization with the exact 1-D integrals of an axis-aligned cell),
@@ -211,27 +242,15 @@ __global__ void __launch_bounds__(CPC *(P + 1) * (P + 1), 4)
 
 // Lattice rows (Y, Z) on a y- or z-vertex plane: the sum of the face-line buffer
 // rows of the (up to 4) rows of cells that hold them, in a fixed order (cell z, then
-// y, lower first); Dirichlet points take x.  Lines enumerated as: Y on a vertex
-// plane (any Z), then Z on a vertex plane with Y off them.
+// y, lower first); Dirichlet points take x.
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_apply_faces(LatDev L, const T *__restrict__ x, const T *__restrict__ fb,
                                                      const T *__restrict__ bsub, T *__restrict__ y, long n) {
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const int X = g % L.Nx;
-  const long line = g / L.Nx, n1 = (long)(L.ny + 1) * L.Nz;
   int Y, Z;
-  if (line < n1) {
-    Y = (int)(line / L.Nz) * P;
-    Z = line % L.Nz;
-  } else if constexpr (P > 1) {
-    const long m = line - n1, off = L.Ny - L.ny - 1;
-    Z = (int)(m / off) * P;
-    const int yn = m % off;
-    Y = (yn / (P - 1)) * P + 1 + yn % (P - 1);
-  } else {
-    return;  // P = 1: every lattice row lies on a y-vertex plane
-  }
+  plane_row<P>(L, g / L.Nx, Y, Z);
   const long gi = lat_index(L, X, Y, Z);
   T val = 0;
   if (lat_dirichlet(L, X, Y, Z)) {
@@ -307,113 +326,106 @@ __global__ void k_apply_gather(LatDev L, const T *__restrict__ x, const T *__res
 // face DoFs (exactly one lattice coordinate on a vertex plane) couple to cell
 // interiors: along their normal line in each of the two cells.
 // ------------------------------------------------------------------------------------
-// Work item: one lattice point of a vertex plane normal to axis `a` (plane k,
-// coordinates u, v along the other two axes b < c, u fastest).  A point that lies
-// on several vertex planes (edge, vertex) is handled by its lowest such axis.
-struct PlanePoint {
-  int C[3];
-  bool face, owner;
-};
-
-template <int P>
-__device__ __forceinline__ bool plane_point(const LatDev &L, int a, long idx, PlanePoint &q) {
-  const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
-  const int Nd[3] = {L.Nx, L.Ny, L.Nz};
-  const int nd[3] = {L.nx, L.ny, L.nz};
-  const long Nb = Nd[b], Nc = Nd[c];
-  if (idx >= (long)(nd[a] + 1) * Nb * Nc) return false;
-  const int u = idx % Nb, v = (idx / Nb) % Nc, k = idx / (Nb * Nc);
-  q.C[a] = k * P;
-  q.C[b] = u;
-  q.C[c] = v;
-  const bool ob = u % P == 0, oc = v % P == 0;
-  q.face = !ob && !oc;
-  q.owner = !((b < a && ob) || (c < a && oc));
-  return true;
+// t = r / dd at an interior point of cell ce with local coordinates l (P_II is
+// diagonal: dd = mu + sum_d sigma_d lambda_{l_d})
+template <typename T>
+__device__ __forceinline__ T interior_scaled(const T *coef, long ce, const T *lam, int l0, int l1, int l2, T rv) {
+  const T *cf = coef + 6 * ce;
+  const T dd = cf[3] + cf[0] * lam[l0] + cf[1] * lam[l1] + cf[2] * lam[l2];
+  return rv / dd;
 }
 
-// Pass 1, per cell (CPB cells along x per block): t = r_I / dd on the interior
-// (P_II is diagonal, dd = mu + sum_d sigma_d lambda_{i_d}), then for every axis a
-// and interior line along a the two face contributions
-//   fc[cell][a][side][u + Q w] = sigma_a sum_i A_{e,i} t_i,  e = 0 (side 0), P (side 1),
-// (u, w: interior coordinates along the other two axes, lower axis first).
-template <int P, typename T, int CPB>
-__global__ void __launch_bounds__(256) k_condense_cells(LatDev L, const T *__restrict__ coef, const T *__restrict__ Ag,
-                                                        const T *__restrict__ lam, const T *__restrict__ r,
-                                                        T *__restrict__ fc, int ncells) {
-  constexpr int N1 = P + 1, N2 = N1 * N1, N3 = N2 * N1, Q = P - 1, Q2 = Q * Q;
-  __shared__ T S[CPB * N3];
-  const long cell0 = (long)blockIdx.x * CPB;
-  for (int k = threadIdx.x; k < CPB * N3; k += blockDim.x) {
-    const int a = k % N1, lk = (k / N1) % CPB, bc = k / (N1 * CPB), b = bc % N1, cq = bc / N1;
-    const long ce = cell0 + lk;
-    T v = 0;
-    if (ce < ncells && a > 0 && a < P && b > 0 && b < P && cq > 0 && cq < P) {
-      const int ex = ce % L.nx, ey = (ce / L.nx) % L.ny, ez = ce / ((long)L.nx * L.ny);
-      const T *cf = coef + 6 * ce;
-      const T dd = cf[3] + cf[0] * lam[a] + cf[1] * lam[b] + cf[2] * lam[cq];
-      v = r[lat_index(L, ex * P + a, ey * P + b, ez * P + cq)] / dd;
-    }
-    S[lk * N3 + a + N1 * b + N2 * cq] = v;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < CPB * 3 * Q2; t += blockDim.x) {
-    const int uw = t % Q2, ax = (t / Q2) % 3, lk = t / (3 * Q2);
-    const long ce = cell0 + lk;
-    if (ce >= ncells) continue;
-    const int u = 1 + uw % Q, w = 1 + uw / Q;
-    // local coordinates (x, y, z) of point i on the line: axis ax varies, the
-    // lower remaining axis takes u, the higher one w
-    const int stride = ax == 0 ? 1 : (ax == 1 ? N1 : N2);
-    const int base = ax == 0 ? N1 * u + N2 * w : (ax == 1 ? u + N2 * w : u + N1 * w);
-    const T *s = S + lk * N3 + base;
-    T lo = 0, hi = 0;
-#pragma unroll
-    for (int i = 1; i < P; ++i) {
-      const T ti = s[i * stride];
-      lo += Ag[i] * ti;
-      hi += Ag[P * N1 + i] * ti;
-    }
-    const T sa = coef[6 * ce + ax];
-    T *o = fc + ((ce * 3 + ax) * 2) * Q2 + uw;
-    o[0] = sa * lo;
-    o[Q2] = sa * hi;
-  }
-}
-
-// Pass 2, per point of the vertex planes: rt_G = r_G - (contributions of the two
-// cells on either side of the face) for face DoFs, r for edge and vertex DoFs, 0 on
-// Dirichlet rows.
+// One block per lattice row, lanes along x.  For a face DoF with normal axis a the
+// two cells sharing the face contribute sigma_a sum_i A_{e,i} t_i over the cell's
+// interior line through the DoF (e = P for the cell below, 0 for the cell above).
+// Rows on a y- or z-vertex plane: every point is a plane point; the normal lines
+// run across rows (coalesced over the lanes).  Rows inside a cross section: only
+// the x-face points (X on an x-vertex plane) are plane points; the row of r is
+// staged in LDS for their x-lines.  Interior points of rt are not written.
 template <int P, typename T>
-__global__ void __launch_bounds__(256) k_condense_plane(LatDev L, int a, const T *__restrict__ fc,
-                                                         const T *__restrict__ r, T *__restrict__ rt) {
-  constexpr int Q = P - 1, Q2 = Q * Q;
-  PlanePoint q;
-  if (!plane_point<P>(L, a, (long)blockIdx.x * blockDim.x + threadIdx.x, q) || !q.owner) return;
-  const long g = lat_index(L, q.C[0], q.C[1], q.C[2]);
-  if (lat_dirichlet(L, q.C[0], q.C[1], q.C[2])) {
-    rt[g] = T(0);
-    return;
-  }
-  T val = r[g];
-  if (q.face && P >= 2) {
-    const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
-    const int uw = (q.C[b] % P - 1) + Q * (q.C[c] % P - 1);
-    int cell[3];
-    for (int d = 0; d < 3; ++d) cell[d] = q.C[d] / P;
-    const int ka = q.C[a] / P;
-    if (ka > 0) {  // the cell below: its face at local coordinate P (side 1)
-      cell[a] = ka - 1;
-      const long ce = cell[0] + (long)L.nx * (cell[1] + (long)L.ny * cell[2]);
-      val -= fc[((ce * 3 + a) * 2 + 1) * Q2 + uw];
+__global__ void __launch_bounds__(256) k_condense_rows(LatDev L, const T *__restrict__ coef,
+                                                       const T *__restrict__ Ag, const T *__restrict__ lam,
+                                                       const T *__restrict__ r, T *__restrict__ rt, long nplane) {
+  constexpr int N1 = P + 1;
+  const long sz = (long)L.Nx * L.Ny;
+  if (blockIdx.x < nplane) {
+    int Y, Z;
+    plane_row<P>(L, blockIdx.x, Y, Z);
+    const bool ony = Y % P == 0, onz = Z % P == 0;
+    const long row = (long)L.Nx * (Y + (long)L.Ny * Z);
+    for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) {
+      const long g = row + X;
+      if (lat_dirichlet(L, X, Y, Z)) {
+        rt[g] = T(0);
+        continue;
+      }
+      T val = r[g];
+      if (P >= 2 && X % P != 0 && ony != onz) {  // face point, normal y (ony) or z (onz)
+        const int a = ony ? 1 : 2, Ca = ony ? Y : Z, ka = Ca / P;
+        const long st = ony ? (long)L.Nx : sz;
+        const int cx = X / P, lx = X % P;
+        const int co = ony ? Z / P : Y / P, lo_ = ony ? Z % P : Y % P;  // the remaining axis
+        const T *ra = r + g;
+        if (ka > 0) {  // the cell below: its face at local coordinate P
+          const long ce = ony ? cx + (long)L.nx * ((ka - 1) + (long)L.ny * co)
+                              : cx + (long)L.nx * (co + (long)L.ny * (ka - 1));
+          T hi = 0;
+#pragma unroll
+          for (int i = 1; i < P; ++i) {
+            const T ti = ony ? interior_scaled(coef, ce, lam, lx, i, lo_, ra[(long)(i - P) * st])
+                             : interior_scaled(coef, ce, lam, lx, lo_, i, ra[(long)(i - P) * st]);
+            hi += Ag[P * N1 + i] * ti;
+          }
+          val -= coef[6 * ce + a] * hi;
+        }
+        if (ka < (ony ? L.ny : L.nz)) {  // the cell above: its face at local coordinate 0
+          const long ce = ony ? cx + (long)L.nx * (ka + (long)L.ny * co) : cx + (long)L.nx * (co + (long)L.ny * ka);
+          T lo = 0;
+#pragma unroll
+          for (int i = 1; i < P; ++i) {
+            const T ti = ony ? interior_scaled(coef, ce, lam, lx, i, lo_, ra[(long)i * st])
+                             : interior_scaled(coef, ce, lam, lx, lo_, i, ra[(long)i * st]);
+            lo += Ag[i] * ti;
+          }
+          val -= coef[6 * ce + a] * lo;
+        }
+      }
+      rt[g] = val;
     }
-    if (ka < ncells_axis(L, a)) {  // the cell above: its face at local coordinate 0 (side 0)
-      cell[a] = ka;
-      const long ce = cell[0] + (long)L.nx * (cell[1] + (long)L.ny * cell[2]);
-      val -= fc[((ce * 3 + a) * 2) * Q2 + uw];
+  } else if constexpr (P >= 2) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *S = reinterpret_cast<T *>(smem_raw);
+    int Y, Z;
+    interior_row<P>(L, blockIdx.x - nplane, Y, Z);
+    const long row = (long)L.Nx * (Y + (long)L.Ny * Z);
+    for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) S[X] = r[row + X];
+    __syncthreads();
+    const int cy = Y / P, ly = Y % P, cz = Z / P, lz = Z % P;
+    const long cyz = (long)L.nx * (cy + (long)L.ny * cz);
+    for (int k = threadIdx.x; k <= L.nx; k += blockDim.x) {
+      const int X = k * P;
+      if (lat_dirichlet_axis(L, 0, X)) {
+        rt[row + X] = T(0);
+        continue;
+      }
+      T val = S[X];
+      if (k > 0) {
+        const long ce = (k - 1) + cyz;
+        T hi = 0;
+#pragma unroll
+        for (int i = 1; i < P; ++i) hi += Ag[P * N1 + i] * interior_scaled(coef, ce, lam, i, ly, lz, S[X - P + i]);
+        val -= coef[6 * ce] * hi;
+      }
+      if (k < L.nx) {
+        const long ce = k + cyz;
+        T lo = 0;
+#pragma unroll
+        for (int i = 1; i < P; ++i) lo += Ag[i] * interior_scaled(coef, ce, lam, i, ly, lz, S[X + i]);
+        val -= coef[6 * ce] * lo;
+      }
+      rt[row + X] = val;
     }
   }
-  rt[g] = val;
 }
 
 // ------------------------------------------------------------------------------------
@@ -596,65 +608,101 @@ __global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E,
 // vertex id) of the patch solutions; Dirichlet rows copy r.
 // Step 4 (harmonic extension, R_Gamma^T): z_I = P_II^{-1} (r_I - P_IG z_G).
 // ------------------------------------------------------------------------------------
+// Sum of the patch solutions at plane point C (ascending vertex id).
 template <int P, typename T>
-__global__ void __launch_bounds__(256) k_expand_plane(LatDev L, int a, const T *__restrict__ r,
-                                                       const T *__restrict__ zbuf, T *__restrict__ z) {
-  PlanePoint q;
-  if (!plane_point<P>(L, a, (long)blockIdx.x * blockDim.x + threadIdx.x, q) || !q.owner) return;
-  const long g = lat_index(L, q.C[0], q.C[1], q.C[2]);
-  if (lat_dirichlet(L, q.C[0], q.C[1], q.C[2])) {
-    z[g] = r[g];
-    return;
-  }
+__device__ __forceinline__ T patch_sum(const LatDev &L, const int C[3], const T *zbuf) {
   constexpr int NR = 1 + 6 * (P - 1) + 12 * (P - 1) * (P - 1);
   int lo[3], hi[3];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    lo[d] = q.C[d] / P;
-    hi[d] = (q.C[d] % P == 0) ? lo[d] : lo[d] + 1;
+    lo[d] = C[d] / P;
+    hi[d] = (C[d] % P == 0) ? lo[d] : lo[d] + 1;
   }
   const int nvx = L.nx + 1, nvy = L.ny + 1;
   T acc = 0;
   for (int vz = lo[2]; vz <= hi[2]; ++vz)
     for (int vy = lo[1]; vy <= hi[1]; ++vy)
       for (int vx = lo[0]; vx <= hi[0]; ++vx) {
-        const int k = patch_local_index(P, q.C[0] - vx * P, q.C[1] - vy * P, q.C[2] - vz * P);
+        const int k = patch_local_index(P, C[0] - vx * P, C[1] - vy * P, C[2] - vz * P);
         const long vid = vx + (long)nvx * (vy + (long)nvy * vz);
         acc += zbuf[vid * NR + k];
       }
-  z[g] = acc;
+  return acc;
 }
 
-// Interior DoFs only: lattice points with no coordinate on a vertex plane,
-// enumerated so that consecutive threads run along x.
+// Step 3 on the rows of the y- and z-vertex planes (every point a plane point).
 template <int P, typename T>
-__global__ void __launch_bounds__(256) k_expand_interior(LatDev L, const T *__restrict__ coef,
-                                                          const T *__restrict__ Ag, const T *__restrict__ lam,
-                                                          const T *__restrict__ r, T *__restrict__ z, long n) {
-  constexpr int N1 = P + 1, Q = P - 1;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const long mx = (long)L.nx * Q, my = (long)L.ny * Q;
-  const int ix = t % mx, iy = (t / mx) % my, iz = t / (mx * my);
-  const int cell[3] = {ix / Q, iy / Q, iz / Q};
-  const int loc[3] = {1 + ix % Q, 1 + iy % Q, 1 + iz % Q};
-  const int C[3] = {cell[0] * P + loc[0], cell[1] * P + loc[1], cell[2] * P + loc[2]};
-  const long g = lat_index(L, C[0], C[1], C[2]);
-  const int cid = cell[0] + L.nx * (cell[1] + L.ny * cell[2]);
-  const T s[3] = {coef[6 * cid], coef[6 * cid + 1], coef[6 * cid + 2]};
-  T dd = coef[6 * cid + 3];
-  T val = r[g];
-  const long stride[3] = {1, (long)L.Nx, (long)L.Nx * L.Ny};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    dd += s[d] * lam[loc[d]];
-    const int Fl[3] = {d == 0 ? cell[0] * P : C[0], d == 1 ? cell[1] * P : C[1], d == 2 ? cell[2] * P : C[2]};
-    const int Fh[3] = {d == 0 ? cell[0] * P + P : C[0], d == 1 ? cell[1] * P + P : C[1],
-                       d == 2 ? cell[2] * P + P : C[2]};
-    const T zl = lat_dirichlet(L, Fl[0], Fl[1], Fl[2]) ? T(0) : z[g - (long)loc[d] * stride[d]];
-    const T zh = lat_dirichlet(L, Fh[0], Fh[1], Fh[2]) ? T(0) : z[g + (long)(P - loc[d]) * stride[d]];
-    val -= s[d] * (Ag[loc[d] * N1] * zl + Ag[loc[d] * N1 + P] * zh);
+__global__ void __launch_bounds__(256) k_expand_plane_rows(LatDev L, const T *__restrict__ r,
+                                                           const T *__restrict__ zbuf, T *__restrict__ z) {
+  int Y, Z;
+  plane_row<P>(L, blockIdx.x, Y, Z);
+  const long row = (long)L.Nx * (Y + (long)L.Ny * Z);
+  for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) {
+    const int C[3] = {X, Y, Z};
+    z[row + X] = lat_dirichlet(L, X, Y, Z) ? r[row + X] : patch_sum<P, T>(L, C, zbuf);
   }
-  z[g] = val / dd;
+}
+
+// Steps 3 and 4 on the rows inside a cell's y-z cross section: the x-face points
+// from the patch solutions (kept in LDS), then every interior point
+//   z_I = (r_I - sum_d sigma_d (A_{l,0} z_lo + A_{l,P} z_hi)) / dd
+// with z_lo, z_hi the plane values at the ends of its line along axis d (the y and
+// z ones written by k_expand_plane_rows; Dirichlet ends count as 0).  The whole row
+// is written once, coalesced.
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_expand_interior_rows(LatDev L, const T *__restrict__ coef,
+                                                              const T *__restrict__ Ag, const T *__restrict__ lam,
+                                                              const T *__restrict__ r, const T *__restrict__ zbuf,
+                                                              T *__restrict__ z) {
+  constexpr int N1 = P + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *zf = reinterpret_cast<T *>(smem_raw);  // x-face values for the interior solve
+  T *zo = zf + (L.nx + 1);                  // x-face outputs (r on Dirichlet points)
+  int Y, Z;
+  interior_row<P>(L, blockIdx.x, Y, Z);
+  const long row = (long)L.Nx * (Y + (long)L.Ny * Z);
+  for (int k = threadIdx.x; k <= L.nx; k += blockDim.x) {
+    const int C[3] = {k * P, Y, Z};
+    if (lat_dirichlet_axis(L, 0, k * P)) {
+      zf[k] = T(0);
+      zo[k] = r[row + k * P];
+    } else {
+      zf[k] = zo[k] = patch_sum<P, T>(L, C, zbuf);
+    }
+  }
+  __syncthreads();
+  const int cy = Y / P, ly = Y % P, cz = Z / P, lz = Z % P;
+  const long cyz = (long)L.nx * (cy + (long)L.ny * cz);
+  const long sz = (long)L.Nx * L.Ny;
+  // y and z ends of the lines through this row (plane rows), Dirichlet ends as 0
+  const bool dyl = lat_dirichlet_axis(L, 1, cy * P), dyh = lat_dirichlet_axis(L, 1, cy * P + P);
+  const bool dzl = lat_dirichlet_axis(L, 2, cz * P), dzh = lat_dirichlet_axis(L, 2, cz * P + P);
+  for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) {
+    const long g = row + X;
+    const int cx = X / P, lx = X % P;
+    if (lx == 0) {
+      z[g] = zo[cx];
+      continue;
+    }
+    const long cid = cx + cyz;
+    const T s[3] = {coef[6 * cid], coef[6 * cid + 1], coef[6 * cid + 2]};
+    T dd = coef[6 * cid + 3];
+    T val = r[g];
+    const int loc[3] = {lx, ly, lz};
+    T zl[3], zh[3];
+    zl[0] = zf[cx];
+    zh[0] = zf[cx + 1];
+    zl[1] = dyl ? T(0) : z[g - (long)ly * L.Nx];
+    zh[1] = dyh ? T(0) : z[g + (long)(P - ly) * L.Nx];
+    zl[2] = dzl ? T(0) : z[g - (long)lz * sz];
+    zh[2] = dzh ? T(0) : z[g + (long)(P - lz) * sz];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      dd += s[d] * lam[loc[d]];
+      val -= s[d] * (Ag[loc[d] * N1] * zl[d] + Ag[loc[d] * N1 + P] * zh[d]);
+    }
+    z[g] = val / dd;
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -993,34 +1041,29 @@ void launch_apply_gather(const LatDev &L, const T *x, const T *ebuf, T *y, hipSt
   k_apply_gather<T><<<nblocks(n, 256), 256, 0, s>>>(L, x, ebuf, y, n);
 }
 
-static long plane_points(const LatDev &L, int a) {
-  const long Nd[3] = {L.Nx, L.Ny, L.Nz}, nd[3] = {L.nx, L.ny, L.nz};
-  return (nd[a] + 1) * Nd[a == 0 ? 1 : 0] * Nd[a == 2 ? 1 : 2];
-}
-
 template <int P, typename T>
-static void condense_p(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *fc, T *rt,
-                       hipStream_t s) {
-  constexpr int CPB = 4;
-  const long nc = (long)L.nx * L.ny * L.nz;
-  if (P >= 2) k_condense_cells<P, T, CPB><<<(unsigned)((nc + CPB - 1) / CPB), 256, 0, s>>>(L, coef, A, lam, r, fc, (int)nc);
-  for (int a = 0; a < 3; ++a)
-    k_condense_plane<P, T><<<nblocks(plane_points(L, a), 256), 256, 0, s>>>(L, a, fc, r, rt);
+static void condense_p(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *rt, hipStream_t s) {
+  const long np = (long)(L.ny + 1) * L.Nz + (long)(L.nz + 1) * (L.Ny - L.ny - 1);
+  const long ni = (long)L.ny * (P - 1) * L.nz * (P - 1);
+  const int bs = L.Nx >= 256 ? 256 : ((L.Nx + 63) / 64) * 64;
+  k_condense_rows<P, T><<<(unsigned)(np + ni), bs, L.Nx * sizeof(T), s>>>(L, coef, A, lam, r, rt, np);
 }
 
 template <int P, typename T>
 static void expand_p(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, const T *zbuf, T *z,
                      hipStream_t s) {
-  for (int a = 0; a < 3; ++a)
-    k_expand_plane<P, T><<<nblocks(plane_points(L, a), 256), 256, 0, s>>>(L, a, r, zbuf, z);
-  const long ni = (long)L.nx * L.ny * L.nz * (P - 1) * (P - 1) * (P - 1);
-  if (ni > 0) k_expand_interior<P, T><<<nblocks(ni, 256), 256, 0, s>>>(L, coef, A, lam, r, z, ni);
+  const long np = (long)(L.ny + 1) * L.Nz + (long)(L.nz + 1) * (L.Ny - L.ny - 1);
+  const long ni = (long)L.ny * (P - 1) * L.nz * (P - 1);
+  const int bs = L.Nx >= 256 ? 256 : ((L.Nx + 63) / 64) * 64;
+  k_expand_plane_rows<P, T><<<(unsigned)np, bs, 0, s>>>(L, r, zbuf, z);
+  if (ni > 0)
+    k_expand_interior_rows<P, T><<<(unsigned)ni, bs, 2 * (L.nx + 1) * sizeof(T), s>>>(L, coef, A, lam, r, zbuf, z);
 }
 
 template <typename T>
-void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *fc, T *rt,
+void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *rt,
                           hipStream_t s) {
-#define RZ_CALL(P) condense_p<P, T>(L, coef, A, lam, r, fc, rt, s)
+#define RZ_CALL(P) condense_p<P, T>(L, coef, A, lam, r, rt, s)
   RZ_DISPATCH_P(L.p, RZ_CALL)
 #undef RZ_CALL
 }
@@ -1141,9 +1184,9 @@ template void launch_apply_grad<float>(const LatDev &, const float *, const doub
 template void launch_apply_gather<double>(const LatDev &, const double *, const double *, double *, hipStream_t);
 template void launch_apply_gather<float>(const LatDev &, const float *, const float *, float *, hipStream_t);
 template void launch_condense_grad<double>(const LatDev &, const double *, const double *, const double *,
-                                           const double *, double *, double *, hipStream_t);
+                                           const double *, double *, hipStream_t);
 template void launch_condense_grad<float>(const LatDev &, const float *, const float *, const float *,
-                                          const float *, float *, float *, hipStream_t);
+                                          const float *, float *, hipStream_t);
 template int launch_patch_solve<double>(const LatDev &, const PatchEllDev &, const double *,
                                          const double *, double *, hipStream_t);
 template int launch_patch_solve<float>(const LatDev &, const PatchEllDev &, const float *,

@@ -98,10 +98,10 @@ void launch_cg_update_f(float a, const float *p, const float *Ap, float *x, floa
 template <typename T>
 void launch_apply_grad(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x,
                        const T *bsub, T *y, T *fbuf, hipStream_t s);
-// fc: scratch of 6 (p-1)^2 values per cell (the per-cell face contributions)
+// rt at every plane point (interior points of rt are left unwritten)
 template <typename T>
-void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *fc,
-                          T *rt, hipStream_t s);
+void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *rt,
+                          hipStream_t s);
 // Returns non-zero when the schedule does not fit the LDS of one block.
 size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves);
 template <typename T>

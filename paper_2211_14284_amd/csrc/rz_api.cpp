@@ -247,15 +247,13 @@ rz_status do_residual64(rz_problem *h, const double *b, const double *x, double 
   return RZ_OK;
 }
 
-// fc: the apply's per-cell buffer, free during a relaxation, holds the per-cell
-// face contributions of the condensation
 template <typename T>
-void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T *f, T *fc, T *rt, T *zb,
+void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T *f, T *rt, T *zb,
                  const T *r, T *z) {
   hipStream_t s = h->ctx->stream;
   {
     Timed t(h, RZ_K_CONDENSE);
-    launch_condense_grad<T>(h->L, coef, A, lam, r, fc, rt, s);
+    launch_condense_grad<T>(h->L, coef, A, lam, r, rt, s);
   }
   {
     Timed t(h, RZ_K_PATCH);
@@ -268,12 +266,12 @@ void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T
 }
 
 rz_status do_relax64(rz_problem *h, const double *r, double *z) {
-  relax_steps<double>(h, h->coef64, h->A64, h->lam64, h->f64, h->eb64, h->rt64, h->zb64, r, z);
+  relax_steps<double>(h, h->coef64, h->A64, h->lam64, h->f64, h->rt64, h->zb64, r, z);
   return RZ_OK;
 }
 
 rz_status do_relax32(rz_problem *h, const float *r, float *z) {
-  relax_steps<float>(h, h->coef32, h->A32, h->lam32, h->f32, h->eb32, h->rt32, h->zb32, r, z);
+  relax_steps<float>(h, h->coef32, h->A32, h->lam32, h->f32, h->rt32, h->zb32, r, z);
   return RZ_OK;
 }
 
