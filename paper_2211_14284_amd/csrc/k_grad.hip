@@ -38,6 +38,16 @@ __device__ __forceinline__ int ncells_axis(const LatDev &L, int a) {
   return a == 0 ? L.nx : (a == 1 ? L.ny : L.nz);
 }
 
+// Workgroups are dispatched to the 8 XCDs in turn (block b to XCD b mod 8), each
+// with its own L2.  Row kernels read neighbouring rows, so block b is mapped to a
+// logical index such that every XCD works through one contiguous range of rows.
+__device__ __forceinline__ long xcd_block(long b, long nblk) {
+  constexpr int kXcd = 8;
+  const long q = nblk / kXcd, rem = nblk % kXcd;
+  const int x = b % kXcd;
+  return x * q + min((long)x, rem) + b / kXcd;
+}
+
 // Lattice rows (Y, Z) along x, enumerated as: rows on a y- or z-vertex plane first
 // (Y on a vertex plane with any Z, then Z on a vertex plane with Y off them), then
 // the rows strictly inside a cell's y-z cross section.
@@ -126,12 +136,16 @@ template <int P, typename T, int CPC>
 __global__ void __launch_bounds__(CPC *(P + 1) * (P + 1), 4)
     k_apply_pencil(LatDev L, Tab1D<P, T> tb, const T *__restrict__ coef, const T *__restrict__ x,
                    const T *__restrict__ bsub, T *__restrict__ y, T *__restrict__ fb) {
-  constexpr int N1 = P + 1, NL = N1 * N1, N3 = NL * N1, NT = CPC * NL, W = CPC * P + 1;
-  __shared__ T S0[CPC * N3], S1[CPC * N3], CR[2][NL];
+  constexpr int N1 = P + 1, NL = N1 * N1, NT = CPC * NL, W = CPC * P + 1;
+  // LDS tile of a cell: element (a, b, c) at a + SB b + SC c, cells CS apart; the
+  // padding spreads the lanes of the z-, y- and x-line passes over the banks
+  constexpr int SB = N1 + 1, SC = SB * N1, CS = SC * N1 + 8;
+  __shared__ T S0[CPC * CS], S1[CPC * CS], CR[2][NL];
   const int tid = threadIdx.x, lc = tid / NL, l = tid % NL;
-  const int ey = blockIdx.x % L.ny, ez = blockIdx.x / L.ny;
+  const int pen = xcd_block(blockIdx.x, gridDim.x);
+  const int ey = pen % L.ny, ez = pen / L.ny;
   const int nch = (L.nx + CPC - 1) / CPC;
-  T *s0 = S0 + lc * N3, *s1 = S1 + lc * N3;
+  T *s0 = S0 + lc * CS, *s1 = S1 + lc * CS;
   // x tile of chunk j: thread tid loads the z-column (a, lk, b) of the chunk's cells,
   // a = tid % N1, lk = (tid / N1) % CPC, b = tid / (N1 CPC), c = 0..P (lanes along x);
   // the loads stay in flight until the values go to LDS at the top of the next chunk
@@ -154,36 +168,37 @@ __global__ void __launch_bounds__(CPC *(P + 1) * (P + 1), 4)
     for (int i = 0; i < N1; ++i) xv[i] = xc[i * zst];
   };
   load(0);
-  T *sx = S0 + llk * N3 + la + N1 * lb;
+  T *sx = S0 + llk * CS + la + SB * lb;
   for (int j = 0; j < nch; ++j) {
     const int nc = min(CPC, L.nx - j * CPC);
 #pragma unroll
-    for (int i = 0; i < N1; ++i) sx[NL * i] = ((okm >> i) & 1u) ? xv[i] : T(0);
+    for (int i = 0; i < N1; ++i) sx[SC * i] = ((okm >> i) & 1u) ? xv[i] : T(0);
     // this chunk's weights first: the compute waits on them, not on the prefetch
     const long cell = (j * CPC + min(lc, nc - 1)) + (long)L.nx * (ey + (long)L.ny * ez);
     const T s1c = coef[6 * cell], s2c = coef[6 * cell + 1], s3c = coef[6 * cell + 2], mu = coef[6 * cell + 3];
     load(min(j + 1, nch - 1));  // unconditional, so no branch merges the wait counts
     T r0[N1], r1[N1], r2[N1];
     __syncthreads();
+    const int lz = l % N1 + SB * (l / N1);  // z-line (a, b) = (l % N1, l / N1)
     {  // z-line (a, b): t1 = B_z x, v = A_z x
 #pragma unroll
-      for (int c = 0; c <= P; ++c) r0[c] = s0[l + NL * c];
+      for (int c = 0; c <= P; ++c) r0[c] = s0[lz + SC * c];
       mass_line<P, T>(tb, r0, r1);
       stiff_line<P, T>(tb, r0, r2);
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c <= P; ++c) {
-      s0[l + NL * c] = r1[c];
-      s1[l + NL * c] = r2[c];
+      s0[lz + SC * c] = r1[c];
+      s1[lz + SC * c] = r2[c];
     }
     __syncthreads();
     {  // y-line (a, c): u = B_y t1, w = mu u + s2 A_y t1 + s3 B_y v
       const int a = l % N1, c = l / N1;
 #pragma unroll
       for (int b = 0; b <= P; ++b) {
-        r0[b] = s0[a + N1 * b + NL * c];
-        r1[b] = s1[a + N1 * b + NL * c];
+        r0[b] = s0[a + SB * b + SC * c];
+        r1[b] = s1[a + SB * b + SC * c];
       }
       T u[N1], t[N1];
       mass_line<P, T>(tb, r0, u);
@@ -192,8 +207,8 @@ __global__ void __launch_bounds__(CPC *(P + 1) * (P + 1), 4)
       __syncthreads();
 #pragma unroll
       for (int b = 0; b <= P; ++b) {
-        s0[a + N1 * b + NL * c] = u[b];
-        s1[a + N1 * b + NL * c] = mu * u[b] + s2c * t[b] + s3c * r2[b];
+        s0[a + SB * b + SC * c] = u[b];
+        s1[a + SB * b + SC * c] = mu * u[b] + s2c * t[b] + s3c * r2[b];
       }
     }
     __syncthreads();
@@ -201,41 +216,41 @@ __global__ void __launch_bounds__(CPC *(P + 1) * (P + 1), 4)
       const int b = l % N1, c = l / N1;
 #pragma unroll
       for (int a = 0; a <= P; ++a) {
-        r0[a] = s0[a + N1 * b + NL * c];
-        r1[a] = s1[a + N1 * b + NL * c];
+        r0[a] = s0[a + SB * b + SC * c];
+        r1[a] = s1[a + SB * b + SC * c];
       }
       stiff_line<P, T>(tb, r0, r2);
       mass_line<P, T>(tb, r1, r0);
       __syncthreads();
 #pragma unroll
-      for (int a = 0; a <= P; ++a) s0[a + N1 * b + NL * c] = s1c * r2[a] + r0[a];
+      for (int a = 0; a <= P; ++a) s0[a + SB * b + SC * c] = s1c * r2[a] + r0[a];
     }
     __syncthreads();
     // rows of the chunk, lanes along x: point xo of row (b, c) is local a = xo % P of
     // cell xo / P plus, at a = 0, the x = P face of the cell before it
     const bool last = j + 1 == nch;
     for (int k = tid; k < NL * W; k += NT) {
-      const int xo = k % W, row = k / W;
+      const int xo = k % W, row = k / W, b = row % N1, c = row / N1, ro = SB * b + SC * c;
       T val;
       if (xo < nc * P) {
         const int lk = xo / P, a = xo % P;
-        val = S0[lk * N3 + a + N1 * row];
-        if (a == 0) val += lk > 0 ? S0[(lk - 1) * N3 + P + N1 * row] : (j > 0 ? CR[(j - 1) & 1][row] : T(0));
+        val = S0[lk * CS + a + ro];
+        if (a == 0) val += lk > 0 ? S0[(lk - 1) * CS + P + ro] : (j > 0 ? CR[(j - 1) & 1][row] : T(0));
       } else if (last && xo == nc * P) {
-        val = S0[(nc - 1) * N3 + P + N1 * row];
+        val = S0[(nc - 1) * CS + P + ro];
       } else {
         continue;
       }
-      const int X = j * CPC * P + xo, b = row % N1, c = row / N1;
+      const int X = j * CPC * P + xo;
       if (b > 0 && b < P && c > 0 && c < P) {
         const long g = lat_index(L, X, ey * P + b, ez * P + c);
         if (lat_dirichlet(L, X, ey * P + b, ez * P + c)) val = x[g];
         y[g] = bsub ? bsub[g] - val : val;
       } else {
-        fb[((long)blockIdx.x * 4 * P + face_row<P>(b, c)) * L.Nx + X] = val;
+        fb[((long)pen * 4 * P + face_row<P>(b, c)) * L.Nx + X] = val;
       }
     }
-    if (tid < NL) CR[j & 1][tid] = S0[(nc - 1) * N3 + P + N1 * tid];
+    if (tid < NL) CR[j & 1][tid] = S0[(nc - 1) * CS + P + SB * (tid % N1) + SC * (tid / N1)];
     __syncthreads();
   }
 }
@@ -341,18 +356,42 @@ __device__ __forceinline__ T interior_scaled(const T *coef, long ce, const T *la
 // Rows on a y- or z-vertex plane: every point is a plane point; the normal lines
 // run across rows (coalesced over the lanes).  Rows inside a cross section: only
 // the x-face points (X on an x-vertex plane) are plane points; the row of r is
-// staged in LDS for their x-lines.  Interior points of rt are not written.
+// handled by k_condense_xface.  Interior points of rt are not written.
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_condense_rows(LatDev L, const T *__restrict__ coef,
                                                        const T *__restrict__ Ag, const T *__restrict__ lam,
-                                                       const T *__restrict__ r, T *__restrict__ rt, long nplane) {
+                                                       const T *__restrict__ r, T *__restrict__ rt) {
   constexpr int N1 = P + 1;
   const long sz = (long)L.Nx * L.Ny;
-  if (blockIdx.x < nplane) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const long blk = xcd_block(blockIdx.x, gridDim.x);
+  {
     int Y, Z;
-    plane_row<P>(L, blockIdx.x, Y, Z);
+    plane_row<P>(L, blk, Y, Z);
     const bool ony = Y % P == 0, onz = Z % P == 0;
     const long row = (long)L.Nx * (Y + (long)L.Ny * Z);
+    // face rows (normal y or z): the weights of the row's cells below and above the
+    // face, staged in LDS (4 per cell: sigma_1..3, mu)
+    const bool face = P >= 2 && ony != onz;
+    const int a = ony ? 1 : 2, Ca = ony ? Y : Z, ka = Ca / P, na = ony ? L.ny : L.nz;
+    const int co = ony ? Z / P : Y / P, lo_ = ony ? Z % P : Y % P;  // the remaining axis
+    T *cw = reinterpret_cast<T *>(smem_raw);  // [2][nx][4]: below, above
+    if (face) {
+      for (int t = threadIdx.x; t < 2 * L.nx; t += blockDim.x) {
+        const int side = t / L.nx, cx = t % L.nx, kc = ka - 1 + side;
+        T v[4] = {0, 0, 0, 0};
+        if (kc >= 0 && kc < na) {
+          const long ce = ony ? cx + (long)L.nx * (kc + (long)L.ny * co) : cx + (long)L.nx * (co + (long)L.ny * kc);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = coef[6 * ce + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cw[4 * t + j] = v[j];
+      }
+      __syncthreads();
+    }
+    const long st = ony ? (long)L.Nx : sz;
+    const T llo = lam[lo_];
     for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) {
       const long g = row + X;
       if (lat_dirichlet(L, X, Y, Z)) {
@@ -360,72 +399,77 @@ __global__ void __launch_bounds__(256) k_condense_rows(LatDev L, const T *__rest
         continue;
       }
       T val = r[g];
-      if (P >= 2 && X % P != 0 && ony != onz) {  // face point, normal y (ony) or z (onz)
-        const int a = ony ? 1 : 2, Ca = ony ? Y : Z, ka = Ca / P;
-        const long st = ony ? (long)L.Nx : sz;
+      if (face && X % P != 0) {  // face point
         const int cx = X / P, lx = X % P;
-        const int co = ony ? Z / P : Y / P, lo_ = ony ? Z % P : Y % P;  // the remaining axis
+        const T llx = lam[lx];
         const T *ra = r + g;
         if (ka > 0) {  // the cell below: its face at local coordinate P
-          const long ce = ony ? cx + (long)L.nx * ((ka - 1) + (long)L.ny * co)
-                              : cx + (long)L.nx * (co + (long)L.ny * (ka - 1));
+          const T *cf = cw + 4 * cx;
           T hi = 0;
 #pragma unroll
           for (int i = 1; i < P; ++i) {
-            const T ti = ony ? interior_scaled(coef, ce, lam, lx, i, lo_, ra[(long)(i - P) * st])
-                             : interior_scaled(coef, ce, lam, lx, lo_, i, ra[(long)(i - P) * st]);
-            hi += Ag[P * N1 + i] * ti;
+            const T dd = ony ? cf[3] + cf[0] * llx + cf[1] * lam[i] + cf[2] * llo
+                             : cf[3] + cf[0] * llx + cf[1] * llo + cf[2] * lam[i];
+            hi += Ag[P * N1 + i] * (ra[(long)(i - P) * st] / dd);
           }
-          val -= coef[6 * ce + a] * hi;
+          val -= cf[a] * hi;
         }
-        if (ka < (ony ? L.ny : L.nz)) {  // the cell above: its face at local coordinate 0
-          const long ce = ony ? cx + (long)L.nx * (ka + (long)L.ny * co) : cx + (long)L.nx * (co + (long)L.ny * ka);
+        if (ka < na) {  // the cell above: its face at local coordinate 0
+          const T *cf = cw + 4 * (L.nx + cx);
           T lo = 0;
 #pragma unroll
           for (int i = 1; i < P; ++i) {
-            const T ti = ony ? interior_scaled(coef, ce, lam, lx, i, lo_, ra[(long)i * st])
-                             : interior_scaled(coef, ce, lam, lx, lo_, i, ra[(long)i * st]);
-            lo += Ag[i] * ti;
+            const T dd = ony ? cf[3] + cf[0] * llx + cf[1] * lam[i] + cf[2] * llo
+                             : cf[3] + cf[0] * llx + cf[1] * llo + cf[2] * lam[i];
+            lo += Ag[i] * (ra[(long)i * st] / dd);
           }
-          val -= coef[6 * ce + a] * lo;
+          val -= cf[a] * lo;
         }
       }
       rt[g] = val;
     }
-  } else if constexpr (P >= 2) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *S = reinterpret_cast<T *>(smem_raw);
-    int Y, Z;
-    interior_row<P>(L, blockIdx.x - nplane, Y, Z);
-    const long row = (long)L.Nx * (Y + (long)L.Ny * Z);
-    for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) S[X] = r[row + X];
-    __syncthreads();
-    const int cy = Y / P, ly = Y % P, cz = Z / P, lz = Z % P;
-    const long cyz = (long)L.nx * (cy + (long)L.ny * cz);
-    for (int k = threadIdx.x; k <= L.nx; k += blockDim.x) {
-      const int X = k * P;
-      if (lat_dirichlet_axis(L, 0, X)) {
-        rt[row + X] = T(0);
-        continue;
-      }
-      T val = S[X];
-      if (k > 0) {
-        const long ce = (k - 1) + cyz;
-        T hi = 0;
-#pragma unroll
-        for (int i = 1; i < P; ++i) hi += Ag[P * N1 + i] * interior_scaled(coef, ce, lam, i, ly, lz, S[X - P + i]);
-        val -= coef[6 * ce] * hi;
-      }
-      if (k < L.nx) {
-        const long ce = k + cyz;
-        T lo = 0;
-#pragma unroll
-        for (int i = 1; i < P; ++i) lo += Ag[i] * interior_scaled(coef, ce, lam, i, ly, lz, S[X + i]);
-        val -= coef[6 * ce] * lo;
-      }
-      rt[row + X] = val;
-    }
   }
+}
+
+// The x-face points of the rows inside the cells' y-z cross sections, one lane per
+// point (consecutive lanes along x, nx + 1 points per row); their x-lines lie in
+// the same lattice row.
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_condense_xface(LatDev L, const T *__restrict__ coef,
+                                                        const T *__restrict__ Ag, const T *__restrict__ lam,
+                                                        const T *__restrict__ r, T *__restrict__ rt, long n) {
+  constexpr int N1 = P + 1;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int k = t % (L.nx + 1);
+  int Y, Z;
+  interior_row<P>(L, t / (L.nx + 1), Y, Z);
+  const int X = k * P;
+  const long g = lat_index(L, X, Y, Z);
+  if (lat_dirichlet_axis(L, 0, X)) {
+    rt[g] = T(0);
+    return;
+  }
+  const int ly = Y % P, lz = Z % P;
+  const long cyz = (long)L.nx * (Y / P + (long)L.ny * (Z / P));
+  const T ly_ = lam[ly], lz_ = lam[lz];
+  T val = r[g];
+  if (k > 0) {
+    const T *cf = coef + 6 * ((k - 1) + cyz);
+    T hi = 0;
+#pragma unroll
+    for (int i = 1; i < P; ++i)
+      hi += Ag[P * N1 + i] * (r[g - P + i] / (cf[3] + cf[0] * lam[i] + cf[1] * ly_ + cf[2] * lz_));
+    val -= cf[0] * hi;
+  }
+  if (k < L.nx) {
+    const T *cf = coef + 6 * (k + cyz);
+    T lo = 0;
+#pragma unroll
+    for (int i = 1; i < P; ++i) lo += Ag[i] * (r[g + i] / (cf[3] + cf[0] * lam[i] + cf[1] * ly_ + cf[2] * lz_));
+    val -= cf[0] * lo;
+  }
+  rt[g] = val;
 }
 
 // ------------------------------------------------------------------------------------
@@ -635,7 +679,7 @@ template <int P, typename T>
 __global__ void __launch_bounds__(256) k_expand_plane_rows(LatDev L, const T *__restrict__ r,
                                                            const T *__restrict__ zbuf, T *__restrict__ z) {
   int Y, Z;
-  plane_row<P>(L, blockIdx.x, Y, Z);
+  plane_row<P>(L, xcd_block(blockIdx.x, gridDim.x), Y, Z);
   const long row = (long)L.Nx * (Y + (long)L.Ny * Z);
   for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) {
     const int C[3] = {X, Y, Z};
@@ -643,64 +687,59 @@ __global__ void __launch_bounds__(256) k_expand_plane_rows(LatDev L, const T *__
   }
 }
 
-// Steps 3 and 4 on the rows inside a cell's y-z cross section: the x-face points
-// from the patch solutions (kept in LDS), then every interior point
+// Step 3 on the x-face points of the rows inside the cells' y-z cross sections,
+// one lane per point (nx + 1 per row).
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_expand_xface(LatDev L, const T *__restrict__ r, const T *__restrict__ zbuf,
+                                                      T *__restrict__ z, long n) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int k = t % (L.nx + 1);
+  int Y, Z;
+  interior_row<P>(L, t / (L.nx + 1), Y, Z);
+  const int C[3] = {k * P, Y, Z};
+  const long g = lat_index(L, C[0], Y, Z);
+  z[g] = lat_dirichlet_axis(L, 0, C[0]) ? r[g] : patch_sum<P, T>(L, C, zbuf);
+}
+
+// Step 4 on the rows inside a cell's y-z cross section: every interior point
 //   z_I = (r_I - sum_d sigma_d (A_{l,0} z_lo + A_{l,P} z_hi)) / dd
-// with z_lo, z_hi the plane values at the ends of its line along axis d (the y and
-// z ones written by k_expand_plane_rows; Dirichlet ends count as 0).  The whole row
-// is written once, coalesced.
+// with z_lo, z_hi the plane values at the ends of its line along axis d (written by
+// k_expand_plane_rows and k_expand_xface; Dirichlet ends count as 0).
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_expand_interior_rows(LatDev L, const T *__restrict__ coef,
                                                               const T *__restrict__ Ag, const T *__restrict__ lam,
-                                                              const T *__restrict__ r, const T *__restrict__ zbuf,
-                                                              T *__restrict__ z) {
+                                                              const T *__restrict__ r, T *__restrict__ z) {
   constexpr int N1 = P + 1;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *zf = reinterpret_cast<T *>(smem_raw);  // x-face values for the interior solve
-  T *zo = zf + (L.nx + 1);                  // x-face outputs (r on Dirichlet points)
   int Y, Z;
-  interior_row<P>(L, blockIdx.x, Y, Z);
+  interior_row<P>(L, xcd_block(blockIdx.x, gridDim.x), Y, Z);
   const long row = (long)L.Nx * (Y + (long)L.Ny * Z);
-  for (int k = threadIdx.x; k <= L.nx; k += blockDim.x) {
-    const int C[3] = {k * P, Y, Z};
-    if (lat_dirichlet_axis(L, 0, k * P)) {
-      zf[k] = T(0);
-      zo[k] = r[row + k * P];
-    } else {
-      zf[k] = zo[k] = patch_sum<P, T>(L, C, zbuf);
-    }
-  }
-  __syncthreads();
   const int cy = Y / P, ly = Y % P, cz = Z / P, lz = Z % P;
   const long cyz = (long)L.nx * (cy + (long)L.ny * cz);
   const long sz = (long)L.Nx * L.Ny;
-  // y and z ends of the lines through this row (plane rows), Dirichlet ends as 0
   const bool dyl = lat_dirichlet_axis(L, 1, cy * P), dyh = lat_dirichlet_axis(L, 1, cy * P + P);
   const bool dzl = lat_dirichlet_axis(L, 2, cz * P), dzh = lat_dirichlet_axis(L, 2, cz * P + P);
+  const T a0y = Ag[ly * N1], aPy = Ag[ly * N1 + P], a0z = Ag[lz * N1], aPz = Ag[lz * N1 + P];
+  const T lmy = lam[ly], lmz = lam[lz];
   for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) {
-    const long g = row + X;
     const int cx = X / P, lx = X % P;
-    if (lx == 0) {
-      z[g] = zo[cx];
-      continue;
-    }
-    const long cid = cx + cyz;
-    const T s[3] = {coef[6 * cid], coef[6 * cid + 1], coef[6 * cid + 2]};
-    T dd = coef[6 * cid + 3];
+    if (lx == 0) continue;  // x-face point, written by k_expand_xface
+    const long g = row + X;
+    const T *cf = coef + 6 * (cx + cyz);
+    T dd = cf[3];
     T val = r[g];
-    const int loc[3] = {lx, ly, lz};
-    T zl[3], zh[3];
-    zl[0] = zf[cx];
-    zh[0] = zf[cx + 1];
-    zl[1] = dyl ? T(0) : z[g - (long)ly * L.Nx];
-    zh[1] = dyh ? T(0) : z[g + (long)(P - ly) * L.Nx];
-    zl[2] = dzl ? T(0) : z[g - (long)lz * sz];
-    zh[2] = dzh ? T(0) : z[g + (long)(P - lz) * sz];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      dd += s[d] * lam[loc[d]];
-      val -= s[d] * (Ag[loc[d] * N1] * zl[d] + Ag[loc[d] * N1 + P] * zh[d]);
-    }
+    const T zlx = lat_dirichlet_axis(L, 0, cx * P) ? T(0) : z[g - lx];
+    const T zhx = lat_dirichlet_axis(L, 0, cx * P + P) ? T(0) : z[g + (P - lx)];
+    const T zly = dyl ? T(0) : z[g - (long)ly * L.Nx];
+    const T zhy = dyh ? T(0) : z[g + (long)(P - ly) * L.Nx];
+    const T zlz = dzl ? T(0) : z[g - (long)lz * sz];
+    const T zhz = dzh ? T(0) : z[g + (long)(P - lz) * sz];
+    dd += cf[0] * lam[lx];
+    val -= cf[0] * (Ag[lx * N1] * zlx + Ag[lx * N1 + P] * zhx);
+    dd += cf[1] * lmy;
+    val -= cf[1] * (a0y * zly + aPy * zhy);
+    dd += cf[2] * lmz;
+    val -= cf[2] * (a0z * zlz + aPz * zhz);
     z[g] = val / dd;
   }
 }
@@ -863,39 +902,38 @@ __global__ void __launch_bounds__(256) k_patch_factor(LatDev L, PatchDev P, cons
 // p-transfer: the embedding of Q_1 in Q_p in FDM coefficients is the Kronecker
 // product of the (p+1)x2 hat matrix E per axis; restriction is its transpose.
 // ------------------------------------------------------------------------------------
-// One block row of 256 lanes along x per lattice row (Y, Z); the y and z weights
-// are uniform over the block.  Coarse Dirichlet vertices and fine Dirichlet rows
-// contribute nothing.
+// One block per lattice row (Y, Z), lanes along x.  The y and z weights are
+// uniform over the row, so the block first combines the four coarse x-lines
+// around the row into one line in LDS (coarse Dirichlet vertices excluded); each
+// fine point then interpolates between two entries of that line.
 template <int P>
 __global__ void __launch_bounds__(256) k_prolong_add_p(LatDev L, const double *__restrict__ E,
-                                                       const double *__restrict__ xc, double *__restrict__ xf,
-                                                       int nxb) {
-  const long row = blockIdx.x / nxb;
-  const int X = (blockIdx.x % nxb) * 256 + threadIdx.x;
-  if (X >= L.Nx) return;
-  const int Y = row % L.Ny, Z = row / L.Ny;
-  if (lat_dirichlet(L, X, Y, Z)) return;
-  int c[3];
-  double w0[3], w1[3];
-  bool m0[3], m1[3];
-  const int C[3] = {X, Y, Z}, n[3] = {L.nx, L.ny, L.nz};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    c[d] = min(C[d] / P, n[d] - 1);
-    const int a = C[d] - c[d] * P;
-    w0[d] = E[2 * a];
-    w1[d] = E[2 * a + 1];
-    m0[d] = !((L.dir & (1u << (2 * d))) && c[d] == 0);
-    m1[d] = !((L.dir & (2u << (2 * d))) && c[d] + 1 == n[d]);
-  }
+                                                       const double *__restrict__ xc, double *__restrict__ xf) {
+  extern __shared__ double cl[];
+  const int Y = blockIdx.x % L.Ny, Z = blockIdx.x / L.Ny;
+  const int cy = min(Y / P, L.ny - 1), cz = min(Z / P, L.nz - 1);
+  const int ay = Y - cy * P, az = Z - cz * P;
+  const double wy[2] = {((L.dir & 4u) && cy == 0) ? 0.0 : E[2 * ay],
+                        ((L.dir & 8u) && cy + 1 == L.ny) ? 0.0 : E[2 * ay + 1]};
+  const double wz[2] = {((L.dir & 16u) && cz == 0) ? 0.0 : E[2 * az],
+                        ((L.dir & 32u) && cz + 1 == L.nz) ? 0.0 : E[2 * az + 1]};
   const long sy = L.nx + 1, sz = sy * (L.ny + 1);
-  const double *q = xc + c[0] + sy * c[1] + sz * c[2];
-  auto xline = [&](long o) {
-    return (m0[0] ? w0[0] * q[o] : 0.0) + (m1[0] ? w1[0] * q[o + 1] : 0.0);
-  };
-  const double a0 = (m0[1] ? w0[1] * xline(0) : 0.0) + (m1[1] ? w1[1] * xline(sy) : 0.0);
-  const double a1 = (m0[1] ? w0[1] * xline(sz) : 0.0) + (m1[1] ? w1[1] * xline(sz + sy) : 0.0);
-  xf[X + (long)L.Nx * row] += (m0[2] ? w0[2] * a0 : 0.0) + (m1[2] ? w1[2] * a1 : 0.0);
+  const double *q = xc + sy * cy + sz * cz;
+  for (int v = threadIdx.x; v <= L.nx; v += blockDim.x) {
+    const bool dv = ((L.dir & 1u) && v == 0) || ((L.dir & 2u) && v == L.nx);
+    const double a0 = (wy[0] != 0.0 ? wy[0] * q[v] : 0.0) + (wy[1] != 0.0 ? wy[1] * q[v + sy] : 0.0);
+    const double a1 = (wy[0] != 0.0 ? wy[0] * q[v + sz] : 0.0) + (wy[1] != 0.0 ? wy[1] * q[v + sz + sy] : 0.0);
+    cl[v] = dv ? 0.0 : (wz[0] != 0.0 ? wz[0] * a0 : 0.0) + (wz[1] != 0.0 ? wz[1] * a1 : 0.0);
+  }
+  __syncthreads();
+  const long row = (long)L.Nx * blockIdx.x;
+  const bool rowdir = lat_dirichlet_axis(L, 1, Y) || lat_dirichlet_axis(L, 2, Z);
+  if (rowdir) return;
+  for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) {
+    if (lat_dirichlet_axis(L, 0, X)) continue;
+    const int cx = min(X / P, L.nx - 1), ax = X - cx * P;
+    xf[row + X] += E[2 * ax] * cl[cx] + E[2 * ax + 1] * cl[cx + 1];
+  }
 }
 
 // Restriction rc = P^T rf as three 1-D passes (x, then y, then z); the weight of a
@@ -1046,7 +1084,9 @@ static void condense_p(const LatDev &L, const T *coef, const T *A, const T *lam,
   const long np = (long)(L.ny + 1) * L.Nz + (long)(L.nz + 1) * (L.Ny - L.ny - 1);
   const long ni = (long)L.ny * (P - 1) * L.nz * (P - 1);
   const int bs = L.Nx >= 256 ? 256 : ((L.Nx + 63) / 64) * 64;
-  k_condense_rows<P, T><<<(unsigned)(np + ni), bs, L.Nx * sizeof(T), s>>>(L, coef, A, lam, r, rt, np);
+  k_condense_rows<P, T><<<(unsigned)np, bs, 8 * L.nx * sizeof(T), s>>>(L, coef, A, lam, r, rt);
+  const long nxf = ni * (L.nx + 1);
+  if (nxf > 0) k_condense_xface<P, T><<<nblocks(nxf, 256), 256, 0, s>>>(L, coef, A, lam, r, rt, nxf);
 }
 
 template <int P, typename T>
@@ -1056,8 +1096,11 @@ static void expand_p(const LatDev &L, const T *coef, const T *A, const T *lam, c
   const long ni = (long)L.ny * (P - 1) * L.nz * (P - 1);
   const int bs = L.Nx >= 256 ? 256 : ((L.Nx + 63) / 64) * 64;
   k_expand_plane_rows<P, T><<<(unsigned)np, bs, 0, s>>>(L, r, zbuf, z);
-  if (ni > 0)
-    k_expand_interior_rows<P, T><<<(unsigned)ni, bs, 2 * (L.nx + 1) * sizeof(T), s>>>(L, coef, A, lam, r, zbuf, z);
+  const long nxf = ni * (L.nx + 1);
+  if (ni > 0) {
+    k_expand_xface<P, T><<<nblocks(nxf, 256), 256, 0, s>>>(L, r, zbuf, z, nxf);
+    k_expand_interior_rows<P, T><<<(unsigned)ni, bs, 0, s>>>(L, coef, A, lam, r, z);
+  }
 }
 
 template <typename T>
@@ -1150,9 +1193,10 @@ void launch_dirichlet_copy_f(const LatDev &L, const float *r, float *z, hipStrea
 
 void launch_prolong_add_grad(const LatDev &L, const double *E, const double *xc, double *xf,
                              hipStream_t s) {
-  const int nxb = (L.Nx + 255) / 256;
-  const unsigned grid = (unsigned)((long)nxb * L.Ny * L.Nz);
-#define RZ_CALL(Q) k_prolong_add_p<Q><<<grid, 256, 0, s>>>(L, E, xc, xf, nxb)
+  const unsigned grid = (unsigned)((long)L.Ny * L.Nz);
+  const int bs = L.Nx >= 256 ? 256 : ((L.Nx + 63) / 64) * 64;
+  const size_t shm = (L.nx + 1) * sizeof(double);
+#define RZ_CALL(Q) k_prolong_add_p<Q><<<grid, bs, shm, s>>>(L, E, xc, xf)
   RZ_DISPATCH_P(L.p, RZ_CALL)
 #undef RZ_CALL
 }
