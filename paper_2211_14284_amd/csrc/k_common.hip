@@ -29,6 +29,16 @@ __global__ void k_f2d(const float *x, double *y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (double)x[i];
 }
+
+__global__ void k_f2d_scale(double a, const float *__restrict__ x, double *__restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * (double)x[i];
+}
+
+__global__ void k_f2d_axpy(double a, const float *__restrict__ x, double *__restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * (double)x[i];
+}
 __global__ void k_axpy(double a, const double *x, double *y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] += a * x[i];
@@ -224,49 +234,27 @@ __global__ void k_negate(double *W, int64_t n) {
     W[i] = -W[i];
 }
 
-// Cross-block data of the coarse sweeps (v, x) is written and read with
-// agent-scope relaxed atomics, which bypass the per-XCD L2, so the grid barrier
-// only has to order these accesses: every thread waits for its stores, one thread
-// per block arrives on the counter and polls the generation word.  No L2
-// write-back or invalidation is needed.  The wait is bounded: after ~2^26 polls
-// the block records status = -1 and continues, so a barrier cannot hang.
+// Cross-block data of the coarse sweeps (v, x) is written once per solve with
+// agent-scope relaxed atomic stores and read with agent-scope atomic loads (both
+// bypass the per-XCD L2 incoherence).  Before the launch every entry holds the
+// signalling-NaN pattern kEmpty, which no arithmetic result can take (computed NaNs
+// are quiet), so a reader polls each entry until it differs from kEmpty: the data
+// itself is the synchronisation and no grid barrier is needed.  An aligned 64-bit
+// store is single-copy atomic, so a reader sees either kEmpty or the final value.
+// The wait is bounded: after ~2^26 polls the thread records status = -1 and goes on.
+constexpr unsigned long long kEmpty = 0xFFF5A5A5A5A5A5A5ull;
+
 __device__ __forceinline__ void st_agent(double *p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double ld_agent(const double *p) {
-  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ unsigned long long ld_agent_bits(const double *p) {
+  return __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<double *>(p)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait until this wave's outstanding vector memory operations (here: the result
-// store) have completed, before the block barrier lets thread 0 publish the flag.
-// A workgroup-scope fence does not wait for them, an agent-scope one would also
-// write back the whole L2.  s_waitcnt immediate: vmcnt 0, expcnt 7, lgkmcnt 15.
-__device__ __forceinline__ void store_done() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-
-// Flag barrier: block b publishes generation `gen` in its own word flags[4 b];
-// wavefront 0 of every block polls all words with one vector load per 64 blocks
-// and a wave vote.  No contended atomics, no L2 maintenance (agent-scope
-// accesses).  Generations only grow (differences are taken modulo 2^32).
-__device__ void grid_barrier(unsigned *flags, unsigned gen, int *status) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    if (threadIdx.x == 0) __hip_atomic_store(flags + 4 * blockIdx.x, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    long spins = 0;
-    while (true) {
-      bool ok = true;
-      for (unsigned b = threadIdx.x; b < gridDim.x; b += 64)
-        ok &= (int)(__hip_atomic_load(flags + 4 * b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - gen) >= 0;
-      if (__all(ok)) break;
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1l << 26)) {
-        if (threadIdx.x == 0) atomicCAS(status, 0, -1);
-        break;
-      }
-    }
-  }
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+__global__ void k_fill_empty(double *a, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = __builtin_bit_cast(double, kEmpty);
 }
 
 // Coupling products of the block LDL^T: out = W_k Cs with Cs the 9-point in-plane
@@ -291,14 +279,12 @@ __global__ void k_coarse_wc(int m, int mx, int my, const double *__restrict__ W,
 //   u_k = W_k r_k (all planes, no barrier: each wavefront owns its rows),
 //   v_0 = u_0, v_k = u_k - M_k v_{k-1},   x_{nb-1} = v_{nb-1}, x_k = v_k - N_k x_{k+1}.
 // One matrix row per wavefront (RPB rows per block); the neighbouring plane's vector
-// is staged in LDS once per block; the next matrix row is loaded into registers
-// before the barrier of the current plane.
+// is staged in LDS once per block; the next matrix row is requested before the
+// wait for that vector, so its loads overlap the wait.
 struct CoarseArgs2 {
   int m, nb;
   const double *W, *M, *N, *r;
   double *u, *v, *x;
-  unsigned *flags;
-  unsigned gen0;
   int *status;
 };
 
@@ -311,13 +297,48 @@ __global__ void __launch_bounds__(64 * RPB) k_coarse_mn(CoarseArgs2 a) {
   const bool has_row = row < m;
   const size_t mm = (size_t)m * m;
   double wr[MPL];
+  // this wavefront's matrix row: loads without branches (column index clamped; the
+  // entries past m are never used), left in flight until the next row_dot
   auto load_row = [&](const double *mat) {
     const double *Wr = mat + (size_t)(has_row ? row : 0) * m;
 #pragma unroll
-    for (int j = 0; j < MPL; ++j) {
-      const int c = lane + 64 * j;
-      wr[j] = (has_row && c < m) ? Wr[c] : 0.0;
+    for (int j = 0; j < MPL; ++j) wr[j] = Wr[min(lane + 64 * j, m - 1)];
+  };
+  // r_k into LDS: each thread's (at most 4) entries loaded together
+  auto stage = [&](const double *vp) {
+    double t[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) t[j] = vp[min((int)(threadIdx.x + blockDim.x * j), m - 1)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = threadIdx.x + blockDim.x * j;
+      if (i < m) vl[i] = t[j];
     }
+    __syncthreads();
+  };
+  // a vector produced by other blocks in this launch into LDS: each entry polled
+  // until it is no longer kEmpty
+  auto stage_wait = [&](const double *vp) {
+    unsigned long long t[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) t[j] = ld_agent_bits(vp + min((int)(threadIdx.x + blockDim.x * j), m - 1));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = threadIdx.x + blockDim.x * j;
+      if (i < m) {
+        long spins = 0;
+        while (t[j] == kEmpty) {
+          __builtin_amdgcn_s_sleep(1);
+          t[j] = ld_agent_bits(vp + i);
+          if (++spins > (1l << 26)) {
+            atomicCAS(a.status, 0, -1);
+            break;
+          }
+        }
+        vl[i] = __builtin_bit_cast(double, t[j]);
+      }
+    }
+    __syncthreads();
   };
   auto row_dot = [&]() {
     double acc = 0.0;
@@ -329,46 +350,39 @@ __global__ void __launch_bounds__(64 * RPB) k_coarse_mn(CoarseArgs2 a) {
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
     return acc;
   };
-  // phase 0: u_k = W_k r_k
+  // phase 0: u_k = W_k r_k (the wave that owns a row keeps u in its own entries)
   load_row(a.W);
   for (int k = 0; k < nb; ++k) {
-    const double *rk = a.r + (size_t)k * m;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) vl[i] = rk[i];
-    __syncthreads();
+    stage(a.r + (size_t)k * m);
     const double acc = row_dot();
     if (k + 1 < nb) load_row(a.W + (k + 1) * mm);
-    else if (nb > 1) load_row(a.M + mm);
     if (has_row && lane == 0) a.u[(size_t)k * m + row] = acc;
     __syncthreads();
   }
-  // forward sweep
+  // forward sweep: each step stores its rows, requests the next matrix row and
+  // waits for the whole previous vector through the data itself
   if (has_row && lane == 0) st_agent(a.v + row, a.u[row]);
-  store_done();
-  grid_barrier(a.flags, a.gen0 + 1, a.status);
+  if (nb > 1) load_row(a.M + mm);
   for (int k = 1; k < nb; ++k) {
-    const double *vp = a.v + (size_t)(k - 1) * m;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) vl[i] = ld_agent(vp + i);
-    __syncthreads();
+    stage_wait(a.v + (size_t)(k - 1) * m);
     const double acc = row_dot();
     if (k + 1 < nb) load_row(a.M + (k + 1) * mm);
     else load_row(a.N + (nb - 2) * mm);
     if (has_row && lane == 0) st_agent(a.v + (size_t)k * m + row, a.u[(size_t)k * m + row] - acc);
-    store_done();
-    grid_barrier(a.flags, a.gen0 + 1 + k, a.status);
-  }
-  // backward sweep
-  if (has_row && lane == 0) st_agent(a.x + (size_t)(nb - 1) * m + row, ld_agent(a.v + (size_t)(nb - 1) * m + row));
-  store_done();
-  if (nb > 1) grid_barrier(a.flags, a.gen0 + nb + 1, a.status);
-  for (int k = nb - 2; k >= 0; --k) {
-    const double *xn = a.x + (size_t)(k + 1) * m;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) vl[i] = ld_agent(xn + i);
     __syncthreads();
+  }
+  // backward sweep (v of this wave's own row was stored by this lane)
+  if (has_row && lane == 0) {
+    const double *vr = a.v + (size_t)(nb - 1) * m + row;
+    st_agent(a.x + (size_t)(nb - 1) * m + row, __builtin_bit_cast(double, ld_agent_bits(vr)));
+  }
+  for (int k = nb - 2; k >= 0; --k) {
+    stage_wait(a.x + (size_t)(k + 1) * m);
     const double acc = row_dot();
     if (k > 0) load_row(a.N + (k - 1) * mm);
-    if (has_row && lane == 0) st_agent(a.x + (size_t)k * m + row, ld_agent(a.v + (size_t)k * m + row) - acc);
-    store_done();
-    if (k > 0) grid_barrier(a.flags, a.gen0 + nb + 1 + (nb - 1 - k), a.status);
+    if (has_row && lane == 0)
+      st_agent(a.x + (size_t)k * m + row, __builtin_bit_cast(double, ld_agent_bits(a.v + (size_t)k * m + row)) - acc);
+    __syncthreads();
   }
 }
 
@@ -394,6 +408,12 @@ __global__ void k_coarse_scatter(int ncoarse, int bx0, int by0, int bz0, int mx,
 void launch_fill(double *y, double v, int64_t n, hipStream_t s) { k_fill<<<nblk(n), kBS, 0, s>>>(y, v, n); }
 void launch_cast_d2f(const double *x, float *y, int64_t n, hipStream_t s) { k_d2f<<<nblk(n), kBS, 0, s>>>(x, y, n); }
 void launch_cast_f2d(const float *x, double *y, int64_t n, hipStream_t s) { k_f2d<<<nblk(n), kBS, 0, s>>>(x, y, n); }
+void launch_f2d_scale(double a, const float *x, double *y, int64_t n, hipStream_t s) {
+  k_f2d_scale<<<nblk(n), kBS, 0, s>>>(a, x, y, n);
+}
+void launch_f2d_axpy(double a, const float *x, double *y, int64_t n, hipStream_t s) {
+  k_f2d_axpy<<<nblk(n), kBS, 0, s>>>(a, x, y, n);
+}
 void launch_axpy(double a, const double *x, double *y, int64_t n, hipStream_t s) {
   k_axpy<<<nblk(n), kBS, 0, s>>>(a, x, y, n);
 }
@@ -491,11 +511,13 @@ void launch_coarse_wc(int m, int mx, int my, const double *W, const double *C, d
 int coarse_blocks(int m) { return m <= 1024 ? (m + 3) / 4 : (m + 15) / 16; }
 
 int launch_coarse_solve(int m, int nb, const double *W, const double *M, const double *N, const double *r, double *u,
-                        double *v, double *x, unsigned *flags, unsigned *gen, int *status, hipStream_t s) {
+                        double *v, double *x, int *status, hipStream_t s) {
   const bool small = m <= 1024;
   const int blocks = coarse_blocks(m);
-  CoarseArgs2 a{m, nb, W, M, N, r, u, v, x, flags, *gen, status};
-  *gen += 2 * (unsigned)nb;
+  const int64_t nv = (int64_t)m * nb;
+  k_fill_empty<<<nblk(nv), kBS, 0, s>>>(v, nv);
+  k_fill_empty<<<nblk(nv), kBS, 0, s>>>(x, nv);
+  CoarseArgs2 a{m, nb, W, M, N, r, u, v, x, status};
   void *args[] = {&a};
   const void *fn;
   const int mpl = (m + 63) / 64;

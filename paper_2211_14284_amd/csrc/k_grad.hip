@@ -11,6 +11,8 @@
 //   * patch solution buffer: nrows values per vertex slot in patch order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "lattice.hpp"
 
@@ -674,16 +676,29 @@ __device__ __forceinline__ T patch_sum(const LatDev &L, const int C[3], const T 
   return acc;
 }
 
+// Output of the expansion: z = scale * (M r) (plane values stored scaled; the
+// interior solve is linear in (r, z_G), so it takes scale * r against them), and,
+// when acc is given, acc += w * (M r) at every point (then scale is 1 and only the
+// plane values of z, needed by the interior solve, are written).
+template <typename T>
+struct ExpandOut {
+  T scale, w;
+  T *acc;
+};
+
 // Step 3 on the rows of the y- and z-vertex planes (every point a plane point).
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_expand_plane_rows(LatDev L, const T *__restrict__ r,
-                                                           const T *__restrict__ zbuf, T *__restrict__ z) {
+                                                           const T *__restrict__ zbuf, T *__restrict__ z,
+                                                           ExpandOut<T> o) {
   int Y, Z;
   plane_row<P>(L, xcd_block(blockIdx.x, gridDim.x), Y, Z);
   const long row = (long)L.Nx * (Y + (long)L.Ny * Z);
   for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) {
     const int C[3] = {X, Y, Z};
-    z[row + X] = lat_dirichlet(L, X, Y, Z) ? r[row + X] : patch_sum<P, T>(L, C, zbuf);
+    const T v = o.scale * (lat_dirichlet(L, X, Y, Z) ? r[row + X] : patch_sum<P, T>(L, C, zbuf));
+    z[row + X] = v;
+    if (o.acc) o.acc[row + X] += o.w * v;
   }
 }
 
@@ -691,7 +706,7 @@ __global__ void __launch_bounds__(256) k_expand_plane_rows(LatDev L, const T *__
 // one lane per point (nx + 1 per row).
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_expand_xface(LatDev L, const T *__restrict__ r, const T *__restrict__ zbuf,
-                                                      T *__restrict__ z, long n) {
+                                                      T *__restrict__ z, ExpandOut<T> o, long n) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const int k = t % (L.nx + 1);
@@ -699,7 +714,9 @@ __global__ void __launch_bounds__(256) k_expand_xface(LatDev L, const T *__restr
   interior_row<P>(L, t / (L.nx + 1), Y, Z);
   const int C[3] = {k * P, Y, Z};
   const long g = lat_index(L, C[0], Y, Z);
-  z[g] = lat_dirichlet_axis(L, 0, C[0]) ? r[g] : patch_sum<P, T>(L, C, zbuf);
+  const T v = o.scale * (lat_dirichlet_axis(L, 0, C[0]) ? r[g] : patch_sum<P, T>(L, C, zbuf));
+  z[g] = v;
+  if (o.acc) o.acc[g] += o.w * v;
 }
 
 // Step 4 on the rows inside a cell's y-z cross section: every interior point
@@ -709,7 +726,8 @@ __global__ void __launch_bounds__(256) k_expand_xface(LatDev L, const T *__restr
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_expand_interior_rows(LatDev L, const T *__restrict__ coef,
                                                               const T *__restrict__ Ag, const T *__restrict__ lam,
-                                                              const T *__restrict__ r, T *__restrict__ z) {
+                                                              const T *__restrict__ r, T *__restrict__ z,
+                                                              ExpandOut<T> o) {
   constexpr int N1 = P + 1;
   int Y, Z;
   interior_row<P>(L, xcd_block(blockIdx.x, gridDim.x), Y, Z);
@@ -727,7 +745,7 @@ __global__ void __launch_bounds__(256) k_expand_interior_rows(LatDev L, const T 
     const long g = row + X;
     const T *cf = coef + 6 * (cx + cyz);
     T dd = cf[3];
-    T val = r[g];
+    T val = o.scale * r[g];
     const T zlx = lat_dirichlet_axis(L, 0, cx * P) ? T(0) : z[g - lx];
     const T zhx = lat_dirichlet_axis(L, 0, cx * P + P) ? T(0) : z[g + (P - lx)];
     const T zly = dyl ? T(0) : z[g - (long)ly * L.Nx];
@@ -740,7 +758,8 @@ __global__ void __launch_bounds__(256) k_expand_interior_rows(LatDev L, const T 
     val -= cf[1] * (a0y * zly + aPy * zhy);
     dd += cf[2] * lmz;
     val -= cf[2] * (a0z * zlz + aPz * zhz);
-    z[g] = val / dd;
+    if (o.acc) o.acc[g] += o.w * (val / dd);
+    else z[g] = val / dd;
   }
 }
 
@@ -1020,12 +1039,24 @@ __global__ void k_restrict_z(LatDev L, const double *__restrict__ E, const doubl
   rc[i] = acc;
 }
 
+// Dirichlet rows only: the points of the six boundary faces of the lattice (face f:
+// axis f / 2, side f % 2), one thread per face point; faces without a Dirichlet
+// condition return at once.  Edge and corner points are visited by each of their
+// faces and receive the same value.
 template <typename T>
-__global__ void k_dirichlet_copy(LatDev L, const T *__restrict__ r, T *__restrict__ z, long n) {
-  long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  int X = g % L.Nx, Y = (g / L.Nx) % L.Ny, Z = g / ((long)L.Nx * L.Ny);
-  if (lat_dirichlet(L, X, Y, Z)) z[g] = r ? r[g] : T(0);
+__global__ void k_dirichlet_copy(LatDev L, const T *__restrict__ r, T *__restrict__ z) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = blockIdx.y;
+  if (!(L.dir & (1u << f))) return;
+  const int a = f >> 1, b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+  const int Nd[3] = {L.Nx, L.Ny, L.Nz};
+  if (t >= (long)Nd[b] * Nd[c]) return;
+  int C[3];
+  C[a] = (f & 1) ? Nd[a] - 1 : 0;
+  C[b] = t % Nd[b];
+  C[c] = t / Nd[b];
+  const long g = lat_index(L, C[0], C[1], C[2]);
+  z[g] = r ? r[g] : T(0);
 }
 
 inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -1091,15 +1122,15 @@ static void condense_p(const LatDev &L, const T *coef, const T *A, const T *lam,
 
 template <int P, typename T>
 static void expand_p(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, const T *zbuf, T *z,
-                     hipStream_t s) {
+                     ExpandOut<T> o, hipStream_t s) {
   const long np = (long)(L.ny + 1) * L.Nz + (long)(L.nz + 1) * (L.Ny - L.ny - 1);
   const long ni = (long)L.ny * (P - 1) * L.nz * (P - 1);
   const int bs = L.Nx >= 256 ? 256 : ((L.Nx + 63) / 64) * 64;
-  k_expand_plane_rows<P, T><<<(unsigned)np, bs, 0, s>>>(L, r, zbuf, z);
+  k_expand_plane_rows<P, T><<<(unsigned)np, bs, 0, s>>>(L, r, zbuf, z, o);
   const long nxf = ni * (L.nx + 1);
   if (ni > 0) {
-    k_expand_xface<P, T><<<nblocks(nxf, 256), 256, 0, s>>>(L, r, zbuf, z, nxf);
-    k_expand_interior_rows<P, T><<<(unsigned)ni, bs, 0, s>>>(L, coef, A, lam, r, z);
+    k_expand_xface<P, T><<<nblocks(nxf, 256), 256, 0, s>>>(L, r, zbuf, z, o, nxf);
+    k_expand_interior_rows<P, T><<<(unsigned)ni, bs, 0, s>>>(L, coef, A, lam, r, z, o);
   }
 }
 
@@ -1165,8 +1196,9 @@ int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, c
 
 template <typename T>
 void launch_expand_grad(const LatDev &L, const PatchDev &P, const T *coef, const T *A, const T *lam,
-                        const T *r, const T *zbuf, T *z, hipStream_t s) {
-#define RZ_CALL(Q) expand_p<Q, T>(L, coef, A, lam, r, zbuf, z, s)
+                        const T *r, const T *zbuf, T *z, T scale, T w, T *acc, hipStream_t s) {
+  const ExpandOut<T> o{scale, w, acc};
+#define RZ_CALL(Q) expand_p<Q, T>(L, coef, A, lam, r, zbuf, z, o, s)
   RZ_DISPATCH_P(L.p, RZ_CALL)
 #undef RZ_CALL
 }
@@ -1181,14 +1213,18 @@ void launch_patch_factor(const LatDev &L, const PatchDev &P, const double *coef,
   k_patch_factor<<<(unsigned)nv, 256, shm, s>>>(L, P, P.erow, coef, B, A, lam, f64, f32, status);
 }
 
+static long max_face_points(const LatDev &L) {
+  return std::max({(long)L.Ny * L.Nz, (long)L.Nx * L.Nz, (long)L.Nx * L.Ny});
+}
+
 void launch_dirichlet_copy(const LatDev &L, const double *r, double *z, hipStream_t s) {
-  long n = (long)L.Nx * L.Ny * L.Nz;
-  k_dirichlet_copy<double><<<nblocks(n, 256), 256, 0, s>>>(L, r, z, n);
+  const long nf = max_face_points(L);
+  k_dirichlet_copy<double><<<dim3(nblocks(nf, 256), 6), 256, 0, s>>>(L, r, z);
 }
 
 void launch_dirichlet_copy_f(const LatDev &L, const float *r, float *z, hipStream_t s) {
-  long n = (long)L.Nx * L.Ny * L.Nz;
-  k_dirichlet_copy<float><<<nblocks(n, 256), 256, 0, s>>>(L, r, z, n);
+  const long nf = max_face_points(L);
+  k_dirichlet_copy<float><<<dim3(nblocks(nf, 256), 6), 256, 0, s>>>(L, r, z);
 }
 
 void launch_prolong_add_grad(const LatDev &L, const double *E, const double *xc, double *xf,
@@ -1236,9 +1272,10 @@ template int launch_patch_solve<double>(const LatDev &, const PatchEllDev &, con
 template int launch_patch_solve<float>(const LatDev &, const PatchEllDev &, const float *,
                                         const float *, float *, hipStream_t);
 template void launch_expand_grad<double>(const LatDev &, const PatchDev &, const double *, const double *,
-                                         const double *, const double *, const double *, double *,
-                                         hipStream_t);
+                                         const double *, const double *, const double *, double *, double,
+                                         double, double *, hipStream_t);
 template void launch_expand_grad<float>(const LatDev &, const PatchDev &, const float *, const float *,
-                                        const float *, const float *, const float *, float *, hipStream_t);
+                                        const float *, const float *, const float *, float *, float, float,
+                                        float *, hipStream_t);
 
 }  // namespace rz

@@ -64,6 +64,9 @@ struct QuadDev {
 void launch_fill(double *y, double v, int64_t n, hipStream_t s);
 void launch_cast_d2f(const double *x, float *y, int64_t n, hipStream_t s);
 void launch_cast_f2d(const float *x, double *y, int64_t n, hipStream_t s);
+// y = a * x (a = 1: plain widening), and y += a * x, x in FP32
+void launch_f2d_scale(double a, const float *x, double *y, int64_t n, hipStream_t s);
+void launch_f2d_axpy(double a, const float *x, double *y, int64_t n, hipStream_t s);
 // y = a*x + y ; y = x + b*y ; z = x - y
 void launch_axpy(double a, const double *x, double *y, int64_t n, hipStream_t s);
 void launch_xpby(const double *x, double b, double *y, int64_t n, hipStream_t s);
@@ -120,9 +123,11 @@ int launch_apply_vec(const VecDev &V, const T *coef, const T *B, const T *D, con
                      hipStream_t s);
 // number of compute units of the current device (cached), for persistent grids
 int device_cu_count();
+// z = scale * (relaxation output); with acc: acc += w * output at every point (scale
+// must then be 1; z receives the plane values only, as scratch)
 template <typename T>
 void launch_expand_grad(const LatDev &L, const PatchDev &P, const T *coef, const T *A,
-                        const T *lam, const T *r, const T *zbuf, T *z, hipStream_t s);
+                        const T *lam, const T *r, const T *zbuf, T *z, T scale, T w, T *acc, hipStream_t s);
 
 // IC factorisation of every vertex patch (FP64) on the static-condensation
 // pattern; writes the FP64 factor and an FP32 copy; *status = 0 or the first
@@ -148,17 +153,16 @@ void launch_restrict_grad(const LatDev &L, const double *E, const double *rf, do
 void launch_schur_update(int m, int mx, const double *Wprev, const double *C, const double *Akk,
                          double *Dk, hipStream_t s);
 void launch_sweep_inverse(int m, double *W, double *tmp, int *status, hipStream_t s);
-// Whole block-tridiagonal solve (forward and backward sweeps over nb planes) in
-// one cooperative launch; bar: two zero-initialised unsigned counters owned by
-// the problem; returns 0 on a successful launch.
 // out = W Cs for the 9-point coupling Cs (m*9, see launch_coarse_solve)
 void launch_coarse_wc(int m, int mx, int my, const double *W, const double *C, double *out, hipStream_t s);
-// cooperative blocks of the coarse solve for plane size m (4 flag words each)
+// cooperative blocks of the coarse solve for plane size m
 int coarse_blocks(int m);
-// M: nb m*m blocks W_k C_k (k >= 1), N: W_k C_{k+1}^T (k <= nb-2); u: nb*m scratch;
-// flags: 4 words per block (zero-initialised once); *gen: host-side generation counter
+// Whole block-tridiagonal solve (forward and backward sweeps over nb planes) in one
+// cooperative launch.  M: nb m*m blocks W_k C_k (k >= 1), N: W_k C_{k+1}^T
+// (k <= nb-2); u: nb*m scratch; v, x: nb*m each, overwritten (filled with the
+// not-yet-written pattern first, in stream order); returns 0 on a successful launch.
 int launch_coarse_solve(int m, int nb, const double *W, const double *M, const double *N, const double *r, double *u,
-                        double *v, double *x, unsigned *flags, unsigned *gen, int *status, hipStream_t s);
+                        double *v, double *x, int *status, hipStream_t s);
 // gather / scatter between the coarse lattice and the free-box block vector
 void launch_coarse_gather(int nfree, int bx0, int by0, int bz0, int mx, int my, int NX, int NY,
                           const double *rc, double *blk, hipStream_t s);

@@ -83,8 +83,6 @@ struct rz_problem {
   int cm = 0, cmx = 0, cmy = 0, cmz = 0, cbx0 = 0, cby0 = 0, cbz0 = 0, cNX = 0, cNY = 0, cNZ = 0;
   double *cW = nullptr, *cC = nullptr, *cCt = nullptr, *cr = nullptr, *cv = nullptr, *cx = nullptr;
   double *cM = nullptr, *cN = nullptr, *cu = nullptr;
-  unsigned *cbar = nullptr;
-  unsigned cgen = 0;
   // krylov
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kAp = nullptr, *kro = nullptr;
   double *partials = nullptr, *dots = nullptr;
@@ -247,9 +245,10 @@ rz_status do_residual64(rz_problem *h, const double *b, const double *x, double 
   return RZ_OK;
 }
 
+// z = scale * M r; with acc: acc += w * M r (z then holds only the plane values)
 template <typename T>
 void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T *f, T *rt, T *zb,
-                 const T *r, T *z) {
+                 const T *r, T *z, T scale = T(1), T w = T(0), T *acc = nullptr) {
   hipStream_t s = h->ctx->stream;
   {
     Timed t(h, RZ_K_CONDENSE);
@@ -261,30 +260,35 @@ void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T
   }
   {
     Timed t(h, RZ_K_EXPAND);
-    launch_expand_grad<T>(h->L, h->P, coef, A, lam, r, zb, z, s);
+    launch_expand_grad<T>(h->L, h->P, coef, A, lam, r, zb, z, scale, w, acc, s);
   }
 }
 
-rz_status do_relax64(rz_problem *h, const double *r, double *z) {
-  relax_steps<double>(h, h->coef64, h->A64, h->lam64, h->f64, h->rt64, h->zb64, r, z);
+rz_status do_relax64(rz_problem *h, const double *r, double *z, double scale = 1.0, double w = 0.0,
+                     double *acc = nullptr) {
+  relax_steps<double>(h, h->coef64, h->A64, h->lam64, h->f64, h->rt64, h->zb64, r, z, scale, w, acc);
   return RZ_OK;
 }
 
-rz_status do_relax32(rz_problem *h, const float *r, float *z) {
-  relax_steps<float>(h, h->coef32, h->A32, h->lam32, h->f32, h->rt32, h->zb32, r, z);
+rz_status do_relax32(rz_problem *h, const float *r, float *z, float scale = 1.0f, float w = 0.0f,
+                     float *acc = nullptr) {
+  relax_steps<float>(h, h->coef32, h->A32, h->lam32, h->f32, h->rt32, h->zb32, r, z, scale, w, acc);
   return RZ_OK;
 }
 
 // fine relaxation on FP64 vectors in the precision of the problem's protocol
-// (FP32 relaxation for the mixed and defect-correction protocols)
-rz_status do_relax_prec(rz_problem *h, const double *r, double *z) {
+// (FP32 relaxation for the mixed and defect-correction protocols):
+// z = scale * M r, or with acc: acc += w * M r (z is then scratch)
+rz_status do_relax_prec(rz_problem *h, const double *r, double *z, double scale = 1.0, double w = 0.0,
+                        double *acc = nullptr) {
   if (h->opts.precision != RZ_PREC_F64) {
     launch_cast_d2f(r, h->r32, h->ndofs, h->ctx->stream);
     do_relax32(h, h->r32, h->z32);
-    launch_cast_f2d(h->z32, z, h->ndofs, h->ctx->stream);
+    if (acc) launch_f2d_axpy(w, h->z32, acc, h->ndofs, h->ctx->stream);
+    else launch_f2d_scale(scale, h->z32, z, h->ndofs, h->ctx->stream);
     return RZ_OK;
   }
-  return do_relax64(h, r, z);
+  return do_relax64(h, r, z, scale, w, acc);
 }
 
 rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv) {
@@ -294,7 +298,7 @@ rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv) {
   const size_t mm = (size_t)m * m;
   launch_coarse_gather(m * nb, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cNX, h->cNY, rcv, h->cr, s);
   (void)mm;
-  if (launch_coarse_solve(m, nb, h->cW, h->cM, h->cN, h->cr, h->cu, h->cv, h->cx, h->cbar, &h->cgen, h->status, s))
+  if (launch_coarse_solve(m, nb, h->cW, h->cM, h->cN, h->cr, h->cu, h->cv, h->cx, h->status, s))
     return fail(h->ctx, RZ_ERR_HIP, "cooperative launch of the coarse solve failed");
   launch_coarse_scatter((int)h->ncoarse, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cmz, h->cNX, h->cNY,
                         h->cx, xcv, s);
@@ -305,8 +309,7 @@ rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
   hipStream_t s = h->ctx->stream;
   const int64_t n = h->ndofs;
   const double w = h->omega;
-  do_relax_prec(h, r, h->vt);
-  v_scale_copy(h, w, h->vt, z);            // z = w M r
+  do_relax_prec(h, r, z, w);               // z = w M r
   do_residual64(h, r, z, h->vr);           // r1 = r - A z
   {
     Timed tm(h, RZ_K_TRANSFER);
@@ -318,8 +321,7 @@ rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
     launch_prolong_add_grad(h->L, h->E64, h->xc, z, s);   // z += P A0^{-1} P^T r1
   }
   do_residual64(h, r, z, h->vr);           // r2 = r - A z
-  do_relax_prec(h, h->vr, h->vt);
-  v_axpy(h, w, h->vt, z);                  // z += w M r2
+  do_relax_prec(h, h->vr, h->vt, 1.0, w, z);  // z += w M r2
   launch_dirichlet_copy(h->L, r, z, s);
   return RZ_OK;
 }
@@ -357,8 +359,7 @@ rz_status do_vcycle32(rz_problem *h, const float *r, float *z) {
   hipStream_t s = h->ctx->stream;
   const int64_t n = h->ndofs;
   const float w = (float)h->omega;
-  do_relax32(h, r, h->t32);
-  launch_scale_copy_f(w, h->t32, z, n, s);      // z = w M r
+  do_relax32(h, r, z, w);                       // z = w M r
   do_residual32(h, r, z, h->vr32);              // r1 = r - A z
   launch_cast_f2d(h->vr32, h->vr, n, s);
   {
@@ -374,8 +375,7 @@ rz_status do_vcycle32(rz_problem *h, const float *r, float *z) {
   }
   launch_add_d2f(h->vt, z, n, s);                // z += P A0^{-1} P^T r1
   do_residual32(h, r, z, h->vr32);              // r2 = r - A z
-  do_relax32(h, h->vr32, h->t32);
-  launch_axpy_f(w, h->t32, z, n, s);             // z += w M r2
+  do_relax32(h, h->vr32, h->t32, 1.0f, w, z);  // z += w M r2
   launch_dirichlet_copy_f(h->L, r, z, s);
   return RZ_OK;
 }
@@ -680,9 +680,6 @@ rz_status setup_coarse(rz_problem *h) {
   if ((e = dalloc(h, &h->cr, nfree))) return e;
   if ((e = dalloc(h, &h->cv, nfree))) return e;
   if ((e = dalloc(h, &h->cx, nfree))) return e;
-  const size_t nflags = 4 * (size_t)coarse_blocks(m);
-  if ((e = dalloc(h, &h->cbar, nflags))) return e;
-  HIPCALL(h, hipMemsetAsync(h->cbar, 0, nflags * sizeof(unsigned), s));
   HIPCALL(h, hipStreamSynchronize(s));
   return RZ_OK;
 }
