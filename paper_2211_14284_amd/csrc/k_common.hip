@@ -274,15 +274,22 @@ __global__ void k_coarse_wc(int m, int mx, int my, const double *__restrict__ W,
   out[idx] = s;
 }
 
-// Whole coarse solve, one persistent cooperative launch, with M_k = W_k C_k and
-// N_k = W_k C_{k+1}^T precomputed:
-//   u_k = W_k r_k (all planes, no barrier: each wavefront owns its rows),
-//   v_0 = u_0, v_k = u_k - M_k v_{k-1},   x_{nb-1} = v_{nb-1}, x_k = v_k - N_k x_{k+1}.
-// One matrix row per wavefront (RPB rows per block); the neighbouring plane's vector
-// is staged in LDS once per block; the next matrix row is requested before the
-// wait for that vector, so its loads overlap the wait.
+// Whole coarse solve, one persistent cooperative launch, on the twisted block
+// factorisation (middle plane q; Inv_k is W_k above q, Z_k below q, G at q):
+//   u_k = Inv_k r_k (all planes, no waiting),
+//   top:    v_0 = u_0,       v_k = u_k - M_k v_{k-1}   (k = 1 .. q-1),
+//   bottom: v_{nb-1} = u_{nb-1}, v_k = u_k - M_k v_{k+1} (k = nb-2 .. q+1),
+//   middle: x_q = u_q - M_q v_{q-1} - N_q v_{q+1},
+//   top:    x_k = v_k - N_k x_{k+1} (k = q-1 .. 0),
+//   bottom: x_k = v_k - N_k x_{k-1} (k = q+1 .. nb-1),
+// with M, N as set up (above q: W_k C_k, W_k Ct_k; below q: Z_k Ct_k, Z_k C_k; at q:
+// G C_q, G Ct_q).  The first nbt blocks work on the top planes and the middle, the
+// rest on the bottom planes, so the two halves advance together.  One matrix row per
+// wavefront (RPB rows per block); the neighbouring plane's vector is staged in LDS
+// once per block; the next matrix row is requested before the wait for that vector,
+// so its loads overlap the wait.
 struct CoarseArgs2 {
-  int m, nb;
+  int m, nb, q, nbt;
   const double *W, *M, *N, *r;
   double *u, *v, *x;
   int *status;
@@ -291,9 +298,10 @@ struct CoarseArgs2 {
 template <int MPL, int RPB>
 __global__ void __launch_bounds__(64 * RPB) k_coarse_mn(CoarseArgs2 a) {
   extern __shared__ double vl[];
-  const int m = a.m, nb = a.nb;
+  const int m = a.m, nb = a.nb, q = a.q;
+  const bool top = blockIdx.x < a.nbt;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int row = blockIdx.x * RPB + wid;
+  const int row = (top ? blockIdx.x : blockIdx.x - a.nbt) * RPB + wid;
   const bool has_row = row < m;
   const size_t mm = (size_t)m * m;
   double wr[MPL];
@@ -350,39 +358,76 @@ __global__ void __launch_bounds__(64 * RPB) k_coarse_mn(CoarseArgs2 a) {
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
     return acc;
   };
-  // phase 0: u_k = W_k r_k (the wave that owns a row keeps u in its own entries)
-  load_row(a.W);
-  for (int k = 0; k < nb; ++k) {
+  auto own = [&](double *arr, int k) { return arr + (size_t)k * m + row; };
+  auto put = [&](double *arr, int k, double val) {
+    if (has_row && lane == 0) st_agent(own(arr, k), val);
+  };
+  auto own_v = [&](int k) { return __builtin_bit_cast(double, ld_agent_bits(own(a.v, k))); };
+  // phase 0: u_k = Inv_k r_k over this side's planes (top: 0 .. q, bottom: q+1 .. nb-1)
+  const int k0 = top ? 0 : q + 1, k1 = top ? q : nb - 1;
+  load_row(a.W + k0 * mm);
+  for (int k = k0; k <= k1; ++k) {
     stage(a.r + (size_t)k * m);
     const double acc = row_dot();
-    if (k + 1 < nb) load_row(a.W + (k + 1) * mm);
+    if (k < k1) load_row(a.W + (k + 1) * mm);
     if (has_row && lane == 0) a.u[(size_t)k * m + row] = acc;
     __syncthreads();
   }
-  // forward sweep: each step stores its rows, requests the next matrix row and
-  // waits for the whole previous vector through the data itself
-  if (has_row && lane == 0) st_agent(a.v + row, a.u[row]);
-  if (nb > 1) load_row(a.M + mm);
-  for (int k = 1; k < nb; ++k) {
-    stage_wait(a.v + (size_t)(k - 1) * m);
-    const double acc = row_dot();
-    if (k + 1 < nb) load_row(a.M + (k + 1) * mm);
-    else load_row(a.N + (nb - 2) * mm);
-    if (has_row && lane == 0) st_agent(a.v + (size_t)k * m + row, a.u[(size_t)k * m + row] - acc);
-    __syncthreads();
-  }
-  // backward sweep (v of this wave's own row was stored by this lane)
-  if (has_row && lane == 0) {
-    const double *vr = a.v + (size_t)(nb - 1) * m + row;
-    st_agent(a.x + (size_t)(nb - 1) * m + row, __builtin_bit_cast(double, ld_agent_bits(vr)));
-  }
-  for (int k = nb - 2; k >= 0; --k) {
-    stage_wait(a.x + (size_t)(k + 1) * m);
-    const double acc = row_dot();
-    if (k > 0) load_row(a.N + (k - 1) * mm);
-    if (has_row && lane == 0)
-      st_agent(a.x + (size_t)k * m + row, __builtin_bit_cast(double, ld_agent_bits(a.v + (size_t)k * m + row)) - acc);
-    __syncthreads();
+  auto own_u = [&](int k) { return a.u[(size_t)k * m + row]; };
+  if (top) {
+    // forward sweep down to q - 1, then the middle plane
+    if (q >= 1) put(a.v, 0, own_u(0));
+    if (q >= 2) load_row(a.M + mm);
+    for (int k = 1; k <= q - 1; ++k) {
+      stage_wait(a.v + (size_t)(k - 1) * m);
+      const double acc = row_dot();
+      load_row(a.M + (k + 1 <= q - 1 ? k + 1 : q) * mm);
+      put(a.v, k, own_u(k) - acc);
+      __syncthreads();
+    }
+    double xq = own_u(q);
+    if (q >= 1) {
+      if (q == 1) load_row(a.M + q * mm);
+      stage_wait(a.v + (size_t)(q - 1) * m);
+      xq -= row_dot();
+      __syncthreads();
+    }
+    if (q + 1 < nb) {
+      load_row(a.N + q * mm);
+      stage_wait(a.v + (size_t)(q + 1) * m);
+      xq -= row_dot();
+      __syncthreads();
+    }
+    put(a.x, q, xq);
+    // back substitution upwards: x_k = v_k - N_k x_{k+1}
+    if (q >= 1) load_row(a.N + (q - 1) * mm);
+    for (int k = q - 1; k >= 0; --k) {
+      stage_wait(a.x + (size_t)(k + 1) * m);
+      const double acc = row_dot();
+      if (k > 0) load_row(a.N + (k - 1) * mm);
+      put(a.x, k, own_v(k) - acc);
+      __syncthreads();
+    }
+  } else {
+    // forward sweep up to q + 1
+    put(a.v, nb - 1, own_u(nb - 1));
+    if (nb - 2 >= q + 1) load_row(a.M + (nb - 2) * mm);
+    for (int k = nb - 2; k >= q + 1; --k) {
+      stage_wait(a.v + (size_t)(k + 1) * m);
+      const double acc = row_dot();
+      put(a.v, k, own_u(k) - acc);
+      if (k > q + 1) load_row(a.M + (k - 1) * mm);
+      __syncthreads();
+    }
+    // back substitution downwards: x_k = v_k - N_k x_{k-1}
+    load_row(a.N + (q + 1) * mm);
+    for (int k = q + 1; k <= nb - 1; ++k) {
+      stage_wait(a.x + (size_t)(k - 1) * m);
+      const double acc = row_dot();
+      if (k < nb - 1) load_row(a.N + (k + 1) * mm);
+      put(a.x, k, own_v(k) - acc);
+      __syncthreads();
+    }
   }
 }
 
@@ -510,14 +555,15 @@ void launch_coarse_wc(int m, int mx, int my, const double *W, const double *C, d
 
 int coarse_blocks(int m) { return m <= 1024 ? (m + 3) / 4 : (m + 15) / 16; }
 
-int launch_coarse_solve(int m, int nb, const double *W, const double *M, const double *N, const double *r, double *u,
-                        double *v, double *x, int *status, hipStream_t s) {
+int launch_coarse_solve(int m, int nb, int q, const double *W, const double *M, const double *N, const double *r,
+                        double *u, double *v, double *x, int *status, hipStream_t s) {
   const bool small = m <= 1024;
-  const int blocks = coarse_blocks(m);
+  const int nbt = coarse_blocks(m);
+  const int blocks = q + 1 < nb ? 2 * nbt : nbt;
   const int64_t nv = (int64_t)m * nb;
   k_fill_empty<<<nblk(nv), kBS, 0, s>>>(v, nv);
   k_fill_empty<<<nblk(nv), kBS, 0, s>>>(x, nv);
-  CoarseArgs2 a{m, nb, W, M, N, r, u, v, x, status};
+  CoarseArgs2 a{m, nb, q, nbt, W, M, N, r, u, v, x, status};
   void *args[] = {&a};
   const void *fn;
   const int mpl = (m + 63) / 64;

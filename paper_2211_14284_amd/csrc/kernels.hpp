@@ -157,12 +157,13 @@ void launch_sweep_inverse(int m, double *W, double *tmp, int *status, hipStream_
 void launch_coarse_wc(int m, int mx, int my, const double *W, const double *C, double *out, hipStream_t s);
 // cooperative blocks of the coarse solve for plane size m
 int coarse_blocks(int m);
-// Whole block-tridiagonal solve (forward and backward sweeps over nb planes) in one
-// cooperative launch.  M: nb m*m blocks W_k C_k (k >= 1), N: W_k C_{k+1}^T
-// (k <= nb-2); u: nb*m scratch; v, x: nb*m each, overwritten (filled with the
-// not-yet-written pattern first, in stream order); returns 0 on a successful launch.
-int launch_coarse_solve(int m, int nb, const double *W, const double *M, const double *N, const double *r, double *u,
-                        double *v, double *x, int *status, hipStream_t s);
+// Whole block-tridiagonal solve in one cooperative launch, on the twisted block
+// factorisation with middle plane q (q = nb - 1: top-down only).  W: nb inverse
+// blocks (m*m each); M, N: nb coupling products each (see k_coarse_mn); u: nb*m
+// scratch; v, x: nb*m each, overwritten (filled with the not-yet-written pattern
+// first, in stream order); returns 0 on a successful launch.
+int launch_coarse_solve(int m, int nb, int q, const double *W, const double *M, const double *N, const double *r,
+                        double *u, double *v, double *x, int *status, hipStream_t s);
 // gather / scatter between the coarse lattice and the free-box block vector
 void launch_coarse_gather(int nfree, int bx0, int by0, int bz0, int mx, int my, int NX, int NY,
                           const double *rc, double *blk, hipStream_t s);

@@ -81,6 +81,7 @@ struct rz_problem {
   double *vt = nullptr, *vaz = nullptr, *vr = nullptr, *rc = nullptr, *xc = nullptr, *rt1 = nullptr, *rt2 = nullptr;
   // coarse
   int cm = 0, cmx = 0, cmy = 0, cmz = 0, cbx0 = 0, cby0 = 0, cbz0 = 0, cNX = 0, cNY = 0, cNZ = 0;
+  int cq = 0;  // middle plane of the twisted coarse factorisation
   double *cW = nullptr, *cC = nullptr, *cCt = nullptr, *cr = nullptr, *cv = nullptr, *cx = nullptr;
   double *cM = nullptr, *cN = nullptr, *cu = nullptr;
   // krylov
@@ -298,7 +299,7 @@ rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv) {
   const size_t mm = (size_t)m * m;
   launch_coarse_gather(m * nb, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cNX, h->cNY, rcv, h->cr, s);
   (void)mm;
-  if (launch_coarse_solve(m, nb, h->cW, h->cM, h->cN, h->cr, h->cu, h->cv, h->cx, h->status, s))
+  if (launch_coarse_solve(m, nb, h->cq, h->cW, h->cM, h->cN, h->cr, h->cu, h->cv, h->cx, h->status, s))
     return fail(h->ctx, RZ_ERR_HIP, "cooperative launch of the coarse solve failed");
   launch_coarse_scatter((int)h->ncoarse, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cmz, h->cNX, h->cNY,
                         h->cx, xcv, s);
@@ -644,8 +645,13 @@ rz_status setup_coarse(rz_problem *h) {
   double *Akk = nullptr, *tmp = nullptr;
   if ((e = dalloc(h, &Akk, (size_t)m * m))) return e;
   if ((e = dalloc(h, &tmp, (size_t)m * m))) return e;
+  // Twisted block factorisation: top-down (W_k, k < q), bottom-up (Z_k, k > q), and
+  // the middle plane q with both Schur terms; plane k's inverse block goes to cW[k].
+  // Planes larger than 1024 use q = nb - 1 (the top-down factorisation alone).
+  const int q = m <= 1024 ? (nb - 1) / 2 : nb - 1;
+  h->cq = q;
   std::vector<double> Ah((size_t)m * m);
-  for (int k = 0; k < nb; ++k) {
+  auto plane_matrix = [&](int k) -> rz_status {
     std::fill(Ah.begin(), Ah.end(), 0.0);
     for (int a = 0; a < m; ++a) {
       int ax = a % h->cmx, ay = a / h->cmx;
@@ -656,25 +662,43 @@ rz_status setup_coarse(rz_problem *h) {
       }
     }
     HIPCALL(h, hipMemcpyAsync(Akk, Ah.data(), sizeof(double) * m * m, hipMemcpyHostToDevice, s));
-    double *Wk = h->cW + (size_t)k * m * m;
-    if (k == 0) {
-      HIPCALL(h, hipMemcpyAsync(Wk, Akk, sizeof(double) * m * m, hipMemcpyDeviceToDevice, s));
-    } else {
-      launch_schur_update(m, h->cmx, h->cW + (size_t)(k - 1) * m * m, h->cC + (size_t)k * m * 9, Akk, Wk, s);
-    }
-    launch_sweep_inverse(m, Wk, tmp, h->status, s);
+    return RZ_OK;
+  };
+  auto block = [&](int k) { return h->cW + (size_t)k * m * m; };
+  for (int k = 0; k <= q; ++k) {  // top-down; at k = q only the upper Schur term so far
+    if ((e = plane_matrix(k))) return e;
+    if (k == 0) HIPCALL(h, hipMemcpyAsync(block(k), Akk, sizeof(double) * m * m, hipMemcpyDeviceToDevice, s));
+    else launch_schur_update(m, h->cmx, block(k - 1), h->cC + (size_t)k * m * 9, Akk, block(k), s);
+    if (k < q) launch_sweep_inverse(m, block(k), tmp, h->status, s);
     HIPCALL(h, hipStreamSynchronize(s));  // Ah is reused for the next plane
   }
+  for (int k = nb - 1; k > q; --k) {  // bottom-up
+    if ((e = plane_matrix(k))) return e;
+    if (k == nb - 1) HIPCALL(h, hipMemcpyAsync(block(k), Akk, sizeof(double) * m * m, hipMemcpyDeviceToDevice, s));
+    else launch_schur_update(m, h->cmx, block(k + 1), h->cCt + (size_t)k * m * 9, Akk, block(k), s);
+    launch_sweep_inverse(m, block(k), tmp, h->status, s);
+    HIPCALL(h, hipStreamSynchronize(s));
+  }
+  if (q + 1 < nb) {  // the middle plane's lower Schur term
+    HIPCALL(h, hipMemcpyAsync(Akk, block(q), sizeof(double) * m * m, hipMemcpyDeviceToDevice, s));
+    launch_schur_update(m, h->cmx, block(q + 1), h->cCt + (size_t)q * m * 9, Akk, block(q), s);
+  }
+  launch_sweep_inverse(m, block(q), tmp, h->status, s);
+  HIPCALL(h, hipStreamSynchronize(s));
   int stv = 0;
   HIPCALL(h, hipMemcpy(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost));
   if (stv) return fail(h->ctx, RZ_ERR_SINGULAR, "coarse factorisation: non-positive pivot");
-  // coupling products for the solve: M_k = W_k C_k, N_k = W_k C_{k+1}^T
+  // coupling products for the solve (C_k: coupling of plane k to plane k-1, Ct_k: to
+  // plane k+1): k < q: M_k = W_k C_k, N_k = W_k Ct_k; k > q: M_k = Z_k Ct_k, N_k =
+  // Z_k C_k; k = q: M_q = G C_q, N_q = G Ct_q
   if ((e = dalloc(h, &h->cM, (size_t)nb * m * m)) || (e = dalloc(h, &h->cN, (size_t)nb * m * m))) return e;
   for (int k = 0; k < nb; ++k) {
-    const double *Wk = h->cW + (size_t)k * m * m;
-    if (k > 0) launch_coarse_wc(m, h->cmx, h->cmy, Wk, h->cC + (size_t)k * m * 9, h->cM + (size_t)k * m * m, s);
-    if (k + 1 < nb)
-      launch_coarse_wc(m, h->cmx, h->cmy, Wk, h->cCt + (size_t)k * m * 9, h->cN + (size_t)k * m * m, s);
+    const double *Ck = h->cC + (size_t)k * m * 9, *Ctk = h->cCt + (size_t)k * m * 9;
+    const bool down = k > q;
+    const double *cm = down ? Ctk : Ck, *cn = down ? Ck : Ctk;
+    const bool hm = down ? k + 1 < nb : k > 0, hn = down ? true : k + 1 < nb;
+    if (hm) launch_coarse_wc(m, h->cmx, h->cmy, block(k), cm, h->cM + (size_t)k * m * m, s);
+    if (hn) launch_coarse_wc(m, h->cmx, h->cmy, block(k), cn, h->cN + (size_t)k * m * m, s);
   }
   if ((e = dalloc(h, &h->cu, nfree))) return e;
   if ((e = dalloc(h, &h->cr, nfree))) return e;
