@@ -482,7 +482,10 @@ __global__ void __launch_bounds__(256) k_condense_xface(LatDev L, const T *__res
 // values stream in ELL order; the block shares the schedule's index tables in LDS.
 // Two variants, chosen by measurement: FP32 streams the values into two register
 // buffers used in turn (pass t + 1 loads while pass t computes); FP64 keeps one
-// buffer loaded at the top of each pass, which measured faster for 8-byte values.
+// buffer loaded at the top of each pass, which measured faster for 8-byte values,
+// with the slot's diagonal in LDS while 16 wavefronts per block still fit (p <= 7)
+// and pivots read from global memory for larger patches, where residency matters
+// more (p = 8: 1.16 -> 0.81 ms per launch measured on C5).
 // ------------------------------------------------------------------------------------
 // sum over the K steps of one lane in a pass of buf[s] * x[col(s)], K uniform: one
 // straight-line body per K so that the LDS reads batch without per-step branches
@@ -525,8 +528,10 @@ __device__ __forceinline__ T group_sum(T s, int G) {
 }
 
 // Single-buffer variant (FP64): the next pass's values are loaded at the top of
-// each pass, steps only up to K.
-template <typename T>
+// each pass, steps only up to K.  DL: the slot's diagonal is copied to LDS next to
+// the vector; otherwise each pass loads its pivots from global memory (cached), which
+// halves the LDS per wavefront and lets more wavefronts share a CU.
+template <typename T, bool DL>
 __global__ void __launch_bounds__(1024) k_patch_solve_s(LatDev L, PatchEllDev E, const T *__restrict__ factor,
                                                          const T *__restrict__ rt, T *__restrict__ zbuf,
                                                          long nslots) {
@@ -534,9 +539,10 @@ __global__ void __launch_bounds__(1024) k_patch_solve_s(LatDev L, PatchEllDev E,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nrows = E.nrows, ne = E.ne, np = E.npass, p = L.p;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-  T *xw = reinterpret_cast<T *>(smem_raw) + (size_t)w * 2 * nrows;  // this wavefront's vector
-  T *dw = xw + nrows;                                                  // and diagonal
-  int *off = reinterpret_cast<int *>(reinterpret_cast<T *>(smem_raw) + (size_t)nw * 2 * nrows);
+  constexpr int VW = DL ? 2 : 1;  // per-wavefront LDS vectors: x (and the diagonal)
+  T *xw = reinterpret_cast<T *>(smem_raw) + (size_t)w * VW * nrows;  // this wavefront's vector
+  T *dw = xw + nrows;                                                   // and diagonal (DL)
+  int *off = reinterpret_cast<int *>(reinterpret_cast<T *>(smem_raw) + (size_t)nw * VW * nrows);
   unsigned short *ecol = reinterpret_cast<unsigned short *>(off + nrows);
   unsigned short *erow = ecol + ne;
   for (int i = tid; i < ne; i += blockDim.x) ecol[i] = (unsigned short)E.ecol[i];
@@ -554,7 +560,7 @@ __global__ void __launch_bounds__(1024) k_patch_solve_s(LatDev L, PatchEllDev E,
       const int X = vx * p + (o & 255) - 64, Y = vy * p + ((o >> 8) & 255) - 64, Z = vz * p + ((o >> 16) & 255) - 64;
       const bool in = X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
       xw[i] = (in && !lat_dirichlet(L, X, Y, Z)) ? rt[lat_index(L, X, Y, Z)] : T(0);
-      dw[i] = f[i];
+      if (DL) dw[i] = f[i];
     }
     T cur[KM];
     {
@@ -564,6 +570,8 @@ __global__ void __launch_bounds__(1024) k_patch_solve_s(LatDev L, PatchEllDev E,
     }
     for (int t = 0; t < np; ++t) {
       const int G = E.pass[3 * t], K = E.pass[3 * t + 1], base = E.pass[3 * t + 2];
+      const unsigned row = erow[64 * t + lane];
+      const T piv = DL ? T(1) : (row != 0xFFFFu ? f[row] : T(1));
       T nxt[KM];
       const int Kn = t + 1 < np ? E.pass[3 * t + 4] : 0, bn = t + 1 < np ? E.pass[3 * t + 5] : 0;
 #pragma unroll
@@ -573,8 +581,7 @@ __global__ void __launch_bounds__(1024) k_patch_solve_s(LatDev L, PatchEllDev E,
       for (int s = 0; s < KM; ++s)
         if (s < K) acc += cur[s] * xw[ecol[base + 64 * s + lane]];
       acc = group_sum(acc, G);
-      const unsigned row = erow[64 * t + lane];
-      if ((lane & (G - 1)) == 0 && row != 0xFFFFu) xw[row] = (xw[row] - acc) / dw[row];
+      if ((lane & (G - 1)) == 0 && row != 0xFFFFu) xw[row] = (xw[row] - acc) / (DL ? dw[row] : piv);
 #pragma unroll
       for (int s = 0; s < KM; ++s) cur[s] = nxt[s];
     }
@@ -1171,8 +1178,35 @@ int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, c
   const long need = (nv + waves - 1) / waves;
   if (grid > need) grid = need;
   if (sizeof(T) == 8) {  // FP64: the single-buffer kernel
-    hipFuncSetAttribute((const void *)k_patch_solve_s<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    k_patch_solve_s<T><<<(unsigned)grid, 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv);
+    if (waves == 16) {  // the diagonal fits in LDS next to the vector at 16 wavefronts per block
+      hipFuncSetAttribute((const void *)k_patch_solve_s<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)shm);
+      k_patch_solve_s<T, true><<<(unsigned)grid, 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv);
+      return 0;
+    }
+    // larger patches: pivots from global memory, and the block size that keeps the
+    // most wavefronts resident per CU (LDS-bound; at most 32 wavefronts per CU)
+    const size_t tab = patch_solve_lds_bytes(E, sizeof(T), 0);
+    int w1 = 0, b1 = 0, best = 0;
+    for (int w = 16; w >= 1; --w) {
+      const size_t need = (size_t)w * E.nrows * sizeof(T) + tab;
+      if (need > kLds) continue;
+      int b = (int)(kLds / need);
+      if (b * w > 32) b = 32 / w;
+      if (b * w > best) {
+        best = b * w;
+        w1 = w;
+        b1 = b;
+      }
+    }
+    if (!w1) return -1;
+    const size_t shm1 = (size_t)w1 * E.nrows * sizeof(T) + tab;
+    long grid1 = (long)device_cu_count() * b1;
+    const long need1 = (nv + w1 - 1) / w1;
+    if (grid1 > need1) grid1 = need1;
+    hipFuncSetAttribute((const void *)k_patch_solve_s<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)shm1);
+    k_patch_solve_s<T, false><<<(unsigned)grid1, 64 * w1, shm1, s>>>(L, E, factor, rt, zbuf, nv);
     return 0;
   }
 #define RZ_CALL(KM)                                                                                          \
