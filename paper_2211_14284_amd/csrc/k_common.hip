@@ -47,6 +47,15 @@ __global__ void k_xpby(const double *x, double b, double *y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = x[i] + b * y[i];
 }
+
+// y = x + b y with b = (num - cross) / den read from device memory (cross optional)
+__global__ void k_xpby_dev(const double *__restrict__ x, const double *__restrict__ num,
+                           const double *__restrict__ cross, const double *__restrict__ den, double *__restrict__ y,
+                           int64_t n) {
+  const double b = (*num - (cross ? *cross : 0.0)) / *den;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = x[i] + b * y[i];
+}
 __global__ void k_sub(const double *x, const double *y, double *z, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     z[i] = x[i] - y[i];
@@ -129,11 +138,17 @@ __global__ void __launch_bounds__(kBS) k_dot_final(int np, int nb, const double 
 
 // CG update fused with the next inner product: x += a p; (ro = r); r -= a Ap;
 // partial sums of r.r (same two-pass reduction as the dots)
-__global__ void __launch_bounds__(kBS) k_cg_update(double a, const double *__restrict__ p,
+// x += a p, r -= a Ap (ro = r before the update when given), partial sums of r.r;
+// a = num / den read from device memory (0 when den <= 0: the host reports the
+// breakdown from the den it reads back)
+__global__ void __launch_bounds__(kBS) k_cg_update(const double *__restrict__ num, const double *__restrict__ den,
+                                                    const double *__restrict__ p,
                                                     const double *__restrict__ Ap, double *__restrict__ x,
                                                     double *__restrict__ r, double *__restrict__ ro, int64_t n,
                                                     double *partials) {
   __shared__ double red[16];
+  const double dn = *den;
+  const double a = dn > 0.0 ? *num / dn : 0.0;
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     x[i] += a * p[i];
@@ -465,6 +480,10 @@ void launch_axpy(double a, const double *x, double *y, int64_t n, hipStream_t s)
 void launch_xpby(const double *x, double b, double *y, int64_t n, hipStream_t s) {
   k_xpby<<<nblk(n), kBS, 0, s>>>(x, b, y, n);
 }
+void launch_xpby_dev(const double *x, const double *num, const double *cross, const double *den, double *y,
+                     int64_t n, hipStream_t s) {
+  k_xpby_dev<<<nblk(n), kBS, 0, s>>>(x, num, cross, den, y, n);
+}
 void launch_sub(const double *x, const double *y, double *z, int64_t n, hipStream_t s) {
   k_sub<<<nblk(n), kBS, 0, s>>>(x, y, z, n);
 }
@@ -508,9 +527,9 @@ void launch_cg_update_f(float a, const float *p, const float *Ap, float *x, floa
   k_dot_final<<<1, kBS, 0, s>>>(1, kDotBlocks, partials, out);
 }
 
-void launch_cg_update(double a, const double *p, const double *Ap, double *x, double *r, double *ro, int64_t n,
-                      double *partials, double *out, hipStream_t s) {
-  k_cg_update<<<kDotBlocks, kBS, 0, s>>>(a, p, Ap, x, r, ro, n, partials);
+void launch_cg_update(const double *num, const double *den, const double *p, const double *Ap, double *x,
+                      double *r, double *ro, int64_t n, double *partials, double *out, hipStream_t s) {
+  k_cg_update<<<kDotBlocks, kBS, 0, s>>>(num, den, p, Ap, x, r, ro, n, partials);
   k_dot_final<<<1, kBS, 0, s>>>(1, kDotBlocks, partials, out);
 }
 

@@ -76,9 +76,13 @@ void launch_scale_copy(double a, const double *x, double *y, int64_t n, hipStrea
 void launch_dots(int npairs, const double *const *xs, const double *const *ys, int64_t n,
                  double *partials, double *out, hipStream_t s);
 int dots_partials_size();
-// x += a p; ro = r (if ro != nullptr); r -= a Ap; out[0] = r.r (two-pass, like launch_dots)
-void launch_cg_update(double a, const double *p, const double *Ap, double *x, double *r, double *ro, int64_t n,
-                      double *partials, double *out, hipStream_t s);
+// x += a p; ro = r (if ro != nullptr); r -= a Ap; out[0] = r.r (two-pass, like
+// launch_dots); a = *num / *den from device memory (0 if *den <= 0)
+void launch_cg_update(const double *num, const double *den, const double *p, const double *Ap, double *x,
+                      double *r, double *ro, int64_t n, double *partials, double *out, hipStream_t s);
+// y = x + b y, b = (*num - *cross) / *den from device memory (cross may be null)
+void launch_xpby_dev(const double *x, const double *num, const double *cross, const double *den, double *y,
+                     int64_t n, hipStream_t s);
 
 // FP32 vectors (inner solve of the defect-correction protocol); inner products
 // accumulate in FP64 into out[k] like launch_dots

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.hpp"
@@ -87,7 +88,7 @@ struct rz_problem {
   // krylov
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kAp = nullptr, *kro = nullptr;
   double *partials = nullptr, *dots = nullptr;
-  double *hdots = nullptr;  // pinned host copy of the dot products (4 values)
+  double *hdots = nullptr;  // pinned host copy of the dot products (8 values)
   int *status = nullptr;
   // per-kernel timing
   bool timing = false;
@@ -841,25 +842,35 @@ namespace {
 // instance; rz_solve_batched advances instances of several problems in lockstep,
 // so their streams overlap on the device.  Both issue the same kernels in the same
 // order, so their results are identical.
+// PCG as a step machine: each step enqueues work and the read-back of the scalars
+// the host needs next; the caller synchronises the stream between steps.  The CG
+// coefficients are formed on the device (alpha in the update kernel, beta in the
+// direction update), so one host round trip per iteration remains: the convergence
+// test on r.r, which decides whether the next V-cycle runs.
+// Device scalar slots (h->dots): [2q], [2q+1]: r.z and (mixed) r_old.z of the
+// iterations with parity q; [4]: p.Ap; [5]: r.r after the update; [6]: other norms.
 struct PcgRun {
   rz_problem *h = nullptr;
   const double *b = nullptr;
   double *x = nullptr;
-  enum Phase { INIT, GOT_BB, GOT_RZ0, GOT_PAP, GOT_RR, GOT_TR, GOT_D2, GOT_FINAL, DONE } phase = INIT;
-  int it = 0, ndots = 0;
-  double nb = 0, tol = 0, rz = 0, relres = 0;
+  enum Phase { INIT, GOT_BB, GOT_RR, GOT_TR, GOT_FINAL, DONE } phase = INIT;
+  int it = 0;
+  double nb = 0, tol = 0, relres = 0;
   rz_status result = RZ_OK;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
-rz_status pcg_dots(PcgRun &R, int np, const double *const *xs, const double *const *ys) {
+enum { kSlotPap = 4, kSlotRr = 5, kSlotNorm = 6 };
+
+// one norm (x.x) into slot kSlotNorm and its host copy hdots[0]
+rz_status pcg_norm(PcgRun &R, const double *v) {
   rz_problem *h = R.h;
+  const double *xs[1] = {v};
   {
     Timed tm(h, RZ_K_KRYLOV);
-    launch_dots(np, xs, ys, h->ndofs, h->partials, h->dots, h->ctx->stream);
+    launch_dots(1, xs, xs, h->ndofs, h->partials, h->dots + kSlotNorm, h->ctx->stream);
   }
-  HIPCALL(h, hipMemcpyAsync(h->hdots, h->dots, sizeof(double) * np, hipMemcpyDeviceToHost, h->ctx->stream));
-  R.ndots = np;
+  HIPCALL(h, hipMemcpyAsync(h->hdots, h->dots + kSlotNorm, sizeof(double), hipMemcpyDeviceToHost, h->ctx->stream));
   return RZ_OK;
 }
 
@@ -867,36 +878,52 @@ rz_status pcg_final(PcgRun &R) {
   rz_problem *h = R.h;
   do_residual64(h, R.b, R.x, h->vr);
   launch_dirichlet_copy(h->L, nullptr, h->vr, h->ctx->stream);
-  const double *xs[1] = {h->vr};
   R.phase = PcgRun::GOT_FINAL;
-  return pcg_dots(R, 1, xs, xs);
+  return pcg_norm(R, h->vr);
 }
 
-rz_status pcg_precondition(PcgRun &R) {
+// One iteration from the current residual r: z = V r, rz (+ cross), p = z + beta p
+// (p = z on the first iteration), Ap, p.Ap, x += alpha p, r -= alpha Ap, r.r; then
+// p.Ap and r.r go back to the host.
+rz_status pcg_iteration(PcgRun &R, bool first) {
   rz_problem *h = R.h;
+  hipStream_t s = h->ctx->stream;
+  const int64_t n = h->ndofs;
+  const bool mixed = h->opts.precision == RZ_PREC_MIXED;
+  const int q = R.it & 1;
+  double *rz = h->dots + 2 * q, *rz_old = h->dots + 2 * (1 - q);
   do_vcycle(h, h->kr, h->kz);
-  R.phase = PcgRun::GOT_D2;
-  if (h->opts.precision == RZ_PREC_MIXED) {
-    const double *xs[2] = {h->kr, h->kro}, *ys[2] = {h->kz, h->kz};
-    return pcg_dots(R, 2, xs, ys);
-  }
-  const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
-  return pcg_dots(R, 1, xs, ys);
-}
-
-rz_status pcg_search(PcgRun &R) {
-  rz_problem *h = R.h;
-  if (R.it >= h->opts.maxit) {
-    R.result = RZ_ERR_NOT_CONVERGED;
-    return pcg_final(R);
+  {
+    Timed tm(h, RZ_K_KRYLOV);
+    if (first) {
+      const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
+      launch_dots(1, xs, ys, n, h->partials, rz, s);
+      launch_scale_copy(1.0, h->kz, h->kp, n, s);
+    } else if (mixed) {
+      const double *xs[2] = {h->kr, h->kro}, *ys[2] = {h->kz, h->kz};
+      launch_dots(2, xs, ys, n, h->partials, rz, s);
+      launch_xpby_dev(h->kz, rz, rz + 1, rz_old, h->kp, n, s);
+    } else {
+      const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
+      launch_dots(1, xs, ys, n, h->partials, rz, s);
+      launch_xpby_dev(h->kz, rz, nullptr, rz_old, h->kp, n, s);
+    }
   }
   do_apply64(h, h->kp, h->kAp);
-  const double *xs[1] = {h->kp}, *ys[1] = {h->kAp};
-  R.phase = PcgRun::GOT_PAP;
-  return pcg_dots(R, 1, xs, ys);
+  {
+    Timed tm(h, RZ_K_KRYLOV);
+    const double *xs[1] = {h->kp}, *ys[1] = {h->kAp};
+    launch_dots(1, xs, ys, n, h->partials, h->dots + kSlotPap, s);
+    launch_cg_update(rz, h->dots + kSlotPap, h->kp, h->kAp, R.x, h->kr, mixed ? h->kro : nullptr, n, h->partials,
+                     h->dots + kSlotRr, s);
+  }
+  HIPCALL(h, hipMemcpyAsync(h->hdots, h->dots + kSlotPap, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  ++R.it;
+  R.phase = PcgRun::GOT_RR;
+  return RZ_OK;
 }
 
-// Advance one step with the dot products of the previous step in h->hdots.
+// Advance one step with the scalars of the previous step in h->hdots.
 rz_status pcg_step(PcgRun &R) {
   rz_problem *h = R.h;
   hipStream_t s = h->ctx->stream;
@@ -910,50 +937,36 @@ rz_status pcg_step(PcgRun &R) {
       launch_fill(R.x, 0.0, n, s);  // x = 0, r = b with Dirichlet rows zero
       v_scale_copy(h, 1.0, R.b, h->kr);
       launch_dirichlet_copy(h->L, nullptr, h->kr, s);
-      const double *xs[1] = {h->kr};
       R.phase = PcgRun::GOT_BB;
-      return pcg_dots(R, 1, xs, xs);
+      return pcg_norm(R, h->kr);
     }
     case PcgRun::GOT_BB: {
       R.nb = std::sqrt(d[0]);
       R.tol = h->opts.rtol * R.nb;
       if (!(R.nb > 0)) return pcg_final(R);
-      do_vcycle(h, h->kr, h->kz);
-      v_scale_copy(h, 1.0, h->kz, h->kp);
-      const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
-      R.phase = PcgRun::GOT_RZ0;
-      return pcg_dots(R, 1, xs, ys);
+      if (h->opts.maxit < 1) {
+        R.result = RZ_ERR_NOT_CONVERGED;
+        return pcg_final(R);
+      }
+      return pcg_iteration(R, true);
     }
-    case PcgRun::GOT_RZ0:
-      R.rz = d[0];
-      return pcg_search(R);
-    case PcgRun::GOT_PAP: {
-      const double pAp = d[0];
+    case PcgRun::GOT_RR: {
+      const double pAp = d[0], rr = d[1];
       if (!(pAp > 0)) {
         R.result = fail(h->ctx, RZ_ERR_BREAKDOWN, "CG breakdown: p.Ap <= 0");
         return pcg_final(R);
       }
-      const double a = R.rz / pAp;
-      {
-        Timed tm(h, RZ_K_KRYLOV);
-        launch_cg_update(a, h->kp, h->kAp, R.x, h->kr, h->opts.precision == RZ_PREC_MIXED ? h->kro : nullptr, n,
-                         h->partials, h->dots, s);
-      }
-      ++R.it;
-      HIPCALL(h, hipMemcpyAsync(h->hdots, h->dots, sizeof(double), hipMemcpyDeviceToHost, s));
-      R.ndots = 1;
-      R.phase = PcgRun::GOT_RR;
-      return RZ_OK;
-    }
-    case PcgRun::GOT_RR: {
-      if (std::sqrt(d[0]) <= R.tol) {  // recurrence converged: check the true residual
+      if (std::sqrt(rr) <= R.tol) {  // recurrence converged: check the true residual
         do_residual64(h, R.b, R.x, h->vr);
         launch_dirichlet_copy(h->L, nullptr, h->vr, s);
-        const double *xs[1] = {h->vr};
         R.phase = PcgRun::GOT_TR;
-        return pcg_dots(R, 1, xs, xs);
+        return pcg_norm(R, h->vr);
       }
-      return pcg_precondition(R);
+      if (R.it >= h->opts.maxit) {
+        R.result = RZ_ERR_NOT_CONVERGED;
+        return pcg_final(R);
+      }
+      return pcg_iteration(R, false);
     }
     case PcgRun::GOT_TR: {
       if (std::sqrt(d[0]) <= R.tol) {
@@ -962,15 +975,14 @@ rz_status pcg_step(PcgRun &R) {
         R.phase = PcgRun::DONE;
         return RZ_OK;
       }
-      v_scale_copy(h, 1.0, h->vr, h->kr);
-      return pcg_precondition(R);
-    }
-    case PcgRun::GOT_D2: {
-      const double d1 = h->opts.precision == RZ_PREC_MIXED ? d[1] : 0.0;
-      const double beta = (d[0] - d1) / R.rz;
-      R.rz = d[0];
-      v_xpby(h, h->kz, beta, h->kp);
-      return pcg_search(R);
+      if (R.it >= h->opts.maxit) {
+        R.result = RZ_ERR_NOT_CONVERGED;
+        R.relres = R.nb > 0 ? std::sqrt(d[0]) / R.nb : 0.0;
+        R.phase = PcgRun::DONE;
+        return RZ_OK;
+      }
+      v_scale_copy(h, 1.0, h->vr, h->kr);  // continue from the true residual
+      return pcg_iteration(R, false);
     }
     case PcgRun::GOT_FINAL:
       R.relres = R.nb > 0 ? std::sqrt(d[0]) / R.nb : 0.0;
@@ -1250,9 +1262,9 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
       (e = dalloc(h, &h->vaz, h->ndofs)) || (e = dalloc(h, &h->vr, h->ndofs)) || (e = dalloc(h, &h->kr, h->ndofs)) ||
       (e = dalloc(h, &h->kz, h->ndofs)) || (e = dalloc(h, &h->kp, h->ndofs)) || (e = dalloc(h, &h->kAp, h->ndofs)) ||
       (e = dalloc(h, &h->kro, h->ndofs)) || (e = dalloc(h, &h->partials, dots_partials_size())) ||
-      (e = dalloc(h, &h->dots, 4)))
+      (e = dalloc(h, &h->dots, 8)))
     return bail(e);
-  if (hipHostMalloc((void **)&h->hdots, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+  if (hipHostMalloc((void **)&h->hdots, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return bail(fail(ctx, RZ_ERR_OOM, "pinned host buffer"));
   if (opts->precision == RZ_PREC_DEFECT &&
       ((e = dalloc(h, &h->kp32, h->ndofs)) || (e = dalloc(h, &h->kAp32, h->ndofs)) ||
@@ -1397,41 +1409,69 @@ rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail(hs[i]->ctx, RZ_ERR_ARG, "rz_solve_batched: a problem appears twice");
   }
-  // one running instance per problem (its right-hand sides one after another);
-  // every round enqueues one step of every running instance, then waits for each
+  // One running instance per problem (its right-hand sides one after another).  Each
+  // enqueued step ends with an event; the host advances every instance whose event
+  // has completed, so problems on different streams progress independently and the
+  // device works on one while the host serves another.
   std::vector<PcgRun> run(n);
   std::vector<int> rhs(n, 0);
   std::vector<rz_status> st(n, RZ_OK);
+  std::vector<hipEvent_t> ev(n, nullptr);
+  std::vector<char> pending(n, 0);
   auto start = [&](int i) {
     run[i] = PcgRun();
     run[i].h = hs[i];
     run[i].b = b[i] + (int64_t)rhs[i] * hs[i]->ndofs;
     run[i].x = x[i] + (int64_t)rhs[i] * hs[i]->ndofs;
   };
-  for (int i = 0; i < n; ++i) start(i);
+  for (int i = 0; i < n; ++i) {
+    start(i);
+    if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) {
+      for (int j = 0; j < i; ++j) hipEventDestroy(ev[j]);
+      return fail(hs[i]->ctx, RZ_ERR_HIP, "rz_solve_batched: event creation");
+    }
+  }
+  auto live = [&](int i) { return rhs[i] < nrhs && st[i] == RZ_OK; };
   int active = n;
   while (active > 0) {
-    for (int i = 0; i < n; ++i)
-      if (rhs[i] < nrhs && st[i] == RZ_OK) {
-        rz_status e = pcg_step(run[i]);
-        if (e) st[i] = e;
-      }
+    bool progressed = false;
     for (int i = 0; i < n; ++i) {
-      if (rhs[i] >= nrhs || st[i] != RZ_OK) continue;
-      if (run[i].phase != PcgRun::DONE && hipStreamSynchronize(hs[i]->ctx->stream) != hipSuccess) {
-        st[i] = fail(hs[i]->ctx, RZ_ERR_HIP, "stream synchronisation");
-        continue;
+      if (!live(i)) continue;
+      if (pending[i]) {
+        const hipError_t q = hipEventQuery(ev[i]);
+        if (q == hipErrorNotReady) continue;
+        pending[i] = 0;
+        if (q != hipSuccess) {
+          st[i] = fail(hs[i]->ctx, RZ_ERR_HIP, "stream execution");
+          continue;
+        }
       }
+      progressed = true;
       if (run[i].phase == PcgRun::DONE) {
         rz_solve_info inf{};
         pcg_finish(run[i], &inf);
         if (infos) infos[(int64_t)i * nrhs + rhs[i]] = inf;
-        if (++rhs[i] < nrhs) start(i);
+        if (++rhs[i] >= nrhs) continue;
+        start(i);
+      }
+      rz_status e = pcg_step(run[i]);
+      if (e) {
+        st[i] = e;
+        continue;
+      }
+      if (run[i].phase != PcgRun::DONE) {
+        if (hipEventRecord(ev[i], hs[i]->ctx->stream) != hipSuccess) {
+          st[i] = fail(hs[i]->ctx, RZ_ERR_HIP, "event record");
+          continue;
+        }
+        pending[i] = 1;
       }
     }
     active = 0;
-    for (int i = 0; i < n; ++i) active += (rhs[i] < nrhs && st[i] == RZ_OK);
+    for (int i = 0; i < n; ++i) active += live(i);
+    if (!progressed && active > 0) std::this_thread::yield();
   }
+  for (int i = 0; i < n; ++i) hipEventDestroy(ev[i]);
   for (int i = 0; i < n; ++i)
     if (st[i]) return st[i];
   return RZ_OK;
