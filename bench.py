@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of a kernel group from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0, factors from a plain 1 GiB copy in the same run); the figure belongs
 # to the kernel version it was taken on (profiles/pmc_patch_solve_hgrad_q7_n32.md)
-MEASURED_TRAFFIC = {"patch": 4.401e9}
+MEASURED_TRAFFIC = {}
 METRIC = "GDoF/s sum-factorized apply; PCG time-to-1e-8, FP64 vs mixed, H(grad) p=7"
 
 
@@ -57,13 +57,15 @@ def kernel_bytes(pb, sz, n):
         "apply": 2 * nd * sz + 6 * nc * sz,
         # r read once, interface right-hand side written once
         "condense": (nd + niface) * sz,
-        # every slot: the off-diagonal factor entries once per sweep (forward and
-        # backward), the diagonal once, its interface vector in and out
-        "patch": ns * (2 * (nnz - nrows) + 3 * nrows) * sz,
+        # every slot: its factor (off-diagonals and diagonal, stored once) read once,
+        # its interface vector in and out; both sweeps stream the off-diagonals, the
+        # second read served by the caches or counted by the HBM counters
+        "patch": ns * (nnz + 2 * nrows) * sz,
         # patch solutions read once, r read once, z written once
         "expand": (ns * nrows + 2 * nd) * sz,
-        # dense inverse diagonal blocks of the coarse LDL^T, read in both sweeps
-        "coarse": 2 * (n - 1) * ((n - 1) ** 2) ** 2 * 8,
+        # dense inverse blocks and coupling products of the coarse factorisation
+        # (W, M, N per plane), each read once
+        "coarse": 3 * (n - 1) * ((n - 1) ** 2) ** 2 * 8,
     }
 
 

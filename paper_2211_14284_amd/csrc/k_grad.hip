@@ -477,9 +477,13 @@ __global__ void __launch_bounds__(256) k_condense_xface(LatDev L, const T *__res
 // ------------------------------------------------------------------------------------
 // Relaxation step 2 (eq. sc-asm-afw): L_v L_v^T z_v = rt|_v for every vertex slot.
 // One wavefront per slot, no block barriers: the passes of the wavefront schedule
-// (levels of the forward sweep, then of the backward sweep) run in program order
-// on the slot's vector in LDS, which only this wavefront touches.  The factor
-// values stream in ELL order; the block shares the schedule's index tables in LDS.
+// (levels of the forward sweep) run in program order on the slot's vector in LDS,
+// which only this wavefront touches, each row gathering its entries; then the same
+// passes run in reverse for the transposed solve, each row finishing its value and
+// pushing it to its columns with LDS atomic adds (rows of one pass may share a
+// column; rows of one level never depend on each other).  The off-diagonals are
+// stored once and stream in ELL order in both sweeps; the block shares the
+// schedule's index tables in LDS.
 // Two variants, chosen by measurement: FP32 streams the values into two register
 // buffers used in turn (pass t + 1 loads while pass t computes); FP64 keeps one
 // buffer loaded at the top of each pass, which measured faster for 8-byte values,
@@ -490,21 +494,38 @@ __global__ void __launch_bounds__(256) k_condense_xface(LatDev L, const T *__res
 // sum over the K steps of one lane in a pass of buf[s] * x[col(s)], K uniform: one
 // straight-line body per K so that the LDS reads batch without per-step branches
 template <int KM, typename T, int K = KM>
-__device__ __forceinline__ T pass_dot(int k, const T (&buf)[KM], const unsigned short *ec, const T *xw) {
+__device__ __forceinline__ double pass_dot(int k, const T (&buf)[KM], const unsigned short *ec, const double *xw) {
   if (k == K) {
     int ix[K];
 #pragma unroll
     for (int s = 0; s < K; ++s) ix[s] = ec[64 * s];
-    T acc = 0;
+    double acc = 0;
 #pragma unroll
-    for (int s = 0; s < K; ++s) acc += buf[s] * xw[ix[s]];
+    for (int s = 0; s < K; ++s) acc += (double)buf[s] * xw[ix[s]];
     return acc;
   }
   if constexpr (K > 1) {
     return pass_dot<KM, T, K - 1>(k, buf, ec, xw);
   } else {
-    return T(0);
+    return 0.0;
   }
+}
+
+// w[col(s)] -= buf[s] * xr over the K steps of one lane in a backward pass (the
+// rows of a pass may share columns: LDS atomic adds; zero values, which include
+// the padding, are skipped)
+template <int KM, typename T, int K = KM>
+__device__ __forceinline__ void pass_push(int k, const T (&buf)[KM], const unsigned short *ec, double *xw, double xr) {
+  if (k == K) {
+    int ix[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) ix[s] = ec[64 * s];
+#pragma unroll
+    for (int s = 0; s < K; ++s)
+      if (buf[s] != T(0)) atomicAdd(&xw[ix[s]], -(double)buf[s] * xr);
+    return;
+  }
+  if constexpr (K > 1) pass_push<KM, T, K - 1>(k, buf, ec, xw, xr);
 }
 
 // raw buffer loads (offsets in bytes; out-of-range offsets read 0)
@@ -562,26 +583,41 @@ __global__ void __launch_bounds__(1024) k_patch_solve_s(LatDev L, PatchEllDev E,
       xw[i] = (in && !lat_dirichlet(L, X, Y, Z)) ? rt[lat_index(L, X, Y, Z)] : T(0);
       if (DL) dw[i] = f[i];
     }
+    // pass sequence u = 0 .. 2 np - 1: the passes forward, then the same in reverse
+    auto pass_of = [&](int u) { return u < np ? u : 2 * np - 1 - u; };
     T cur[KM];
     {
       const int K = E.pass[1], base = E.pass[2];
 #pragma unroll
       for (int s = 0; s < KM; ++s) cur[s] = s < K ? fe[base + 64 * s + lane] : T(0);
     }
-    for (int t = 0; t < np; ++t) {
+    for (int u = 0; u < 2 * np; ++u) {
+      const int t = pass_of(u);
       const int G = E.pass[3 * t], K = E.pass[3 * t + 1], base = E.pass[3 * t + 2];
       const unsigned row = erow[64 * t + lane];
       const T piv = DL ? T(1) : (row != 0xFFFFu ? f[row] : T(1));
       T nxt[KM];
-      const int Kn = t + 1 < np ? E.pass[3 * t + 4] : 0, bn = t + 1 < np ? E.pass[3 * t + 5] : 0;
+      const int tn = pass_of(u + 1);
+      const int Kn = u + 1 < 2 * np ? E.pass[3 * tn + 1] : 0, bn = u + 1 < 2 * np ? E.pass[3 * tn + 2] : 0;
 #pragma unroll
       for (int s = 0; s < KM; ++s) nxt[s] = s < Kn ? fe[bn + 64 * s + lane] : T(0);
-      T acc = 0;
+      const bool lead = (lane & (G - 1)) == 0 && row != 0xFFFFu;
+      if (u < np) {  // forward: row gathers L_rc z_c, then z_r = (rt_r - sum) / L_rr
+        T acc = 0;
 #pragma unroll
-      for (int s = 0; s < KM; ++s)
-        if (s < K) acc += cur[s] * xw[ecol[base + 64 * s + lane]];
-      acc = group_sum(acc, G);
-      if ((lane & (G - 1)) == 0 && row != 0xFFFFu) xw[row] = (xw[row] - acc) / (DL ? dw[row] : piv);
+        for (int s = 0; s < KM; ++s)
+          if (s < K) acc += cur[s] * xw[ecol[base + 64 * s + lane]];
+        acc = group_sum(acc, G);
+        if (lead) xw[row] = (xw[row] - acc) / (DL ? dw[row] : piv);
+      } else {  // backward: x_r = w_r / L_rr, then w_c -= L_rc x_r for the row's entries
+        if (lead) xw[row] = xw[row] / (DL ? dw[row] : piv);
+        if (row != 0xFFFFu) {
+          const T xr = xw[row];
+#pragma unroll
+          for (int s = 0; s < KM; ++s)
+            if (s < K && cur[s] != T(0)) atomicAdd(&xw[ecol[base + 64 * s + lane]], -cur[s] * xr);
+        }
+      }
 #pragma unroll
       for (int s = 0; s < KM; ++s) cur[s] = nxt[s];
     }
@@ -597,9 +633,13 @@ __global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nrows = E.nrows, ne = E.ne, np = E.npass, p = L.p;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-  T *xw = reinterpret_cast<T *>(smem_raw) + (size_t)w * 2 * nrows;  // this wavefront's vector
-  T *dw = xw + nrows;                                                  // and diagonal
-  int *off = reinterpret_cast<int *>(reinterpret_cast<T *>(smem_raw) + (size_t)nw * 2 * nrows);
+  // LDS: the wavefronts' vectors (FP64 whatever T is: the sweeps accumulate in FP64,
+  // which also keeps the backward pushes on the FP64 LDS atomic add, several times
+  // faster than the FP32 one), then their diagonals (T), then the shared tables
+  double *xw = reinterpret_cast<double *>(smem_raw) + (size_t)w * nrows;  // this wavefront's vector
+  T *dw = reinterpret_cast<T *>(reinterpret_cast<double *>(smem_raw) + (size_t)nw * nrows) + (size_t)w * nrows;
+  int *off = reinterpret_cast<int *>(reinterpret_cast<T *>(reinterpret_cast<double *>(smem_raw) + (size_t)nw * nrows) +
+                                     (size_t)nw * nrows);
   unsigned short *ecol = reinterpret_cast<unsigned short *>(off + nrows);
   unsigned short *erow = ecol + ne;
   for (int i = tid; i < ne; i += blockDim.x) ecol[i] = (unsigned short)E.ecol[i];
@@ -618,7 +658,7 @@ __global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E,
       const int o = off[i];
       const int X = vx * p + (o & 255) - 64, Y = vy * p + ((o >> 8) & 255) - 64, Z = vz * p + ((o >> 16) & 255) - 64;
       const bool in = X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
-      xw[i] = (in && !lat_dirichlet(L, X, Y, Z)) ? rt[lat_index(L, X, Y, Z)] : T(0);
+      xw[i] = (in && !lat_dirichlet(L, X, Y, Z)) ? (double)rt[lat_index(L, X, Y, Z)] : 0.0;
       dw[i] = f[i];
     }
     // Factor values of pass t through a buffer resource spanning this slot: steps
@@ -632,27 +672,38 @@ __global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E,
 #pragma unroll
       for (int s = 0; s < KM; ++s) buf[s] = buffer_load<T>(fr, s < K ? o + 64 * s * sizeof(T) : 0x80000000u);
     };
-    auto run_pass = [&](const T (&buf)[KM], int t) {
+    // pass sequence u = 0 .. 2 np - 1: the passes forward (gather), then the same in
+    // reverse (push form of the transposed solve)
+    const int nu = 2 * np;
+    auto pass_of = [&](int u) { return u < np ? u : 2 * np - 1 - u; };
+    auto run_pass = [&](const T (&buf)[KM], int u) {
+      const int t = pass_of(u);
       const int G = E.pass[3 * t], K = E.pass[3 * t + 1], base = E.pass[3 * t + 2];
-      T acc = 0;
-      if (K > 0) {
-        acc = pass_dot<KM, T>(K, buf, ecol + base + lane, xw);
-        acc = group_sum(acc, G);
-      }
       const unsigned row = erow[64 * t + lane];
-      if ((lane & (G - 1)) == 0 && row != 0xFFFFu) xw[row] = (xw[row] - acc) / dw[row];
+      const bool lead = (lane & (G - 1)) == 0 && row != 0xFFFFu;
+      if (u < np) {
+        double acc = 0;
+        if (K > 0) {
+          acc = pass_dot<KM, T>(K, buf, ecol + base + lane, xw);
+          acc = group_sum(acc, G);
+        }
+        if (lead) xw[row] = (xw[row] - acc) / (double)dw[row];
+      } else {
+        if (lead) xw[row] = xw[row] / (double)dw[row];
+        if (K > 0 && row != 0xFFFFu) pass_push<KM, T>(K, buf, ecol + base + lane, xw, xw[row]);
+      }
     };
-    // two register buffers in turn: pass t computes while pass t + 1 loads
+    // two register buffers in turn: pass u computes while pass u + 1 loads
     T ba[KM], bb[KM];
-    load_pass(ba, 0);
-    for (int t = 0; t < np; t += 2) {
-      load_pass(bb, min(t + 1, np - 1));
-      run_pass(ba, t);
-      load_pass(ba, min(t + 2, np - 1));
-      if (t + 1 < np) run_pass(bb, t + 1);
+    load_pass(ba, pass_of(0));
+    for (int u = 0; u < nu; u += 2) {
+      load_pass(bb, pass_of(min(u + 1, nu - 1)));
+      run_pass(ba, u);
+      load_pass(ba, pass_of(min(u + 2, nu - 1)));
+      if (u + 1 < nu) run_pass(bb, u + 1);
     }
     T *zo = zbuf + sl * (long)nrows;
-    for (int i = lane; i < nrows; i += 64) zo[i] = xw[i];
+    for (int i = lane; i < nrows; i += 64) zo[i] = (T)xw[i];
   }
 }
 
@@ -1161,58 +1212,74 @@ int device_cu_count() {
   return cus;
 }
 
+// LDS of a patch-solve block: per wavefront row_bytes per patch row, plus the shared
+// schedule tables (row offsets, ELL columns, pass rows)
+static size_t patch_solve_lds(const PatchEllDev &E, size_t row_bytes, int waves) {
+  return (size_t)waves * E.nrows * row_bytes + 4 * (size_t)E.nrows + 2 * (size_t)E.ne + 2 * 64 * (size_t)E.npass;
+}
+
 size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves) {
-  return (size_t)waves * 2 * E.nrows * elem + 4 * (size_t)E.nrows + 2 * (size_t)E.ne + 2 * 64 * (size_t)E.npass;
+  return patch_solve_lds(E, 2 * elem, waves);
+}
+
+// wavefronts per block and blocks per CU for row_bytes of LDS per patch row: 16
+// wavefronts per block when they fit (blocks per CU as the LDS allows, up to 32
+// wavefronts), otherwise the block size with the most resident wavefronts
+static bool patch_solve_shape(const PatchEllDev &E, size_t row_bytes, int &waves, int &per_cu) {
+  constexpr size_t kLds = 160 * 1024;
+  waves = per_cu = 0;
+  int best = 0;
+  for (int w = 16; w >= 1; --w) {
+    const size_t need = patch_solve_lds(E, row_bytes, w);
+    if (need > kLds) continue;
+    int b = (int)(kLds / need);
+    if (b * w > 32) b = 32 / w;
+    if (b * w > best) {
+      best = b * w;
+      waves = w;
+      per_cu = b;
+    }
+  }
+  return waves > 0;
 }
 
 template <typename T>
 int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf, hipStream_t s) {
   const long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
   constexpr size_t kLds = 160 * 1024;
-  int waves = 16;
-  while (waves > 1 && patch_solve_lds_bytes(E, sizeof(T), waves) > kLds) --waves;
-  const size_t shm = patch_solve_lds_bytes(E, sizeof(T), waves);
-  if (shm > kLds) return -1;
-  const int per_cu = 2 * shm <= kLds ? 2 : 1;
-  long grid = (long)device_cu_count() * per_cu;
-  const long need = (nv + waves - 1) / waves;
-  if (grid > need) grid = need;
+  auto grid_of = [&](int waves, int per_cu) {
+    long grid = (long)device_cu_count() * per_cu;
+    const long need = (nv + waves - 1) / waves;
+    return (unsigned)(grid > need ? need : grid);
+  };
   if (sizeof(T) == 8) {  // FP64: the single-buffer kernel
-    if (waves == 16) {  // the diagonal fits in LDS next to the vector at 16 wavefronts per block
+    if (patch_solve_lds(E, 2 * sizeof(T), 16) <= kLds) {
+      // the diagonal fits in LDS next to the vector at 16 wavefronts per block
+      const size_t shm = patch_solve_lds(E, 2 * sizeof(T), 16);
+      const int per_cu = 2 * shm <= kLds ? 2 : 1;
       hipFuncSetAttribute((const void *)k_patch_solve_s<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)shm);
-      k_patch_solve_s<T, true><<<(unsigned)grid, 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv);
+      k_patch_solve_s<T, true><<<grid_of(16, per_cu), 64 * 16, shm, s>>>(L, E, factor, rt, zbuf, nv);
       return 0;
     }
-    // larger patches: pivots from global memory, and the block size that keeps the
-    // most wavefronts resident per CU (LDS-bound; at most 32 wavefronts per CU)
-    const size_t tab = patch_solve_lds_bytes(E, sizeof(T), 0);
-    int w1 = 0, b1 = 0, best = 0;
-    for (int w = 16; w >= 1; --w) {
-      const size_t need = (size_t)w * E.nrows * sizeof(T) + tab;
-      if (need > kLds) continue;
-      int b = (int)(kLds / need);
-      if (b * w > 32) b = 32 / w;
-      if (b * w > best) {
-        best = b * w;
-        w1 = w;
-        b1 = b;
-      }
-    }
-    if (!w1) return -1;
-    const size_t shm1 = (size_t)w1 * E.nrows * sizeof(T) + tab;
-    long grid1 = (long)device_cu_count() * b1;
-    const long need1 = (nv + w1 - 1) / w1;
-    if (grid1 > need1) grid1 = need1;
+    // larger patches: pivots from global memory, residency-maximising blocks
+    int waves, per_cu;
+    if (!patch_solve_shape(E, sizeof(T), waves, per_cu)) return -1;
+    const size_t shm = patch_solve_lds(E, sizeof(T), waves);
     hipFuncSetAttribute((const void *)k_patch_solve_s<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)shm1);
-    k_patch_solve_s<T, false><<<(unsigned)grid1, 64 * w1, shm1, s>>>(L, E, factor, rt, zbuf, nv);
+                        (int)shm);
+    k_patch_solve_s<T, false><<<grid_of(waves, per_cu), 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv);
     return 0;
   }
+  // FP32: the two-buffer kernel, vectors in FP64 and diagonals in T in LDS
+  int waves, per_cu;
+  if (!patch_solve_shape(E, sizeof(double) + sizeof(T), waves, per_cu)) return -1;
+  const size_t shm = patch_solve_lds(E, sizeof(double) + sizeof(T), waves);
+  const unsigned grid = grid_of(waves, per_cu);
 #define RZ_CALL(KM)                                                                                          \
   hipFuncSetAttribute((const void *)k_patch_solve_w<T, KM>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                       (int)shm);                                                                             \
-  k_patch_solve_w<T, KM><<<(unsigned)grid, 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv)
+  k_patch_solve_w<T, KM><<<grid, 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv)
   switch (E.kmax) {
     case 1: RZ_CALL(1); break;
     case 2: RZ_CALL(2); break;

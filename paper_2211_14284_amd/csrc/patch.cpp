@@ -89,11 +89,10 @@ void build_patch_symbolic(int p, PatchSymbolic &ps) {
   build_wave_schedule(ps);
 }
 
-// Lay out one level's rows (forward) or columns (backward) in passes.  items:
-// (row, list of (CSR entry, x index)).  G is the power of two that minimises the
-// padded size with at most kMaxSteps steps per pass (ties: the smaller G).
-static void schedule_level(PatchSymbolic &ps, std::vector<std::pair<int, std::vector<std::pair<int, int>>>> items,
-                           bool forward) {
+// Lay out one level's rows in passes.  items: (row, list of (CSR entry, x index)).
+// G is the power of two that minimises the padded size with at most kMaxSteps
+// steps per pass (ties: the smaller G).
+static void schedule_level(PatchSymbolic &ps, std::vector<std::pair<int, std::vector<std::pair<int, int>>>> items) {
   const int W = PatchSymbolic::kLanes, KM = PatchSymbolic::kMaxSteps;
   std::stable_sort(items.begin(), items.end(),
                    [](const auto &a, const auto &b) { return a.second.size() > b.second.size(); });
@@ -131,7 +130,7 @@ static void schedule_level(PatchSymbolic &ps, std::vector<std::pair<int, std::ve
       for (int m = 0; m < (int)it.second.size(); ++m) {
         const int pos = base + (m / G) * W + j * G + (m % G);
         ps.ecol[pos] = it.second[m].second;
-        (forward ? ps.pos1 : ps.pos2)[it.second[m].first] = ps.nrows + pos;
+        ps.pos1[it.second[m].first] = ps.nrows + pos;
       }
     }
   }
@@ -156,24 +155,14 @@ void build_wave_schedule(PatchSymbolic &ps) {
         for (int k = ps.rowptr[r]; k < ps.rowptr[r + 1] - 1; ++k) e.push_back({k, ps.col[k]});
         items.push_back({r, e});
       }
-    schedule_level(ps, items, true);
+    schedule_level(ps, items);
   }
   ps.nfpass = (int)ps.pass_g.size();
   ps.ef = (int)ps.ecol.size();
-  // backward: column i gathers L_ji x_j, j > i, levels in reverse
-  for (int l = ps.nlev - 1; l >= 0; --l) {
-    std::vector<std::pair<int, std::vector<std::pair<int, int>>>> items;
-    for (int i = 0; i < n; ++i)
-      if (ps.level[i] == l) {
-        std::vector<std::pair<int, int>> e;
-        for (int t = ps.uptr[i]; t < ps.uptr[i + 1]; ++t) e.push_back({ps.upos[t], ps.urow[t]});
-        items.push_back({i, e});
-      }
-    schedule_level(ps, items, false);
-  }
-  ps.npass = (int)ps.pass_g.size();
-  ps.eb = (int)ps.ecol.size() - ps.ef;
-  ps.stride = n + ps.ef + ps.eb;
+  // the backward sweep reuses these passes in reverse (push form): no second copy
+  ps.npass = ps.nfpass;
+  ps.eb = 0;
+  ps.stride = n + ps.ef;
 }
 
 }  // namespace rz

@@ -21,18 +21,20 @@ struct PatchSymbolic {
   std::vector<int> level;          // forward level of every row
 
   // Wavefront schedule of the two sweeps (one 64-lane wavefront per patch).  A
-  // pass works on up to 64/G rows (forward) or columns (backward) of one level,
-  // G lanes each; lane j*G+q takes entries q, q+G, ... of its row, so step s of
-  // the pass reads ELL position base + 64 s + lane.  A slot's factor values are
-  // [diagonal (nrows)] [forward ELL (ef)] [backward ELL (eb)], padding zero, so
-  // each sweep streams its values once, coalesced.
+  // pass works on up to 64/G rows of one forward level, G lanes each; lane j*G+q
+  // takes entries q, q+G, ... of its row, so step s of the pass reads ELL position
+  // base + 64 s + lane.  A slot's factor values are [diagonal (nrows)] [ELL (ef)],
+  // padding zero.  The forward sweep runs the passes in order, each row gathering
+  // its entries (L z = r); the backward sweep runs the same passes in reverse, each
+  // row first finishing x_j = w_j / L_jj and then pushing L_ji x_j to its columns
+  // (L^T x = z), so the off-diagonals are stored and streamed once per sweep.
   static constexpr int kLanes = 64, kMaxSteps = 8;
-  int npass = 0, nfpass = 0, ef = 0, eb = 0, stride = 0;
+  int npass = 0, nfpass = 0, ef = 0, eb = 0, stride = 0;  // eb = 0, npass = nfpass
   std::vector<int> pass_g, pass_k, pass_base;  // per pass: lanes per row, steps, ELL offset
-  std::vector<int> ecol;   // ef + eb: index of the x entry read at each ELL position (padding 0)
+  std::vector<int> ecol;   // ef: index of the x entry read at each ELL position (padding 0)
   std::vector<int> erow;   // npass*64: row solved by the lane's group (-1: none)
-  std::vector<int> pos1;   // nnz: CSR entry -> value position in the slot (diagonal or forward ELL)
-  std::vector<int> pos2;   // nnz: CSR entry -> backward ELL value position (-1 for the diagonal)
+  std::vector<int> pos1;   // nnz: CSR entry -> value position in the slot (diagonal or ELL)
+  std::vector<int> pos2;   // nnz: all -1 (no second copy of the off-diagonals)
 };
 
 // Build the layout and the static-condensation pattern of a full (untruncated)
