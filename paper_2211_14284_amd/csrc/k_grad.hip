@@ -484,12 +484,9 @@ __global__ void __launch_bounds__(256) k_condense_xface(LatDev L, const T *__res
 // column; rows of one level never depend on each other).  The off-diagonals are
 // stored once and stream in ELL order in both sweeps; the block shares the
 // schedule's index tables in LDS.
-// Two variants, chosen by measurement: FP32 streams the values into two register
-// buffers used in turn (pass t + 1 loads while pass t computes); FP64 keeps one
-// buffer loaded at the top of each pass, which measured faster for 8-byte values,
-// with the slot's diagonal in LDS while 16 wavefronts per block still fit (p <= 7)
-// and pivots read from global memory for larger patches, where residency matters
-// more (p = 8: 1.16 -> 0.81 ms per launch measured on C5).
+// The values stream into two register buffers used in turn (pass u + 1 loads while
+// pass u computes) through a buffer resource spanning the slot.  The slot's vector
+// is kept in FP64 in LDS for both precisions (the FP32 factor is widened on use).
 // ------------------------------------------------------------------------------------
 // sum over the K steps of one lane in a pass of buf[s] * x[col(s)], K uniform: one
 // straight-line body per K so that the LDS reads batch without per-step branches
@@ -546,84 +543,6 @@ template <typename T>
 __device__ __forceinline__ T group_sum(T s, int G) {
   for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   return s;
-}
-
-// Single-buffer variant (FP64): the next pass's values are loaded at the top of
-// each pass, steps only up to K.  DL: the slot's diagonal is copied to LDS next to
-// the vector; otherwise each pass loads its pivots from global memory (cached), which
-// halves the LDS per wavefront and lets more wavefronts share a CU.
-template <typename T, bool DL>
-__global__ void __launch_bounds__(1024) k_patch_solve_s(LatDev L, PatchEllDev E, const T *__restrict__ factor,
-                                                         const T *__restrict__ rt, T *__restrict__ zbuf,
-                                                         long nslots) {
-  constexpr int KM = 8;  // at most kMaxSteps steps per pass
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int nrows = E.nrows, ne = E.ne, np = E.npass, p = L.p;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-  constexpr int VW = DL ? 2 : 1;  // per-wavefront LDS vectors: x (and the diagonal)
-  T *xw = reinterpret_cast<T *>(smem_raw) + (size_t)w * VW * nrows;  // this wavefront's vector
-  T *dw = xw + nrows;                                                   // and diagonal (DL)
-  int *off = reinterpret_cast<int *>(reinterpret_cast<T *>(smem_raw) + (size_t)nw * VW * nrows);
-  unsigned short *ecol = reinterpret_cast<unsigned short *>(off + nrows);
-  unsigned short *erow = ecol + ne;
-  for (int i = tid; i < ne; i += blockDim.x) ecol[i] = (unsigned short)E.ecol[i];
-  for (int i = tid; i < np * 64; i += blockDim.x) erow[i] = (unsigned short)(E.erow[i] & 0xFFFF);
-  for (int i = tid; i < nrows; i += blockDim.x)
-    off[i] = (E.off[3 * i] + 64) | ((E.off[3 * i + 1] + 64) << 8) | ((E.off[3 * i + 2] + 64) << 16);
-  __syncthreads();
-  const int nvx = L.nx + 1, nvy = L.ny + 1;
-  for (long sl = (long)blockIdx.x * nw + w; sl < nslots; sl += (long)gridDim.x * nw) {
-    const T *f = factor + sl * (long)E.stride;
-    const T *fe = f + nrows;
-    const int vx = sl % nvx, vy = (sl / nvx) % nvy, vz = sl / ((long)nvx * nvy);
-    for (int i = lane; i < nrows; i += 64) {
-      const int o = off[i];
-      const int X = vx * p + (o & 255) - 64, Y = vy * p + ((o >> 8) & 255) - 64, Z = vz * p + ((o >> 16) & 255) - 64;
-      const bool in = X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
-      xw[i] = (in && !lat_dirichlet(L, X, Y, Z)) ? rt[lat_index(L, X, Y, Z)] : T(0);
-      if (DL) dw[i] = f[i];
-    }
-    // pass sequence u = 0 .. 2 np - 1: the passes forward, then the same in reverse
-    auto pass_of = [&](int u) { return u < np ? u : 2 * np - 1 - u; };
-    T cur[KM];
-    {
-      const int K = E.pass[1], base = E.pass[2];
-#pragma unroll
-      for (int s = 0; s < KM; ++s) cur[s] = s < K ? fe[base + 64 * s + lane] : T(0);
-    }
-    for (int u = 0; u < 2 * np; ++u) {
-      const int t = pass_of(u);
-      const int G = E.pass[3 * t], K = E.pass[3 * t + 1], base = E.pass[3 * t + 2];
-      const unsigned row = erow[64 * t + lane];
-      const T piv = DL ? T(1) : (row != 0xFFFFu ? f[row] : T(1));
-      T nxt[KM];
-      const int tn = pass_of(u + 1);
-      const int Kn = u + 1 < 2 * np ? E.pass[3 * tn + 1] : 0, bn = u + 1 < 2 * np ? E.pass[3 * tn + 2] : 0;
-#pragma unroll
-      for (int s = 0; s < KM; ++s) nxt[s] = s < Kn ? fe[bn + 64 * s + lane] : T(0);
-      const bool lead = (lane & (G - 1)) == 0 && row != 0xFFFFu;
-      if (u < np) {  // forward: row gathers L_rc z_c, then z_r = (rt_r - sum) / L_rr
-        T acc = 0;
-#pragma unroll
-        for (int s = 0; s < KM; ++s)
-          if (s < K) acc += cur[s] * xw[ecol[base + 64 * s + lane]];
-        acc = group_sum(acc, G);
-        if (lead) xw[row] = (xw[row] - acc) / (DL ? dw[row] : piv);
-      } else {  // backward: x_r = w_r / L_rr, then w_c -= L_rc x_r for the row's entries
-        if (lead) xw[row] = xw[row] / (DL ? dw[row] : piv);
-        if (row != 0xFFFFu) {
-          const T xr = xw[row];
-#pragma unroll
-          for (int s = 0; s < KM; ++s)
-            if (s < K && cur[s] != T(0)) atomicAdd(&xw[ecol[base + 64 * s + lane]], -cur[s] * xr);
-        }
-      }
-#pragma unroll
-      for (int s = 0; s < KM; ++s) cur[s] = nxt[s];
-    }
-    T *zo = zbuf + sl * (long)nrows;
-    for (int i = lane; i < nrows; i += 64) zo[i] = xw[i];
-  }
 }
 
 template <typename T, int KM>
@@ -1246,32 +1165,12 @@ static bool patch_solve_shape(const PatchEllDev &E, size_t row_bytes, int &waves
 template <typename T>
 int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf, hipStream_t s) {
   const long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
-  constexpr size_t kLds = 160 * 1024;
   auto grid_of = [&](int waves, int per_cu) {
     long grid = (long)device_cu_count() * per_cu;
     const long need = (nv + waves - 1) / waves;
     return (unsigned)(grid > need ? need : grid);
   };
-  if (sizeof(T) == 8) {  // FP64: the single-buffer kernel
-    if (patch_solve_lds(E, 2 * sizeof(T), 16) <= kLds) {
-      // the diagonal fits in LDS next to the vector at 16 wavefronts per block
-      const size_t shm = patch_solve_lds(E, 2 * sizeof(T), 16);
-      const int per_cu = 2 * shm <= kLds ? 2 : 1;
-      hipFuncSetAttribute((const void *)k_patch_solve_s<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)shm);
-      k_patch_solve_s<T, true><<<grid_of(16, per_cu), 64 * 16, shm, s>>>(L, E, factor, rt, zbuf, nv);
-      return 0;
-    }
-    // larger patches: pivots from global memory, residency-maximising blocks
-    int waves, per_cu;
-    if (!patch_solve_shape(E, sizeof(T), waves, per_cu)) return -1;
-    const size_t shm = patch_solve_lds(E, sizeof(T), waves);
-    hipFuncSetAttribute((const void *)k_patch_solve_s<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)shm);
-    k_patch_solve_s<T, false><<<grid_of(waves, per_cu), 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv);
-    return 0;
-  }
-  // FP32: the two-buffer kernel, vectors in FP64 and diagonals in T in LDS
+  // vectors in FP64 and diagonals in T in LDS
   int waves, per_cu;
   if (!patch_solve_shape(E, sizeof(double) + sizeof(T), waves, per_cu)) return -1;
   const size_t shm = patch_solve_lds(E, sizeof(double) + sizeof(T), waves);
