@@ -1141,10 +1141,10 @@ size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves) {
   return patch_solve_lds(E, 2 * elem, waves);
 }
 
-// wavefronts per block and blocks per CU for row_bytes of LDS per patch row: 16
-// wavefronts per block when they fit (blocks per CU as the LDS allows, up to 32
-// wavefronts), otherwise the block size with the most resident wavefronts
-static bool patch_solve_shape(const PatchEllDev &E, size_t row_bytes, int &waves, int &per_cu) {
+// wavefronts per block and blocks per CU for row_bytes of LDS per patch row: the
+// block size with the most resident wavefronts per CU, at most cap (ties: larger
+// blocks)
+static bool patch_solve_shape(const PatchEllDev &E, size_t row_bytes, int cap, int &waves, int &per_cu) {
   constexpr size_t kLds = 160 * 1024;
   waves = per_cu = 0;
   int best = 0;
@@ -1152,7 +1152,7 @@ static bool patch_solve_shape(const PatchEllDev &E, size_t row_bytes, int &waves
     const size_t need = patch_solve_lds(E, row_bytes, w);
     if (need > kLds) continue;
     int b = (int)(kLds / need);
-    if (b * w > 32) b = 32 / w;
+    if (b * w > cap) b = cap / w;
     if (b * w > best) {
       best = b * w;
       waves = w;
@@ -1170,9 +1170,12 @@ int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, c
     const long need = (nv + waves - 1) / waves;
     return (unsigned)(grid > need ? need : grid);
   };
-  // vectors in FP64 and diagonals in T in LDS
+  // vectors in FP64 and diagonals in T in LDS; at most 12 resident wavefronts per CU
+  // for FP64 (measured at p = 7: 12 -> 0.70 ms, 16 -> 0.73 ms, 8 -> 0.77 ms per launch;
+  // fewer slots in flight keep more of the factor cached between the two sweeps),
+  // as many as fit for FP32 (18 at p = 7: 0.42 ms; 12: 0.57 ms)
   int waves, per_cu;
-  if (!patch_solve_shape(E, sizeof(double) + sizeof(T), waves, per_cu)) return -1;
+  if (!patch_solve_shape(E, sizeof(double) + sizeof(T), sizeof(T) == 8 ? 12 : 32, waves, per_cu)) return -1;
   const size_t shm = patch_solve_lds(E, sizeof(double) + sizeof(T), waves);
   const unsigned grid = grid_of(waves, per_cu);
 #define RZ_CALL(KM)                                                                                          \
