@@ -142,7 +142,9 @@ __global__ void __launch_bounds__(CPC *(P + 1) * (P + 1), 4)
   // LDS tile of a cell: element (a, b, c) at a + SB b + SC c, cells CS apart; the
   // padding spreads the lanes of the z-, y- and x-line passes over the banks
   constexpr int SB = N1 + 1, SC = SB * N1, CS = SC * N1 + 8;
-  __shared__ T S0[CPC * CS], S1[CPC * CS], CR[2][NL];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *S0 = reinterpret_cast<T *>(smem_raw), *S1 = S0 + CPC * CS;
+  T(*CR)[NL] = reinterpret_cast<T(*)[NL]>(S1 + CPC * CS);  // x = P face carried between chunks
   const int tid = threadIdx.x, lc = tid / NL, l = tid % NL;
   const int pen = xcd_block(blockIdx.x, gridDim.x);
   const int ey = pen % L.ny, ez = pen / L.ny;
@@ -1061,13 +1063,19 @@ template <int P, typename T>
 static void apply_pencil(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x,
                          const T *bsub, T *y, T *fb, hipStream_t s) {
   constexpr int NL = (P + 1) * (P + 1);
-  constexpr int CPC = NL >= 256 ? 1 : 256 / NL;
+  // cells per chunk: 512 threads for P = 6, 7 (fewer, larger chunks per row of cells;
+  // two blocks per CU), 256 otherwise
+  constexpr int CPC = (P == 6 || P == 7) ? 512 / NL : (NL >= 256 ? 1 : 256 / NL);
+  constexpr int N1 = P + 1, CS = (N1 + 1) * N1 * N1 + 8;
+  const size_t shm = (2 * (size_t)CPC * CS + 2 * NL) * sizeof(T);
+  if (shm > 64 * 1024)
+    hipFuncSetAttribute((const void *)k_apply_pencil<P, T, CPC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   Tab1D<P, T> tb;
   for (int i = 0; i < (P + 1) * (P + 1); ++i) {
     tb.B[i] = (T)Bh[i];
     tb.A[i] = (T)Ah[i];
   }
-  k_apply_pencil<P, T, CPC><<<(unsigned)(L.ny * L.nz), CPC * NL, 0, s>>>(L, tb, coef, x, bsub, y, fb);
+  k_apply_pencil<P, T, CPC><<<(unsigned)(L.ny * L.nz), CPC * NL, shm, s>>>(L, tb, coef, x, bsub, y, fb);
   const long nlines = (long)(L.ny + 1) * L.Nz + (long)(L.nz + 1) * (L.Ny - L.ny - 1);
   const long n = nlines * L.Nx;
   k_apply_faces<P, T><<<nblocks(n, 256), 256, 0, s>>>(L, x, fb, bsub, y, n);
