@@ -934,6 +934,118 @@ __global__ void __launch_bounds__(256) k_prolong_add_p(LatDev L, const double *_
   }
 }
 
+// Coarse correction and the residual after it, in one pass per lattice row:
+//   z += P xc,   r -= A P xc   (r holds r - A z_old on entry, r - A z_new on exit).
+// P xc is trilinear in each cell, so (A P xc)_K = s1 (AE x BE x BE) c + s2 (BE x AE x BE) c
+// + s3 (BE x BE x AE) c + mu (BE x BE x BE) c with c the cell's 8 coarse corner
+// values and AE = A E, BE = B E the (p+1) x 2 products of the 1-D tables with the
+// hat embedding E (cellwise-constant weights on Cartesian cells).  Coarse Dirichlet
+// vertices count as 0, which also makes P xc vanish on fine Dirichlet points; fine
+// Dirichlet rows keep z and r.  The block stages the (up to 9) coarse x-lines around
+// the row and the weights of the row's cells in LDS.
+template <int P>
+__global__ void __launch_bounds__(256) k_prolong_residual_p(LatDev L, const double *__restrict__ E,
+                                                            const double *__restrict__ T2, const double *__restrict__ coef,
+                                                            const double *__restrict__ xc, double *__restrict__ z,
+                                                            double *__restrict__ r) {
+  // block: the lattice rows Y = cy P .. cy P + P - 1 (and Y = ny P in the last layer)
+  // of one z-coordinate Z; they share the coarse lines at vertices cy - 1 .. cy + 1
+  // along y and the weights of the cells cy - 1, cy
+  extern __shared__ double sm[];
+  const int nv = L.nx + 1;
+  double *lines = sm;                 // [3 (vy = cy-1+d)][3 (vz = vz0+d)][nv]
+  double *cw = lines + 9 * nv;        // [2 (cy-1, cy)][2 (z cells)][nx][4]
+  double *tb = cw + 16 * L.nx;        // [2][P+1][2]: AE, BE
+  const int cy = blockIdx.x % L.ny, Z = blockIdx.x / L.ny;
+  int czv[2], bzv[2], nz = 0;
+  if (Z % P == 0) {
+    if (Z / P > 0) { czv[nz] = Z / P - 1; bzv[nz++] = P; }
+    if (Z / P < L.nz) { czv[nz] = Z / P; bzv[nz++] = 0; }
+  } else {
+    czv[0] = Z / P; bzv[0] = Z % P; nz = 1;
+  }
+  const int vz0 = czv[0];
+  const long sy = nv, sz = (long)nv * (L.ny + 1);
+  for (int t = threadIdx.x; t < 9 * nv; t += blockDim.x) {
+    const int v = t % nv, d = t / nv, vy = cy - 1 + d % 3, vz = vz0 + d / 3;
+    double val = 0.0;
+    if (vy >= 0 && vy <= L.ny && vz <= L.nz) {
+      const bool dir = ((L.dir & 1u) && v == 0) || ((L.dir & 2u) && v == L.nx) || ((L.dir & 4u) && vy == 0) ||
+                       ((L.dir & 8u) && vy == L.ny) || ((L.dir & 16u) && vz == 0) || ((L.dir & 32u) && vz == L.nz);
+      val = dir ? 0.0 : xc[v + sy * vy + sz * vz];
+    }
+    lines[t] = val;
+  }
+  for (int t = threadIdx.x; t < 16 * L.nx; t += blockDim.x) {
+    const int q = t % 4, cx = (t / 4) % L.nx, iy = (t / (4 * L.nx)) % 2, iz = t / (8 * L.nx);
+    const int ccy = cy - 1 + iy;
+    cw[t] = (ccy >= 0 && iz < nz) ? coef[6 * (cx + (long)L.nx * (ccy + (long)L.ny * czv[iz])) + q] : 0.0;
+  }
+  for (int t = threadIdx.x; t < 4 * (P + 1); t += blockDim.x) tb[t] = T2[t];
+  __syncthreads();
+  if (lat_dirichlet_axis(L, 2, Z)) return;
+  const double *AE = tb, *BE = tb + 2 * (P + 1);
+  const int pz = min(Z / P, L.nz - 1), az = Z - pz * P;
+  const double wz[2] = {E[2 * az], E[2 * az + 1]};
+  const int nrow = cy + 1 == L.ny ? P + 1 : P;
+  for (int t = threadIdx.x; t < nrow * L.Nx; t += blockDim.x) {
+    const int X = t % L.Nx, Y = cy * P + t / L.Nx;
+    if (lat_dirichlet_axis(L, 0, X) || lat_dirichlet_axis(L, 1, Y)) continue;
+    // the cells containing the point along y (index into the staged cells: cy - 1 + iy)
+    int iyv[2], byv[2], ny = 0;
+    if (Y % P == 0) {
+      if (Y / P > 0) { iyv[ny] = Y / P - 1 - (cy - 1); byv[ny++] = P; }
+      if (Y / P < L.ny) { iyv[ny] = Y / P - (cy - 1); byv[ny++] = 0; }
+    } else {
+      iyv[0] = 1; byv[0] = Y % P; ny = 1;
+    }
+    // z += P xc (cell cy along y, the last cell for the last vertex plane)
+    const int ay = Y - cy * P;
+    const int px = min(X / P, L.nx - 1), ax = X - px * P;
+    double pacc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const double *ln = lines + nv * ((1 + j) + 3 * (pz + k - vz0));
+        pacc += wz[k] * E[2 * ay + j] * (E[2 * ax] * ln[px] + E[2 * ax + 1] * ln[px + 1]);
+      }
+    // r -= A P xc, summed over the cells containing the point
+    int cxv[2], bxv[2], nx = 0;
+    if (X % P == 0) {
+      if (X / P > 0) { cxv[nx] = X / P - 1; bxv[nx++] = P; }
+      if (X / P < L.nx) { cxv[nx] = X / P; bxv[nx++] = 0; }
+    } else {
+      cxv[0] = X / P; bxv[0] = X % P; nx = 1;
+    }
+    double acc = 0.0;
+    for (int iz = 0; iz < nz; ++iz)
+      for (int i2 = 0; i2 < ny; ++i2) {
+        const int iy = iyv[i2], b = byv[i2];
+        const double By[2] = {BE[2 * b], BE[2 * b + 1]}, Ay[2] = {AE[2 * b], AE[2 * b + 1]};
+        const double Bz[2] = {BE[2 * bzv[iz]], BE[2 * bzv[iz] + 1]}, Az[2] = {AE[2 * bzv[iz]], AE[2 * bzv[iz] + 1]};
+        for (int ix = 0; ix < nx; ++ix) {
+          const int cx = cxv[ix], a = bxv[ix];
+          const double *s = cw + 4 * (cx + L.nx * (iy + 2 * iz));
+          const double Ax0 = AE[2 * a], Ax1 = AE[2 * a + 1], Bx0 = BE[2 * a], Bx1 = BE[2 * a + 1];
+#pragma unroll
+          for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              // cell (cy - 1 + iy) spans the vertex lines iy + j (= vy - (cy - 1))
+              const double *ln = lines + nv * ((iy + j) + 3 * (czv[iz] + k - vz0));
+              const double c0 = ln[cx], c1 = ln[cx + 1];
+              const double ax_ = Ax0 * c0 + Ax1 * c1, bx_ = Bx0 * c0 + Bx1 * c1;
+              acc += s[0] * ax_ * By[j] * Bz[k] + bx_ * (s[1] * Ay[j] * Bz[k] + s[2] * By[j] * Az[k] + s[3] * By[j] * Bz[k]);
+            }
+        }
+      }
+    const long g = (long)X + (long)L.Nx * (Y + (long)L.Ny * Z);
+    z[g] += pacc;
+    r[g] -= acc;
+  }
+}
+
 // Restriction rc = P^T rf as three 1-D passes (x, then y, then z); the weight of a
 // fine coordinate X for coarse vertex V is E[X - (V-1)p][1] left of V p, 1 at V p,
 // E[X - V p][0] right of it.  Fine Dirichlet entries are read as zero, coarse
@@ -1244,6 +1356,15 @@ void launch_prolong_add_grad(const LatDev &L, const double *E, const double *xc,
   const int bs = L.Nx >= 256 ? 256 : ((L.Nx + 63) / 64) * 64;
   const size_t shm = (L.nx + 1) * sizeof(double);
 #define RZ_CALL(Q) k_prolong_add_p<Q><<<grid, bs, shm, s>>>(L, E, xc, xf)
+  RZ_DISPATCH_P(L.p, RZ_CALL)
+#undef RZ_CALL
+}
+
+void launch_prolong_residual_grad(const LatDev &L, const double *E, const double *T2, const double *coef,
+                                  const double *xc, double *z, double *r, hipStream_t s) {
+  const unsigned grid = (unsigned)((long)L.ny * L.Nz);
+  const size_t shm = (9 * (size_t)(L.nx + 1) + 16 * (size_t)L.nx + 4 * (size_t)(L.p + 1)) * sizeof(double);
+#define RZ_CALL(Q) k_prolong_residual_p<Q><<<grid, 256, shm, s>>>(L, E, T2, coef, xc, z, r)
   RZ_DISPATCH_P(L.p, RZ_CALL)
 #undef RZ_CALL
 }

@@ -59,6 +59,7 @@ struct rz_problem {
   PatchEllDev PE{};
   std::vector<void *> allocs;
   double *coef64 = nullptr, *B64 = nullptr, *A64 = nullptr, *lam64 = nullptr, *E64 = nullptr;
+  double *T2_64 = nullptr;  // (p+1) x 2 products A E, then B E (fused coarse correction and residual)
   float *coef32 = nullptr, *B32 = nullptr, *A32 = nullptr, *lam32 = nullptr;
   // H(curl) / H(div): apply only
   int space = RZ_GRAD;
@@ -318,11 +319,16 @@ rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
     launch_restrict_grad(h->L, h->E64, h->vr, h->rc, h->rt1, h->rt2, s);
   }
   do_coarse(h, h->rc, h->xc);
-  {
+  if (h->T2_64) {  // z += P xc and r2 = r1 - A P xc in one pass
     Timed tm(h, RZ_K_TRANSFER);
-    launch_prolong_add_grad(h->L, h->E64, h->xc, z, s);   // z += P A0^{-1} P^T r1
+    launch_prolong_residual_grad(h->L, h->E64, h->T2_64, h->coef64, h->xc, z, h->vr, s);
+  } else {
+    {
+      Timed tm(h, RZ_K_TRANSFER);
+      launch_prolong_add_grad(h->L, h->E64, h->xc, z, s);   // z += P A0^{-1} P^T r1
+    }
+    do_residual64(h, r, z, h->vr);           // r2 = r - A z
   }
-  do_residual64(h, r, z, h->vr);           // r2 = r - A z
   do_relax_prec(h, h->vr, h->vt, 1.0, w, z);  // z += w M r2
   launch_dirichlet_copy(h->L, r, z, s);
   return RZ_OK;
@@ -1209,6 +1215,16 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
       (e = upload(h, &h->lam64, lamf)) || (e = upload(h, &h->E64, h->t.E)) || (e = upload(h, &h->coef32, c32)) ||
       (e = upload(h, &h->B32, B32)) || (e = upload(h, &h->A32, A32)) || (e = upload(h, &h->lam32, l32)))
     return bail(e);
+  if (!h->quad) {  // A E and B E for the fused coarse correction and residual
+    std::vector<double> T2(4 * (size_t)n1, 0.0);
+    for (int a = 0; a < n1; ++a)
+      for (int i = 0; i < 2; ++i)
+        for (int m = 0; m < n1; ++m) {
+          T2[2 * a + i] += h->t.A[a * n1 + m] * h->t.E[2 * m + i];
+          T2[2 * n1 + 2 * a + i] += h->t.B[a * n1 + m] * h->t.E[2 * m + i];
+        }
+    if ((e = upload(h, &h->T2_64, T2))) return bail(e);
+  }
   if (h->quad) {
     auto to32 = [](const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); };
     const QuadTables &qt = h->qt;
