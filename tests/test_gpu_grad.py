@@ -120,11 +120,17 @@ def test_ic_factor_parity(rz, ctx, n, p):
         assert np.abs(L[~mask]).max(initial=0.0) == 0.0
 
 
-@pytest.mark.parametrize("n,p", [((3, 2, 4), 3), ((4, 4, 4), 4), ((3, 3, 3), 7)])
-def test_relax_parity(rz, ctx, n, p):
+# every degree (each has its own pass schedule), full and partial Dirichlet masks
+RELAX_CASES = [((3, 2, 4), 3, 0x3F), ((4, 4, 4), 4, 0x3F), ((3, 3, 3), 7, 0x3F), ((3, 3, 2), 1, 0x3F),
+               ((2, 3, 2), 2, 0x15), ((3, 2, 3), 5, 0x2A), ((2, 2, 3), 6, 0x3F), ((2, 2, 2), 8, 0x15),
+               ((2, 2, 2), 9, 0x3F), ((3, 2, 2), 7, 0x0C)]
+
+
+@pytest.mark.parametrize("n,p,dirichlet", RELAX_CASES)
+def test_relax_parity(rz, ctx, n, p, dirichlet):
     al, be = coefs(n)
-    ref = Ref(n, p, al, be)
-    pb = rz.Problem(ctx, n, p, al, be, omega=0.3)
+    ref = Ref(n, p, al, be, dirichlet=dirichlet)
+    pb = rz.Problem(ctx, n, p, al, be, omega=0.3, dirichlet=dirichlet)
     r = np.where(ref.mask, 0.0, synth.uniform_pm1(11, ref.lat.ndofs))
     z_ref = ref.R.apply(r)
     z = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
@@ -151,7 +157,9 @@ def test_transfer_parity(rz, ctx, n, p):
     assert rel(H(rc), ref.Pr.T @ np.where(ref.mask, 0.0, rf)) < 1e-13
 
 
-@pytest.mark.parametrize("n", [(3, 2, 4), (5, 4, 3), (8, 8, 8)])
+# 1 to 7 free coarse planes (the middle plane of the twisted factorisation and the
+# halves around it in every arrangement)
+@pytest.mark.parametrize("n", [(3, 2, 4), (5, 4, 3), (8, 8, 8), (3, 3, 2), (4, 3, 5), (3, 4, 6)])
 def test_coarse_solve_parity(rz, ctx, n):
     al, be = coefs(n)
     ref = Ref(n, 2, al, be)
@@ -162,12 +170,14 @@ def test_coarse_solve_parity(rz, ctx, n):
     assert rel(H(xc), ref.cs.solve(rc)) < 1e-12
 
 
-@pytest.mark.parametrize("n,p", [((3, 2, 4), 3), ((4, 4, 4), 4)])
-def test_vcycle_parity(rz, ctx, n, p):
+# includes the coarse correction fused with the residual after it (Cartesian cells)
+@pytest.mark.parametrize("n,p,dirichlet", [((3, 2, 4), 3, 0x3F), ((4, 4, 4), 4, 0x3F), ((3, 3, 3), 7, 0x3F),
+                                           ((3, 4, 3), 5, 0x15), ((3, 3, 4), 2, 0x2A)])
+def test_vcycle_parity(rz, ctx, n, p, dirichlet):
     al, be = coefs(n)
-    ref = Ref(n, p, al, be)
+    ref = Ref(n, p, al, be, dirichlet=dirichlet)
     om = 0.37
-    pb = rz.Problem(ctx, n, p, al, be, omega=om)
+    pb = rz.Problem(ctx, n, p, al, be, omega=om, dirichlet=dirichlet)
     V = pmg.VCycle(ref.lat, ref.A, ref.R, ref.Pr, ref.cs, om)
     r = np.where(ref.mask, 0.0, synth.uniform_pm1(41, ref.lat.ndofs))
     z = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
