@@ -360,15 +360,25 @@ __device__ __forceinline__ T interior_scaled(const T *coef, long ce, const T *la
 // Rows on a y- or z-vertex plane: every point is a plane point; the normal lines
 // run across rows (coalesced over the lanes).  Rows inside a cross section: only
 // the x-face points (X on an x-vertex plane) are plane points; the row of r is
-// handled by k_condense_xface.  Interior points of rt are not written.
+// handled by extra blocks of the same launch.  Interior points of rt are not written.
+template <int P, typename T>
+__device__ void condense_xface(const LatDev &L, const T *__restrict__ coef, const T *__restrict__ Ag,
+                               const T *__restrict__ lam, const T *__restrict__ r, T *__restrict__ rt, long t,
+                               long n);
+
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_condense_rows(LatDev L, const T *__restrict__ coef,
                                                        const T *__restrict__ Ag, const T *__restrict__ lam,
-                                                       const T *__restrict__ r, T *__restrict__ rt) {
+                                                       const T *__restrict__ r, T *__restrict__ rt, long nplane,
+                                                       long nxf) {
   constexpr int N1 = P + 1;
   const long sz = (long)L.Nx * L.Ny;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const long blk = xcd_block(blockIdx.x, gridDim.x);
+  if (blockIdx.x >= nplane) {  // the x-face points of the other rows, one lane each
+    condense_xface<P, T>(L, coef, Ag, lam, r, rt, (blockIdx.x - nplane) * (long)blockDim.x + threadIdx.x, nxf);
+    return;
+  }
+  const long blk = xcd_block(blockIdx.x, nplane);
   {
     int Y, Z;
     plane_row<P>(L, blk, Y, Z);
@@ -437,13 +447,12 @@ __global__ void __launch_bounds__(256) k_condense_rows(LatDev L, const T *__rest
 
 // The x-face points of the rows inside the cells' y-z cross sections, one lane per
 // point (consecutive lanes along x, nx + 1 points per row); their x-lines lie in
-// the same lattice row.
+// the same lattice row.  Run by the blocks appended to the k_condense_rows launch.
 template <int P, typename T>
-__global__ void __launch_bounds__(256) k_condense_xface(LatDev L, const T *__restrict__ coef,
-                                                        const T *__restrict__ Ag, const T *__restrict__ lam,
-                                                        const T *__restrict__ r, T *__restrict__ rt, long n) {
+__device__ void condense_xface(const LatDev &L, const T *__restrict__ coef, const T *__restrict__ Ag,
+                               const T *__restrict__ lam, const T *__restrict__ r, T *__restrict__ rt, long t,
+                               long n) {
   constexpr int N1 = P + 1;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const int k = t % (L.nx + 1);
   int Y, Z;
@@ -667,11 +676,19 @@ struct ExpandOut {
 
 // Step 3 on the rows of the y- and z-vertex planes (every point a plane point).
 template <int P, typename T>
+__device__ void expand_xface(const LatDev &L, const T *__restrict__ r, const T *__restrict__ zbuf, T *__restrict__ z,
+                             const ExpandOut<T> &o, long t, long n);
+
+template <int P, typename T>
 __global__ void __launch_bounds__(256) k_expand_plane_rows(LatDev L, const T *__restrict__ r,
                                                            const T *__restrict__ zbuf, T *__restrict__ z,
-                                                           ExpandOut<T> o) {
+                                                           ExpandOut<T> o, long nplane, long nxf) {
+  if (blockIdx.x >= nplane) {  // the x-face points of the other rows, one lane each
+    expand_xface<P, T>(L, r, zbuf, z, o, (blockIdx.x - nplane) * (long)blockDim.x + threadIdx.x, nxf);
+    return;
+  }
   int Y, Z;
-  plane_row<P>(L, xcd_block(blockIdx.x, gridDim.x), Y, Z);
+  plane_row<P>(L, xcd_block(blockIdx.x, nplane), Y, Z);
   const long row = (long)L.Nx * (Y + (long)L.Ny * Z);
   for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) {
     const int C[3] = {X, Y, Z};
@@ -682,11 +699,11 @@ __global__ void __launch_bounds__(256) k_expand_plane_rows(LatDev L, const T *__
 }
 
 // Step 3 on the x-face points of the rows inside the cells' y-z cross sections,
-// one lane per point (nx + 1 per row).
+// one lane per point (nx + 1 per row); run by the blocks appended to the
+// k_expand_plane_rows launch.
 template <int P, typename T>
-__global__ void __launch_bounds__(256) k_expand_xface(LatDev L, const T *__restrict__ r, const T *__restrict__ zbuf,
-                                                      T *__restrict__ z, ExpandOut<T> o, long n) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void expand_xface(const LatDev &L, const T *__restrict__ r, const T *__restrict__ zbuf, T *__restrict__ z,
+                             const ExpandOut<T> &o, long t, long n) {
   if (t >= n) return;
   const int k = t % (L.nx + 1);
   int Y, Z;
@@ -701,7 +718,7 @@ __global__ void __launch_bounds__(256) k_expand_xface(LatDev L, const T *__restr
 // Step 4 on the rows inside a cell's y-z cross section: every interior point
 //   z_I = (r_I - sum_d sigma_d (A_{l,0} z_lo + A_{l,P} z_hi)) / dd
 // with z_lo, z_hi the plane values at the ends of its line along axis d (written by
-// k_expand_plane_rows and k_expand_xface; Dirichlet ends count as 0).
+// k_expand_plane_rows, x-face points included; Dirichlet ends count as 0).
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_expand_interior_rows(LatDev L, const T *__restrict__ coef,
                                                               const T *__restrict__ Ag, const T *__restrict__ lam,
@@ -720,7 +737,7 @@ __global__ void __launch_bounds__(256) k_expand_interior_rows(LatDev L, const T 
   const T lmy = lam[ly], lmz = lam[lz];
   for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) {
     const int cx = X / P, lx = X % P;
-    if (lx == 0) continue;  // x-face point, written by k_expand_xface
+    if (lx == 0) continue;  // x-face point, written by the previous launch
     const long g = row + X;
     const T *cf = coef + 6 * (cx + cyz);
     T dd = cf[3];
@@ -1212,9 +1229,9 @@ static void condense_p(const LatDev &L, const T *coef, const T *A, const T *lam,
   const long np = (long)(L.ny + 1) * L.Nz + (long)(L.nz + 1) * (L.Ny - L.ny - 1);
   const long ni = (long)L.ny * (P - 1) * L.nz * (P - 1);
   const int bs = L.Nx >= 256 ? 256 : ((L.Nx + 63) / 64) * 64;
-  k_condense_rows<P, T><<<(unsigned)np, bs, 8 * L.nx * sizeof(T), s>>>(L, coef, A, lam, r, rt);
   const long nxf = ni * (L.nx + 1);
-  if (nxf > 0) k_condense_xface<P, T><<<nblocks(nxf, 256), 256, 0, s>>>(L, coef, A, lam, r, rt, nxf);
+  const long nb = np + (long)nblocks(nxf, bs);
+  k_condense_rows<P, T><<<(unsigned)nb, bs, 8 * L.nx * sizeof(T), s>>>(L, coef, A, lam, r, rt, np, nxf);
 }
 
 template <int P, typename T>
@@ -1223,12 +1240,9 @@ static void expand_p(const LatDev &L, const T *coef, const T *A, const T *lam, c
   const long np = (long)(L.ny + 1) * L.Nz + (long)(L.nz + 1) * (L.Ny - L.ny - 1);
   const long ni = (long)L.ny * (P - 1) * L.nz * (P - 1);
   const int bs = L.Nx >= 256 ? 256 : ((L.Nx + 63) / 64) * 64;
-  k_expand_plane_rows<P, T><<<(unsigned)np, bs, 0, s>>>(L, r, zbuf, z, o);
   const long nxf = ni * (L.nx + 1);
-  if (ni > 0) {
-    k_expand_xface<P, T><<<nblocks(nxf, 256), 256, 0, s>>>(L, r, zbuf, z, o, nxf);
-    k_expand_interior_rows<P, T><<<(unsigned)ni, bs, 0, s>>>(L, coef, A, lam, r, z, o);
-  }
+  k_expand_plane_rows<P, T><<<(unsigned)(np + (long)nblocks(nxf, bs)), bs, 0, s>>>(L, r, zbuf, z, o, np, nxf);
+  if (ni > 0) k_expand_interior_rows<P, T><<<(unsigned)ni, bs, 0, s>>>(L, coef, A, lam, r, z, o);
 }
 
 template <typename T>
