@@ -20,9 +20,22 @@ FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950", "-munsafe-fp-ato
          "-Wno-unused-command-line-argument"]
 
 
+def _pass_tables():
+    """Run gen_pass_tables (host g++) to write the compile-time patch schedules."""
+    exe = os.path.join(BUILD, "gen_pass_tables")
+    cmd = [os.environ.get("CXX", "g++"), "-O1", "-std=c++17", "-I", CSRC, os.path.join(CSRC, "gen_pass_tables.cpp"),
+           os.path.join(CSRC, "patch.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    r = subprocess.run([exe, os.path.join(BUILD, "pass_tables.inc")], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"gen_pass_tables failed\n{r.stdout}\n{r.stderr}")
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + ["-I", BUILD, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -33,6 +46,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
+    _pass_tables()
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"

@@ -536,18 +536,19 @@ __device__ __forceinline__ void pass_push(int k, const T (&buf)[KM], const unsig
   if constexpr (K > 1) pass_push<KM, T, K - 1>(k, buf, ec, xw, xr);
 }
 
-// raw buffer loads (offsets in bytes; out-of-range offsets read 0)
+// raw buffer loads (offsets in bytes, per-lane voff plus wave-uniform soff;
+// out-of-range offsets read 0)
 template <typename T>
-__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff = 0);
 template <>
-__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff) {
   typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-  const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0);
   return __builtin_bit_cast(double, v);
 }
 template <>
-__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
 }
 
 template <typename T>
@@ -634,6 +635,144 @@ __global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E,
     }
     T *zo = zbuf + sl * (long)nrows;
     for (int i = lane; i < nrows; i += 64) zo[i] = (T)xw[i];
+  }
+}
+
+// Register-resident variant for the degrees whose factor values fit a wavefront's
+// registers (KT steps per lane: 97 at p = 7, so 194 VGPRs in FP64).  The schedule
+// is compiled in (PassTable, generated from the same routine the setup runs), so
+// every pass's steps sit at fixed register indices: a slot's off-diagonals are
+// loaded once, all at the start of the slot (ELL step s of the slot is one fully
+// coalesced row of 64 values), consumed by the forward sweep as they arrive and
+// reused from registers by the backward sweep, which therefore touches no memory.
+// The diagonals are kept inverted in LDS.
+template <int P>
+struct PassTable {
+  static constexpr int NR = 0, NP = 0, KT = 0;
+};
+#include "pass_tables.inc"
+
+template <int G>
+__device__ __forceinline__ double group_sum_c(double s) {
+#pragma unroll
+  for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  return s;
+}
+
+// forward pass t (gather): x_row = (w_row - sum_s L[row, col(s)] x_col(s)) / L_row,row
+template <typename T, int P, int t>
+__device__ __forceinline__ void fwd_passes(const T (&v)[PassTable<P>::KT], double *xw, const double *iw,
+                                           const unsigned short *ecol, const unsigned short *erow, int lane) {
+  using S = PassTable<P>;
+  if constexpr (t < S::NP) {
+    constexpr int G = S::G[t], K = S::K[t], c0 = S::C[t];
+    const unsigned row = erow[64 * t + lane];
+    double acc = 0;
+    if constexpr (K > 0) {
+      int ix[K];
+#pragma unroll
+      for (int s = 0; s < K; ++s) ix[s] = ecol[64 * (c0 + s) + lane];
+#pragma unroll
+      for (int s = 0; s < K; ++s) acc += (double)v[c0 + s] * xw[ix[s]];
+      acc = group_sum_c<G>(acc);
+    }
+    if ((lane & (G - 1)) == 0 && row != 0xFFFFu) xw[row] = (xw[row] - acc) * iw[row];
+    fwd_passes<T, P, t + 1>(v, xw, iw, ecol, erow, lane);
+  }
+}
+
+// backward pass t (push form of L^T x = z): x_row = w_row / L_row,row, then
+// w_col(s) -= L[row, col(s)] x_row (zero values, the padding among them, skipped)
+template <typename T, int P, int t>
+__device__ __forceinline__ void bwd_passes(const T (&v)[PassTable<P>::KT], double *xw, const double *iw,
+                                           const unsigned short *ecol, const unsigned short *erow, int lane) {
+  using S = PassTable<P>;
+  if constexpr (t >= 0) {
+    constexpr int G = S::G[t], K = S::K[t], c0 = S::C[t];
+    const unsigned row = erow[64 * t + lane];
+    if (row != 0xFFFFu) {
+      const double x = xw[row] * iw[row];
+      if ((lane & (G - 1)) == 0) xw[row] = x;
+#pragma unroll
+      for (int s = 0; s < K; ++s) {
+        T vs = v[c0 + s];
+        // an empty asm marks vs as redefined, so the FP32 factor is widened again here
+        // instead of the forward sweep's widened copies staying live in registers
+        if constexpr (sizeof(T) == 4) asm("" : "+v"(vs));
+        if (vs != T(0)) atomicAdd(&xw[ecol[64 * (c0 + s) + lane]], -(double)vs * x);
+      }
+    }
+    bwd_passes<T, P, t - 1>(v, xw, iw, ecol, erow, lane);
+  }
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, const T *__restrict__ factor,
+                                                        const T *__restrict__ rt, T *__restrict__ zbuf,
+                                                        long nslots) {
+  using S = PassTable<P>;
+  constexpr int NR = S::NR, NP = S::NP, KT = S::KT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ne = E.ne;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  // LDS: the wavefronts' vectors, their inverted diagonals (both FP64), the shared tables
+  double *xw = reinterpret_cast<double *>(smem_raw) + (size_t)w * NR;
+  double *iw = reinterpret_cast<double *>(smem_raw) + (size_t)(nw + w) * NR;
+  int *off = reinterpret_cast<int *>(reinterpret_cast<double *>(smem_raw) + (size_t)2 * nw * NR);
+  unsigned short *ecol = reinterpret_cast<unsigned short *>(off + NR);
+  unsigned short *erow = ecol + ne;
+  for (int i = tid; i < ne; i += blockDim.x) ecol[i] = (unsigned short)E.ecol[i];
+  for (int i = tid; i < NP * 64; i += blockDim.x) erow[i] = (unsigned short)(E.erow[i] & 0xFFFF);
+  for (int i = tid; i < NR; i += blockDim.x)
+    off[i] = (E.off[3 * i] + 64) | ((E.off[3 * i + 1] + 64) << 8) | ((E.off[3 * i + 2] + 64) << 16);
+  __syncthreads();
+  const int nvx = L.nx + 1, nvy = L.ny + 1;
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  for (long sl = (long)blockIdx.x * nw + wu; sl < nslots; sl += (long)gridDim.x * nw) {
+    const T *f = factor + sl * (long)E.stride;
+    const int vx = sl % nvx, vy = (sl / nvx) % nvy, vz = sl / ((long)nvx * nvy);
+    // right-hand side and diagonals first, then every off-diagonal of the slot
+    constexpr int NI = (NR + 63) / 64;
+    T rhs[NI], dia[NI];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int i = lane + 64 * j;
+      rhs[j] = T(0);
+      dia[j] = T(1);
+      if (i < NR) {
+        const int o = off[i];
+        const int X = vx * P + (o & 255) - 64, Y = vy * P + ((o >> 8) & 255) - 64, Z = vz * P + ((o >> 16) & 255) - 64;
+        const bool in = X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
+        if (in && !lat_dirichlet(L, X, Y, Z)) rhs[j] = rt[lat_index(L, X, Y, Z)];
+        dia[j] = f[i];
+      }
+    }
+    // half the off-diagonals are in flight while the vector and the inverted
+    // diagonals go to LDS (which frees their registers), then the rest
+    const __amdgpu_buffer_rsrc_t fr =
+        __builtin_amdgcn_make_buffer_rsrc((void *)f, (short)0, E.stride * (int)sizeof(T), 0x00020000);
+    constexpr int KA = KT / 2;
+    T v[KT];
+#pragma unroll
+    for (int s = 0; s < KA; ++s) v[s] = buffer_load<T>(fr, lane * (unsigned)sizeof(T), (NR + 64 * s) * sizeof(T));
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int i = lane + 64 * j;
+      if (i < NR) {
+        xw[i] = (double)rhs[j];
+        iw[i] = 1.0 / (double)dia[j];
+      }
+    }
+#pragma unroll
+    for (int s = KA; s < KT; ++s) v[s] = buffer_load<T>(fr, lane * (unsigned)sizeof(T), (NR + 64 * s) * sizeof(T));
+    fwd_passes<T, P, 0>(v, xw, iw, ecol, erow, lane);
+    bwd_passes<T, P, NP - 1>(v, xw, iw, ecol, erow, lane);
+    T *zo = zbuf + sl * (long)NR;
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int i = lane + 64 * j;
+      if (i < NR) zo[i] = (T)xw[i];
+    }
   }
 }
 
@@ -1296,9 +1435,68 @@ static bool patch_solve_shape(const PatchEllDev &E, size_t row_bytes, int cap, i
   return waves > 0;
 }
 
+template <int P>
+static bool pass_table_matches(const int *pass, int np, int nrows, int ne) {
+  using S = PassTable<P>;
+  if (S::NP != np || S::NR != nrows || 64 * S::KT != ne) return false;
+  for (int t = 0; t < np; ++t)
+    if (pass[3 * t] != S::G[t] || pass[3 * t + 1] != S::K[t] || pass[3 * t + 2] != 64 * S::C[t]) return false;
+  return true;
+}
+
+bool patch_regs_table_matches(int p, const int *pass, int np, int nrows, int ne) {
+  switch (p) {
+    case 2: return pass_table_matches<2>(pass, np, nrows, ne);
+    case 3: return pass_table_matches<3>(pass, np, nrows, ne);
+    case 4: return pass_table_matches<4>(pass, np, nrows, ne);
+    case 5: return pass_table_matches<5>(pass, np, nrows, ne);
+    case 6: return pass_table_matches<6>(pass, np, nrows, ne);
+    case 7: return pass_table_matches<7>(pass, np, nrows, ne);
+    case 8: return pass_table_matches<8>(pass, np, nrows, ne);
+    default: return false;
+  }
+}
+
+// the register kernel: four wavefronts per block, as many blocks per CU as the
+// registers (2 at p = 7 in FP64) and the LDS allow
+template <typename T, int P>
+static int launch_patch_solve_r(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf,
+                                hipStream_t s) {
+  using S = PassTable<P>;
+  constexpr int waves = 4;
+  const long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
+  const size_t shm = (size_t)2 * waves * S::NR * sizeof(double) + 4 * (size_t)S::NR + 2 * (size_t)E.ne + 2 * 64 * S::NP;
+  static const int per_cu = [&] {
+    hipFuncSetAttribute((const void *)k_patch_solve_r<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_patch_solve_r<T, P>, 64 * waves, shm) != hipSuccess) b = 0;
+    return b;
+  }();
+  if (per_cu <= 0) return -1;
+  long grid = (long)device_cu_count() * per_cu;
+  const long need = (nv + waves - 1) / waves;
+  if (grid > need) grid = need;
+  k_patch_solve_r<T, P><<<(unsigned)grid, 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv);
+  return 0;
+}
+
 template <typename T>
 int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf, hipStream_t s) {
   const long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
+  if (E.regs) {  // factor values in registers: FP64 up to p = 7, FP32 up to p = 8
+    switch (L.p) {
+      case 2: return launch_patch_solve_r<T, 2>(L, E, factor, rt, zbuf, s);
+      case 3: return launch_patch_solve_r<T, 3>(L, E, factor, rt, zbuf, s);
+      case 4: return launch_patch_solve_r<T, 4>(L, E, factor, rt, zbuf, s);
+      case 5: return launch_patch_solve_r<T, 5>(L, E, factor, rt, zbuf, s);
+      case 6: return launch_patch_solve_r<T, 6>(L, E, factor, rt, zbuf, s);
+      case 7: return launch_patch_solve_r<T, 7>(L, E, factor, rt, zbuf, s);
+      case 8:
+        if constexpr (sizeof(T) == 4) return launch_patch_solve_r<T, 8>(L, E, factor, rt, zbuf, s);
+        break;
+      default: break;
+    }
+  }
   auto grid_of = [&](int waves, int per_cu) {
     long grid = (long)device_cu_count() * per_cu;
     const long need = (nv + waves - 1) / waves;

@@ -48,6 +48,7 @@ struct PatchEllDev {
   const int *ecol;                 // ne: x index read at every ELL position
   const int *erow;                 // 64*npass: row solved by each lane's group (-1 none)
   const int *off;                  // 3*nrows: lattice offsets of the patch rows
+  int regs;                        // 1: the schedule equals the one compiled into the register kernel
 };
 
 // Trilinear cells with sampled coefficients: vertex coordinates (nvertices x 3,
@@ -110,6 +111,9 @@ template <typename T>
 void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *rt,
                           hipStream_t s);
 // Returns non-zero when the schedule does not fit the LDS of one block.
+// true when the host pass table (G, K, ELL offset per pass; ne ELL values) of
+// degree p equals the schedule compiled into the register-resident patch solve
+bool patch_regs_table_matches(int p, const int *pass, int np, int nrows, int ne);
 size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves);
 template <typename T>
 int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf, hipStream_t s);
