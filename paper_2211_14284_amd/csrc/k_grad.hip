@@ -642,67 +642,121 @@ __global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E,
 // registers (KT steps per lane: 97 at p = 7, so 194 VGPRs in FP64).  The schedule
 // is compiled in (PassTable, generated from the same routine the setup runs), so
 // every pass's steps sit at fixed register indices: a slot's off-diagonals are
-// loaded once, all at the start of the slot (ELL step s of the slot is one fully
-// coalesced row of 64 values), consumed by the forward sweep as they arrive and
-// reused from registers by the backward sweep, which therefore touches no memory.
-// The diagonals are kept inverted in LDS.
+// loaded once (ELL step s of the slot is one fully coalesced row of 64 values),
+// used by the forward sweep and again from registers by the backward sweep, which
+// reloads each pass's registers with the next slot's values as soon as the pass
+// is done, so the next slot's factor streams in while this one finishes.  The
+// diagonals are kept inverted in LDS.
 template <int P>
 struct PassTable {
   static constexpr int NR = 0, NP = 0, KT = 0;
 };
 #include "pass_tables.inc"
 
+// one DPP move of a double (both halves; every lane reads a lane of its own row)
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// sum over aligned groups of G lanes, the same value on every lane of a group:
+// lane swaps within quads, then the mirror images within 8 and 16 lanes (DPP),
+// then cross-lane shuffles for 32 and 64
 template <int G>
 __device__ __forceinline__ double group_sum_c(double s) {
-#pragma unroll
-  for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if constexpr (G >= 2) s += dpp_move<0xB1>(s);   // quad_perm 1,0,3,2
+  if constexpr (G >= 4) s += dpp_move<0x4E>(s);   // quad_perm 2,3,0,1
+  if constexpr (G >= 8) s += dpp_move<0x141>(s);  // row_half_mirror
+  if constexpr (G >= 16) s += dpp_move<0x140>(s); // row_mirror
+  if constexpr (G >= 32) s += __shfl_xor(s, 16, 64);
+  if constexpr (G >= 64) s += __shfl_xor(s, 32, 64);
   return s;
 }
 
-// forward pass t (gather): x_row = (w_row - sum_s L[row, col(s)] x_col(s)) / L_row,row
+// indices of one pass read ahead of it: the lane's row, its columns, and (forward)
+// the row's right-hand side and inverted diagonal
+template <int K>
+struct PassIdx {
+  unsigned row;
+  int ix[K > 0 ? K : 1];
+  double b, d;
+};
+
+template <int P, int t>
+__device__ __forceinline__ void read_idx(PassIdx<PassTable<P>::K[t]> &q, const unsigned short *ecol,
+                                         const unsigned short *erow, int lane) {
+  constexpr int K = PassTable<P>::K[t], c0 = PassTable<P>::C[t];
+  q.row = erow[64 * t + lane];
+#pragma unroll
+  for (int s = 0; s < K; ++s) q.ix[s] = ecol[64 * (c0 + s) + lane];
+}
+
+// forward pass t (gather): x_row = (w_row - sum_s L[row, col(s)] x_col(s)) / L_row,row.
+// Pass t + 1's indices are read while pass t computes, and its row's right-hand
+// side before pass t writes (rows of different passes are distinct).
 template <typename T, int P, int t>
 __device__ __forceinline__ void fwd_passes(const T (&v)[PassTable<P>::KT], double *xw, const double *iw,
-                                           const unsigned short *ecol, const unsigned short *erow, int lane) {
+                                           const unsigned short *ecol, const unsigned short *erow, int lane,
+                                           const PassIdx<PassTable<P>::K[t]> &q) {
   using S = PassTable<P>;
-  if constexpr (t < S::NP) {
-    constexpr int G = S::G[t], K = S::K[t], c0 = S::C[t];
-    const unsigned row = erow[64 * t + lane];
-    double acc = 0;
-    if constexpr (K > 0) {
-      int ix[K];
+  constexpr int G = S::G[t], K = S::K[t], c0 = S::C[t];
+  double xg[K > 0 ? K : 1];
 #pragma unroll
-      for (int s = 0; s < K; ++s) ix[s] = ecol[64 * (c0 + s) + lane];
+  for (int s = 0; s < K; ++s) xg[s] = xw[q.ix[s]];
+  PassIdx<S::K[t + 1 < S::NP ? t + 1 : t]> n;
+  if constexpr (t + 1 < S::NP) read_idx<P, t + 1>(n, ecol, erow, lane);
+  double acc = 0;
+  if constexpr (K > 0) {
 #pragma unroll
-      for (int s = 0; s < K; ++s) acc += (double)v[c0 + s] * xw[ix[s]];
-      acc = group_sum_c<G>(acc);
-    }
-    if ((lane & (G - 1)) == 0 && row != 0xFFFFu) xw[row] = (xw[row] - acc) * iw[row];
-    fwd_passes<T, P, t + 1>(v, xw, iw, ecol, erow, lane);
+    for (int s = 0; s < K; ++s) acc += (double)v[c0 + s] * xg[s];
+    acc = group_sum_c<G>(acc);
   }
+  if constexpr (t + 1 < S::NP) {
+    const unsigned r = n.row != 0xFFFFu ? n.row : 0u;
+    n.b = xw[r];
+    n.d = iw[r];
+  }
+  if ((lane & (G - 1)) == 0 && q.row != 0xFFFFu) xw[q.row] = (q.b - acc) * q.d;
+  if constexpr (t + 1 < S::NP) fwd_passes<T, P, t + 1>(v, xw, iw, ecol, erow, lane, n);
 }
 
 // backward pass t (push form of L^T x = z): x_row = w_row / L_row,row, then
-// w_col(s) -= L[row, col(s)] x_row (zero values, the padding among them, skipped)
+// w_col(s) -= L[row, col(s)] x_row.  Padding values are zero and push nothing
+// (their adds of -0 leave every value as it is).  Pass t - 1's indices and
+// inverted diagonal are read while pass t computes (the diagonals never change).
+// Once pass t has pushed, its registers load the next slot's values of pass t
+// (through nr, which reads zeros without memory access past the last slot).
 template <typename T, int P, int t>
-__device__ __forceinline__ void bwd_passes(const T (&v)[PassTable<P>::KT], double *xw, const double *iw,
-                                           const unsigned short *ecol, const unsigned short *erow, int lane) {
+__device__ __forceinline__ void bwd_passes(T (&v)[PassTable<P>::KT], double *xw, const double *iw,
+                                           const unsigned short *ecol, const unsigned short *erow, int lane,
+                                           const PassIdx<PassTable<P>::K[t]> &q, __amdgpu_buffer_rsrc_t nr) {
   using S = PassTable<P>;
-  if constexpr (t >= 0) {
-    constexpr int G = S::G[t], K = S::K[t], c0 = S::C[t];
-    const unsigned row = erow[64 * t + lane];
-    if (row != 0xFFFFu) {
-      const double x = xw[row] * iw[row];
-      if ((lane & (G - 1)) == 0) xw[row] = x;
+  constexpr int G = S::G[t], K = S::K[t], c0 = S::C[t];
+  const bool has = q.row != 0xFFFFu;
+  const double a = xw[has ? q.row : 0u];
+  PassIdx<S::K[t > 0 ? t - 1 : 0]> n;
+  if constexpr (t > 0) read_idx<P, t - 1>(n, ecol, erow, lane);
+  if (has) {
+    const double x = a * q.d;
+    if ((lane & (G - 1)) == 0) xw[q.row] = x;
 #pragma unroll
-      for (int s = 0; s < K; ++s) {
-        T vs = v[c0 + s];
-        // an empty asm marks vs as redefined, so the FP32 factor is widened again here
-        // instead of the forward sweep's widened copies staying live in registers
-        if constexpr (sizeof(T) == 4) asm("" : "+v"(vs));
-        if (vs != T(0)) atomicAdd(&xw[ecol[64 * (c0 + s) + lane]], -(double)vs * x);
-      }
+    for (int s = 0; s < K; ++s) {
+      T vs = v[c0 + s];
+      // an empty asm marks vs as redefined, so the FP32 factor is widened again here
+      // instead of the forward sweep's widened copies staying live in registers
+      if constexpr (sizeof(T) == 4) asm("" : "+v"(vs));
+      atomicAdd(&xw[q.ix[s]], -(double)vs * x);
     }
-    bwd_passes<T, P, t - 1>(v, xw, iw, ecol, erow, lane);
+  }
+#pragma unroll
+  for (int s = 0; s < K; ++s)
+    v[c0 + s] = buffer_load<T>(nr, lane * (unsigned)sizeof(T), (S::NR + 64 * (c0 + s)) * sizeof(T));
+  if constexpr (t > 0) {
+    n.d = iw[n.row != 0xFFFFu ? n.row : 0u];
+    bwd_passes<T, P, t - 1>(v, xw, iw, ecol, erow, lane, n, nr);
   }
 }
 
@@ -728,10 +782,25 @@ __global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, 
   __syncthreads();
   const int nvx = L.nx + 1, nvy = L.ny + 1;
   const int wu = __builtin_amdgcn_readfirstlane(w);
-  for (long sl = (long)blockIdx.x * nw + wu; sl < nslots; sl += (long)gridDim.x * nw) {
+  const long step = (long)gridDim.x * nw;
+  // a slot's factor through a buffer resource; past the last slot its range is
+  // empty, so that loads read zeros without touching memory
+  auto slot_rsrc = [&](long s) {
+    const bool ok = s < nslots;
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(factor + (ok ? s : 0) * (long)E.stride), (short)0,
+                                             ok ? E.stride * (int)sizeof(T) : 0, 0x00020000);
+  };
+  long sl = (long)blockIdx.x * nw + wu;
+  T v[KT];  // the current slot's off-diagonals (ELL step s of the slot in v[s])
+  {
+    const __amdgpu_buffer_rsrc_t fr = slot_rsrc(sl);
+#pragma unroll
+    for (int s = 0; s < KT; ++s) v[s] = buffer_load<T>(fr, lane * (unsigned)sizeof(T), (NR + 64 * s) * sizeof(T));
+  }
+  for (; sl < nslots; sl += step) {
     const T *f = factor + sl * (long)E.stride;
     const int vx = sl % nvx, vy = (sl / nvx) % nvy, vz = sl / ((long)nvx * nvy);
-    // right-hand side and diagonals first, then every off-diagonal of the slot
+    // right-hand side and diagonals (the off-diagonals are loaded already)
     constexpr int NI = (NR + 63) / 64;
     T rhs[NI], dia[NI];
 #pragma unroll
@@ -747,14 +816,6 @@ __global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, 
         dia[j] = f[i];
       }
     }
-    // half the off-diagonals are in flight while the vector and the inverted
-    // diagonals go to LDS (which frees their registers), then the rest
-    const __amdgpu_buffer_rsrc_t fr =
-        __builtin_amdgcn_make_buffer_rsrc((void *)f, (short)0, E.stride * (int)sizeof(T), 0x00020000);
-    constexpr int KA = KT / 2;
-    T v[KT];
-#pragma unroll
-    for (int s = 0; s < KA; ++s) v[s] = buffer_load<T>(fr, lane * (unsigned)sizeof(T), (NR + 64 * s) * sizeof(T));
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
       const int i = lane + 64 * j;
@@ -763,10 +824,20 @@ __global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, 
         iw[i] = 1.0 / (double)dia[j];
       }
     }
-#pragma unroll
-    for (int s = KA; s < KT; ++s) v[s] = buffer_load<T>(fr, lane * (unsigned)sizeof(T), (NR + 64 * s) * sizeof(T));
-    fwd_passes<T, P, 0>(v, xw, iw, ecol, erow, lane);
-    bwd_passes<T, P, NP - 1>(v, xw, iw, ecol, erow, lane);
+    {
+      PassIdx<S::K[0]> q;
+      read_idx<P, 0>(q, ecol, erow, lane);
+      const unsigned r = q.row != 0xFFFFu ? q.row : 0u;
+      q.b = xw[r];
+      q.d = iw[r];
+      fwd_passes<T, P, 0>(v, xw, iw, ecol, erow, lane, q);
+    }
+    {
+      PassIdx<S::K[NP - 1]> q;
+      read_idx<P, NP - 1>(q, ecol, erow, lane);
+      q.d = iw[q.row != 0xFFFFu ? q.row : 0u];
+      bwd_passes<T, P, NP - 1>(v, xw, iw, ecol, erow, lane, q, slot_rsrc(sl + step));
+    }
     T *zo = zbuf + sl * (long)NR;
 #pragma unroll
     for (int j = 0; j < NI; ++j) {

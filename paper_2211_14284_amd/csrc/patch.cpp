@@ -124,13 +124,18 @@ static void schedule_level(PatchSymbolic &ps, std::vector<std::pair<int, std::ve
     ps.ecol.resize(base + (size_t)W * K, 0);
     const size_t r0 = ps.erow.size();
     ps.erow.resize(r0 + W, -1);
+    // Row j's entries start at a rotation of j G: the rows of a level share many
+    // columns, and the rotation spreads a column over different steps, so that the
+    // backward sweep's pushes of one step hit fewer equal addresses.
     for (int j = 0; j < R && t + j < n; ++j) {
       const auto &it = items[t + j];
+      const int len = (int)it.second.size();
       for (int q = 0; q < G; ++q) ps.erow[r0 + j * G + q] = it.first;
-      for (int m = 0; m < (int)it.second.size(); ++m) {
+      for (int m = 0; m < len; ++m) {
+        const auto &e = it.second[(m + j * G) % len];
         const int pos = base + (m / G) * W + j * G + (m % G);
-        ps.ecol[pos] = it.second[m].second;
-        ps.pos1[it.second[m].first] = ps.nrows + pos;
+        ps.ecol[pos] = e.second;
+        ps.pos1[e.first] = ps.nrows + pos;
       }
     }
   }
