@@ -551,6 +551,30 @@ __device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, un
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
 }
 
+// two adjacent values per lane: one 16-byte (FP64) or 8-byte (FP32) load
+template <typename T>
+__device__ __forceinline__ void buffer_load2(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff, T &a, T &b);
+template <>
+__device__ __forceinline__ void buffer_load2<double>(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff, double &a,
+                                                     double &b) {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, 0);
+  a = __builtin_bit_cast(double, u2{v.x, v.y});
+  b = __builtin_bit_cast(double, u2{v.z, v.w});
+}
+template <>
+__device__ __forceinline__ void buffer_load2<float>(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff, float &a,
+                                                    float &b) {
+  // split through a 64-bit integer: taking the two elements of the returned
+  // 2 x u32 vector directly compiles (hipcc of ROCm 7.2) into a single 4-byte load
+  // whose value serves both
+  const unsigned long long v =
+      __builtin_bit_cast(unsigned long long, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+  a = __builtin_bit_cast(float, (unsigned)v);
+  b = __builtin_bit_cast(float, (unsigned)(v >> 32));
+}
+
 template <typename T>
 __device__ __forceinline__ T group_sum(T s, int G) {
   for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
@@ -598,10 +622,14 @@ __global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E,
     const __amdgpu_buffer_rsrc_t fr =
         __builtin_amdgcn_make_buffer_rsrc((void *)f, (short)0, E.stride * (int)sizeof(T), 0x00020000);
     auto load_pass = [&](T (&buf)[KM], int t) {
-      const int K = E.pass[3 * t + 1];
-      const unsigned o = (unsigned)(nrows + E.pass[3 * t + 2] + lane) * sizeof(T);
+      const int K = E.pass[3 * t + 1], base = E.ell0 + E.pass[3 * t + 2];
+      const int K2 = K & ~1;
 #pragma unroll
-      for (int s = 0; s < KM; ++s) buf[s] = buffer_load<T>(fr, s < K ? o + 64 * s * sizeof(T) : 0x80000000u);
+      for (int s = 0; s < KM; ++s) {
+        // value position of step s (steps in lane-adjacent pairs, an odd last step alone)
+        const int pos = s < K2 ? base + 128 * (s >> 1) + 2 * lane + (s & 1) : base + 64 * s + lane;
+        buf[s] = buffer_load<T>(fr, s < K ? (unsigned)pos * sizeof(T) : 0x80000000u);
+      }
     };
     // pass sequence u = 0 .. 2 np - 1: the passes forward (gather), then the same in
     // reverse (push form of the transposed solve)
@@ -642,7 +670,7 @@ __global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E,
 // registers (KT steps per lane: 97 at p = 7, so 194 VGPRs in FP64).  The schedule
 // is compiled in (PassTable, generated from the same routine the setup runs), so
 // every pass's steps sit at fixed register indices: a slot's off-diagonals are
-// loaded once (ELL step s of the slot is one fully coalesced row of 64 values),
+// loaded once (two steps of a pass per load, fully coalesced across the lanes),
 // used by the forward sweep and again from registers by the backward sweep, which
 // reloads each pass's registers with the next slot's values as soon as the pass
 // is done, so the next slot's factor streams in while this one finishes.  The
@@ -657,8 +685,8 @@ struct PassTable {
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double x) {
   const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
   return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
@@ -674,6 +702,27 @@ __device__ __forceinline__ double group_sum_c(double s) {
   if constexpr (G >= 32) s += __shfl_xor(s, 16, 64);
   if constexpr (G >= 64) s += __shfl_xor(s, 32, 64);
   return s;
+}
+
+// pass t's values of a slot into their registers: the lane-adjacent step pairs
+// with one load each, an odd last step alone
+template <typename T, int P, int t>
+__device__ __forceinline__ void load_pass_regs(T (&v)[PassTable<P>::KT], __amdgpu_buffer_rsrc_t r, int lane) {
+  using S = PassTable<P>;
+  constexpr int K = S::K[t], c0 = S::C[t], base = S::E0 + 64 * c0;
+#pragma unroll
+  for (int g = 0; g < K / 2; ++g)
+    buffer_load2<T>(r, 2 * lane * (unsigned)sizeof(T), (base + 128 * g) * (unsigned)sizeof(T), v[c0 + 2 * g],
+                    v[c0 + 2 * g + 1]);
+  if constexpr (K & 1) v[c0 + K - 1] = buffer_load<T>(r, lane * (unsigned)sizeof(T), (base + 64 * (K - 1)) * sizeof(T));
+}
+
+template <typename T, int P, int t = 0>
+__device__ __forceinline__ void load_all_regs(T (&v)[PassTable<P>::KT], __amdgpu_buffer_rsrc_t r, int lane) {
+  if constexpr (t < PassTable<P>::NP) {
+    load_pass_regs<T, P, t>(v, r, lane);
+    load_all_regs<T, P, t + 1>(v, r, lane);
+  }
 }
 
 // indices of one pass read ahead of it: the lane's row, its columns, and (forward)
@@ -695,8 +744,11 @@ __device__ __forceinline__ void read_idx(PassIdx<PassTable<P>::K[t]> &q, const u
 }
 
 // forward pass t (gather): x_row = (w_row - sum_s L[row, col(s)] x_col(s)) / L_row,row.
-// Pass t + 1's indices are read while pass t computes, and its row's right-hand
-// side before pass t writes (rows of different passes are distinct).
+// Every lane of a row's group holds the same sum and writes the same value, and
+// lanes without a row use the dummy entry NR (zero vector value and diagonal), so
+// the sweeps run without lane masks.  Pass t + 1's indices are read while pass t
+// computes, and its row's right-hand side before pass t writes (rows of different
+// passes are distinct).
 template <typename T, int P, int t>
 __device__ __forceinline__ void fwd_passes(const T (&v)[PassTable<P>::KT], double *xw, const double *iw,
                                            const unsigned short *ecol, const unsigned short *erow, int lane,
@@ -710,52 +762,51 @@ __device__ __forceinline__ void fwd_passes(const T (&v)[PassTable<P>::KT], doubl
   if constexpr (t + 1 < S::NP) read_idx<P, t + 1>(n, ecol, erow, lane);
   double acc = 0;
   if constexpr (K > 0) {
+    // two interleaved partial sums halve the dependent chain
+    double a0 = 0, a1 = 0;
 #pragma unroll
-    for (int s = 0; s < K; ++s) acc += (double)v[c0 + s] * xg[s];
-    acc = group_sum_c<G>(acc);
+    for (int s = 0; s < K; s += 2) a0 += (double)v[c0 + s] * xg[s];
+#pragma unroll
+    for (int s = 1; s < K; s += 2) a1 += (double)v[c0 + s] * xg[s];
+    acc = group_sum_c<G>(a0 + a1);
   }
   if constexpr (t + 1 < S::NP) {
-    const unsigned r = n.row != 0xFFFFu ? n.row : 0u;
-    n.b = xw[r];
-    n.d = iw[r];
+    n.b = xw[n.row];
+    n.d = iw[n.row];
   }
-  if ((lane & (G - 1)) == 0 && q.row != 0xFFFFu) xw[q.row] = (q.b - acc) * q.d;
+  xw[q.row] = (q.b - acc) * q.d;
   if constexpr (t + 1 < S::NP) fwd_passes<T, P, t + 1>(v, xw, iw, ecol, erow, lane, n);
 }
 
 // backward pass t (push form of L^T x = z): x_row = w_row / L_row,row, then
-// w_col(s) -= L[row, col(s)] x_row.  Padding values are zero and push nothing
-// (their adds of -0 leave every value as it is).  Pass t - 1's indices and
-// inverted diagonal are read while pass t computes (the diagonals never change).
-// Once pass t has pushed, its registers load the next slot's values of pass t
-// (through nr, which reads zeros without memory access past the last slot).
+// w_col(s) -= L[row, col(s)] x_row.  Padding values are zero, and their adds of -0
+// leave every value as it is (the dummy row's value is zero too).  Pass t - 1's
+// indices and inverted diagonal are read while pass t computes (the diagonals
+// never change).  Once pass t has pushed, its registers load the next slot's
+// values of pass t (through nr, which reads zeros without memory access past the
+// last slot).
 template <typename T, int P, int t>
 __device__ __forceinline__ void bwd_passes(T (&v)[PassTable<P>::KT], double *xw, const double *iw,
                                            const unsigned short *ecol, const unsigned short *erow, int lane,
                                            const PassIdx<PassTable<P>::K[t]> &q, __amdgpu_buffer_rsrc_t nr) {
   using S = PassTable<P>;
-  constexpr int G = S::G[t], K = S::K[t], c0 = S::C[t];
-  const bool has = q.row != 0xFFFFu;
-  const double a = xw[has ? q.row : 0u];
+  constexpr int K = S::K[t], c0 = S::C[t];
+  const double a = xw[q.row];
   PassIdx<S::K[t > 0 ? t - 1 : 0]> n;
   if constexpr (t > 0) read_idx<P, t - 1>(n, ecol, erow, lane);
-  if (has) {
-    const double x = a * q.d;
-    if ((lane & (G - 1)) == 0) xw[q.row] = x;
+  const double x = a * q.d;
+  xw[q.row] = x;
 #pragma unroll
-    for (int s = 0; s < K; ++s) {
-      T vs = v[c0 + s];
-      // an empty asm marks vs as redefined, so the FP32 factor is widened again here
-      // instead of the forward sweep's widened copies staying live in registers
-      if constexpr (sizeof(T) == 4) asm("" : "+v"(vs));
-      atomicAdd(&xw[q.ix[s]], -(double)vs * x);
-    }
+  for (int s = 0; s < K; ++s) {
+    T vs = v[c0 + s];
+    // an empty asm marks vs as redefined, so the FP32 factor is widened again here
+    // instead of the forward sweep's widened copies staying live in registers
+    if constexpr (sizeof(T) == 4) asm("" : "+v"(vs));
+    atomicAdd(&xw[q.ix[s]], -(double)vs * x);
   }
-#pragma unroll
-  for (int s = 0; s < K; ++s)
-    v[c0 + s] = buffer_load<T>(nr, lane * (unsigned)sizeof(T), (S::NR + 64 * (c0 + s)) * sizeof(T));
+  load_pass_regs<T, P, t>(v, nr, lane);
   if constexpr (t > 0) {
-    n.d = iw[n.row != 0xFFFFu ? n.row : 0u];
+    n.d = iw[n.row];
     bwd_passes<T, P, t - 1>(v, xw, iw, ecol, erow, lane, n, nr);
   }
 }
@@ -769,14 +820,16 @@ __global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ne = E.ne;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-  // LDS: the wavefronts' vectors, their inverted diagonals (both FP64), the shared tables
-  double *xw = reinterpret_cast<double *>(smem_raw) + (size_t)w * NR;
-  double *iw = reinterpret_cast<double *>(smem_raw) + (size_t)(nw + w) * NR;
-  int *off = reinterpret_cast<int *>(reinterpret_cast<double *>(smem_raw) + (size_t)2 * nw * NR);
+  // LDS: the wavefronts' vectors and their inverted diagonals (both FP64, NR + 1
+  // entries: the last is the dummy row of lanes without a row), the shared tables
+  constexpr int NR1 = NR + 1;
+  double *xw = reinterpret_cast<double *>(smem_raw) + (size_t)w * NR1;
+  double *iw = reinterpret_cast<double *>(smem_raw) + (size_t)(nw + w) * NR1;
+  int *off = reinterpret_cast<int *>(reinterpret_cast<double *>(smem_raw) + (size_t)2 * nw * NR1);
   unsigned short *ecol = reinterpret_cast<unsigned short *>(off + NR);
   unsigned short *erow = ecol + ne;
   for (int i = tid; i < ne; i += blockDim.x) ecol[i] = (unsigned short)E.ecol[i];
-  for (int i = tid; i < NP * 64; i += blockDim.x) erow[i] = (unsigned short)(E.erow[i] & 0xFFFF);
+  for (int i = tid; i < NP * 64; i += blockDim.x) erow[i] = (unsigned short)(E.erow[i] < 0 ? NR : E.erow[i]);
   for (int i = tid; i < NR; i += blockDim.x)
     off[i] = (E.off[3 * i] + 64) | ((E.off[3 * i + 1] + 64) << 8) | ((E.off[3 * i + 2] + 64) << 16);
   __syncthreads();
@@ -791,12 +844,8 @@ __global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, 
                                              ok ? E.stride * (int)sizeof(T) : 0, 0x00020000);
   };
   long sl = (long)blockIdx.x * nw + wu;
-  T v[KT];  // the current slot's off-diagonals (ELL step s of the slot in v[s])
-  {
-    const __amdgpu_buffer_rsrc_t fr = slot_rsrc(sl);
-#pragma unroll
-    for (int s = 0; s < KT; ++s) v[s] = buffer_load<T>(fr, lane * (unsigned)sizeof(T), (NR + 64 * s) * sizeof(T));
-  }
+  T v[KT];  // the current slot's off-diagonals (step s of the slot's passes in v[s])
+  load_all_regs<T, P>(v, slot_rsrc(sl), lane);
   for (; sl < nslots; sl += step) {
     const T *f = factor + sl * (long)E.stride;
     const int vx = sl % nvx, vy = (sl / nvx) % nvy, vz = sl / ((long)nvx * nvy);
@@ -824,18 +873,21 @@ __global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, 
         iw[i] = 1.0 / (double)dia[j];
       }
     }
+    if (lane == 0) {  // the dummy row
+      xw[NR] = 0.0;
+      iw[NR] = 0.0;
+    }
     {
       PassIdx<S::K[0]> q;
       read_idx<P, 0>(q, ecol, erow, lane);
-      const unsigned r = q.row != 0xFFFFu ? q.row : 0u;
-      q.b = xw[r];
-      q.d = iw[r];
+      q.b = xw[q.row];
+      q.d = iw[q.row];
       fwd_passes<T, P, 0>(v, xw, iw, ecol, erow, lane, q);
     }
     {
       PassIdx<S::K[NP - 1]> q;
       read_idx<P, NP - 1>(q, ecol, erow, lane);
-      q.d = iw[q.row != 0xFFFFu ? q.row : 0u];
+      q.d = iw[q.row];
       bwd_passes<T, P, NP - 1>(v, xw, iw, ecol, erow, lane, q, slot_rsrc(sl + step));
     }
     T *zo = zbuf + sl * (long)NR;
@@ -1507,23 +1559,23 @@ static bool patch_solve_shape(const PatchEllDev &E, size_t row_bytes, int cap, i
 }
 
 template <int P>
-static bool pass_table_matches(const int *pass, int np, int nrows, int ne) {
+static bool pass_table_matches(const int *pass, int np, int nrows, int ne, int ell0) {
   using S = PassTable<P>;
-  if (S::NP != np || S::NR != nrows || 64 * S::KT != ne) return false;
+  if (S::NP != np || S::NR != nrows || 64 * S::KT != ne || S::E0 != ell0) return false;
   for (int t = 0; t < np; ++t)
     if (pass[3 * t] != S::G[t] || pass[3 * t + 1] != S::K[t] || pass[3 * t + 2] != 64 * S::C[t]) return false;
   return true;
 }
 
-bool patch_regs_table_matches(int p, const int *pass, int np, int nrows, int ne) {
+bool patch_regs_table_matches(int p, const int *pass, int np, int nrows, int ne, int ell0) {
   switch (p) {
-    case 2: return pass_table_matches<2>(pass, np, nrows, ne);
-    case 3: return pass_table_matches<3>(pass, np, nrows, ne);
-    case 4: return pass_table_matches<4>(pass, np, nrows, ne);
-    case 5: return pass_table_matches<5>(pass, np, nrows, ne);
-    case 6: return pass_table_matches<6>(pass, np, nrows, ne);
-    case 7: return pass_table_matches<7>(pass, np, nrows, ne);
-    case 8: return pass_table_matches<8>(pass, np, nrows, ne);
+    case 2: return pass_table_matches<2>(pass, np, nrows, ne, ell0);
+    case 3: return pass_table_matches<3>(pass, np, nrows, ne, ell0);
+    case 4: return pass_table_matches<4>(pass, np, nrows, ne, ell0);
+    case 5: return pass_table_matches<5>(pass, np, nrows, ne, ell0);
+    case 6: return pass_table_matches<6>(pass, np, nrows, ne, ell0);
+    case 7: return pass_table_matches<7>(pass, np, nrows, ne, ell0);
+    case 8: return pass_table_matches<8>(pass, np, nrows, ne, ell0);
     default: return false;
   }
 }
@@ -1536,7 +1588,8 @@ static int launch_patch_solve_r(const LatDev &L, const PatchEllDev &E, const T *
   using S = PassTable<P>;
   constexpr int waves = 4;
   const long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
-  const size_t shm = (size_t)2 * waves * S::NR * sizeof(double) + 4 * (size_t)S::NR + 2 * (size_t)E.ne + 2 * 64 * S::NP;
+  const size_t shm =
+      (size_t)2 * waves * (S::NR + 1) * sizeof(double) + 4 * (size_t)S::NR + 2 * (size_t)E.ne + 2 * 64 * S::NP;
   static const int per_cu = [&] {
     hipFuncSetAttribute((const void *)k_patch_solve_r<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     int b = 0;

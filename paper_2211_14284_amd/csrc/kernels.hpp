@@ -49,6 +49,7 @@ struct PatchEllDev {
   const int *erow;                 // 64*npass: row solved by each lane's group (-1 none)
   const int *off;                  // 3*nrows: lattice offsets of the patch rows
   int regs;                        // 1: the schedule equals the one compiled into the register kernel
+  int ell0;                        // offset of the ELL values in a slot (values at ell0 + ell_pos)
 };
 
 // Trilinear cells with sampled coefficients: vertex coordinates (nvertices x 3,
@@ -113,7 +114,7 @@ void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *l
 // Returns non-zero when the schedule does not fit the LDS of one block.
 // true when the host pass table (G, K, ELL offset per pass; ne ELL values) of
 // degree p equals the schedule compiled into the register-resident patch solve
-bool patch_regs_table_matches(int p, const int *pass, int np, int nrows, int ne);
+bool patch_regs_table_matches(int p, const int *pass, int np, int nrows, int ne, int ell0);
 size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves);
 template <typename T>
 int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf, hipStream_t s);

@@ -133,9 +133,9 @@ static void schedule_level(PatchSymbolic &ps, std::vector<std::pair<int, std::ve
       for (int q = 0; q < G; ++q) ps.erow[r0 + j * G + q] = it.first;
       for (int m = 0; m < len; ++m) {
         const auto &e = it.second[(m + j * G) % len];
-        const int pos = base + (m / G) * W + j * G + (m % G);
-        ps.ecol[pos] = e.second;
-        ps.pos1[e.first] = ps.nrows + pos;
+        const int s = m / G, lane = j * G + (m % G);
+        ps.ecol[base + s * W + lane] = e.second;
+        ps.pos1[e.first] = ps.ell0 + ell_pos(base, K, s, lane);
       }
     }
   }
@@ -150,6 +150,7 @@ void build_wave_schedule(PatchSymbolic &ps) {
   ps.pass_base.clear();
   ps.ecol.clear();
   ps.erow.clear();
+  ps.ell0 = (n + 1) & ~1;
   for (int r = 0; r < n; ++r) ps.pos1[ps.rowptr[r + 1] - 1] = r;  // diagonal
   // forward: row i gathers L_ij x_j, j < i
   for (int l = 0; l < ps.nlev; ++l) {
@@ -167,7 +168,7 @@ void build_wave_schedule(PatchSymbolic &ps) {
   // the backward sweep reuses these passes in reverse (push form): no second copy
   ps.npass = ps.nfpass;
   ps.eb = 0;
-  ps.stride = n + ps.ef;
+  ps.stride = ps.ell0 + ps.ef;
 }
 
 }  // namespace rz

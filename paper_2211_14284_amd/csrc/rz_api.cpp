@@ -1267,7 +1267,8 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
   for (int k : ps.pass_k) kmax = std::max(kmax, k);
   h->PE = PatchEllDev{ps.nrows, ps.npass, ps.ef + ps.eb, ps.stride, kmax, dsym + o_pass, dsym + o_ecol,
                       dsym + o_erow, dsym + o_off,
-                      patch_regs_table_matches(p, passes.data(), ps.npass, ps.nrows, ps.ef + ps.eb) ? 1 : 0};
+                      patch_regs_table_matches(p, passes.data(), ps.npass, ps.nrows, ps.ef + ps.eb, ps.ell0) ? 1 : 0,
+                      ps.ell0};
   if (patch_solve_lds_bytes(h->PE, sizeof(double), 1) > 160 * 1024)
     return bail(fail(ctx, RZ_ERR_ARG, "patch schedule does not fit the LDS"));
   const size_t nf = (size_t)h->nvert * ps.stride, nzb = (size_t)h->nvert * ps.nrows;
