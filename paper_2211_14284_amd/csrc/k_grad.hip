@@ -417,26 +417,31 @@ __global__ void __launch_bounds__(256) k_condense_rows(LatDev L, const T *__rest
         const int cx = X / P, lx = X % P;
         const T llx = lam[lx];
         const T *ra = r + g;
+        // the interior values on the normal line in both cells, all loads in flight
+        // together before either sum
+        T vb[P > 1 ? P - 1 : 1], va[P > 1 ? P - 1 : 1];
+#pragma unroll
+        for (int i = 1; i < P; ++i) {
+          vb[i - 1] = ka > 0 ? ra[(long)(i - P) * st] : T(0);
+          va[i - 1] = ka < na ? ra[(long)i * st] : T(0);
+        }
+        // the cell's diagonal at (lx, i, lo_) with the normal axis at i: the
+        // weights of the normal and of the remaining in-face axis
+        const int an = ony ? 1 : 2, at = ony ? 2 : 1;
         if (ka > 0) {  // the cell below: its face at local coordinate P
           const T *cf = cw + 4 * cx;
+          const T e = cf[3] + cf[0] * llx, cn = cf[an], ct = cf[at] * llo;
           T hi = 0;
 #pragma unroll
-          for (int i = 1; i < P; ++i) {
-            const T dd = ony ? cf[3] + cf[0] * llx + cf[1] * lam[i] + cf[2] * llo
-                             : cf[3] + cf[0] * llx + cf[1] * llo + cf[2] * lam[i];
-            hi += Ag[P * N1 + i] * (ra[(long)(i - P) * st] / dd);
-          }
+          for (int i = 1; i < P; ++i) hi += Ag[P * N1 + i] * (vb[i - 1] / (e + cn * lam[i] + ct));
           val -= cf[a] * hi;
         }
         if (ka < na) {  // the cell above: its face at local coordinate 0
           const T *cf = cw + 4 * (L.nx + cx);
+          const T e = cf[3] + cf[0] * llx, cn = cf[an], ct = cf[at] * llo;
           T lo = 0;
 #pragma unroll
-          for (int i = 1; i < P; ++i) {
-            const T dd = ony ? cf[3] + cf[0] * llx + cf[1] * lam[i] + cf[2] * llo
-                             : cf[3] + cf[0] * llx + cf[1] * llo + cf[2] * lam[i];
-            lo += Ag[i] * (ra[(long)i * st] / dd);
-          }
+          for (int i = 1; i < P; ++i) lo += Ag[i] * (va[i - 1] / (e + cn * lam[i] + ct));
           val -= cf[a] * lo;
         }
       }
@@ -908,21 +913,31 @@ __global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, 
 template <int P, typename T>
 __device__ __forceinline__ T patch_sum(const LatDev &L, const int C[3], const T *zbuf) {
   constexpr int NR = 1 + 6 * (P - 1) + 12 * (P - 1) * (P - 1);
-  int lo[3], hi[3];
+  // the point's vertices: lo, and lo + 1 along the axes where the point is off the
+  // vertex planes; the (up to 8) loads are issued together, then summed in
+  // ascending vertex id (absent vertices add zero)
+  int lo[3];
+  bool two[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     lo[d] = C[d] / P;
-    hi[d] = (C[d] % P == 0) ? lo[d] : lo[d] + 1;
+    two[d] = C[d] % P != 0;
   }
   const int nvx = L.nx + 1, nvy = L.ny + 1;
+  T val[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int ix = c & 1, iy = (c >> 1) & 1, iz = c >> 2;
+    val[c] = T(0);
+    if ((ix == 0 || two[0]) && (iy == 0 || two[1]) && (iz == 0 || two[2])) {
+      const int vx = lo[0] + ix, vy = lo[1] + iy, vz = lo[2] + iz;
+      const int k = patch_local_index(P, C[0] - vx * P, C[1] - vy * P, C[2] - vz * P);
+      val[c] = zbuf[(vx + (long)nvx * (vy + (long)nvy * vz)) * NR + k];
+    }
+  }
   T acc = 0;
-  for (int vz = lo[2]; vz <= hi[2]; ++vz)
-    for (int vy = lo[1]; vy <= hi[1]; ++vy)
-      for (int vx = lo[0]; vx <= hi[0]; ++vx) {
-        const int k = patch_local_index(P, C[0] - vx * P, C[1] - vy * P, C[2] - vz * P);
-        const long vid = vx + (long)nvx * (vy + (long)nvy * vz);
-        acc += zbuf[vid * NR + k];
-      }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc += val[c];
   return acc;
 }
 
@@ -997,26 +1012,38 @@ __global__ void __launch_bounds__(256) k_expand_interior_rows(LatDev L, const T 
   const bool dzl = lat_dirichlet_axis(L, 2, cz * P), dzh = lat_dirichlet_axis(L, 2, cz * P + P);
   const T a0y = Ag[ly * N1], aPy = Ag[ly * N1 + P], a0z = Ag[lz * N1], aPz = Ag[lz * N1 + P];
   const T lmy = lam[ly], lmz = lam[lz];
+  // the x-dependent table entries (A_{lx,0}, A_{lx,P}, lambda_lx) in LDS
+  __shared__ T tx[3 * N1];
+  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
+    tx[3 * i] = Ag[i * N1];
+    tx[3 * i + 1] = Ag[i * N1 + P];
+    tx[3 * i + 2] = lam[i];
+  }
+  __syncthreads();
   for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) {
     const int cx = X / P, lx = X % P;
     if (lx == 0) continue;  // x-face point, written by the previous launch
     const long g = row + X;
     const T *cf = coef + 6 * (cx + cyz);
-    T dd = cf[3];
-    T val = o.scale * r[g];
+    // every load of the point first (the accumulated output too)
+    const T ac = o.acc ? o.acc[g] : T(0);
+    const T c0 = cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3];
+    const T rg = r[g];
     const T zlx = lat_dirichlet_axis(L, 0, cx * P) ? T(0) : z[g - lx];
     const T zhx = lat_dirichlet_axis(L, 0, cx * P + P) ? T(0) : z[g + (P - lx)];
     const T zly = dyl ? T(0) : z[g - (long)ly * L.Nx];
     const T zhy = dyh ? T(0) : z[g + (long)(P - ly) * L.Nx];
     const T zlz = dzl ? T(0) : z[g - (long)lz * sz];
     const T zhz = dzh ? T(0) : z[g + (long)(P - lz) * sz];
-    dd += cf[0] * lam[lx];
-    val -= cf[0] * (Ag[lx * N1] * zlx + Ag[lx * N1 + P] * zhx);
-    dd += cf[1] * lmy;
-    val -= cf[1] * (a0y * zly + aPy * zhy);
-    dd += cf[2] * lmz;
-    val -= cf[2] * (a0z * zlz + aPz * zhz);
-    if (o.acc) o.acc[g] += o.w * (val / dd);
+    T dd = c3;
+    T val = o.scale * rg;
+    dd += c0 * tx[3 * lx + 2];
+    val -= c0 * (tx[3 * lx] * zlx + tx[3 * lx + 1] * zhx);
+    dd += c1 * lmy;
+    val -= c1 * (a0y * zly + aPy * zhy);
+    dd += c2 * lmz;
+    val -= c2 * (a0z * zlz + aPz * zhz);
+    if (o.acc) o.acc[g] = ac + o.w * (val / dd);
     else z[g] = val / dd;
   }
 }
@@ -1236,48 +1263,90 @@ __global__ void __launch_bounds__(256) k_prolong_residual_p(LatDev L, const doub
   double *cw = lines + 9 * nv;        // [2 (cy-1, cy)][2 (z cells)][nx][4]
   double *tb = cw + 16 * L.nx;        // [2][P+1][2]: AE, BE
   const int cy = blockIdx.x % L.ny, Z = blockIdx.x / L.ny;
-  int czv[2], bzv[2], nz = 0;
-  if (Z % P == 0) {
-    if (Z / P > 0) { czv[nz] = Z / P - 1; bzv[nz++] = P; }
-    if (Z / P < L.nz) { czv[nz] = Z / P; bzv[nz++] = 0; }
-  } else {
-    czv[0] = Z / P; bzv[0] = Z % P; nz = 1;
-  }
+  // the cells containing the coordinate along one axis: (cell, local coordinate)
+  // for up to two cells, written without run-time array indices (registers)
+  auto cells_of = [](int C, int nc, int (&cv)[2], int (&bv)[2]) {
+    const int c = C / P;
+    if (C % P != 0) {
+      cv[0] = cv[1] = c;
+      bv[0] = bv[1] = C % P;
+      return 1;
+    }
+    const bool below = c > 0, above = c < nc;
+    cv[0] = below ? c - 1 : c;
+    bv[0] = below ? P : 0;
+    cv[1] = c;
+    bv[1] = 0;
+    return (below ? 1 : 0) + (above && below ? 1 : 0) + (!below && above ? 1 : 0);
+  };
+  int czv[2], bzv[2];
+  const int nz = cells_of(Z, L.nz, czv, bzv);
   const int vz0 = czv[0];
   const long sy = nv, sz = (long)nv * (L.ny + 1);
-  for (int t = threadIdx.x; t < 9 * nv; t += blockDim.x) {
-    const int v = t % nv, d = t / nv, vy = cy - 1 + d % 3, vz = vz0 + d / 3;
-    double val = 0.0;
-    if (vy >= 0 && vy <= L.ny && vz <= L.nz) {
+  // staging of lines, cw and tb (contiguous in LDS) as one index range, four
+  // entries per thread per round with their loads in flight together
+  const int n_ln = 9 * nv, n_cw = 16 * L.nx, n_st = n_ln + n_cw + 4 * (P + 1);
+  auto stage_value = [&](int t) -> double {
+    if (t < n_ln) {
+      const int v = t % nv, d = t / nv, vy = cy - 1 + d % 3, vz = vz0 + d / 3;
+      if (vy < 0 || vy > L.ny || vz > L.nz) return 0.0;
       const bool dir = ((L.dir & 1u) && v == 0) || ((L.dir & 2u) && v == L.nx) || ((L.dir & 4u) && vy == 0) ||
                        ((L.dir & 8u) && vy == L.ny) || ((L.dir & 16u) && vz == 0) || ((L.dir & 32u) && vz == L.nz);
-      val = dir ? 0.0 : xc[v + sy * vy + sz * vz];
+      return dir ? 0.0 : xc[v + sy * vy + sz * vz];
     }
-    lines[t] = val;
+    if (t < n_ln + n_cw) {
+      const int u = t - n_ln;
+      const int q = u % 4, cx = (u / 4) % L.nx, iy = (u / (4 * L.nx)) % 2, iz = u / (8 * L.nx);
+      const int ccy = cy - 1 + iy;
+      return (ccy >= 0 && iz < nz) ? coef[6 * (cx + (long)L.nx * (ccy + (long)L.ny * (iz ? czv[1] : czv[0]))) + q]
+                                   : 0.0;
+    }
+    return T2[t - n_ln - n_cw];
+  };
+  for (int t0 = threadIdx.x; t0 < n_st; t0 += 4 * blockDim.x) {
+    double sv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int t = t0 + k * blockDim.x;
+      sv[k] = t < n_st ? stage_value(t) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int t = t0 + k * blockDim.x;
+      if (t < n_st) sm[t] = sv[k];
+    }
   }
-  for (int t = threadIdx.x; t < 16 * L.nx; t += blockDim.x) {
-    const int q = t % 4, cx = (t / 4) % L.nx, iy = (t / (4 * L.nx)) % 2, iz = t / (8 * L.nx);
-    const int ccy = cy - 1 + iy;
-    cw[t] = (ccy >= 0 && iz < nz) ? coef[6 * (cx + (long)L.nx * (ccy + (long)L.ny * czv[iz])) + q] : 0.0;
-  }
-  for (int t = threadIdx.x; t < 4 * (P + 1); t += blockDim.x) tb[t] = T2[t];
   __syncthreads();
   if (lat_dirichlet_axis(L, 2, Z)) return;
   const double *AE = tb, *BE = tb + 2 * (P + 1);
   const int pz = min(Z / P, L.nz - 1), az = Z - pz * P;
   const double wz[2] = {E[2 * az], E[2 * az + 1]};
   const int nrow = cy + 1 == L.ny ? P + 1 : P;
-  for (int t = threadIdx.x; t < nrow * L.Nx; t += blockDim.x) {
+  // four points per thread per round: their z and r loads first, then the sums
+  const int npt = nrow * L.Nx;
+  for (int t0 = threadIdx.x; t0 < npt; t0 += 4 * blockDim.x) {
+    double zv[4], rv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int t = t0 + k * blockDim.x;
+      zv[k] = rv[k] = 0.0;
+      if (t < npt) {
+        const long g = (long)(t % L.Nx) + (long)L.Nx * (cy * P + t / L.Nx + (long)L.Ny * Z);
+        zv[k] = z[g];
+        rv[k] = r[g];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+    const int t = t0 + k * blockDim.x;
+    if (t >= npt) continue;
     const int X = t % L.Nx, Y = cy * P + t / L.Nx;
     if (lat_dirichlet_axis(L, 0, X) || lat_dirichlet_axis(L, 1, Y)) continue;
     // the cells containing the point along y (index into the staged cells: cy - 1 + iy)
-    int iyv[2], byv[2], ny = 0;
-    if (Y % P == 0) {
-      if (Y / P > 0) { iyv[ny] = Y / P - 1 - (cy - 1); byv[ny++] = P; }
-      if (Y / P < L.ny) { iyv[ny] = Y / P - (cy - 1); byv[ny++] = 0; }
-    } else {
-      iyv[0] = 1; byv[0] = Y % P; ny = 1;
-    }
+    int iyv[2], byv[2];
+    const int ny = cells_of(Y, L.ny, iyv, byv);
+    iyv[0] -= cy - 1;
+    iyv[1] -= cy - 1;
     // z += P xc (cell cy along y, the last cell for the last vertex plane)
     const int ay = Y - cy * P;
     const int px = min(X / P, L.nx - 1), ax = X - px * P;
@@ -1290,20 +1359,21 @@ __global__ void __launch_bounds__(256) k_prolong_residual_p(LatDev L, const doub
         pacc += wz[k] * E[2 * ay + j] * (E[2 * ax] * ln[px] + E[2 * ax + 1] * ln[px + 1]);
       }
     // r -= A P xc, summed over the cells containing the point
-    int cxv[2], bxv[2], nx = 0;
-    if (X % P == 0) {
-      if (X / P > 0) { cxv[nx] = X / P - 1; bxv[nx++] = P; }
-      if (X / P < L.nx) { cxv[nx] = X / P; bxv[nx++] = 0; }
-    } else {
-      cxv[0] = X / P; bxv[0] = X % P; nx = 1;
-    }
+    int cxv[2], bxv[2];
+    const int nx = cells_of(X, L.nx, cxv, bxv);
     double acc = 0.0;
-    for (int iz = 0; iz < nz; ++iz)
-      for (int i2 = 0; i2 < ny; ++i2) {
+    // fixed trip counts with guards, so that the short index arrays stay in registers
+#pragma unroll
+    for (int iz = 0; iz < 2; ++iz)
+#pragma unroll
+      for (int i2 = 0; i2 < 2; ++i2) {
+        if (iz >= nz || i2 >= ny) continue;
         const int iy = iyv[i2], b = byv[i2];
         const double By[2] = {BE[2 * b], BE[2 * b + 1]}, Ay[2] = {AE[2 * b], AE[2 * b + 1]};
         const double Bz[2] = {BE[2 * bzv[iz]], BE[2 * bzv[iz] + 1]}, Az[2] = {AE[2 * bzv[iz]], AE[2 * bzv[iz] + 1]};
-        for (int ix = 0; ix < nx; ++ix) {
+#pragma unroll
+        for (int ix = 0; ix < 2; ++ix) {
+          if (ix >= nx) continue;
           const int cx = cxv[ix], a = bxv[ix];
           const double *s = cw + 4 * (cx + L.nx * (iy + 2 * iz));
           const double Ax0 = AE[2 * a], Ax1 = AE[2 * a + 1], Bx0 = BE[2 * a], Bx1 = BE[2 * a + 1];
@@ -1320,8 +1390,9 @@ __global__ void __launch_bounds__(256) k_prolong_residual_p(LatDev L, const doub
         }
       }
     const long g = (long)X + (long)L.Nx * (Y + (long)L.Ny * Z);
-    z[g] += pacc;
-    r[g] -= acc;
+    z[g] = zv[k] + pacc;
+    r[g] = rv[k] - acc;
+    }
   }
 }
 
