@@ -1001,17 +1001,21 @@ __global__ void __launch_bounds__(256) k_expand_interior_rows(LatDev L, const T 
                                                               const T *__restrict__ Ag, const T *__restrict__ lam,
                                                               const T *__restrict__ r, T *__restrict__ z,
                                                               ExpandOut<T> o) {
+  // block: the P - 1 interior rows Y = cy P + ly (ly = 1 .. P - 1) of one y-layer of
+  // cells at one interior z-coordinate Z; a thread takes one x for all of them, so
+  // the y-face values at the layer's two ends and the cell weights are loaded once,
+  // and every load of the thread's P - 1 points is in flight before the first sum
   constexpr int N1 = P + 1;
-  int Y, Z;
-  interior_row<P>(L, xcd_block(blockIdx.x, gridDim.x), Y, Z);
-  const long row = (long)L.Nx * (Y + (long)L.Ny * Z);
-  const int cy = Y / P, ly = Y % P, cz = Z / P, lz = Z % P;
+  const long b = xcd_block(blockIdx.x, gridDim.x);
+  const int cy = b % L.ny;
+  constexpr int PI = P > 1 ? P - 1 : 1;  // interior coordinates per cell (P = 1 has none)
+  const int iz = b / L.ny, cz = iz / PI, lz = 1 + iz % PI, Z = cz * P + lz;
+  const long sy = L.Nx, sz = (long)L.Nx * L.Ny;
+  const long base = sy * ((long)cy * P + (long)L.Ny * Z);  // lattice row Y = cy P
   const long cyz = (long)L.nx * (cy + (long)L.ny * cz);
-  const long sz = (long)L.Nx * L.Ny;
   const bool dyl = lat_dirichlet_axis(L, 1, cy * P), dyh = lat_dirichlet_axis(L, 1, cy * P + P);
   const bool dzl = lat_dirichlet_axis(L, 2, cz * P), dzh = lat_dirichlet_axis(L, 2, cz * P + P);
-  const T a0y = Ag[ly * N1], aPy = Ag[ly * N1 + P], a0z = Ag[lz * N1], aPz = Ag[lz * N1 + P];
-  const T lmy = lam[ly], lmz = lam[lz];
+  const T a0z = Ag[lz * N1], aPz = Ag[lz * N1 + P], lmz = lam[lz];
   // the x-dependent table entries (A_{lx,0}, A_{lx,P}, lambda_lx) in LDS
   __shared__ T tx[3 * N1];
   for (int i = threadIdx.x; i < N1; i += blockDim.x) {
@@ -1023,28 +1027,40 @@ __global__ void __launch_bounds__(256) k_expand_interior_rows(LatDev L, const T 
   for (int X = threadIdx.x; X < L.Nx; X += blockDim.x) {
     const int cx = X / P, lx = X % P;
     if (lx == 0) continue;  // x-face point, written by the previous launch
-    const long g = row + X;
     const T *cf = coef + 6 * (cx + cyz);
-    // every load of the point first (the accumulated output too)
-    const T ac = o.acc ? o.acc[g] : T(0);
+    const bool dxl = lat_dirichlet_axis(L, 0, cx * P), dxh = lat_dirichlet_axis(L, 0, cx * P + P);
+    const long g0 = base + X;
     const T c0 = cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3];
-    const T rg = r[g];
-    const T zlx = lat_dirichlet_axis(L, 0, cx * P) ? T(0) : z[g - lx];
-    const T zhx = lat_dirichlet_axis(L, 0, cx * P + P) ? T(0) : z[g + (P - lx)];
-    const T zly = dyl ? T(0) : z[g - (long)ly * L.Nx];
-    const T zhy = dyh ? T(0) : z[g + (long)(P - ly) * L.Nx];
-    const T zlz = dzl ? T(0) : z[g - (long)lz * sz];
-    const T zhz = dzh ? T(0) : z[g + (long)(P - lz) * sz];
-    T dd = c3;
-    T val = o.scale * rg;
-    dd += c0 * tx[3 * lx + 2];
-    val -= c0 * (tx[3 * lx] * zlx + tx[3 * lx + 1] * zhx);
-    dd += c1 * lmy;
-    val -= c1 * (a0y * zly + aPy * zhy);
-    dd += c2 * lmz;
-    val -= c2 * (a0z * zlz + aPz * zhz);
-    if (o.acc) o.acc[g] = ac + o.w * (val / dd);
-    else z[g] = val / dd;
+    const T zly = dyl ? T(0) : z[g0];
+    const T zhy = dyh ? T(0) : z[g0 + P * sy];
+    constexpr int NI = P > 1 ? P - 1 : 1;
+    T rv[NI], av[NI], zlx[NI], zhx[NI], zlz[NI], zhz[NI];
+#pragma unroll
+    for (int k = 0; k < P - 1; ++k) {
+      const long g = g0 + (k + 1) * sy;
+      rv[k] = r[g];
+      av[k] = o.acc ? o.acc[g] : T(0);
+      zlx[k] = dxl ? T(0) : z[g - lx];
+      zhx[k] = dxh ? T(0) : z[g + (P - lx)];
+      zlz[k] = dzl ? T(0) : z[g - (long)lz * sz];
+      zhz[k] = dzh ? T(0) : z[g + (long)(P - lz) * sz];
+    }
+    const T a0x = tx[3 * lx], aPx = tx[3 * lx + 1], lmx = tx[3 * lx + 2];
+#pragma unroll
+    for (int k = 0; k < P - 1; ++k) {
+      const int ly = k + 1;
+      const long g = g0 + ly * sy;
+      T dd = c3;
+      T val = o.scale * rv[k];
+      dd += c0 * lmx;
+      val -= c0 * (a0x * zlx[k] + aPx * zhx[k]);
+      dd += c1 * lam[ly];
+      val -= c1 * (Ag[ly * N1] * zly + Ag[ly * N1 + P] * zhy);
+      dd += c2 * lmz;
+      val -= c2 * (a0z * zlz[k] + aPz * zhz[k]);
+      if (o.acc) o.acc[g] = av[k] + o.w * (val / dd);
+      else z[g] = val / dd;
+    }
   }
 }
 
@@ -1575,7 +1591,7 @@ static void expand_p(const LatDev &L, const T *coef, const T *A, const T *lam, c
   const int bs = L.Nx >= 256 ? 256 : ((L.Nx + 63) / 64) * 64;
   const long nxf = ni * (L.nx + 1);
   k_expand_plane_rows<P, T><<<(unsigned)(np + (long)nblocks(nxf, bs)), bs, 0, s>>>(L, r, zbuf, z, o, np, nxf);
-  if (ni > 0) k_expand_interior_rows<P, T><<<(unsigned)ni, bs, 0, s>>>(L, coef, A, lam, r, z, o);
+  if (ni > 0) k_expand_interior_rows<P, T><<<(unsigned)(ni / (P > 1 ? P - 1 : 1)), bs, 0, s>>>(L, coef, A, lam, r, z, o);
 }
 
 template <typename T>
