@@ -1265,11 +1265,11 @@ __global__ void __launch_bounds__(256) k_prolong_add_p(LatDev L, const double *_
 // vertices count as 0, which also makes P xc vanish on fine Dirichlet points; fine
 // Dirichlet rows keep z and r.  The block stages the (up to 9) coarse x-lines around
 // the row and the weights of the row's cells in LDS.
-template <int P>
+template <int P, typename TV>
 __global__ void __launch_bounds__(256) k_prolong_residual_p(LatDev L, const double *__restrict__ E,
                                                             const double *__restrict__ T2, const double *__restrict__ coef,
-                                                            const double *__restrict__ xc, double *__restrict__ z,
-                                                            double *__restrict__ r) {
+                                                            const double *__restrict__ xc, TV *__restrict__ z,
+                                                            TV *__restrict__ r) {
   // block: the lattice rows Y = cy P .. cy P + P - 1 (and Y = ny P in the last layer)
   // of one z-coordinate Z; they share the coarse lines at vertices cy - 1 .. cy + 1
   // along y and the weights of the cells cy - 1, cy
@@ -1348,8 +1348,8 @@ __global__ void __launch_bounds__(256) k_prolong_residual_p(LatDev L, const doub
       zv[k] = rv[k] = 0.0;
       if (t < npt) {
         const long g = (long)(t % L.Nx) + (long)L.Nx * (cy * P + t / L.Nx + (long)L.Ny * Z);
-        zv[k] = z[g];
-        rv[k] = r[g];
+        zv[k] = (double)z[g];
+        rv[k] = (double)r[g];
       }
     }
 #pragma unroll
@@ -1406,8 +1406,8 @@ __global__ void __launch_bounds__(256) k_prolong_residual_p(LatDev L, const doub
         }
       }
     const long g = (long)X + (long)L.Nx * (Y + (long)L.Ny * Z);
-    z[g] = zv[k] + pacc;
-    r[g] = rv[k] - acc;
+    z[g] = (TV)(zv[k] + pacc);
+    r[g] = (TV)(rv[k] - acc);
     }
   }
 }
@@ -1783,13 +1783,24 @@ void launch_prolong_add_grad(const LatDev &L, const double *E, const double *xc,
 #undef RZ_CALL
 }
 
-void launch_prolong_residual_grad(const LatDev &L, const double *E, const double *T2, const double *coef,
-                                  const double *xc, double *z, double *r, hipStream_t s) {
+template <typename TV>
+static void prolong_residual(const LatDev &L, const double *E, const double *T2, const double *coef,
+                             const double *xc, TV *z, TV *r, hipStream_t s) {
   const unsigned grid = (unsigned)((long)L.ny * L.Nz);
   const size_t shm = (9 * (size_t)(L.nx + 1) + 16 * (size_t)L.nx + 4 * (size_t)(L.p + 1)) * sizeof(double);
-#define RZ_CALL(Q) k_prolong_residual_p<Q><<<grid, 256, shm, s>>>(L, E, T2, coef, xc, z, r)
+#define RZ_CALL(Q) k_prolong_residual_p<Q, TV><<<grid, 256, shm, s>>>(L, E, T2, coef, xc, z, r)
   RZ_DISPATCH_P(L.p, RZ_CALL)
 #undef RZ_CALL
+}
+
+void launch_prolong_residual_grad(const LatDev &L, const double *E, const double *T2, const double *coef,
+                                  const double *xc, double *z, double *r, hipStream_t s) {
+  prolong_residual<double>(L, E, T2, coef, xc, z, r, s);
+}
+
+void launch_prolong_residual_grad_f(const LatDev &L, const double *E, const double *T2, const double *coef,
+                                    const double *xc, float *z, float *r, hipStream_t s) {
+  prolong_residual<float>(L, E, T2, coef, xc, z, r, s);
 }
 
 void launch_restrict_grad(const LatDev &L, const double *E, const double *rf, double *rc, double *t1, double *t2,

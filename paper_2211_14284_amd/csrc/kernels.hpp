@@ -156,6 +156,9 @@ void launch_prolong_add_grad(const LatDev &L, const double *E, const double *xc,
 // T2: the (p+1) x 2 products A E then B E of the 1-D tables with the hat embedding
 void launch_prolong_residual_grad(const LatDev &L, const double *E, const double *T2, const double *coef,
                                   const double *xc, double *z, double *r, hipStream_t s);
+// the same on FP32 vectors z and r (sums in FP64)
+void launch_prolong_residual_grad_f(const LatDev &L, const double *E, const double *T2, const double *coef,
+                                    const double *xc, float *z, float *r, hipStream_t s);
 // t1: (nx+1)*Ny*Nz and t2: (nx+1)*(ny+1)*Nz scratch arrays
 void launch_restrict_grad(const LatDev &L, const double *E, const double *rf, double *rc, double *t1,
                           double *t2, hipStream_t s);

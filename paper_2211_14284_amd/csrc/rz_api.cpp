@@ -376,13 +376,18 @@ rz_status do_vcycle32(rz_problem *h, const float *r, float *z) {
   }
   rz_status e = do_coarse(h, h->rc, h->xc);
   if (e) return e;
-  launch_fill(h->vt, 0.0, n, s);
-  {
+  if (h->T2_64) {  // z += P A0^{-1} P^T r1 and r2 = r1 - A P A0^{-1} P^T r1 = r - A z in one pass
     Timed tm(h, RZ_K_TRANSFER);
-    launch_prolong_add_grad(h->L, h->E64, h->xc, h->vt, s);
+    launch_prolong_residual_grad_f(h->L, h->E64, h->T2_64, h->coef64, h->xc, z, h->vr32, s);
+  } else {
+    launch_fill(h->vt, 0.0, n, s);
+    {
+      Timed tm(h, RZ_K_TRANSFER);
+      launch_prolong_add_grad(h->L, h->E64, h->xc, h->vt, s);
+    }
+    launch_add_d2f(h->vt, z, n, s);              // z += P A0^{-1} P^T r1
+    do_residual32(h, r, z, h->vr32);            // r2 = r - A z
   }
-  launch_add_d2f(h->vt, z, n, s);                // z += P A0^{-1} P^T r1
-  do_residual32(h, r, z, h->vr32);              // r2 = r - A z
   do_relax32(h, h->vr32, h->t32, 1.0f, w, z);  // z += w M r2
   launch_dirichlet_copy_f(h->L, r, z, s);
   return RZ_OK;

@@ -185,7 +185,9 @@ def test_vcycle_parity(rz, ctx, n, p, dirichlet):
     assert rel(H(z), V(r)) < 1e-12
 
 
-@pytest.mark.parametrize("n,p,prec", [((4, 4, 4), 4, 0), ((3, 3, 3), 7, 0), ((4, 4, 4), 4, 1)])
+# prec 1 (FP32 relaxation) includes the FP32 coarse correction fused with its residual
+@pytest.mark.parametrize("n,p,prec", [((4, 4, 4), 4, 0), ((3, 3, 3), 7, 0), ((4, 4, 4), 4, 1), ((3, 3, 3), 7, 1),
+                                      ((3, 4, 2), 5, 1)])
 def test_solve_parity(rz, ctx, n, p, prec):
     al, be = coefs(n)
     ref = Ref(n, p, al, be)
