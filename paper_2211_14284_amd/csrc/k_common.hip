@@ -303,15 +303,19 @@ __global__ void k_coarse_wc(int m, int mx, int my, const double *__restrict__ W,
 // wavefront (RPB rows per block); the neighbouring plane's vector is staged in LDS
 // once per block; the next matrix row is requested before the wait for that vector,
 // so its loads overlap the wait.
+// TM: element type of the stored dense blocks (FP64, or FP32 for the mixed
+// protocols); vectors and sums are FP64 either way
+template <typename TM>
 struct CoarseArgs2 {
   int m, nb, q, nbt;
-  const double *W, *M, *N, *r;
+  const TM *W, *M, *N;
+  const double *r;
   double *u, *v, *x;
   int *status;
 };
 
-template <int MPL, int RPB>
-__global__ void __launch_bounds__(64 * RPB) k_coarse_mn(CoarseArgs2 a) {
+template <int MPL, int RPB, typename TM>
+__global__ void __launch_bounds__(64 * RPB) k_coarse_mn(CoarseArgs2<TM> a) {
   extern __shared__ double vl[];
   const int m = a.m, nb = a.nb, q = a.q;
   const bool top = blockIdx.x < a.nbt;
@@ -319,11 +323,11 @@ __global__ void __launch_bounds__(64 * RPB) k_coarse_mn(CoarseArgs2 a) {
   const int row = (top ? blockIdx.x : blockIdx.x - a.nbt) * RPB + wid;
   const bool has_row = row < m;
   const size_t mm = (size_t)m * m;
-  double wr[MPL];
+  TM wr[MPL];
   // this wavefront's matrix row: loads without branches (column index clamped; the
   // entries past m are never used), left in flight until the next row_dot
-  auto load_row = [&](const double *mat) {
-    const double *Wr = mat + (size_t)(has_row ? row : 0) * m;
+  auto load_row = [&](const TM *mat) {
+    const TM *Wr = mat + (size_t)(has_row ? row : 0) * m;
 #pragma unroll
     for (int j = 0; j < MPL; ++j) wr[j] = Wr[min(lane + 64 * j, m - 1)];
   };
@@ -368,7 +372,7 @@ __global__ void __launch_bounds__(64 * RPB) k_coarse_mn(CoarseArgs2 a) {
 #pragma unroll
     for (int j = 0; j < MPL; ++j) {
       const int c = lane + 64 * j;
-      if (c < m) acc += wr[j] * vl[c];
+      if (c < m) acc += (double)wr[j] * vl[c];
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
     return acc;
@@ -574,29 +578,40 @@ void launch_coarse_wc(int m, int mx, int my, const double *W, const double *C, d
 
 int coarse_blocks(int m) { return m <= 1024 ? (m + 3) / 4 : (m + 15) / 16; }
 
-int launch_coarse_solve(int m, int nb, int q, const double *W, const double *M, const double *N, const double *r,
-                        double *u, double *v, double *x, int *status, hipStream_t s) {
+template <typename TM>
+static int coarse_solve(int m, int nb, int q, const TM *W, const TM *M, const TM *N, const double *r, double *u,
+                        double *v, double *x, int *status, hipStream_t s) {
   const bool small = m <= 1024;
   const int nbt = coarse_blocks(m);
   const int blocks = q + 1 < nb ? 2 * nbt : nbt;
   const int64_t nv = (int64_t)m * nb;
   k_fill_empty<<<nblk(nv), kBS, 0, s>>>(v, nv);
   k_fill_empty<<<nblk(nv), kBS, 0, s>>>(x, nv);
-  CoarseArgs2 a{m, nb, q, nbt, W, M, N, r, u, v, x, status};
+  CoarseArgs2<TM> a{m, nb, q, nbt, W, M, N, r, u, v, x, status};
   void *args[] = {&a};
   const void *fn;
   const int mpl = (m + 63) / 64;
   if (small) {
-    if (mpl <= 4) fn = (const void *)k_coarse_mn<4, 4>;
-    else if (mpl <= 8) fn = (const void *)k_coarse_mn<8, 4>;
-    else fn = (const void *)k_coarse_mn<16, 4>;
+    if (mpl <= 4) fn = (const void *)k_coarse_mn<4, 4, TM>;
+    else if (mpl <= 8) fn = (const void *)k_coarse_mn<8, 4, TM>;
+    else fn = (const void *)k_coarse_mn<16, 4, TM>;
   } else {
-    if (mpl <= 32) fn = (const void *)k_coarse_mn<32, 16>;
-    else if (mpl <= 64) fn = (const void *)k_coarse_mn<64, 16>;
+    if (mpl <= 32) fn = (const void *)k_coarse_mn<32, 16, TM>;
+    else if (mpl <= 64) fn = (const void *)k_coarse_mn<64, 16, TM>;
     else return -1;
   }
   hipError_t e = hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(small ? 256 : 1024), args, sizeof(double) * m, s);
   return e == hipSuccess ? 0 : -1;
+}
+
+int launch_coarse_solve(int m, int nb, int q, const double *W, const double *M, const double *N, const double *r,
+                        double *u, double *v, double *x, int *status, hipStream_t s) {
+  return coarse_solve<double>(m, nb, q, W, M, N, r, u, v, x, status, s);
+}
+
+int launch_coarse_solve_f(int m, int nb, int q, const float *W, const float *M, const float *N, const double *r,
+                          double *u, double *v, double *x, int *status, hipStream_t s) {
+  return coarse_solve<float>(m, nb, q, W, M, N, r, u, v, x, status, s);
 }
 
 void launch_coarse_gather(int nfree, int bx0, int by0, int bz0, int mx, int my, int NX, int NY, const double *rc,

@@ -180,6 +180,9 @@ int coarse_blocks(int m);
 // first, in stream order); returns 0 on a successful launch.
 int launch_coarse_solve(int m, int nb, int q, const double *W, const double *M, const double *N, const double *r,
                         double *u, double *v, double *x, int *status, hipStream_t s);
+// the same with the dense blocks stored in FP32 (vectors and sums in FP64)
+int launch_coarse_solve_f(int m, int nb, int q, const float *W, const float *M, const float *N, const double *r,
+                          double *u, double *v, double *x, int *status, hipStream_t s);
 // gather / scatter between the coarse lattice and the free-box block vector
 void launch_coarse_gather(int nfree, int bx0, int by0, int bz0, int mx, int my, int NX, int NY,
                           const double *rc, double *blk, hipStream_t s);

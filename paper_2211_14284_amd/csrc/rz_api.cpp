@@ -86,6 +86,8 @@ struct rz_problem {
   int cq = 0;  // middle plane of the twisted coarse factorisation
   double *cW = nullptr, *cC = nullptr, *cCt = nullptr, *cr = nullptr, *cv = nullptr, *cx = nullptr;
   double *cM = nullptr, *cN = nullptr, *cu = nullptr;
+  // FP32 copies of the dense blocks W, M, N (mixed and defect-correction protocols)
+  float *cW32 = nullptr, *cM32 = nullptr, *cN32 = nullptr;
   // krylov
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kAp = nullptr, *kro = nullptr;
   double *partials = nullptr, *dots = nullptr;
@@ -294,15 +296,18 @@ rz_status do_relax_prec(rz_problem *h, const double *r, double *z, double scale 
   return do_relax64(h, r, z, scale, w, acc);
 }
 
-rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv) {
+// Coarse solve; f32 selects the FP32 copies of the dense blocks (V-cycles of the
+// mixed protocols), otherwise FP64 throughout.
+rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv, bool f32 = false) {
   Timed tm(h, RZ_K_COARSE);
   hipStream_t s = h->ctx->stream;
   const int m = h->cm, nb = h->cmz;
-  const size_t mm = (size_t)m * m;
   launch_coarse_gather(m * nb, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cNX, h->cNY, rcv, h->cr, s);
-  (void)mm;
-  if (launch_coarse_solve(m, nb, h->cq, h->cW, h->cM, h->cN, h->cr, h->cu, h->cv, h->cx, h->status, s))
-    return fail(h->ctx, RZ_ERR_HIP, "cooperative launch of the coarse solve failed");
+  const int rc = f32 && h->cW32
+                     ? launch_coarse_solve_f(m, nb, h->cq, h->cW32, h->cM32, h->cN32, h->cr, h->cu, h->cv, h->cx,
+                                             h->status, s)
+                     : launch_coarse_solve(m, nb, h->cq, h->cW, h->cM, h->cN, h->cr, h->cu, h->cv, h->cx, h->status, s);
+  if (rc) return fail(h->ctx, RZ_ERR_HIP, "cooperative launch of the coarse solve failed");
   launch_coarse_scatter((int)h->ncoarse, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cmz, h->cNX, h->cNY,
                         h->cx, xcv, s);
   return RZ_OK;
@@ -318,7 +323,7 @@ rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
     Timed tm(h, RZ_K_TRANSFER);
     launch_restrict_grad(h->L, h->E64, h->vr, h->rc, h->rt1, h->rt2, s);
   }
-  do_coarse(h, h->rc, h->xc);
+  do_coarse(h, h->rc, h->xc, h->opts.precision != RZ_PREC_F64);
   if (h->T2_64) {  // z += P xc and r2 = r1 - A P xc in one pass
     Timed tm(h, RZ_K_TRANSFER);
     launch_prolong_residual_grad(h->L, h->E64, h->T2_64, h->coef64, h->xc, z, h->vr, s);
@@ -374,7 +379,7 @@ rz_status do_vcycle32(rz_problem *h, const float *r, float *z) {
     Timed tm(h, RZ_K_TRANSFER);
     launch_restrict_grad(h->L, h->E64, h->vr, h->rc, h->rt1, h->rt2, s);
   }
-  rz_status e = do_coarse(h, h->rc, h->xc);
+  rz_status e = do_coarse(h, h->rc, h->xc, true);
   if (e) return e;
   if (h->T2_64) {  // z += P A0^{-1} P^T r1 and r2 = r1 - A P A0^{-1} P^T r1 = r - A z in one pass
     Timed tm(h, RZ_K_TRANSFER);
@@ -716,6 +721,15 @@ rz_status setup_coarse(rz_problem *h) {
   if ((e = dalloc(h, &h->cr, nfree))) return e;
   if ((e = dalloc(h, &h->cv, nfree))) return e;
   if ((e = dalloc(h, &h->cx, nfree))) return e;
+  if (h->opts.precision != RZ_PREC_F64) {
+    // the V-cycle of the mixed protocols streams the blocks in FP32 (half the bytes of
+    // the coarse solve; its vectors and sums stay FP64)
+    const size_t nbm = (size_t)nb * m * m;
+    if ((e = dalloc(h, &h->cW32, nbm)) || (e = dalloc(h, &h->cM32, nbm)) || (e = dalloc(h, &h->cN32, nbm))) return e;
+    launch_cast_d2f(h->cW, h->cW32, (int64_t)nbm, s);
+    launch_cast_d2f(h->cM, h->cM32, (int64_t)nbm, s);
+    launch_cast_d2f(h->cN, h->cN32, (int64_t)nbm, s);
+  }
   HIPCALL(h, hipStreamSynchronize(s));
   return RZ_OK;
 }
