@@ -194,11 +194,14 @@ rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const
  *   RZ_EXPORT_TABLES1D   double: lambda (p-1), B (p+1)^2, A (p+1)^2, D p*(p+1),
  *                        E (p+1)*2 (p=1 embedding), all row-major
  *   RZ_EXPORT_AUXCOEF    double (ncells, 6) separable auxiliary weights
- *   RZ_EXPORT_OMEGA      double: the smoother damping of rz_vcycle / rz_solve   */
+ *   RZ_EXPORT_OMEGA      double: the smoother damping of rz_vcycle / rz_solve
+ *   RZ_EXPORT_PATCH_KERNEL int32 pair (FP64, FP32): 1 when the H(grad) patch solve
+ *                        keeps a patch's factor in registers between its two sweeps,
+ *                        0 when it streams the factor in both sweeps   */
 enum {
   RZ_EXPORT_DOFMAP = 0, RZ_EXPORT_PATCH = 1, RZ_EXPORT_IC_PATTERN = 2,
   RZ_EXPORT_IC_FACTOR = 3, RZ_EXPORT_TABLES1D = 4, RZ_EXPORT_AUXCOEF = 5,
-  RZ_EXPORT_OMEGA = 6
+  RZ_EXPORT_OMEGA = 6, RZ_EXPORT_PATCH_KERNEL = 7
 };
 rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *bytes);
 

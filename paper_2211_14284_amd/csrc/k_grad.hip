@@ -1691,10 +1691,16 @@ static int launch_patch_solve_r(const LatDev &L, const PatchEllDev &E, const T *
   return 0;
 }
 
+// the register kernel's range: the compiled schedule matches, p >= 2, and the slot's
+// values fit the registers (FP64 up to p = 7, FP32 up to p = 8)
+bool patch_solve_uses_regs(const PatchEllDev &E, int p, size_t elem) {
+  return E.regs && p >= 2 && p <= (elem == 8 ? 7 : 8);
+}
+
 template <typename T>
 int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf, hipStream_t s) {
   const long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
-  if (E.regs) {  // factor values in registers: FP64 up to p = 7, FP32 up to p = 8
+  if (patch_solve_uses_regs(E, L.p, sizeof(T))) {
     switch (L.p) {
       case 2: return launch_patch_solve_r<T, 2>(L, E, factor, rt, zbuf, s);
       case 3: return launch_patch_solve_r<T, 3>(L, E, factor, rt, zbuf, s);

@@ -115,6 +115,9 @@ void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *l
 // true when the host pass table (G, K, ELL offset per pass; ne ELL values) of
 // degree p equals the schedule compiled into the register-resident patch solve
 bool patch_regs_table_matches(int p, const int *pass, int np, int nrows, int ne, int ell0);
+// whether the patch solve of degree p in elements of elem bytes runs the
+// register-resident kernel (else the streaming one)
+bool patch_solve_uses_regs(const PatchEllDev &E, int p, size_t elem);
 size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves);
 template <typename T>
 int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf, hipStream_t s);

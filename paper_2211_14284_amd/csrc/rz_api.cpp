@@ -1670,6 +1670,11 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
     case RZ_EXPORT_OMEGA:
       put(&h->omega, sizeof(double));
       break;
+    case RZ_EXPORT_PATCH_KERNEL: {
+      const int32_t v[2] = {patch_solve_uses_regs(h->PE, h->p, 8) ? 1 : 0, patch_solve_uses_regs(h->PE, h->p, 4) ? 1 : 0};
+      put(v, sizeof v);
+      break;
+    }
     default:
       return fail(h->ctx, RZ_ERR_ARG, "bad export kind");
   }

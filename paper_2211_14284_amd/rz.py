@@ -24,7 +24,7 @@ F64, F32 = 0, 1
 COEF_CONST, COEF_CELL, COEF_SAMPLES = 0, 1, 2
 PREC_F64, PREC_MIXED, PREC_DEFECT = 0, 1, 2
 EXPORT_DOFMAP, EXPORT_PATCH, EXPORT_IC_PATTERN, EXPORT_IC_FACTOR = 0, 1, 2, 3
-EXPORT_TABLES1D, EXPORT_AUXCOEF, EXPORT_OMEGA = 4, 5, 6
+EXPORT_TABLES1D, EXPORT_AUXCOEF, EXPORT_OMEGA, EXPORT_PATCH_KERNEL = 4, 5, 6, 7
 KERNELS = ("apply", "condense", "patch", "expand", "transfer", "coarse", "krylov")
 STATUS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_OOM", -3: "RZ_ERR_BREAKDOWN",
           -4: "RZ_ERR_NOT_CONVERGED", -5: "RZ_ERR_HIP", -6: "RZ_ERR_SINGULAR", -7: "RZ_ERR_NODEVICE"}
@@ -291,6 +291,11 @@ class Problem:
 
     def omega(self):
         return float(self._export(EXPORT_OMEGA)[0])
+
+    def patch_kernel(self):
+        """(FP64, FP32): 1 where the patch solve holds the factor in registers."""
+        v = self._export(EXPORT_PATCH_KERNEL, dtype=np.int32)
+        return int(v[0]), int(v[1])
 
     def close(self):
         if self.handle:

@@ -185,6 +185,16 @@ def test_vcycle_parity(rz, ctx, n, p, dirichlet):
     assert rel(H(z), V(r)) < 1e-12
 
 
+# which patch-solve kernel runs: the register-resident one wherever the compiled
+# schedule applies and a slot's values fit (FP64 p <= 7, FP32 p <= 8); the relaxation
+# parity cases above run every degree, so both kernels are checked against the oracle
+@pytest.mark.parametrize("p", range(1, 10))
+def test_patch_kernel_choice(rz, ctx, p):
+    pb = rz.Problem(ctx, (2, 2, 2), p, 1.0, 1.0)
+    expect = (int(2 <= p <= 7), int(2 <= p <= 8))
+    assert pb.patch_kernel() == expect
+
+
 # prec 1 (FP32 relaxation) includes the FP32 coarse correction fused with its residual
 @pytest.mark.parametrize("n,p,prec", [((4, 4, 4), 4, 0), ((3, 3, 3), 7, 0), ((4, 4, 4), 4, 1), ((3, 3, 3), 7, 1),
                                       ((3, 4, 2), 5, 1)])
