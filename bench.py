@@ -313,8 +313,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
-              "(multi-GPU sharding is a design in DESIGN.md, not built); rerun with --gpus 1",
+        print("bench.py measures one GPU only: the hot path runs on a single MI355X "
+              "(sharding across GPUs is designed, not built); rerun with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     import torch
