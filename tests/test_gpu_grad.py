@@ -123,7 +123,18 @@ def test_ic_factor_parity(rz, ctx, n, p):
 # every degree (each has its own pass schedule), full and partial Dirichlet masks
 RELAX_CASES = [((3, 2, 4), 3, 0x3F), ((4, 4, 4), 4, 0x3F), ((3, 3, 3), 7, 0x3F), ((3, 3, 2), 1, 0x3F),
                ((2, 3, 2), 2, 0x15), ((3, 2, 3), 5, 0x2A), ((2, 2, 3), 6, 0x3F), ((2, 2, 2), 8, 0x15),
-               ((2, 2, 2), 9, 0x3F), ((3, 2, 2), 7, 0x0C)]
+               ((2, 2, 2), 9, 0x3F), ((3, 2, 2), 7, 0x0C),
+               # one cell (8 vertex slots: a launch of two blocks), no Dirichlet face
+               # (boundary patches with full rows), an elongated mesh
+               ((1, 1, 1), 7, 0x00), ((2, 2, 2), 7, 0x00), ((1, 1, 1), 3, 0x00), ((5, 1, 1), 6, 0x03)]
+
+
+def test_setup_rejects_empty_coarse_axis(rz, ctx):
+    """One cell with every face Dirichlet leaves the p = 1 coarse problem no free
+    DoF: setup reports a bad argument instead of building an empty coarse solve."""
+    with pytest.raises(rz.RzError) as e:
+        rz.Problem(ctx, (1, 1, 1), 3, 1.0, 1.0)
+    assert "coarse" in str(e.value)
 
 
 @pytest.mark.parametrize("n,p,dirichlet", RELAX_CASES)
