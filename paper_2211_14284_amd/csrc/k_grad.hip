@@ -497,12 +497,13 @@ __device__ void condense_xface(const LatDev &L, const T *__restrict__ coef, cons
 // which only this wavefront touches, each row gathering its entries; then the same
 // passes run in reverse for the transposed solve, each row finishing its value and
 // pushing it to its columns with LDS atomic adds (rows of one pass may share a
-// column; rows of one level never depend on each other).  The off-diagonals are
-// stored once and stream in ELL order in both sweeps; the block shares the
-// schedule's index tables in LDS.
-// The values stream into two register buffers used in turn (pass u + 1 loads while
-// pass u computes) through a buffer resource spanning the slot.  The slot's vector
-// is kept in FP64 in LDS for both precisions (the FP32 factor is widened on use).
+// column; rows of one level never depend on each other).  The block shares the
+// schedule's index tables in LDS, and the slot's vector is kept in FP64 in LDS for
+// both precisions (the FP32 factor is widened on use).
+// Two kernels: k_patch_solve_r (below) holds a slot's off-diagonals in registers
+// between the sweeps; k_patch_solve_w, for the degrees and precisions whose values do
+// not fit, streams them in both sweeps into two register buffers used in turn (pass
+// u + 1 loads while pass u computes) through a buffer resource spanning the slot.
 // ------------------------------------------------------------------------------------
 // sum over the K steps of one lane in a pass of buf[s] * x[col(s)], K uniform: one
 // straight-line body per K so that the LDS reads batch without per-step branches
