@@ -711,23 +711,69 @@ __device__ __forceinline__ double group_sum_c(double s) {
 }
 
 // pass t's values of a slot into their registers: the lane-adjacent step pairs
-// with one load each, an odd last step alone
+// with one load each, an odd last step alone.  A lane whose row is trivial (outside
+// the domain or on a Dirichlet face: an identity row, and a zero column in every
+// other row) takes an offset past the slot's range, which reads zeros without a
+// memory access.
 template <typename T, int P, int t>
-__device__ __forceinline__ void load_pass_regs(T (&v)[PassTable<P>::KT], __amdgpu_buffer_rsrc_t r, int lane) {
+__device__ __forceinline__ void load_pass_regs(T (&v)[PassTable<P>::KT], __amdgpu_buffer_rsrc_t r, int lane,
+                                               bool on) {
   using S = PassTable<P>;
   constexpr int K = S::K[t], c0 = S::C[t], base = S::E0 + 64 * c0;
+  constexpr unsigned kOut = 0x80000000u;
+  const unsigned o2 = on ? 2 * lane * (unsigned)sizeof(T) : kOut, o1 = on ? lane * (unsigned)sizeof(T) : kOut;
 #pragma unroll
   for (int g = 0; g < K / 2; ++g)
-    buffer_load2<T>(r, 2 * lane * (unsigned)sizeof(T), (base + 128 * g) * (unsigned)sizeof(T), v[c0 + 2 * g],
-                    v[c0 + 2 * g + 1]);
-  if constexpr (K & 1) v[c0 + K - 1] = buffer_load<T>(r, lane * (unsigned)sizeof(T), (base + 64 * (K - 1)) * sizeof(T));
+    buffer_load2<T>(r, o2, (base + 128 * g) * (unsigned)sizeof(T), v[c0 + 2 * g], v[c0 + 2 * g + 1]);
+  if constexpr (K & 1) v[c0 + K - 1] = buffer_load<T>(r, o1, (base + 64 * (K - 1)) * sizeof(T));
+}
+
+// the vertex of a slot and whether its patch lies inside the domain away from the
+// boundary (then no row of it is trivial)
+struct SlotPos {
+  int vx, vy, vz;
+  bool inner;
+};
+
+__device__ __forceinline__ SlotPos slot_pos(const LatDev &L, long sl) {
+  const int nvx = L.nx + 1, nvy = L.ny + 1;
+  SlotPos s;
+  s.vx = sl % nvx;
+  s.vy = (sl / nvx) % nvy;
+  s.vz = sl / ((long)nvx * nvy);
+  s.inner = s.vx >= 1 && s.vx < L.nx && s.vy >= 1 && s.vy < L.ny && s.vz >= 1 && s.vz < L.nz;
+  return s;
+}
+
+// bit t set when the lane's row in pass t is a real row of the slot at s (inside the
+// domain and not on a Dirichlet face; the dummy row NR is not); all set for inner
+// slots.  One short loop per boundary slot (at most 32 passes).
+template <typename T, int P>
+__device__ __forceinline__ unsigned real_row_mask(const LatDev &L, const int *off, const unsigned short *erow,
+                                                  int lane, const SlotPos &s) {
+  static_assert(PassTable<P>::NP <= 32, "one bit per pass");
+  // FP32 launches are bound by the latency of the passes rather than by HBM, so they
+  // load every row
+  if (sizeof(T) == 4 || s.inner) return 0xFFFFFFFFu;
+  unsigned m = 0;
+#pragma unroll 1
+  for (int t = 0; t < PassTable<P>::NP; ++t) {
+    const unsigned row = erow[64 * t + lane];
+    if (row >= (unsigned)PassTable<P>::NR) continue;
+    const int o = off[row];
+    const int X = s.vx * P + (o & 255) - 64, Y = s.vy * P + ((o >> 8) & 255) - 64,
+              Z = s.vz * P + ((o >> 16) & 255) - 64;
+    if (X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz && !lat_dirichlet(L, X, Y, Z)) m |= 1u << t;
+  }
+  return m;
 }
 
 template <typename T, int P, int t = 0>
-__device__ __forceinline__ void load_all_regs(T (&v)[PassTable<P>::KT], __amdgpu_buffer_rsrc_t r, int lane) {
+__device__ __forceinline__ void load_all_regs(T (&v)[PassTable<P>::KT], __amdgpu_buffer_rsrc_t r, int lane,
+                                              unsigned mask) {
   if constexpr (t < PassTable<P>::NP) {
-    load_pass_regs<T, P, t>(v, r, lane);
-    load_all_regs<T, P, t + 1>(v, r, lane);
+    load_pass_regs<T, P, t>(v, r, lane, (mask >> t) & 1u);
+    load_all_regs<T, P, t + 1>(v, r, lane, mask);
   }
 }
 
@@ -794,7 +840,8 @@ __device__ __forceinline__ void fwd_passes(const T (&v)[PassTable<P>::KT], doubl
 template <typename T, int P, int t>
 __device__ __forceinline__ void bwd_passes(T (&v)[PassTable<P>::KT], double *xw, const double *iw,
                                            const unsigned short *ecol, const unsigned short *erow, int lane,
-                                           const PassIdx<PassTable<P>::K[t]> &q, __amdgpu_buffer_rsrc_t nr) {
+                                           const PassIdx<PassTable<P>::K[t]> &q, __amdgpu_buffer_rsrc_t nr,
+                                           unsigned nmask) {
   using S = PassTable<P>;
   constexpr int K = S::K[t], c0 = S::C[t];
   const double a = xw[q.row];
@@ -810,10 +857,10 @@ __device__ __forceinline__ void bwd_passes(T (&v)[PassTable<P>::KT], double *xw,
     if constexpr (sizeof(T) == 4) asm("" : "+v"(vs));
     atomicAdd(&xw[q.ix[s]], -(double)vs * x);
   }
-  load_pass_regs<T, P, t>(v, nr, lane);
+  load_pass_regs<T, P, t>(v, nr, lane, (nmask >> t) & 1u);
   if constexpr (t > 0) {
     n.d = iw[n.row];
-    bwd_passes<T, P, t - 1>(v, xw, iw, ecol, erow, lane, n, nr);
+    bwd_passes<T, P, t - 1>(v, xw, iw, ecol, erow, lane, n, nr, nmask);
   }
 }
 
@@ -851,7 +898,7 @@ __global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, 
   };
   long sl = (long)blockIdx.x * nw + wu;
   T v[KT];  // the current slot's off-diagonals (step s of the slot's passes in v[s])
-  load_all_regs<T, P>(v, slot_rsrc(sl), lane);
+  if (sl < nslots) load_all_regs<T, P>(v, slot_rsrc(sl), lane, real_row_mask<T, P>(L, off, erow, lane, slot_pos(L, sl)));
   for (; sl < nslots; sl += step) {
     const T *f = factor + sl * (long)E.stride;
     const int vx = sl % nvx, vy = (sl / nvx) % nvy, vz = sl / ((long)nvx * nvy);
@@ -871,6 +918,8 @@ __global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, 
         dia[j] = f[i];
       }
     }
+    // the next slot's real rows (while this slot's right-hand side is in flight)
+    const unsigned nmask = real_row_mask<T, P>(L, off, erow, lane, slot_pos(L, sl + step));
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
       const int i = lane + 64 * j;
@@ -894,7 +943,7 @@ __global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, 
       PassIdx<S::K[NP - 1]> q;
       read_idx<P, NP - 1>(q, ecol, erow, lane);
       q.d = iw[q.row];
-      bwd_passes<T, P, NP - 1>(v, xw, iw, ecol, erow, lane, q, slot_rsrc(sl + step));
+      bwd_passes<T, P, NP - 1>(v, xw, iw, ecol, erow, lane, q, slot_rsrc(sl + step), nmask);
     }
     T *zo = zbuf + sl * (long)NR;
 #pragma unroll
