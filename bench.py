@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of a kernel group from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0, factors from a plain 1 GiB copy in the same run); the figure belongs
 # to the kernel version it was taken on (profiles/pmc_patch_solve_hgrad_q7_n32.md)
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {"patch": 2.281e9}
 METRIC = "GDoF/s sum-factorized apply; PCG time-to-1e-8, FP64 vs mixed, H(grad) p=7"
 
 
