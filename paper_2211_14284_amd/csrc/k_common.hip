@@ -267,10 +267,6 @@ __device__ __forceinline__ unsigned long long ld_agent_bits(const double *p) {
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_fill_empty(double *a, int64_t n) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) a[i] = __builtin_bit_cast(double, kEmpty);
-}
 
 // Coupling products of the block LDL^T: out = W_k Cs with Cs the 9-point in-plane
 // coupling of plane k to a neighbouring plane (C[a][j]: row a, neighbour j of a), so
@@ -450,12 +446,16 @@ __global__ void __launch_bounds__(64 * RPB) k_coarse_mn(CoarseArgs2<TM> a) {
   }
 }
 
+// the free coarse values into the plane-blocked order of the coarse solve, and
+// its sweep vectors v, x (as many entries) set to kEmpty for the solve that follows
 __global__ void k_coarse_gather(int nfree, int bx0, int by0, int bz0, int mx, int my, int NX, int NY,
-                                const double *rc, double *blk) {
+                                const double *rc, double *blk, double *v, double *xv) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nfree) return;
   int x = i % mx, y = (i / mx) % my, z = i / (mx * my);
   blk[i] = rc[(bx0 + x) + (int64_t)NX * ((by0 + y) + (int64_t)NY * (bz0 + z))];
+  v[i] = __builtin_bit_cast(double, kEmpty);
+  xv[i] = __builtin_bit_cast(double, kEmpty);
 }
 
 __global__ void k_coarse_scatter(int ncoarse, int bx0, int by0, int bz0, int mx, int my, int mz, int NX, int NY,
@@ -585,8 +585,6 @@ static int coarse_solve(int m, int nb, int q, const TM *W, const TM *M, const TM
   const int nbt = coarse_blocks(m);
   const int blocks = q + 1 < nb ? 2 * nbt : nbt;
   const int64_t nv = (int64_t)m * nb;
-  k_fill_empty<<<nblk(nv), kBS, 0, s>>>(v, nv);
-  k_fill_empty<<<nblk(nv), kBS, 0, s>>>(x, nv);
   CoarseArgs2<TM> a{m, nb, q, nbt, W, M, N, r, u, v, x, status};
   void *args[] = {&a};
   const void *fn;
@@ -615,8 +613,8 @@ int launch_coarse_solve_f(int m, int nb, int q, const float *W, const float *M, 
 }
 
 void launch_coarse_gather(int nfree, int bx0, int by0, int bz0, int mx, int my, int NX, int NY, const double *rc,
-                          double *blk, hipStream_t s) {
-  k_coarse_gather<<<(nfree + 255) / 256, 256, 0, s>>>(nfree, bx0, by0, bz0, mx, my, NX, NY, rc, blk);
+                          double *blk, double *v, double *x, hipStream_t s) {
+  k_coarse_gather<<<(nfree + 255) / 256, 256, 0, s>>>(nfree, bx0, by0, bz0, mx, my, NX, NY, rc, blk, v, x);
 }
 
 void launch_coarse_scatter(int ncoarse, int bx0, int by0, int bz0, int mx, int my, int mz, int NX, int NY,

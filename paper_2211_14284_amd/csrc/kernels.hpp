@@ -179,16 +179,19 @@ int coarse_blocks(int m);
 // Whole block-tridiagonal solve in one cooperative launch, on the twisted block
 // factorisation with middle plane q (q = nb - 1: top-down only).  W: nb inverse
 // blocks (m*m each); M, N: nb coupling products each (see k_coarse_mn); u: nb*m
-// scratch; v, x: nb*m each, overwritten (filled with the not-yet-written pattern
-// first, in stream order); returns 0 on a successful launch.
+// scratch; v, x: nb*m each, overwritten; on entry they must hold the not-yet-written
+// pattern (launch_coarse_gather sets it, earlier in the same stream); returns 0 on a
+// successful launch.
 int launch_coarse_solve(int m, int nb, int q, const double *W, const double *M, const double *N, const double *r,
                         double *u, double *v, double *x, int *status, hipStream_t s);
 // the same with the dense blocks stored in FP32 (vectors and sums in FP64)
 int launch_coarse_solve_f(int m, int nb, int q, const float *W, const float *M, const float *N, const double *r,
                           double *u, double *v, double *x, int *status, hipStream_t s);
-// gather / scatter between the coarse lattice and the free-box block vector
+// gather / scatter between the coarse lattice and the free-box block vector; the
+// gather also sets the sweep vectors v, x (nfree entries each) to the empty pattern
+// that launch_coarse_solve(_f) expects (call it before each solve)
 void launch_coarse_gather(int nfree, int bx0, int by0, int bz0, int mx, int my, int NX, int NY,
-                          const double *rc, double *blk, hipStream_t s);
+                          const double *rc, double *blk, double *v, double *x, hipStream_t s);
 void launch_coarse_scatter(int ncoarse, int bx0, int by0, int bz0, int mx, int my, int mz, int NX,
                            int NY, const double *blk, double *xc, hipStream_t s);
 

@@ -302,7 +302,8 @@ rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv, bool f32 = fa
   Timed tm(h, RZ_K_COARSE);
   hipStream_t s = h->ctx->stream;
   const int m = h->cm, nb = h->cmz;
-  launch_coarse_gather(m * nb, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cNX, h->cNY, rcv, h->cr, s);
+  launch_coarse_gather(m * nb, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cNX, h->cNY, rcv, h->cr, h->cv, h->cx,
+                       s);
   const int rc = f32 && h->cW32
                      ? launch_coarse_solve_f(m, nb, h->cq, h->cW32, h->cM32, h->cN32, h->cr, h->cu, h->cv, h->cx,
                                              h->status, s)
