@@ -627,14 +627,30 @@ __global__ void __launch_bounds__(1024) k_patch_solve_w(LatDev L, PatchEllDev E,
     // so the loads carry no branch and stay in flight across the other buffer's pass.
     const __amdgpu_buffer_rsrc_t fr =
         __builtin_amdgcn_make_buffer_rsrc((void *)f, (short)0, E.stride * (int)sizeof(T), 0x00020000);
+    // FP64: bit t set when the lane's row in pass t is real (boundary slots: trivial
+    // rows are identity rows with zero columns, their values are not loaded)
+    unsigned real = 0xFFFFFFFFu;
+    const bool inner = vx >= 1 && vx < L.nx && vy >= 1 && vy < L.ny && vz >= 1 && vz < L.nz;
+    if (sizeof(T) == 8 && !inner && np <= 32) {
+      real = 0;
+      for (int t = 0; t < np; ++t) {
+        const unsigned row = erow[64 * t + lane];
+        if (row >= (unsigned)nrows) continue;
+        const int o = off[row];
+        const int X = vx * p + (o & 255) - 64, Y = vy * p + ((o >> 8) & 255) - 64, Z = vz * p + ((o >> 16) & 255) - 64;
+        if (X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz && !lat_dirichlet(L, X, Y, Z))
+          real |= 1u << t;
+      }
+    }
     auto load_pass = [&](T (&buf)[KM], int t) {
       const int K = E.pass[3 * t + 1], base = E.ell0 + E.pass[3 * t + 2];
       const int K2 = K & ~1;
+      const bool on = (real >> t) & 1u;
 #pragma unroll
       for (int s = 0; s < KM; ++s) {
         // value position of step s (steps in lane-adjacent pairs, an odd last step alone)
         const int pos = s < K2 ? base + 128 * (s >> 1) + 2 * lane + (s & 1) : base + 64 * s + lane;
-        buf[s] = buffer_load<T>(fr, s < K ? (unsigned)pos * sizeof(T) : 0x80000000u);
+        buf[s] = buffer_load<T>(fr, s < K && on ? (unsigned)pos * sizeof(T) : 0x80000000u);
       }
     };
     // pass sequence u = 0 .. 2 np - 1: the passes forward (gather), then the same in
