@@ -1743,8 +1743,12 @@ static int launch_patch_solve_r(const LatDev &L, const PatchEllDev &E, const T *
   const long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
   const size_t shm =
       (size_t)2 * waves * (S::NR + 1) * sizeof(double) + 4 * (size_t)S::NR + 2 * (size_t)E.ne + 2 * 64 * S::NP;
+  // the LDS attribute on every launch (it belongs to the current device); the
+  // occupancy once (one device type)
+  if (hipFuncSetAttribute((const void *)k_patch_solve_r<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) !=
+      hipSuccess)
+    return -1;
   static const int per_cu = [&] {
-    hipFuncSetAttribute((const void *)k_patch_solve_r<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     int b = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_patch_solve_r<T, P>, 64 * waves, shm) != hipSuccess) b = 0;
     return b;

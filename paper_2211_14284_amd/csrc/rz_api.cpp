@@ -252,8 +252,8 @@ rz_status do_residual64(rz_problem *h, const double *b, const double *x, double 
 
 // z = scale * M r; with acc: acc += w * M r (z then holds only the plane values)
 template <typename T>
-void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T *f, T *rt, T *zb,
-                 const T *r, T *z, T scale = T(1), T w = T(0), T *acc = nullptr) {
+rz_status relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T *f, T *rt, T *zb,
+                      const T *r, T *z, T scale = T(1), T w = T(0), T *acc = nullptr) {
   hipStream_t s = h->ctx->stream;
   {
     Timed t(h, RZ_K_CONDENSE);
@@ -261,24 +261,23 @@ void relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T
   }
   {
     Timed t(h, RZ_K_PATCH);
-    launch_patch_solve<T>(h->L, h->PE, f, rt, zb, s);
+    if (launch_patch_solve<T>(h->L, h->PE, f, rt, zb, s)) return fail(h->ctx, RZ_ERR_HIP, "patch solve launch failed");
   }
   {
     Timed t(h, RZ_K_EXPAND);
     launch_expand_grad<T>(h->L, h->P, coef, A, lam, r, zb, z, scale, w, acc, s);
   }
+  return RZ_OK;
 }
 
 rz_status do_relax64(rz_problem *h, const double *r, double *z, double scale = 1.0, double w = 0.0,
                      double *acc = nullptr) {
-  relax_steps<double>(h, h->coef64, h->A64, h->lam64, h->f64, h->rt64, h->zb64, r, z, scale, w, acc);
-  return RZ_OK;
+  return relax_steps<double>(h, h->coef64, h->A64, h->lam64, h->f64, h->rt64, h->zb64, r, z, scale, w, acc);
 }
 
 rz_status do_relax32(rz_problem *h, const float *r, float *z, float scale = 1.0f, float w = 0.0f,
                      float *acc = nullptr) {
-  relax_steps<float>(h, h->coef32, h->A32, h->lam32, h->f32, h->rt32, h->zb32, r, z, scale, w, acc);
-  return RZ_OK;
+  return relax_steps<float>(h, h->coef32, h->A32, h->lam32, h->f32, h->rt32, h->zb32, r, z, scale, w, acc);
 }
 
 // fine relaxation on FP64 vectors in the precision of the problem's protocol
@@ -288,7 +287,7 @@ rz_status do_relax_prec(rz_problem *h, const double *r, double *z, double scale 
                         double *acc = nullptr) {
   if (h->opts.precision != RZ_PREC_F64) {
     launch_cast_d2f(r, h->r32, h->ndofs, h->ctx->stream);
-    do_relax32(h, h->r32, h->z32);
+    if (rz_status e = do_relax32(h, h->r32, h->z32)) return e;
     if (acc) launch_f2d_axpy(w, h->z32, acc, h->ndofs, h->ctx->stream);
     else launch_f2d_scale(scale, h->z32, z, h->ndofs, h->ctx->stream);
     return RZ_OK;
@@ -318,7 +317,7 @@ rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
   hipStream_t s = h->ctx->stream;
   const int64_t n = h->ndofs;
   const double w = h->omega;
-  do_relax_prec(h, r, z, w);               // z = w M r
+  if (rz_status e = do_relax_prec(h, r, z, w)) return e;  // z = w M r
   do_residual64(h, r, z, h->vr);           // r1 = r - A z
   {
     Timed tm(h, RZ_K_TRANSFER);
@@ -335,7 +334,7 @@ rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
     }
     do_residual64(h, r, z, h->vr);           // r2 = r - A z
   }
-  do_relax_prec(h, h->vr, h->vt, 1.0, w, z);  // z += w M r2
+  if (rz_status e = do_relax_prec(h, h->vr, h->vt, 1.0, w, z)) return e;  // z += w M r2
   launch_dirichlet_copy(h->L, r, z, s);
   return RZ_OK;
 }
@@ -373,7 +372,7 @@ rz_status do_vcycle32(rz_problem *h, const float *r, float *z) {
   hipStream_t s = h->ctx->stream;
   const int64_t n = h->ndofs;
   const float w = (float)h->omega;
-  do_relax32(h, r, z, w);                       // z = w M r
+  if (rz_status e = do_relax32(h, r, z, w)) return e;  // z = w M r
   do_residual32(h, r, z, h->vr32);              // r1 = r - A z
   launch_cast_f2d(h->vr32, h->vr, n, s);
   {
@@ -394,7 +393,7 @@ rz_status do_vcycle32(rz_problem *h, const float *r, float *z) {
     launch_add_d2f(h->vt, z, n, s);              // z += P A0^{-1} P^T r1
     do_residual32(h, r, z, h->vr32);            // r2 = r - A z
   }
-  do_relax32(h, h->vr32, h->t32, 1.0f, w, z);  // z += w M r2
+  if (rz_status e2 = do_relax32(h, h->vr32, h->t32, 1.0f, w, z)) return e2;  // z += w M r2
   launch_dirichlet_copy_f(h->L, r, z, s);
   return RZ_OK;
 }
@@ -552,7 +551,7 @@ rz_status estimate_lambda(rz_problem *h, double *lam_out) {
     v0[g] = lat_dirichlet_h(h, X, Y, Z) ? 0.0 : 2.0 * u - 1.0;
   }
   HIPCALL(h, hipMemcpyAsync(h->kr, v0.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
-  do_relax_prec(h, h->kr, h->kz);
+  if (rz_status e = do_relax_prec(h, h->kr, h->kz)) return e;
   HIPCALL(h, hipMemcpyAsync(h->kp, h->kz, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   double rz_;
   {
@@ -570,7 +569,7 @@ rz_status estimate_lambda(rz_problem *h, double *lam_out) {
     if (!(pAp > 0)) break;
     double a = rz_ / pAp;
     v_axpy(h, -a, h->kAp, h->kr);
-    do_relax_prec(h, h->kr, h->kz);
+    if ((e = do_relax_prec(h, h->kr, h->kz))) return e;
     double rzn;
     const double *xs2[1] = {h->kr}, *ys2[1] = {h->kz};
     e = dots_host(h, 1, xs2, ys2, &rzn);
@@ -918,7 +917,7 @@ rz_status pcg_iteration(PcgRun &R, bool first) {
   const bool mixed = h->opts.precision == RZ_PREC_MIXED;
   const int q = R.it & 1;
   double *rz = h->dots + 2 * q, *rz_old = h->dots + 2 * (1 - q);
-  do_vcycle(h, h->kr, h->kz);
+  if (rz_status e = do_vcycle(h, h->kr, h->kz)) return e;
   {
     Timed tm(h, RZ_K_KRYLOV);
     if (first) {
