@@ -180,3 +180,39 @@ def test_pcg_reaches_direct_solution(n, p):
     assert eA < 1e-7
     # iteration count inside the band of Table hgrad-iter (SC-ICC, Cartesian: 10-11)
     assert 8 <= it <= 16
+
+
+def test_vcycle_symmetric_positive_definite():
+    """With the same symmetric smoother before and after an exact coarse correction,
+    the V(1,1) cycle's error propagation (I - S A)(I - P A0^{-1} P^T A)(I - S A) is
+    self-adjoint in the A inner product, so the cycle is a symmetric operator on the
+    free DoFs, and positive for a damping below 2 / lambda_max(S A).  A residual taken
+    against the wrong iterate, a coarse correction that skips the transpose, or an
+    unequal pre- and post-smoothing breaks the symmetry."""
+    n, p = 3, 3
+    al = synth.cell_coefficients(n ** 3, 3)
+    be = synth.cell_coefficients(n ** 3, 4)
+    lat, A, R, Pr, cs = _solver(n, p, al, be)
+    mask = lat.dirichlet_mask()
+    v0 = np.where(mask, 0.0, synth.uniform_pm1(5, lat.ndofs))
+    lam = pmg.lanczos_lambda_max(A, lambda r: np.where(mask, 0.0, R.apply(r)), v0)
+    V = pmg.VCycle(lat, A, R, Pr, cs, pmg.omega_from_lambda(lam))
+    us = [np.where(mask, 0.0, synth.uniform_pm1(20 + k, lat.ndofs)) for k in range(3)]
+    Vu = [V(u) for u in us]
+    for i in range(3):
+        assert us[i] @ Vu[i] > 0
+        for j in range(i + 1, 3):
+            a, b = us[i] @ Vu[j], us[j] @ Vu[i]
+            assert abs(a - b) <= 1e-12 * np.sqrt((us[i] @ Vu[i]) * (us[j] @ Vu[j])), (i, j, a, b)
+    # the same check fails for a cycle whose post-smoothing uses the first residual
+    class Skewed(pmg.VCycle):
+        def __call__(self, r):
+            r = np.where(self.dmask, 0.0, r)
+            z = self.omega * np.where(self.dmask, 0.0, self.relax.apply(r))
+            r1 = r - self.A @ z
+            r1[self.dmask] = 0.0
+            z = z + self.Pr @ self.coarse.solve(self.Pr.T @ r1)
+            return z + self.omega * np.where(self.dmask, 0.0, self.relax.apply(r1))
+    S = Skewed(lat, A, R, Pr, cs, pmg.omega_from_lambda(lam))
+    a, b = us[0] @ S(us[1]), us[1] @ S(us[0])
+    assert abs(a - b) > 1e-8 * abs(a)
