@@ -159,3 +159,22 @@ def test_full_size_solve_residual(setup, prec):
         assert res <= bound, (c0, res, bound)
     if prec:
         pm.close()
+
+
+def test_full_size_vcycle_symmetric(setup):
+    """At the full size, a property the oracle cannot reach directly: the V(1,1) cycle
+    (same smoother before and after an exact coarse correction) is a symmetric,
+    positive operator on the free DoFs, so u.V(v) = v.V(u) and u.V(u) > 0."""
+    rz, ctx, pb, al, be = setup
+    free = ~_global_dirichlet(np.arange(pb.ndofs))
+    us = [torch.as_tensor(np.where(free, synth.uniform_pm1(80 + k, pb.ndofs), 0.0), device="cuda:0")
+          for k in range(2)]
+    vs = [torch.empty_like(u) for u in us]
+    for u, v in zip(us, vs):
+        pb.vcycle(u, v)
+    torch.cuda.synchronize()
+    a = float(torch.dot(us[0], vs[1]))
+    b = float(torch.dot(us[1], vs[0]))
+    n0, n1 = float(torch.dot(us[0], vs[0])), float(torch.dot(us[1], vs[1]))
+    assert n0 > 0 and n1 > 0
+    assert abs(a - b) <= 1e-10 * np.sqrt(n0 * n1), (a, b)
