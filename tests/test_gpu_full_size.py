@@ -178,3 +178,24 @@ def test_full_size_vcycle_symmetric(setup):
     n0, n1 = float(torch.dot(us[0], vs[0])), float(torch.dot(us[1], vs[1]))
     assert n0 > 0 and n1 > 0
     assert abs(a - b) <= 1e-10 * np.sqrt(n0 * n1), (a, b)
+
+
+@pytest.mark.parametrize("op", ["apply", "relax"])
+def test_full_size_operator_symmetric(setup, op):
+    """The operator and the patch relaxation are symmetric positive definite on the
+    free DoFs at any size (the relaxation is a sum of R_v^T (L_v L_v^T)^{-1} R_v over
+    the vertex patches with the symmetric condensation around it)."""
+    rz, ctx, pb, al, be = setup
+    free = ~_global_dirichlet(np.arange(pb.ndofs))
+    us = [torch.as_tensor(np.where(free, synth.uniform_pm1(90 + k, pb.ndofs), 0.0), device="cuda:0")
+          for k in range(2)]
+    vs = [torch.empty_like(u) for u in us]
+    for u, v in zip(us, vs):
+        getattr(pb, op)(u, v)
+    torch.cuda.synchronize()
+    # Dirichlet rows copy their input (zero here): only free rows enter the products
+    a = float(torch.dot(us[0], vs[1]))
+    b = float(torch.dot(us[1], vs[0]))
+    n0, n1 = float(torch.dot(us[0], vs[0])), float(torch.dot(us[1], vs[1]))
+    assert n0 > 0 and n1 > 0
+    assert abs(a - b) <= 1e-11 * np.sqrt(n0 * n1), (op, a, b)
