@@ -132,3 +132,22 @@ def test_c5_solve_residual(setup):
         g, y = _oracle_apply(c0, xh, v, a, b)
         free = ~_global_dirichlet(g)
         assert np.abs(bb[g[free]] - y[free]).max() <= bound, c0
+
+
+@pytest.mark.parametrize("op", ["apply", "relax", "vcycle"])
+def test_c5_operator_symmetric(setup, op):
+    """On the perturbed C5 mesh (quadrature apply, streaming patch solve at p = 8):
+    the operator, the relaxation and the V-cycle are symmetric positive operators on
+    the free DoFs, a property that holds at any size."""
+    rz, ctx, pb, v, a, b = setup
+    free = ~_global_dirichlet(np.arange(pb.ndofs))
+    us = [torch.as_tensor(np.where(free, synth.uniform_pm1(60 + k, pb.ndofs), 0.0), device="cuda:0")
+          for k in range(2)]
+    vs = [torch.empty_like(u) for u in us]
+    for u, w in zip(us, vs):
+        getattr(pb, op)(u, w)
+    torch.cuda.synchronize()
+    x, y = float(torch.dot(us[0], vs[1])), float(torch.dot(us[1], vs[0]))
+    n0, n1 = float(torch.dot(us[0], vs[0])), float(torch.dot(us[1], vs[1]))
+    assert n0 > 0 and n1 > 0
+    assert abs(x - y) <= 1e-10 * np.sqrt(n0 * n1), (op, x, y)
