@@ -105,3 +105,25 @@ def test_c3_full_size_sampled(rz, ctx):
         latw, g, cells, own = _window(c0, NC, P, lat)
         yw = matfree.apply(latw, x[g], 1.0, 1.0)
         assert np.linalg.norm(yh[g[own]] - yw[own]) < 1e-12 * np.linalg.norm(yw[own]), c0
+
+
+@pytest.mark.parametrize("space", ["curl", "div"])
+def test_c3_full_size_symmetric(rz, ctx, space):
+    """At the C3 size (NCE_6 / NCF_6 on 16^3): the operator is symmetric positive on
+    the free DoFs (Dirichlet rows copy their input, zero here), a property that holds
+    at any size."""
+    NC, P = 16, 6
+    lat = Lattice(Mesh(NC, NC, NC), space, P)
+    mask = lat.dirichlet_mask()
+    pb = rz.Problem(ctx, NC, P, 1.0, 1.0, space=space)
+    assert pb.ndofs == lat.ndofs
+    us = [torch.as_tensor(np.where(mask, 0.0, synth.uniform_pm1(30 + k, lat.ndofs)), device="cuda:0")
+          for k in range(2)]
+    vs = [torch.empty_like(u) for u in us]
+    for u, v in zip(us, vs):
+        pb.apply(u, v)
+    torch.cuda.synchronize()
+    a, b = float(torch.dot(us[0], vs[1])), float(torch.dot(us[1], vs[0]))
+    n0, n1 = float(torch.dot(us[0], vs[0])), float(torch.dot(us[1], vs[1]))
+    assert n0 > 0 and n1 > 0
+    assert abs(a - b) <= 1e-11 * np.sqrt(n0 * n1), (space, a, b)
