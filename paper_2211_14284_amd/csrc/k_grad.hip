@@ -271,28 +271,48 @@ __global__ void __launch_bounds__(256) k_apply_faces(LatDev L, const T *__restri
   int Y, Z;
   plane_row<P>(L, g / L.Nx, Y, Z);
   const long gi = lat_index(L, X, Y, Z);
+  const bool dir = lat_dirichlet(L, X, Y, Z);
+  // the (up to 2 x 2) rows of cells holding the point along y and z: candidate j is
+  // the cell below (j = 0, local coordinate P) or above (j = 1, local 0) on a vertex
+  // plane, the cell itself (j = 0) off it; the loads of all candidates go out
+  // together, then sum in the fixed order (z cells outer, y cells inner)
+  const int qy = Y / P, qz = Z / P;
+  const bool ony = Y % P == 0, onz = Z % P == 0;
+  T f[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int i = c & 1, k = c >> 1;
+    int cyc, byc, czc, bzc;
+    bool ok = !dir;
+    if (ony) {
+      cyc = i ? qy : qy - 1;
+      byc = i ? 0 : P;
+      ok = ok && cyc >= 0 && cyc < L.ny;
+    } else {
+      cyc = qy;
+      byc = Y % P;
+      ok = ok && i == 0;
+    }
+    if (onz) {
+      czc = k ? qz : qz - 1;
+      bzc = k ? 0 : P;
+      ok = ok && czc >= 0 && czc < L.nz;
+    } else {
+      czc = qz;
+      bzc = Z % P;
+      ok = ok && k == 0;
+    }
+    f[c] = ok ? fb[(((long)cyc + (long)L.ny * czc) * 4 * P + face_row<P>(byc, bzc)) * L.Nx + X] : T(0);
+  }
+  const T bs = bsub ? bsub[gi] : T(0);
   T val = 0;
-  if (lat_dirichlet(L, X, Y, Z)) {
+  if (dir) {
     val = x[gi];
   } else {
-    int cy[2], by[2], ny = 0, cz[2], bz[2], nz = 0;
-    if (Y % P == 0) {
-      if (Y / P > 0) { cy[ny] = Y / P - 1; by[ny++] = P; }
-      if (Y / P < L.ny) { cy[ny] = Y / P; by[ny++] = 0; }
-    } else {
-      cy[0] = Y / P; by[0] = Y % P; ny = 1;
-    }
-    if (Z % P == 0) {
-      if (Z / P > 0) { cz[nz] = Z / P - 1; bz[nz++] = P; }
-      if (Z / P < L.nz) { cz[nz] = Z / P; bz[nz++] = 0; }
-    } else {
-      cz[0] = Z / P; bz[0] = Z % P; nz = 1;
-    }
-    for (int k = 0; k < nz; ++k)
-      for (int i = 0; i < ny; ++i)
-        val += fb[(((long)cy[i] + (long)L.ny * cz[k]) * 4 * P + face_row<P>(by[i], bz[k])) * L.Nx + X];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) val += f[c];
   }
-  y[gi] = bsub ? bsub[gi] - val : val;
+  y[gi] = bsub ? bs - val : val;
 }
 
 // Interface rows of y: sum of the contributions of the (up to 8) cells that hold the
