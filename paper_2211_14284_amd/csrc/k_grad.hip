@@ -330,33 +330,40 @@ __global__ void k_apply_gather(LatDev L, const T *__restrict__ x, const T *__res
     y[g] = x[g];
     return;
   }
-  int cl[3][2], lo[3][2], cnt[3];
+  // per axis the (1 or 2) cells holding the coordinate: candidate 0 is the cell below
+  // (local p) on a vertex plane, else the cell itself; candidate 1 the cell above
+  // (local 0).  All (up to 8) loads go out together, then sum in the fixed order
+  // (z cells outer, x cells inner; absent cells add zero).
+  int c0[3], l0[3];
+  bool has0[3], has1[3];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const int nc = ncells_axis(L, d);
-    cnt[d] = 0;
+    const int nc = ncells_axis(L, d), c = C[d] / p;
     if (C[d] % p == 0) {
-      const int c = C[d] / p;
-      if (c - 1 >= 0) {
-        cl[d][cnt[d]] = c - 1;
-        lo[d][cnt[d]++] = p;
-      }
-      if (c < nc) {
-        cl[d][cnt[d]] = c;
-        lo[d][cnt[d]++] = 0;
-      }
+      has0[d] = c - 1 >= 0;
+      has1[d] = c < nc;
+      c0[d] = c - 1;
+      l0[d] = p;
     } else {
-      cl[d][0] = C[d] / p;
-      lo[d][0] = C[d] % p;
-      cnt[d] = 1;
+      has0[d] = true;
+      has1[d] = false;
+      c0[d] = c;
+      l0[d] = C[d] % p;
     }
   }
+  T v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int i = q & 1, j = (q >> 1) & 1, k = q >> 2;
+    const bool ok = (i ? has1[0] : has0[0]) && (j ? has1[1] : has0[1]) && (k ? has1[2] : has0[2]);
+    const int cx = i ? c0[0] + 1 : c0[0], cy = j ? c0[1] + 1 : c0[1], cz = k ? c0[2] + 1 : c0[2];
+    const int lx = i ? 0 : l0[0], ly = j ? 0 : l0[1], lz = k ? 0 : l0[2];
+    const long cell = cx + (long)L.nx * (cy + (long)L.ny * cz);
+    v[q] = ok ? ebuf[cell * n3 + lx + n1 * (ly + n1 * lz)] : T(0);
+  }
   T acc = 0;
-  for (int k = 0; k < cnt[2]; ++k)
-    for (int j = 0; j < cnt[1]; ++j)
-      for (int i = 0; i < cnt[0]; ++i) {
-        const long cell = cl[0][i] + (long)L.nx * (cl[1][j] + (long)L.ny * cl[2][k]);
-        acc += ebuf[cell * n3 + lo[0][i] + n1 * (lo[1][j] + n1 * lo[2][k])];
-      }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc += v[q];
   y[g] = acc;
 }
 
