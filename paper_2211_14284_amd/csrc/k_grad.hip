@@ -1559,34 +1559,49 @@ __global__ void k_restrict_x(LatDev L, const double *__restrict__ E, const doubl
   t1[i] = acc;
 }
 
+// y and z passes: the 2P - 1 taps of a coarse vertex as one unrolled body (loads of
+// all taps in flight together), summed in ascending fine coordinate; taps outside the
+// lattice add zero
+template <int P>
 __global__ void k_restrict_y(LatDev L, const double *__restrict__ E, const double *__restrict__ t1,
                              double *__restrict__ t2, long n) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int p = L.p, NCX = L.nx + 1, NCY = L.ny + 1;
+  const int NCX = L.nx + 1, NCY = L.ny + 1;
   const int VX = i % NCX, VY = (i / NCX) % NCY;
   const int Z = i / ((long)NCX * NCY);
-  const int lo = max(0, VY * p - (p - 1)), hi = min(L.Ny - 1, VY * p + (p - 1));
+  double v[2 * P - 1];
+#pragma unroll
+  for (int o = -(P - 1); o <= P - 1; ++o) {
+    const int Y = VY * P + o;
+    v[o + P - 1] = Y >= 0 && Y < L.Ny ? t1[VX + (long)NCX * (Y + (long)L.Ny * Z)] : 0.0;
+  }
   double acc = 0.0;
-  for (int Y = lo; Y <= hi; ++Y) acc += hat_weight(E, p, Y - VY * p) * t1[VX + (long)NCX * (Y + (long)L.Ny * Z)];
+#pragma unroll
+  for (int o = -(P - 1); o <= P - 1; ++o) acc += hat_weight(E, P, o) * v[o + P - 1];
   t2[i] = acc;
 }
 
+template <int P>
 __global__ void k_restrict_z(LatDev L, const double *__restrict__ E, const double *__restrict__ t2,
                              double *__restrict__ rc, long n) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int p = L.p, NC[3] = {L.nx + 1, L.ny + 1, L.nz + 1};
+  const int NC[3] = {L.nx + 1, L.ny + 1, L.nz + 1};
   const int VX = i % NC[0], VY = (i / NC[0]) % NC[1], VZ = i / ((long)NC[0] * NC[1]);
   const bool dir = ((L.dir & 1u) && VX == 0) || ((L.dir & 2u) && VX == NC[0] - 1) ||
                    ((L.dir & 4u) && VY == 0) || ((L.dir & 8u) && VY == NC[1] - 1) ||
                    ((L.dir & 16u) && VZ == 0) || ((L.dir & 32u) && VZ == NC[2] - 1);
-  double acc = 0.0;
-  if (!dir) {
-    const int lo = max(0, VZ * p - (p - 1)), hi = min(L.Nz - 1, VZ * p + (p - 1));
-    for (int Z = lo; Z <= hi; ++Z) acc += hat_weight(E, p, Z - VZ * p) * t2[VX + (long)NC[0] * (VY + (long)NC[1] * Z)];
+  double v[2 * P - 1];
+#pragma unroll
+  for (int o = -(P - 1); o <= P - 1; ++o) {
+    const int Z = VZ * P + o;
+    v[o + P - 1] = !dir && Z >= 0 && Z < L.Nz ? t2[VX + (long)NC[0] * (VY + (long)NC[1] * Z)] : 0.0;
   }
-  rc[i] = acc;
+  double acc = 0.0;
+#pragma unroll
+  for (int o = -(P - 1); o <= P - 1; ++o) acc += hat_weight(E, P, o) * v[o + P - 1];
+  rc[i] = dir ? 0.0 : acc;
 }
 
 // Dirichlet rows only: the points of the six boundary faces of the lattice (face f:
@@ -1922,8 +1937,11 @@ void launch_restrict_grad(const LatDev &L, const double *E, const double *rf, do
   } else {
     k_restrict_x<<<nblocks(n1, 256), 256, 0, s>>>(L, E, rf, t1, n1);
   }
-  k_restrict_y<<<nblocks(n2, 256), 256, 0, s>>>(L, E, t1, t2, n2);
-  k_restrict_z<<<nblocks(n3, 256), 256, 0, s>>>(L, E, t2, rc, n3);
+#define RZ_CALL(Q)                                                          \
+  k_restrict_y<Q><<<nblocks(n2, 256), 256, 0, s>>>(L, E, t1, t2, n2); \
+  k_restrict_z<Q><<<nblocks(n3, 256), 256, 0, s>>>(L, E, t2, rc, n3)
+  RZ_DISPATCH_P(L.p, RZ_CALL)
+#undef RZ_CALL
 }
 
 template void launch_apply_grad<double>(const LatDev &, const double *, const double *, const double *,
