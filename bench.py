@@ -70,16 +70,19 @@ def kernel_bytes(pb, sz, n):
 
 
 def time_solves(torch, pb, bt, x, steps, warmup):
+    """Wall time per solve over `steps` solves with the per-kernel events off; then
+    the same number of solves with them on, for the per-kernel breakdown only."""
     for _ in range(warmup):
         pb.solve(bt, x)
-    torch.cuda.synchronize()
-    pb.timing(True)
-    pb.timing_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = [pb.solve(bt, x) for _ in range(steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    pb.timing(True)
+    pb.timing_read()
+    for _ in range(steps):
+        pb.solve(bt, x)
     kt = pb.timing_read()
     pb.timing(False)
     return (t1 - t0) * 1e3 / steps, infos, kt
@@ -404,6 +407,8 @@ def main():
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()
+    torch.cuda.synchronize()
+    rz.close_all()
     print(json.dumps(out), flush=True)
 
 

@@ -122,6 +122,8 @@ void rz_opts_default(rz_opts *o);
  * the host-side data (numbering, 1-D tables, patch layout, IC pattern) for
  * rz_export, and every compute call returns RZ_ERR_NODEVICE. */
 rz_status rz_create(rz_ctx **ctx, int device, void *stream);
+/* Destroy a context.  RZ_ERR_ARG (and nothing destroyed) while problems or MLPs
+ * created on it have not been freed. */
 rz_status rz_destroy(rz_ctx *ctx);
 const char *rz_last_error(const rz_ctx *ctx);
 
@@ -183,6 +185,14 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *inf
 rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const *b, double *const *x,
                            int32_t nrhs, rz_solve_info *infos);
 
+/* Wait for the problem's queued work and report a coarse-solve wait that gave up.
+ * The coarse solve (inside rz_coarse_solve, rz_vcycle and rz_solve) synchronises
+ * its planes through bounded waits on data written in the same launch; a wait that
+ * runs out records a flag on the device (the result is then not valid).  rz_solve
+ * checks the flag itself; after the asynchronous calls, rz_sync returns RZ_ERR_HIP
+ * if it is set (and clears it), RZ_OK otherwise. */
+rz_status rz_sync(rz_problem *h);
+
 /* Export host copies of setup products for parity checks.  If buf is NULL, *bytes
  * receives the size needed.  what:
  *   RZ_EXPORT_DOFMAP     int64 (ncells, ncell_dofs) cell -> lattice index
@@ -240,7 +250,10 @@ rz_status rz_aux_data(const rz_problem *h, double *targets, double *features, do
 
 /* Replace the auxiliary weights (host array ncells x 6, all > 0) and rebuild what
  * depends on them: the patch IC factors and, unless omega was fixed, omega.
- * Synchronous.  RZ_ERR_BREAKDOWN if an IC pivot is not positive. */
+ * Quadrature-path problems only (on Cartesian cells with cellwise-constant
+ * coefficients the six weights are the operator itself: RZ_ERR_ARG).
+ * Synchronous.  RZ_ERR_BREAKDOWN if an IC pivot is not positive; the previous
+ * weights and factors are then restored. */
 rz_status rz_set_aux(rz_problem *h, const double *coef6);
 
 typedef struct rz_mlp rz_mlp;   /* opaque; parameters on the device of ctx */

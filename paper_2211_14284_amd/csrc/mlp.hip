@@ -14,10 +14,12 @@
 #include "../../include/rz.h"
 
 namespace rz {
-void *ctx_stream(const rz_ctx *ctx);  // the context's HIP stream (rz_api.cpp)
+void *ctx_stream(const rz_ctx *ctx);        // the context's HIP stream (rz_api.cpp)
+void ctx_retain(rz_ctx *ctx, int delta);   // count of live objects on a context
 }
 
 struct rz_mlp {
+  rz_ctx *ctx = nullptr;
   int nin = 0, nhid = 0, nout = 0;
   hipStream_t stream = nullptr;
   size_t nparam = 0;
@@ -234,6 +236,8 @@ rz_status rz_mlp_create(rz_ctx *ctx, int32_t nin, int32_t nhid, int32_t nout, ui
     rz_mlp_free(h);
     return RZ_ERR_HIP;
   }
+  h->ctx = ctx;
+  rz::ctx_retain(ctx, 1);
   *out = h;
   return RZ_OK;
 }
@@ -241,6 +245,7 @@ rz_status rz_mlp_create(rz_ctx *ctx, int32_t nin, int32_t nhid, int32_t nout, ui
 rz_status rz_mlp_free(rz_mlp *h) {
   if (!h) return RZ_OK;
   hipStreamSynchronize(h->stream);
+  rz::ctx_retain(h->ctx, -1);
   for (void *p : {(void *)h->param, (void *)h->grad, (void *)h->m, (void *)h->v, (void *)h->a1, (void *)h->a2,
                   (void *)h->y, (void *)h->g2, (void *)h->g1, (void *)h->gy, (void *)h->lossbuf, (void *)h->xb,
                   (void *)h->yb, (void *)h->perm})

@@ -23,10 +23,14 @@ struct rz_ctx {
   int device = -1;
   hipStream_t stream = nullptr;
   std::string err;
+  int nlive = 0;  // problems and MLPs created on this context and not yet freed
 };
 
 namespace rz {
 void *ctx_stream(const rz_ctx *ctx) { return ctx ? (void *)ctx->stream : nullptr; }
+void ctx_retain(rz_ctx *ctx, int delta) {
+  if (ctx) ctx->nlive += delta;
+}
 }  // namespace rz
 
 namespace {
@@ -105,6 +109,8 @@ rz_status fail(rz_ctx *ctx, rz_status st, const std::string &msg) {
   if (ctx) ctx->err = msg;
   return st;
 }
+
+rz_status take_device_status(rz_problem *h);
 
 #define HIPCALL(h, expr)                                                                   \
   do {                                                                                     \
@@ -427,10 +433,16 @@ rz_status defect_solve(rz_problem *h, const double *b, double *x, rz_solve_info 
   hipStream_t s = h->ctx->stream;
   const int64_t n = h->ndofs;
   rz_status e;
-  hipEvent_t ev0, ev1;
-  HIPCALL(h, hipEventCreate(&ev0));
-  HIPCALL(h, hipEventCreate(&ev1));
-  HIPCALL(h, hipEventRecord(ev0, s));
+  struct EventPair {  // destroyed on every return path
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+      if (a) hipEventDestroy(a);
+      if (b) hipEventDestroy(b);
+    }
+  } ev;
+  HIPCALL(h, hipEventCreate(&ev.a));
+  HIPCALL(h, hipEventCreate(&ev.b));
+  HIPCALL(h, hipEventRecord(ev.a, s));
   launch_fill(x, 0.0, n, s);
   v_scale_copy(h, 1.0, b, h->kr);
   launch_dirichlet_copy(h->L, nullptr, h->kr, s);
@@ -496,12 +508,11 @@ rz_status defect_solve(rz_problem *h, const double *b, double *x, rz_solve_info 
     }
     launch_add_f2d(h->ke32, x, n, s);
   }
-  HIPCALL(h, hipEventRecord(ev1, s));
-  HIPCALL(h, hipEventSynchronize(ev1));
+  HIPCALL(h, hipEventRecord(ev.b, s));
+  HIPCALL(h, hipEventSynchronize(ev.b));
   float ms = 0;
-  hipEventElapsedTime(&ms, ev0, ev1);
-  hipEventDestroy(ev0);
-  hipEventDestroy(ev1);
+  hipEventElapsedTime(&ms, ev.a, ev.b);
+  if (result == RZ_OK) result = take_device_status(h);
   if (info) {
     info->iters = it;
     info->status = result;
@@ -745,6 +756,21 @@ void release(rz_problem *h) {
   }
   h->ev_pool.clear();
   h->ev_used.clear();
+}
+
+// The coarse solve's bounded waits record -1 in the problem's status word when a
+// wait gives up (its result is then garbage).  Synchronises the stream, reads and
+// clears the word.
+rz_status take_device_status(rz_problem *h) {
+  if (!h->status) return RZ_OK;
+  int stv = 0;
+  HIPCALL(h, hipMemcpyAsync(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost, h->ctx->stream));
+  HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+  if (stv == 0) return RZ_OK;
+  const int zero = 0;
+  HIPCALL(h, hipMemcpyAsync(h->status, &zero, sizeof(int), hipMemcpyHostToDevice, h->ctx->stream));
+  HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+  return fail(h->ctx, RZ_ERR_HIP, "a bounded wait of the coarse solve gave up (device status word set)");
 }
 
 rz_status require_device(const rz_problem *h) {
@@ -1019,17 +1045,22 @@ rz_status pcg_step(PcgRun &R) {
   return RZ_OK;
 }
 
+void pcg_release(PcgRun &R) {
+  if (R.ev0) hipEventDestroy(R.ev0);
+  if (R.ev1) hipEventDestroy(R.ev1);
+  R.ev0 = R.ev1 = nullptr;
+}
+
 rz_status pcg_finish(PcgRun &R, rz_solve_info *info) {
   rz_problem *h = R.h;
   float ms = 0;
   if (R.ev0) {
-    HIPCALL(h, hipEventRecord(R.ev1, h->ctx->stream));
-    HIPCALL(h, hipEventSynchronize(R.ev1));
-    hipEventElapsedTime(&ms, R.ev0, R.ev1);
-    hipEventDestroy(R.ev0);
-    hipEventDestroy(R.ev1);
-    R.ev0 = R.ev1 = nullptr;
+    const bool ok = hipEventRecord(R.ev1, h->ctx->stream) == hipSuccess && hipEventSynchronize(R.ev1) == hipSuccess;
+    if (ok) hipEventElapsedTime(&ms, R.ev0, R.ev1);
+    pcg_release(R);
+    if (!ok) return fail(h->ctx, RZ_ERR_HIP, "stream execution failed during the solve");
   }
+  if (R.result == RZ_OK) R.result = take_device_status(h);
   if (info) {
     info->iters = R.it;
     info->status = R.result;
@@ -1073,13 +1104,20 @@ rz_status rz_create(rz_ctx **ctx, int device, void *stream) {
 }
 
 rz_status rz_destroy(rz_ctx *ctx) {
+  if (!ctx) return RZ_OK;
+  if (ctx->nlive > 0) {
+    ctx->err = "rz_destroy: " + std::to_string(ctx->nlive) + " problem(s) or MLP(s) on this context are not freed";
+    return RZ_ERR_ARG;
+  }
+  if (ctx->device >= 0) hipStreamSynchronize(ctx->stream);
   delete ctx;
   return RZ_OK;
 }
 
 const char *rz_last_error(const rz_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz_opts *opts, rz_problem **out) {
+static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz_opts *opts,
+                            rz_problem **out) {
   if (!ctx || !mesh || !cf || !opts || !out) return RZ_ERR_ARG;
   *out = nullptr;
   if (opts->space != RZ_GRAD && opts->space != RZ_CURL && opts->space != RZ_DIV)
@@ -1343,10 +1381,17 @@ rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz
   return RZ_OK;
 }
 
+rz_status rz_setup(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf, const rz_opts *opts, rz_problem **out) {
+  const rz_status e = setup_impl(ctx, mesh, cf, opts, out);
+  if (e == RZ_OK) ctx->nlive += 1;
+  return e;
+}
+
 rz_status rz_free(rz_problem *h) {
   if (!h) return RZ_OK;
   if (h->ctx && h->ctx->device >= 0) hipStreamSynchronize(h->ctx->stream);
   release(h);
+  if (h->ctx) h->ctx->nlive -= 1;
   delete h;
   return RZ_OK;
 }
@@ -1428,8 +1473,14 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *inf
   R.b = b;
   R.x = x;
   while (R.phase != PcgRun::DONE) {
-    if ((e = pcg_step(R))) return e;
-    if (R.phase != PcgRun::DONE) HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+    if ((e = pcg_step(R))) {
+      pcg_release(R);
+      return e;
+    }
+    if (R.phase != PcgRun::DONE && hipStreamSynchronize(h->ctx->stream) != hipSuccess) {
+      pcg_release(R);
+      return fail(h->ctx, RZ_ERR_HIP, "stream execution failed during the solve");
+    }
   }
   return pcg_finish(R, info);
 }
@@ -1455,6 +1506,7 @@ rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const
   std::vector<rz_status> st(n, RZ_OK);
   std::vector<hipEvent_t> ev(n, nullptr);
   std::vector<char> pending(n, 0);
+  rz_status first_fail = RZ_OK;  // first non-OK result of a finished solve
   auto start = [&](int i) {
     run[i] = PcgRun();
     run[i].h = hs[i];
@@ -1486,8 +1538,9 @@ rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const
       progressed = true;
       if (run[i].phase == PcgRun::DONE) {
         rz_solve_info inf{};
-        pcg_finish(run[i], &inf);
+        const rz_status r = pcg_finish(run[i], &inf);
         if (infos) infos[(int64_t)i * nrhs + rhs[i]] = inf;
+        if (r != RZ_OK && first_fail == RZ_OK) first_fail = r;  // keep solving the others
         if (++rhs[i] >= nrhs) continue;
         start(i);
       }
@@ -1508,10 +1561,13 @@ rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const
     for (int i = 0; i < n; ++i) active += live(i);
     if (!progressed && active > 0) std::this_thread::yield();
   }
-  for (int i = 0; i < n; ++i) hipEventDestroy(ev[i]);
+  for (int i = 0; i < n; ++i) {
+    hipEventDestroy(ev[i]);
+    pcg_release(run[i]);  // instances stopped by an error still hold their events
+  }
   for (int i = 0; i < n; ++i)
     if (st[i]) return st[i];
-  return RZ_OK;
+  return first_fail;
 }
 
 rz_status rz_aux_data(const rz_problem *h, double *targets, double *features, double *base) {
@@ -1536,15 +1592,11 @@ rz_status rz_aux_data(const rz_problem *h, double *targets, double *features, do
   return RZ_OK;
 }
 
-rz_status rz_set_aux(rz_problem *h, const double *coef6) {
-  rz_status e = require_device(h);
-  if (e) return e;
-  if ((e = require_grad(h))) return e;
-  if (!coef6) return fail(h->ctx, RZ_ERR_ARG, "rz_set_aux: null weights");
-  for (int64_t k = 0; k < 6 * h->ncells; ++k)
-    if (!(coef6[k] > 0)) return fail(h->ctx, RZ_ERR_ARG, "rz_set_aux: weights must be positive");
+// Upload per-cell auxiliary weights and refactor the vertex patches with them.
+// Returns 0, or the 1-based index of the patch slot whose IC broke down.
+namespace {
+rz_status refactor_patches(rz_problem *h, int *breakdown) {
   hipStream_t s = h->ctx->stream;
-  h->coef.assign(coef6, coef6 + 6 * h->ncells);
   std::vector<float> c32(h->coef.begin(), h->coef.end());
   HIPCALL(h, hipMemcpyAsync(h->coef64, h->coef.data(), sizeof(double) * h->coef.size(), hipMemcpyHostToDevice, s));
   HIPCALL(h, hipMemcpyAsync(h->coef32, c32.data(), sizeof(float) * c32.size(), hipMemcpyHostToDevice, s));
@@ -1553,16 +1605,41 @@ rz_status rz_set_aux(rz_problem *h, const double *coef6) {
   HIPCALL(h, hipMemsetAsync(h->f32, 0, nf * sizeof(float), s));
   HIPCALL(h, hipMemsetAsync(h->status, 0, sizeof(int), s));
   launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, h->f64, h->f32, h->status, s);
-  int stv = 0;
-  HIPCALL(h, hipMemcpyAsync(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCALL(h, hipMemcpyAsync(breakdown, h->status, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCALL(h, hipStreamSynchronize(s));
-  if (stv) return fail(h->ctx, RZ_ERR_BREAKDOWN, "incomplete Cholesky breakdown after rz_set_aux");
+  return RZ_OK;
+}
+}  // namespace
+
+rz_status rz_set_aux(rz_problem *h, const double *coef6) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  if ((e = require_grad(h))) return e;
+  // On Cartesian cells with cellwise-constant coefficients the six weights are the
+  // operator's own (P = A there): replacing them would change the matrix solved.
+  if (!h->quad)
+    return fail(h->ctx, RZ_ERR_ARG, "rz_set_aux: needs trilinear cells or sampled coefficients (the weights of a "
+                                    "Cartesian problem define its operator)");
+  if (!coef6) return fail(h->ctx, RZ_ERR_ARG, "rz_set_aux: null weights");
+  for (int64_t k = 0; k < 6 * h->ncells; ++k)
+    if (!(coef6[k] > 0)) return fail(h->ctx, RZ_ERR_ARG, "rz_set_aux: weights must be positive");
+  std::vector<double> old = h->coef;
+  h->coef.assign(coef6, coef6 + 6 * h->ncells);
+  int stv = 0;
+  if ((e = refactor_patches(h, &stv))) return e;
+  if (stv) {  // restore the previous weights and their factors
+    h->coef.swap(old);
+    int st2 = 0;
+    if ((e = refactor_patches(h, &st2))) return e;
+    return fail(h->ctx, RZ_ERR_BREAKDOWN,
+                "incomplete Cholesky breakdown with the new weights (previous weights restored)");
+  }
   if (!(h->opts.omega > 0)) {
     double lam = 0;
     if ((e = estimate_lambda(h, &lam))) return e;
     h->omega = 2.0 / (1.2 * lam);
   }
-  HIPCALL(h, hipStreamSynchronize(s));
+  HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
   return RZ_OK;
 }
 
@@ -1686,6 +1763,13 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
   std::memcpy(buf, out.data(), out.size());
   *bytes = (int64_t)out.size();
   return RZ_OK;
+}
+
+rz_status rz_sync(rz_problem *h) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+  return take_device_status(h);
 }
 
 rz_status rz_timing_enable(rz_problem *h, int on) {

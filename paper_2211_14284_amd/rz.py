@@ -5,9 +5,11 @@ passed as torch tensors (their data pointers) on the context's stream.
 There is no fallback: if the shared library is missing, importing this module
 raises.
 """
+import atexit
 import ctypes
 import sys
 import os
+import weakref
 
 import numpy as np
 
@@ -75,6 +77,7 @@ _proto = {
     "rz_vcycle": (ctypes.c_int, [_vp, _vp, _vp]),
     "rz_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(SolveInfo)]),
     "rz_export": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_int64)]),
+    "rz_sync": (ctypes.c_int, [_vp]),
     "rz_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "rz_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "rz_aux_data": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -97,6 +100,28 @@ for _name, (_res, _args) in _proto.items():
     _f = getattr(lib, _name)
     _f.restype = _res
     _f.argtypes = _args
+
+
+# Every object that holds a library handle.  At interpreter exit (before module
+# teardown) the problems and MLPs are freed, then the contexts, so no device
+# buffer, pinned buffer or event outlives the Python objects into the HIP
+# runtime's own teardown.
+_live = weakref.WeakSet()
+
+
+def close_all():
+    """Free every live problem and MLP, then every context (also run at exit)."""
+    objs = list(_live)
+    for last in (False, True):
+        for o in objs:
+            if isinstance(o, Context) == last:
+                try:
+                    o.close()
+                except RzError:
+                    pass
+
+
+atexit.register(close_all)
 
 
 def _ptr(t):
@@ -122,6 +147,7 @@ class Context:
         self.device = device
         # the stream must outlive the context (and the problems, which hold the context)
         self._stream = stream
+        _live.add(self)
 
     def error(self):
         return lib.rz_last_error(self.handle).decode()
@@ -131,8 +157,9 @@ class Context:
             raise RzError(code, self.error())
 
     def close(self):
+        """Destroy the context (its problems and MLPs must be closed first)."""
         if self.handle:
-            lib.rz_destroy(self.handle)
+            self.check(lib.rz_destroy(self.handle))
             self.handle = _vp()
 
     def __del__(self):
@@ -201,6 +228,7 @@ class Problem:
          self.npatches) = list(s)
         self.n = (nx, ny, nz)
         self.p = p
+        _live.add(self)
 
     # ---- compute (device tensors) -------------------------------------------------
     def apply(self, x, y, dtype=F64):
@@ -220,6 +248,10 @@ class Problem:
 
     def vcycle(self, r, z):
         self.ctx.check(lib.rz_vcycle(self.handle, _ptr(r), _ptr(z)))
+
+    def sync(self):
+        """Wait for the queued work; raises if a coarse-solve wait gave up."""
+        self.ctx.check(lib.rz_sync(self.handle))
 
     def solve(self, b, x, check=True):
         info = SolveInfo()
@@ -338,6 +370,7 @@ class MLP:
         self._check(lib.rz_mlp_create(ctx.handle, nin, nhid, nout, seed, ctypes.byref(self.handle)))
         self.nin, self.nhid, self.nout = nin, nhid, nout
         self.nparams = int(lib.rz_mlp_nparams(self.handle))
+        _live.add(self)
 
     def _check(self, code):
         if code != 0:
