@@ -206,16 +206,21 @@ class SCRelaxGrad:
             self.factors.append(L)
             self.patterns.append(pv)
 
-    def apply(self, r):
-        r = np.asarray(r, dtype=np.float64)
-        z = np.zeros_like(r)
-        zI = r[self.I] / self.dII
-        rt = r[self.G] - self.PGI @ zI
+    def patch_sum(self, rt):
+        """sum_v R_v^T (L_v L_v^T)^{-1} R_v rt for a vector rt on the interface set G."""
         zG = np.zeros(self.G.size)
         for (vid, dofs), L in zip(self.patches, self.factors):
             loc = self.pos[dofs]
             y = scipy.linalg.solve_triangular(L, rt[loc], lower=True)
             zG[loc] += scipy.linalg.solve_triangular(L.T, y, lower=False)
+        return zG
+
+    def apply(self, r):
+        r = np.asarray(r, dtype=np.float64)
+        z = np.zeros_like(r)
+        zI = r[self.I] / self.dII
+        rt = r[self.G] - self.PGI @ zI
+        zG = self.patch_sum(rt)
         zI = zI - (self.PIG @ zG) / self.dII
         z[self.I] = zI
         z[self.G] = zG
