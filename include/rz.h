@@ -147,6 +147,20 @@ rz_status rz_sizes(const rz_problem *h, int64_t sizes[8]);
  * x, y: device arrays of sizes[0] elements of type t; x and y must not overlap. */
 rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t);
 
+/* y = A x exactly as rz_apply (same kernels, same result), for callers that cannot
+ * allocate device memory at call time or must not trigger the library's own
+ * allocations (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The call allocates nothing: the apply's workspace (the
+ * face-line buffer of the Cartesian H(grad) path, the per-cell outputs of the
+ * quadrature and H(curl)/H(div) paths) is a static device array of 64 MiB per GPU,
+ * its address taken once per device by rz_create.  RZ_ERR_ARG if the problem needs
+ * more workspace than that (ny*nz*4p*Nx elements on the Cartesian H(grad) path,
+ * ncells*(p+1)^3 on the quadrature path, ncells*3p(p+1)^2 for H(curl)/H(div)).
+ * Every call on one GPU shares that array and it keeps the last call's contents:
+ * calls that overlap in time on one GPU (other streams, other contexts or
+ * threads) race and give wrong results; calls ordered on one stream are safe. */
+rz_status rz_apply_noalloc(rz_problem *h, const void *x, void *y, rz_dtype t);
+
 /* z = M^{-1} r, one application of the statically condensed additive Schwarz
  * relaxation on the auxiliary operator (eqs. schur, sc-asm-afw): cell-interior
  * solves, vertex-star interface patch solves with the IC factors, harmonic

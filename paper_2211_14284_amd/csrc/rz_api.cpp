@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -34,6 +35,33 @@ void ctx_retain(rz_ctx *ctx, int delta) {
 }  // namespace rz
 
 namespace {
+
+// Workspace of rz_apply_noalloc: one static device array per GPU (each device that
+// loads the library holds its own copy until the process ends).  Host code never
+// passes `scratch` itself to a kernel; it uses the device address taken once per
+// device by scratch_init.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// With `device` current: record the device address of `scratch` (once per device).
+hipError_t scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void *scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
 
 using namespace rz;
 
@@ -1094,6 +1122,7 @@ rz_status rz_create(rz_ctx **ctx, int device, void *stream) {
   c->stream = static_cast<hipStream_t>(stream);
   if (device >= 0) {
     hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = scratch_init(device);
     if (e != hipSuccess) {
       delete c;
       return RZ_ERR_HIP;
@@ -1416,6 +1445,58 @@ rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t) {
   if (t == RZ_F64) return do_apply64(h, static_cast<const double *>(x), static_cast<double *>(y));
   if (t == RZ_F32) return do_apply32(h, static_cast<const float *>(x), static_cast<float *>(y));
   return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad dtype");
+}
+
+// Bytes of the apply's workspace (face-line buffer of the Cartesian H(grad) path,
+// per-cell outputs of the quadrature and vector-space paths) for element size sz.
+static size_t apply_workspace_bytes(const rz_problem *h, size_t sz) {
+  if (h->space != RZ_GRAD) return (size_t)h->ncells * h->V.cell_dofs * sz;
+  const size_t n1 = (size_t)h->p + 1;
+  if (h->quad) return (size_t)h->ncells * n1 * n1 * n1 * sz;
+  return (size_t)h->ny * h->nz * 4 * h->p * h->Nx * sz;
+}
+
+rz_status rz_apply_noalloc(rz_problem *h, const void *x, void *y, rz_dtype t) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  if (!x || !y || x == y) return fail(h->ctx, RZ_ERR_ARG, "rz_apply_noalloc: bad vectors");
+  if (t != RZ_F64 && t != RZ_F32) return fail(h->ctx, RZ_ERR_ARG, "rz_apply_noalloc: bad dtype");
+  const size_t need = apply_workspace_bytes(h, t == RZ_F64 ? 8 : 4);
+  if (need > kScratchBytes) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "rz_apply_noalloc: this problem needs %zu bytes of workspace, more than the %zu "
+                  "bytes of the static scratch (use rz_apply)", need, kScratchBytes);
+    return fail(h->ctx, RZ_ERR_ARG, msg);
+  }
+  void *ws = scratch_ptr(h->ctx->device);
+  if (!ws) return fail(h->ctx, RZ_ERR_HIP, "rz_apply_noalloc: no scratch address for this device");
+  hipStream_t s = h->ctx->stream;
+  if (t == RZ_F64) {
+    const double *xd = static_cast<const double *>(x);
+    double *yd = static_cast<double *>(y), *wd = static_cast<double *>(ws);
+    if (h->space != RZ_GRAD) {
+      if (launch_apply_vec<double>(h->V, h->coef64, h->B64, h->D64, xd, yd, wd, s))
+        return fail(h->ctx, RZ_ERR_ARG, "unsupported degree");
+    } else if (h->quad) {
+      launch_apply_quad_cells<double>(h->L, h->Q64, xd, yd, wd, s);
+      launch_apply_gather<double>(h->L, xd, wd, yd, s);
+    } else {
+      launch_apply_grad<double>(h->L, h->coef64, h->t.B.data(), h->t.A.data(), xd, nullptr, yd, wd, s);
+    }
+  } else {
+    const float *xf = static_cast<const float *>(x);
+    float *yf = static_cast<float *>(y), *wf = static_cast<float *>(ws);
+    if (h->space != RZ_GRAD) {
+      if (launch_apply_vec<float>(h->V, h->coef32, h->B32, h->D32, xf, yf, wf, s))
+        return fail(h->ctx, RZ_ERR_ARG, "unsupported degree");
+    } else if (h->quad) {
+      launch_apply_quad_cells<float>(h->L, h->Q32, xf, yf, wf, s);
+      launch_apply_gather<float>(h->L, xf, wf, yf, s);
+    } else {
+      launch_apply_grad<float>(h->L, h->coef32, h->t.B.data(), h->t.A.data(), xf, nullptr, yf, wf, s);
+    }
+  }
+  return RZ_OK;
 }
 
 rz_status rz_relax(rz_problem *h, const void *r, void *z, rz_dtype t) {

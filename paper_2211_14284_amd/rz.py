@@ -70,6 +70,7 @@ _proto = {
     "rz_free": (ctypes.c_int, [_vp]),
     "rz_sizes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "rz_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+    "rz_apply_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
     "rz_relax": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
     "rz_prolong_add": (ctypes.c_int, [_vp, _vp, _vp]),
     "rz_restrict": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -233,6 +234,10 @@ class Problem:
     # ---- compute (device tensors) -------------------------------------------------
     def apply(self, x, y, dtype=F64):
         self.ctx.check(lib.rz_apply(self.handle, _ptr(x), _ptr(y), dtype))
+
+    def apply_noalloc(self, x, y, dtype=F64):
+        """y = A x with the library's static workspace (no allocation in the call)."""
+        self.ctx.check(lib.rz_apply_noalloc(self.handle, _ptr(x), _ptr(y), dtype))
 
     def relax(self, r, z, dtype=F64):
         self.ctx.check(lib.rz_relax(self.handle, _ptr(r), _ptr(z), dtype))
