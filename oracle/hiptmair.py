@@ -178,7 +178,7 @@ class Condensed:
         PII = P[self.I][:, self.I].tocsr()
         ncomp, lab = connected_components(PII != 0, directed=False)
         sizes = np.bincount(lab, minlength=ncomp)
-        if sizes.max() > 3:
+        if sizes.size and sizes.max() > 3:
             raise ValueError("P_II has a block larger than 3 x 3")
         self.block_sizes = sizes
         rows, cols, vals = [], [], []
@@ -193,8 +193,11 @@ class Condensed:
             cols.append(cc.ravel())
             vals.append(Linv.ravel())
         n = self.I.size
-        self.Linv = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                                  shape=(n, n))
+        if n:
+            self.Linv = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                      shape=(n, n))
+        else:                       # p = 1: no cell-interior DoF
+            self.Linv = sp.csr_matrix((0, 0))
         self.PGI = P[self.G][:, self.I].tocsr()
         self.PIG = P[self.I][:, self.G].tocsr()
         W = self.Linv @ self.PIG
