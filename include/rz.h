@@ -103,6 +103,8 @@ typedef struct {
   double omega;        /* smoother damping; 0 = 2/(1.2*lambda_max) with lambda_max  *
                         * estimated by 10 Lanczos steps on M^{-1}A                   */
   uint64_t lanczos_seed; /* SplitMix64 seed of the Lanczos start vector (default 99) */
+  double hdiv_eps;     /* H(div): multiple of the (beta-weighted) mass added to the   *
+                        * curl-curl potential problem (remark of Sec. 4.3); 0 = 1e-3 */
 } rz_opts;
 
 /* Results of rz_solve. */
@@ -221,11 +223,16 @@ rz_status rz_sync(rz_problem *h);
  *   RZ_EXPORT_OMEGA      double: the smoother damping of rz_vcycle / rz_solve
  *   RZ_EXPORT_PATCH_KERNEL int32 pair (FP64, FP32): 1 when the H(grad) patch solve
  *                        keeps a patch's factor in registers between its two sweeps,
- *                        0 when it streams the factor in both sweeps   */
+ *                        0 when it streams the factor in both sweeps
+ *   RZ_EXPORT_EDGE_PATCH int64: edge id, then the DoFs (ascending) of non-empty
+ *                        edge-star patch `index` of H(curl) (or of the NCE_p
+ *                        potential problem of H(div)); edge ids run over the axis
+ *                        (x, y, z) then lattice order of (cell along the axis,
+ *                        vertices across it)   */
 enum {
   RZ_EXPORT_DOFMAP = 0, RZ_EXPORT_PATCH = 1, RZ_EXPORT_IC_PATTERN = 2,
   RZ_EXPORT_IC_FACTOR = 3, RZ_EXPORT_TABLES1D = 4, RZ_EXPORT_AUXCOEF = 5,
-  RZ_EXPORT_OMEGA = 6, RZ_EXPORT_PATCH_KERNEL = 7
+  RZ_EXPORT_OMEGA = 6, RZ_EXPORT_PATCH_KERNEL = 7, RZ_EXPORT_EDGE_PATCH = 8
 };
 rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *bytes);
 

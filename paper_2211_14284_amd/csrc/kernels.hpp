@@ -25,6 +25,33 @@ struct VecDev {
   int cell_dofs;
 };
 
+// Per-cell algebra of the H(curl) / H(div) relaxation (device): the local numbering
+// (component and tile coordinates of every local DoF), the interior / interface
+// split, the interior blocks (at most 3 x 3) with their inverse Cholesky factors,
+// and P_GI, P_IG in CSR with one value set per key (cells with equal weights share
+// a key).
+template <typename T>
+struct VecCellDev {
+  int nI, nG, nblk, nnz_gi, nnz_ig;
+  const int *il, *gl;        // local DoF of each interior / interface position
+  const int *lcomp, *lcrd;   // per local DoF: component, 3 tile coordinates
+  const int *blk;            // 3 interior positions per block (-1 padded)
+  const int *key;            // key of every cell
+  const T *linv;             // per key: 9 values per block (L^{-1}, row-major, lower)
+  const int *gi_ptr, *gi_col;
+  const T *gi_val;           // per key: nnz_gi values
+  const int *ig_ptr, *ig_col;
+  const T *ig_val;           // per key: nnz_ig values
+};
+
+// Edge-star patch layout (fixed per degree: p mode blocks) and the patches.
+struct EdgeDev {
+  int p, nslot, fac_stride, npatch;
+  int blk_n[9], blk_slot[9], blk_fac[9];
+  const int *idx;   // npatch * nslot global DoFs (-1: absent slot)
+  const int *type;  // npatch: factor set of each patch
+};
+
 // Symbolic patch data on the device.
 struct PatchDev {
   int nrows, nnz;
@@ -133,6 +160,34 @@ void launch_apply_gather(const LatDev &L, const T *x, const T *ebuf, T *y, hipSt
 template <typename T>
 int launch_apply_vec(const VecDev &V, const T *coef, const T *B, const T *D, const T *x, T *y, T *ebuf,
                      hipStream_t s);
+// ---- H(curl) / H(div) relaxation ---------------------------------------------------
+// z_I = P_II^{-1} r_I at the interior DoFs; eb (ncells * nG) = P_GI z_I per cell
+template <typename T>
+void launch_vc_condense(const VecDev &V, const VecCellDev<T> &C, const T *r, T *z, T *eb, hipStream_t s);
+// z_I -= P_II^{-1} P_IG z_G
+template <typename T>
+void launch_vc_expand(const VecDev &V, const VecCellDev<T> &C, T *z, hipStream_t s);
+// y[rows[t]] = (x ? x[rows[t]] : 0) + sign * sum_{k in ptr[t]..ptr[t+1]} buf[pos[k]]
+template <typename T>
+void launch_list_gather(int n, const int *rows, const int *ptr, const int *pos, const T *buf, const T *x, T *y,
+                        T sign, hipStream_t s);
+// y[rows[t]] = d[t] * x[rows[t]]
+template <typename T>
+void launch_rows_scale(int n, const int *rows, const T *d, const T *x, T *y, hipStream_t s);
+// y[row t] (+= if add) sum_k val[k] x[col[k]], row t = rows ? rows[t] : t (sums in TV)
+template <typename TV, typename TX, typename TY>
+void launch_csr(int n, const int *rows, const int *ptr, const int *col, const TV *val, const TX *x, TY *y, int add,
+                hipStream_t s);
+// edge-star Cholesky solves: zb (npatch * nslot) from rt
+template <typename T>
+void launch_edge_solve(const EdgeDev &E, const T *fac, const T *rt, T *zb, hipStream_t s);
+// y = M x, dense m x m row-major matrix in TM, FP64 vectors
+template <typename TM>
+void launch_gemv(int m, const TM *M, const double *x, double *y, hipStream_t s);
+// z[list[t]] = r ? r[list[t]] : 0
+template <typename T>
+void launch_list_copy(int n, const int *list, const T *r, T *z, hipStream_t s);
+
 // number of compute units of the current device (cached), for persistent grids
 int device_cu_count();
 // z = scale * (relaxation output); with acc: acc += w * output at every point (scale

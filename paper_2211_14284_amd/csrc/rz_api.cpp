@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -19,6 +20,7 @@
 #include "geom.hpp"
 #include "patch.hpp"
 #include "tables1d.hpp"
+#include "vec_local.hpp"
 
 struct rz_ctx {
   int device = -1;
@@ -125,6 +127,53 @@ struct rz_problem {
   double *partials = nullptr, *dots = nullptr;
   double *hdots = nullptr;  // pinned host copy of the dot products (8 values)
   int *status = nullptr;
+  // ---- H(curl) / H(div): statically condensed Pavarino-Hiptmair relaxation --------
+  VecCellDev<double> vc64{};
+  VecCellDev<float> vc32{};
+  int nGam = 0;
+  int *gam = nullptr;                       // free interface DoFs, ascending
+  int *cg_ptr = nullptr, *cg_pos = nullptr; // condensation sums (positions in veb)
+  double *veb64 = nullptr;
+  float *veb32 = nullptr;                   // ncells * nG per-cell P_GI z_I
+  double *vrt64 = nullptr;
+  float *vrt32 = nullptr;                   // condensed right-hand side (all DoFs)
+  EdgeDev ed{};                             // curl: edge stars of the problem
+  double *efac64 = nullptr, *ezb64 = nullptr;
+  float *efac32 = nullptr, *ezb32 = nullptr;
+  int *eg_ptr = nullptr, *eg_pos = nullptr; // sums back (rows = gam)
+  std::vector<int64_t> edge_ids;            // curl: edge of every patch; div: of the potential's
+  std::vector<int> edge_idx;                // slot DoFs (host copy, for exports)
+  int edge_nslot = 0;
+  double *dinv64 = nullptr;
+  float *dinv32 = nullptr;                  // div: face stars (diagonal)
+  rz_problem *pot = nullptr;                // curl: Q_p potential problem (vertex-star IC)
+  EdgeDev ped{};                            // div: edge stars of the NCE potential problem
+  double *pfac64 = nullptr, *pzb64 = nullptr;
+  float *pfac32 = nullptr, *pzb32 = nullptr;
+  int npg = 0;
+  int *pg_rows = nullptr, *pg_ptr = nullptr, *pg_pos = nullptr;
+  int ndt = 0;                              // Dt^T: rows = free interface DoFs of the potential
+  int *dt_rows = nullptr, *dt_ptr = nullptr, *dt_col = nullptr;
+  double *dt_val64 = nullptr;
+  float *dt_val32 = nullptr;
+  int *d_ptr = nullptr, *d_col = nullptr;   // Dt: rows = gam
+  double *d_val64 = nullptr;
+  float *d_val32 = nullptr;
+  int64_t pndofs = 0;
+  double *vq64 = nullptr, *vy64 = nullptr;
+  float *vq32 = nullptr, *vy32 = nullptr;   // potential vectors
+  int ncf = 0;                              // free DoFs of the p = 1 space
+  double *cinv64 = nullptr;
+  float *cinv32 = nullptr;                  // dense A_0^{-1}
+  int *pr_ptr = nullptr, *pr_col = nullptr; // restriction (rows: coarse free, compact)
+  double *pr_val = nullptr;
+  int npf = 0;
+  int *pp_rows = nullptr, *pp_ptr = nullptr, *pp_col = nullptr;  // prolongation
+  double *pp_val = nullptr;
+  double *vcr = nullptr, *vcx = nullptr;
+  int nDir = 0;
+  int *dlist = nullptr;
+  std::vector<char> dmask;                  // host: Dirichlet rows
   // per-kernel timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -139,6 +188,10 @@ rz_status fail(rz_ctx *ctx, rz_status st, const std::string &msg) {
 }
 
 rz_status take_device_status(rz_problem *h);
+rz_status setup_vec_relax(rz_problem *h, const std::vector<double> &al, const std::vector<double> &be,
+                          const std::vector<std::array<double, 3>> &hs);
+rz_status alloc_krylov(rz_problem *h);
+rz_status estimate_lambda(rz_problem *h, double *lam_out);
 
 #define HIPCALL(h, expr)                                                                   \
   do {                                                                                     \
@@ -253,6 +306,82 @@ void v_scale_copy(rz_problem *h, double a, const double *x, double *y) {
   launch_scale_copy(a, x, y, h->ndofs, h->ctx->stream);
 }
 
+// z_D = r_D (r == nullptr: z_D = 0) on the Dirichlet rows of the problem's space
+void dir_copy(rz_problem *h, const double *r, double *z, hipStream_t s) {
+  if (h->space == RZ_GRAD) launch_dirichlet_copy(h->L, r, z, s);
+  else launch_list_copy<double>(h->nDir, h->dlist, r, z, s);
+}
+void dir_copy_f(rz_problem *h, const float *r, float *z, hipStream_t s) {
+  if (h->space == RZ_GRAD) launch_dirichlet_copy_f(h->L, r, z, s);
+  else launch_list_copy<float>(h->nDir, h->dlist, r, z, s);
+}
+
+// z = M^{-1} r for H(curl) / H(div): statically condensed Pavarino-Hiptmair
+// relaxation (eq. schur for the interiors, eq. sc-asm-hiptmair on the interface
+// without the coarse term):
+//   z_I = P_II^{-1} r_I;  rt = r_G - P_GI z_I;
+//   z_G = sum_i R_i^T S_i^{-1} R_i rt + Dt (sum_j R_j^T Bt_j^{-1} R_j) Dt^T rt;
+//   z_I -= P_II^{-1} P_IG z_G;  z_D = r_D.
+// T selects the precision of vectors, factors and sums.
+template <typename T>
+struct VecRelaxPtrs {
+  const VecCellDev<T> *vc;
+  T *veb, *vrt, *ezb, *vq, *vy, *pzb;
+  const T *efac, *dinv, *dtv, *dv, *pfac;
+  const T *fq, *coefq, *Aq, *lamq;  // curl: the Q_p potential problem
+  T *zbq;
+};
+
+VecRelaxPtrs<double> vec_ptrs64(rz_problem *h) {
+  const rz_problem *q = h->pot;
+  return {&h->vc64, h->veb64, h->vrt64, h->ezb64, h->vq64, h->vy64, h->pzb64, h->efac64, h->dinv64,
+          h->dt_val64, h->d_val64, h->pfac64, q ? q->f64 : nullptr, q ? q->coef64 : nullptr,
+          q ? q->A64 : nullptr, q ? q->lam64 : nullptr, q ? q->zb64 : nullptr};
+}
+VecRelaxPtrs<float> vec_ptrs32(rz_problem *h) {
+  const rz_problem *q = h->pot;
+  return {&h->vc32, h->veb32, h->vrt32, h->ezb32, h->vq32, h->vy32, h->pzb32, h->efac32, h->dinv32,
+          h->dt_val32, h->d_val32, h->pfac32, q ? q->f32 : nullptr, q ? q->coef32 : nullptr,
+          q ? q->A32 : nullptr, q ? q->lam32 : nullptr, q ? q->zb32 : nullptr};
+}
+
+template <typename T>
+rz_status relax_vec(rz_problem *h, const VecRelaxPtrs<T> &X, const T *r, T *z) {
+  hipStream_t s = h->ctx->stream;
+  {
+    Timed t(h, RZ_K_CONDENSE);
+    launch_vc_condense<T>(h->V, *X.vc, r, z, X.veb, s);
+    launch_list_gather<T>(h->nGam, h->gam, h->cg_ptr, h->cg_pos, X.veb, r, X.vrt, T(-1), s);
+  }
+  {
+    Timed t(h, RZ_K_PATCH);
+    if (h->space == RZ_CURL) {  // edge stars (exact Cholesky)
+      launch_edge_solve<T>(h->ed, X.efac, X.vrt, X.ezb, s);
+      launch_list_gather<T>(h->nGam, h->gam, h->eg_ptr, h->eg_pos, X.ezb, (const T *)nullptr, z, T(1), s);
+    } else {  // face stars: the interface Schur complement is diagonal on a face
+      launch_rows_scale<T>(h->nGam, h->gam, X.dinv, X.vrt, z, s);
+    }
+    // potential term: Dt (sum_j R_j^T Bt_j^{-1} R_j) Dt^T rt
+    launch_csr<T, T, T>(h->ndt, h->dt_rows, h->dt_ptr, h->dt_col, X.dtv, X.vrt, X.vq, 0, s);
+    if (h->space == RZ_CURL) {
+      rz_problem *q = h->pot;
+      if (launch_patch_solve<T>(q->L, q->PE, X.fq, X.vq, X.zbq, s))
+        return fail(h->ctx, RZ_ERR_HIP, "potential patch solve launch failed");
+      launch_expand_grad<T>(q->L, q->P, X.coefq, X.Aq, X.lamq, X.vq, X.zbq, X.vy, T(1), T(0), (T *)nullptr, s);
+    } else {
+      launch_edge_solve<T>(h->ped, X.pfac, X.vq, X.pzb, s);
+      launch_list_gather<T>(h->npg, h->pg_rows, h->pg_ptr, h->pg_pos, X.pzb, (const T *)nullptr, X.vy, T(1), s);
+    }
+    launch_csr<T, T, T>(h->nGam, h->gam, h->d_ptr, h->d_col, X.dv, X.vy, z, 1, s);
+  }
+  {
+    Timed t(h, RZ_K_EXPAND);
+    launch_vc_expand<T>(h->V, *X.vc, z, s);
+    launch_list_copy<T>(h->nDir, h->dlist, r, z, s);
+  }
+  return RZ_OK;
+}
+
 // ---------------------------------------------------------------------------------------
 // operator pieces on the device
 // ---------------------------------------------------------------------------------------
@@ -306,11 +435,23 @@ rz_status relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, co
 
 rz_status do_relax64(rz_problem *h, const double *r, double *z, double scale = 1.0, double w = 0.0,
                      double *acc = nullptr) {
+  if (h->space != RZ_GRAD) {
+    if (rz_status e = relax_vec<double>(h, vec_ptrs64(h), r, z)) return e;
+    if (acc) launch_axpy(w, z, acc, h->ndofs, h->ctx->stream);
+    else if (scale != 1.0) launch_scale_copy(scale, z, z, h->ndofs, h->ctx->stream);
+    return RZ_OK;
+  }
   return relax_steps<double>(h, h->coef64, h->A64, h->lam64, h->f64, h->rt64, h->zb64, r, z, scale, w, acc);
 }
 
 rz_status do_relax32(rz_problem *h, const float *r, float *z, float scale = 1.0f, float w = 0.0f,
                      float *acc = nullptr) {
+  if (h->space != RZ_GRAD) {
+    if (rz_status e = relax_vec<float>(h, vec_ptrs32(h), r, z)) return e;
+    if (acc) launch_axpy_f(w, z, acc, h->ndofs, h->ctx->stream);
+    else if (scale != 1.0f) launch_scale_copy_f(scale, z, z, h->ndofs, h->ctx->stream);
+    return RZ_OK;
+  }
   return relax_steps<float>(h, h->coef32, h->A32, h->lam32, h->f32, h->rt32, h->zb32, r, z, scale, w, acc);
 }
 
@@ -318,7 +459,8 @@ rz_status do_relax32(rz_problem *h, const float *r, float *z, float scale = 1.0f
 // (FP32 relaxation for the mixed and defect-correction protocols):
 // z = scale * M r, or with acc: acc += w * M r (z is then scratch)
 rz_status do_relax_prec(rz_problem *h, const double *r, double *z, double scale = 1.0, double w = 0.0,
-                        double *acc = nullptr) {
+                        double *acc = nullptr);
+rz_status do_relax_prec(rz_problem *h, const double *r, double *z, double scale, double w, double *acc) {
   if (h->opts.precision != RZ_PREC_F64) {
     launch_cast_d2f(r, h->r32, h->ndofs, h->ctx->stream);
     if (rz_status e = do_relax32(h, h->r32, h->z32)) return e;
@@ -347,7 +489,44 @@ rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv, bool f32 = fa
   return RZ_OK;
 }
 
+// coarse correction of the H(curl) / H(div) cycle: z += P A_0^{-1} P^T r1 (FP64
+// coarse vectors; the dense inverse in FP32 for the mixed protocols)
+template <typename T>
+void coarse_correction_vec(rz_problem *h, const double *r1, T *z, bool f32) {
+  hipStream_t s = h->ctx->stream;
+  if (h->ncf == 0) return;
+  {
+    Timed tm(h, RZ_K_TRANSFER);
+    launch_csr<double, double, double>(h->ncf, nullptr, h->pr_ptr, h->pr_col, h->pr_val, r1, h->vcr, 0, s);
+  }
+  {
+    Timed tm(h, RZ_K_COARSE);
+    if (f32 && h->cinv32) launch_gemv<float>(h->ncf, h->cinv32, h->vcr, h->vcx, s);
+    else launch_gemv<double>(h->ncf, h->cinv64, h->vcr, h->vcx, s);
+  }
+  {
+    Timed tm(h, RZ_K_TRANSFER);
+    launch_csr<double, double, T>(h->npf, h->pp_rows, h->pp_ptr, h->pp_col, h->pp_val, h->vcx, z, 1, s);
+  }
+}
+
+rz_status do_residual64(rz_problem *h, const double *b, const double *x, double *out);
+rz_status do_residual32(rz_problem *h, const float *b, const float *x, float *out);
+
+// hybrid V(1,1) for H(curl) / H(div), FP64 vectors
+rz_status do_vcycle_vec(rz_problem *h, const double *r, double *z) {
+  const double w = h->omega;
+  if (rz_status e = do_relax_prec(h, r, z, w, 0.0, nullptr)) return e;  // z = w M r
+  if (rz_status e = do_residual64(h, r, z, h->vr)) return e;            // r1 = r - A z
+  coarse_correction_vec<double>(h, h->vr, z, h->opts.precision != RZ_PREC_F64);
+  if (rz_status e = do_residual64(h, r, z, h->vr)) return e;            // r2 = r - A z
+  if (rz_status e = do_relax_prec(h, h->vr, h->vt, 1.0, w, z)) return e;  // z += w M r2
+  dir_copy(h, r, z, h->ctx->stream);
+  return RZ_OK;
+}
+
 rz_status do_vcycle(rz_problem *h, const double *r, double *z) {
+  if (h->space != RZ_GRAD) return do_vcycle_vec(h, r, z);
   hipStream_t s = h->ctx->stream;
   const int64_t n = h->ndofs;
   const double w = h->omega;
@@ -400,9 +579,24 @@ rz_status do_residual32(rz_problem *h, const float *b, const float *x, float *ou
   return RZ_OK;
 }
 
+// The same cycle on FP32 vectors for H(curl) / H(div) (coarse correction in FP64)
+rz_status do_vcycle32_vec(rz_problem *h, const float *r, float *z) {
+  hipStream_t s = h->ctx->stream;
+  const float w = (float)h->omega;
+  if (rz_status e = do_relax32(h, r, z, w)) return e;       // z = w M r
+  if (rz_status e = do_residual32(h, r, z, h->vr32)) return e;  // r1 = r - A z
+  launch_cast_f2d(h->vr32, h->vr, h->ndofs, s);
+  coarse_correction_vec<float>(h, h->vr, z, true);
+  if (rz_status e = do_residual32(h, r, z, h->vr32)) return e;  // r2 = r - A z
+  if (rz_status e = do_relax32(h, h->vr32, h->t32, 1.0f, w, z)) return e;  // z += w M r2
+  dir_copy_f(h, r, z, s);
+  return RZ_OK;
+}
+
 // The V(1,1) cycle on FP32 vectors (inner solve of the defect-correction
 // protocol): FP32 apply and relaxation, the coarse correction in FP64.
 rz_status do_vcycle32(rz_problem *h, const float *r, float *z) {
+  if (h->space != RZ_GRAD) return do_vcycle32_vec(h, r, z);
   hipStream_t s = h->ctx->stream;
   const int64_t n = h->ndofs;
   const float w = (float)h->omega;
@@ -473,7 +667,7 @@ rz_status defect_solve(rz_problem *h, const double *b, double *x, rz_solve_info 
   HIPCALL(h, hipEventRecord(ev.a, s));
   launch_fill(x, 0.0, n, s);
   v_scale_copy(h, 1.0, b, h->kr);
-  launch_dirichlet_copy(h->L, nullptr, h->kr, s);
+  dir_copy(h, nullptr, h->kr, s);
   double bb;
   {
     const double *xs[1] = {h->kr};
@@ -486,7 +680,7 @@ rz_status defect_solve(rz_problem *h, const double *b, double *x, rz_solve_info 
   for (int outer = 0; outer < 64; ++outer) {
     if (outer > 0) {  // true residual of the current iterate
       do_residual64(h, b, x, h->kr);
-      launch_dirichlet_copy(h->L, nullptr, h->kr, s);
+      dir_copy(h, nullptr, h->kr, s);
       const double *xs[1] = {h->kr};
       if ((e = dots_host(h, 1, xs, xs, &rr))) return e;
     }
@@ -586,8 +780,14 @@ rz_status estimate_lambda(rz_problem *h, double *lam_out) {
   uint64_t st = h->opts.lanczos_seed;
   for (int64_t g = 0; g < n; ++g) {
     double u = (double)(splitmix_next(st) >> 11) * 0x1.0p-53;
-    int X = g % h->Nx, Y = (g / h->Nx) % h->Ny, Z = g / ((int64_t)h->Nx * h->Ny);
-    v0[g] = lat_dirichlet_h(h, X, Y, Z) ? 0.0 : 2.0 * u - 1.0;
+    bool d;
+    if (h->space == RZ_GRAD) {
+      int X = g % h->Nx, Y = (g / h->Nx) % h->Ny, Z = g / ((int64_t)h->Nx * h->Ny);
+      d = lat_dirichlet_h(h, X, Y, Z);
+    } else {
+      d = h->dmask[g] != 0;
+    }
+    v0[g] = d ? 0.0 : 2.0 * u - 1.0;
   }
   HIPCALL(h, hipMemcpyAsync(h->kr, v0.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
   if (rz_status e = do_relax_prec(h, h->kr, h->kz)) return e;
@@ -774,6 +974,11 @@ rz_status setup_coarse(rz_problem *h) {
 }
 
 void release(rz_problem *h) {
+  if (h->pot) {
+    release(h->pot);
+    delete h->pot;
+    h->pot = nullptr;
+  }
   for (void *p : h->allocs) hipFree(p);
   h->allocs.clear();
   if (h->hdots) hipHostFree(h->hdots);
@@ -809,6 +1014,658 @@ rz_status require_device(const rz_problem *h) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------------------
+// pieces of the H(grad) setup shared by problems and the internal Q_p potential problem
+// of the H(curl) relaxation
+// ---------------------------------------------------------------------------------------
+namespace {
+
+// symbolic patch pattern, free DoFs, non-empty patches, lattice description
+void grad_symbolic(rz_problem *h) {
+  const int p = h->p;
+  build_patch_symbolic(p, h->ps);
+  h->erow.resize(h->ps.nnz);
+  for (int r = 0; r < h->ps.nrows; ++r)
+    for (int k = h->ps.rowptr[r]; k < h->ps.rowptr[r + 1]; ++k) h->erow[k] = r;
+  int64_t nd = 0;
+  for (int64_t g = 0; g < h->ndofs; ++g) {
+    int X = g % h->Nx, Y = (g / h->Nx) % h->Ny, Z = g / ((int64_t)h->Nx * h->Ny);
+    nd += lat_dirichlet_h(h, X, Y, Z);
+  }
+  h->nfree = h->ndofs - nd;
+  h->patch_vids.clear();
+  for (int64_t v = 0; v < h->nvert; ++v) {
+    int G[3];
+    for (int k = 0; k < h->ps.nrows; ++k)
+      if (patch_row_present(h, v, k, G)) {
+        h->patch_vids.push_back(v);
+        break;
+      }
+  }
+  h->L = LatDev{p, h->nx, h->ny, h->nz, h->Nx, h->Ny, h->Nz, h->dir};
+}
+
+// status word, weights and 1-D tables on the device, the patch schedule, and the IC
+// factors of every vertex patch (FP64 pivots, FP32 copy)
+rz_status grad_patch_device(rz_problem *h) {
+  rz_ctx *ctx = h->ctx;
+  hipStream_t s = ctx->stream;
+  rz_status e;
+  const int p = h->p, n1 = p + 1;
+  std::vector<double> lamf(n1, 0.0);
+  for (int i = 1; i < p; ++i) lamf[i] = h->t.lam[i - 1];
+  std::vector<float> c32(h->coef.begin(), h->coef.end()), B32(h->t.B.begin(), h->t.B.end()),
+      A32(h->t.A.begin(), h->t.A.end()), l32(lamf.begin(), lamf.end());
+  if ((e = dalloc(h, &h->status, 1))) return e;
+  HIPCALL(h, hipMemsetAsync(h->status, 0, sizeof(int), s));
+  if ((e = upload(h, &h->coef64, h->coef)) || (e = upload(h, &h->B64, h->t.B)) || (e = upload(h, &h->A64, h->t.A)) ||
+      (e = upload(h, &h->lam64, lamf)) || (e = upload(h, &h->coef32, c32)) || (e = upload(h, &h->B32, B32)) ||
+      (e = upload(h, &h->A32, A32)) || (e = upload(h, &h->lam32, l32)))
+    return e;
+  const PatchSymbolic &ps = h->ps;
+  std::vector<int> sym;
+  auto push = [&](const std::vector<int> &v) {
+    size_t o = sym.size();
+    sym.insert(sym.end(), v.begin(), v.end());
+    return o;
+  };
+  std::vector<int> passes;
+  for (int t = 0; t < ps.npass; ++t) {
+    passes.push_back(ps.pass_g[t]);
+    passes.push_back(ps.pass_k[t]);
+    passes.push_back(ps.pass_base[t]);
+  }
+  size_t o_off = push(ps.off), o_rp = push(ps.rowptr), o_col = push(ps.col), o_er = push(h->erow),
+         o_up = push(ps.uptr), o_ur = push(ps.urow), o_upos = push(ps.upos), o_fp = push(ps.flev_ptr),
+         o_fr = push(ps.flev_rows), o_bp = push(ps.blev_ptr), o_br = push(ps.blev_rows), o_p1 = push(ps.pos1),
+         o_p2 = push(ps.pos2), o_pass = push(passes), o_ecol = push(ps.ecol), o_erow = push(ps.erow);
+  int *dsym = nullptr;
+  if ((e = upload(h, &dsym, sym))) return e;
+  h->P = PatchDev{ps.nrows, ps.nnz, (int)ps.flev_ptr.size() - 1, (int)ps.blev_ptr.size() - 1,
+                  dsym + o_off, dsym + o_rp, dsym + o_col, dsym + o_er, dsym + o_up, dsym + o_ur, dsym + o_upos,
+                  dsym + o_fp, dsym + o_fr, dsym + o_bp, dsym + o_br, ps.stride, dsym + o_p1, dsym + o_p2};
+  int kmax = 1;
+  for (int k : ps.pass_k) kmax = std::max(kmax, k);
+  h->PE = PatchEllDev{ps.nrows, ps.npass, ps.ef + ps.eb, ps.stride, kmax, dsym + o_pass, dsym + o_ecol,
+                      dsym + o_erow, dsym + o_off,
+                      patch_regs_table_matches(p, passes.data(), ps.npass, ps.nrows, ps.ef + ps.eb, ps.ell0) ? 1 : 0,
+                      ps.ell0};
+  if (patch_solve_lds_bytes(h->PE, sizeof(double), 1) > 160 * 1024)
+    return fail(ctx, RZ_ERR_ARG, "patch schedule does not fit the LDS");
+  const size_t nf = (size_t)h->nvert * ps.stride, nzb = (size_t)h->nvert * ps.nrows;
+  if ((e = dalloc(h, &h->f64, nf)) || (e = dalloc(h, &h->f32, nf)) || (e = dalloc(h, &h->zb64, nzb)) ||
+      (e = dalloc(h, &h->zb32, nzb)))
+    return e;
+  // the workspace of the vertex patches: keep rows of empty slots well defined
+  launch_fill(h->zb64, 0.0, (int64_t)nzb, s);
+  launch_fill_f(h->zb32, 0.0f, (int64_t)nzb, s);
+  // ELL padding of the factors must read as zero
+  HIPCALL(h, hipMemsetAsync(h->f64, 0, nf * sizeof(double), s));
+  HIPCALL(h, hipMemsetAsync(h->f32, 0, nf * sizeof(float), s));
+  launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, h->f64, h->f32, h->status, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(ctx, RZ_ERR_HIP, "patch factorisation failed");
+  int stv = 0;
+  HIPCALL(h, hipMemcpy(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost));
+  if (stv) {
+    char msg[128];
+    std::snprintf(msg, sizeof msg, "incomplete Cholesky breakdown in vertex patch %d", stv - 1);
+    return fail(ctx, RZ_ERR_BREAKDOWN, msg);
+  }
+  return RZ_OK;
+}
+
+// vectors of the V-cycle and of the Krylov methods (ndofs each), dot-product
+// scratch and the pinned host copy of the scalars
+rz_status alloc_krylov(rz_problem *h) {
+  rz_status e;
+  const int64_t n = h->ndofs;
+  if ((e = dalloc(h, &h->r32, n)) || (e = dalloc(h, &h->z32, n)) || (e = dalloc(h, &h->vt, n)) ||
+      (e = dalloc(h, &h->vaz, n)) || (e = dalloc(h, &h->vr, n)) || (e = dalloc(h, &h->kr, n)) ||
+      (e = dalloc(h, &h->kz, n)) || (e = dalloc(h, &h->kp, n)) || (e = dalloc(h, &h->kAp, n)) ||
+      (e = dalloc(h, &h->kro, n)) || (e = dalloc(h, &h->partials, dots_partials_size())) ||
+      (e = dalloc(h, &h->dots, 8)))
+    return e;
+  if (hipHostMalloc((void **)&h->hdots, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return fail(h->ctx, RZ_ERR_OOM, "pinned host buffer");
+  if (h->opts.precision == RZ_PREC_DEFECT &&
+      ((e = dalloc(h, &h->kp32, n)) || (e = dalloc(h, &h->kAp32, n)) || (e = dalloc(h, &h->ko32, n)) ||
+       (e = dalloc(h, &h->ke32, n)) || (e = dalloc(h, &h->t32, n)) || (e = dalloc(h, &h->az32, n)) ||
+       (e = dalloc(h, &h->vr32, n))))
+    return e;
+  return RZ_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// H(curl) / H(div): setup of the statically condensed Pavarino-Hiptmair relaxation
+// (Sec. 4.3-4.5), the p = 1 coarse problem and the transfers (Sec. 4.3, 5)
+// ---------------------------------------------------------------------------------------
+namespace {
+
+// lattice of NCE_p (space 1) / NCF_p (space 2) on an n[0] x n[1] x n[2] mesh
+void vec_lattice(int space, int p, const int n[3], int ext[3][3], int64_t off[4]) {
+  int64_t o = 0;
+  for (int m = 0; m < 3; ++m) {
+    off[m] = o;
+    int64_t sz = 1;
+    for (int a = 0; a < 3; ++a) {
+      ext[m][a] = n[a] * p + (vec_is_P(space, m, a) ? 1 : 0);
+      sz *= ext[m][a];
+    }
+    o += sz;
+  }
+  off[3] = o;
+}
+
+void vec_coords(const int64_t off[4], const int ext[3][3], int64_t g, int &m, int X[3]) {
+  m = 0;
+  while (m < 2 && g >= off[m + 1]) ++m;
+  const int64_t r = g - off[m];
+  X[0] = (int)(r % ext[m][0]);
+  X[1] = (int)((r / ext[m][0]) % ext[m][1]);
+  X[2] = (int)(r / ((int64_t)ext[m][0] * ext[m][1]));
+}
+
+int64_t vec_index(const int64_t off[4], const int ext[3][3], int m, const int X[3]) {
+  return off[m] + X[0] + (int64_t)ext[m][0] * (X[1] + (int64_t)ext[m][1] * X[2]);
+}
+
+// trace condition on a Dirichlet face: a continuous coordinate on that face's plane
+bool vec_dirichlet(int space, unsigned dir, const int ext[3][3], int m, const int X[3]) {
+  for (int a = 0; a < 3; ++a) {
+    if (!vec_is_P(space, m, a)) continue;
+    if ((dir & (1u << (2 * a))) && X[a] == 0) return true;
+    if ((dir & (1u << (2 * a + 1))) && X[a] == ext[m][a] - 1) return true;
+  }
+  return false;
+}
+
+bool vec_interior(int space, int p, int m, const int X[3]) {
+  for (int a = 0; a < 3; ++a)
+    if (vec_is_P(space, m, a) && X[a] % p == 0) return false;
+  return true;
+}
+
+// keys: cells with bitwise equal weights share one
+void cell_keys(const std::vector<double> &w6, int64_t ncells, std::vector<int> &key,
+               std::vector<std::array<double, 6>> &keyw) {
+  std::map<std::array<double, 6>, int> km;
+  key.resize(ncells);
+  keyw.clear();
+  for (int64_t c = 0; c < ncells; ++c) {
+    std::array<double, 6> w;
+    for (int k = 0; k < 6; ++k) w[k] = w6[6 * c + k];
+    auto it = km.find(w);
+    if (it == km.end()) {
+      it = km.emplace(w, (int)keyw.size()).first;
+      keyw.push_back(w);
+    }
+    key[c] = it->second;
+  }
+}
+
+bool condense_keys(const VecLocal &L, const SpRows basis[6], const std::vector<std::array<double, 6>> &keyw,
+                   bool want_S, std::vector<CellCondensed> &conds, std::string &err) {
+  conds.assign(keyw.size(), CellCondensed());
+  for (size_t k = 0; k < keyw.size(); ++k)
+    if (!vec_condense(L, basis, keyw[k].data(), want_S, conds[k], err)) return false;
+  for (size_t k = 1; k < conds.size(); ++k)
+    if (conds[k].blocks.size() != conds[0].blocks.size() || conds[k].gi_col != conds[0].gi_col ||
+        conds[k].ig_col != conds[0].ig_col) {
+      err = "cell operators of one problem differ in structure";
+      return false;
+    }
+  return true;
+}
+
+template <typename T>
+std::vector<T> as_type(const std::vector<double> &v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+// CSR transpose: (rows r_ids with ptr/col/val) -> rows = distinct columns ascending
+void csr_transpose(const std::vector<int> &rid, const std::vector<int> &ptr, const std::vector<int> &col,
+                   const std::vector<double> &val, int64_t ncols, std::vector<int> &trid, std::vector<int> &tptr,
+                   std::vector<int> &tcol, std::vector<double> &tval) {
+  std::vector<int> cnt(ncols, 0);
+  for (int c : col) cnt[c] += 1;
+  std::vector<int64_t> start(ncols, -1);
+  trid.clear();
+  tptr.assign(1, 0);
+  for (int64_t c = 0; c < ncols; ++c)
+    if (cnt[c]) {
+      start[c] = tptr.back();
+      trid.push_back((int)c);
+      tptr.push_back(tptr.back() + cnt[c]);
+    }
+  tcol.assign(tptr.back(), 0);
+  tval.assign(tptr.back(), 0.0);
+  std::vector<int> fill(ncols, 0);
+  for (size_t t = 0; t < rid.size(); ++t)
+    for (int k = ptr[t]; k < ptr[t + 1]; ++k) {
+      const int c = col[k];
+      const int64_t o = start[c] + fill[c]++;
+      tcol[o] = rid[t];
+      tval[o] = val[k];
+    }
+}
+
+rz_status upload_cells(rz_problem *h, const VecLocal &L, const std::vector<CellCondensed> &conds,
+                       const std::vector<int> &key) {
+  rz_status e;
+  const CellCondensed &c0 = conds[0];
+  std::vector<int> blk;
+  for (auto &b : c0.blocks) blk.insert(blk.end(), b.begin(), b.end());
+  std::vector<double> linv, giv, igv;
+  for (const CellCondensed &c : conds) {
+    linv.insert(linv.end(), c.linv.begin(), c.linv.end());
+    giv.insert(giv.end(), c.gi_val.begin(), c.gi_val.end());
+    igv.insert(igv.end(), c.ig_val.begin(), c.ig_val.end());
+  }
+  int *il = nullptr, *gl = nullptr, *lc = nullptr, *lx = nullptr, *db = nullptr, *dk = nullptr, *gp = nullptr,
+      *gc = nullptr, *ip = nullptr, *ic = nullptr;
+  double *l64 = nullptr, *g64 = nullptr, *i64 = nullptr;
+  float *l32 = nullptr, *g32 = nullptr, *i32 = nullptr;
+  if ((e = upload(h, &il, c0.I)) || (e = upload(h, &gl, c0.G)) || (e = upload(h, &lc, L.comp)) ||
+      (e = upload(h, &lx, L.crd)) || (e = upload(h, &db, blk)) || (e = upload(h, &dk, key)) ||
+      (e = upload(h, &gp, c0.gi_ptr)) || (e = upload(h, &gc, c0.gi_col)) || (e = upload(h, &ip, c0.ig_ptr)) ||
+      (e = upload(h, &ic, c0.ig_col)) || (e = upload(h, &l64, linv)) || (e = upload(h, &g64, giv)) ||
+      (e = upload(h, &i64, igv)) || (e = upload(h, &l32, as_type<float>(linv))) ||
+      (e = upload(h, &g32, as_type<float>(giv))) || (e = upload(h, &i32, as_type<float>(igv))))
+    return e;
+  const int nI = (int)c0.I.size(), nG = (int)c0.G.size(), nb = (int)c0.blocks.size();
+  const int ngi = (int)c0.gi_col.size(), nig = (int)c0.ig_col.size();
+  h->vc64 = VecCellDev<double>{nI, nG, nb, ngi, nig, il, gl, lc, lx, db, dk, l64, gp, gc, g64, ip, ic, i64};
+  h->vc32 = VecCellDev<float>{nI, nG, nb, ngi, nig, il, gl, lc, lx, db, dk, l32, gp, gc, g32, ip, ic, i32};
+  return RZ_OK;
+}
+
+rz_status upload_edges(rz_problem *h, const EdgePatches &ep, EdgeDev &ed, double **f64, float **f32, double **zb64,
+                       float **zb32) {
+  rz_status e;
+  int *idx = nullptr, *typ = nullptr;
+  if ((e = upload(h, &idx, ep.idx)) || (e = upload(h, &typ, ep.type)) || (e = upload(h, f64, ep.fac)) ||
+      (e = upload(h, f32, as_type<float>(ep.fac))))
+    return e;
+  const size_t nz = ep.edge_id.size() * (size_t)ep.lay.nslot;
+  if ((e = dalloc(h, zb64, nz)) || (e = dalloc(h, zb32, nz))) return e;
+  ed = EdgeDev{};
+  ed.p = ep.lay.p;
+  ed.nslot = ep.lay.nslot;
+  ed.fac_stride = ep.lay.fac_stride;
+  ed.npatch = (int)ep.edge_id.size();
+  for (int i = 0; i < ep.lay.p; ++i) {
+    ed.blk_n[i] = ep.lay.blk_n[i];
+    ed.blk_slot[i] = ep.lay.blk_slot[i];
+    ed.blk_fac[i] = ep.lay.blk_fac[i];
+  }
+  ed.idx = idx;
+  ed.type = typ;
+  return RZ_OK;
+}
+
+// the Q_p potential problem of the H(curl) relaxation: B = (grad phi, beta grad psi)
+// with the problem's mesh and Dirichlet faces; its vertex-star patches factored by
+// incomplete Cholesky on the static-condensation pattern (as an H(grad) problem)
+rz_status build_grad_potential(rz_problem *h, const std::vector<double> &coefq) {
+  rz_problem *q = new rz_problem();
+  h->pot = q;
+  q->ctx = h->ctx;
+  q->opts = h->opts;
+  q->opts.space = RZ_GRAD;
+  q->space = RZ_GRAD;
+  q->p = h->p;
+  q->nx = h->nx;
+  q->ny = h->ny;
+  q->nz = h->nz;
+  q->dir = h->dir;
+  q->Nx = h->nx * h->p + 1;
+  q->Ny = h->ny * h->p + 1;
+  q->Nz = h->nz * h->p + 1;
+  q->ndofs = (int64_t)q->Nx * q->Ny * q->Nz;
+  q->ncells = h->ncells;
+  q->nvert = h->nvert;
+  q->t = h->t;
+  q->t1 = h->t1;
+  q->coef = coefq;
+  grad_symbolic(q);
+  return grad_patch_device(q);
+}
+
+rz_status setup_vec_relax(rz_problem *h, const std::vector<double> &al, const std::vector<double> &be,
+                          const std::vector<std::array<double, 3>> &hs) {
+  rz_ctx *ctx = h->ctx;
+  hipStream_t s = ctx->stream;
+  rz_status e;
+  std::string err;
+  const int p = h->p, space = h->space;
+  const int n[3] = {h->nx, h->ny, h->nz};
+  const int64_t nc = h->ncells;
+  int ext[3][3];
+  int64_t off[4];
+  vec_lattice(space, p, n, ext, off);
+  // ---- cell algebra of the operator --------------------------------------------------
+  VecLocal Lp;
+  vec_local_layout(space, p, Lp);
+  SpRows basis[6];
+  vec_basis_matrices(h->t, Lp, basis);
+  std::vector<int> key;
+  std::vector<std::array<double, 6>> keyw;
+  cell_keys(h->coef, nc, key, keyw);
+  std::vector<CellCondensed> conds;
+  if (!condense_keys(Lp, basis, keyw, true, conds, err)) return fail(ctx, RZ_ERR_BREAKDOWN, err);
+  if ((e = upload_cells(h, Lp, conds, key))) return e;
+  const int nG = (int)conds[0].G.size();
+  // ---- free interface DoFs and the condensation sums -------------------------------
+  std::vector<int> cnt(h->ndofs, 0);
+  for (int64_t c = 0; c < nc; ++c) {
+    const int cc[3] = {(int)(c % n[0]), (int)((c / n[0]) % n[1]), (int)(c / ((int64_t)n[0] * n[1]))};
+    for (int g = 0; g < nG; ++g) {
+      const int l = conds[0].G[g], m = Lp.comp[l];
+      int X[3];
+      for (int a = 0; a < 3; ++a) X[a] = cc[a] * p + Lp.crd[3 * l + a];
+      if (!vec_dirichlet(space, h->dir, ext, m, X)) cnt[vec_index(off, ext, m, X)] += 1;
+    }
+  }
+  std::vector<int> gam, cptr(1, 0), cpos;
+  std::vector<int64_t> start(h->ndofs, -1);
+  for (int64_t g = 0; g < h->ndofs; ++g)
+    if (cnt[g]) {
+      start[g] = cptr.back();
+      gam.push_back((int)g);
+      cptr.push_back(cptr.back() + cnt[g]);
+    }
+  cpos.assign(cptr.back(), 0);
+  std::fill(cnt.begin(), cnt.end(), 0);
+  for (int64_t c = 0; c < nc; ++c) {
+    const int cc[3] = {(int)(c % n[0]), (int)((c / n[0]) % n[1]), (int)(c / ((int64_t)n[0] * n[1]))};
+    for (int g = 0; g < nG; ++g) {
+      const int l = conds[0].G[g], m = Lp.comp[l];
+      int X[3];
+      for (int a = 0; a < 3; ++a) X[a] = cc[a] * p + Lp.crd[3 * l + a];
+      if (vec_dirichlet(space, h->dir, ext, m, X)) continue;
+      const int64_t gi = vec_index(off, ext, m, X);
+      cpos[start[gi] + cnt[gi]++] = (int)(c * nG + g);
+    }
+  }
+  h->nGam = (int)gam.size();
+  if ((e = upload(h, &h->gam, gam)) || (e = upload(h, &h->cg_ptr, cptr)) || (e = upload(h, &h->cg_pos, cpos)) ||
+      (e = dalloc(h, &h->veb64, (size_t)nc * nG)) || (e = dalloc(h, &h->veb32, (size_t)nc * nG)) ||
+      (e = dalloc(h, &h->vrt64, h->ndofs)) || (e = dalloc(h, &h->vrt32, h->ndofs)))
+    return e;
+  // ---- local solves: edge stars (curl) or face stars (div, diagonal) ----------------
+  if (space == RZ_CURL) {
+    EdgePatches ep;
+    if (!edge_patches_build(p, n, h->dir, ext, off, Lp, key, conds, ep, err)) return fail(ctx, RZ_ERR_BREAKDOWN, err);
+    if (ep.rows != gam) return fail(ctx, RZ_ERR_ARG, "edge patches do not cover the interface DoFs");
+    if ((e = upload_edges(h, ep, h->ed, &h->efac64, &h->efac32, &h->ezb64, &h->ezb32)) ||
+        (e = upload(h, &h->eg_ptr, ep.ptr)) || (e = upload(h, &h->eg_pos, ep.pos)))
+      return e;
+    h->edge_ids = ep.edge_id;
+    h->edge_idx = ep.idx;
+    h->edge_nslot = ep.lay.nslot;
+  } else {
+    std::vector<double> dsum(gam.size(), 0.0);
+    for (size_t t = 0; t < gam.size(); ++t)
+      for (int k = cptr[t]; k < cptr[t + 1]; ++k) {
+        const int c = cpos[k] / nG, g = cpos[k] % nG;
+        dsum[t] += conds[key[c]].S[(size_t)g * nG + g];
+      }
+    for (double &d : dsum) {
+      if (!(d > 0)) return fail(ctx, RZ_ERR_BREAKDOWN, "face-star pivot is not positive");
+      d = 1.0 / d;
+    }
+    if ((e = upload(h, &h->dinv64, dsum)) || (e = upload(h, &h->dinv32, as_type<float>(dsum)))) return e;
+  }
+  // ---- the potential problem and D_GG -------------------------------------------------
+  const Tables1D &t = h->t;
+  const int n1 = p + 1;
+  std::vector<int> drow, dptr(1, 0), dcol;
+  std::vector<double> dval;
+  int64_t pndofs = 0;
+  if (space == RZ_CURL) {
+    std::vector<double> coefq(6 * nc, 0.0);
+    for (int64_t c = 0; c < nc; ++c) {
+      const double V = hs[c][0] * hs[c][1] * hs[c][2];
+      for (int d = 0; d < 3; ++d) coefq[6 * c + d] = be[c] * V / (2.0 * hs[c][d] * hs[c][d]);
+    }
+    if ((e = build_grad_potential(h, coefq))) return e;
+    const rz_problem *q = h->pot;
+    pndofs = q->ndofs;
+    auto q_free_iface = [&](const int Y[3]) {
+      if (Y[0] % p && Y[1] % p && Y[2] % p) return false;
+      return !lat_dirichlet_h(q, Y[0], Y[1], Y[2]);
+    };
+    for (int g : gam) {  // grad: NCE component m at X <- Q_p points along m
+      int m, X[3];
+      vec_coords(off, ext, g, m, X);
+      const int c = X[m] / p, j = X[m] % p;
+      for (int a = 0; a <= p; ++a) {
+        const double v = t.D[j * n1 + a];
+        if (v == 0.0) continue;
+        int Y[3] = {X[0], X[1], X[2]};
+        Y[m] = c * p + a;
+        if (!q_free_iface(Y)) continue;
+        dcol.push_back((int)(Y[0] + (int64_t)q->Nx * (Y[1] + (int64_t)q->Ny * Y[2])));
+        dval.push_back(v);
+      }
+      dptr.push_back((int)dcol.size());
+    }
+  } else {
+    // NCE_p potential: B = (curl phi, beta curl psi) + eps (phi, beta psi)
+    const double eps = h->opts.hdiv_eps > 0 ? h->opts.hdiv_eps : 1e-3;
+    std::vector<double> coefe(6 * nc, 0.0);
+    for (int64_t c = 0; c < nc; ++c) {
+      const double V = hs[c][0] * hs[c][1] * hs[c][2];
+      for (int d = 0; d < 3; ++d) {
+        coefe[6 * c + d] = be[c] * 2.0 * hs[c][d] * hs[c][d] / V;
+        coefe[6 * c + 3 + d] = eps * be[c] * V / (2.0 * hs[c][d] * hs[c][d]);
+      }
+    }
+    int exte[3][3];
+    int64_t offe[4];
+    vec_lattice(RZ_CURL, p, n, exte, offe);
+    pndofs = offe[3];
+    VecLocal Le;
+    vec_local_layout(RZ_CURL, p, Le);
+    SpRows basise[6];
+    vec_basis_matrices(t, Le, basise);
+    std::vector<int> keye;
+    std::vector<std::array<double, 6>> keywe;
+    cell_keys(coefe, nc, keye, keywe);
+    std::vector<CellCondensed> condse;
+    if (!condense_keys(Le, basise, keywe, true, condse, err)) return fail(ctx, RZ_ERR_BREAKDOWN, err);
+    EdgePatches ep;
+    if (!edge_patches_build(p, n, h->dir, exte, offe, Le, keye, condse, ep, err))
+      return fail(ctx, RZ_ERR_BREAKDOWN, err);
+    if ((e = upload_edges(h, ep, h->ped, &h->pfac64, &h->pfac32, &h->pzb64, &h->pzb32)) ||
+        (e = upload(h, &h->pg_rows, ep.rows)) || (e = upload(h, &h->pg_ptr, ep.ptr)) ||
+        (e = upload(h, &h->pg_pos, ep.pos)))
+      return e;
+    h->npg = (int)ep.rows.size();
+    h->edge_ids = ep.edge_id;
+    h->edge_idx = ep.idx;
+    h->edge_nslot = ep.lay.nslot;
+    auto e_free_iface = [&](int c, const int Y[3]) {
+      return !vec_interior(RZ_CURL, p, c, Y) && !vec_dirichlet(RZ_CURL, h->dir, exte, c, Y);
+    };
+    for (int g : gam) {  // curl: NCF component k at X <- NCE d_{a1} u_{a2} - d_{a2} u_{a1}
+      int k, X[3];
+      vec_coords(off, ext, g, k, X);
+      const int a1 = (k + 1) % 3, a2 = (k + 2) % 3;
+      const int terms[2][3] = {{1, a2, a1}, {-1, a1, a2}};  // sign, component, derivative axis
+      std::vector<std::pair<int, double>> row;
+      for (auto &tm : terms) {
+        const int c = tm[1], d = tm[2];
+        const int cd = X[d] / p, j = X[d] % p;
+        for (int a = 0; a <= p; ++a) {
+          const double v = tm[0] * t.D[j * n1 + a];
+          if (v == 0.0) continue;
+          int Y[3] = {X[0], X[1], X[2]};
+          Y[d] = cd * p + a;
+          if (!e_free_iface(c, Y)) continue;
+          row.push_back({(int)vec_index(offe, exte, c, Y), v});
+        }
+      }
+      std::sort(row.begin(), row.end());
+      for (auto &rv : row) {
+        dcol.push_back(rv.first);
+        dval.push_back(rv.second);
+      }
+      dptr.push_back((int)dcol.size());
+    }
+  }
+  drow = gam;
+  std::vector<int> trid, tptr, tcol;
+  std::vector<double> tval;
+  csr_transpose(drow, dptr, dcol, dval, pndofs, trid, tptr, tcol, tval);
+  h->pndofs = pndofs;
+  h->ndt = (int)trid.size();
+  if ((e = upload(h, &h->d_ptr, dptr)) || (e = upload(h, &h->d_col, dcol)) || (e = upload(h, &h->d_val64, dval)) ||
+      (e = upload(h, &h->d_val32, as_type<float>(dval))) || (e = upload(h, &h->dt_rows, trid)) ||
+      (e = upload(h, &h->dt_ptr, tptr)) || (e = upload(h, &h->dt_col, tcol)) ||
+      (e = upload(h, &h->dt_val64, tval)) || (e = upload(h, &h->dt_val32, as_type<float>(tval))) ||
+      (e = dalloc(h, &h->vq64, pndofs)) || (e = dalloc(h, &h->vq32, pndofs)) || (e = dalloc(h, &h->vy64, pndofs)) ||
+      (e = dalloc(h, &h->vy32, pndofs)))
+    return e;
+  // entries of the potential vectors outside the rows written stay zero
+  launch_fill(h->vq64, 0.0, pndofs, s);
+  launch_fill_f(h->vq32, 0.0f, pndofs, s);
+  launch_fill(h->vy64, 0.0, pndofs, s);
+  launch_fill_f(h->vy32, 0.0f, pndofs, s);
+  // ---- Dirichlet rows --------------------------------------------------------------------
+  std::vector<int> dl;
+  h->dmask.assign(h->ndofs, 0);
+  for (int64_t g = 0; g < h->ndofs; ++g) {
+    int m, X[3];
+    vec_coords(off, ext, g, m, X);
+    if (vec_dirichlet(space, h->dir, ext, m, X)) {
+      dl.push_back((int)g);
+      h->dmask[g] = 1;
+    }
+  }
+  h->nDir = (int)dl.size();
+  if ((e = upload(h, &h->dlist, dl))) return e;
+  // ---- the p = 1 coarse problem: dense inverse on its free DoFs ---------------------
+  int ext1[3][3];
+  int64_t off1[4];
+  vec_lattice(space, 1, n, ext1, off1);
+  std::vector<int> cmap(off1[3], -1);
+  int ncf = 0;
+  for (int64_t g = 0; g < off1[3]; ++g) {
+    int m, X[3];
+    vec_coords(off1, ext1, g, m, X);
+    if (!vec_dirichlet(space, h->dir, ext1, m, X)) cmap[g] = ncf++;
+  }
+  h->ncf = ncf;
+  if (ncf > 0) {
+    VecLocal L1;
+    vec_local_layout(space, 1, L1);
+    SpRows basis1[6];
+    vec_basis_matrices(h->t1, L1, basis1);
+    std::vector<double> A0((size_t)ncf * ncf, 0.0);
+    std::vector<int> lg(L1.nloc);
+    for (int64_t c = 0; c < nc; ++c) {
+      const int cc[3] = {(int)(c % n[0]), (int)((c / n[0]) % n[1]), (int)(c / ((int64_t)n[0] * n[1]))};
+      for (int l = 0; l < L1.nloc; ++l) {
+        int X[3];
+        for (int a = 0; a < 3; ++a) X[a] = cc[a] + L1.crd[3 * l + a];
+        lg[l] = cmap[vec_index(off1, ext1, L1.comp[l], X)];
+      }
+      for (int k = 0; k < 6; ++k) {
+        const double w = h->coef[6 * c + k];
+        for (int r = 0; r < L1.nloc; ++r) {
+          if (lg[r] < 0) continue;
+          for (auto &ev : basis1[k][r])
+            if (lg[ev.first] >= 0) A0[(size_t)lg[r] * ncf + lg[ev.first]] += w * ev.second;
+        }
+      }
+    }
+    if ((e = upload(h, &h->cinv64, A0))) return e;
+    std::vector<double>().swap(A0);
+    double *tmp = nullptr;
+    if (hipMalloc(&tmp, sizeof(double) * (size_t)ncf * ncf) != hipSuccess)
+      return fail(ctx, RZ_ERR_OOM, "coarse inverse workspace");
+    launch_sweep_inverse(ncf, h->cinv64, tmp, h->status, s);
+    const hipError_t se = hipStreamSynchronize(s);
+    hipFree(tmp);
+    if (se != hipSuccess) return fail(ctx, RZ_ERR_HIP, "coarse inverse failed");
+    int stv = 0;
+    HIPCALL(h, hipMemcpy(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost));
+    if (stv) return fail(ctx, RZ_ERR_SINGULAR, "coarse factorisation: non-positive pivot");
+    if (h->opts.precision != RZ_PREC_F64) {
+      if ((e = dalloc(h, &h->cinv32, (size_t)ncf * ncf))) return e;
+      launch_cast_d2f(h->cinv64, h->cinv32, (int64_t)ncf * ncf, s);
+    }
+    // prolongation (the embedding of the p = 1 space, per axis: hats on continuous
+    // axes, the constant r_0 on broken ones) and restriction = its transpose
+    std::vector<int> prow, pptr(1, 0), pcol;
+    std::vector<double> pval;
+    for (int64_t g = 0; g < h->ndofs; ++g) {
+      if (h->dmask[g]) continue;
+      int m, X[3];
+      vec_coords(off, ext, g, m, X);
+      int cnum[3], cix[3][2];
+      double cw[3][2];
+      bool empty = false;
+      for (int a = 0; a < 3; ++a) {
+        const int c = X[a] / p, i = X[a] % p;
+        if (vec_is_P(space, m, a)) {
+          if (i == 0) {
+            cnum[a] = 1;
+            cix[a][0] = c;
+            cw[a][0] = 1.0;
+          } else {
+            cnum[a] = 2;
+            cix[a][0] = c;
+            cw[a][0] = t.E[2 * i];
+            cix[a][1] = c + 1;
+            cw[a][1] = t.E[2 * i + 1];
+          }
+        } else {
+          cnum[a] = 1;
+          cix[a][0] = c;
+          cw[a][0] = i == 0 ? 1.0 : 0.0;
+          empty = empty || i != 0;
+        }
+      }
+      if (empty) continue;
+      std::vector<std::pair<int, double>> row;
+      for (int k = 0; k < cnum[2]; ++k)
+        for (int j = 0; j < cnum[1]; ++j)
+          for (int i = 0; i < cnum[0]; ++i) {
+            const double w = cw[0][i] * cw[1][j] * cw[2][k];
+            if (w == 0.0) continue;
+            const int Y[3] = {cix[0][i], cix[1][j], cix[2][k]};
+            const int ci = cmap[vec_index(off1, ext1, m, Y)];
+            if (ci >= 0) row.push_back({ci, w});
+          }
+      if (row.empty()) continue;
+      std::sort(row.begin(), row.end());
+      prow.push_back((int)g);
+      for (auto &rv : row) {
+        pcol.push_back(rv.first);
+        pval.push_back(rv.second);
+      }
+      pptr.push_back((int)pcol.size());
+    }
+    std::vector<int> rrid, rptr, rcol;
+    std::vector<double> rval;
+    csr_transpose(prow, pptr, pcol, pval, ncf, rrid, rptr, rcol, rval);
+    if ((int)rrid.size() != ncf) return fail(ctx, RZ_ERR_ARG, "a coarse DoF has no fine counterpart");
+    h->npf = (int)prow.size();
+    if ((e = upload(h, &h->pp_rows, prow)) || (e = upload(h, &h->pp_ptr, pptr)) || (e = upload(h, &h->pp_col, pcol)) ||
+        (e = upload(h, &h->pp_val, pval)) || (e = upload(h, &h->pr_ptr, rptr)) || (e = upload(h, &h->pr_col, rcol)) ||
+        (e = upload(h, &h->pr_val, rval)) || (e = dalloc(h, &h->vcr, ncf)) || (e = dalloc(h, &h->vcx, ncf)))
+      return e;
+  }
+  HIPCALL(h, hipStreamSynchronize(s));
+  return RZ_OK;
+}
+
+}  // namespace
+
 // =========================================================================================
 // public API
 // =========================================================================================
@@ -828,6 +1685,8 @@ rz_status setup_vector(rz_problem *h, const rz_coef *cf, rz_problem **out) {
     return fail(ctx, RZ_ERR_ARG, "H(curl)/H(div) need axis-aligned cells and cellwise-constant coefficients");
   }
   const int nvx = h->nx + 1, nvy = h->ny + 1;
+  std::vector<double> alc(h->ncells), bec(h->ncells);
+  std::vector<std::array<double, 3>> hsc(h->ncells);
   for (int64_t c = 0; c < h->ncells; ++c) {
     int cx = c % h->nx, cy = (c / h->nx) % h->ny, cz = c / ((int64_t)h->nx * h->ny);
     const double hs[3] = {h->vert[3 * (cx + 1)] - h->vert[3 * cx],
@@ -835,6 +1694,9 @@ rz_status setup_vector(rz_problem *h, const rz_coef *cf, rz_problem **out) {
                           h->vert[3 * ((int64_t)(cz + 1) * nvx * nvy) + 2] - h->vert[3 * ((int64_t)cz * nvx * nvy) + 2]};
     const double al = cf->kind == RZ_COEF_CONST ? cf->alpha[0] : cf->alpha[c];
     const double be = cf->kind == RZ_COEF_CONST ? cf->beta[0] : cf->beta[c];
+    alc[c] = al;
+    bec[c] = be;
+    hsc[c] = {hs[0], hs[1], hs[2]};
     const double V = hs[0] * hs[1] * hs[2];
     for (int d = 0; d < 3; ++d) {
       if (h->space == RZ_CURL) {
@@ -898,8 +1760,18 @@ rz_status setup_vector(rz_problem *h, const rz_coef *cf, rz_problem **out) {
   const size_t neb = (size_t)h->ncells * Vd.cell_dofs;
   if ((e = upload(h, &h->coef64, h->coef)) || (e = upload(h, &h->coef32, c32)) || (e = upload(h, &h->B64, h->t.B)) ||
       (e = upload(h, &h->B32, B32)) || (e = upload(h, &h->D64, h->t.D)) || (e = upload(h, &h->D32, D32)) ||
-      (e = dalloc(h, &h->eb64, neb)) || (e = dalloc(h, &h->eb32, neb)))
+      (e = dalloc(h, &h->eb64, neb)) || (e = dalloc(h, &h->eb32, neb)) || (e = dalloc(h, &h->status, 1)))
     return bail(e);
+  if (hipMemsetAsync(h->status, 0, sizeof(int), s) != hipSuccess) return bail(fail(ctx, RZ_ERR_HIP, "memset"));
+  // the relaxation, coarse problem and transfers of the solver
+  if ((e = setup_vec_relax(h, alc, bec, hsc)) || (e = alloc_krylov(h))) return bail(e);
+  if (h->opts.omega > 0) {
+    h->omega = h->opts.omega;
+  } else {
+    double lam = 0;
+    if ((e = estimate_lambda(h, &lam))) return bail(e);
+    h->omega = 2.0 / (1.2 * lam);
+  }
   if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(ctx, RZ_ERR_HIP, "setup failed"));
   *out = h;
   return RZ_OK;
@@ -907,7 +1779,7 @@ rz_status setup_vector(rz_problem *h, const rz_coef *cf, rz_problem **out) {
 
 rz_status require_grad(const rz_problem *h) {
   if (h->space != RZ_GRAD)
-    return fail(h->ctx, RZ_ERR_ARG, "this call is available for H(grad) only (H(curl)/H(div): apply)");
+    return fail(h->ctx, RZ_ERR_ARG, "this call is available for H(grad) only");
   return RZ_OK;
 }
 
@@ -956,7 +1828,7 @@ rz_status pcg_norm(PcgRun &R, const double *v) {
 rz_status pcg_final(PcgRun &R) {
   rz_problem *h = R.h;
   do_residual64(h, R.b, R.x, h->vr);
-  launch_dirichlet_copy(h->L, nullptr, h->vr, h->ctx->stream);
+  dir_copy(h, nullptr, h->vr, h->ctx->stream);
   R.phase = PcgRun::GOT_FINAL;
   return pcg_norm(R, h->vr);
 }
@@ -1015,7 +1887,7 @@ rz_status pcg_step(PcgRun &R) {
       HIPCALL(h, hipEventRecord(R.ev0, s));
       launch_fill(R.x, 0.0, n, s);  // x = 0, r = b with Dirichlet rows zero
       v_scale_copy(h, 1.0, R.b, h->kr);
-      launch_dirichlet_copy(h->L, nullptr, h->kr, s);
+      dir_copy(h, nullptr, h->kr, s);
       R.phase = PcgRun::GOT_BB;
       return pcg_norm(R, h->kr);
     }
@@ -1037,7 +1909,7 @@ rz_status pcg_step(PcgRun &R) {
       }
       if (std::sqrt(rr) <= R.tol) {  // recurrence converged: check the true residual
         do_residual64(h, R.b, R.x, h->vr);
-        launch_dirichlet_copy(h->L, nullptr, h->vr, s);
+        dir_copy(h, nullptr, h->vr, s);
         R.phase = PcgRun::GOT_TR;
         return pcg_norm(R, h->vr);
       }
@@ -1257,26 +2129,7 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
     }
   }
   if (opts->space != RZ_GRAD) return setup_vector(h, cf, out);
-  build_patch_symbolic(p, h->ps);
-  h->erow.resize(h->ps.nnz);
-  for (int r = 0; r < h->ps.nrows; ++r)
-    for (int k = h->ps.rowptr[r]; k < h->ps.rowptr[r + 1]; ++k) h->erow[k] = r;
-  // free DoFs and non-empty patches
-  int64_t nd = 0;
-  for (int64_t g = 0; g < h->ndofs; ++g) {
-    int X = g % h->Nx, Y = (g / h->Nx) % h->Ny, Z = g / ((int64_t)h->Nx * h->Ny);
-    nd += lat_dirichlet_h(h, X, Y, Z);
-  }
-  h->nfree = h->ndofs - nd;
-  for (int64_t v = 0; v < h->nvert; ++v) {
-    int G[3];
-    for (int k = 0; k < h->ps.nrows; ++k)
-      if (patch_row_present(h, v, k, G)) {
-        h->patch_vids.push_back(v);
-        break;
-      }
-  }
-  h->L = LatDev{p, h->nx, h->ny, h->nz, h->Nx, h->Ny, h->Nz, h->dir};
+  grad_symbolic(h);
   if (ctx->device < 0) {
     *out = h;
     return RZ_OK;
@@ -1290,17 +2143,9 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
     delete h;
     return st;
   };
+  if ((e = grad_patch_device(h))) return bail(e);
   const int n1 = p + 1;
-  std::vector<double> lamf(n1, 0.0);
-  for (int i = 1; i < p; ++i) lamf[i] = h->t.lam[i - 1];
-  std::vector<float> c32(h->coef.begin(), h->coef.end()), B32(h->t.B.begin(), h->t.B.end()),
-      A32(h->t.A.begin(), h->t.A.end()), l32(lamf.begin(), lamf.end());
-  if ((e = dalloc(h, &h->status, 1))) return bail(e);
-  if (hipMemsetAsync(h->status, 0, sizeof(int), s) != hipSuccess) return bail(fail(ctx, RZ_ERR_HIP, "memset"));
-  if ((e = upload(h, &h->coef64, h->coef)) || (e = upload(h, &h->B64, h->t.B)) || (e = upload(h, &h->A64, h->t.A)) ||
-      (e = upload(h, &h->lam64, lamf)) || (e = upload(h, &h->E64, h->t.E)) || (e = upload(h, &h->coef32, c32)) ||
-      (e = upload(h, &h->B32, B32)) || (e = upload(h, &h->A32, A32)) || (e = upload(h, &h->lam32, l32)))
-    return bail(e);
+  if ((e = upload(h, &h->E64, h->t.E))) return bail(e);
   if (!h->quad) {  // A E and B E for the fused coarse correction and residual
     std::vector<double> T2(4 * (size_t)n1, 0.0);
     for (int a = 0; a < n1; ++a)
@@ -1326,72 +2171,10 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
     h->Q64 = QuadDev<double>{dv, a64, b64, qB, qD, qw, qx, qL};
     h->Q32 = QuadDev<float>{dv, a32, b32, fB, fD, fw, fx, fL};
   }
-  // symbolic patch arrays
-  const PatchSymbolic &ps = h->ps;
-  std::vector<int> sym;
-  auto push = [&](const std::vector<int> &v) {
-    size_t o = sym.size();
-    sym.insert(sym.end(), v.begin(), v.end());
-    return o;
-  };
-  std::vector<int> passes;
-  for (int t = 0; t < ps.npass; ++t) {
-    passes.push_back(ps.pass_g[t]);
-    passes.push_back(ps.pass_k[t]);
-    passes.push_back(ps.pass_base[t]);
-  }
-  size_t o_off = push(ps.off), o_rp = push(ps.rowptr), o_col = push(ps.col), o_er = push(h->erow),
-         o_up = push(ps.uptr), o_ur = push(ps.urow), o_upos = push(ps.upos), o_fp = push(ps.flev_ptr),
-         o_fr = push(ps.flev_rows), o_bp = push(ps.blev_ptr), o_br = push(ps.blev_rows), o_p1 = push(ps.pos1),
-         o_p2 = push(ps.pos2), o_pass = push(passes), o_ecol = push(ps.ecol), o_erow = push(ps.erow);
-  int *dsym = nullptr;
-  if ((e = upload(h, &dsym, sym))) return bail(e);
-  h->P = PatchDev{ps.nrows, ps.nnz, (int)ps.flev_ptr.size() - 1, (int)ps.blev_ptr.size() - 1,
-                  dsym + o_off, dsym + o_rp, dsym + o_col, dsym + o_er, dsym + o_up, dsym + o_ur, dsym + o_upos,
-                  dsym + o_fp, dsym + o_fr, dsym + o_bp, dsym + o_br, ps.stride, dsym + o_p1, dsym + o_p2};
-  int kmax = 1;
-  for (int k : ps.pass_k) kmax = std::max(kmax, k);
-  h->PE = PatchEllDev{ps.nrows, ps.npass, ps.ef + ps.eb, ps.stride, kmax, dsym + o_pass, dsym + o_ecol,
-                      dsym + o_erow, dsym + o_off,
-                      patch_regs_table_matches(p, passes.data(), ps.npass, ps.nrows, ps.ef + ps.eb, ps.ell0) ? 1 : 0,
-                      ps.ell0};
-  if (patch_solve_lds_bytes(h->PE, sizeof(double), 1) > 160 * 1024)
-    return bail(fail(ctx, RZ_ERR_ARG, "patch schedule does not fit the LDS"));
-  const size_t nf = (size_t)h->nvert * ps.stride, nzb = (size_t)h->nvert * ps.nrows;
   const size_t neb = (size_t)h->ncells * (p + 1) * (p + 1) * (p + 1);
-  if ((e = dalloc(h, &h->eb64, neb)) || (e = dalloc(h, &h->eb32, neb)) || (e = dalloc(h, &h->f64, nf)) ||
-      (e = dalloc(h, &h->f32, nf)) || (e = dalloc(h, &h->zb64, nzb)) ||
-      (e = dalloc(h, &h->zb32, nzb)) || (e = dalloc(h, &h->rt64, h->ndofs)) || (e = dalloc(h, &h->rt32, h->ndofs)) ||
-      (e = dalloc(h, &h->r32, h->ndofs)) || (e = dalloc(h, &h->z32, h->ndofs)) || (e = dalloc(h, &h->vt, h->ndofs)) ||
-      (e = dalloc(h, &h->vaz, h->ndofs)) || (e = dalloc(h, &h->vr, h->ndofs)) || (e = dalloc(h, &h->kr, h->ndofs)) ||
-      (e = dalloc(h, &h->kz, h->ndofs)) || (e = dalloc(h, &h->kp, h->ndofs)) || (e = dalloc(h, &h->kAp, h->ndofs)) ||
-      (e = dalloc(h, &h->kro, h->ndofs)) || (e = dalloc(h, &h->partials, dots_partials_size())) ||
-      (e = dalloc(h, &h->dots, 8)))
+  if ((e = dalloc(h, &h->eb64, neb)) || (e = dalloc(h, &h->eb32, neb)) || (e = dalloc(h, &h->rt64, h->ndofs)) ||
+      (e = dalloc(h, &h->rt32, h->ndofs)) || (e = alloc_krylov(h)))
     return bail(e);
-  if (hipHostMalloc((void **)&h->hdots, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
-    return bail(fail(ctx, RZ_ERR_OOM, "pinned host buffer"));
-  if (opts->precision == RZ_PREC_DEFECT &&
-      ((e = dalloc(h, &h->kp32, h->ndofs)) || (e = dalloc(h, &h->kAp32, h->ndofs)) ||
-       (e = dalloc(h, &h->ko32, h->ndofs)) || (e = dalloc(h, &h->ke32, h->ndofs)) ||
-       (e = dalloc(h, &h->t32, h->ndofs)) || (e = dalloc(h, &h->az32, h->ndofs)) ||
-       (e = dalloc(h, &h->vr32, h->ndofs))))
-    return bail(e);
-  // the workspace of the vertex patches: keep rows of empty slots well defined
-  launch_fill(h->zb64, 0.0, (int64_t)nzb, s);
-  // ELL padding of the factors must read as zero
-  if (hipMemsetAsync(h->f64, 0, nf * sizeof(double), s) != hipSuccess ||
-      hipMemsetAsync(h->f32, 0, nf * sizeof(float), s) != hipSuccess)
-    return bail(fail(ctx, RZ_ERR_HIP, "memset"));
-  launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, h->f64, h->f32, h->status, s);
-  if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(ctx, RZ_ERR_HIP, "patch factorisation failed"));
-  int stv = 0;
-  if (hipMemcpy(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
-    return bail(fail(ctx, RZ_ERR_HIP, "status read"));
-  if (stv) {
-    char msg[128];
-    std::snprintf(msg, sizeof msg, "incomplete Cholesky breakdown in vertex patch %d", stv - 1);
-    return bail(fail(ctx, RZ_ERR_BREAKDOWN, msg));
-  }
   if ((e = dalloc(h, &h->rt1, (size_t)(h->nx + 1) * h->Ny * h->Nz)) ||
       (e = dalloc(h, &h->rt2, (size_t)(h->nx + 1) * (h->ny + 1) * h->Nz)) ||
       (e = dalloc(h, &h->rc, (size_t)(h->nx + 1) * (h->ny + 1) * (h->nz + 1))) ||
@@ -1427,6 +2210,23 @@ rz_status rz_free(rz_problem *h) {
 
 rz_status rz_sizes(const rz_problem *h, int64_t sizes[8]) {
   if (!h || !sizes) return RZ_ERR_ARG;
+  if (h->space != RZ_GRAD) {
+    const int nx = h->nx, ny = h->ny, nz = h->nz;
+    sizes[0] = h->ndofs;
+    sizes[1] = h->nfree;
+    sizes[2] = h->ncells;
+    // star patches of the relaxation: edges (curl) or faces (div)
+    sizes[3] = h->space == RZ_CURL ? (int64_t)nx * (ny + 1) * (nz + 1) + (int64_t)(nx + 1) * ny * (nz + 1) +
+                                         (int64_t)(nx + 1) * (ny + 1) * nz
+                                   : (int64_t)(nx + 1) * ny * nz + (int64_t)nx * (ny + 1) * nz +
+                                         (int64_t)nx * ny * (nz + 1);
+    // p = 1 lattice DoFs
+    sizes[4] = h->space == RZ_CURL ? sizes[3] : sizes[3];
+    sizes[5] = h->ed.fac_stride;     // curl: factor values of one edge patch
+    sizes[6] = h->edge_nslot;        // slots of one edge patch (curl; div: its potential)
+    sizes[7] = (int64_t)h->edge_ids.size();  // non-empty edge patches
+    return RZ_OK;
+  }
   sizes[0] = h->ndofs;
   sizes[1] = h->nfree;
   sizes[2] = h->ncells;
@@ -1502,7 +2302,6 @@ rz_status rz_apply_noalloc(rz_problem *h, const void *x, void *y, rz_dtype t) {
 rz_status rz_relax(rz_problem *h, const void *r, void *z, rz_dtype t) {
   rz_status e = require_device(h);
   if (e) return e;
-  if ((e = require_grad(h))) return e;
   if (!r || !z || r == z) return fail(h->ctx, RZ_ERR_ARG, "rz_relax: bad vectors");
   if (t == RZ_F64) return do_relax64(h, static_cast<const double *>(r), static_cast<double *>(z));
   if (t == RZ_F32) return do_relax32(h, static_cast<const float *>(r), static_cast<float *>(z));
@@ -1538,7 +2337,6 @@ rz_status rz_coarse_solve(rz_problem *h, const double *rcv, double *xcv) {
 rz_status rz_vcycle(rz_problem *h, const double *r, double *z) {
   rz_status e = require_device(h);
   if (e) return e;
-  if ((e = require_grad(h))) return e;
   if (!r || !z || r == z) return fail(h->ctx, RZ_ERR_ARG, "rz_vcycle: bad vectors");
   return do_vcycle(h, r, z);
 }
@@ -1546,7 +2344,6 @@ rz_status rz_vcycle(rz_problem *h, const double *r, double *z) {
 rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *info) {
   rz_status e = require_device(h);
   if (e) return e;
-  if ((e = require_grad(h))) return e;
   if (!b || !x || b == x) return fail(h->ctx, RZ_ERR_ARG, "rz_solve: bad vectors");
   if (h->opts.precision == RZ_PREC_DEFECT) return defect_solve(h, b, x, info);
   PcgRun R;
@@ -1572,7 +2369,7 @@ rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const
   for (int i = 0; i < n; ++i) {
     if (!hs[i] || !b[i] || !x[i]) return RZ_ERR_ARG;
     rz_status e = require_device(hs[i]);
-    if (e || (e = require_grad(hs[i]))) return e;
+    if (e) return e;
     if (hs[i]->opts.precision == RZ_PREC_DEFECT)
       return fail(hs[i]->ctx, RZ_ERR_ARG, "rz_solve_batched: the defect-correction protocol is not batched");
     for (int j = 0; j < i; ++j)
@@ -1828,6 +2625,19 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
     case RZ_EXPORT_OMEGA:
       put(&h->omega, sizeof(double));
       break;
+    case RZ_EXPORT_EDGE_PATCH: {
+      if (h->space == RZ_GRAD) return fail(h->ctx, RZ_ERR_ARG, "edge patches exist for H(curl) / H(div) only");
+      if (index < 0 || index >= (int64_t)h->edge_ids.size()) return fail(h->ctx, RZ_ERR_ARG, "bad patch index");
+      std::vector<int64_t> v;
+      for (int k = 0; k < h->edge_nslot; ++k) {
+        const int g = h->edge_idx[(size_t)index * h->edge_nslot + k];
+        if (g >= 0) v.push_back(g);
+      }
+      std::sort(v.begin(), v.end());
+      put(&h->edge_ids[index], sizeof(int64_t));
+      put(v.data(), sizeof(int64_t) * v.size());
+      break;
+    }
     case RZ_EXPORT_PATCH_KERNEL: {
       const int32_t v[2] = {patch_solve_uses_regs(h->PE, h->p, 8) ? 1 : 0, patch_solve_uses_regs(h->PE, h->p, 4) ? 1 : 0};
       put(v, sizeof v);

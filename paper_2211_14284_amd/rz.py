@@ -27,6 +27,7 @@ COEF_CONST, COEF_CELL, COEF_SAMPLES = 0, 1, 2
 PREC_F64, PREC_MIXED, PREC_DEFECT = 0, 1, 2
 EXPORT_DOFMAP, EXPORT_PATCH, EXPORT_IC_PATTERN, EXPORT_IC_FACTOR = 0, 1, 2, 3
 EXPORT_TABLES1D, EXPORT_AUXCOEF, EXPORT_OMEGA, EXPORT_PATCH_KERNEL = 4, 5, 6, 7
+EXPORT_EDGE_PATCH = 8
 KERNELS = ("apply", "condense", "patch", "expand", "transfer", "coarse", "krylov")
 STATUS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_OOM", -3: "RZ_ERR_BREAKDOWN",
           -4: "RZ_ERR_NOT_CONVERGED", -5: "RZ_ERR_HIP", -6: "RZ_ERR_SINGULAR", -7: "RZ_ERR_NODEVICE"}
@@ -51,7 +52,7 @@ class Coef(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("space", ctypes.c_int32), ("p", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double), ("omega", ctypes.c_double),
-                ("lanczos_seed", ctypes.c_uint64)]
+                ("lanczos_seed", ctypes.c_uint64), ("hdiv_eps", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -290,6 +291,12 @@ class Problem:
 
     def patch(self, k):
         v = self._export(EXPORT_PATCH, k, dtype=np.int64)
+        return int(v[0]), v[1:]
+
+    def edge_patch(self, k):
+        """(edge id, DoFs) of non-empty edge-star patch k (H(curl); H(div): its
+        NCE_p potential problem)."""
+        v = self._export(EXPORT_EDGE_PATCH, k, dtype=np.int64)
         return int(v[0]), v[1:]
 
     def ic_pattern(self, k):
