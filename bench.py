@@ -1,19 +1,26 @@
 #!/usr/bin/env python
-"""Benchmark of the H(grad) hot path on one MI355X.
+"""Benchmark of the hot path on one MI355X.
 
-Workload (default): Q_7 on a uniform 32^3 hexahedral mesh of the unit cube
-(225^3 = 11,390,625 lattice DoFs), cellwise-constant alpha, beta log-uniform in
-[1e-2, 1e2) (SplitMix64 seeds 1, 2), U[-1,1) right-hand side (seed 0), homogeneous
-Dirichlet boundary.
+Headline workload (C2): H(grad) Q_7 on a uniform 32^3 hexahedral mesh of the unit
+cube (225^3 = 11,390,625 lattice DoFs), cellwise-constant alpha, beta log-uniform
+in [1e-2, 1e2) (SplitMix64 seeds 1, 2), U[-1,1) right-hand side (seed 0),
+homogeneous Dirichlet boundary.
 
 One step = one PCG solve from x = 0 to a true relative residual of 1e-8 with the
 p-multigrid V(1,1) preconditioner (statically condensed vertex-star relaxation
 with IC patch factors, p=1 coarse solve), all vectors resident in HBM; setup is
-done once before the timed region and reported separately.  Printed: one JSON
-line with the FP64 solve throughput as `value`, plus the mixed-precision solve,
-the operator-apply throughput, per-kernel times and the roofline of the dominant
-kernel (HIP events on the library stream over the timed region), and the CPU
-oracle timed on a bounded sample.
+done once before the timed region and reported separately.  The timed solves run
+without per-kernel events; a second pass of the same solves with the events on
+gives the per-kernel breakdown and the launch times of the rooflines.
+
+Printed: one JSON line with the FP64 solve throughput as `value`, the mixed and
+defect-correction protocols, the operator applies with their rooflines, the
+workloads C1 (Q_4 on 4^3), C3 (NCE_6 on 16^3, solved), C5 (Q_8 on a perturbed
+24^3 mesh) and the batched workload (64 problems of all three spaces), and the
+CPU oracle timed on a bounded sample with the errors of GPU solutions against it.
+
+`--only NAME` runs one piece alone (for profiling): c2, c2-apply, c3, c3-apply,
+c5-apply.
 """
 import argparse
 import json
@@ -27,9 +34,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of a kernel group from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0,
-# WRITE_SIZE x 1.0, factors from a plain 1 GiB copy in the same run); the figure belongs
-# to the kernel version it was taken on (profiles/pmc_patch_solve_hgrad_q7_n32.md)
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+# HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0, WRITE_SIZE
+# x 1.0; factors from a plain 1 GiB copy in the same run), valid for the kernel
+# version they were taken on (profiles/pmc_patch_solve_hgrad_q7_n32.md)
 MEASURED_TRAFFIC = {"patch": 2.281e9}
 METRIC = "GDoF/s sum-factorized apply; PCG time-to-1e-8, FP64 vs mixed, H(grad) p=7"
 
@@ -46,27 +55,6 @@ def workload(n, p):
     ndofs = (n * p + 1) ** 3
     b = synth.rhs_values(ndofs, 0)
     return alpha, beta, b
-
-
-def kernel_bytes(pb, sz, n):
-    """Algorithmic HBM bytes of one launch of each timed kernel group (element size sz)."""
-    nd, ns, nnz, nrows, nc, p = pb.ndofs, pb.nslots, pb.nnz, pb.nrows, pb.ncells, pb.p
-    niface = nd - nc * (p - 1) ** 3
-    return {
-        # x read once, y written once, 6 weights per cell
-        "apply": 2 * nd * sz + 6 * nc * sz,
-        # r read once, interface right-hand side written once
-        "condense": (nd + niface) * sz,
-        # every slot: its factor (off-diagonals and diagonal, stored once) read once,
-        # its interface vector in and out; both sweeps stream the off-diagonals, the
-        # second read served by the caches or counted by the HBM counters
-        "patch": ns * (nnz + 2 * nrows) * sz,
-        # patch solutions read once, r read once, z written once
-        "expand": (ns * nrows + 2 * nd) * sz,
-        # dense inverse blocks and coupling products of the coarse factorisation
-        # (W, M, N per plane), each read once
-        "coarse": 3 * (n - 1) * ((n - 1) ** 2) ** 2 * 8,
-    }
 
 
 def time_solves(torch, pb, bt, x, steps, warmup):
@@ -89,6 +77,7 @@ def time_solves(torch, pb, bt, x, steps, warmup):
 
 
 def time_apply(torch, pb, dtype_t, code, reps=50, warm=10):
+    """Median device time (ms) of one apply, HIP events on the library's stream."""
     x = torch.rand(pb.ndofs, dtype=dtype_t, device="cuda:0")
     y = torch.empty_like(x)
     for _ in range(warm):
@@ -103,6 +92,142 @@ def time_apply(torch, pb, dtype_t, code, reps=50, warm=10):
         e1.synchronize()
         ts.append(e0.elapsed_time(e1))
     return float(np.median(ts))
+
+
+def hbm_roof(bytes_, ms, kernel, note):
+    ach = bytes_ / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": kernel, "avg_launch_ms": round(ms, 4),
+            "algorithmic_bytes_per_launch": int(bytes_), "bytes": note}
+
+
+def alu_roof(flops, ms, peak, kernel, note):
+    ach = flops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(ach / peak, 4), "kernel": kernel, "avg_launch_ms": round(ms, 4),
+            "algorithmic_flops_per_launch": int(flops), "flops": note}
+
+
+# ---------------------------------------------------------------------------------------
+def bench_c2(torch, rz, ctx, args, out):
+    alpha, beta, b = workload(args.n, args.p)
+    log(f"C2 setup FP64 n={args.n} p={args.p}")
+    t0 = time.perf_counter()
+    pb = rz.Problem(ctx, args.n, args.p, alpha, beta, precision=rz.PREC_F64)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"setup done in {setup_s:.2f} s; timing {args.steps} FP64 solves")
+    bt = torch.as_tensor(b, device="cuda:0")
+    x = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
+    ms, infos, kt = time_solves(torch, pb, bt, x, args.steps, args.warmup)
+    st = pb.stats()
+    nd = pb.ndofs
+    # the patch solve, the dominant kernel: its own bytes per launch as the scope
+    # table states them (two sweeps over the factor of every non-empty patch, the
+    # patch vectors in and out), and the single-read minimum beside them
+    per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}
+    two_sweeps = (2 * st["factor_nnz"] + 2 * st["patch_rows"]) * 8
+    one_read = (st["factor_nnz"] + 2 * st["patch_rows"]) * 8
+    roof = hbm_roof(two_sweeps, per_launch["patch"], "patch",
+                    "2 sweeps x factor nnz of all non-empty vertex patches + patch vectors in/out, FP64")
+    roof["frac_single_read"] = round(one_read / (per_launch["patch"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    roof["bytes_single_read"] = int(one_read)
+    roof["traffic"] = MEASURED_TRAFFIC["patch"] if (args.p == 7 and args.n == 32) else None
+    dom = max(kt, key=lambda k: kt[k][0])
+    log(f"FP64 solve {ms:.3f} ms, {infos[-1].iters} iterations; timing the apply")
+    a64 = time_apply(torch, pb, torch.float64, rz.F64)
+    a32 = time_apply(torch, pb, torch.float32, rz.F32)
+    nc = pb.ncells
+    out.update({
+        "value": round(nd / (ms * 1e-3) / 1e9, 5), "ms_per_step": round(ms, 4),
+        "config": {"workload": f"C2: H(grad) Q_{args.p} on {args.n}^3 uniform hex mesh, cellwise log-uniform "
+                               f"alpha,beta in [1e-2,1e2), U[-1,1) RHS; PCG to true rel. residual 1e-8",
+                   "ndofs": nd, "nfree": pb.nfree, "cells": nc, "p": args.p},
+        "pcg_ms_f64": round(ms, 4), "iters_f64": infos[-1].iters, "rel_res_f64": max(i.rel_res for i in infos),
+        "iters_natural_f64": infos[-1].iters_natural,
+        "setup_s_f64": round(setup_s, 3), "omega": pb.omega(),
+        "apply_ms_f64": round(a64, 4), "apply_ms_f32": round(a32, 4),
+        "apply_gdofs_f64": round(nd / (a64 * 1e-3) / 1e9, 2), "apply_gdofs_f32": round(nd / (a32 * 1e-3) / 1e9, 2),
+        "kernel_ms_per_step_f64": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
+        "kernel_launches_per_step_f64": {k: v[1] / args.steps for k, v in kt.items()},
+        "dominant_kernel": dom,
+        "roofline": roof,
+    })
+    out["rooflines"] = {
+        "patch_f64": roof,
+        "apply_c2_f64": hbm_roof(2 * nd * 8 + 6 * nc * 8, a64, "k_apply_pencil+k_apply_faces",
+                                 "x in, y out, 6 weights per cell (FP64)"),
+        "apply_c2_f32": hbm_roof(2 * nd * 4 + 6 * nc * 4, a32, "k_apply_pencil+k_apply_faces",
+                                 "x in, y out, 6 weights per cell (FP32)"),
+    }
+    pb.close()
+    if not args.no_mixed:
+        for prec, name in ((rz.PREC_MIXED, "mixed"), (rz.PREC_DEFECT, "defect")):
+            log(f"C2 setup ({name})")
+            t0 = time.perf_counter()
+            pm = rz.Problem(ctx, args.n, args.p, alpha, beta, precision=prec)
+            torch.cuda.synchronize()
+            out[f"setup_s_{name}"] = round(time.perf_counter() - t0, 3)
+            msm, infm, ktm = time_solves(torch, pm, bt, x, args.steps, args.warmup)
+            out[f"pcg_ms_{name}"] = round(msm, 4)
+            out[f"iters_{name}"] = infm[-1].iters
+            out[f"rel_res_{name}"] = max(i.rel_res for i in infm)
+            out[f"kernel_ms_per_step_{name}"] = {k: round(v[0] / args.steps, 4) for k, v in ktm.items()}
+            out[f"speedup_{name}_vs_f64"] = round(ms / msm, 3)
+            pm.close()
+
+
+def bench_c1(torch, rz, ctx, steps=20):
+    """C1: Q_4 on 4^3, alpha = beta = 1; apply latency and PCG time (FP64)."""
+    import synth
+    pb = rz.Problem(ctx, 4, 4, 1.0, 1.0)
+    b = torch.as_tensor(synth.rhs_values(pb.ndofs, 0), device="cuda:0")
+    x = torch.empty_like(b)
+    ms, infos, _ = time_solves(torch, pb, b, x, steps, 2)
+    a = time_apply(torch, pb, torch.float64, rz.F64)
+    out = {"workload": "C1: H(grad) Q_4 on 4^3, alpha=beta=1", "ndofs": pb.ndofs, "nfree": pb.nfree,
+           "apply_us_f64": round(a * 1e3, 2), "pcg_ms_f64": round(ms, 4), "iters_f64": infos[-1].iters,
+           "rel_res_f64": infos[-1].rel_res}
+    sol = x.cpu().numpy()
+    pb.close()
+    return out, sol
+
+
+def bench_c3(torch, rz, ctx, steps, warmup, n=16, p=6):
+    """C3: H(curl) NCE_6 on a uniform 16^3 mesh, alpha = beta = 1: applies and PCG in
+    the three precision protocols (FP64, FP32 relaxation, FP32 operator)."""
+    import synth
+    out = {"workload": f"C3: H(curl) NCE_{p} on {n}^3 uniform hex mesh, alpha=beta=1, tangential Dirichlet, "
+                       f"SC-PH relaxation, NCE_1 coarse"}
+    b = None
+    for prec, name in ((rz.PREC_F64, "f64"), (rz.PREC_MIXED, "mixed"), (rz.PREC_DEFECT, "defect")):
+        log(f"C3 setup ({name})")
+        t0 = time.perf_counter()
+        pb = rz.Problem(ctx, n, p, 1.0, 1.0, space="curl", precision=prec)
+        torch.cuda.synchronize()
+        out[f"setup_s_{name}"] = round(time.perf_counter() - t0, 3)
+        if b is None:
+            # entries on Dirichlet rows are read as zero by the solver
+            b = torch.as_tensor(synth.rhs_values(pb.ndofs, 0), device="cuda:0")
+            x = torch.empty_like(b)
+            out["ndofs"], out["nfree"] = pb.ndofs, pb.nfree
+        ms, infos, kt = time_solves(torch, pb, b, x, steps, warmup)
+        out[f"pcg_ms_{name}"] = round(ms, 4)
+        out[f"iters_{name}"] = infos[-1].iters
+        out[f"rel_res_{name}"] = max(i.rel_res for i in infos)
+        out[f"kernel_ms_per_step_{name}"] = {k: round(v[0] / steps, 4) for k, v in kt.items()}
+        if prec == rz.PREC_F64:
+            out["gdofs_f64"] = round(pb.ndofs / (ms * 1e-3) / 1e9, 5)
+            for nm, dt, code, sz in (("f64", torch.float64, rz.F64, 8), ("f32", torch.float32, rz.F32, 4)):
+                a = time_apply(torch, pb, dt, code)
+                out[f"apply_ms_{nm}"] = round(a, 4)
+                out[f"apply_gdofs_{nm}"] = round(pb.ndofs / (a * 1e-3) / 1e9, 2)
+                out[f"roofline_apply_{nm}"] = hbm_roof(2 * pb.ndofs * sz + 6 * pb.ncells * sz, a, "k_apply_vec",
+                                                       "x in, y out, 6 weights per cell")
+        pb.close()
+    out["speedup_mixed_vs_f64"] = round(out["pcg_ms_f64"] / out["pcg_ms_mixed"], 3)
+    out["speedup_defect_vs_f64"] = round(out["pcg_ms_f64"] / out["pcg_ms_defect"], 3)
+    return out
 
 
 def c5_aux_variants(torch, rz, ctx, pb, b, x, n, p, train_seeds=(10, 11, 12, 13)):
@@ -129,9 +254,11 @@ def c5_aux_variants(torch, rz, ctx, pb, b, x, n, p, train_seeds=(10, 11, 12, 13)
     Xs, Ys = [], []
     for s in train_seeds:
         v = synth.perturbed_vertices(n, s)
-        hp = rz.Problem(rz.Context(-1), n, p, synth.c5_coefficient_samples(v, n), 1.0, vertices=v)
+        hctx = rz.Context(-1)
+        hp = rz.Problem(hctx, n, p, synth.c5_coefficient_samples(v, n), 1.0, vertices=v)
         t, f, bs = hp.aux_data()
         hp.close()
+        hctx.close()
         Xs.append(f.astype(np.float32))
         Ys.append(np.log(t / bs).astype(np.float32))
     X = torch.as_tensor(np.concatenate(Xs), device="cuda:0")
@@ -155,7 +282,15 @@ def c5_aux_variants(torch, rz, ctx, pb, b, x, n, p, train_seeds=(10, 11, 12, 13)
     return res
 
 
-def bench_c5(torch, rz, ctx, steps, warmup, n=24, p=8):
+def c5_flops_per_cell(p, q):
+    """Algorithmic flops of one trilinear cell of the quadrature apply: the
+    contractions 2[4q(p+1)^3 + 6q^2(p+1)^2 + 8q^3(p+1)] plus about 150 per
+    quadrature point for J, the adjugate, det J, the coefficient and the pullback."""
+    n1 = p + 1
+    return 2 * (4 * q * n1 ** 3 + 6 * q * q * n1 ** 2 + 8 * q ** 3 * n1) + 150 * q ** 3
+
+
+def bench_c5(torch, rz, ctx, steps, warmup, n=24, p=8, aux=True):
     """Q_8 on a 24^3 mesh with interior vertices perturbed by up to 0.15 h (seed 3),
     alpha = exp(0.5 sin 2pi x sin 2pi y sin 2pi z) sampled at 27 reference points per
     cell, beta = 1, U[-1,1) RHS (seed 0): PCG with the cell-averaged separable
@@ -163,9 +298,10 @@ def bench_c5(torch, rz, ctx, steps, warmup, n=24, p=8):
     import synth
     v = synth.perturbed_vertices(n, 3)
     a = synth.c5_coefficient_samples(v, n)
-    out = {"workload": f"H(grad) Q_{p} on a perturbed {n}^3 mesh (trilinear cells, interior vertices "
+    out = {"workload": f"C5: H(grad) Q_{p} on a perturbed {n}^3 mesh (trilinear cells, interior vertices "
                        f"+-0.15h), alpha=exp(0.5 sin sin sin) sampled 27/cell, beta=1; "
                        f"cell-averaged separable auxiliary"}
+    q = int(np.ceil(3 * (p + 1) / 2))
     for prec, name in ((rz.PREC_F64, "f64"), (rz.PREC_MIXED, "mixed")):
         log(f"C5 setup ({name})")
         t0 = time.perf_counter()
@@ -181,37 +317,26 @@ def bench_c5(torch, rz, ctx, steps, warmup, n=24, p=8):
         out[f"rel_res_{name}"] = max(i.rel_res for i in infos)
         out[f"kernel_ms_per_step_{name}"] = {k: round(v_[0] / steps, 4) for k, v_ in kt.items()}
         if prec == rz.PREC_F64:
-            out["aux"] = c5_aux_variants(torch, rz, ctx, pb, b, x, n, p)
+            if aux:
+                out["aux"] = c5_aux_variants(torch, rz, ctx, pb, b, x, n, p)
             out["gdofs_f64"] = round(pb.ndofs / (ms * 1e-3) / 1e9, 5)
-            out["apply_ms_f64"] = round(time_apply(torch, pb, torch.float64, rz.F64), 4)
-            out["apply_ms_f32"] = round(time_apply(torch, pb, torch.float32, rz.F32), 4)
-            out["apply_gdofs_f64"] = round(pb.ndofs / (out["apply_ms_f64"] * 1e-3) / 1e9, 2)
-            out["apply_gdofs_f32"] = round(pb.ndofs / (out["apply_ms_f32"] * 1e-3) / 1e9, 2)
+            fl = c5_flops_per_cell(p, q) * pb.ncells
+            for nm, dt, code, peak in (("f64", torch.float64, rz.F64, FP64_PEAK_TFLOPS),
+                                       ("f32", torch.float32, rz.F32, FP32_PEAK_TFLOPS)):
+                am = time_apply(torch, pb, dt, code)
+                out[f"apply_ms_{nm}"] = round(am, 4)
+                out[f"apply_gdofs_{nm}"] = round(pb.ndofs / (am * 1e-3) / 1e9, 2)
+                out[f"roofline_apply_{nm}"] = alu_roof(fl, am, peak, "k_apply_quad+k_apply_gather",
+                                                       f"sum factorization at q={q} + ~150 flops per point")
         pb.close()
     return out
 
 
-def bench_c3(torch, rz, ctx, n=16, p=6):
-    """H(curl) NCE_6 on a uniform 16^3 mesh, alpha = beta = 1: operator apply throughput
-    (the H(curl) relaxation is not built, so no solve)."""
-    pb = rz.Problem(ctx, n, p, 1.0, 1.0, space="curl")
-    out = {"workload": f"H(curl) NCE_{p} on {n}^3 uniform hex mesh, alpha=beta=1 (apply only)",
-           "ndofs": pb.ndofs, "nfree": pb.nfree}
-    for name, dt, code in (("f64", torch.float64, rz.F64), ("f32", torch.float32, rz.F32)):
-        ms = time_apply(torch, pb, dt, code)
-        out[f"apply_ms_{name}"] = round(ms, 4)
-        out[f"apply_gdofs_{name}"] = round(pb.ndofs / (ms * 1e-3) / 1e9, 2)
-    pb.close()
-    return out
-
-
 def bench_batched(torch, rz, nrhs=4, nctx=2, count=64):
-    """The batched workload: 64 problems with (n, p) drawn per problem (n in 4..16,
-    p in 3..9, streams 1000+i), 4 right-hand sides each (seeds 4i..4i+3), alpha =
-    beta = 1.  Only H(grad) is built, so every member is solved as an H(grad) Riesz
-    map of its drawn size and degree.  Sequential rz_solve calls vs rz_solve_batched
-    over `nctx` contexts (streams); two streams measured fastest (1, 2, 4, 8 streams:
-    0.94x, 1.42x, 1.09x, 0.94x of the sequential time)."""
+    """The batched workload: 64 problems with (space, n, p) drawn per problem
+    (space in grad/curl/div, n in 4..16, p in 3..9, streams 1000+i), 4 right-hand
+    sides each (seeds 4i..4i+3), alpha = beta = 1.  Sequential rz_solve calls vs
+    rz_solve_batched over `nctx` contexts (streams)."""
     import synth
     streams = [torch.cuda.Stream() for _ in range(nctx)]
     ctxs = [rz.Context(0, s) for s in streams]
@@ -220,7 +345,7 @@ def bench_batched(torch, rz, nrhs=4, nctx=2, count=64):
     probs, bs, xs, spec = [], [], [], []
     for i in range(count):
         space, n, p = synth.batch_spec(i)
-        pb = rz.Problem(ctxs[i % nctx], n, p, 1.0, 1.0)
+        pb = rz.Problem(ctxs[i % nctx], n, p, 1.0, 1.0, space=space)
         probs.append(pb)
         spec.append((space, n, p))
         bs.append(torch.as_tensor(np.stack([synth.rhs_values(pb.ndofs, 4 * i + r) for r in range(nrhs)]),
@@ -249,10 +374,10 @@ def bench_batched(torch, rz, nrhs=4, nctx=2, count=64):
     torch.cuda.synchronize()
     t_con = time.perf_counter() - t0
     iters = [inf.iters for row in con for inf in row]
-    out = {"workload": f"{count} H(grad) Riesz maps, n in 4..16, p in 3..9 (drawn per problem), "
-                       f"{nrhs} RHS each, alpha=beta=1 (members drawn as curl/div solved as grad)",
+    out = {"workload": f"C4: {count} Riesz maps, space in grad/curl/div, n in 4..16, p in 3..9 (drawn per "
+                       f"problem), {nrhs} RHS each, alpha=beta=1, FP64",
            "problems": count, "rhs_per_problem": nrhs, "total_dofs_x_rhs": dofs_rhs,
-           "spaces_drawn": {s: sum(1 for q in spec if q[0] == s) for s in ("grad", "curl", "div")},
+           "spaces": {s: sum(1 for q in spec if q[0] == s) for s in ("grad", "curl", "div")},
            "setup_s": round(setup_s, 2), "sequential_s": round(t_seq, 4), "batched_s": round(t_con, 4),
            "contexts": nctx, "gdofs_rhs_per_s_sequential": round(dofs_rhs / t_seq / 1e9, 4),
            "gdofs_rhs_per_s_batched": round(dofs_rhs / t_con / 1e9, 4),
@@ -260,23 +385,48 @@ def bench_batched(torch, rz, nrhs=4, nctx=2, count=64):
            "max_rel_res": max(inf.rel_res for row in con for inf in row)}
     for pb in probs:
         pb.close()
+    for c in ctxs:
+        c.close()
     return out
 
 
-def cpu_baseline(n=4, p=7, min_s=10.0):
-    """The oracle's FP64 PCG (same method, same recipe) on a bounded sample."""
+def gpu_small_solutions(torch, rz, ctx):
+    """GPU solutions of small instances of the workloads, for the error against the
+    oracle computed in the CPU leg: C2's recipe at n = 4 (Q_7), C3's at n = 3 (NCE_6),
+    and the H(div) Riesz map NCF_4 on 3^3."""
+    import synth
+    sols = {}
+    al, be = synth.cell_coefficients(64, 1), synth.cell_coefficients(64, 2)
+    for name, (space, n, p, a, bcoef) in {"c2_n4": ("grad", 4, 7, al, be), "c3_n3": ("curl", 3, 6, 1.0, 1.0),
+                                          "div_n3": ("div", 3, 4, 1.0, 1.0)}.items():
+        pb = rz.Problem(ctx, n, p, a, bcoef, space=space)
+        b = torch.as_tensor(synth.rhs_values(pb.ndofs, 0), device="cuda:0")
+        x = torch.empty_like(b)
+        info = pb.solve(b, x)
+        sols[name] = {"x": x.cpu().numpy(), "iters": info.iters, "rel_res": info.rel_res}
+        pb.close()
+    return sols
+
+
+def cpu_baseline(gpu, min_s=10.0):
+    """The oracle (plain NumPy/SciPy FP64, as it stands) on the host's cores, on
+    bounded samples of the workloads, and the error of GPU solutions against it."""
     from threadpoolctl import threadpool_limits
+    import scipy.sparse.linalg as spla
     import synth
     from oracle.lattice import Mesh, Lattice
-    from oracle import assemble as asm, auxop, schwarz, pmg
-    with threadpool_limits(limits=1):
-        al = synth.cell_coefficients(n ** 3, 1)
-        be = synth.cell_coefficients(n ** 3, 2)
+    from oracle import assemble as asm, auxop, schwarz, pmg, matfree, hiptmair as hp
+    from oracle import quadrature as oq
+    cores = len(os.sched_getaffinity(0))
+    res = {}
+    with threadpool_limits(limits=cores):
+        # PCG time-to-1e-8 on the C2 recipe at n = 6 (Q_7, 79,507 DoFs), setup excluded
+        n, p = 6, 7
+        al, be = synth.cell_coefficients(n ** 3, 1), synth.cell_coefficients(n ** 3, 2)
         m = Mesh(n, n, n)
         lat, latc = Lattice(m, "grad", p), Lattice(m, "grad", 1)
         A = asm.with_dirichlet(lat, asm.cartesian_operator(lat, al, be))
-        co = auxop.cartesian_coefficient_array(lat, al, be)
-        R = schwarz.SCRelaxGrad(lat, auxop.separable_operator(lat, co))
+        R = schwarz.SCRelaxGrad(lat, auxop.separable_operator(lat, auxop.cartesian_coefficient_array(lat, al, be)))
         Pr = pmg.prolongation(lat, latc)
         cs = pmg.CoarseSolver(latc, asm.with_dirichlet(latc, asm.cartesian_operator(latc, al, be)))
         mask = lat.dirichlet_mask()
@@ -284,18 +434,76 @@ def cpu_baseline(n=4, p=7, min_s=10.0):
         lam = pmg.lanczos_lambda_max(A, lambda r: np.where(mask, 0.0, R.apply(r)), v0)
         V = pmg.VCycle(lat, A, R, Pr, cs, pmg.omega_from_lambda(lam))
         b = np.where(mask, 0.0, synth.rhs_values(lat.ndofs, 0))
-        # a bounded sample: repeat the solve until at least min_s seconds of CPU work
         reps, t = 0, 0.0
         while t < min_s:
             t0 = time.perf_counter()
-            x, it, _ = pmg.pcg(A, b, V)
+            _, it, _ = pmg.pcg(A, b, V)
             t += time.perf_counter() - t0
             reps += 1
         t /= reps
-    return {"value": lat.ndofs / t / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle FP64 PCG to 1e-8 (same V(1,1)/IC/p-MG method and coefficient recipe), "
-                      f"Q_{p} on {n}^3 cells = {lat.ndofs} DoFs, {it} iterations, setup excluded, "
-                      f"{t:.3f} s per solve on 1 host thread, mean of {reps} repetitions"}
+        pcg_value = lat.ndofs / t / 1e9
+        res["pcg_sample"] = (f"oracle FP64 PCG to 1e-8 (same V(1,1)/IC/p-MG method, C2 coefficient recipe), "
+                             f"Q_{p} on {n}^3 cells = {lat.ndofs} DoFs, {it} iterations, setup excluded, "
+                             f"{t:.3f} s per solve, mean of {reps}")
+        # O6 matrix-free apply on the C2 recipe at n = 16 (1/8 of C2's cells)
+        n16 = 16
+        al16, be16 = synth.cell_coefficients(n16 ** 3, 1), synth.cell_coefficients(n16 ** 3, 2)
+        lat16 = Lattice(Mesh(n16, n16, n16), "grad", 7)
+        x16 = synth.uniform_pm1(5, lat16.ndofs)
+        t0 = time.perf_counter()
+        matfree.apply(lat16, x16, al16, be16)
+        ta = time.perf_counter() - t0
+        res["apply_gdofs"] = lat16.ndofs / ta / 1e9
+        res["apply_sample"] = (f"oracle sum-factorized einsum apply (FP64), Q_7 on 16^3 = {lat16.ndofs} DoFs "
+                               f"with the C2 coefficient recipe, {ta:.2f} s")
+        # errors of GPU solutions against the oracle's direct solves
+        errs = {}
+
+        def a_err(A_, xs_, xg):
+            e = xg - xs_
+            return float(np.sqrt(e @ (A_ @ e) / (xs_ @ (A_ @ xs_))))
+        if "c1" in gpu:
+            lat1 = Lattice(Mesh(4, 4, 4), "grad", 4)
+            A1 = asm.with_dirichlet(lat1, asm.cartesian_operator(lat1, 1.0, 1.0))
+            b1 = np.where(lat1.dirichlet_mask(), 0.0, synth.rhs_values(lat1.ndofs, 0))
+            errs["c1"] = a_err(A1, spla.spsolve(A1.tocsc(), b1), np.where(lat1.dirichlet_mask(), 0.0, gpu["c1"]))
+        small = gpu.get("small", {})
+        for name, (space, n_, p_, a_, b_) in {"c2_n4": ("grad", 4, 7, True, True),
+                                              "c3_n3": ("curl", 3, 6, False, False),
+                                              "div_n3": ("div", 3, 4, False, False)}.items():
+            if name not in small:
+                continue
+            la = Lattice(Mesh(n_, n_, n_), space, p_)
+            aa = synth.cell_coefficients(n_ ** 3, 1) if a_ else 1.0
+            bb = synth.cell_coefficients(n_ ** 3, 2) if b_ else 1.0
+            Aa = asm.with_dirichlet(la, asm.cartesian_operator(la, aa, bb))
+            ma = la.dirichlet_mask()
+            ba = np.where(ma, 0.0, synth.rhs_values(la.ndofs, 0))
+            errs[name] = {"A_norm_rel_error": a_err(Aa, spla.spsolve(Aa.tocsc(), ba),
+                                                    np.where(ma, 0.0, small[name]["x"])),
+                          "gpu_iters": small[name]["iters"], "gpu_rel_res": small[name]["rel_res"]}
+        res["errors_vs_oracle_direct_solve"] = errs
+        # C5 input: the 27-sample triquadratic interpolant of alpha against alpha(x) at
+        # the q = 14 Gauss-Lobatto points of every cell
+        v = synth.perturbed_vertices(24, 3)
+        smp = synth.c5_coefficient_samples(v, 24)
+        xq, _ = oq.rule(14, "gll")
+        interp = oq.sampled_values(smp, xq)                       # (ncells, q^3)
+        mesh24 = Mesh(24, 24, 24, vertices=v)
+        cv = mesh24.cell_vertices()
+        worst = 0.0
+        for c0 in range(0, cv.shape[0], 2048):
+            X = []
+            for k in range(c0, min(cv.shape[0], c0 + 2048)):
+                Xk, _ = asm.trilinear_jacobian(cv[k], xq)
+                X.append(Xk)
+            X = np.stack(X)
+            ex = synth.c5_alpha(X.reshape(-1, 3)).reshape(X.shape[0], -1)
+            worst = max(worst, float(np.max(np.abs(interp[c0:c0 + X.shape[0]] - ex) / ex)))
+        res["c5_alpha_interpolation_max_rel_error"] = worst
+    out = {"value": pcg_value, "unit": "GDoF/s", "cores": cores, "kind": "oracle", "sample": res["pcg_sample"]}
+    out.update({k: v for k, v in res.items() if k != "pcg_sample"})
+    return out
 
 
 def main():
@@ -305,6 +513,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--p", type=int, default=7)
+    ap.add_argument("--only", choices=["c2", "c2-apply", "c3", "c3-apply", "c5-apply"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
@@ -323,90 +532,59 @@ def main():
     import torch
     from paper_2211_14284_amd import rz
     torch.cuda.init()
-    stream = torch.cuda.current_stream()
-    ctx = rz.Context(0, stream)
+    ctx = rz.Context(0, torch.cuda.current_stream())
     if args.calib_copy:
         src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    alpha, beta, b = workload(args.n, args.p)
-    log(f"setup FP64 problem n={args.n} p={args.p}")
-    t0 = time.perf_counter()
-    pb = rz.Problem(ctx, args.n, args.p, alpha, beta, precision=rz.PREC_F64)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    log(f"setup done in {setup_s:.2f} s; timing {args.steps} FP64 solves")
-    bt = torch.as_tensor(b, device="cuda:0")
-    x = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
-    ms, infos, kt = time_solves(torch, pb, bt, x, args.steps, args.warmup)
-    iters = infos[-1].iters
-    relres = max(i.rel_res for i in infos)
-    # dominant kernel and its roofline (algorithmic bytes / average launch time)
-    kb = kernel_bytes(pb, 8, args.n)
-    dom = max(kt, key=lambda k: kt[k][0])
-    per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}
-    roof = None
-    if dom in kb and kt[dom][1]:
-        ach = kb[dom] / (per_launch[dom] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": MEASURED_TRAFFIC.get(dom) if args.p == 7 and args.n == 32 else None,
-                "kernel": dom,
-                "avg_launch_ms": round(per_launch[dom], 4), "algorithmic_bytes_per_launch": kb[dom]}
-    log(f"FP64 solve {ms:.3f} ms, {iters} iterations; timing the apply")
-    apply64 = time_apply(torch, pb, torch.float64, rz.F64)
-    apply32 = time_apply(torch, pb, torch.float32, rz.F32)
-    out = {
-        "metric": METRIC, "value": round(pb.ndofs / (ms * 1e-3) / 1e9, 5), "unit": "GDoF/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"H(grad) Q_{args.p} on {args.n}^3 uniform hex mesh, cellwise log-uniform "
-                               f"alpha,beta in [1e-2,1e2), U[-1,1) RHS; PCG to rel. residual 1e-8",
-                   "ndofs": pb.ndofs, "nfree": pb.nfree, "cells": pb.ncells, "p": args.p},
-        "pcg_ms_f64": round(ms, 4), "iters_f64": iters, "rel_res_f64": relres,
-        "setup_s_f64": round(setup_s, 3), "omega": pb.omega(),
-        "apply_gdofs_f64": round(pb.ndofs / (apply64 * 1e-3) / 1e9, 2),
-        "apply_gdofs_f32": round(pb.ndofs / (apply32 * 1e-3) / 1e9, 2),
-        "apply_ms_f64": round(apply64, 4), "apply_ms_f32": round(apply32, 4),
-        "kernel_ms_per_step_f64": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
-        "kernel_launches_per_step_f64": {k: v[1] / args.steps for k, v in kt.items()},
-        "roofline": roof,
-    }
-    pb.close()
-    if not args.no_mixed:
-        log("setup mixed-precision problem")
-        t0 = time.perf_counter()
-        pm = rz.Problem(ctx, args.n, args.p, alpha, beta, precision=rz.PREC_MIXED)
+    if args.only:
+        piece = args.only
+        res = {}
+        if piece == "c2":
+            bench_c2(torch, rz, ctx, argparse.Namespace(**{**vars(args), "no_mixed": True}), res)
+        elif piece == "c2-apply":
+            alpha, beta, _ = workload(args.n, args.p)
+            pb = rz.Problem(ctx, args.n, args.p, alpha, beta, omega=0.3)
+            res["apply_ms_f64"] = time_apply(torch, pb, torch.float64, rz.F64, reps=args.steps)
+            res["apply_ms_f32"] = time_apply(torch, pb, torch.float32, rz.F32, reps=args.steps)
+            pb.close()
+        elif piece == "c3":
+            res = bench_c3(torch, rz, ctx, args.steps, args.warmup)
+        elif piece == "c3-apply":
+            pb = rz.Problem(ctx, 16, 6, 1.0, 1.0, space="curl", omega=0.3)
+            res["apply_ms_f64"] = time_apply(torch, pb, torch.float64, rz.F64, reps=args.steps)
+            res["apply_ms_f32"] = time_apply(torch, pb, torch.float32, rz.F32, reps=args.steps)
+            pb.close()
+        elif piece == "c5-apply":
+            import synth
+            v = synth.perturbed_vertices(24, 3)
+            pb = rz.Problem(ctx, 24, 8, synth.c5_coefficient_samples(v, 24), 1.0, vertices=v, omega=0.3)
+            res["apply_ms_f64"] = time_apply(torch, pb, torch.float64, rz.F64, reps=args.steps)
+            res["apply_ms_f32"] = time_apply(torch, pb, torch.float32, rz.F32, reps=args.steps)
+            pb.close()
         torch.cuda.synchronize()
-        out["setup_s_mixed"] = round(time.perf_counter() - t0, 3)
-        msm, infm, ktm = time_solves(torch, pm, bt, x, args.steps, args.warmup)
-        out["pcg_ms_mixed"] = round(msm, 4)
-        out["iters_mixed"] = infm[-1].iters
-        out["rel_res_mixed"] = max(i.rel_res for i in infm)
-        out["kernel_ms_per_step_mixed"] = {k: round(v[0] / args.steps, 4) for k, v in ktm.items()}
-        out["speedup_mixed_vs_f64"] = round(ms / msm, 3)
-        pm.close()
-        log("setup defect-correction problem (FP32 operator)")
-        pd = rz.Problem(ctx, args.n, args.p, alpha, beta, precision=rz.PREC_DEFECT)
-        msd, infd, ktd = time_solves(torch, pd, bt, x, args.steps, args.warmup)
-        out["pcg_ms_defect"] = round(msd, 4)
-        out["iters_defect_inner"] = infd[-1].iters
-        out["rel_res_defect"] = max(i.rel_res for i in infd)
-        out["kernel_ms_per_step_defect"] = {k: round(v[0] / args.steps, 4) for k, v in ktd.items()}
-        out["speedup_defect_vs_f64"] = round(ms / msd, 3)
-        pd.close()
+        rz.close_all()
+        print(json.dumps({"only": piece, **res}), flush=True)
+        return
+    out = {"metric": METRIC, "value": None, "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
+    bench_c2(torch, rz, ctx, args, out)
+    gpu = {}
+    log("C1")
+    out["c1"], gpu["c1"] = bench_c1(torch, rz, ctx)
+    if not args.no_c3:
+        out["c3"] = bench_c3(torch, rz, ctx, max(1, args.steps // 2), 1)
     if not args.no_c5:
         out["c5"] = bench_c5(torch, rz, ctx, max(1, args.steps // 2), 1)
-    if not args.no_c3:
-        out["c3"] = bench_c3(torch, rz, ctx)
     if not args.no_batched:
         out["batched"] = bench_batched(torch, rz)
     if not args.no_cpu_baseline:
+        gpu["small"] = gpu_small_solutions(torch, rz, ctx)
         log("CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(gpu)
     torch.cuda.synchronize()
     rz.close_all()
     print(json.dumps(out), flush=True)

@@ -114,6 +114,10 @@ typedef struct {
   double rel_res;         /* true ||b - A x||_2 / ||b||_2 at exit                     */
   double omega;           /* smoother damping that was used                           */
   double t_solve_ms;      /* device time of the solve (hipEvents on the stream)       */
+  int32_t iters_natural;  /* iterations after which the natural norm (r^T M^{-1} r)^{1/2} *
+                           * of the residual had dropped by rtol, the paper's criterion  *
+                           * (Sec. 5.1); -1 if it did not within the solve (or for the   *
+                           * defect-correction protocol)                                 */
 } rz_solve_info;
 
 /* Fill *o with defaults (space grad, p = 4, FP64, maxit 200, rtol 1e-8, omega 0). */
@@ -224,6 +228,9 @@ rz_status rz_sync(rz_problem *h);
  *   RZ_EXPORT_PATCH_KERNEL int32 pair (FP64, FP32): 1 when the H(grad) patch solve
  *                        keeps a patch's factor in registers between its two sweeps,
  *                        0 when it streams the factor in both sweeps
+ *   RZ_EXPORT_STATS      int64 pair (H(grad)): lower non-zeros (diagonal included)
+ *                        and rows of the IC factors of all non-empty vertex patches
+ *                        (the factor values the patch solve needs, without padding)
  *   RZ_EXPORT_EDGE_PATCH int64: edge id, then the DoFs (ascending) of non-empty
  *                        edge-star patch `index` of H(curl) (or of the NCE_p
  *                        potential problem of H(div)); edge ids run over the axis
@@ -232,7 +239,7 @@ rz_status rz_sync(rz_problem *h);
 enum {
   RZ_EXPORT_DOFMAP = 0, RZ_EXPORT_PATCH = 1, RZ_EXPORT_IC_PATTERN = 2,
   RZ_EXPORT_IC_FACTOR = 3, RZ_EXPORT_TABLES1D = 4, RZ_EXPORT_AUXCOEF = 5,
-  RZ_EXPORT_OMEGA = 6, RZ_EXPORT_PATCH_KERNEL = 7, RZ_EXPORT_EDGE_PATCH = 8
+  RZ_EXPORT_OMEGA = 6, RZ_EXPORT_PATCH_KERNEL = 7, RZ_EXPORT_EDGE_PATCH = 8, RZ_EXPORT_STATS = 9
 };
 rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *bytes);
 

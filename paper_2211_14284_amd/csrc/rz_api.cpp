@@ -741,6 +741,7 @@ rz_status defect_solve(rz_problem *h, const double *b, double *x, rz_solve_info 
     info->rel_res = nb > 0 ? std::sqrt(rr) / nb : 0.0;
     info->omega = h->omega;
     info->t_solve_ms = ms;
+    info->iters_natural = -1;
   }
   return result;
 }
@@ -1806,6 +1807,8 @@ struct PcgRun {
   double *x = nullptr;
   enum Phase { INIT, GOT_BB, GOT_RR, GOT_TR, GOT_FINAL, DONE } phase = INIT;
   int it = 0;
+  double rz0 = 0;           // r.z of the first iteration (natural norm squared)
+  int it_natural = -1;      // first iteration count at which the natural norm had dropped by rtol
   double nb = 0, tol = 0, relres = 0;
   rz_status result = RZ_OK;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1869,6 +1872,7 @@ rz_status pcg_iteration(PcgRun &R, bool first) {
                      h->dots + kSlotRr, s);
   }
   HIPCALL(h, hipMemcpyAsync(h->hdots, h->dots + kSlotPap, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCALL(h, hipMemcpyAsync(h->hdots + 2, rz, sizeof(double), hipMemcpyDeviceToHost, s));
   ++R.it;
   R.phase = PcgRun::GOT_RR;
   return RZ_OK;
@@ -1903,6 +1907,11 @@ rz_status pcg_step(PcgRun &R) {
     }
     case PcgRun::GOT_RR: {
       const double pAp = d[0], rr = d[1];
+      // the paper's criterion (Sec. 5.1): the natural norm (r^T M^{-1} r)^{1/2} of the
+      // residual that started this iteration, against the first one
+      if (R.it == 1) R.rz0 = d[2];
+      if (R.it_natural < 0 && R.it > 1 && std::sqrt(std::fabs(d[2])) <= h->opts.rtol * std::sqrt(std::fabs(R.rz0)))
+        R.it_natural = R.it - 1;
       if (!(pAp > 0)) {
         R.result = fail(h->ctx, RZ_ERR_BREAKDOWN, "CG breakdown: p.Ap <= 0");
         return pcg_final(R);
@@ -1967,6 +1976,7 @@ rz_status pcg_finish(PcgRun &R, rz_solve_info *info) {
     info->rel_res = R.relres;
     info->omega = h->omega;
     info->t_solve_ms = ms;
+    info->iters_natural = R.it_natural;
   }
   return R.result;
 }
@@ -2625,6 +2635,45 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
     case RZ_EXPORT_OMEGA:
       put(&h->omega, sizeof(double));
       break;
+    case RZ_EXPORT_STATS: {
+      // H(grad): lower non-zeros (diagonal included) and rows of the IC factors of all
+      // non-empty vertex patches, without padding or the identity rows of absent DoFs
+      if (h->space != RZ_GRAD) return fail(h->ctx, RZ_ERR_ARG, "statistics of vertex patches: H(grad) only");
+      int64_t nnz = 0, rows = 0;
+      const int nvx = h->nx + 1, nvy = h->ny + 1;
+      for (int64_t vid : h->patch_vids) {
+        const int V[3] = {(int)(vid % nvx), (int)((vid / nvx) % nvy), (int)(vid / ((int64_t)nvx * nvy))};
+        const int nc[3] = {h->nx, h->ny, h->nz};
+        bool inner = true;
+        for (int d = 0; d < 3; ++d) inner = inner && V[d] >= 1 && V[d] <= nc[d] - 1;
+        if (inner) {  // a full star away from the boundary: every row, the whole pattern
+          nnz += h->ps.nnz;
+          rows += h->ps.nrows;
+          continue;
+        }
+        std::vector<int> pres(h->ps.nrows, 0);
+        std::vector<std::array<int, 3>> G(h->ps.nrows);
+        for (int k = 0; k < h->ps.nrows; ++k) {
+          int g3[3];
+          if (patch_row_present(h, vid, k, g3)) {
+            pres[k] = 1;
+            G[k] = {g3[0], g3[1], g3[2]};
+            ++rows;
+          }
+        }
+        for (int r = 0; r < h->ps.nrows; ++r) {
+          if (!pres[r]) continue;
+          for (int k = h->ps.rowptr[r]; k < h->ps.rowptr[r + 1]; ++k) {
+            const int c = h->ps.col[k];
+            if (!pres[c]) continue;
+            if (r == c || patch_entry_allowed(h, vid, G[r].data(), G[c].data())) ++nnz;
+          }
+        }
+      }
+      const int64_t v[2] = {nnz, rows};
+      put(v, sizeof v);
+      break;
+    }
     case RZ_EXPORT_EDGE_PATCH: {
       if (h->space == RZ_GRAD) return fail(h->ctx, RZ_ERR_ARG, "edge patches exist for H(curl) / H(div) only");
       if (index < 0 || index >= (int64_t)h->edge_ids.size()) return fail(h->ctx, RZ_ERR_ARG, "bad patch index");

@@ -27,7 +27,7 @@ COEF_CONST, COEF_CELL, COEF_SAMPLES = 0, 1, 2
 PREC_F64, PREC_MIXED, PREC_DEFECT = 0, 1, 2
 EXPORT_DOFMAP, EXPORT_PATCH, EXPORT_IC_PATTERN, EXPORT_IC_FACTOR = 0, 1, 2, 3
 EXPORT_TABLES1D, EXPORT_AUXCOEF, EXPORT_OMEGA, EXPORT_PATCH_KERNEL = 4, 5, 6, 7
-EXPORT_EDGE_PATCH = 8
+EXPORT_EDGE_PATCH, EXPORT_STATS = 8, 9
 KERNELS = ("apply", "condense", "patch", "expand", "transfer", "coarse", "krylov")
 STATUS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_OOM", -3: "RZ_ERR_BREAKDOWN",
           -4: "RZ_ERR_NOT_CONVERGED", -5: "RZ_ERR_HIP", -6: "RZ_ERR_SINGULAR", -7: "RZ_ERR_NODEVICE"}
@@ -57,7 +57,7 @@ class Opts(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_res", ctypes.c_double),
-                ("omega", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+                ("omega", ctypes.c_double), ("t_solve_ms", ctypes.c_double), ("iters_natural", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -298,6 +298,12 @@ class Problem:
         NCE_p potential problem)."""
         v = self._export(EXPORT_EDGE_PATCH, k, dtype=np.int64)
         return int(v[0]), v[1:]
+
+    def stats(self):
+        """{factor_nnz, patch_rows}: lower non-zeros and rows of the IC factors of all
+        non-empty vertex patches (H(grad))."""
+        v = self._export(EXPORT_STATS, dtype=np.int64)
+        return {"factor_nnz": int(v[0]), "patch_rows": int(v[1])}
 
     def ic_pattern(self, k):
         return self._export(EXPORT_IC_PATTERN, k, dtype=np.int32).reshape(-1, 2)
