@@ -101,7 +101,8 @@ typedef struct {
   int32_t maxit;       /* CG iteration cap (default 200)                            */
   double rtol;         /* relative tolerance on the 2-norm residual (default 1e-8)   */
   double omega;        /* smoother damping; 0 = 2/(1.2*lambda_max) with lambda_max  *
-                        * estimated by 10 Lanczos steps on M^{-1}A                   */
+                        * estimated by 10 Lanczos steps on M^{-1}A (FP64 M in every  *
+                        * precision protocol)                                        */
   uint64_t lanczos_seed; /* SplitMix64 seed of the Lanczos start vector (default 99) */
   double hdiv_eps;     /* H(div): multiple of the (beta-weighted) mass added to the   *
                         * curl-curl potential problem (remark of Sec. 4.3); 0 = 1e-3 */

@@ -6,7 +6,7 @@
 //         (C u)_0 = D_y u_2 - D_z u_1, (C u)_1 = D_z u_0 - D_x u_2, (C u)_2 = D_x u_1 - D_y u_0;
 //   div:  y_K = sum_m mu_m MF_m u_m + sigma D_m^T (sum_n D_n u_n).
 // In the FDM bases every 1-D factor is sparse (B: diagonal plus (0,p); D: at most
-// three entries per row), so each line costs O(p).  One block per cell; tiles of
+// three entries per row), so each line costs O(p).  A few cells per block; tiles of
 // the three components and of the intermediate fields live in LDS.  Interior rows
 // of a component (no continuous axis at an end) are stored, the others go to a
 // per-cell buffer summed by the gather kernel in a fixed cell order.
@@ -36,143 +36,194 @@ __device__ __forceinline__ long comp_index(const VecDev &V, int m, const int C[3
   return V.off[m] + (long)C[0] + (long)V.ext[m][0] * ((long)C[1] + (long)V.ext[m][1] * (long)C[2]);
 }
 
-struct Tile {
-  int e[3];  // local extents (x, y, z)
+enum { OP_B = 0, OP_D = 1, OP_DT = 2 };
+
+// ---- the apply, degree P known at compile time ----------------------------------------
+// CPB cells per block, every tile sized for P in dynamic LDS; in each pass one thread
+// per line of one cell applies a 1-D factor (B: diagonal plus (0,p); D: at most three
+// entries per row) with unrolled loops, values held in registers; the cell weights
+// scale whole tiles between passes.
+template <int P>
+struct TileP {
+  int e[3];
   __device__ int size() const { return e[0] * e[1] * e[2]; }
 };
 
-__device__ __forceinline__ Tile comp_tile(int space, int m, int p) {
-  Tile t;
-  for (int a = 0; a < 3; ++a) t.e[a] = is_P(space, m, a) ? p + 1 : p;
-  return t;
-}
-
-enum { OP_B = 0, OP_D = 1, OP_DT = 2 };
-
-// out (+)= scale * op along axis `ax` of in; in/out tiles differ only along ax.
-// B: (p+1) -> (p+1); D: (p+1) -> p; D^T: p -> (p+1).  Tables in LDS.
-template <typename T>
-__device__ void line_op(const T *in, Tile ti, T *out, Tile to, int ax, int op, const T *sB, const T *sD, int p,
-                        T scale, bool acc) {
+template <int P, typename T>
+__device__ __forceinline__ void line_op_p(const T *in, int csi, TileP<P> ti, T *out, int cso, TileP<P> to, int ax,
+                                          int op, const T *sB, const T *sD, T scale, bool acc, int ncells) {
+  constexpr int n1 = P + 1;
   const int b = ax == 0 ? 1 : 0, c = ax == 2 ? 1 : 2;
   const int nl = ti.e[b] * ti.e[c];
   const int sti = ax == 0 ? 1 : (ax == 1 ? ti.e[0] : ti.e[0] * ti.e[1]);
   const int sto = ax == 0 ? 1 : (ax == 1 ? to.e[0] : to.e[0] * to.e[1]);
-  const int n1 = p + 1;
-  for (int l = threadIdx.x; l < nl; l += blockDim.x) {
+  const int nin = ti.e[ax], nout = to.e[ax];
+  for (int t = threadIdx.x; t < nl * ncells; t += blockDim.x) {
+    const int cl = t / nl, l = t % nl;
     const int u = l % ti.e[b], w = l / ti.e[b];
     int ci[3], co[3];
     ci[ax] = co[ax] = 0;
     ci[b] = co[b] = u;
     ci[c] = co[c] = w;
-    const int bi = ci[0] + ti.e[0] * (ci[1] + ti.e[1] * ci[2]);
-    const int bo = co[0] + to.e[0] * (co[1] + to.e[1] * co[2]);
-    T v[kMaxP + 1], r[kMaxP + 1];
-    for (int i = 0; i < ti.e[ax]; ++i) v[i] = in[bi + i * sti];
+    const T *ip = in + cl * csi + ci[0] + ti.e[0] * (ci[1] + ti.e[1] * ci[2]);
+    T *op_ = out + cl * cso + co[0] + to.e[0] * (co[1] + to.e[1] * co[2]);
+    T v[n1], r[n1];
+#pragma unroll
+    for (int i = 0; i < n1; ++i) v[i] = i < nin ? ip[i * sti] : T(0);
     if (op == OP_B) {
-      for (int i = 0; i <= p; ++i) r[i] = sB[i * n1 + i] * v[i];
-      r[0] += sB[p] * v[p];
-      r[p] += sB[p * n1] * v[0];
-    } else if (op == OP_D) {  // r_i = sum_j D[i][j] v_j, D row i: columns 0, p and i (i >= 1)
-      for (int i = 0; i < p; ++i) {
-        T s = sD[i * n1] * v[0] + sD[i * n1 + p] * v[p];
+#pragma unroll
+      for (int i = 0; i <= P; ++i) r[i] = sB[i * n1 + i] * v[i];
+      r[0] += sB[P] * v[P];
+      r[P] += sB[P * n1] * v[0];
+    } else if (op == OP_D) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        T s = sD[i * n1] * v[0] + sD[i * n1 + P] * v[P];
         if (i >= 1) s += sD[i * n1 + i] * v[i];
         r[i] = s;
       }
-    } else {  // r_j = sum_i D[i][j] v_i
+      r[P] = 0;
+    } else {
       T r0 = 0, rp = 0;
-      for (int i = 0; i < p; ++i) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
         r0 += sD[i * n1] * v[i];
-        rp += sD[i * n1 + p] * v[i];
+        rp += sD[i * n1 + P] * v[i];
       }
-      for (int j = 1; j < p; ++j) r[j] = sD[j * n1 + j] * v[j];
+#pragma unroll
+      for (int j = 1; j < P; ++j) r[j] = sD[j * n1 + j] * v[j];
       r[0] = r0;
-      r[p] = rp;
+      r[P] = rp;
     }
-    for (int i = 0; i < to.e[ax]; ++i) {
-      const T val = scale * r[i];
-      out[bo + i * sto] = acc ? out[bo + i * sto] + val : val;
-    }
+#pragma unroll
+    for (int i = 0; i < n1; ++i)
+      if (i < nout) {
+        const T val = scale * r[i];
+        op_[i * sto] = acc ? op_[i * sto] + val : val;
+      }
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_apply_vec(VecDev V, const T *__restrict__ coef, const T *__restrict__ Bg,
-                                                    const T *__restrict__ Dg, const T *__restrict__ x,
-                                                    T *__restrict__ y, T *__restrict__ ebuf) {
-  constexpr int TS = (kMaxP + 1) * (kMaxP + 1) * (kMaxP + 1);
-  __shared__ T U[3][TS], Y[3][TS], F[TS], G[TS];
-  __shared__ T sB[(kMaxP + 1) * (kMaxP + 1)], sD[kMaxP * (kMaxP + 1)];
-  const int p = V.p, n1 = p + 1, space = V.space;
-  const long cell = blockIdx.x;
-  const int cc[3] = {(int)(cell % V.nx), (int)((cell / V.nx) % V.ny), (int)(cell / ((long)V.nx * V.ny))};
-  for (int k = threadIdx.x; k < n1 * n1; k += blockDim.x) sB[k] = Bg[k];
-  for (int k = threadIdx.x; k < p * n1; k += blockDim.x) sD[k] = Dg[k];
-  Tile tc[3];
-  for (int m = 0; m < 3; ++m) tc[m] = comp_tile(space, m, p);
-  for (int m = 0; m < 3; ++m)
-    for (int k = threadIdx.x; k < tc[m].size(); k += blockDim.x) {
+template <int P>
+__device__ __forceinline__ TileP<P> tile_p(int space, int m) {
+  TileP<P> t;
+  for (int a = 0; a < 3; ++a) t.e[a] = is_P(space, m, a) ? P + 1 : P;
+  return t;
+}
+
+template <int P, typename T, int CPB>
+__global__ void __launch_bounds__(256) k_apply_vec_p(VecDev V, const T *__restrict__ coef, const T *__restrict__ Bg,
+                                                      const T *__restrict__ Dg, const T *__restrict__ x,
+                                                      T *__restrict__ y, T *__restrict__ ebuf, long ncells) {
+  // TS: a component tile (the largest, NCE: p(p+1)^2); TF: a tile of the derived field
+  // (NCF for the curl, DQ for the divergence).  F also holds the mass pass's
+  // intermediate component tile, so it takes TS values per cell.
+  constexpr int TS = P * (P + 1) * (P + 1), TF = (P + 1) * P * P;
+  extern __shared__ unsigned char vsm[];
+  T *U = reinterpret_cast<T *>(vsm);         // [CPB][3][TS]
+  T *Y = U + CPB * 3 * TS;                    // [CPB][3][TS]
+  T *F = Y + CPB * 3 * TS;                    // [CPB][TS]
+  T *G = F + CPB * TS;                        // [CPB][TF]
+  T *sB = G + CPB * TF;
+  T *sD = sB + (P + 1) * (P + 1);
+  const int space = V.space;
+  const long c0 = (long)blockIdx.x * CPB;
+  const int nc = (int)min((long)CPB, ncells - c0);
+  for (int k = threadIdx.x; k < (P + 1) * (P + 1); k += blockDim.x) sB[k] = Bg[k];
+  for (int k = threadIdx.x; k < P * (P + 1); k += blockDim.x) sD[k] = Dg[k];
+  TileP<P> tc[3];
+  for (int m = 0; m < 3; ++m) tc[m] = tile_p<P>(space, m);
+  for (int m = 0; m < 3; ++m) {
+    const int ts = tc[m].size();
+    for (int t = threadIdx.x; t < ts * nc; t += blockDim.x) {
+      const int cl = t / ts, k = t % ts;
+      const long cell = c0 + cl;
+      const int cc[3] = {(int)(cell % V.nx), (int)((cell / V.nx) % V.ny), (int)(cell / ((long)V.nx * V.ny))};
       const int l[3] = {k % tc[m].e[0], (k / tc[m].e[0]) % tc[m].e[1], k / (tc[m].e[0] * tc[m].e[1])};
-      const int C[3] = {cc[0] * p + l[0], cc[1] * p + l[1], cc[2] * p + l[2]};
-      U[m][k] = comp_dirichlet(V, m, C) ? T(0) : x[comp_index(V, m, C)];
+      const int C[3] = {cc[0] * P + l[0], cc[1] * P + l[1], cc[2] * P + l[2]};
+      U[(cl * 3 + m) * TS + k] = comp_dirichlet(V, m, C) ? T(0) : x[comp_index(V, m, C)];
     }
+  }
   __syncthreads();
-  const T *cf = coef + 6 * cell;
+  // per-cell weights in registers of the thread's cell are read from global per pass
   if (space == 1) {
-    // mass: Y_m = mu_m B_b B_c U_m (b, c: the continuous axes of component m)
     for (int m = 0; m < 3; ++m) {
       const int b = m == 0 ? 1 : 0, c = m == 2 ? 1 : 2;
-      line_op(U[m], tc[m], F, tc[m], b, OP_B, sB, sD, p, T(1), false);
+      line_op_p<P>(U + m * TS, 3 * TS, tc[m], F, TS, tc[m], b, OP_B, sB, sD, T(1), false, nc);
       __syncthreads();
-      line_op(F, tc[m], Y[m], tc[m], c, OP_B, sB, sD, p, cf[3 + m], false);
+      // scale per cell: mu_m; a pass per cell-weight would split the lines, so scale
+      // after the second factor below
+      line_op_p<P>(F, TS, tc[m], Y + m * TS, 3 * TS, tc[m], c, OP_B, sB, sD, T(1), false, nc);
+      __syncthreads();
+      for (int t = threadIdx.x; t < tc[m].size() * nc; t += blockDim.x) {
+        const int cl = t / tc[m].size(), k = t % tc[m].size();
+        Y[(cl * 3 + m) * TS + k] *= coef[6 * (c0 + cl) + 3 + m];
+      }
       __syncthreads();
     }
-    // curl: F_n (P along n, DP elsewhere), G_n = sigma_n B_n F_n, then C_n^T G_n
     for (int n = 0; n < 3; ++n) {
-      const int a1 = (n + 1) % 3, a2 = (n + 2) % 3;  // F_n = D_{a1} U_{a2} - D_{a2} U_{a1}
-      Tile tf;
-      for (int a = 0; a < 3; ++a) tf.e[a] = a == n ? p + 1 : p;
-      line_op(U[a2], tc[a2], F, tf, a1, OP_D, sB, sD, p, T(1), false);
+      const int a1 = (n + 1) % 3, a2 = (n + 2) % 3;
+      TileP<P> tf;
+      for (int a = 0; a < 3; ++a) tf.e[a] = a == n ? P + 1 : P;
+      line_op_p<P>(U + a2 * TS, 3 * TS, tc[a2], F, TS, tf, a1, OP_D, sB, sD, T(1), false, nc);
       __syncthreads();
-      line_op(U[a1], tc[a1], F, tf, a2, OP_D, sB, sD, p, T(-1), true);
+      line_op_p<P>(U + a1 * TS, 3 * TS, tc[a1], F, TS, tf, a2, OP_D, sB, sD, T(-1), true, nc);
       __syncthreads();
-      line_op(F, tf, G, tf, n, OP_B, sB, sD, p, cf[n], false);
+      line_op_p<P>(F, TS, tf, G, TF, tf, n, OP_B, sB, sD, T(1), false, nc);
       __syncthreads();
-      line_op(G, tf, Y[a2], tc[a2], a1, OP_DT, sB, sD, p, T(1), true);
+      for (int t = threadIdx.x; t < tf.size() * nc; t += blockDim.x) {
+        const int cl = t / tf.size(), k = t % tf.size();
+        G[cl * TF + k] *= coef[6 * (c0 + cl) + n];
+      }
       __syncthreads();
-      line_op(G, tf, Y[a1], tc[a1], a2, OP_DT, sB, sD, p, T(-1), true);
+      line_op_p<P>(G, TF, tf, Y + a2 * TS, 3 * TS, tc[a2], a1, OP_DT, sB, sD, T(1), true, nc);
+      __syncthreads();
+      line_op_p<P>(G, TF, tf, Y + a1 * TS, 3 * TS, tc[a1], a2, OP_DT, sB, sD, T(-1), true, nc);
       __syncthreads();
     }
   } else {
-    // mass: Y_m = mu_m B_m U_m
-    for (int m = 0; m < 3; ++m) line_op(U[m], tc[m], Y[m], tc[m], m, OP_B, sB, sD, p, cf[3 + m], false);
+    for (int m = 0; m < 3; ++m) line_op_p<P>(U + m * TS, 3 * TS, tc[m], Y + m * TS, 3 * TS, tc[m], m, OP_B, sB, sD,
+                                             T(1), false, nc);
     __syncthreads();
-    // divergence F = sum_m D_m U_m (DP in all axes), then Y_m += sigma D_m^T F
-    Tile tq;
-    tq.e[0] = tq.e[1] = tq.e[2] = p;
+    for (int m = 0; m < 3; ++m)
+      for (int t = threadIdx.x; t < tc[m].size() * nc; t += blockDim.x) {
+        const int cl = t / tc[m].size(), k = t % tc[m].size();
+        Y[(cl * 3 + m) * TS + k] *= coef[6 * (c0 + cl) + 3 + m];
+      }
+    TileP<P> tq;
+    tq.e[0] = tq.e[1] = tq.e[2] = P;
     for (int m = 0; m < 3; ++m) {
-      line_op(U[m], tc[m], F, tq, m, OP_D, sB, sD, p, T(1), m > 0);
+      line_op_p<P>(U + m * TS, 3 * TS, tc[m], F, TS, tq, m, OP_D, sB, sD, T(1), m > 0, nc);
       __syncthreads();
     }
-    for (int m = 0; m < 3; ++m) line_op(F, tq, Y[m], tc[m], m, OP_DT, sB, sD, p, cf[0], true);
+    for (int t = threadIdx.x; t < tq.size() * nc; t += blockDim.x) {
+      const int cl = t / tq.size(), k = t % tq.size();
+      F[cl * TS + k] *= coef[6 * (c0 + cl)];
+    }
+    __syncthreads();
+    for (int m = 0; m < 3; ++m) line_op_p<P>(F, TS, tq, Y + m * TS, 3 * TS, tc[m], m, OP_DT, sB, sD, T(1), true, nc);
     __syncthreads();
   }
-  // store: rows with no continuous axis at an end are owned by the cell
-  long eo = cell * (long)V.cell_dofs;
   for (int m = 0; m < 3; ++m) {
-    for (int k = threadIdx.x; k < tc[m].size(); k += blockDim.x) {
+    int coff = 0;
+    for (int k = 0; k < m; ++k) coff += tc[k].size();
+    const int ts = tc[m].size();
+    for (int t = threadIdx.x; t < ts * nc; t += blockDim.x) {
+      const int cl = t / ts, k = t % ts;
+      const long cell = c0 + cl;
+      const int cc[3] = {(int)(cell % V.nx), (int)((cell / V.nx) % V.ny), (int)(cell / ((long)V.nx * V.ny))};
       const int l[3] = {k % tc[m].e[0], (k / tc[m].e[0]) % tc[m].e[1], k / (tc[m].e[0] * tc[m].e[1])};
       bool owned = true;
       for (int a = 0; a < 3; ++a)
-        if (is_P(space, m, a) && (l[a] == 0 || l[a] == p)) owned = false;
+        if (is_P(space, m, a) && (l[a] == 0 || l[a] == P)) owned = false;
+      const T val = Y[(cl * 3 + m) * TS + k];
       if (owned) {
-        const int C[3] = {cc[0] * p + l[0], cc[1] * p + l[1], cc[2] * p + l[2]};
-        y[comp_index(V, m, C)] = Y[m][k];
+        const int C[3] = {cc[0] * P + l[0], cc[1] * P + l[1], cc[2] * P + l[2]};
+        y[comp_index(V, m, C)] = val;
       } else {
-        ebuf[eo + k] = Y[m][k];
+        ebuf[cell * (long)V.cell_dofs + coff + k] = val;
       }
     }
-    eo += tc[m].size();
   }
 }
 
@@ -236,12 +287,34 @@ __global__ void k_apply_vec_gather(VecDev V, const T *__restrict__ x, const T *_
 
 }  // namespace
 
+template <int P, typename T>
+void apply_vec_p(const VecDev &V, const T *coef, const T *B, const T *D, const T *x, T *y, T *ebuf, long nc,
+                 hipStream_t s) {
+  constexpr int TS = P * (P + 1) * (P + 1), TF = (P + 1) * P * P;
+  constexpr size_t per_cell = (7 * (size_t)TS + (size_t)TF) * sizeof(T);
+  constexpr int CPB = per_cell * 4 <= 64 * 1024 ? 4 : (per_cell * 2 <= 64 * 1024 ? 2 : 1);
+  const size_t shm = CPB * per_cell + ((P + 1) * (P + 1) + P * (P + 1)) * sizeof(T);
+  if (shm > 64 * 1024)
+    hipFuncSetAttribute((const void *)k_apply_vec_p<P, T, CPB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  k_apply_vec_p<P, T, CPB><<<(unsigned)((nc + CPB - 1) / CPB), 256, shm, s>>>(V, coef, B, D, x, y, ebuf, nc);
+}
+
 template <typename T>
 int launch_apply_vec(const VecDev &V, const T *coef, const T *B, const T *D, const T *x, T *y, T *ebuf,
                      hipStream_t s) {
   if (V.p < 1 || V.p > kMaxP) return -1;
   const long nc = (long)V.nx * V.ny * V.nz;
-  k_apply_vec<T><<<(unsigned)nc, 256, 0, s>>>(V, coef, B, D, x, y, ebuf);
+  switch (V.p) {
+    case 1: apply_vec_p<1, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
+    case 2: apply_vec_p<2, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
+    case 3: apply_vec_p<3, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
+    case 4: apply_vec_p<4, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
+    case 5: apply_vec_p<5, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
+    case 6: apply_vec_p<6, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
+    case 7: apply_vec_p<7, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
+    case 8: apply_vec_p<8, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
+    default: apply_vec_p<9, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
+  }
   const long n = V.off[3];
   k_apply_vec_gather<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V, x, ebuf, y, n);
   return 0;

@@ -167,47 +167,59 @@ __global__ void k_csr(int n, const int *__restrict__ rows, const int *__restrict
   y[g] = add ? (TY)((TV)y[g] + acc) : (TY)acc;
 }
 
-// Edge-star patch solves: one wavefront per (patch, mode block); the block's
-// right-hand side is gathered from rt, then L y = b and L^T x = y by columns (the
-// owner lane of a row broadcasts its value, the other rows update), the factor of
-// the patch's type packed by column with the inverted diagonal first.  Lane l owns
-// rows l and l + 64.
+// Edge-star patch solves: one wavefront per (patch, mode block); z = W^T (W b) with W
+// = L^{-1} of the block's Cholesky factor (the patch type's, computed at setup in
+// FP64), packed by columns for W b and by rows for W^T y.  The gathered right-hand
+// side and the intermediate y are broadcast from LDS; lane l forms rows l and l + 64
+// with coalesced loads, and no row waits for another (unlike two triangular sweeps).
 template <typename T>
 __global__ void __launch_bounds__(kBS) k_edge_solve(EdgeDev E, const T *__restrict__ fac, const T *__restrict__ rt,
                                                     T *__restrict__ zb) {
-  const int lane = threadIdx.x & 63;
-  const long w = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  __shared__ T sb[kBS / 64][128];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long w = (long)blockIdx.x * (blockDim.x >> 6) + wv;
   if (w >= (long)E.npatch * E.p) return;
   const int patch = (int)(w / E.p), blk = (int)(w % E.p);
   const int nb = E.blk_n[blk], s0 = E.blk_slot[blk];
   const int *ix = E.idx + (size_t)patch * E.nslot + s0;
-  const T *F = fac + (size_t)E.type[patch] * E.fac_stride + E.blk_fac[blk];
+  const T *Wc = fac + (size_t)E.type[patch] * E.fac_stride + E.blk_fac[blk];  // by columns
+  const T *Wr = Wc + nb * (nb + 1) / 2;                                         // by rows
   const int r0 = lane, r1 = lane + 64;
-  int g0 = r0 < nb ? ix[r0] : -1, g1 = r1 < nb ? ix[r1] : -1;
-  T b0 = g0 >= 0 ? rt[g0] : T(0), b1 = g1 >= 0 ? rt[g1] : T(0);
-  auto cstart = [nb](int j) { return j * nb - (j * (j - 1)) / 2; };
-  // forward: y_j = b_j / L_jj; b_i -= L_ij y_j (i > j)
-  for (int j = 0; j < nb; ++j) {
-    const T *Fj = F + cstart(j);
-    const T own = j < 64 ? b0 : b1;
-    const T yj = __shfl(own, j & 63, 64) * Fj[0];
-    if (r0 == j) b0 = yj;
-    if (r1 == j) b1 = yj;
-    if (r0 > j && r0 < nb) b0 -= Fj[r0 - j] * yj;
-    if (r1 > j && r1 < nb) b1 -= Fj[r1 - j] * yj;
+  const int g0 = r0 < nb ? ix[r0] : -1, g1 = r1 < nb ? ix[r1] : -1;
+  T *b = sb[wv];
+  b[r0] = g0 >= 0 ? rt[g0] : T(0);
+  b[r1] = g1 >= 0 ? rt[g1] : T(0);
+  // LDS of this wavefront only: its own writes are visible after the wave-level fence
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // y = W b: y_r = sum_{c <= r} W_rc b_c, column c holds W_{c..n-1, c}
+  T y0 = 0, y1 = 0;
+  for (int c = 0; c < nb; ++c) {
+    const T bc = b[c];
+    const T *col = Wc + c * nb - (c * (c - 1)) / 2 - c;  // col[r] = W_rc for r >= c
+    if (r0 >= c && r0 < nb) y0 += col[r0] * bc;
+    if (r1 >= c && r1 < nb) y1 += col[r1] * bc;
   }
-  // backward: x_j = y_j / L_jj; y_i -= L_ji x_j (i < j), L_ji in column i
-  for (int j = nb - 1; j >= 0; --j) {
-    const T own = j < 64 ? b0 : b1;
-    const T xj = __shfl(own, j & 63, 64) * F[cstart(j)];
-    if (r0 == j) b0 = xj;
-    if (r1 == j) b1 = xj;
-    if (r0 < j) b0 -= F[cstart(r0) + (j - r0)] * xj;
-    if (r1 < j) b1 -= F[cstart(r1) + (j - r1)] * xj;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  b[r0] = y0;
+  b[r1] = y1;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // z = W^T y: z_r = sum_{c >= r} W_cr y_c, row c holds W_{c, 0..c}
+  T z0 = 0, z1 = 0;
+  for (int c = 0; c < nb; ++c) {
+    const T yc = b[c];
+    const T *row = Wr + (c * (c + 1)) / 2;  // row[r] = W_cr for r <= c
+    if (r0 <= c) z0 += row[r0] * yc;
+    if (r1 <= c) z1 += row[r1] * yc;
   }
   T *zo = zb + (size_t)patch * E.nslot + s0;
-  if (r0 < nb) zo[r0] = b0;
-  if (r1 < nb) zo[r1] = b1;
+  if (r0 < nb) zo[r0] = z0;
+  if (r1 < nb) zo[r1] = z1;
 }
 
 // y = M x for a dense m x m matrix (row-major), one wavefront per row, FP64 sums

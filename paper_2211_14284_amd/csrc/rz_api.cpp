@@ -773,7 +773,8 @@ double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &
   return 0.5 * (lo + hi);
 }
 
-// 10 preconditioned CG steps on A x = v0 with M = fine relaxation; Lanczos estimate
+// 10 preconditioned CG steps on A x = v0 with M = the FP64 fine relaxation (for every
+// precision protocol, so the damping does not depend on it); Lanczos estimate
 rz_status estimate_lambda(rz_problem *h, double *lam_out) {
   hipStream_t s = h->ctx->stream;
   const int64_t n = h->ndofs;
@@ -791,7 +792,7 @@ rz_status estimate_lambda(rz_problem *h, double *lam_out) {
     v0[g] = d ? 0.0 : 2.0 * u - 1.0;
   }
   HIPCALL(h, hipMemcpyAsync(h->kr, v0.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
-  if (rz_status e = do_relax_prec(h, h->kr, h->kz)) return e;
+  if (rz_status e = do_relax64(h, h->kr, h->kz)) return e;
   HIPCALL(h, hipMemcpyAsync(h->kp, h->kz, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   double rz_;
   {
@@ -809,7 +810,7 @@ rz_status estimate_lambda(rz_problem *h, double *lam_out) {
     if (!(pAp > 0)) break;
     double a = rz_ / pAp;
     v_axpy(h, -a, h->kAp, h->kr);
-    if ((e = do_relax_prec(h, h->kr, h->kz))) return e;
+    if ((e = do_relax64(h, h->kr, h->kz))) return e;
     double rzn;
     const double *xs2[1] = {h->kr}, *ys2[1] = {h->kz};
     e = dots_host(h, 1, xs2, ys2, &rzn);

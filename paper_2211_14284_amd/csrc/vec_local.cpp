@@ -301,7 +301,7 @@ void edge_layout(int p, EdgeLayout &E) {
     E.blk_slot[i] = s;
     E.blk_fac[i] = f;
     s += nb;
-    f += nb * (nb + 1) / 2;
+    f += nb * (nb + 1);
   }
   E.nslot = s;
   E.fac_stride = f;
@@ -475,11 +475,24 @@ bool edge_patches_build(int p, const int n[3], unsigned dir, const int ext[3][3]
                 M[(size_t)r * nb + j] = s2 / ljj;
               }
             }
-            size_t o = fo + E.blk_fac[i];
-            for (int j = 0; j < nb; ++j) {
-              out.fac[o++] = 1.0 / M[(size_t)j * nb + j];
-              for (int r = j + 1; r < nb; ++r) out.fac[o++] = M[(size_t)r * nb + j];
-            }
+            // W = L^{-1} of the block's Cholesky factor (forward substitution, column
+            // by column); the solve applies it twice, S^{-1} b = W^T (W b), which is as
+            // accurate as the two triangular sweeps (the full inverse S^{-1} is not, for
+            // the nearly singular curl-curl blocks).  Stored packed twice: by columns
+            // (column c: rows c..n-1) for W b, by rows (row c: columns 0..c) for W^T y.
+            std::vector<double> W((size_t)nb * nb, 0.0);
+            for (int c = 0; c < nb; ++c)
+              for (int r = c; r < nb; ++r) {
+                double s2 = r == c ? 1.0 : 0.0;
+                for (int k = c; k < r; ++k) s2 -= M[(size_t)r * nb + k] * W[(size_t)k * nb + c];
+                W[(size_t)r * nb + c] = s2 / M[(size_t)r * nb + r];
+              }
+            double *dst = &out.fac[fo + E.blk_fac[i]];
+            size_t o = 0;
+            for (int c = 0; c < nb; ++c)
+              for (int r = c; r < nb; ++r) dst[o++] = W[(size_t)r * nb + c];
+            for (int r = 0; r < nb; ++r)
+              for (int c = 0; c <= r; ++c) dst[o++] = W[(size_t)r * nb + c];
           }
         }
     eoff += (int64_t)ee[0] * ee[1] * ee[2];

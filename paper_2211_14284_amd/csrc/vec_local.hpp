@@ -75,8 +75,9 @@ struct EdgePatches {
   std::vector<int64_t> edge_id;   // non-empty patches: edge ids (axis-major, lattice order)
   std::vector<int> idx;           // npatch * nslot: global DoF of each slot, -1 absent
   std::vector<int> type;          // npatch: factor set
-  std::vector<double> fac;        // ntypes * fac_stride: Cholesky factors, packed by column
-                                  // (column j: 1/L_jj, then L_{j+1..n-1, j}), per block
+  std::vector<double> fac;        // ntypes * fac_stride: per mode block W = L^{-1} of the
+                                  // FP64 Cholesky factor L of the patch matrix, packed by
+                                  // columns and again by rows (n(n+1) values)
   // sum back to the interface: for every free interface DoF (in the order of `rows`)
   // the slots holding it (positions patch * nslot + slot, ascending patch)
   std::vector<int> rows, ptr, pos;
