@@ -114,9 +114,9 @@ def test_full_size_apply_sampled(setup):
     yh, y32h = y.cpu().numpy(), y32.double().cpu().numpy()
     for c0 in CELLS + RNG_CELLS:
         g, yr = _oracle_apply(c0, x, al, be)
-        d = np.linalg.norm(yh[g] - yr) / np.linalg.norm(yr)
+        d = max(np.linalg.norm(yh[g] - yr) / np.linalg.norm(yr), np.abs(yh[g] - yr).max() / np.abs(yr).max())
         assert d < 1e-12, (c0, d)
-        d32 = np.linalg.norm(y32h[g] - yr) / np.linalg.norm(yr)
+        d32 = max(np.linalg.norm(y32h[g] - yr) / np.linalg.norm(yr), np.abs(y32h[g] - yr).max() / np.abs(yr).max())
         assert d32 < 1e-5, (c0, d32)
 
 
@@ -134,9 +134,11 @@ def test_full_size_relax_sampled(setup):
         g, zr = _oracle_relax(c0, r, al, be)
         free = ~_global_dirichlet(g)
         assert np.array_equal(zh[g[~free]], r[g[~free]])   # identity rows
-        d = np.linalg.norm(zh[g[free]] - zr[free]) / np.linalg.norm(zr[free])
+        d = max(np.linalg.norm(zh[g[free]] - zr[free]) / np.linalg.norm(zr[free]),
+                np.abs(zh[g[free]] - zr[free]).max() / np.abs(zr[free]).max())
         assert d < 1e-12, (c0, d)
-        d32 = np.linalg.norm(z32h[g[free]] - zr[free]) / np.linalg.norm(zr[free])
+        d32 = max(np.linalg.norm(z32h[g[free]] - zr[free]) / np.linalg.norm(zr[free]),
+                  np.abs(z32h[g[free]] - zr[free]).max() / np.abs(zr[free]).max())
         assert d32 < 1e-4, (c0, d32)
 
 

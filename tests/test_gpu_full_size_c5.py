@@ -102,7 +102,9 @@ def test_c5_apply_sampled(setup):
     for c0 in CELLS:
         g, yr = _oracle_apply(c0, x, v, a, b)
         assert np.linalg.norm(yh[g] - yr) < 1e-12 * np.linalg.norm(yr), c0
+        assert np.abs(yh[g] - yr).max() < 1e-12 * np.abs(yr).max(), c0
         assert np.linalg.norm(y32h[g] - yr) < 1e-5 * np.linalg.norm(yr), c0
+        assert np.abs(y32h[g] - yr).max() < 1e-5 * np.abs(yr).max(), c0
 
 
 def test_c5_relax_sampled(setup):
@@ -117,6 +119,7 @@ def test_c5_relax_sampled(setup):
         g, zr = _oracle_relax(c0, r, v, a, b)
         free = ~_global_dirichlet(g)
         assert np.linalg.norm(zh[g[free]] - zr[free]) < 1e-12 * np.linalg.norm(zr[free]), c0
+        assert np.abs(zh[g[free]] - zr[free]).max() < 1e-12 * np.abs(zr[free]).max(), c0
 
 
 def test_c5_solve_residual(setup):

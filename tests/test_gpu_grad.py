@@ -36,7 +36,11 @@ def ctx(rz):
 
 
 def rel(a, b):
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+    """Relative error, the larger of the 2-norm one and the per-entry one
+    (max |a - b| / max |b|), so that one wrong entry cannot hide in the norm."""
+    nb = max(np.linalg.norm(b), 1e-300)
+    mb = max(np.abs(b).max(initial=0.0), 1e-300)
+    return max(np.linalg.norm(a - b) / nb, np.abs(a - b).max(initial=0.0) / mb)
 
 
 def T(x, dtype=torch.float64):
