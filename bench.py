@@ -160,6 +160,8 @@ def bench_c2(torch, rz, ctx, args, out):
         "apply_c2_f32": hbm_roof(2 * nd * 4 + 6 * nc * 4, a32, "k_apply_pencil+k_apply_faces",
                                  "x in, y out, 6 weights per cell (FP32)"),
     }
+    if args.nrhs > 1:
+        out["multi_rhs_f64"] = bench_multi_rhs(torch, rz, pb, args.nrhs, per_launch["patch"], ms, infos[-1].iters)
     pb.close()
     if not args.no_mixed:
         for prec, name in ((rz.PREC_MIXED, "mixed"), (rz.PREC_DEFECT, "defect")):
@@ -175,6 +177,37 @@ def bench_c2(torch, rz, ctx, args, out):
             out[f"kernel_ms_per_step_{name}"] = {k: round(v[0] / args.steps, 4) for k, v in ktm.items()}
             out[f"speedup_{name}_vs_f64"] = round(ms / msm, 3)
             pm.close()
+
+
+def bench_multi_rhs(torch, rz, pb, nrhs, patch_ms_1, solve_ms_1, iters_1, reps=3):
+    """One rz_solve on nrhs right-hand sides (seeds 0..nrhs-1, interleaved (ndofs,
+    nrhs)) against nrhs single solves: wall time, and the patch solve's time per
+    launch (each slot's factor read once for up to four vectors)."""
+    import synth
+    log(f"C2 multi-RHS: {nrhs} right-hand sides in one solve")
+    B = torch.as_tensor(np.ascontiguousarray(np.stack([synth.rhs_values(pb.ndofs, r) for r in range(nrhs)], axis=1)),
+                        device="cuda:0")
+    X = torch.empty_like(B)
+    pb.solve(B, X)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        infos = pb.solve(B, X)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    pb.timing(True)
+    pb.timing_read()
+    pb.solve(B, X)
+    kt = pb.timing_read()
+    pb.timing(False)
+    patch_launch = kt["patch"][0] / max(kt["patch"][1], 1)
+    return {"nrhs": nrhs, "ms_per_call": round(ms, 3), "ms_per_rhs": round(ms / nrhs, 3),
+            "single_rhs_ms": round(solve_ms_1, 3), "speedup_per_rhs_vs_single": round(solve_ms_1 * nrhs / ms, 3),
+            "iters": [i.iters for i in infos], "single_rhs_iters": iters_1,
+            "max_rel_res": max(i.rel_res for i in infos),
+            "patch_ms_per_launch": round(patch_launch, 4), "patch_ms_per_launch_single": round(patch_ms_1, 4),
+            "patch_vectors_per_launch": min(nrhs, 4),
+            "kernel_ms_per_call": {k: round(v[0], 3) for k, v in kt.items()}}
 
 
 def bench_c1(torch, rz, ctx, steps=20):
@@ -335,29 +368,32 @@ def bench_c5(torch, rz, ctx, steps, warmup, n=24, p=8, aux=True):
 def bench_batched(torch, rz, nrhs=4, nctx=2, count=64):
     """The batched workload: 64 problems with (space, n, p) drawn per problem
     (space in grad/curl/div, n in 4..16, p in 3..9, streams 1000+i), 4 right-hand
-    sides each (seeds 4i..4i+3), alpha = beta = 1.  Sequential rz_solve calls vs
-    rz_solve_batched over `nctx` contexts (streams)."""
+    sides each (seeds 4i..4i+3), alpha = beta = 1.  Sequential single-vector
+    rz_solve calls vs one rz_solve_batched over `nctx` contexts (streams), each
+    problem's right-hand sides in lockstep as one multi-vector."""
     import synth
     streams = [torch.cuda.Stream() for _ in range(nctx)]
     ctxs = [rz.Context(0, s) for s in streams]
     log(f"batched: setting up {count} problems")
     t0 = time.perf_counter()
-    probs, bs, xs, spec = [], [], [], []
+    probs, bs, xs, spec, bcols, xcols = [], [], [], [], [], []
     for i in range(count):
         space, n, p = synth.batch_spec(i)
         pb = rz.Problem(ctxs[i % nctx], n, p, 1.0, 1.0, space=space)
         probs.append(pb)
         spec.append((space, n, p))
-        bs.append(torch.as_tensor(np.stack([synth.rhs_values(pb.ndofs, 4 * i + r) for r in range(nrhs)]),
-                                  device="cuda:0"))
-        xs.append(torch.zeros((nrhs, pb.ndofs), dtype=torch.float64, device="cuda:0"))
+        cols = [synth.rhs_values(pb.ndofs, 4 * i + r) for r in range(nrhs)]
+        bs.append(torch.as_tensor(np.ascontiguousarray(np.stack(cols, axis=1)), device="cuda:0"))
+        xs.append(torch.zeros((pb.ndofs, nrhs), dtype=torch.float64, device="cuda:0"))
+        bcols.append([torch.as_tensor(c, device="cuda:0") for c in cols])
+        xcols.append([torch.zeros(pb.ndofs, dtype=torch.float64, device="cuda:0") for _ in range(nrhs)])
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     dofs_rhs = sum(pb.ndofs for pb in probs) * nrhs
     log("batched: sequential solves")
 
     def sequential():
-        for pb, b, x in zip(probs, bs, xs):
+        for pb, b, x in zip(probs, bcols, xcols):
             for r in range(nrhs):
                 pb.solve(b[r], x[r])
         torch.cuda.synchronize()
@@ -519,6 +555,7 @@ def main():
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--nrhs", type=int, default=4, help="right-hand sides of the C2 multi-vector solve (1: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB once before the solves (outside the timed region), a plain copy "
                          "kernel of known size for scaling HBM byte counters")

@@ -16,6 +16,12 @@
  * Vectors hold every lattice DoF; Dirichlet rows act as the identity (outputs copy
  * the input there, inputs there are read as zero elsewhere).
  *
+ * Several right-hand sides (nrhs > 1 in rz_apply, rz_relax, rz_vcycle, rz_solve,
+ * rz_solve_batched): multi-vectors are DoF-major with the right-hand side fastest,
+ * value r of DoF g at v[g*nrhs + r] (a row-major ndofs x nrhs array).  The first
+ * call with more right-hand sides than before allocates the per-vector workspace
+ * (kept until rz_free and reused by later calls with as many or fewer).
+ *
  * Ownership: the caller owns every vector (device pointers, e.g. the data of a
  * torch tensor on the library's device).  The library owns tables, factors and
  * workspace, all allocated in rz_setup and released by rz_free.  Host arrays
@@ -150,11 +156,12 @@ rz_status rz_free(rz_problem *h);
  * [6] rows of one patch, [7] non-empty patches. */
 rz_status rz_sizes(const rz_problem *h, int64_t sizes[8]);
 
-/* y = A x (eq. sum-factorization: matrix-free, per-cell tensor contractions).
- * x, y: device arrays of sizes[0] elements of type t; x and y must not overlap. */
-rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t);
+/* y = A x (Sec. 3.2, eq. sum-factorization: matrix-free, per-cell tensor
+ * contractions).  x, y: device arrays of sizes[0]*nrhs elements of type t (nrhs >= 1
+ * right-hand sides, interleaved as above); x and y must not overlap. */
+rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t, int32_t nrhs);
 
-/* y = A x exactly as rz_apply (same kernels, same result), for callers that cannot
+/* y = A x exactly as rz_apply with nrhs = 1 (same kernels, same result), for callers that cannot
  * allocate device memory at call time or must not trigger the library's own
  * allocations (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  The call allocates nothing: the apply's workspace (the
@@ -169,38 +176,51 @@ rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t);
 rz_status rz_apply_noalloc(rz_problem *h, const void *x, void *y, rz_dtype t);
 
 /* z = M^{-1} r, one application of the statically condensed additive Schwarz
- * relaxation on the auxiliary operator (eqs. schur, sc-asm-afw): cell-interior
- * solves, vertex-star interface patch solves with the IC factors, harmonic
- * extension.  Device arrays of type t (RZ_F32 uses FP32 factors). */
-rz_status rz_relax(rz_problem *h, const void *r, void *z, rz_dtype t);
+ * relaxation on the auxiliary operator.  H(grad) (Sec. 4.4, eqs. schur and
+ * sc-asm-afw; Sec. 4.5): cell-interior solves, vertex-star interface patch solves
+ * with the IC factors on the static-condensation pattern, harmonic extension.
+ * H(curl) / H(div) (Sec. 4.3-4.4, eqs. sc-ph and sc-asm-hiptmair): edge-star
+ * Cholesky solves (curl) or face-star Jacobi (div) on the condensed interface, plus
+ * the potential term through the interface exterior derivative.  Device arrays of
+ * sizes[0]*nrhs elements of type t (RZ_F32 uses FP32 factors).  With nrhs > 1 the
+ * H(grad) vertex-patch solve reads each patch factor once for up to four vectors. */
+rz_status rz_relax(rz_problem *h, const void *r, void *z, rz_dtype t, int32_t nrhs);
 
-/* Transfers between the degree-p lattice and the p=1 lattice (sizes[4]):
+/* Transfers between the degree-p lattice and the p=1 lattice (sizes[4]) of the
+ * two-level method (Sec. 4.3, eq. asm-afw: the coarse space V_{h,1}; Sec. 5):
  * xf += P xc (prolongation, the embedding V_{h,1} in V_{h,p}) and rc = P^T rf.
- * FP64 device arrays; Dirichlet entries of the output are zero (prolong adds 0). */
+ * FP64 device arrays; Dirichlet entries of the output are zero (prolong adds 0).
+ * H(grad) only (RZ_ERR_ARG otherwise). */
 rz_status rz_prolong_add(rz_problem *h, const double *xc, double *xf);
 rz_status rz_restrict(rz_problem *h, const double *rf, double *rc);
 
-/* xc = A_0^{-1} rc on the free p=1 DoFs (FP64 block-tridiagonal LDL^T); Dirichlet
- * entries of xc are zero. */
+/* xc = A_0^{-1} rc on the free p=1 DoFs (the coarse problem of eq. asm-afw, Sec.
+ * 4.3: the same form at p = 1; FP64 block-tridiagonal LDL^T); Dirichlet entries of
+ * xc are zero.  H(grad) only (RZ_ERR_ARG otherwise). */
 rz_status rz_coarse_solve(rz_problem *h, const double *rc, double *xc);
 
-/* z = V(r): hybrid V(1,1) cycle (damped relaxation, coarse correction, damped
- * relaxation), FP64 device arrays. */
-rz_status rz_vcycle(rz_problem *h, const double *r, double *z);
+/* z = V(r): hybrid V(1,1) cycle of Sec. 5 (damped relaxation, coarse correction
+ * of eq. asm-afw, damped relaxation), FP64 device arrays of sizes[0]*nrhs
+ * elements. */
+rz_status rz_vcycle(rz_problem *h, const double *r, double *z, int32_t nrhs);
 
-/* Solve A x = b by CG preconditioned with the V-cycle from x = 0, until the true
- * ||b - A x||_2 <= rtol ||b||_2.  b, x: FP64 device arrays of sizes[0].  info may
- * be NULL.  Returns RZ_ERR_NOT_CONVERGED if maxit is reached (x holds the last
- * iterate). */
-rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *info);
+/* Solve A x = b by CG preconditioned with the V-cycle (Sec. 5) from x = 0, until
+ * the true ||b - A x||_2 <= rtol ||b||_2 for every right-hand side.  b, x: FP64
+ * device arrays of sizes[0]*nrhs elements.  The right-hand sides iterate in
+ * lockstep (their V-cycles together; one that has converged stops), each with the
+ * arithmetic of a solve on its own: the results equal nrhs separate solves.  The
+ * defect-correction protocol solves them one after another.  info: NULL or nrhs
+ * results.  Returns the first failing status of the right-hand sides;
+ * RZ_ERR_NOT_CONVERGED if maxit is reached (x holds the last iterate). */
+rz_status rz_solve(rz_problem *h, const double *b, double *x, int32_t nrhs, rz_solve_info *info);
 
 /* Batch of independent solves (the batched workload of many Riesz maps of uneven
  * size and degree).  Problem i (each problem at most once) solves nrhs right-hand
- * sides b[i] + r*ndofs_i into x[i] + r*ndofs_i (device pointers, r = 0..nrhs-1),
- * one after another.  The PCG iterations of all problems advance in lockstep from
- * the calling thread: each round enqueues one step of every running solve on its
- * problem's stream, then waits for the streams, so problems created on different
- * contexts (streams) overlap on the device.  Results equal those of rz_solve.
+ * sides b[i] into x[i] (device multi-vectors of ndofs_i*nrhs elements, interleaved
+ * as above), in lockstep as rz_solve does.  The problems advance from the calling
+ * thread: it enqueues one step of every problem whose previous step has finished
+ * on its problem's stream, so problems created on different contexts (streams)
+ * overlap on the device.  Results equal those of rz_solve.
  * infos: n*nrhs results (may be NULL).  Synchronous; returns the first failing
  * status (the other solves still run to completion). */
 rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const *b, double *const *x,

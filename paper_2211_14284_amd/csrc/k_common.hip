@@ -48,6 +48,19 @@ __global__ void k_xpby(const double *x, double b, double *y, int64_t n) {
     y[i] = x[i] + b * y[i];
 }
 
+// Multi-vector layouts: interleaved (value r of DoF g at u[g * nv + r]) and planar
+// (vector r contiguous at v + r * ld).  One thread per DoF moves its nv values.
+template <typename T>
+__global__ void k_deinterleave(const T *__restrict__ u, T *__restrict__ v, int nv, int64_t ld, int64_t n) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
+    for (int r = 0; r < nv; ++r) v[r * ld + g] = u[g * nv + r];
+}
+template <typename T>
+__global__ void k_interleave(const T *__restrict__ v, T *__restrict__ u, int nv, int64_t ld, int64_t n) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
+    for (int r = 0; r < nv; ++r) u[g * nv + r] = v[r * ld + g];
+}
+
 // y = x + b y with b = (num - cross) / den read from device memory (cross optional)
 __global__ void k_xpby_dev(const double *__restrict__ x, const double *__restrict__ num,
                            const double *__restrict__ cross, const double *__restrict__ den, double *__restrict__ y,
@@ -491,6 +504,19 @@ void launch_xpby_dev(const double *x, const double *num, const double *cross, co
 void launch_sub(const double *x, const double *y, double *z, int64_t n, hipStream_t s) {
   k_sub<<<nblk(n), kBS, 0, s>>>(x, y, z, n);
 }
+template <typename T>
+void launch_deinterleave(const T *u, T *v, int nv, int64_t ld, int64_t n, hipStream_t s) {
+  k_deinterleave<T><<<nblk(n), kBS, 0, s>>>(u, v, nv, ld, n);
+}
+template <typename T>
+void launch_interleave(const T *v, T *u, int nv, int64_t ld, int64_t n, hipStream_t s) {
+  k_interleave<T><<<nblk(n), kBS, 0, s>>>(v, u, nv, ld, n);
+}
+template void launch_deinterleave<double>(const double *, double *, int, int64_t, int64_t, hipStream_t);
+template void launch_deinterleave<float>(const float *, float *, int, int64_t, int64_t, hipStream_t);
+template void launch_interleave<double>(const double *, double *, int, int64_t, int64_t, hipStream_t);
+template void launch_interleave<float>(const float *, float *, int, int64_t, int64_t, hipStream_t);
+
 void launch_scale_copy(double a, const double *x, double *y, int64_t n, hipStream_t s) {
   k_scale_copy<<<nblk(n), kBS, 0, s>>>(a, x, y, n);
 }

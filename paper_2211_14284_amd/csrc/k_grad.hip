@@ -821,16 +821,16 @@ __device__ __forceinline__ void load_all_regs(T (&v)[PassTable<P>::KT], __amdgpu
 }
 
 // indices of one pass read ahead of it: the lane's row, its columns, and (forward)
-// the row's right-hand side and inverted diagonal
-template <int K>
+// the row's right-hand sides (one per vector) and inverted diagonal
+template <int K, int NV>
 struct PassIdx {
   unsigned row;
   int ix[K > 0 ? K : 1];
-  double b, d;
+  double b[NV], d;
 };
 
-template <int P, int t>
-__device__ __forceinline__ void read_idx(PassIdx<PassTable<P>::K[t]> &q, const unsigned short *ecol,
+template <int P, int NV, int t>
+__device__ __forceinline__ void read_idx(PassIdx<PassTable<P>::K[t], NV> &q, const unsigned short *ecol,
                                          const unsigned short *erow, int lane) {
   constexpr int K = PassTable<P>::K[t], c0 = PassTable<P>::C[t];
   q.row = erow[64 * t + lane];
@@ -838,90 +838,106 @@ __device__ __forceinline__ void read_idx(PassIdx<PassTable<P>::K[t]> &q, const u
   for (int s = 0; s < K; ++s) q.ix[s] = ecol[64 * (c0 + s) + lane];
 }
 
-// forward pass t (gather): x_row = (w_row - sum_s L[row, col(s)] x_col(s)) / L_row,row.
-// Every lane of a row's group holds the same sum and writes the same value, and
-// lanes without a row use the dummy entry NR (zero vector value and diagonal), so
-// the sweeps run without lane masks.  Pass t + 1's indices are read while pass t
-// computes, and its row's right-hand side before pass t writes (rows of different
-// passes are distinct).
-template <typename T, int P, int t>
+// forward pass t (gather): x_row = (w_row - sum_s L[row, col(s)] x_col(s)) / L_row,row,
+// for each of the NV vectors, which sit interleaved in LDS (row-major, NV values
+// per row), so every factor value in registers serves all of them.  Every lane of
+// a row's group holds the same sum and writes the same value, and lanes without a
+// row use the dummy entry NR (zero vector values and diagonal), so the sweeps run
+// without lane masks.  Pass t + 1's indices are read while pass t computes, and its
+// row's right-hand sides before pass t writes (rows of different passes are
+// distinct).
+template <typename T, int P, int NV, int t>
 __device__ __forceinline__ void fwd_passes(const T (&v)[PassTable<P>::KT], double *xw, const double *iw,
                                            const unsigned short *ecol, const unsigned short *erow, int lane,
-                                           const PassIdx<PassTable<P>::K[t]> &q) {
+                                           const PassIdx<PassTable<P>::K[t], NV> &q) {
   using S = PassTable<P>;
   constexpr int G = S::G[t], K = S::K[t], c0 = S::C[t];
-  double xg[K > 0 ? K : 1];
+  double xg[K > 0 ? K : 1][NV];
 #pragma unroll
-  for (int s = 0; s < K; ++s) xg[s] = xw[q.ix[s]];
-  PassIdx<S::K[t + 1 < S::NP ? t + 1 : t]> n;
-  if constexpr (t + 1 < S::NP) read_idx<P, t + 1>(n, ecol, erow, lane);
-  double acc = 0;
-  if constexpr (K > 0) {
-    // two interleaved partial sums halve the dependent chain
-    double a0 = 0, a1 = 0;
+  for (int s = 0; s < K; ++s)
 #pragma unroll
-    for (int s = 0; s < K; s += 2) a0 += (double)v[c0 + s] * xg[s];
+    for (int r = 0; r < NV; ++r) xg[s][r] = xw[q.ix[s] * NV + r];
+  PassIdx<S::K[t + 1 < S::NP ? t + 1 : t], NV> n;
+  if constexpr (t + 1 < S::NP) read_idx<P, NV, t + 1>(n, ecol, erow, lane);
+  double acc[NV];
 #pragma unroll
-    for (int s = 1; s < K; s += 2) a1 += (double)v[c0 + s] * xg[s];
-    acc = group_sum_c<G>(a0 + a1);
+  for (int r = 0; r < NV; ++r) {
+    acc[r] = 0;
+    if constexpr (K > 0) {
+      // two interleaved partial sums halve the dependent chain
+      double a0 = 0, a1 = 0;
+#pragma unroll
+      for (int s = 0; s < K; s += 2) a0 += (double)v[c0 + s] * xg[s][r];
+#pragma unroll
+      for (int s = 1; s < K; s += 2) a1 += (double)v[c0 + s] * xg[s][r];
+      acc[r] = group_sum_c<G>(a0 + a1);
+    }
   }
   if constexpr (t + 1 < S::NP) {
-    n.b = xw[n.row];
+#pragma unroll
+    for (int r = 0; r < NV; ++r) n.b[r] = xw[n.row * NV + r];
     n.d = iw[n.row];
   }
-  xw[q.row] = (q.b - acc) * q.d;
-  if constexpr (t + 1 < S::NP) fwd_passes<T, P, t + 1>(v, xw, iw, ecol, erow, lane, n);
+#pragma unroll
+  for (int r = 0; r < NV; ++r) xw[q.row * NV + r] = (q.b[r] - acc[r]) * q.d;
+  if constexpr (t + 1 < S::NP) fwd_passes<T, P, NV, t + 1>(v, xw, iw, ecol, erow, lane, n);
 }
 
 // backward pass t (push form of L^T x = z): x_row = w_row / L_row,row, then
-// w_col(s) -= L[row, col(s)] x_row.  Padding values are zero, and their adds of -0
-// leave every value as it is (the dummy row's value is zero too).  Pass t - 1's
-// indices and inverted diagonal are read while pass t computes (the diagonals
-// never change).  Once pass t has pushed, its registers load the next slot's
-// values of pass t (through nr, which reads zeros without memory access past the
-// last slot).
-template <typename T, int P, int t>
+// w_col(s) -= L[row, col(s)] x_row, for each vector.  Padding values are zero, and
+// their adds of -0 leave every value as it is (the dummy row's values are zero too).
+// Pass t - 1's indices and inverted diagonal are read while pass t computes (the
+// diagonals never change).  Once pass t has pushed, its registers load the next
+// slot's values of pass t (through nr, which reads zeros without memory access past
+// the last slot).
+template <typename T, int P, int NV, int t>
 __device__ __forceinline__ void bwd_passes(T (&v)[PassTable<P>::KT], double *xw, const double *iw,
                                            const unsigned short *ecol, const unsigned short *erow, int lane,
-                                           const PassIdx<PassTable<P>::K[t]> &q, __amdgpu_buffer_rsrc_t nr,
+                                           const PassIdx<PassTable<P>::K[t], NV> &q, __amdgpu_buffer_rsrc_t nr,
                                            unsigned nmask) {
   using S = PassTable<P>;
   constexpr int K = S::K[t], c0 = S::C[t];
-  const double a = xw[q.row];
-  PassIdx<S::K[t > 0 ? t - 1 : 0]> n;
-  if constexpr (t > 0) read_idx<P, t - 1>(n, ecol, erow, lane);
-  const double x = a * q.d;
-  xw[q.row] = x;
+  double x[NV];
+#pragma unroll
+  for (int r = 0; r < NV; ++r) x[r] = xw[q.row * NV + r];
+  PassIdx<S::K[t > 0 ? t - 1 : 0], NV> n;
+  if constexpr (t > 0) read_idx<P, NV, t - 1>(n, ecol, erow, lane);
+#pragma unroll
+  for (int r = 0; r < NV; ++r) {
+    x[r] *= q.d;
+    xw[q.row * NV + r] = x[r];
+  }
 #pragma unroll
   for (int s = 0; s < K; ++s) {
     T vs = v[c0 + s];
     // an empty asm marks vs as redefined, so the FP32 factor is widened again here
     // instead of the forward sweep's widened copies staying live in registers
     if constexpr (sizeof(T) == 4) asm("" : "+v"(vs));
-    atomicAdd(&xw[q.ix[s]], -(double)vs * x);
+#pragma unroll
+    for (int r = 0; r < NV; ++r) atomicAdd(&xw[q.ix[s] * NV + r], -(double)vs * x[r]);
   }
   load_pass_regs<T, P, t>(v, nr, lane, (nmask >> t) & 1u);
   if constexpr (t > 0) {
     n.d = iw[n.row];
-    bwd_passes<T, P, t - 1>(v, xw, iw, ecol, erow, lane, n, nr, nmask);
+    bwd_passes<T, P, NV, t - 1>(v, xw, iw, ecol, erow, lane, n, nr, nmask);
   }
 }
 
-template <typename T, int P>
+template <typename T, int P, int NV>
 __global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, const T *__restrict__ factor,
-                                                        const T *__restrict__ rt, T *__restrict__ zbuf,
-                                                        long nslots) {
+                                                        PatchVecs<T> V, long nslots) {
   using S = PassTable<P>;
   constexpr int NR = S::NR, NP = S::NP, KT = S::KT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ne = E.ne;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-  // LDS: the wavefronts' vectors and their inverted diagonals (both FP64, NR + 1
-  // entries: the last is the dummy row of lanes without a row), the shared tables
+  // LDS: the wavefronts' vectors (NV interleaved, FP64, NR + 1 rows: the last is the
+  // dummy row of lanes without a row), their inverted diagonals (FP64), the shared
+  // tables
   constexpr int NR1 = NR + 1;
-  double *xw = reinterpret_cast<double *>(smem_raw) + (size_t)w * NR1;
-  double *iw = reinterpret_cast<double *>(smem_raw) + (size_t)(nw + w) * NR1;
-  int *off = reinterpret_cast<int *>(reinterpret_cast<double *>(smem_raw) + (size_t)2 * nw * NR1);
+  double *xw = reinterpret_cast<double *>(smem_raw) + (size_t)w * NR1 * NV;
+  double *iw = reinterpret_cast<double *>(smem_raw) + (size_t)nw * NR1 * NV + (size_t)w * NR1;
+  int *off = reinterpret_cast<int *>(reinterpret_cast<double *>(smem_raw) + (size_t)nw * NR1 * (NV + 1));
   unsigned short *ecol = reinterpret_cast<unsigned short *>(off + NR);
   unsigned short *erow = ecol + ne;
   for (int i = tid; i < ne; i += blockDim.x) ecol[i] = (unsigned short)E.ecol[i];
@@ -945,54 +961,65 @@ __global__ void __launch_bounds__(256) k_patch_solve_r(LatDev L, PatchEllDev E, 
   for (; sl < nslots; sl += step) {
     const T *f = factor + sl * (long)E.stride;
     const int vx = sl % nvx, vy = (sl / nvx) % nvy, vz = sl / ((long)nvx * nvy);
-    // right-hand side and diagonals (the off-diagonals are loaded already)
+    // right-hand sides and diagonals (the off-diagonals are loaded already)
     constexpr int NI = (NR + 63) / 64;
-    T rhs[NI], dia[NI];
+    T rhs[NI][NV], dia[NI];
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
       const int i = lane + 64 * j;
-      rhs[j] = T(0);
+#pragma unroll
+      for (int r = 0; r < NV; ++r) rhs[j][r] = T(0);
       dia[j] = T(1);
       if (i < NR) {
         const int o = off[i];
         const int X = vx * P + (o & 255) - 64, Y = vy * P + ((o >> 8) & 255) - 64, Z = vz * P + ((o >> 16) & 255) - 64;
         const bool in = X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
-        if (in && !lat_dirichlet(L, X, Y, Z)) rhs[j] = rt[lat_index(L, X, Y, Z)];
+        if (in && !lat_dirichlet(L, X, Y, Z)) {
+          const long g = lat_index(L, X, Y, Z);
+#pragma unroll
+          for (int r = 0; r < NV; ++r) rhs[j][r] = V.rt[r][g];
+        }
         dia[j] = f[i];
       }
     }
-    // the next slot's real rows (while this slot's right-hand side is in flight)
+    // the next slot's real rows (while this slot's right-hand sides are in flight)
     const unsigned nmask = real_row_mask<T, P>(L, off, erow, lane, slot_pos(L, sl + step));
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
       const int i = lane + 64 * j;
       if (i < NR) {
-        xw[i] = (double)rhs[j];
+#pragma unroll
+        for (int r = 0; r < NV; ++r) xw[i * NV + r] = (double)rhs[j][r];
         iw[i] = 1.0 / (double)dia[j];
       }
     }
     if (lane == 0) {  // the dummy row
-      xw[NR] = 0.0;
+#pragma unroll
+      for (int r = 0; r < NV; ++r) xw[NR * NV + r] = 0.0;
       iw[NR] = 0.0;
     }
     {
-      PassIdx<S::K[0]> q;
-      read_idx<P, 0>(q, ecol, erow, lane);
-      q.b = xw[q.row];
+      PassIdx<S::K[0], NV> q;
+      read_idx<P, NV, 0>(q, ecol, erow, lane);
+#pragma unroll
+      for (int r = 0; r < NV; ++r) q.b[r] = xw[q.row * NV + r];
       q.d = iw[q.row];
-      fwd_passes<T, P, 0>(v, xw, iw, ecol, erow, lane, q);
+      fwd_passes<T, P, NV, 0>(v, xw, iw, ecol, erow, lane, q);
     }
     {
-      PassIdx<S::K[NP - 1]> q;
-      read_idx<P, NP - 1>(q, ecol, erow, lane);
+      PassIdx<S::K[NP - 1], NV> q;
+      read_idx<P, NV, NP - 1>(q, ecol, erow, lane);
       q.d = iw[q.row];
-      bwd_passes<T, P, NP - 1>(v, xw, iw, ecol, erow, lane, q, slot_rsrc(sl + step), nmask);
+      bwd_passes<T, P, NV, NP - 1>(v, xw, iw, ecol, erow, lane, q, slot_rsrc(sl + step), nmask);
     }
-    T *zo = zbuf + sl * (long)NR;
 #pragma unroll
-    for (int j = 0; j < NI; ++j) {
-      const int i = lane + 64 * j;
-      if (i < NR) zo[i] = (T)xw[i];
+    for (int r = 0; r < NV; ++r) {
+      T *zo = V.zb[r] + sl * (long)NR;
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        const int i = lane + 64 * j;
+        if (i < NR) zo[i] = (T)xw[i * NV + r];
+      }
     }
   }
 }
@@ -1777,30 +1804,49 @@ bool patch_regs_table_matches(int p, const int *pass, int np, int nrows, int ne,
 
 // the register kernel: four wavefronts per block, as many blocks per CU as the
 // registers (2 at p = 7 in FP64) and the LDS allow
-template <typename T, int P>
-static int launch_patch_solve_r(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf,
+template <typename T, int P, int NV>
+static int launch_patch_solve_r(const LatDev &L, const PatchEllDev &E, const T *factor, const PatchVecs<T> &V,
                                 hipStream_t s) {
   using S = PassTable<P>;
   constexpr int waves = 4;
   const long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
-  const size_t shm =
-      (size_t)2 * waves * (S::NR + 1) * sizeof(double) + 4 * (size_t)S::NR + 2 * (size_t)E.ne + 2 * 64 * S::NP;
+  const size_t shm = (size_t)waves * (NV + 1) * (S::NR + 1) * sizeof(double) + 4 * (size_t)S::NR +
+                     2 * (size_t)E.ne + 2 * 64 * S::NP;
   // the LDS attribute on every launch (it belongs to the current device); the
   // occupancy once (one device type)
-  if (hipFuncSetAttribute((const void *)k_patch_solve_r<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) !=
-      hipSuccess)
+  if (hipFuncSetAttribute((const void *)k_patch_solve_r<T, P, NV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)shm) != hipSuccess)
     return -1;
   static const int per_cu = [&] {
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_patch_solve_r<T, P>, 64 * waves, shm) != hipSuccess) b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_patch_solve_r<T, P, NV>, 64 * waves, shm) != hipSuccess)
+      b = 0;
     return b;
   }();
   if (per_cu <= 0) return -1;
   long grid = (long)device_cu_count() * per_cu;
   const long need = (nv + waves - 1) / waves;
   if (grid > need) grid = need;
-  k_patch_solve_r<T, P><<<(unsigned)grid, 64 * waves, shm, s>>>(L, E, factor, rt, zbuf, nv);
+  k_patch_solve_r<T, P, NV><<<(unsigned)grid, 64 * waves, shm, s>>>(L, E, factor, V, nv);
   return 0;
+}
+
+// one register-kernel launch over NV vectors (NV = 1, 2 or 4)
+template <typename T, int NV>
+static int launch_patch_solve_r_nv(const LatDev &L, const PatchEllDev &E, const T *factor, const PatchVecs<T> &V,
+                                   hipStream_t s) {
+  switch (L.p) {
+    case 2: return launch_patch_solve_r<T, 2, NV>(L, E, factor, V, s);
+    case 3: return launch_patch_solve_r<T, 3, NV>(L, E, factor, V, s);
+    case 4: return launch_patch_solve_r<T, 4, NV>(L, E, factor, V, s);
+    case 5: return launch_patch_solve_r<T, 5, NV>(L, E, factor, V, s);
+    case 6: return launch_patch_solve_r<T, 6, NV>(L, E, factor, V, s);
+    case 7: return launch_patch_solve_r<T, 7, NV>(L, E, factor, V, s);
+    case 8:
+      if constexpr (sizeof(T) == 4) return launch_patch_solve_r<T, 8, NV>(L, E, factor, V, s);
+      return -1;
+    default: return -1;
+  }
 }
 
 // the register kernel's range: the compiled schedule matches, p >= 2, and the slot's
@@ -1813,18 +1859,10 @@ template <typename T>
 int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf, hipStream_t s) {
   const long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
   if (patch_solve_uses_regs(E, L.p, sizeof(T))) {
-    switch (L.p) {
-      case 2: return launch_patch_solve_r<T, 2>(L, E, factor, rt, zbuf, s);
-      case 3: return launch_patch_solve_r<T, 3>(L, E, factor, rt, zbuf, s);
-      case 4: return launch_patch_solve_r<T, 4>(L, E, factor, rt, zbuf, s);
-      case 5: return launch_patch_solve_r<T, 5>(L, E, factor, rt, zbuf, s);
-      case 6: return launch_patch_solve_r<T, 6>(L, E, factor, rt, zbuf, s);
-      case 7: return launch_patch_solve_r<T, 7>(L, E, factor, rt, zbuf, s);
-      case 8:
-        if constexpr (sizeof(T) == 4) return launch_patch_solve_r<T, 8>(L, E, factor, rt, zbuf, s);
-        break;
-      default: break;
-    }
+    PatchVecs<T> V{};
+    V.rt[0] = rt;
+    V.zb[0] = zbuf;
+    return launch_patch_solve_r_nv<T, 1>(L, E, factor, V, s);
   }
   auto grid_of = [&](int waves, int per_cu) {
     long grid = (long)device_cu_count() * per_cu;
@@ -1954,6 +1992,38 @@ template void launch_condense_grad<double>(const LatDev &, const double *, const
                                            const double *, double *, hipStream_t);
 template void launch_condense_grad<float>(const LatDev &, const float *, const float *, const float *,
                                           const float *, float *, hipStream_t);
+// The patch solve of nvec right-hand sides rt[r] into zb[r].  The register kernel
+// takes up to four vectors per launch, each slot's factor loaded once for all of
+// them; the streaming kernel runs once per vector.
+template <typename T>
+int launch_patch_solve_multi(const LatDev &L, const PatchEllDev &E, const T *factor, int nvec, const T *const *rt,
+                             T *const *zb, hipStream_t s) {
+  if (nvec < 1) return 0;
+  if (!patch_solve_uses_regs(E, L.p, sizeof(T))) {
+    for (int r = 0; r < nvec; ++r)
+      if (int e = launch_patch_solve<T>(L, E, factor, rt[r], zb[r], s)) return e;
+    return 0;
+  }
+  for (int r0 = 0; r0 < nvec;) {
+    const int left = nvec - r0, nv = left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    PatchVecs<T> V{};
+    for (int r = 0; r < nv; ++r) {
+      V.rt[r] = rt[r0 + r];
+      V.zb[r] = zb[r0 + r];
+    }
+    const int e = nv == 4   ? launch_patch_solve_r_nv<T, 4>(L, E, factor, V, s)
+                  : nv == 2 ? launch_patch_solve_r_nv<T, 2>(L, E, factor, V, s)
+                            : launch_patch_solve_r_nv<T, 1>(L, E, factor, V, s);
+    if (e) return e;
+    r0 += nv;
+  }
+  return 0;
+}
+
+template int launch_patch_solve_multi<double>(const LatDev &, const PatchEllDev &, const double *, int,
+                                              const double *const *, double *const *, hipStream_t);
+template int launch_patch_solve_multi<float>(const LatDev &, const PatchEllDev &, const float *, int,
+                                             const float *const *, float *const *, hipStream_t);
 template int launch_patch_solve<double>(const LatDev &, const PatchEllDev &, const double *,
                                          const double *, double *, hipStream_t);
 template int launch_patch_solve<float>(const LatDev &, const PatchEllDev &, const float *,

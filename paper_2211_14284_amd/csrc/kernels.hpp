@@ -101,6 +101,12 @@ void launch_axpy(double a, const double *x, double *y, int64_t n, hipStream_t s)
 void launch_xpby(const double *x, double b, double *y, int64_t n, hipStream_t s);
 void launch_sub(const double *x, const double *y, double *z, int64_t n, hipStream_t s);
 void launch_scale_copy(double a, const double *x, double *y, int64_t n, hipStream_t s);
+// Multi-vector layouts: interleaved u (value r of DoF g at u[g * nv + r]) to planar v
+// (vector r at v + r * ld, n values each), and back.
+template <typename T>
+void launch_deinterleave(const T *u, T *v, int nv, int64_t ld, int64_t n, hipStream_t s);
+template <typename T>
+void launch_interleave(const T *v, T *u, int nv, int64_t ld, int64_t n, hipStream_t s);
 // Deterministic two-pass dot products: out[k] = <x_k, y_k> for up to 3 pairs.
 void launch_dots(int npairs, const double *const *xs, const double *const *ys, int64_t n,
                  double *partials, double *out, hipStream_t s);
@@ -146,8 +152,18 @@ bool patch_regs_table_matches(int p, const int *pass, int np, int nrows, int ne,
 // register-resident kernel (else the streaming one)
 bool patch_solve_uses_regs(const PatchEllDev &E, int p, size_t elem);
 size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves);
+// Right-hand sides and outputs of one patch-solve launch over several vectors.
+constexpr int kPatchMaxVecs = 4;
+template <typename T>
+struct PatchVecs {
+  const T *rt[kPatchMaxVecs];
+  T *zb[kPatchMaxVecs];
+};
 template <typename T>
 int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, const T *rt, T *zbuf, hipStream_t s);
+template <typename T>
+int launch_patch_solve_multi(const LatDev &L, const PatchEllDev &E, const T *factor, int nvec, const T *const *rt,
+                             T *const *zb, hipStream_t s);
 // Cell phase of y = A x on trilinear cells (interior rows to y, interface rows to
 // ebuf); the interface rows are then summed by launch_apply_gather.  Returns
 // non-zero for an unsupported degree.

@@ -13,6 +13,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -174,6 +175,14 @@ struct rz_problem {
   int nDir = 0;
   int *dlist = nullptr;
   std::vector<char> dmask;                  // host: Dirichlet rows
+  // several right-hand sides: planar copies of the caller's interleaved
+  // multi-vectors (mcap vectors each) and the per-vector buffers of right-hand
+  // sides 1 .. mcap-1 (right-hand side 0 uses the buffers above)
+  int mcap = 0;
+  size_t mnzb = 0;
+  std::vector<void *> mallocs;
+  double *mb = nullptr, *mx = nullptr, *mvec = nullptr, *mzb64 = nullptr, *mdots = nullptr, *mhdots = nullptr;
+  float *mf32 = nullptr, *mzb32 = nullptr;
   // per-kernel timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -217,6 +226,71 @@ rz_status upload(rz_problem *h, T **ptr, const std::vector<T> &v) {
   if (st != RZ_OK) return st;
   HIPCALL(h, hipMemcpyAsync(*ptr, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, h->ctx->stream));
   return RZ_OK;
+}
+
+// The workspace of calls on several right-hand sides (grown on first use with more
+// vectors than it holds, kept until rz_free).
+void free_multi(rz_problem *h) {
+  for (void *p : h->mallocs) hipFree(p);
+  h->mallocs.clear();
+  if (h->mhdots) hipHostFree(h->mhdots);
+  h->mb = h->mx = h->mvec = h->mzb64 = h->mdots = h->mhdots = nullptr;
+  h->mf32 = h->mzb32 = nullptr;
+  h->mcap = 0;
+  h->mnzb = 0;
+}
+
+constexpr int kRhsVecs = 7;  // FP64 vectors per extra right-hand side: r, z, p, Ap, r_old, V-cycle residual, rt
+constexpr int kRhsVecs32 = 2;  // FP32: rt, r
+
+rz_status ensure_multi(rz_problem *h, int nv) {
+  if (nv <= h->mcap) return RZ_OK;
+  HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+  free_multi(h);
+  const size_t n = (size_t)h->ndofs, extra = (size_t)nv - 1;
+  const size_t nzb = h->space == RZ_GRAD ? (size_t)h->nvert * h->ps.nrows : 0;
+  auto al = [&](auto **ptr, size_t count) -> rz_status {
+    void *q = nullptr;
+    const hipError_t e = hipMalloc(&q, sizeof(**ptr) * (count ? count : 1));
+    if (e != hipSuccess) return fail(h->ctx, RZ_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    h->mallocs.push_back(q);
+    *ptr = static_cast<std::remove_reference_t<decltype(*ptr)>>(q);
+    return RZ_OK;
+  };
+  rz_status e;
+  if ((e = al(&h->mb, nv * n)) || (e = al(&h->mx, nv * n))) return e;
+  if (extra) {
+    if ((e = al(&h->mvec, extra * kRhsVecs * n)) || (e = al(&h->mf32, extra * kRhsVecs32 * n)) ||
+        (e = al(&h->mdots, 8 * extra)))
+      return e;
+    if (nzb) {
+      if ((e = al(&h->mzb64, extra * nzb)) || (e = al(&h->mzb32, extra * nzb))) return e;
+      launch_fill(h->mzb64, 0.0, (int64_t)(extra * nzb), h->ctx->stream);
+      launch_fill_f(h->mzb32, 0.0f, (int64_t)(extra * nzb), h->ctx->stream);
+    }
+    if (hipHostMalloc((void **)&h->mhdots, 8 * extra * sizeof(double), hipHostMallocDefault) != hipSuccess)
+      return fail(h->ctx, RZ_ERR_OOM, "pinned host buffer");
+  }
+  h->mcap = nv;
+  h->mnzb = nzb;
+  return RZ_OK;
+}
+
+// Buffers of right-hand side i of a multi-vector call.
+struct RhsBufs {
+  double *r, *z, *p, *Ap, *ro, *vr, *rt64, *zb64, *dots, *hdots;
+  float *rt32, *zb32, *r32;
+};
+
+RhsBufs rhs_bufs(rz_problem *h, int i) {
+  if (i == 0)
+    return {h->kr, h->kz, h->kp, h->kAp, h->kro, h->vr, h->rt64, h->zb64, h->dots, h->hdots, h->rt32, h->zb32, h->r32};
+  const size_t n = (size_t)h->ndofs, k = (size_t)i - 1;
+  double *v = h->mvec + k * kRhsVecs * n;
+  float *f = h->mf32 + k * kRhsVecs32 * n;
+  return {v,         v + n,     v + 2 * n, v + 3 * n, v + 4 * n, v + 5 * n, v + 6 * n,
+          h->mzb64 ? h->mzb64 + k * h->mnzb : nullptr,         h->mdots + 8 * k, h->mhdots + 8 * k,
+          f,         h->mzb32 ? h->mzb32 + k * h->mnzb : nullptr,          f + n};
 }
 
 bool lat_dirichlet_h(const rz_problem *h, int X, int Y, int Z) {
@@ -626,6 +700,126 @@ rz_status do_vcycle32(rz_problem *h, const float *r, float *z) {
   return RZ_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// Several right-hand sides at once (planar vectors; ids name the right-hand sides,
+// which select their per-vector buffers).  The H(grad) vertex-patch solve runs once
+// for all of them, each slot's factor loaded once (launch_patch_solve_multi); the
+// other steps run per vector, in the same order and arithmetic as for one vector.
+// ---------------------------------------------------------------------------------------
+VecRelaxPtrs<double> vec_ptrs(rz_problem *h, double *) { return vec_ptrs64(h); }
+VecRelaxPtrs<float> vec_ptrs(rz_problem *h, float *) { return vec_ptrs32(h); }
+
+void axpy_t(double a, const double *x, double *y, int64_t n, hipStream_t s) { launch_axpy(a, x, y, n, s); }
+void axpy_t(float a, const float *x, float *y, int64_t n, hipStream_t s) { launch_axpy_f(a, x, y, n, s); }
+void scale_copy_t(double a, const double *x, double *y, int64_t n, hipStream_t s) { launch_scale_copy(a, x, y, n, s); }
+void scale_copy_t(float a, const float *x, float *y, int64_t n, hipStream_t s) { launch_scale_copy_f(a, x, y, n, s); }
+
+// z_j = scale M r_j, or with acc: acc_j += w M r_j (z_j is then scratch, and may be
+// one buffer for all j); post(j) runs once vector j's result is complete.
+template <typename T, typename Post>
+rz_status relax_multi(rz_problem *h, int nv, const int *ids, const T *const *r, T *const *z, T scale, T w,
+                      T *const *acc, Post post) {
+  hipStream_t s = h->ctx->stream;
+  if (h->space != RZ_GRAD) {
+    for (int j = 0; j < nv; ++j) {
+      if (rz_status e = relax_vec<T>(h, vec_ptrs(h, (T *)nullptr), r[j], z[j])) return e;
+      if (acc) axpy_t(w, z[j], acc[j], h->ndofs, s);
+      else if (scale != T(1)) scale_copy_t(scale, z[j], z[j], h->ndofs, s);
+      post(j);
+    }
+    return RZ_OK;
+  }
+  constexpr bool f64 = sizeof(T) == 8;
+  const T *coef, *A, *lam, *f;
+  if constexpr (f64) {
+    coef = h->coef64, A = h->A64, lam = h->lam64, f = h->f64;
+  } else {
+    coef = h->coef32, A = h->A32, lam = h->lam32, f = h->f32;
+  }
+  std::vector<T *> rt(nv), zb(nv);
+  for (int j = 0; j < nv; ++j) {
+    const RhsBufs B = rhs_bufs(h, ids[j]);
+    if constexpr (f64) {
+      rt[j] = B.rt64, zb[j] = B.zb64;
+    } else {
+      rt[j] = B.rt32, zb[j] = B.zb32;
+    }
+  }
+  {
+    Timed t(h, RZ_K_CONDENSE);
+    for (int j = 0; j < nv; ++j) launch_condense_grad<T>(h->L, coef, A, lam, r[j], rt[j], s);
+  }
+  {
+    Timed t(h, RZ_K_PATCH);
+    if (launch_patch_solve_multi<T>(h->L, h->PE, f, nv, rt.data(), zb.data(), s))
+      return fail(h->ctx, RZ_ERR_HIP, "patch solve launch failed");
+  }
+  {
+    Timed t(h, RZ_K_EXPAND);
+    for (int j = 0; j < nv; ++j) {
+      launch_expand_grad<T>(h->L, h->P, coef, A, lam, r[j], zb[j], z[j], scale, w, acc ? acc[j] : nullptr, s);
+      post(j);
+    }
+  }
+  return RZ_OK;
+}
+
+// relax_multi on FP64 vectors in the precision of the problem's protocol (as
+// do_relax_prec): z_j = scale M r_j, or acc_j += w M r_j
+rz_status relax_prec_multi(rz_problem *h, int nv, const int *ids, const double *const *r, double *const *z,
+                           double scale, double w, double *const *acc) {
+  hipStream_t s = h->ctx->stream;
+  const int64_t n = h->ndofs;
+  if (h->opts.precision == RZ_PREC_F64) return relax_multi<double>(h, nv, ids, r, z, scale, w, acc, [](int) {});
+  std::vector<const float *> r32(nv);
+  std::vector<float *> z32(nv, h->z32);
+  for (int j = 0; j < nv; ++j) {
+    float *b = rhs_bufs(h, ids[j]).r32;
+    launch_cast_d2f(r[j], b, n, s);
+    r32[j] = b;
+  }
+  return relax_multi<float>(h, nv, ids, r32.data(), z32.data(), 1.0f, 0.0f, nullptr, [&](int j) {
+    if (acc) launch_f2d_axpy(w, h->z32, acc[j], n, s);
+    else launch_f2d_scale(scale, h->z32, z[j], n, s);
+  });
+}
+
+// z_j = V(r_j) for nv vectors (the cycle of do_vcycle; FP64 vectors)
+rz_status vcycle_multi(rz_problem *h, int nv, const int *ids, const double *const *r, double *const *z) {
+  if (h->space != RZ_GRAD) {
+    for (int j = 0; j < nv; ++j)
+      if (rz_status e = do_vcycle_vec(h, r[j], z[j])) return e;
+    return RZ_OK;
+  }
+  hipStream_t s = h->ctx->stream;
+  const double w = h->omega;
+  const bool f32c = h->opts.precision != RZ_PREC_F64;
+  if (rz_status e = relax_prec_multi(h, nv, ids, r, z, w, 0.0, nullptr)) return e;  // z = w M r
+  std::vector<double *> vr(nv), vt(nv, h->vt);
+  for (int j = 0; j < nv; ++j) {
+    vr[j] = rhs_bufs(h, ids[j]).vr;
+    do_residual64(h, r[j], z[j], vr[j]);  // r1 = r - A z
+    {
+      Timed tm(h, RZ_K_TRANSFER);
+      launch_restrict_grad(h->L, h->E64, vr[j], h->rc, h->rt1, h->rt2, s);
+    }
+    if (rz_status e = do_coarse(h, h->rc, h->xc, f32c)) return e;
+    if (h->T2_64) {  // z += P xc and r2 = r1 - A P xc in one pass
+      Timed tm(h, RZ_K_TRANSFER);
+      launch_prolong_residual_grad(h->L, h->E64, h->T2_64, h->coef64, h->xc, z[j], vr[j], s);
+    } else {
+      {
+        Timed tm(h, RZ_K_TRANSFER);
+        launch_prolong_add_grad(h->L, h->E64, h->xc, z[j], s);
+      }
+      do_residual64(h, r[j], z[j], vr[j]);  // r2 = r - A z
+    }
+  }
+  if (rz_status e = relax_prec_multi(h, nv, ids, vr.data(), vt.data(), 1.0, w, z)) return e;  // z += w M r2
+  for (int j = 0; j < nv; ++j) launch_dirichlet_copy(h->L, r[j], z[j], s);
+  return RZ_OK;
+}
+
 rz_status dots_host(rz_problem *h, int np, const double *const *xs, const double *const *ys, double *out) {
   {
     Timed tm(h, RZ_K_KRYLOV);
@@ -983,6 +1177,7 @@ void release(rz_problem *h) {
   }
   for (void *p : h->allocs) hipFree(p);
   h->allocs.clear();
+  free_multi(h);
   if (h->hdots) hipHostFree(h->hdots);
   h->hdots = nullptr;
   for (auto &e : h->ev_pool) {
@@ -1789,197 +1984,260 @@ rz_status require_grad(const rz_problem *h) {
 
 namespace {
 
-// PCG (Sec. 5) as a state machine: each step enqueues stream-ordered work and the
-// dot products it needs (copied asynchronously to pinned host memory); the caller
-// waits for the stream and hands the values to the next step.  rz_solve runs one
-// instance; rz_solve_batched advances instances of several problems in lockstep,
-// so their streams overlap on the device.  Both issue the same kernels in the same
-// order, so their results are identical.
-// PCG as a step machine: each step enqueues work and the read-back of the scalars
-// the host needs next; the caller synchronises the stream between steps.  The CG
-// coefficients are formed on the device (alpha in the update kernel, beta in the
-// direction update), so one host round trip per iteration remains: the convergence
-// test on r.r, which decides whether the next V-cycle runs.
-// Device scalar slots (h->dots): [2q], [2q+1]: r.z and (mixed) r_old.z of the
-// iterations with parity q; [4]: p.Ap; [5]: r.r after the update; [6]: other norms.
-struct PcgRun {
+// PCG (Sec. 5) on nv right-hand sides of one problem as a step machine.  Each step
+// enqueues stream-ordered work for every right-hand side that is still running,
+// and the read-back of the scalars the host needs next (copied asynchronously to
+// pinned memory); the caller waits for the stream (or an event) and calls the next
+// step.  The right-hand sides iterate in lockstep: their V-cycles run together
+// (vcycle_multi, one patch solve per relaxation for all of them), every other step
+// per vector.  A right-hand side that has converged drops out of the later steps.
+// The CG coefficients are formed on the device (alpha in the update kernel, beta in
+// the direction update), so one host round trip per iteration remains: the
+// convergence test on r.r, which decides whether the next V-cycle runs.
+// Device scalar slots (dots of each right-hand side): [2q], [2q+1]: r.z and (mixed)
+// r_old.z of the iterations with parity q; [4]: p.Ap; [5]: r.r after the update;
+// [6]: other norms.
+struct BlockRun {
   rz_problem *h = nullptr;
-  const double *b = nullptr;
-  double *x = nullptr;
-  enum Phase { INIT, GOT_BB, GOT_RR, GOT_TR, GOT_FINAL, DONE } phase = INIT;
-  int it = 0;
-  double rz0 = 0;           // r.z of the first iteration (natural norm squared)
-  int it_natural = -1;      // first iteration count at which the natural norm had dropped by rtol
-  double nb = 0, tol = 0, relres = 0;
-  rz_status result = RZ_OK;
+  int nv = 0;
+  const double *bu = nullptr;  // caller's vectors (interleaved when nv > 1)
+  double *xu = nullptr;
+  // per right-hand side: what the last step enqueued, and what comes next
+  enum Kind { NONE, NORM_B, ITER, TRUE_RES, FINAL, DONE };
+  struct Rhs {
+    const double *b = nullptr;
+    double *x = nullptr;
+    Kind enq = NONE, next = NONE;
+    bool restart = false;     // continue from the true residual (stored in Ap)
+    int it = 0;
+    double rz0 = 0;           // r.z of the first iteration (natural norm squared)
+    int it_natural = -1;      // first iteration count at which the natural norm had dropped by rtol
+    double nb = 0, tol = 0, relres = 0;
+    rz_status result = RZ_OK;
+  };
+  std::vector<Rhs> s;
+  bool started = false, done = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
 enum { kSlotPap = 4, kSlotRr = 5, kSlotNorm = 6 };
 
-// one norm (x.x) into slot kSlotNorm and its host copy hdots[0]
-rz_status pcg_norm(PcgRun &R, const double *v) {
-  rz_problem *h = R.h;
+// v.v into slot kSlotNorm of right-hand side i
+void block_norm(rz_problem *h, int i, const double *v) {
   const double *xs[1] = {v};
-  {
-    Timed tm(h, RZ_K_KRYLOV);
-    launch_dots(1, xs, xs, h->ndofs, h->partials, h->dots + kSlotNorm, h->ctx->stream);
-  }
-  HIPCALL(h, hipMemcpyAsync(h->hdots, h->dots + kSlotNorm, sizeof(double), hipMemcpyDeviceToHost, h->ctx->stream));
-  return RZ_OK;
+  Timed tm(h, RZ_K_KRYLOV);
+  launch_dots(1, xs, xs, h->ndofs, h->partials, rhs_bufs(h, i).dots + kSlotNorm, h->ctx->stream);
 }
 
-rz_status pcg_final(PcgRun &R) {
-  rz_problem *h = R.h;
-  do_residual64(h, R.b, R.x, h->vr);
-  dir_copy(h, nullptr, h->vr, h->ctx->stream);
-  R.phase = PcgRun::GOT_FINAL;
-  return pcg_norm(R, h->vr);
-}
-
-// One iteration from the current residual r: z = V r, rz (+ cross), p = z + beta p
-// (p = z on the first iteration), Ap, p.Ap, x += alpha p, r -= alpha Ap, r.r; then
-// p.Ap and r.r go back to the host.
-rz_status pcg_iteration(PcgRun &R, bool first) {
-  rz_problem *h = R.h;
+// one CG iteration of right-hand side i after its V-cycle z = V r: r.z (+ cross),
+// p = z + beta p (p = z on the first iteration), Ap, p.Ap, x += alpha p,
+// r -= alpha Ap, r.r
+rz_status block_iteration_tail(rz_problem *h, int i, BlockRun::Rhs &R) {
   hipStream_t s = h->ctx->stream;
   const int64_t n = h->ndofs;
+  const RhsBufs B = rhs_bufs(h, i);
   const bool mixed = h->opts.precision == RZ_PREC_MIXED;
   const int q = R.it & 1;
-  double *rz = h->dots + 2 * q, *rz_old = h->dots + 2 * (1 - q);
-  if (rz_status e = do_vcycle(h, h->kr, h->kz)) return e;
+  double *rz = B.dots + 2 * q, *rz_old = B.dots + 2 * (1 - q);
   {
     Timed tm(h, RZ_K_KRYLOV);
-    if (first) {
-      const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
+    if (R.it == 0) {
+      const double *xs[1] = {B.r}, *ys[1] = {B.z};
       launch_dots(1, xs, ys, n, h->partials, rz, s);
-      launch_scale_copy(1.0, h->kz, h->kp, n, s);
+      launch_scale_copy(1.0, B.z, B.p, n, s);
     } else if (mixed) {
-      const double *xs[2] = {h->kr, h->kro}, *ys[2] = {h->kz, h->kz};
+      const double *xs[2] = {B.r, B.ro}, *ys[2] = {B.z, B.z};
       launch_dots(2, xs, ys, n, h->partials, rz, s);
-      launch_xpby_dev(h->kz, rz, rz + 1, rz_old, h->kp, n, s);
+      launch_xpby_dev(B.z, rz, rz + 1, rz_old, B.p, n, s);
     } else {
-      const double *xs[1] = {h->kr}, *ys[1] = {h->kz};
+      const double *xs[1] = {B.r}, *ys[1] = {B.z};
       launch_dots(1, xs, ys, n, h->partials, rz, s);
-      launch_xpby_dev(h->kz, rz, nullptr, rz_old, h->kp, n, s);
+      launch_xpby_dev(B.z, rz, nullptr, rz_old, B.p, n, s);
     }
   }
-  do_apply64(h, h->kp, h->kAp);
+  if (rz_status e = do_apply64(h, B.p, B.Ap)) return e;
   {
     Timed tm(h, RZ_K_KRYLOV);
-    const double *xs[1] = {h->kp}, *ys[1] = {h->kAp};
-    launch_dots(1, xs, ys, n, h->partials, h->dots + kSlotPap, s);
-    launch_cg_update(rz, h->dots + kSlotPap, h->kp, h->kAp, R.x, h->kr, mixed ? h->kro : nullptr, n, h->partials,
-                     h->dots + kSlotRr, s);
+    const double *xs[1] = {B.p}, *ys[1] = {B.Ap};
+    launch_dots(1, xs, ys, n, h->partials, B.dots + kSlotPap, s);
+    launch_cg_update(rz, B.dots + kSlotPap, B.p, B.Ap, R.x, B.r, mixed ? B.ro : nullptr, n, h->partials,
+                     B.dots + kSlotRr, s);
   }
-  HIPCALL(h, hipMemcpyAsync(h->hdots, h->dots + kSlotPap, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCALL(h, hipMemcpyAsync(h->hdots + 2, rz, sizeof(double), hipMemcpyDeviceToHost, s));
   ++R.it;
-  R.phase = PcgRun::GOT_RR;
   return RZ_OK;
 }
 
-// Advance one step with the scalars of the previous step in h->hdots.
-rz_status pcg_step(PcgRun &R) {
-  rz_problem *h = R.h;
-  hipStream_t s = h->ctx->stream;
-  const int64_t n = h->ndofs;
-  const double *d = h->hdots;
-  switch (R.phase) {
-    case PcgRun::INIT: {
-      HIPCALL(h, hipEventCreate(&R.ev0));
-      HIPCALL(h, hipEventCreate(&R.ev1));
-      HIPCALL(h, hipEventRecord(R.ev0, s));
-      launch_fill(R.x, 0.0, n, s);  // x = 0, r = b with Dirichlet rows zero
-      v_scale_copy(h, 1.0, R.b, h->kr);
-      dir_copy(h, nullptr, h->kr, s);
-      R.phase = PcgRun::GOT_BB;
-      return pcg_norm(R, h->kr);
-    }
-    case PcgRun::GOT_BB: {
-      R.nb = std::sqrt(d[0]);
+// Decide what right-hand side i does next from the scalars of the last step.
+void block_decide(rz_problem *h, int i, BlockRun::Rhs &R) {
+  const double *d = rhs_bufs(h, i).hdots;
+  switch (R.enq) {
+    case BlockRun::NORM_B:
+      R.nb = std::sqrt(d[kSlotNorm]);
       R.tol = h->opts.rtol * R.nb;
-      if (!(R.nb > 0)) return pcg_final(R);
-      if (h->opts.maxit < 1) {
+      if (!(R.nb > 0)) {
+        R.next = BlockRun::FINAL;
+      } else if (h->opts.maxit < 1) {
         R.result = RZ_ERR_NOT_CONVERGED;
-        return pcg_final(R);
+        R.next = BlockRun::FINAL;
+      } else {
+        R.next = BlockRun::ITER;
       }
-      return pcg_iteration(R, true);
-    }
-    case PcgRun::GOT_RR: {
-      const double pAp = d[0], rr = d[1];
+      break;
+    case BlockRun::ITER: {
+      const double pAp = d[kSlotPap], rr = d[kSlotRr], rzv = d[2 * ((R.it - 1) & 1)];
       // the paper's criterion (Sec. 5.1): the natural norm (r^T M^{-1} r)^{1/2} of the
       // residual that started this iteration, against the first one
-      if (R.it == 1) R.rz0 = d[2];
-      if (R.it_natural < 0 && R.it > 1 && std::sqrt(std::fabs(d[2])) <= h->opts.rtol * std::sqrt(std::fabs(R.rz0)))
+      if (R.it == 1) R.rz0 = rzv;
+      if (R.it_natural < 0 && R.it > 1 && std::sqrt(std::fabs(rzv)) <= h->opts.rtol * std::sqrt(std::fabs(R.rz0)))
         R.it_natural = R.it - 1;
       if (!(pAp > 0)) {
         R.result = fail(h->ctx, RZ_ERR_BREAKDOWN, "CG breakdown: p.Ap <= 0");
-        return pcg_final(R);
-      }
-      if (std::sqrt(rr) <= R.tol) {  // recurrence converged: check the true residual
-        do_residual64(h, R.b, R.x, h->vr);
-        dir_copy(h, nullptr, h->vr, s);
-        R.phase = PcgRun::GOT_TR;
-        return pcg_norm(R, h->vr);
-      }
-      if (R.it >= h->opts.maxit) {
+        R.next = BlockRun::FINAL;
+      } else if (std::sqrt(rr) <= R.tol) {  // recurrence converged: check the true residual
+        R.next = BlockRun::TRUE_RES;
+      } else if (R.it >= h->opts.maxit) {
         R.result = RZ_ERR_NOT_CONVERGED;
-        return pcg_final(R);
+        R.next = BlockRun::FINAL;
+      } else {
+        R.next = BlockRun::ITER;
       }
-      return pcg_iteration(R, false);
+      break;
     }
-    case PcgRun::GOT_TR: {
-      if (std::sqrt(d[0]) <= R.tol) {
+    case BlockRun::TRUE_RES: {
+      const double tr = std::sqrt(d[kSlotNorm]);
+      R.relres = R.nb > 0 ? tr / R.nb : 0.0;
+      if (tr <= R.tol) {
         R.result = RZ_OK;
-        R.relres = R.nb > 0 ? std::sqrt(d[0]) / R.nb : 0.0;
-        R.phase = PcgRun::DONE;
-        return RZ_OK;
-      }
-      if (R.it >= h->opts.maxit) {
+        R.next = BlockRun::DONE;
+      } else if (R.it >= h->opts.maxit) {
         R.result = RZ_ERR_NOT_CONVERGED;
-        R.relres = R.nb > 0 ? std::sqrt(d[0]) / R.nb : 0.0;
-        R.phase = PcgRun::DONE;
-        return RZ_OK;
+        R.next = BlockRun::DONE;
+      } else {
+        R.restart = true;  // continue from the true residual
+        R.next = BlockRun::ITER;
       }
-      v_scale_copy(h, 1.0, h->vr, h->kr);  // continue from the true residual
-      return pcg_iteration(R, false);
+      break;
     }
-    case PcgRun::GOT_FINAL:
-      R.relres = R.nb > 0 ? std::sqrt(d[0]) / R.nb : 0.0;
-      R.phase = PcgRun::DONE;
-      return RZ_OK;
-    case PcgRun::DONE:
-      return RZ_OK;
+    case BlockRun::FINAL:
+      R.relres = R.nb > 0 ? std::sqrt(d[kSlotNorm]) / R.nb : 0.0;
+      R.next = BlockRun::DONE;
+      break;
+    default:
+      break;
   }
+  R.enq = BlockRun::NONE;
+}
+
+// Advance every right-hand side by one step (the caller has waited for the
+// previous step's work).
+rz_status block_step(BlockRun &B) {
+  rz_problem *h = B.h;
+  hipStream_t s = h->ctx->stream;
+  const int64_t n = h->ndofs;
+  const int nv = B.nv;
+  if (!B.started) {
+    B.started = true;
+    HIPCALL(h, hipEventCreate(&B.ev0));
+    HIPCALL(h, hipEventCreate(&B.ev1));
+    HIPCALL(h, hipEventRecord(B.ev0, s));
+    B.s.assign(nv, BlockRun::Rhs());
+    if (nv > 1) {
+      if (rz_status e = ensure_multi(h, nv)) return e;
+      launch_deinterleave<double>(B.bu, h->mb, nv, n, n, s);
+      for (int i = 0; i < nv; ++i) {
+        B.s[i].b = h->mb + (size_t)i * n;
+        B.s[i].x = h->mx + (size_t)i * n;
+      }
+    } else {
+      B.s[0].b = B.bu;
+      B.s[0].x = B.xu;
+    }
+    for (int i = 0; i < nv; ++i) {  // x = 0, r = b with Dirichlet rows zero
+      const RhsBufs R = rhs_bufs(h, i);
+      launch_fill(B.s[i].x, 0.0, n, s);
+      v_scale_copy(h, 1.0, B.s[i].b, R.r);
+      dir_copy(h, nullptr, R.r, s);
+      block_norm(h, i, R.r);
+      B.s[i].enq = BlockRun::NORM_B;
+    }
+  } else {
+    for (int i = 0; i < nv; ++i) block_decide(h, i, B.s[i]);
+    std::vector<int> ids;
+    std::vector<const double *> rs;
+    std::vector<double *> zs;
+    for (int i = 0; i < nv; ++i) {
+      BlockRun::Rhs &R = B.s[i];
+      if (R.next != BlockRun::ITER) continue;
+      const RhsBufs Bi = rhs_bufs(h, i);
+      if (R.restart) v_scale_copy(h, 1.0, Bi.Ap, Bi.r);
+      R.restart = false;
+      ids.push_back(i);
+      rs.push_back(Bi.r);
+      zs.push_back(Bi.z);
+    }
+    if (!ids.empty()) {
+      if (rz_status e = vcycle_multi(h, (int)ids.size(), ids.data(), rs.data(), zs.data())) return e;
+      for (int i : ids) {
+        if (rz_status e = block_iteration_tail(h, i, B.s[i])) return e;
+        B.s[i].enq = BlockRun::ITER;
+      }
+    }
+    for (int i = 0; i < nv; ++i) {
+      BlockRun::Rhs &R = B.s[i];
+      if (R.next != BlockRun::TRUE_RES && R.next != BlockRun::FINAL) continue;
+      const RhsBufs Bi = rhs_bufs(h, i);  // the true residual goes to Ap
+      if (rz_status e = do_residual64(h, R.b, R.x, Bi.Ap)) return e;
+      dir_copy(h, nullptr, Bi.Ap, s);
+      block_norm(h, i, Bi.Ap);
+      R.enq = R.next;
+    }
+  }
+  bool any = false;
+  for (const BlockRun::Rhs &R : B.s) any |= R.enq != BlockRun::NONE;
+  if (!any) {
+    if (nv > 1) launch_interleave<double>(h->mx, B.xu, nv, n, n, s);
+    B.done = true;
+    return RZ_OK;
+  }
+  HIPCALL(h, hipMemcpyAsync(h->hdots, h->dots, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (nv > 1)
+    HIPCALL(h, hipMemcpyAsync(h->mhdots, h->mdots, 8 * (size_t)(nv - 1) * sizeof(double), hipMemcpyDeviceToHost, s));
   return RZ_OK;
 }
 
-void pcg_release(PcgRun &R) {
-  if (R.ev0) hipEventDestroy(R.ev0);
-  if (R.ev1) hipEventDestroy(R.ev1);
-  R.ev0 = R.ev1 = nullptr;
+void block_release(BlockRun &B) {
+  if (B.ev0) hipEventDestroy(B.ev0);
+  if (B.ev1) hipEventDestroy(B.ev1);
+  B.ev0 = B.ev1 = nullptr;
 }
 
-rz_status pcg_finish(PcgRun &R, rz_solve_info *info) {
-  rz_problem *h = R.h;
+// Wait for the solve, fill infos (nv entries, may be null) and return the first
+// failing status of the right-hand sides.
+rz_status block_finish(BlockRun &B, rz_solve_info *infos) {
+  rz_problem *h = B.h;
   float ms = 0;
-  if (R.ev0) {
-    const bool ok = hipEventRecord(R.ev1, h->ctx->stream) == hipSuccess && hipEventSynchronize(R.ev1) == hipSuccess;
-    if (ok) hipEventElapsedTime(&ms, R.ev0, R.ev1);
-    pcg_release(R);
+  if (B.ev0) {
+    const bool ok = hipEventRecord(B.ev1, h->ctx->stream) == hipSuccess && hipEventSynchronize(B.ev1) == hipSuccess;
+    if (ok) hipEventElapsedTime(&ms, B.ev0, B.ev1);
+    block_release(B);
     if (!ok) return fail(h->ctx, RZ_ERR_HIP, "stream execution failed during the solve");
   }
-  if (R.result == RZ_OK) R.result = take_device_status(h);
-  if (info) {
-    info->iters = R.it;
-    info->status = R.result;
-    info->rel_res = R.relres;
-    info->omega = h->omega;
-    info->t_solve_ms = ms;
-    info->iters_natural = R.it_natural;
+  const rz_status dev = take_device_status(h);
+  rz_status first = RZ_OK;
+  for (int i = 0; i < B.nv; ++i) {
+    BlockRun::Rhs &R = B.s[i];
+    if (R.result == RZ_OK) R.result = dev;
+    if (R.result != RZ_OK && first == RZ_OK) first = R.result;
+    if (infos) {
+      infos[i].iters = R.it;
+      infos[i].status = R.result;
+      infos[i].rel_res = R.relres;
+      infos[i].omega = h->omega;
+      infos[i].t_solve_ms = ms;
+      infos[i].iters_natural = R.it_natural;
+    }
   }
-  return R.result;
+  return first;
 }
 
 }  // namespace
@@ -2249,13 +2507,31 @@ rz_status rz_sizes(const rz_problem *h, int64_t sizes[8]) {
   return RZ_OK;
 }
 
-rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t) {
+rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t, int32_t nrhs) {
   rz_status e = require_device(h);
   if (e) return e;
-  if (!x || !y || x == y) return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad vectors");
-  if (t == RZ_F64) return do_apply64(h, static_cast<const double *>(x), static_cast<double *>(y));
-  if (t == RZ_F32) return do_apply32(h, static_cast<const float *>(x), static_cast<float *>(y));
-  return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad dtype");
+  if (!x || !y || x == y || nrhs < 1) return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad vectors");
+  if (t != RZ_F64 && t != RZ_F32) return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad dtype");
+  if (nrhs == 1) {
+    if (t == RZ_F64) return do_apply64(h, static_cast<const double *>(x), static_cast<double *>(y));
+    return do_apply32(h, static_cast<const float *>(x), static_cast<float *>(y));
+  }
+  if ((e = ensure_multi(h, nrhs))) return e;
+  hipStream_t s = h->ctx->stream;
+  const int64_t n = h->ndofs;
+  if (t == RZ_F64) {
+    launch_deinterleave<double>(static_cast<const double *>(x), h->mb, nrhs, n, n, s);
+    for (int r = 0; r < nrhs; ++r)
+      if ((e = do_apply64(h, h->mb + (size_t)r * n, h->mx + (size_t)r * n))) return e;
+    launch_interleave<double>(h->mx, static_cast<double *>(y), nrhs, n, n, s);
+  } else {
+    float *xb = reinterpret_cast<float *>(h->mb), *yb = reinterpret_cast<float *>(h->mx);
+    launch_deinterleave<float>(static_cast<const float *>(x), xb, nrhs, n, n, s);
+    for (int r = 0; r < nrhs; ++r)
+      if ((e = do_apply32(h, xb + (size_t)r * n, yb + (size_t)r * n))) return e;
+    launch_interleave<float>(yb, static_cast<float *>(y), nrhs, n, n, s);
+  }
+  return RZ_OK;
 }
 
 // Bytes of the apply's workspace (face-line buffer of the Cartesian H(grad) path,
@@ -2310,13 +2586,36 @@ rz_status rz_apply_noalloc(rz_problem *h, const void *x, void *y, rz_dtype t) {
   return RZ_OK;
 }
 
-rz_status rz_relax(rz_problem *h, const void *r, void *z, rz_dtype t) {
+rz_status rz_relax(rz_problem *h, const void *r, void *z, rz_dtype t, int32_t nrhs) {
   rz_status e = require_device(h);
   if (e) return e;
-  if (!r || !z || r == z) return fail(h->ctx, RZ_ERR_ARG, "rz_relax: bad vectors");
-  if (t == RZ_F64) return do_relax64(h, static_cast<const double *>(r), static_cast<double *>(z));
-  if (t == RZ_F32) return do_relax32(h, static_cast<const float *>(r), static_cast<float *>(z));
-  return fail(h->ctx, RZ_ERR_ARG, "rz_relax: bad dtype");
+  if (!r || !z || r == z || nrhs < 1) return fail(h->ctx, RZ_ERR_ARG, "rz_relax: bad vectors");
+  if (t != RZ_F64 && t != RZ_F32) return fail(h->ctx, RZ_ERR_ARG, "rz_relax: bad dtype");
+  if (nrhs == 1) {
+    if (t == RZ_F64) return do_relax64(h, static_cast<const double *>(r), static_cast<double *>(z));
+    return do_relax32(h, static_cast<const float *>(r), static_cast<float *>(z));
+  }
+  if ((e = ensure_multi(h, nrhs))) return e;
+  hipStream_t s = h->ctx->stream;
+  const int64_t n = h->ndofs;
+  std::vector<int> ids(nrhs);
+  for (int i = 0; i < nrhs; ++i) ids[i] = i;
+  auto run = [&](auto *rb, auto *zb) -> rz_status {
+    using T = std::remove_pointer_t<decltype(rb)>;
+    launch_deinterleave<T>(static_cast<const T *>(r), rb, nrhs, n, n, s);
+    std::vector<const T *> rs(nrhs);
+    std::vector<T *> zs(nrhs);
+    for (int i = 0; i < nrhs; ++i) {
+      rs[i] = rb + (size_t)i * n;
+      zs[i] = zb + (size_t)i * n;
+    }
+    if (rz_status e2 = relax_multi<T>(h, nrhs, ids.data(), rs.data(), zs.data(), T(1), T(0), nullptr, [](int) {}))
+      return e2;
+    launch_interleave<T>(zb, static_cast<T *>(z), nrhs, n, n, s);
+    return RZ_OK;
+  };
+  if (t == RZ_F64) return run(h->mb, h->mx);
+  return run(reinterpret_cast<float *>(h->mb), reinterpret_cast<float *>(h->mx));
 }
 
 rz_status rz_prolong_add(rz_problem *h, const double *xc, double *xf) {
@@ -2345,40 +2644,72 @@ rz_status rz_coarse_solve(rz_problem *h, const double *rcv, double *xcv) {
   return do_coarse(h, rcv, xcv);
 }
 
-rz_status rz_vcycle(rz_problem *h, const double *r, double *z) {
+rz_status rz_vcycle(rz_problem *h, const double *r, double *z, int32_t nrhs) {
   rz_status e = require_device(h);
   if (e) return e;
-  if (!r || !z || r == z) return fail(h->ctx, RZ_ERR_ARG, "rz_vcycle: bad vectors");
-  return do_vcycle(h, r, z);
+  if (!r || !z || r == z || nrhs < 1) return fail(h->ctx, RZ_ERR_ARG, "rz_vcycle: bad vectors");
+  if (nrhs == 1) return do_vcycle(h, r, z);
+  if ((e = ensure_multi(h, nrhs))) return e;
+  hipStream_t s = h->ctx->stream;
+  const int64_t n = h->ndofs;
+  launch_deinterleave<double>(r, h->mb, nrhs, n, n, s);
+  std::vector<int> ids(nrhs);
+  std::vector<const double *> rs(nrhs);
+  std::vector<double *> zs(nrhs);
+  for (int i = 0; i < nrhs; ++i) {
+    ids[i] = i;
+    rs[i] = h->mb + (size_t)i * n;
+    zs[i] = h->mx + (size_t)i * n;
+  }
+  if ((e = vcycle_multi(h, nrhs, ids.data(), rs.data(), zs.data()))) return e;
+  launch_interleave<double>(h->mx, z, nrhs, n, n, s);
+  return RZ_OK;
 }
 
-rz_status rz_solve(rz_problem *h, const double *b, double *x, rz_solve_info *info) {
+rz_status rz_solve(rz_problem *h, const double *b, double *x, int32_t nrhs, rz_solve_info *info) {
   rz_status e = require_device(h);
   if (e) return e;
-  if (!b || !x || b == x) return fail(h->ctx, RZ_ERR_ARG, "rz_solve: bad vectors");
-  if (h->opts.precision == RZ_PREC_DEFECT) return defect_solve(h, b, x, info);
-  PcgRun R;
-  R.h = h;
-  R.b = b;
-  R.x = x;
-  while (R.phase != PcgRun::DONE) {
-    if ((e = pcg_step(R))) {
-      pcg_release(R);
+  if (!b || !x || b == x || nrhs < 1) return fail(h->ctx, RZ_ERR_ARG, "rz_solve: bad vectors");
+  if (h->opts.precision == RZ_PREC_DEFECT) {
+    if (nrhs == 1) return defect_solve(h, b, x, info);
+    // one right-hand side after another (planar copies)
+    if ((e = ensure_multi(h, nrhs))) return e;
+    hipStream_t s = h->ctx->stream;
+    const int64_t n = h->ndofs;
+    launch_deinterleave<double>(b, h->mb, nrhs, n, n, s);
+    rz_status first = RZ_OK;
+    for (int i = 0; i < nrhs; ++i) {
+      rz_status r = defect_solve(h, h->mb + (size_t)i * n, h->mx + (size_t)i * n, info ? info + i : nullptr);
+      if (r == RZ_ERR_HIP || r == RZ_ERR_ARG || r == RZ_ERR_OOM) return r;
+      if (r != RZ_OK && first == RZ_OK) first = r;
+    }
+    launch_interleave<double>(h->mx, x, nrhs, n, n, s);
+    HIPCALL(h, hipStreamSynchronize(s));
+    return first;
+  }
+  BlockRun B;
+  B.h = h;
+  B.nv = nrhs;
+  B.bu = b;
+  B.xu = x;
+  while (!B.done) {
+    if ((e = block_step(B))) {
+      block_release(B);
       return e;
     }
-    if (R.phase != PcgRun::DONE && hipStreamSynchronize(h->ctx->stream) != hipSuccess) {
-      pcg_release(R);
+    if (hipStreamSynchronize(h->ctx->stream) != hipSuccess) {
+      block_release(B);
       return fail(h->ctx, RZ_ERR_HIP, "stream execution failed during the solve");
     }
   }
-  return pcg_finish(R, info);
+  return block_finish(B, info);
 }
 
 rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const *b, double *const *x, int32_t nrhs,
                            rz_solve_info *infos) {
   if (!hs || !b || !x || n < 0 || nrhs < 1) return RZ_ERR_ARG;
   for (int i = 0; i < n; ++i) {
-    if (!hs[i] || !b[i] || !x[i]) return RZ_ERR_ARG;
+    if (!hs[i] || !b[i] || !x[i] || b[i] == x[i]) return RZ_ERR_ARG;
     rz_status e = require_device(hs[i]);
     if (e) return e;
     if (hs[i]->opts.precision == RZ_PREC_DEFECT)
@@ -2386,30 +2717,26 @@ rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail(hs[i]->ctx, RZ_ERR_ARG, "rz_solve_batched: a problem appears twice");
   }
-  // One running instance per problem (its right-hand sides one after another).  Each
-  // enqueued step ends with an event; the host advances every instance whose event
-  // has completed, so problems on different streams progress independently and the
-  // device works on one while the host serves another.
-  std::vector<PcgRun> run(n);
-  std::vector<int> rhs(n, 0);
+  // One block run per problem (its right-hand sides in lockstep).  Each enqueued
+  // step ends with an event; the host advances every run whose event has completed,
+  // so problems on different streams progress independently and the device works
+  // on one while the host serves another.
+  std::vector<BlockRun> run(n);
   std::vector<rz_status> st(n, RZ_OK);
   std::vector<hipEvent_t> ev(n, nullptr);
-  std::vector<char> pending(n, 0);
+  std::vector<char> pending(n, 0), finished(n, 0);
   rz_status first_fail = RZ_OK;  // first non-OK result of a finished solve
-  auto start = [&](int i) {
-    run[i] = PcgRun();
-    run[i].h = hs[i];
-    run[i].b = b[i] + (int64_t)rhs[i] * hs[i]->ndofs;
-    run[i].x = x[i] + (int64_t)rhs[i] * hs[i]->ndofs;
-  };
   for (int i = 0; i < n; ++i) {
-    start(i);
+    run[i].h = hs[i];
+    run[i].nv = nrhs;
+    run[i].bu = b[i];
+    run[i].xu = x[i];
     if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) {
       for (int j = 0; j < i; ++j) hipEventDestroy(ev[j]);
       return fail(hs[i]->ctx, RZ_ERR_HIP, "rz_solve_batched: event creation");
     }
   }
-  auto live = [&](int i) { return rhs[i] < nrhs && st[i] == RZ_OK; };
+  auto live = [&](int i) { return !finished[i] && st[i] == RZ_OK; };
   int active = n;
   while (active > 0) {
     bool progressed = false;
@@ -2425,26 +2752,21 @@ rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const
         }
       }
       progressed = true;
-      if (run[i].phase == PcgRun::DONE) {
-        rz_solve_info inf{};
-        const rz_status r = pcg_finish(run[i], &inf);
-        if (infos) infos[(int64_t)i * nrhs + rhs[i]] = inf;
+      if (run[i].done) {
+        const rz_status r = block_finish(run[i], infos ? infos + (int64_t)i * nrhs : nullptr);
         if (r != RZ_OK && first_fail == RZ_OK) first_fail = r;  // keep solving the others
-        if (++rhs[i] >= nrhs) continue;
-        start(i);
+        finished[i] = 1;
+        continue;
       }
-      rz_status e = pcg_step(run[i]);
-      if (e) {
+      if (rz_status e = block_step(run[i])) {
         st[i] = e;
         continue;
       }
-      if (run[i].phase != PcgRun::DONE) {
-        if (hipEventRecord(ev[i], hs[i]->ctx->stream) != hipSuccess) {
-          st[i] = fail(hs[i]->ctx, RZ_ERR_HIP, "event record");
-          continue;
-        }
-        pending[i] = 1;
+      if (hipEventRecord(ev[i], hs[i]->ctx->stream) != hipSuccess) {
+        st[i] = fail(hs[i]->ctx, RZ_ERR_HIP, "event record");
+        continue;
       }
+      pending[i] = 1;
     }
     active = 0;
     for (int i = 0; i < n; ++i) active += live(i);
@@ -2452,7 +2774,7 @@ rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const
   }
   for (int i = 0; i < n; ++i) {
     hipEventDestroy(ev[i]);
-    pcg_release(run[i]);  // instances stopped by an error still hold their events
+    block_release(run[i]);  // runs stopped by an error still hold their events
   }
   for (int i = 0; i < n; ++i)
     if (st[i]) return st[i];

@@ -70,14 +70,14 @@ _proto = {
                                 ctypes.POINTER(_vp)]),
     "rz_free": (ctypes.c_int, [_vp]),
     "rz_sizes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)]),
-    "rz_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+    "rz_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int32]),
     "rz_apply_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
-    "rz_relax": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+    "rz_relax": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int32]),
     "rz_prolong_add": (ctypes.c_int, [_vp, _vp, _vp]),
     "rz_restrict": (ctypes.c_int, [_vp, _vp, _vp]),
     "rz_coarse_solve": (ctypes.c_int, [_vp, _vp, _vp]),
-    "rz_vcycle": (ctypes.c_int, [_vp, _vp, _vp]),
-    "rz_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(SolveInfo)]),
+    "rz_vcycle": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),
+    "rz_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(SolveInfo)]),
     "rz_export": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "rz_sync": (ctypes.c_int, [_vp]),
     "rz_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -124,6 +124,19 @@ def close_all():
 
 
 atexit.register(close_all)
+
+
+def _nrhs(t, nrhs=None):
+    """Right-hand sides of a multi-vector: the second extent of an (ndofs, nrhs)
+    tensor (DoF-major, right-hand side fastest), 1 for a vector; an explicit
+    nrhs for int addresses."""
+    if nrhs is not None:
+        return int(nrhs)
+    if t is None or isinstance(t, int) or t.dim() == 1:
+        return 1
+    if t.dim() != 2 or not t.is_contiguous():
+        raise ValueError("multi-vectors are contiguous (ndofs, nrhs) tensors")
+    return int(t.shape[1])
 
 
 def _ptr(t):
@@ -233,15 +246,17 @@ class Problem:
         _live.add(self)
 
     # ---- compute (device tensors) -------------------------------------------------
-    def apply(self, x, y, dtype=F64):
-        self.ctx.check(lib.rz_apply(self.handle, _ptr(x), _ptr(y), dtype))
+    def apply(self, x, y, dtype=F64, nrhs=None):
+        """y = A x; x, y: (ndofs,) or (ndofs, nrhs) device tensors."""
+        self.ctx.check(lib.rz_apply(self.handle, _ptr(x), _ptr(y), dtype, _nrhs(x, nrhs)))
 
     def apply_noalloc(self, x, y, dtype=F64):
         """y = A x with the library's static workspace (no allocation in the call)."""
         self.ctx.check(lib.rz_apply_noalloc(self.handle, _ptr(x), _ptr(y), dtype))
 
-    def relax(self, r, z, dtype=F64):
-        self.ctx.check(lib.rz_relax(self.handle, _ptr(r), _ptr(z), dtype))
+    def relax(self, r, z, dtype=F64, nrhs=None):
+        """z = M^{-1} r; r, z: (ndofs,) or (ndofs, nrhs) device tensors."""
+        self.ctx.check(lib.rz_relax(self.handle, _ptr(r), _ptr(z), dtype, _nrhs(r, nrhs)))
 
     def prolong_add(self, xc, xf):
         self.ctx.check(lib.rz_prolong_add(self.handle, _ptr(xc), _ptr(xf)))
@@ -252,19 +267,24 @@ class Problem:
     def coarse_solve(self, rc, xc):
         self.ctx.check(lib.rz_coarse_solve(self.handle, _ptr(rc), _ptr(xc)))
 
-    def vcycle(self, r, z):
-        self.ctx.check(lib.rz_vcycle(self.handle, _ptr(r), _ptr(z)))
+    def vcycle(self, r, z, nrhs=None):
+        self.ctx.check(lib.rz_vcycle(self.handle, _ptr(r), _ptr(z), _nrhs(r, nrhs)))
 
     def sync(self):
         """Wait for the queued work; raises if a coarse-solve wait gave up."""
         self.ctx.check(lib.rz_sync(self.handle))
 
-    def solve(self, b, x, check=True):
-        info = SolveInfo()
-        code = lib.rz_solve(self.handle, _ptr(b), _ptr(x), ctypes.byref(info))
+    def solve(self, b, x, check=True, nrhs=None):
+        """Solve A x = b.  b, x: (ndofs,) device tensors (returns a SolveInfo) or
+        (ndofs, nrhs) multi-vectors (returns a list of nrhs SolveInfo)."""
+        k = _nrhs(b, nrhs)
+        infos = (SolveInfo * k)()
+        code = lib.rz_solve(self.handle, _ptr(b), _ptr(x), k, infos)
         if check:
             self.ctx.check(code)
-        return info
+        if k == 1 and (nrhs is None and (b is None or isinstance(b, int) or b.dim() == 1)):
+            return infos[0]
+        return [infos[r] for r in range(k)]
 
     # ---- per-kernel device timing --------------------------------------------------
     def timing(self, on=True):
@@ -362,11 +382,11 @@ class Problem:
 
 
 def solve_batched(problems, bs, xs, check=True):
-    """Batched solves: problems[i] solves the nrhs rows of the device tensor bs[i]
-    (shape nrhs x ndofs) into xs[i]; problems on different contexts run
-    concurrently.  Returns an (n, nrhs) list of SolveInfo."""
+    """Batched solves: problems[i] solves the device tensor bs[i] ((ndofs,) or
+    (ndofs, nrhs): the same nrhs for every problem) into xs[i]; problems on
+    different contexts run concurrently.  Returns an (n, nrhs) list of SolveInfo."""
     n = len(problems)
-    nrhs = bs[0].shape[0] if n else 1
+    nrhs = _nrhs(bs[0]) if n else 1
     H = (_vp * n)(*[p.handle for p in problems])
     B = (_vp * n)(*[_ptr(b) for b in bs])
     X = (_vp * n)(*[_ptr(x) for x in xs])

@@ -1,8 +1,10 @@
 """Batched solves (rz_solve_batched): problems of uneven size and degree on several
-contexts (streams) solved concurrently, several right-hand sides each.  Every
-batched result must equal the single rz_solve of the same problem and right-hand
-side bit for bit (the kernels are deterministic), reach the tolerance, and the
-first problem is checked against the oracle's direct solve."""
+contexts (streams) solved concurrently, several right-hand sides each (multi-vectors
+of shape (ndofs, nrhs), the right-hand side fastest).  Every batched result must
+equal the single rz_solve of the same problem and right-hand side bit for bit (the
+kernels are deterministic, and a multi-vector solve does the arithmetic of separate
+solves), reach the tolerance, and the first problem is checked against the oracle's
+direct solve."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -29,9 +31,9 @@ def test_batched_equals_single_solves():
     for i, (n, p) in enumerate(SPECS):
         pb = rz.Problem(ctxs[i % 3], n, p, 1.0, 1.0)
         probs.append(pb)
-        b = np.stack([synth.rhs_values(pb.ndofs, 4 * i + r) for r in range(nrhs)])
-        bs.append(torch.as_tensor(b, device="cuda:0"))
-        xs.append(torch.zeros((nrhs, pb.ndofs), dtype=torch.float64, device="cuda:0"))
+        b = np.stack([synth.rhs_values(pb.ndofs, 4 * i + r) for r in range(nrhs)], axis=1)
+        bs.append(torch.as_tensor(np.ascontiguousarray(b), device="cuda:0"))
+        xs.append(torch.zeros((pb.ndofs, nrhs), dtype=torch.float64, device="cuda:0"))
     torch.cuda.synchronize()
     infos = rz.solve_batched(probs, bs, xs)
     torch.cuda.synchronize()
@@ -40,14 +42,14 @@ def test_batched_equals_single_solves():
             assert infos[i][r].rel_res <= 1e-8
             x1 = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
             with torch.cuda.stream(streams[i % 3]):
-                info = pb.solve(bs[i][r], x1)
+                info = pb.solve(bs[i][:, r].contiguous(), x1)
             torch.cuda.synchronize()
             assert info.iters == infos[i][r].iters
-            assert torch.equal(x1, xs[i][r])
+            assert torch.equal(x1, xs[i][:, r])
     n, p = SPECS[0]
     lat = Lattice(Mesh(n, n, n), "grad", p)
     A = asm.with_dirichlet(lat, asm.cartesian_operator(lat, 1.0, 1.0))
-    b0 = np.where(lat.dirichlet_mask(), 0.0, bs[0][0].cpu().numpy())
+    b0 = np.where(lat.dirichlet_mask(), 0.0, bs[0][:, 0].cpu().numpy())
     xs0 = spla.spsolve(A.tocsc(), b0)
-    x0 = xs[0][0].cpu().numpy()
+    x0 = xs[0][:, 0].cpu().numpy()
     assert np.linalg.norm(x0 - xs0) < 1e-6 * np.linalg.norm(xs0)
