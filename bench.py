@@ -182,7 +182,7 @@ def bench_c2(torch, rz, ctx, args, out):
 def bench_multi_rhs(torch, rz, pb, nrhs, patch_ms_1, solve_ms_1, iters_1, reps=3):
     """One rz_solve on nrhs right-hand sides (seeds 0..nrhs-1, interleaved (ndofs,
     nrhs)) against nrhs single solves: wall time, and the patch solve's time per
-    launch (each slot's factor read once for up to four vectors)."""
+    launch (each slot's factor read once for two vectors)."""
     import synth
     log(f"C2 multi-RHS: {nrhs} right-hand sides in one solve")
     B = torch.as_tensor(np.ascontiguousarray(np.stack([synth.rhs_values(pb.ndofs, r) for r in range(nrhs)], axis=1)),
@@ -206,7 +206,7 @@ def bench_multi_rhs(torch, rz, pb, nrhs, patch_ms_1, solve_ms_1, iters_1, reps=3
             "iters": [i.iters for i in infos], "single_rhs_iters": iters_1,
             "max_rel_res": max(i.rel_res for i in infos),
             "patch_ms_per_launch": round(patch_launch, 4), "patch_ms_per_launch_single": round(patch_ms_1, 4),
-            "patch_vectors_per_launch": min(nrhs, 4),
+            "patch_vectors_per_launch": min(nrhs, 2),
             "kernel_ms_per_call": {k: round(v[0], 3) for k, v in kt.items()}}
 
 
@@ -549,7 +549,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--p", type=int, default=7)
-    ap.add_argument("--only", choices=["c2", "c2-apply", "c3", "c3-apply", "c5-apply"], default=None)
+    ap.add_argument("--only", choices=["c2", "c2-apply", "c2-relax", "c3", "c3-apply", "c5-apply"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
@@ -586,6 +586,25 @@ def main():
             pb = rz.Problem(ctx, args.n, args.p, alpha, beta, omega=0.3)
             res["apply_ms_f64"] = time_apply(torch, pb, torch.float64, rz.F64, reps=args.steps)
             res["apply_ms_f32"] = time_apply(torch, pb, torch.float32, rz.F32, reps=args.steps)
+            pb.close()
+        elif piece == "c2-relax":
+            # the relaxation on 1 and on nrhs vectors (patch-solve launches over one and
+            # over several vectors), for kernel traces and HBM counters
+            alpha, beta, _ = workload(args.n, args.p)
+            pb = rz.Problem(ctx, args.n, args.p, alpha, beta, omega=0.3)
+            for k in (1, args.nrhs):
+                r = torch.rand((pb.ndofs, k), dtype=torch.float64, device="cuda:0").squeeze(1)
+                z = torch.empty_like(r)
+                pb.relax(r, z)
+                torch.cuda.synchronize()
+                pb.timing(True)
+                pb.timing_read()
+                for _ in range(args.steps):
+                    pb.relax(r, z)
+                kt = pb.timing_read()
+                pb.timing(False)
+                res[f"nrhs{k}"] = {g: round(v[0] / max(v[1], 1), 4) for g, v in kt.items() if v[1]}
+                del r, z
             pb.close()
         elif piece == "c3":
             res = bench_c3(torch, rz, ctx, args.steps, args.warmup)

@@ -183,7 +183,7 @@ rz_status rz_apply_noalloc(rz_problem *h, const void *x, void *y, rz_dtype t);
  * Cholesky solves (curl) or face-star Jacobi (div) on the condensed interface, plus
  * the potential term through the interface exterior derivative.  Device arrays of
  * sizes[0]*nrhs elements of type t (RZ_F32 uses FP32 factors).  With nrhs > 1 the
- * H(grad) vertex-patch solve reads each patch factor once for up to four vectors. */
+ * H(grad) vertex-patch solve reads each patch factor once per pair of vectors. */
 rz_status rz_relax(rz_problem *h, const void *r, void *z, rz_dtype t, int32_t nrhs);
 
 /* Transfers between the degree-p lattice and the p=1 lattice (sizes[4]) of the

@@ -1993,8 +1993,10 @@ template void launch_condense_grad<double>(const LatDev &, const double *, const
 template void launch_condense_grad<float>(const LatDev &, const float *, const float *, const float *,
                                           const float *, float *, hipStream_t);
 // The patch solve of nvec right-hand sides rt[r] into zb[r].  The register kernel
-// takes up to four vectors per launch, each slot's factor loaded once for all of
-// them; the streaming kernel runs once per vector.
+// takes two vectors per launch, each slot's factor loaded once for both (measured at
+// p = 7 in FP64: 0.351 ms per vector with two per launch, 0.403 with four, whose
+// extra registers leave one wavefront per SIMD, 0.450 alone); the streaming kernel
+// runs once per vector.
 template <typename T>
 int launch_patch_solve_multi(const LatDev &L, const PatchEllDev &E, const T *factor, int nvec, const T *const *rt,
                              T *const *zb, hipStream_t s) {
@@ -2005,15 +2007,14 @@ int launch_patch_solve_multi(const LatDev &L, const PatchEllDev &E, const T *fac
     return 0;
   }
   for (int r0 = 0; r0 < nvec;) {
-    const int left = nvec - r0, nv = left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    const int nv = nvec - r0 >= 2 ? 2 : 1;
     PatchVecs<T> V{};
     for (int r = 0; r < nv; ++r) {
       V.rt[r] = rt[r0 + r];
       V.zb[r] = zb[r0 + r];
     }
-    const int e = nv == 4   ? launch_patch_solve_r_nv<T, 4>(L, E, factor, V, s)
-                  : nv == 2 ? launch_patch_solve_r_nv<T, 2>(L, E, factor, V, s)
-                            : launch_patch_solve_r_nv<T, 1>(L, E, factor, V, s);
+    const int e = nv == 2 ? launch_patch_solve_r_nv<T, 2>(L, E, factor, V, s)
+                          : launch_patch_solve_r_nv<T, 1>(L, E, factor, V, s);
     if (e) return e;
     r0 += nv;
   }

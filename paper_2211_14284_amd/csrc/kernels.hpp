@@ -153,7 +153,7 @@ bool patch_regs_table_matches(int p, const int *pass, int np, int nrows, int ne,
 bool patch_solve_uses_regs(const PatchEllDev &E, int p, size_t elem);
 size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves);
 // Right-hand sides and outputs of one patch-solve launch over several vectors.
-constexpr int kPatchMaxVecs = 4;
+constexpr int kPatchMaxVecs = 2;
 template <typename T>
 struct PatchVecs {
   const T *rt[kPatchMaxVecs];

@@ -702,9 +702,10 @@ rz_status do_vcycle32(rz_problem *h, const float *r, float *z) {
 
 // ---------------------------------------------------------------------------------------
 // Several right-hand sides at once (planar vectors; ids name the right-hand sides,
-// which select their per-vector buffers).  The H(grad) vertex-patch solve runs once
-// for all of them, each slot's factor loaded once (launch_patch_solve_multi); the
-// other steps run per vector, in the same order and arithmetic as for one vector.
+// which select their per-vector buffers).  The H(grad) vertex-patch solve runs on two
+// vectors per launch, each slot's factor loaded once for both
+// (launch_patch_solve_multi); the other steps run per vector, in the same order and
+// arithmetic as for one vector.
 // ---------------------------------------------------------------------------------------
 VecRelaxPtrs<double> vec_ptrs(rz_problem *h, double *) { return vec_ptrs64(h); }
 VecRelaxPtrs<float> vec_ptrs(rz_problem *h, float *) { return vec_ptrs32(h); }
@@ -1989,7 +1990,7 @@ namespace {
 // and the read-back of the scalars the host needs next (copied asynchronously to
 // pinned memory); the caller waits for the stream (or an event) and calls the next
 // step.  The right-hand sides iterate in lockstep: their V-cycles run together
-// (vcycle_multi, one patch solve per relaxation for all of them), every other step
+// (vcycle_multi: the patch solves of a relaxation take two vectors per launch), every other step
 // per vector.  A right-hand side that has converged drops out of the later steps.
 // The CG coefficients are formed on the device (alpha in the update kernel, beta in
 // the direction update), so one host round trip per iteration remains: the

@@ -1,7 +1,7 @@
 """Several right-hand sides in one call (nrhs > 1 in rz_apply, rz_relax, rz_vcycle,
 rz_solve).  Multi-vectors are (ndofs, nrhs) tensors, DoF-major with the right-hand
 side fastest.  A multi-vector call does per vector the arithmetic of a call on that
-vector alone (the H(grad) patch solve reads each factor once for up to four vectors
+vector alone (the H(grad) patch solve reads each factor once for two vectors
 but keeps every vector's sums in the same order), so every result must equal the
 single-vector call bit for bit; one right-hand side of each solve is also checked
 against the oracle's direct solve."""
