@@ -138,6 +138,10 @@ def bench_c2(torch, rz, ctx, args, out):
     a64 = time_apply(torch, pb, torch.float64, rz.F64)
     a32 = time_apply(torch, pb, torch.float32, rz.F32)
     nc = pb.ncells
+    bf = bf16_apply_report(torch, rz, pb, 0, "k_apply_pencil+k_apply_faces (BF16 vectors)")
+    bf.pop("roofline")
+    bf["roofline"] = hbm_roof(2 * nd * 2 + 6 * nc * 4, bf["apply_ms"], "k_apply_pencil+k_apply_faces",
+                              "x in, y out (BF16), 6 FP32 weights per cell")
     out.update({
         "value": round(nd / (ms * 1e-3) / 1e9, 5), "ms_per_step": round(ms, 4),
         "config": {"workload": f"C2: H(grad) Q_{args.p} on {args.n}^3 uniform hex mesh, cellwise log-uniform "
@@ -146,7 +150,7 @@ def bench_c2(torch, rz, ctx, args, out):
         "pcg_ms_f64": round(ms, 4), "iters_f64": infos[-1].iters, "rel_res_f64": max(i.rel_res for i in infos),
         "iters_natural_f64": infos[-1].iters_natural,
         "setup_s_f64": round(setup_s, 3), "omega": pb.omega(),
-        "apply_ms_f64": round(a64, 4), "apply_ms_f32": round(a32, 4),
+        "apply_ms_f64": round(a64, 4), "apply_ms_f32": round(a32, 4), "apply_bf16": bf,
         "apply_gdofs_f64": round(nd / (a64 * 1e-3) / 1e9, 2), "apply_gdofs_f32": round(nd / (a32 * 1e-3) / 1e9, 2),
         "kernel_ms_per_step_f64": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
         "kernel_launches_per_step_f64": {k: v[1] / args.steps for k, v in kt.items()},
@@ -361,8 +365,30 @@ def bench_c5(torch, rz, ctx, steps, warmup, n=24, p=8, aux=True):
                 out[f"apply_gdofs_{nm}"] = round(pb.ndofs / (am * 1e-3) / 1e9, 2)
                 out[f"roofline_apply_{nm}"] = alu_roof(fl, am, peak, "k_apply_quad+k_apply_gather",
                                                        f"sum factorization at q={q} + ~150 flops per point")
+            out["apply_bf16"] = bf16_apply_report(torch, rz, pb, fl, "k_apply_quad_mfma+k_apply_gather")
         pb.close()
     return out
+
+
+def bf16_apply_report(torch, rz, pb, flops, kernel):
+    """BF16 apply: median time, its rate against the FP32 vector peak (the pointwise
+    pullback in FP32 sets its floor; the contractions run on the matrix cores), and
+    its error against the library's FP64 apply of the same BF16 input (the FP64 apply
+    equals the oracle to 1e-12)."""
+    am = time_apply(torch, pb, torch.bfloat16, rz.BF16)
+    x = (torch.rand(pb.ndofs, dtype=torch.float64, device="cuda:0") * 2 - 1).to(torch.bfloat16)
+    y = torch.empty_like(x)
+    pb.apply(x, y, rz.BF16)
+    x64 = x.to(torch.float64)
+    y64 = torch.empty_like(x64)
+    pb.apply(x64, y64, rz.F64)
+    torch.cuda.synchronize()
+    d = y.to(torch.float64) - y64
+    return {"apply_ms": round(am, 4), "apply_gdofs": round(pb.ndofs / (am * 1e-3) / 1e9, 2),
+            "rel_err_2norm_vs_f64": float(d.norm() / y64.norm()),
+            "rel_err_max_vs_f64": float(d.abs().max() / y64.abs().max()),
+            "roofline": alu_roof(flops, am, FP32_PEAK_TFLOPS, kernel,
+                                 "the FP32 apply's flop count (contractions + pointwise), FP32 vector peak")}
 
 
 def bench_batched(torch, rz, nrhs=4, nctx=2, count=64):
@@ -586,6 +612,7 @@ def main():
             pb = rz.Problem(ctx, args.n, args.p, alpha, beta, omega=0.3)
             res["apply_ms_f64"] = time_apply(torch, pb, torch.float64, rz.F64, reps=args.steps)
             res["apply_ms_f32"] = time_apply(torch, pb, torch.float32, rz.F32, reps=args.steps)
+            res["apply_ms_bf16"] = time_apply(torch, pb, torch.bfloat16, rz.BF16, reps=args.steps)
             pb.close()
         elif piece == "c2-relax":
             # the relaxation on 1 and on nrhs vectors (patch-solve launches over one and
@@ -619,6 +646,7 @@ def main():
             pb = rz.Problem(ctx, 24, 8, synth.c5_coefficient_samples(v, 24), 1.0, vertices=v, omega=0.3)
             res["apply_ms_f64"] = time_apply(torch, pb, torch.float64, rz.F64, reps=args.steps)
             res["apply_ms_f32"] = time_apply(torch, pb, torch.float32, rz.F32, reps=args.steps)
+            res["apply_ms_bf16"] = time_apply(torch, pb, torch.bfloat16, rz.BF16, reps=args.steps)
             pb.close()
         torch.cuda.synchronize()
         rz.close_all()

@@ -59,7 +59,9 @@ typedef enum {
   RZ_ERR_NODEVICE = -7       /* compute call on a host-only context             */
 } rz_status;
 
-typedef enum { RZ_F64 = 0, RZ_F32 = 1 } rz_dtype;
+/* Element type of device vectors.  RZ_BF16: bfloat16 (the upper 16 bits of an IEEE
+ * binary32, rounded to nearest even), for rz_apply only (FP32 arithmetic). */
+typedef enum { RZ_F64 = 0, RZ_F32 = 1, RZ_BF16 = 2 } rz_dtype;
 
 /* Mesh: structured nx*ny*nz hexahedra.  vertex_xyz: host array of
  * (nx+1)(ny+1)(nz+1) points (x,y,z), vertex vx + (nx+1)*(vy + (ny+1)*vz);
@@ -158,7 +160,14 @@ rz_status rz_sizes(const rz_problem *h, int64_t sizes[8]);
 
 /* y = A x (Sec. 3.2, eq. sum-factorization: matrix-free, per-cell tensor
  * contractions).  x, y: device arrays of sizes[0]*nrhs elements of type t (nrhs >= 1
- * right-hand sides, interleaved as above); x and y must not overlap. */
+ * right-hand sides, interleaved as above); x and y must not overlap.
+ * RZ_BF16 (H(grad)): BF16 vectors.  On trilinear cells or with sampled coefficients
+ * the 1-D contractions run on the matrix cores with BF16 operands and FP32
+ * accumulation, every contraction's result rounded to BF16 before the next, the
+ * pullback in FP32; on Cartesian cells with cellwise-constant coefficients the sparse
+ * FDM line operators run in FP32 on BF16 loads and stores.  The result carries the
+ * rounding error of BF16 (about 1e-2 relative; the bench reports it against FP64).
+ * RZ_ERR_ARG for H(curl) / H(div). */
 rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t, int32_t nrhs);
 
 /* y = A x exactly as rz_apply with nrhs = 1 (same kernels, same result), for callers that cannot

@@ -516,6 +516,10 @@ template void launch_deinterleave<double>(const double *, double *, int, int64_t
 template void launch_deinterleave<float>(const float *, float *, int, int64_t, int64_t, hipStream_t);
 template void launch_interleave<double>(const double *, double *, int, int64_t, int64_t, hipStream_t);
 template void launch_interleave<float>(const float *, float *, int, int64_t, int64_t, hipStream_t);
+template void launch_deinterleave<unsigned short>(const unsigned short *, unsigned short *, int, int64_t, int64_t,
+                                                  hipStream_t);
+template void launch_interleave<unsigned short>(const unsigned short *, unsigned short *, int, int64_t, int64_t,
+                                                hipStream_t);
 
 void launch_scale_copy(double a, const double *x, double *y, int64_t n, hipStream_t s) {
   k_scale_copy<<<nblk(n), kBS, 0, s>>>(a, x, y, n);

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 
+#include "bf16.hpp"
 #include "kernels.hpp"
 #include "lattice.hpp"
 
@@ -134,10 +135,10 @@ __device__ __forceinline__ int face_row(int b, int c) {
   return c == 0 ? b : (c == P ? P + 1 + b : 2 * (P + 1) + 2 * (c - 1) + (b == P));
 }
 
-template <int P, typename T, int CPC>
+template <int P, typename T, int CPC, typename S = T>
 __global__ void __launch_bounds__(CPC *(P + 1) * (P + 1), 4)
-    k_apply_pencil(LatDev L, Tab1D<P, T> tb, const T *__restrict__ coef, const T *__restrict__ x,
-                   const T *__restrict__ bsub, T *__restrict__ y, T *__restrict__ fb) {
+    k_apply_pencil(LatDev L, Tab1D<P, T> tb, const T *__restrict__ coef, const S *__restrict__ x,
+                   const S *__restrict__ bsub, S *__restrict__ y, T *__restrict__ fb) {
   constexpr int N1 = P + 1, NL = N1 * N1, NT = CPC * NL, W = CPC * P + 1;
   // LDS tile of a cell: element (a, b, c) at a + SB b + SC c, cells CS apart; the
   // padding spreads the lanes of the z-, y- and x-line passes over the banks
@@ -167,9 +168,9 @@ __global__ void __launch_bounds__(CPC *(P + 1) * (P + 1), 4)
     const bool okx = j * CPC + llk < L.nx && !lat_dirichlet_axis(L, 0, X);
     okm = okx ? zmask : 0u;
     // always in bounds (x clamped to the lattice); masked values are never used
-    const T *xc = x + lat_index(L, min(X, L.Nx - 1), Yl, ez * P);
+    const S *xc = x + lat_index(L, min(X, L.Nx - 1), Yl, ez * P);
 #pragma unroll
-    for (int i = 0; i < N1; ++i) xv[i] = xc[i * zst];
+    for (int i = 0; i < N1; ++i) xv[i] = st_load<T, S>(xc[i * zst]);
   };
   load(0);
   T *sx = S0 + llk * CS + la + SB * lb;
@@ -248,8 +249,8 @@ __global__ void __launch_bounds__(CPC *(P + 1) * (P + 1), 4)
       const int X = j * CPC * P + xo;
       if (b > 0 && b < P && c > 0 && c < P) {
         const long g = lat_index(L, X, ey * P + b, ez * P + c);
-        if (lat_dirichlet(L, X, ey * P + b, ez * P + c)) val = x[g];
-        y[g] = bsub ? bsub[g] - val : val;
+        if (lat_dirichlet(L, X, ey * P + b, ez * P + c)) val = st_load<T, S>(x[g]);
+        y[g] = st_store<S, T>(bsub ? st_load<T, S>(bsub[g]) - val : val);
       } else {
         fb[((long)pen * 4 * P + face_row<P>(b, c)) * L.Nx + X] = val;
       }
@@ -262,9 +263,9 @@ __global__ void __launch_bounds__(CPC *(P + 1) * (P + 1), 4)
 // Lattice rows (Y, Z) on a y- or z-vertex plane: the sum of the face-line buffer
 // rows of the (up to 4) rows of cells that hold them, in a fixed order (cell z, then
 // y, lower first); Dirichlet points take x.
-template <int P, typename T>
-__global__ void __launch_bounds__(256) k_apply_faces(LatDev L, const T *__restrict__ x, const T *__restrict__ fb,
-                                                     const T *__restrict__ bsub, T *__restrict__ y, long n) {
+template <int P, typename T, typename S = T>
+__global__ void __launch_bounds__(256) k_apply_faces(LatDev L, const S *__restrict__ x, const T *__restrict__ fb,
+                                                     const S *__restrict__ bsub, S *__restrict__ y, long n) {
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const int X = g % L.Nx;
@@ -304,22 +305,22 @@ __global__ void __launch_bounds__(256) k_apply_faces(LatDev L, const T *__restri
     }
     f[c] = ok ? fb[(((long)cyc + (long)L.ny * czc) * 4 * P + face_row<P>(byc, bzc)) * L.Nx + X] : T(0);
   }
-  const T bs = bsub ? bsub[gi] : T(0);
+  const T bs = bsub ? st_load<T, S>(bsub[gi]) : T(0);
   T val = 0;
   if (dir) {
-    val = x[gi];
+    val = st_load<T, S>(x[gi]);
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c) val += f[c];
   }
-  y[gi] = bsub ? bs - val : val;
+  y[gi] = st_store<S, T>(bsub ? bs - val : val);
 }
 
 // Interface rows of y: sum of the contributions of the (up to 8) cells that hold the
 // DoF, read from the per-cell buffer in a fixed order (z, y, x of the cells);
 // Dirichlet rows copy x.  Rows interior to a cell were written by the cell kernel.
-template <typename T>
-__global__ void k_apply_gather(LatDev L, const T *__restrict__ x, const T *__restrict__ ebuf, T *__restrict__ y,
+template <typename S, typename T>
+__global__ void k_apply_gather(LatDev L, const S *__restrict__ x, const T *__restrict__ ebuf, S *__restrict__ y,
                                long n) {
   long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
@@ -364,7 +365,7 @@ __global__ void k_apply_gather(LatDev L, const T *__restrict__ x, const T *__res
   T acc = 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc += v[q];
-  y[g] = acc;
+  y[g] = st_store<S, T>(acc);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1672,9 +1673,9 @@ inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); 
     default: break;            \
   }
 
-template <int P, typename T>
-static void apply_pencil(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const T *x,
-                         const T *bsub, T *y, T *fb, hipStream_t s) {
+template <int P, typename T, typename S = T>
+static void apply_pencil(const LatDev &L, const T *coef, const double *Bh, const double *Ah, const S *x,
+                         const S *bsub, S *y, T *fb, hipStream_t s) {
   constexpr int NL = (P + 1) * (P + 1);
   // cells per chunk: 512 threads for P = 6, 7 (fewer, larger chunks per row of cells;
   // two blocks per CU), 256 otherwise
@@ -1682,16 +1683,17 @@ static void apply_pencil(const LatDev &L, const T *coef, const double *Bh, const
   constexpr int N1 = P + 1, CS = (N1 + 1) * N1 * N1 + 8;
   const size_t shm = (2 * (size_t)CPC * CS + 2 * NL) * sizeof(T);
   if (shm > 64 * 1024)
-    hipFuncSetAttribute((const void *)k_apply_pencil<P, T, CPC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipFuncSetAttribute((const void *)k_apply_pencil<P, T, CPC, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)shm);
   Tab1D<P, T> tb;
   for (int i = 0; i < (P + 1) * (P + 1); ++i) {
     tb.B[i] = (T)Bh[i];
     tb.A[i] = (T)Ah[i];
   }
-  k_apply_pencil<P, T, CPC><<<(unsigned)(L.ny * L.nz), CPC * NL, shm, s>>>(L, tb, coef, x, bsub, y, fb);
+  k_apply_pencil<P, T, CPC, S><<<(unsigned)(L.ny * L.nz), CPC * NL, shm, s>>>(L, tb, coef, x, bsub, y, fb);
   const long nlines = (long)(L.ny + 1) * L.Nz + (long)(L.nz + 1) * (L.Ny - L.ny - 1);
   const long n = nlines * L.Nx;
-  k_apply_faces<P, T><<<nblocks(n, 256), 256, 0, s>>>(L, x, fb, bsub, y, n);
+  k_apply_faces<P, T, S><<<nblocks(n, 256), 256, 0, s>>>(L, x, fb, bsub, y, n);
 }
 
 template <typename T>
@@ -1702,10 +1704,24 @@ void launch_apply_grad(const LatDev &L, const T *coef, const double *Bh, const d
 #undef RZ_CALL
 }
 
+// BF16 vectors: FP32 weights, arithmetic and face-line buffer
+void launch_apply_grad_bf16(const LatDev &L, const float *coef, const double *Bh, const double *Ah, const bf16_t *x,
+                            bf16_t *y, float *fbuf, hipStream_t s) {
+#define RZ_CALL(Q) apply_pencil<Q, float, bf16_t>(L, coef, Bh, Ah, x, nullptr, y, fbuf, s)
+  RZ_DISPATCH_P(L.p, RZ_CALL)
+#undef RZ_CALL
+}
+
 template <typename T>
 void launch_apply_gather(const LatDev &L, const T *x, const T *ebuf, T *y, hipStream_t s) {
   long n = (long)L.Nx * L.Ny * L.Nz;
-  k_apply_gather<T><<<nblocks(n, 256), 256, 0, s>>>(L, x, ebuf, y, n);
+  k_apply_gather<T, T><<<nblocks(n, 256), 256, 0, s>>>(L, x, ebuf, y, n);
+}
+
+// BF16 vectors, FP32 per-cell buffer (the matrix-core apply)
+void launch_apply_gather_bf16(const LatDev &L, const bf16_t *x, const float *ebuf, bf16_t *y, hipStream_t s) {
+  long n = (long)L.Nx * L.Ny * L.Nz;
+  k_apply_gather<bf16_t, float><<<nblocks(n, 256), 256, 0, s>>>(L, x, ebuf, y, n);
 }
 
 template <int P, typename T>

@@ -164,6 +164,17 @@ int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, c
 template <typename T>
 int launch_patch_solve_multi(const LatDev &L, const PatchEllDev &E, const T *factor, int nvec, const T *const *rt,
                              T *const *zb, hipStream_t s);
+// y = A x on BF16 vectors (Cartesian H(grad)): FP32 weights, arithmetic and face-line
+// buffer, BF16 loads of x and stores of y.
+void launch_apply_grad_bf16(const LatDev &L, const float *coef, const double *Bh, const double *Ah,
+                            const unsigned short *x, unsigned short *y, float *fbuf, hipStream_t s);
+// The same on BF16 vectors x, y (FP32 per-cell buffer): the 1-D contractions on the
+// matrix cores (BF16 operands, FP32 accumulation), the pullback in FP32; then the
+// gather of the interface rows.  Returns non-zero for an unsupported degree.
+int launch_apply_quad_cells_bf16(const LatDev &L, const QuadDev<float> &G, const unsigned short *x,
+                                 unsigned short *y, float *ebuf, hipStream_t s);
+void launch_apply_gather_bf16(const LatDev &L, const unsigned short *x, const float *ebuf, unsigned short *y,
+                              hipStream_t s);
 // Cell phase of y = A x on trilinear cells (interior rows to y, interface rows to
 // ebuf); the interface rows are then summed by launch_apply_gather.  Returns
 // non-zero for an unsupported degree.

@@ -641,6 +641,22 @@ rz_status do_apply32(rz_problem *h, const float *x, float *y) {
   return RZ_OK;
 }
 
+// y = A x on BF16 vectors (H(grad)): matrix-core contractions on trilinear cells or
+// sampled coefficients, FP32 line operators with BF16 loads and stores on Cartesian
+// cells
+rz_status do_apply_bf16(rz_problem *h, const uint16_t *x, uint16_t *y) {
+  Timed t(h, RZ_K_APPLY);
+  hipStream_t s = h->ctx->stream;
+  if (h->quad) {
+    if (launch_apply_quad_cells_bf16(h->L, h->Q32, x, y, h->eb32, s))
+      return fail(h->ctx, RZ_ERR_ARG, "unsupported degree");
+    launch_apply_gather_bf16(h->L, x, h->eb32, y, s);
+  } else {
+    launch_apply_grad_bf16(h->L, h->coef32, h->t.B.data(), h->t.A.data(), x, y, h->eb32, s);
+  }
+  return RZ_OK;
+}
+
 rz_status do_residual32(rz_problem *h, const float *b, const float *x, float *out) {
   if (h->space == RZ_GRAD && !h->quad) {
     Timed t(h, RZ_K_APPLY);
@@ -2512,15 +2528,23 @@ rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t, int32_t nr
   rz_status e = require_device(h);
   if (e) return e;
   if (!x || !y || x == y || nrhs < 1) return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad vectors");
-  if (t != RZ_F64 && t != RZ_F32) return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad dtype");
+  if (t != RZ_F64 && t != RZ_F32 && t != RZ_BF16) return fail(h->ctx, RZ_ERR_ARG, "rz_apply: bad dtype");
+  if (t == RZ_BF16 && h->space != RZ_GRAD) return fail(h->ctx, RZ_ERR_ARG, "rz_apply: BF16 vectors are H(grad) only");
   if (nrhs == 1) {
     if (t == RZ_F64) return do_apply64(h, static_cast<const double *>(x), static_cast<double *>(y));
+    if (t == RZ_BF16) return do_apply_bf16(h, static_cast<const uint16_t *>(x), static_cast<uint16_t *>(y));
     return do_apply32(h, static_cast<const float *>(x), static_cast<float *>(y));
   }
   if ((e = ensure_multi(h, nrhs))) return e;
   hipStream_t s = h->ctx->stream;
   const int64_t n = h->ndofs;
-  if (t == RZ_F64) {
+  if (t == RZ_BF16) {
+    uint16_t *xb = reinterpret_cast<uint16_t *>(h->mb), *yb = reinterpret_cast<uint16_t *>(h->mx);
+    launch_deinterleave<unsigned short>(static_cast<const uint16_t *>(x), xb, nrhs, n, n, s);
+    for (int r = 0; r < nrhs; ++r)
+      if ((e = do_apply_bf16(h, xb + (size_t)r * n, yb + (size_t)r * n))) return e;
+    launch_interleave<unsigned short>(yb, static_cast<uint16_t *>(y), nrhs, n, n, s);
+  } else if (t == RZ_F64) {
     launch_deinterleave<double>(static_cast<const double *>(x), h->mb, nrhs, n, n, s);
     for (int r = 0; r < nrhs; ++r)
       if ((e = do_apply64(h, h->mb + (size_t)r * n, h->mx + (size_t)r * n))) return e;

@@ -22,7 +22,7 @@ lib = ctypes.CDLL(LIB_PATH)
 
 GRAD, CURL, DIV = 0, 1, 2
 SPACES = {"grad": GRAD, "curl": CURL, "div": DIV}
-F64, F32 = 0, 1
+F64, F32, BF16 = 0, 1, 2
 COEF_CONST, COEF_CELL, COEF_SAMPLES = 0, 1, 2
 PREC_F64, PREC_MIXED, PREC_DEFECT = 0, 1, 2
 EXPORT_DOFMAP, EXPORT_PATCH, EXPORT_IC_PATTERN, EXPORT_IC_FACTOR = 0, 1, 2, 3
