@@ -21,7 +21,7 @@ import numpy as np
 from .tables1d import Element1D, gauss_legendre
 from .lattice import Lattice, component_kinds
 from .assemble import (kron3, ref_grad, ref_curl, ref_div, trilinear_jacobian, assemble,
-                       _blockdiag, cell_sizes)
+                       _blockdiag, cell_sizes, _cell_coef)
 
 
 def _broken_1d(el):
@@ -49,15 +49,22 @@ def _diag_mass(el, kinds, weight, xq):
     return d.ravel()
 
 
-def paper_cell_matrix(el: Element1D, space, corners, alpha, beta, q):
-    """P_K of eq. sum-factorization_approx on one trilinear cell."""
-    xq, wq = gauss_legendre(q)
+def paper_cell_matrix(el: Element1D, space, corners, alpha, beta, q, kind="gl"):
+    """P_K of eq. sum-factorization_approx on one trilinear cell, the broken mass
+    diagonals by q-point Gauss-Legendre (kind="gl") or Gauss-Lobatto-Legendre
+    (kind="gll") quadrature per axis.  alpha, beta: scalars, callables of physical
+    points, or 27 reference samples of the cell (triquadratic interpolation)."""
+    if kind == "gl":
+        xq, wq = gauss_legendre(q)
+    else:
+        from .quadrature import rule
+        xq, wq = rule(q, kind)
     W = np.einsum("z,y,x->zyx", wq, wq, wq).ravel()
     X, J = trilinear_jacobian(corners, xq)
     det = np.linalg.det(J)
     Jinv = np.linalg.inv(J)
-    a = alpha(X) if callable(alpha) else np.full(X.shape[0], float(alpha))
-    b = beta(X) if callable(beta) else np.full(X.shape[0], float(beta))
+    a = _cell_coef(alpha, X, xq)
+    b = _cell_coef(beta, X, xq)
     G_ = np.einsum("qrs,qts->qrt", Jinv, Jinv)            # J^{-1} J^{-T}
     H_ = np.einsum("qsr,qst->qrt", J, J) / (det ** 2)[:, None, None]   # J^T J / det^2
     p = el.p
@@ -135,18 +142,51 @@ def separable_cell_matrix(el: Element1D, space, c):
     raise ValueError(space)
 
 
-def paper_operator(lat: Lattice, alpha, beta, q=None):
-    """Global auxiliary operator with the paper's broken-diagonal construction."""
+def paper_operator(lat: Lattice, alpha, beta, q=None, kind="gl"):
+    """Global auxiliary operator with the paper's broken-diagonal construction.
+    alpha, beta: scalar, callable, per-cell array (ncells,) or per-cell samples
+    (ncells, 27)."""
     mesh = lat.mesh
     el = Element1D(lat.p)
     q = q or (lat.p + 2)
     cv = mesh.cell_vertices()
+
+    def pick(c, k):
+        if callable(c) or np.isscalar(c):
+            return c
+        c = np.asarray(c)
+        return c[k] if c.ndim == 2 else float(c[k])
+
     mats = []
     for k in range(mesh.ncells):
-        a = alpha if (callable(alpha) or np.isscalar(alpha)) else float(alpha[k])
-        b = beta if (callable(beta) or np.isscalar(beta)) else float(beta[k])
-        mats.append(paper_cell_matrix(el, lat.space, cv[k], a, b, q))
+        mats.append(paper_cell_matrix(el, lat.space, cv[k], pick(alpha, k), pick(beta, k), q, kind))
     return assemble(lat, mats)
+
+
+def paper_diagonals_grad(el: Element1D, corners, alpha, beta, q, kind="gll"):
+    """The two broken diagonals of one H(grad) cell: diag of the beta-mass in the
+    broken Q_p basis ((p+1)^3 values) and, per NCE component m, diag of the
+    alpha-mass with the metric entry (J^-1 J^-T)_mm in the broken NCE_p basis
+    (p (p+1)^2 values each); x-fastest local order, component m with its DP index
+    along axis m."""
+    if kind == "gl":
+        xq, wq = gauss_legendre(q)
+    else:
+        from .quadrature import rule
+        xq, wq = rule(q, kind)
+    W = np.einsum("z,y,x->zyx", wq, wq, wq).ravel()
+    X, J = trilinear_jacobian(corners, xq)
+    det = np.linalg.det(J)
+    Jinv = np.linalg.inv(J)
+    a = _cell_coef(alpha, X, xq)
+    b = _cell_coef(beta, X, xq)
+    G_ = np.einsum("qrs,qts->qrt", Jinv, Jinv)
+    sh = (q, q, q)
+    p = el.p
+    dm = _diag_mass(el, component_kinds("grad", p)[0], (W * det * b).reshape(sh), xq)
+    kE = component_kinds("curl", p)
+    da = [_diag_mass(el, kE[m], (W * det * a * G_[:, m, m]).reshape(sh), xq) for m in range(3)]
+    return dm, da
 
 
 def separable_operator(lat: Lattice, coefs):

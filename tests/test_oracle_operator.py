@@ -284,3 +284,59 @@ def test_auxiliary_spd_on_distorted(space):
     P = asm.with_dirichlet(lat, auxop.paper_operator(lat, lambda X: 1 + X[:, 0], 0.5)).toarray()
     assert np.abs(P - P.T).max() < 1e-13 * np.abs(P).max()
     assert np.linalg.eigvalsh(P).min() > 0
+
+
+def test_auxiliary_sampled_gll_equals_operator_on_cartesian():
+    # Sec. 3.2: P = A on Cartesian cells with constant coefficients, also when the
+    # coefficients come as 27 reference samples and the diagonals use the GLL rule
+    m = Mesh(2, 2, 1)
+    m.vertices[:, 1] *= 0.6
+    lat = Lattice(m, "grad", 3)
+    A = asm.quadrature_operator(lat, 2.0, 0.3)
+    P = auxop.paper_operator(lat, np.full((m.ncells, 27), 2.0), np.full((m.ncells, 27), 0.3), q=6, kind="gll")
+    assert abs(A - P).max() < 1e-13 * abs(A).max()
+
+
+@pytest.mark.parametrize("p", [2, 5])
+def test_paper_diagonals_closed_form_on_boxes(p):
+    # the broken bases are L2-orthonormal on the reference cell, so on a box with
+    # constant coefficients the weighted mass matrices are multiples of the
+    # identity: beta det J for the Q_p part and alpha det J (J^-1 J^-T)_mm =
+    # alpha V / (2 h_m^2) for NCE component m
+    from oracle.tables1d import Element1D
+    el = Element1D(p)
+    h = np.array([0.5, 0.3, 0.8])
+    corners = np.array([[(k & 1) * h[0], ((k >> 1) & 1) * h[1], (k >> 2) * h[2]] for k in range(8)])
+    V = h.prod()
+    dm, da = auxop.paper_diagonals_grad(el, corners, 1.7, 0.4, p + 2, kind="gll")
+    assert dm.size == (p + 1) ** 3 and np.allclose(dm, 0.4 * V / 8, rtol=1e-12)
+    for m_ in range(3):
+        assert da[m_].size == p * (p + 1) ** 2
+        assert np.allclose(da[m_], 1.7 * V / (2 * h[m_] ** 2), rtol=1e-12)
+
+
+def test_paper_auxiliary_interior_block_diagonal_on_distorted():
+    # the remark of Sec. 4.4 for k = 0: P_II stays diagonal for the broken-diagonal
+    # auxiliary on any cell (the interior FDM functions are unchanged by the broken
+    # transformation and D has a single entry in each interior column); its entries
+    # are dm + sum_m lambda_{i_m} da_m
+    from oracle.tables1d import Element1D
+    from oracle.quadrature import sample_function
+    from oracle.schwarz import interior_mask
+    m = distorted_mesh()
+    lat = Lattice(m, "grad", 4)
+    a = sample_function(m, lambda X: 1 + X[:, 0] ** 2)
+    P = auxop.paper_operator(lat, a, 0.7, q=8, kind="gll").tocsr()
+    I = np.where(interior_mask(lat))[0]
+    PII = P[I][:, I].toarray()
+    assert np.abs(PII - np.diag(np.diag(PII))).max() == 0.0
+    el = Element1D(4)
+    dm, da = auxop.paper_diagonals_grad(el, m.cell_vertices()[0], a[0], 0.7, 8, kind="gll")
+    n1, p = 5, 4
+    g = lat.cell_dofs()[0]
+    for (ia, ib, ic) in [(1, 1, 1), (2, 3, 1), (3, 2, 2)]:
+        k = ia + n1 * (ib + n1 * ic)
+        want = dm[k] + el.lam[ia - 1] * da[0][ia + p * (ib + n1 * ic)] \
+            + el.lam[ib - 1] * da[1][ia + n1 * (ib + p * ic)] + el.lam[ic - 1] * da[2][ia + n1 * (ib + n1 * ic)]
+        # cell 0's interior DoF is owned by cell 0 alone
+        assert abs(P[g[k], g[k]] - want) < 1e-12 * abs(want)
