@@ -270,7 +270,8 @@ def bench_c3(torch, rz, ctx, steps, warmup, n=16, p=6):
 def c5_aux_variants(torch, rz, ctx, pb, b, x, n, p, train_seeds=(10, 11, 12, 13)):
     """FP64 PCG on the C5 problem with three separable auxiliaries: cell averages
     (default), the least-squares fit to the broken diagonals, and an MLP trained on
-    meshes with other perturbation seeds (features -> log(fit / average))."""
+    meshes with other perturbation seeds (features -> log(fit / average)); and with
+    the paper's auxiliary itself (the broken diagonals per DoF)."""
     import synth
     res = {}
     t_fit, feats, base = pb.aux_data()
@@ -316,6 +317,22 @@ def c5_aux_variants(torch, rz, ctx, pb, b, x, n, p, train_seeds=(10, 11, 12, 13)
     res["mlp_train"] = {"cells": int(X.shape[0]), "data_s": round(t_data, 2), "train_s": round(t_train, 2),
                         "final_loss": loss}
     pb.set_aux(base)
+    # the paper's own auxiliary: per-DoF broken diagonals (not separable), its own
+    # problem (setup includes the diagonals of every cell)
+    log("C5: the paper's auxiliary (broken diagonals)")
+    v = synth.perturbed_vertices(n, 3)
+    t0 = time.perf_counter()
+    pp = rz.Problem(ctx, n, p, synth.c5_coefficient_samples(v, n), 1.0, vertices=v, aux=rz.AUX_PAPER_DIAG)
+    torch.cuda.synchronize()
+    setup_pd = time.perf_counter() - t0
+    pp.solve(b, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = pp.solve(b, x)
+    torch.cuda.synchronize()
+    res["paper_diagonals"] = {"iters": info.iters, "pcg_ms": round((time.perf_counter() - t0) * 1e3, 3),
+                              "rel_res": info.rel_res, "omega": pp.omega(), "setup_s": round(setup_pd, 2)}
+    pp.close()
     return res
 
 

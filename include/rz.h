@@ -114,7 +114,21 @@ typedef struct {
   uint64_t lanczos_seed; /* SplitMix64 seed of the Lanczos start vector (default 99) */
   double hdiv_eps;     /* H(div): multiple of the (beta-weighted) mass added to the   *
                         * curl-curl potential problem (remark of Sec. 4.3); 0 = 1e-3 */
+  int32_t aux;         /* auxiliary operator of the relaxation on trilinear cells     *
+                        * (H(grad)): RZ_AUX_CELL_AVG (default) or RZ_AUX_PAPER_DIAG    */
 } rz_opts;
+
+/* Auxiliary operators P of the relaxation (Sec. 3.2).  On Cartesian cells with
+ * cellwise-constant coefficients both equal A exactly (and the library uses its
+ * separable form).  On trilinear cells or with sampled coefficients:
+ *   RZ_AUX_CELL_AVG   the separable form with six weights per cell, cell averages
+ *                     of the coefficient-weighted metric (rz_set_aux replaces them);
+ *   RZ_AUX_PAPER_DIAG the paper's auxiliary, eq. sum-factorization_approx: the
+ *                     beta- and alpha-weighted mass matrices replaced by their
+ *                     diagonals in the broken bases (eq. mass_in_broken_basis),
+ *                     (p+1)^3 + 3 p (p+1)^2 values per cell computed at setup with
+ *                     the apply's quadrature; P_II stays diagonal. */
+enum { RZ_AUX_CELL_AVG = 0, RZ_AUX_PAPER_DIAG = 1 };
 
 /* Results of rz_solve. */
 typedef struct {
@@ -129,7 +143,8 @@ typedef struct {
                            * defect-correction protocol)                                 */
 } rz_solve_info;
 
-/* Fill *o with defaults (space grad, p = 4, FP64, maxit 200, rtol 1e-8, omega 0). */
+/* Fill *o with defaults (space grad, p = 4, FP64, maxit 200, rtol 1e-8, omega 0,
+ * aux RZ_AUX_CELL_AVG). */
 void rz_opts_default(rz_opts *o);
 
 /* Create a context on HIP device `device` and stream `stream` (a hipStream_t, may
@@ -261,6 +276,10 @@ rz_status rz_sync(rz_problem *h);
  *   RZ_EXPORT_STATS      int64 pair (H(grad)): lower non-zeros (diagonal included)
  *                        and rows of the IC factors of all non-empty vertex patches
  *                        (the factor values the patch solve needs, without padding)
+ *   RZ_EXPORT_PAPER_DIAG double: the broken diagonals of cell `index` with
+ *                        RZ_AUX_PAPER_DIAG, (p+1)^3 (beta-mass, x fastest) then
+ *                        3 blocks of p (p+1)^2 (alpha-mass of NCE component m, its
+ *                        DP index along axis m)
  *   RZ_EXPORT_EDGE_PATCH int64: edge id, then the DoFs (ascending) of non-empty
  *                        edge-star patch `index` of H(curl) (or of the NCE_p
  *                        potential problem of H(div)); edge ids run over the axis
@@ -269,7 +288,8 @@ rz_status rz_sync(rz_problem *h);
 enum {
   RZ_EXPORT_DOFMAP = 0, RZ_EXPORT_PATCH = 1, RZ_EXPORT_IC_PATTERN = 2,
   RZ_EXPORT_IC_FACTOR = 3, RZ_EXPORT_TABLES1D = 4, RZ_EXPORT_AUXCOEF = 5,
-  RZ_EXPORT_OMEGA = 6, RZ_EXPORT_PATCH_KERNEL = 7, RZ_EXPORT_EDGE_PATCH = 8, RZ_EXPORT_STATS = 9
+  RZ_EXPORT_OMEGA = 6, RZ_EXPORT_PATCH_KERNEL = 7, RZ_EXPORT_EDGE_PATCH = 8, RZ_EXPORT_STATS = 9,
+  RZ_EXPORT_PAPER_DIAG = 10
 };
 rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *bytes);
 

@@ -112,9 +112,9 @@ bool q1_cell_matrix(const double *corners, const double *as, const double *bs, c
   return true;
 }
 
-void christoffel(const Tables1D &t, const QuadTables &Q, std::vector<double> &kP, std::vector<double> &kD) {
-  const int p = t.p, n = p + 1, q = Q.q;
-  // inverse of the broken transformation G (Gauss-Jordan with partial pivoting)
+// inverse of the broken transformation G (Gauss-Jordan with partial pivoting)
+static std::vector<double> broken_inverse(const Tables1D &t) {
+  const int n = t.p + 1;
   std::vector<double> G(t.G), Gi(n * n, 0.0);
   for (int i = 0; i < n; ++i) Gi[i * n + i] = 1.0;
   for (int c = 0; c < n; ++c) {
@@ -139,6 +139,33 @@ void christoffel(const Tables1D &t, const QuadTables &Q, std::vector<double> &kP
         }
       }
   }
+  return Gi;
+}
+
+// squares of the broken degree-p functions (fP, q x (p+1): s(x) G^-1) and of the
+// degree-(p-1) L2 basis (fD, q x p: r_0 = 2^-1/2, r_k = lambda_k^-1/2 s_k') at Q.xq
+static void broken_squares(const Tables1D &t, const QuadTables &Q, std::vector<double> &fP, std::vector<double> &fD) {
+  const int p = t.p, n = p + 1, q = Q.q;
+  const std::vector<double> Gi = broken_inverse(t);
+  fP.assign((size_t)q * n, 0.0);
+  fD.assign((size_t)q * p, 0.0);
+  for (int i = 0; i < q; ++i) {
+    for (int k = 0; k < n; ++k) {
+      double v = 0.0;
+      for (int j = 0; j < n; ++j) v += Q.Bq[i * n + j] * Gi[j * n + k];
+      fP[(size_t)i * n + k] = v * v;
+    }
+    fD[(size_t)i * p] = 0.5;
+    for (int k = 1; k < p; ++k) {
+      const double r = Q.Dq[i * n + k] / std::sqrt(t.lam[k - 1]);
+      fD[(size_t)i * p + k] = r * r;
+    }
+  }
+}
+
+void christoffel(const Tables1D &t, const QuadTables &Q, std::vector<double> &kP, std::vector<double> &kD) {
+  const int p = t.p, n = p + 1, q = Q.q;
+  const std::vector<double> Gi = broken_inverse(t);
   kP.assign(q, 0.0);
   kD.assign(q, 0.0);
   for (int i = 0; i < q; ++i) {
@@ -185,6 +212,68 @@ bool fit_targets(const double *corners, const double *as, const double *bs, cons
       }
   for (int s = 0; s < 3; ++s) out[s] = sig[s];
   for (int s = 0; s < 3; ++s) out[3 + s] = mu;
+  return true;
+}
+
+PaperDiagTables::PaperDiagTables(const Tables1D &t, const QuadTables &Q) : p(t.p), q(Q.q) {
+  broken_squares(t, Q, fP, fD);
+}
+
+// d[l][j][i] = sum_{z,y,x} W[z][y][x] f2[z][l] f1[y][j] f0[x][i] (sum factorised: x,
+// then y, then z), f_a with n_a columns; d x fastest
+static void diag_contract(const std::vector<double> &W, int q, const double *f0, int n0, const double *f1, int n1,
+                          const double *f2, int n2, double *d) {
+  std::vector<double> t1((size_t)q * q * n0), t2((size_t)q * n1 * n0);
+  for (int z = 0; z < q; ++z)
+    for (int y = 0; y < q; ++y)
+      for (int i = 0; i < n0; ++i) {
+        double s = 0.0;
+        for (int x = 0; x < q; ++x) s += W[((size_t)z * q + y) * q + x] * f0[x * n0 + i];
+        t1[((size_t)z * q + y) * n0 + i] = s;
+      }
+  for (int z = 0; z < q; ++z)
+    for (int j = 0; j < n1; ++j)
+      for (int i = 0; i < n0; ++i) {
+        double s = 0.0;
+        for (int y = 0; y < q; ++y) s += t1[((size_t)z * q + y) * n0 + i] * f1[y * n1 + j];
+        t2[((size_t)z * n1 + j) * n0 + i] = s;
+      }
+  for (int l = 0; l < n2; ++l)
+    for (int j = 0; j < n1; ++j)
+      for (int i = 0; i < n0; ++i) {
+        double s = 0.0;
+        for (int z = 0; z < q; ++z) s += t2[((size_t)z * n1 + j) * n0 + i] * f2[z * n2 + l];
+        d[((size_t)l * n1 + j) * n0 + i] = s;
+      }
+}
+
+bool paper_diagonals(const double *corners, const double *as, const double *bs, const QuadTables &Q,
+                     const PaperDiagTables &T, double *dm, double *da) {
+  const int q = Q.q, p = T.p, n = p + 1;
+  const size_t nq = (size_t)q * q * q;
+  std::vector<double> wb(nq), wa[3] = {std::vector<double>(nq), std::vector<double>(nq), std::vector<double>(nq)};
+  for (int k = 0; k < q; ++k)
+    for (int j = 0; j < q; ++j)
+      for (int i = 0; i < q; ++i) {
+        const double xi[3] = {Q.xq[i], Q.xq[j], Q.xq[k]};
+        double J[9], Ji[9];
+        const double det = trilinear_jacobian(corners, xi, J);
+        if (!(det > 0)) return false;
+        inverse3(J, det, Ji);
+        const double al = interp27(as, Q, i, j, k), be = interp27(bs, Q, i, j, k);
+        if (!(al > 0) || !(be > 0)) return false;
+        const double w = Q.wq[i] * Q.wq[j] * Q.wq[k] * det;
+        const size_t o = ((size_t)k * q + j) * q + i;
+        wb[o] = w * be;
+        for (int m = 0; m < 3; ++m)
+          wa[m][o] = w * al * (Ji[3 * m] * Ji[3 * m] + Ji[3 * m + 1] * Ji[3 * m + 1] + Ji[3 * m + 2] * Ji[3 * m + 2]);
+      }
+  const double *fP = T.fP.data(), *fD = T.fD.data();
+  diag_contract(wb, q, fP, n, fP, n, fP, n, dm);
+  const size_t nc = (size_t)p * n * n;
+  diag_contract(wa[0], q, fD, p, fP, n, fP, n, da);
+  diag_contract(wa[1], q, fP, n, fD, p, fP, n, da + nc);
+  diag_contract(wa[2], q, fP, n, fP, n, fD, p, da + 2 * nc);
   return true;
 }
 

@@ -44,6 +44,23 @@ void christoffel(const Tables1D &t, const QuadTables &Q, std::vector<double> &kP
 bool fit_targets(const double *corners, const double *as, const double *bs, const QuadTables &Q,
                  const std::vector<double> &kP, const std::vector<double> &kD, double out[6]);
 
+// The paper's auxiliary operator on a trilinear cell (Sec. 3.2, eqs.
+// mass_in_broken_basis and sum-factorization_approx): the diagonals of the weighted
+// mass matrices in the broken bases, by the quadrature Q.  PaperDiagTables holds the
+// squares of the broken 1-D functions at the points (per degree).
+struct PaperDiagTables {
+  int p = 0, q = 0;
+  std::vector<double> fP, fD;  // q x (p+1) broken P_p squares, q x p DP_{p-1} squares
+  PaperDiagTables() = default;
+  PaperDiagTables(const Tables1D &t, const QuadTables &Q);
+};
+// dm: (p+1)^3 values, diag of the beta-mass in the broken Q_p basis; da: three blocks
+// of p (p+1)^2, diag of the alpha-mass weighted by (J^-1 J^-T)_mm in the broken basis
+// of NCE_p component m (its DP index along axis m); x-fastest local order.  Returns
+// false if det J or an interpolated coefficient is not positive at a point.
+bool paper_diagonals(const double *corners, const double *as, const double *bs, const QuadTables &Q,
+                     const PaperDiagTables &T, double *dm, double *da);
+
 // 51 dimensionless features of a cell: corner offsets from the centroid over the
 // mean edge length minus those of a cube (24), log alpha samples minus their mean (27).
 void cell_features(const double *corners, const double *as, double out[51]);

@@ -1227,11 +1227,113 @@ __device__ double cell_schur_value(int p, const double *B, const double *A, cons
   return v - s[du] * A[u[du] * n1 + t[du]] * s[dw] * A[t[dw] * n1 + w[dw]] / dd;
 }
 
+// The paper's auxiliary (eq. sum-factorization_approx) on one cell from its broken
+// diagonals: P_K(u, w) = sum over broken indices of dm Gbar Gbar (x3) + sum_m sum_r
+// D[r][u_m] D[r][w_m] da_m (Gbar Gbar along the other two axes).  Gbar is the
+// identity on interior indices and mixes the two end functions, so along an axis
+// the broken indices are u_d (interior, w_d = u_d) or both ends (u_d and w_d ends);
+// along the DP axis of component m the row r is u_m or w_m where one is interior,
+// every row when both are ends.
+struct PdCell {
+  const double *dm, *da;  // this cell's (p+1)^3 and 3 p (p+1)^2 diagonals
+  const double *G, *D;    // (p+1)^2 broken transformation, p x (p+1) D-hat
+};
+
+// broken indices along one axis for local coordinates (a, b) and their G G factors
+__device__ __forceinline__ int pd_axis(int p, const double *G, int a, int b, int idx[2], double f[2]) {
+  const int n1 = p + 1;
+  if (!on_end(p, a) || !on_end(p, b)) {
+    if (a != b) return 0;
+    idx[0] = a;
+    f[0] = 1.0;
+    return 1;
+  }
+  idx[0] = 0;
+  f[0] = G[a] * G[b];
+  idx[1] = p;
+  f[1] = G[p * n1 + a] * G[p * n1 + b];
+  return 2;
+}
+
+__device__ double pd_entry(int p, const PdCell &C, const int u[3], const int w[3]) {
+  const int n1 = p + 1;
+  int ix[3][2];
+  double fx[3][2];
+  int nb[3];
+  for (int d = 0; d < 3; ++d) nb[d] = pd_axis(p, C.G, u[d], w[d], ix[d], fx[d]);
+  double v = 0.0;
+  if (nb[0] && nb[1] && nb[2])
+    for (int c = 0; c < nb[2]; ++c)
+      for (int b = 0; b < nb[1]; ++b)
+        for (int a = 0; a < nb[0]; ++a)
+          v += C.dm[ix[0][a] + n1 * (ix[1][b] + n1 * ix[2][c])] * fx[0][a] * fx[1][b] * fx[2][c];
+  const long nc = (long)p * n1 * n1;
+  for (int m = 0; m < 3; ++m) {
+    const int e1 = (m + 1) % 3, e2 = (m + 2) % 3;
+    if (!nb[e1] || !nb[e2]) continue;
+    int r0, r1;
+    if (!on_end(p, u[m])) {
+      r0 = r1 = u[m];
+    } else if (!on_end(p, w[m])) {
+      r0 = r1 = w[m];
+    } else {
+      r0 = 0;
+      r1 = p - 1;
+    }
+    const double *da = C.da + m * nc;
+    for (int r = r0; r <= r1; ++r) {
+      const double dd = C.D[r * n1 + u[m]] * C.D[r * n1 + w[m]];
+      if (dd == 0.0) continue;
+      for (int b2 = 0; b2 < nb[e2]; ++b2)
+        for (int b1 = 0; b1 < nb[e1]; ++b1) {
+          int t[3];
+          t[m] = r;
+          t[e1] = ix[e1][b1];
+          t[e2] = ix[e2][b2];
+          // component m: extent p along m, p + 1 along the others, x fastest
+          const int ex = m == 0 ? p : n1, ey = m == 1 ? p : n1;
+          v += da[t[0] + ex * (t[1] + ey * t[2])] * dd * fx[e1][b1] * fx[e2][b2];
+        }
+    }
+  }
+  return v;
+}
+
+// one cell's Schur-complement entry of interface DoFs u, w (cell_schur_value with
+// the paper's auxiliary): P_GG(u, w) minus the interior DoFs coupled to both
+__device__ double pd_cell_schur(int p, const PdCell &C, const int u[3], const int w[3]) {
+  double v = pd_entry(p, C, u, w);
+  if (p < 2) return v;
+  int nu = on_end(p, u[0]) + on_end(p, u[1]) + on_end(p, u[2]);
+  int nw = on_end(p, w[0]) + on_end(p, w[1]) + on_end(p, w[2]);
+  if (nu != 1 || nw != 1) return v;
+  int du = on_end(p, u[0]) ? 0 : (on_end(p, u[1]) ? 1 : 2);
+  int dw = on_end(p, w[0]) ? 0 : (on_end(p, w[1]) ? 1 : 2);
+  if (du == dw) {
+    for (int e = 0; e < 3; ++e)
+      if (e != du && u[e] != w[e]) return v;
+    for (int i = 1; i < p; ++i) {
+      int t[3] = {u[0], u[1], u[2]};
+      t[du] = i;
+      v -= pd_entry(p, C, u, t) * pd_entry(p, C, t, w) / pd_entry(p, C, t, t);
+    }
+    return v;
+  }
+  int e = 3 - du - dw;
+  if (u[e] != w[e]) return v;
+  int t[3];
+  t[du] = w[du];
+  t[dw] = u[dw];
+  t[e] = u[e];
+  return v - pd_entry(p, C, u, t) * pd_entry(p, C, t, w) / pd_entry(p, C, t, t);
+}
+
 __global__ void __launch_bounds__(256) k_patch_factor(LatDev L, PatchDev P, const int *__restrict__ erow,
                                                        const double *__restrict__ coef,
                                                        const double *__restrict__ Bg, const double *__restrict__ Ag,
-                                                       const double *__restrict__ lamg, double *__restrict__ f64,
-                                                       float *__restrict__ f32, int *status) {
+                                                       const double *__restrict__ lamg, PdDev pd,
+                                                       double *__restrict__ f64, float *__restrict__ f32,
+                                                       int *status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *S = reinterpret_cast<double *>(smem_raw);
   const int p = L.p, n1 = p + 1;
@@ -1281,8 +1383,13 @@ __global__ void __launch_bounds__(256) k_patch_factor(LatDev L, PatchDev P, cons
         if (!cell_schur_coupled(p, u, w)) continue;
         ok = true;
         int cid = cc[0] + L.nx * (cc[1] + L.ny * cc[2]);
-        double s[3] = {coef[6 * cid], coef[6 * cid + 1], coef[6 * cid + 2]};
-        val += cell_schur_value(p, sB, sA, sl, s, coef[6 * cid + 3], u, w);
+        if (pd.dm) {
+          const PdCell C{pd.dm + (long)cid * n1 * n1 * n1, pd.da + (long)cid * 3 * p * n1 * n1, pd.G, pd.D};
+          val += pd_cell_schur(p, C, u, w);
+        } else {
+          double s[3] = {coef[6 * cid], coef[6 * cid + 1], coef[6 * cid + 2]};
+          val += cell_schur_value(p, sB, sA, sl, s, coef[6 * cid + 3], u, w);
+        }
       }
     }
     S[k] = ok ? val : 0.0;
@@ -1745,6 +1852,27 @@ static void expand_p(const LatDev &L, const T *coef, const T *A, const T *lam, c
   if (ni > 0) k_expand_interior_rows<P, T><<<(unsigned)(ni / (P > 1 ? P - 1 : 1)), bs, 0, s>>>(L, coef, A, lam, r, z, o);
 }
 
+template <int P, typename T>
+static void expand_plane_p(const LatDev &L, const T *r, const T *zbuf, T *z, ExpandOut<T> o, hipStream_t s) {
+  const long np = (long)(L.ny + 1) * L.Nz + (long)(L.nz + 1) * (L.Ny - L.ny - 1);
+  const long ni = (long)L.ny * (P - 1) * L.nz * (P - 1);
+  const int bs = L.Nx >= 256 ? 256 : ((L.Nx + 63) / 64) * 64;
+  const long nxf = ni * (L.nx + 1);
+  k_expand_plane_rows<P, T><<<(unsigned)(np + (long)nblocks(nxf, bs)), bs, 0, s>>>(L, r, zbuf, z, o, np, nxf);
+}
+
+template <typename T>
+void launch_expand_plane_grad(const LatDev &L, const T *r, const T *zbuf, T *z, T scale, T w, T *acc, hipStream_t s) {
+  const ExpandOut<T> o{scale, w, acc};
+#define RZ_CALL(Q) expand_plane_p<Q, T>(L, r, zbuf, z, o, s)
+  RZ_DISPATCH_P(L.p, RZ_CALL)
+#undef RZ_CALL
+}
+template void launch_expand_plane_grad<double>(const LatDev &, const double *, const double *, double *, double,
+                                               double, double *, hipStream_t);
+template void launch_expand_plane_grad<float>(const LatDev &, const float *, const float *, float *, float, float,
+                                              float *, hipStream_t);
+
 template <typename T>
 void launch_condense_grad(const LatDev &L, const T *coef, const T *A, const T *lam, const T *r, T *rt,
                           hipStream_t s) {
@@ -1922,13 +2050,13 @@ void launch_expand_grad(const LatDev &L, const PatchDev &P, const T *coef, const
 }
 
 void launch_patch_factor(const LatDev &L, const PatchDev &P, const double *coef, const double *B,
-                         const double *A, const double *lam, double *f64, float *f32, int *status,
+                         const double *A, const double *lam, const PdDev &pd, double *f64, float *f32, int *status,
                          hipStream_t s) {
   long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
   const int n1 = L.p + 1;
   size_t shm = sizeof(double) * (P.nnz + 2 * n1 * n1 + n1) + P.nnz;
   if (shm > 65536) hipFuncSetAttribute((const void *)k_patch_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  k_patch_factor<<<(unsigned)nv, 256, shm, s>>>(L, P, P.erow, coef, B, A, lam, f64, f32, status);
+  k_patch_factor<<<(unsigned)nv, 256, shm, s>>>(L, P, P.erow, coef, B, A, lam, pd, f64, f32, status);
 }
 
 static long max_face_points(const LatDev &L) {

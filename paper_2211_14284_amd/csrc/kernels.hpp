@@ -223,11 +223,34 @@ template <typename T>
 void launch_expand_grad(const LatDev &L, const PatchDev &P, const T *coef, const T *A,
                         const T *lam, const T *r, const T *zbuf, T *z, T scale, T w, T *acc, hipStream_t s);
 
+// The paper's auxiliary on trilinear cells (eq. sum-factorization_approx): per-cell
+// broken diagonals (FP64, setup) -- dm (p+1)^3 and da 3 p (p+1)^2 per cell -- with the
+// 1-D broken transformation G ((p+1)^2) and D-hat (p x (p+1)); dm == nullptr selects
+// the separable per-cell weights.
+struct PdDev {
+  const double *dm, *da, *G, *D;
+};
+// Solve-time data of that auxiliary: P_II diagonal and w_d(t) = sqrt(lambda_{t_d})
+// da_d(t) at cell-interior lattice points, D-hat in the compute precision.
+template <typename T>
+struct PdSolve {
+  const T *pii, *w0, *w1, *w2, *D;
+};
+template <typename T>
+void launch_condense_pd(const LatDev &L, const PdSolve<T> &S, const T *r, T *rt, hipStream_t s);
+template <typename T>
+void launch_expand_interior_pd(const LatDev &L, const PdSolve<T> &S, const T *r, T *z, T scale, T w, T *acc,
+                               hipStream_t s);
+// the plane part of launch_expand_grad alone (patch sums at plane points, Dirichlet
+// rows copy r; z = scale * value, or acc += w * value as well)
+template <typename T>
+void launch_expand_plane_grad(const LatDev &L, const T *r, const T *zbuf, T *z, T scale, T w, T *acc, hipStream_t s);
+
 // IC factorisation of every vertex patch (FP64) on the static-condensation
 // pattern; writes the FP64 factor and an FP32 copy; *status = 0 or the first
 // failing patch + 1 (pivot <= 0).
 void launch_patch_factor(const LatDev &L, const PatchDev &P, const double *coef, const double *B,
-                         const double *A, const double *lam, double *f64, float *f32, int *status,
+                         const double *A, const double *lam, const PdDev &pd, double *f64, float *f32, int *status,
                          hipStream_t s);
 
 // z_D = r_D on Dirichlet rows of the Q_p lattice (r == nullptr: z_D = 0).

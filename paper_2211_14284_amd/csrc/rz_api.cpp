@@ -183,6 +183,13 @@ struct rz_problem {
   std::vector<void *> mallocs;
   double *mb = nullptr, *mx = nullptr, *mvec = nullptr, *mzb64 = nullptr, *mdots = nullptr, *mhdots = nullptr;
   float *mf32 = nullptr, *mzb32 = nullptr;
+  // the paper's auxiliary on trilinear cells (broken diagonals, eq.
+  // sum-factorization_approx) instead of the separable per-cell weights
+  bool pd = false;
+  std::vector<double> pd_host_dm, pd_host_da;   // per cell, until uploaded
+  double *pd_dm = nullptr, *pd_da = nullptr, *pd_G = nullptr, *pd_D64 = nullptr;
+  PdSolve<double> pds64{};
+  PdSolve<float> pds32{};
   // per-kernel timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -291,6 +298,11 @@ RhsBufs rhs_bufs(rz_problem *h, int i) {
   return {v,         v + n,     v + 2 * n, v + 3 * n, v + 4 * n, v + 5 * n, v + 6 * n,
           h->mzb64 ? h->mzb64 + k * h->mnzb : nullptr,         h->mdots + 8 * k, h->mhdots + 8 * k,
           f,         h->mzb32 ? h->mzb32 + k * h->mnzb : nullptr,          f + n};
+}
+
+template <typename T>
+std::vector<T> as_type(const std::vector<double> &v) {
+  return std::vector<T>(v.begin(), v.end());
 }
 
 bool lat_dirichlet_h(const rz_problem *h, int X, int Y, int Z) {
@@ -488,13 +500,35 @@ rz_status do_residual64(rz_problem *h, const double *b, const double *x, double 
 }
 
 // z = scale * M r; with acc: acc += w * M r (z then holds only the plane values)
+const PdSolve<double> &pd_solve(const rz_problem *h, double *) { return h->pds64; }
+const PdSolve<float> &pd_solve(const rz_problem *h, float *) { return h->pds32; }
+
+// relaxation steps 1 and 4 of the H(grad) path: the separable weights, or the
+// paper's auxiliary (per-point data)
+template <typename T>
+void condense_any(rz_problem *h, const T *coef, const T *A, const T *lam, const T *r, T *rt) {
+  if (h->pd) launch_condense_pd<T>(h->L, pd_solve(h, (T *)nullptr), r, rt, h->ctx->stream);
+  else launch_condense_grad<T>(h->L, coef, A, lam, r, rt, h->ctx->stream);
+}
+template <typename T>
+void expand_any(rz_problem *h, const T *coef, const T *A, const T *lam, const T *r, const T *zb, T *z, T scale, T w,
+                T *acc) {
+  hipStream_t s = h->ctx->stream;
+  if (h->pd) {
+    launch_expand_plane_grad<T>(h->L, r, zb, z, scale, w, acc, s);
+    launch_expand_interior_pd<T>(h->L, pd_solve(h, (T *)nullptr), r, z, scale, w, acc, s);
+  } else {
+    launch_expand_grad<T>(h->L, h->P, coef, A, lam, r, zb, z, scale, w, acc, s);
+  }
+}
+
 template <typename T>
 rz_status relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T *f, T *rt, T *zb,
                       const T *r, T *z, T scale = T(1), T w = T(0), T *acc = nullptr) {
   hipStream_t s = h->ctx->stream;
   {
     Timed t(h, RZ_K_CONDENSE);
-    launch_condense_grad<T>(h->L, coef, A, lam, r, rt, s);
+    condense_any<T>(h, coef, A, lam, r, rt);
   }
   {
     Timed t(h, RZ_K_PATCH);
@@ -502,7 +536,7 @@ rz_status relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, co
   }
   {
     Timed t(h, RZ_K_EXPAND);
-    launch_expand_grad<T>(h->L, h->P, coef, A, lam, r, zb, z, scale, w, acc, s);
+    expand_any<T>(h, coef, A, lam, r, zb, z, scale, w, acc);
   }
   return RZ_OK;
 }
@@ -764,7 +798,7 @@ rz_status relax_multi(rz_problem *h, int nv, const int *ids, const T *const *r, 
   }
   {
     Timed t(h, RZ_K_CONDENSE);
-    for (int j = 0; j < nv; ++j) launch_condense_grad<T>(h->L, coef, A, lam, r[j], rt[j], s);
+    for (int j = 0; j < nv; ++j) condense_any<T>(h, coef, A, lam, r[j], rt[j]);
   }
   {
     Timed t(h, RZ_K_PATCH);
@@ -774,7 +808,7 @@ rz_status relax_multi(rz_problem *h, int nv, const int *ids, const T *const *r, 
   {
     Timed t(h, RZ_K_EXPAND);
     for (int j = 0; j < nv; ++j) {
-      launch_expand_grad<T>(h->L, h->P, coef, A, lam, r[j], zb[j], z[j], scale, w, acc ? acc[j] : nullptr, s);
+      expand_any<T>(h, coef, A, lam, r[j], zb[j], z[j], scale, w, acc ? acc[j] : nullptr);
       post(j);
     }
   }
@@ -1235,6 +1269,88 @@ rz_status require_device(const rz_problem *h) {
 namespace {
 
 // symbolic patch pattern, free DoFs, non-empty patches, lattice description
+PdDev pd_dev(const rz_problem *h) {
+  if (!h->pd) return PdDev{nullptr, nullptr, nullptr, nullptr};
+  return PdDev{h->pd_dm, h->pd_da, h->pd_G, h->pd_D64};
+}
+
+// The broken diagonals of every cell (host, FP64, cells split over the host's
+// threads): (p+1)^3 + 3 p (p+1)^2 values per cell.
+bool paper_diagonals_all(rz_problem *h) {
+  const int p = h->p, n1 = p + 1;
+  const size_t nm = (size_t)n1 * n1 * n1, na = 3 * (size_t)p * n1 * n1;
+  h->pd_host_dm.assign(nm * h->ncells, 0.0);
+  h->pd_host_da.assign(na * h->ncells, 0.0);
+  const PaperDiagTables T(h->t, h->qt);
+  const int nvx = h->nx + 1, nvy = h->ny + 1;
+  unsigned nt = std::thread::hardware_concurrency();
+  nt = std::max(1u, std::min(nt, 32u));
+  std::vector<char> ok(nt, 1);
+  std::vector<std::thread> pool;
+  for (unsigned w = 0; w < nt; ++w)
+    pool.emplace_back([&, w] {
+      for (int64_t c = w; c < h->ncells; c += nt) {
+        const int cx = c % h->nx, cy = (c / h->nx) % h->ny, cz = c / ((int64_t)h->nx * h->ny);
+        double corners[24];
+        for (int k = 0; k < 8; ++k) {
+          const int64_t vid = (cx + (k & 1)) + nvx * ((cy + ((k >> 1) & 1)) + (int64_t)nvy * (cz + (k >> 2)));
+          for (int r = 0; r < 3; ++r) corners[3 * k + r] = h->vert[3 * vid + r];
+        }
+        if (!paper_diagonals(corners, &h->asmp[27 * c], &h->bsmp[27 * c], h->qt, T, &h->pd_host_dm[nm * c],
+                             &h->pd_host_da[na * c]))
+          ok[w] = 0;
+      }
+    });
+  for (auto &t : pool) t.join();
+  for (char o : ok)
+    if (!o) return false;
+  return true;
+}
+
+// Device data of the paper's auxiliary: the per-cell diagonals and 1-D tables (for
+// the patch factorisation), and at every cell-interior lattice point t the P_II
+// diagonal dm + sum_d lambda_{t_d} da_d and w_d = sqrt(lambda_{t_d}) da_d (for the
+// condensation and extension), FP64 and FP32.
+rz_status upload_paper_diagonals(rz_problem *h) {
+  const int p = h->p, n1 = p + 1;
+  const size_t nm = (size_t)n1 * n1 * n1, na = 3 * (size_t)p * n1 * n1, nc = (size_t)p * n1 * n1;
+  const int64_t N = h->ndofs;
+  std::vector<double> pii(N, 1.0), w[3] = {std::vector<double>(N, 0.0), std::vector<double>(N, 0.0),
+                                            std::vector<double>(N, 0.0)};
+  for (int64_t c = 0; c < h->ncells; ++c) {
+    const int cx = c % h->nx, cy = (c / h->nx) % h->ny, cz = c / ((int64_t)h->nx * h->ny);
+    const double *dm = &h->pd_host_dm[nm * c], *da = &h->pd_host_da[na * c];
+    for (int k = 1; k < p; ++k)
+      for (int j = 1; j < p; ++j)
+        for (int i = 1; i < p; ++i) {
+          const int64_t g = (int64_t)(cx * p + i) + h->Nx * ((int64_t)(cy * p + j) + (int64_t)h->Ny * (cz * p + k));
+          const double dx = da[i + p * (j + n1 * k)], dy = da[nc + i + n1 * (j + p * k)],
+                       dz = da[2 * nc + i + n1 * (j + n1 * k)];
+          const double li = h->t.lam[i - 1], lj = h->t.lam[j - 1], lk = h->t.lam[k - 1];
+          pii[g] = dm[i + n1 * (j + n1 * k)] + li * dx + lj * dy + lk * dz;
+          w[0][g] = std::sqrt(li) * dx;
+          w[1][g] = std::sqrt(lj) * dy;
+          w[2][g] = std::sqrt(lk) * dz;
+        }
+  }
+  rz_status e;
+  double *pii64, *w64[3], *D64;
+  float *pii32, *w32[3], *D32;
+  if ((e = upload(h, &h->pd_dm, h->pd_host_dm)) || (e = upload(h, &h->pd_da, h->pd_host_da)) ||
+      (e = upload(h, &h->pd_G, h->t.G)) || (e = upload(h, &D64, h->t.D)) || (e = upload(h, &pii64, pii)) ||
+      (e = upload(h, &w64[0], w[0])) || (e = upload(h, &w64[1], w[1])) || (e = upload(h, &w64[2], w[2])) ||
+      (e = upload(h, &D32, as_type<float>(h->t.D))) || (e = upload(h, &pii32, as_type<float>(pii))) ||
+      (e = upload(h, &w32[0], as_type<float>(w[0]))) || (e = upload(h, &w32[1], as_type<float>(w[1]))) ||
+      (e = upload(h, &w32[2], as_type<float>(w[2]))))
+    return e;
+  h->pd_D64 = D64;
+  h->pds64 = PdSolve<double>{pii64, w64[0], w64[1], w64[2], D64};
+  h->pds32 = PdSolve<float>{pii32, w32[0], w32[1], w32[2], D32};
+  h->pd_host_dm = std::vector<double>();
+  h->pd_host_da = std::vector<double>();
+  return RZ_OK;
+}
+
 void grad_symbolic(rz_problem *h) {
   const int p = h->p;
   build_patch_symbolic(p, h->ps);
@@ -1316,7 +1432,7 @@ rz_status grad_patch_device(rz_problem *h) {
   // ELL padding of the factors must read as zero
   HIPCALL(h, hipMemsetAsync(h->f64, 0, nf * sizeof(double), s));
   HIPCALL(h, hipMemsetAsync(h->f32, 0, nf * sizeof(float), s));
-  launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, h->f64, h->f32, h->status, s);
+  launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, pd_dev(h), h->f64, h->f32, h->status, s);
   if (hipStreamSynchronize(s) != hipSuccess) return fail(ctx, RZ_ERR_HIP, "patch factorisation failed");
   int stv = 0;
   HIPCALL(h, hipMemcpy(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost));
@@ -1433,10 +1549,6 @@ bool condense_keys(const VecLocal &L, const SpRows basis[6], const std::vector<s
   return true;
 }
 
-template <typename T>
-std::vector<T> as_type(const std::vector<double> &v) {
-  return std::vector<T>(v.begin(), v.end());
-}
 
 // CSR transpose: (rows r_ids with ptr/col/val) -> rows = distinct columns ascending
 void csr_transpose(const std::vector<int> &rid, const std::vector<int> &ptr, const std::vector<int> &col,
@@ -2271,6 +2383,7 @@ void rz_opts_default(rz_opts *o) {
   o->rtol = 1e-8;
   o->omega = 0.0;
   o->lanczos_seed = 99;
+  o->aux = RZ_AUX_CELL_AVG;
 }
 
 rz_status rz_create(rz_ctx **ctx, int device, void *stream) {
@@ -2317,6 +2430,7 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
   if (!cf->alpha || !cf->beta) return fail(ctx, RZ_ERR_ARG, "missing coefficients");
   if (opts->precision != RZ_PREC_F64 && opts->precision != RZ_PREC_MIXED && opts->precision != RZ_PREC_DEFECT)
     return fail(ctx, RZ_ERR_ARG, "bad precision");
+  if (opts->aux != RZ_AUX_CELL_AVG && opts->aux != RZ_AUX_PAPER_DIAG) return fail(ctx, RZ_ERR_ARG, "bad aux");
   rz_problem *h = new rz_problem();
   h->ctx = ctx;
   h->opts = *opts;
@@ -2413,6 +2527,13 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
         return fail(ctx, RZ_ERR_ARG, "non-positive Jacobian determinant or coefficient at a quadrature point");
       }
     }
+    if (opts->aux == RZ_AUX_PAPER_DIAG && opts->space == RZ_GRAD) {
+      if (!paper_diagonals_all(h)) {
+        delete h;
+        return fail(ctx, RZ_ERR_ARG, "non-positive Jacobian determinant or coefficient at a quadrature point");
+      }
+      h->pd = true;
+    }
   }
   if (opts->space != RZ_GRAD) return setup_vector(h, cf, out);
   grad_symbolic(h);
@@ -2429,6 +2550,7 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
     delete h;
     return st;
   };
+  if (h->pd && (e = upload_paper_diagonals(h))) return bail(e);
   if ((e = grad_patch_device(h))) return bail(e);
   const int n1 = p + 1;
   if ((e = upload(h, &h->E64, h->t.E))) return bail(e);
@@ -2840,7 +2962,7 @@ rz_status refactor_patches(rz_problem *h, int *breakdown) {
   HIPCALL(h, hipMemsetAsync(h->f64, 0, nf * sizeof(double), s));
   HIPCALL(h, hipMemsetAsync(h->f32, 0, nf * sizeof(float), s));
   HIPCALL(h, hipMemsetAsync(h->status, 0, sizeof(int), s));
-  launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, h->f64, h->f32, h->status, s);
+  launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, pd_dev(h), h->f64, h->f32, h->status, s);
   HIPCALL(h, hipMemcpyAsync(breakdown, h->status, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCALL(h, hipStreamSynchronize(s));
   return RZ_OK;
@@ -2848,6 +2970,7 @@ rz_status refactor_patches(rz_problem *h, int *breakdown) {
 }  // namespace
 
 rz_status rz_set_aux(rz_problem *h, const double *coef6) {
+  if (h && h->pd) return fail(h->ctx, RZ_ERR_ARG, "rz_set_aux: the problem uses the paper's auxiliary (RZ_AUX_PAPER_DIAG)");
   rz_status e = require_device(h);
   if (e) return e;
   if ((e = require_grad(h))) return e;
@@ -2889,6 +3012,17 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
     std::memcpy(out.data() + o, src, nb);
   };
   switch (what) {
+    case RZ_EXPORT_PAPER_DIAG: {
+      if (!h->pd) return fail(h->ctx, RZ_ERR_ARG, "rz_export: the problem does not use RZ_AUX_PAPER_DIAG");
+      if (index < 0 || index >= h->ncells) return fail(h->ctx, RZ_ERR_ARG, "rz_export: bad cell");
+      const size_t nm = (size_t)n1 * n1 * n1, na = 3 * (size_t)p * n1 * n1;
+      std::vector<double> v(nm + na);
+      HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+      HIPCALL(h, hipMemcpy(v.data(), h->pd_dm + nm * index, nm * sizeof(double), hipMemcpyDeviceToHost));
+      HIPCALL(h, hipMemcpy(v.data() + nm, h->pd_da + na * index, na * sizeof(double), hipMemcpyDeviceToHost));
+      put(v.data(), v.size() * sizeof(double));
+      break;
+    }
     case RZ_EXPORT_DOFMAP: {
       if (h->space != RZ_GRAD) {
         const VecDev &Vd = h->V;

@@ -27,7 +27,8 @@ COEF_CONST, COEF_CELL, COEF_SAMPLES = 0, 1, 2
 PREC_F64, PREC_MIXED, PREC_DEFECT = 0, 1, 2
 EXPORT_DOFMAP, EXPORT_PATCH, EXPORT_IC_PATTERN, EXPORT_IC_FACTOR = 0, 1, 2, 3
 EXPORT_TABLES1D, EXPORT_AUXCOEF, EXPORT_OMEGA, EXPORT_PATCH_KERNEL = 4, 5, 6, 7
-EXPORT_EDGE_PATCH, EXPORT_STATS = 8, 9
+EXPORT_EDGE_PATCH, EXPORT_STATS, EXPORT_PAPER_DIAG = 8, 9, 10
+AUX_CELL_AVG, AUX_PAPER_DIAG = 0, 1
 KERNELS = ("apply", "condense", "patch", "expand", "transfer", "coarse", "krylov")
 STATUS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_OOM", -3: "RZ_ERR_BREAKDOWN",
           -4: "RZ_ERR_NOT_CONVERGED", -5: "RZ_ERR_HIP", -6: "RZ_ERR_SINGULAR", -7: "RZ_ERR_NODEVICE"}
@@ -52,7 +53,7 @@ class Coef(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("space", ctypes.c_int32), ("p", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double), ("omega", ctypes.c_double),
-                ("lanczos_seed", ctypes.c_uint64), ("hdiv_eps", ctypes.c_double)]
+                ("lanczos_seed", ctypes.c_uint64), ("hdiv_eps", ctypes.c_double), ("aux", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -342,6 +343,12 @@ class Problem:
             out[name] = v[o:o + size].reshape(shape)
             o += size
         return out
+
+    def paper_diagonals(self, cell):
+        """(dm, da): the broken diagonals of one cell (RZ_AUX_PAPER_DIAG problems)."""
+        v = self._export(EXPORT_PAPER_DIAG, cell)
+        n1 = self.p + 1
+        return v[:n1 ** 3], v[n1 ** 3:].reshape(3, -1)
 
     def aux_coefficients(self):
         return self._export(EXPORT_AUXCOEF).reshape(self.ncells, 6)
