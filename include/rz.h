@@ -276,6 +276,11 @@ rz_status rz_sync(rz_problem *h);
  *   RZ_EXPORT_STATS      int64 pair (H(grad)): lower non-zeros (diagonal included)
  *                        and rows of the IC factors of all non-empty vertex patches
  *                        (the factor values the patch solve needs, without padding)
+ *   RZ_EXPORT_AUTOTUNE   double, per precision (FP64, then FP32) of the streaming
+ *                        vertex-patch solve: the number n of candidates the setup
+ *                        timed, n pairs (resident wavefronts per CU, ms per launch),
+ *                        then the chosen count (n = 0 and 0 where the register
+ *                        kernel runs)
  *   RZ_EXPORT_PAPER_DIAG double: the broken diagonals of cell `index` with
  *                        RZ_AUX_PAPER_DIAG, (p+1)^3 (beta-mass, x fastest) then
  *                        3 blocks of p (p+1)^2 (alpha-mass of NCE component m, its
@@ -289,7 +294,7 @@ enum {
   RZ_EXPORT_DOFMAP = 0, RZ_EXPORT_PATCH = 1, RZ_EXPORT_IC_PATTERN = 2,
   RZ_EXPORT_IC_FACTOR = 3, RZ_EXPORT_TABLES1D = 4, RZ_EXPORT_AUXCOEF = 5,
   RZ_EXPORT_OMEGA = 6, RZ_EXPORT_PATCH_KERNEL = 7, RZ_EXPORT_EDGE_PATCH = 8, RZ_EXPORT_STATS = 9,
-  RZ_EXPORT_PAPER_DIAG = 10
+  RZ_EXPORT_PAPER_DIAG = 10, RZ_EXPORT_AUTOTUNE = 11
 };
 rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *bytes);
 

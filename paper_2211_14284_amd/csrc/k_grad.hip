@@ -1924,6 +1924,10 @@ static bool patch_solve_shape(const PatchEllDev &E, size_t row_bytes, int cap, i
   return waves > 0;
 }
 
+bool patch_solve_stream_shape(const PatchEllDev &E, size_t elem, int cap, int &waves, int &per_cu) {
+  return patch_solve_shape(E, sizeof(double) + elem, cap, waves, per_cu);
+}
+
 template <int P>
 static bool pass_table_matches(const int *pass, int np, int nrows, int ne, int ell0) {
   using S = PassTable<P>;
@@ -2013,12 +2017,16 @@ int launch_patch_solve(const LatDev &L, const PatchEllDev &E, const T *factor, c
     const long need = (nv + waves - 1) / waves;
     return (unsigned)(grid > need ? need : grid);
   };
-  // vectors in FP64 and diagonals in T in LDS; at most 12 resident wavefronts per CU
-  // for FP64 (measured at p = 7: 12 -> 0.70 ms, 16 -> 0.73 ms, 8 -> 0.77 ms per launch;
-  // fewer slots in flight keep more of the factor cached between the two sweeps),
-  // as many as fit for FP32 (18 at p = 7: 0.42 ms; 12: 0.57 ms)
+  // vectors in FP64 and diagonals in T in LDS; the resident wavefronts per CU as the
+  // setup's autotuner chose them, else at most 12 for FP64 (measured at p = 7: 12 ->
+  // 0.70 ms, 16 -> 0.73 ms, 8 -> 0.77 ms per launch; fewer slots in flight keep more
+  // of the factor cached between the two sweeps) and as many as fit for FP32 (18 at
+  // p = 7: 0.42 ms; 12: 0.57 ms)
   int waves, per_cu;
-  if (!patch_solve_shape(E, sizeof(double) + sizeof(T), sizeof(T) == 8 ? 12 : 32, waves, per_cu)) return -1;
+  const int tuned = E.cap[sizeof(T) == 8 ? 0 : 1];
+  if (!patch_solve_shape(E, sizeof(double) + sizeof(T), tuned > 0 ? tuned : (sizeof(T) == 8 ? 12 : 32), waves,
+                         per_cu))
+    return -1;
   const size_t shm = patch_solve_lds(E, sizeof(double) + sizeof(T), waves);
   const unsigned grid = grid_of(waves, per_cu);
 #define RZ_CALL(KM)                                                                                          \

@@ -77,6 +77,8 @@ struct PatchEllDev {
   const int *off;                  // 3*nrows: lattice offsets of the patch rows
   int regs;                        // 1: the schedule equals the one compiled into the register kernel
   int ell0;                        // offset of the ELL values in a slot (values at ell0 + ell_pos)
+  int cap[2];                      // streaming kernel: resident wavefronts per CU (FP64, FP32),
+                                   // chosen by the setup's autotuner; 0 = the built-in default
 };
 
 // Trilinear cells with sampled coefficients: vertex coordinates (nvertices x 3,
@@ -152,6 +154,9 @@ bool patch_regs_table_matches(int p, const int *pass, int np, int nrows, int ne,
 // register-resident kernel (else the streaming one)
 bool patch_solve_uses_regs(const PatchEllDev &E, int p, size_t elem);
 size_t patch_solve_lds_bytes(const PatchEllDev &E, size_t elem, int waves);
+// the streaming kernel's block shape (wavefronts per block, blocks per CU) for at
+// most cap resident wavefronts per CU; false if no block fits the LDS
+bool patch_solve_stream_shape(const PatchEllDev &E, size_t elem, int cap, int &waves, int &per_cu);
 // Right-hand sides and outputs of one patch-solve launch over several vectors.
 constexpr int kPatchMaxVecs = 2;
 template <typename T>

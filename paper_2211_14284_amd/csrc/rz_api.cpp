@@ -190,6 +190,9 @@ struct rz_problem {
   double *pd_dm = nullptr, *pd_da = nullptr, *pd_G = nullptr, *pd_D64 = nullptr;
   PdSolve<double> pds64{};
   PdSolve<float> pds32{};
+  // autotuned streaming patch solve: per precision (FP64, FP32) the candidates' caps
+  // and their times (ms per launch), the chosen cap
+  std::vector<std::pair<int, double>> tune[2];
   // per-kernel timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -1016,6 +1019,59 @@ double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &
     else lo = mid;
   }
   return 0.5 * (lo + hi);
+}
+
+// Autotuner of the streaming vertex-patch solve (the degrees and precisions whose
+// factor does not fit the registers): for each candidate number of resident
+// wavefronts per CU that gives a distinct block shape, one warm-up and three timed
+// launches on the problem's own factors (right-hand side zero: the work does not
+// depend on its values), and the fastest is kept in the problem's patch data.  The
+// block shape does not change the arithmetic of a patch (one wavefront per slot), so
+// results are the same for every choice.
+template <typename T>
+rz_status autotune_patch_solve(rz_problem *h, const T *f, T *rt, T *zb, int which) {
+  hipStream_t s = h->ctx->stream;
+  static const int kCaps[] = {4, 8, 12, 16, 20, 24, 32, 40};
+  std::vector<std::pair<int, int>> seen;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCALL(h, hipEventCreate(&e0));
+  HIPCALL(h, hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t &a, &b;
+    ~Ev() {
+      if (a) hipEventDestroy(a);
+      if (b) hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  if (sizeof(T) == 8) launch_fill(reinterpret_cast<double *>(rt), 0.0, h->ndofs, s);
+  else launch_fill_f(reinterpret_cast<float *>(rt), 0.0f, h->ndofs, s);
+  h->tune[which].clear();
+  double best = 0;
+  int best_cap = 0;
+  for (int cap : kCaps) {
+    int w = 0, b = 0;
+    if (!patch_solve_stream_shape(h->PE, sizeof(T), cap, w, b)) continue;
+    bool dup = false;
+    for (auto &q : seen) dup |= q.first == w && q.second == b;
+    if (dup) continue;
+    seen.push_back({w, b});
+    h->PE.cap[which] = cap;
+    if (launch_patch_solve<T>(h->L, h->PE, f, rt, zb, s)) return fail(h->ctx, RZ_ERR_HIP, "patch solve launch failed");
+    HIPCALL(h, hipEventRecord(e0, s));
+    for (int k = 0; k < 3; ++k) launch_patch_solve<T>(h->L, h->PE, f, rt, zb, s);
+    HIPCALL(h, hipEventRecord(e1, s));
+    HIPCALL(h, hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCALL(h, hipEventElapsedTime(&ms, e0, e1));
+    const double t = ms / 3.0;
+    h->tune[which].push_back({cap, t});
+    if (best_cap == 0 || t < best) {
+      best = t;
+      best_cap = cap;
+    }
+  }
+  h->PE.cap[which] = best_cap;
+  return RZ_OK;
 }
 
 // 10 preconditioned CG steps on A x = v0 with M = the FP64 fine relaxation (for every
@@ -2589,6 +2645,10 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
       (e = dalloc(h, &h->xc, (size_t)(h->nx + 1) * (h->ny + 1) * (h->nz + 1))))
     return bail(e);
   if ((e = setup_coarse(h))) return bail(e);
+  if (!patch_solve_uses_regs(h->PE, p, 8) && (e = autotune_patch_solve<double>(h, h->f64, h->rt64, h->zb64, 0)))
+    return bail(e);
+  if (!patch_solve_uses_regs(h->PE, p, 4) && (e = autotune_patch_solve<float>(h, h->f32, h->rt32, h->zb32, 1)))
+    return bail(e);
   if (opts->omega > 0) {
     h->omega = opts->omega;
   } else {
@@ -3012,6 +3072,20 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
     std::memcpy(out.data() + o, src, nb);
   };
   switch (what) {
+    case RZ_EXPORT_AUTOTUNE: {
+      for (int w = 0; w < 2; ++w) {
+        const double n = (double)h->tune[w].size();
+        put(&n, sizeof n);
+        for (auto &q : h->tune[w]) {
+          const double c = q.first, t = q.second;
+          put(&c, sizeof c);
+          put(&t, sizeof t);
+        }
+        const double chosen = h->PE.cap[w];
+        put(&chosen, sizeof chosen);
+      }
+      break;
+    }
     case RZ_EXPORT_PAPER_DIAG: {
       if (!h->pd) return fail(h->ctx, RZ_ERR_ARG, "rz_export: the problem does not use RZ_AUX_PAPER_DIAG");
       if (index < 0 || index >= h->ncells) return fail(h->ctx, RZ_ERR_ARG, "rz_export: bad cell");

@@ -27,7 +27,7 @@ COEF_CONST, COEF_CELL, COEF_SAMPLES = 0, 1, 2
 PREC_F64, PREC_MIXED, PREC_DEFECT = 0, 1, 2
 EXPORT_DOFMAP, EXPORT_PATCH, EXPORT_IC_PATTERN, EXPORT_IC_FACTOR = 0, 1, 2, 3
 EXPORT_TABLES1D, EXPORT_AUXCOEF, EXPORT_OMEGA, EXPORT_PATCH_KERNEL = 4, 5, 6, 7
-EXPORT_EDGE_PATCH, EXPORT_STATS, EXPORT_PAPER_DIAG = 8, 9, 10
+EXPORT_EDGE_PATCH, EXPORT_STATS, EXPORT_PAPER_DIAG, EXPORT_AUTOTUNE = 8, 9, 10, 11
 AUX_CELL_AVG, AUX_PAPER_DIAG = 0, 1
 KERNELS = ("apply", "condense", "patch", "expand", "transfer", "coarse", "krylov")
 STATUS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_OOM", -3: "RZ_ERR_BREAKDOWN",
@@ -178,8 +178,9 @@ class Context:
             self.check(lib.rz_destroy(self.handle))
             self.handle = _vp()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps the check usable when module globals are gone
+        if _finalizing():
             return
         try:
             self.close()
@@ -350,6 +351,18 @@ class Problem:
         n1 = self.p + 1
         return v[:n1 ** 3], v[n1 ** 3:].reshape(3, -1)
 
+    def autotune(self):
+        """{"f64"|"f32": {"candidates": [(cap, ms), ...], "chosen": cap}} of the
+        streaming patch solve's setup autotuner (empty where the register kernel runs)."""
+        v = self._export(EXPORT_AUTOTUNE)
+        out, o = {}, 0
+        for name in ("f64", "f32"):
+            n = int(v[o])
+            cand = [(int(v[o + 1 + 2 * k]), float(v[o + 2 + 2 * k])) for k in range(n)]
+            out[name] = {"candidates": cand, "chosen": int(v[o + 1 + 2 * n])}
+            o += 2 + 2 * n
+        return out
+
     def aux_coefficients(self):
         return self._export(EXPORT_AUXCOEF).reshape(self.ncells, 6)
 
@@ -379,8 +392,9 @@ class Problem:
             lib.rz_free(self.handle)
             self.handle = _vp()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps the check usable when module globals are gone
+        if _finalizing():
             return
         try:
             self.close()
@@ -455,8 +469,9 @@ class MLP:
             lib.rz_mlp_free(self.handle)
             self.handle = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps the check usable when module globals are gone
+        if _finalizing():
             return
         try:
             self.close()

@@ -266,3 +266,25 @@ def test_solve_defect_correction(rz, ctx, n, p):
     eA = np.sqrt((xg - xs) @ (ref.A @ (xg - xs)) / (xs @ (ref.A @ xs)))
     assert eA < 1e-7
     assert 5 <= info.iters <= 80
+
+
+@pytest.mark.parametrize("p", [3, 8, 9])
+def test_patch_solve_autotune(rz, ctx, p):
+    # the setup times the streaming patch solve for the candidate block shapes where
+    # it runs (FP64 p >= 8, FP32 p = 9) and keeps the fastest; nothing is tuned where
+    # the register kernel runs.  Relaxation parity at these degrees (test_relax_parity)
+    # runs with the chosen shapes.
+    pb = rz.Problem(ctx, (2, 2, 2), p, 1.0, 1.0, omega=0.3)
+    try:
+        tune = pb.autotune()
+        f64, f32 = pb.patch_kernel()
+        for name, regs in (("f64", f64), ("f32", f32)):
+            cand = tune[name]["candidates"]
+            if regs:
+                assert cand == [] and tune[name]["chosen"] == 0
+            else:
+                assert len(cand) >= 1 and all(ms > 0 for _, ms in cand)
+                best = min(cand, key=lambda c: c[1])[0]
+                assert tune[name]["chosen"] == best
+    finally:
+        pb.close()
