@@ -167,59 +167,68 @@ __global__ void k_csr(int n, const int *__restrict__ rows, const int *__restrict
   y[g] = add ? (TY)((TV)y[g] + acc) : (TY)acc;
 }
 
-// Edge-star patch solves: one wavefront per (patch, mode block); z = W^T (W b) with W
-// = L^{-1} of the block's Cholesky factor (the patch type's, computed at setup in
-// FP64), packed by columns for W b and by rows for W^T y.  The gathered right-hand
-// side and the intermediate y are broadcast from LDS; lane l forms rows l and l + 64
-// with coalesced loads, and no row waits for another (unlike two triangular sweeps).
-template <typename T>
-__global__ void __launch_bounds__(kBS) k_edge_solve(EdgeDev E, const T *__restrict__ fac, const T *__restrict__ rt,
-                                                    T *__restrict__ zb) {
-  __shared__ T sb[kBS / 64][128];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const long w = (long)blockIdx.x * (blockDim.x >> 6) + wv;
-  if (w >= (long)E.npatch * E.p) return;
-  const int patch = (int)(w / E.p), blk = (int)(w % E.p);
-  const int nb = E.blk_n[blk], s0 = E.blk_slot[blk];
+// Edge-star patch solves, z = W^T (W b) per (patch, mode block) with W = L^{-1} of the
+// block's Cholesky factor (the patch type's, computed at setup in FP64).  A block of
+// the kernel takes one mode block of up to 256 patches of one type: W goes to LDS once
+// (by rows), and each lane solves one patch with its n values in registers (n fixed
+// per degree and mode: 4p - 3 for mode 0, 8p - 3 for the others): y = W b bottom-up
+// and z = W^T y top-down in place (y_r needs b_0..b_r, z_r needs y_r..y_{n-1}), every
+// W entry read by all lanes at once.  Sums run over ascending column index.
+// (the empty asm with a memory clobber after each row keeps the compiler from holding
+// the LDS values of W in registers across rows and phases: only v stays live)
+template <typename T, int N>
+__device__ __forceinline__ void edge_block_solve(const T *W, T (&v)[N]) {
+#pragma unroll
+  for (int r = N - 1; r >= 0; --r) {
+    T acc = 0;
+#pragma unroll
+    for (int c = 0; c <= r; ++c) acc += W[r * (r + 1) / 2 + c] * v[c];
+    v[r] = acc;
+    asm volatile("" ::: "memory");
+  }
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    T acc = 0;
+#pragma unroll
+    for (int c = r; c < N; ++c) acc += W[c * (c + 1) / 2 + r] * v[c];
+    v[r] = acc;
+    asm volatile("" ::: "memory");
+  }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void edge_chunk(const EdgeDev &E, const T *__restrict__ fac, const T *__restrict__ rt,
+                                           T *__restrict__ zb, T *sW, int blk) {
+  const int c0 = E.chunk[3 * blockIdx.x], c1 = E.chunk[3 * blockIdx.x + 1], type = E.chunk[3 * blockIdx.x + 2];
+  const int s0 = E.blk_slot[blk];
+  // the block's W by rows: it follows the by-columns copy in the factor set
+  const T *Wr = fac + (size_t)type * E.fac_stride + E.blk_fac[blk] + N * (N + 1) / 2;
+  for (int k = threadIdx.x; k < N * (N + 1) / 2; k += blockDim.x) sW[k] = Wr[k];
+  __syncthreads();
+  const int q = c0 + (int)threadIdx.x;
+  if (q >= c1) return;
+  const int patch = E.plist[q];
   const int *ix = E.idx + (size_t)patch * E.nslot + s0;
-  const T *Wc = fac + (size_t)E.type[patch] * E.fac_stride + E.blk_fac[blk];  // by columns
-  const T *Wr = Wc + nb * (nb + 1) / 2;                                         // by rows
-  const int r0 = lane, r1 = lane + 64;
-  const int g0 = r0 < nb ? ix[r0] : -1, g1 = r1 < nb ? ix[r1] : -1;
-  T *b = sb[wv];
-  b[r0] = g0 >= 0 ? rt[g0] : T(0);
-  b[r1] = g1 >= 0 ? rt[g1] : T(0);
-  // LDS of this wavefront only: its own writes are visible after the wave-level fence
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // y = W b: y_r = sum_{c <= r} W_rc b_c, column c holds W_{c..n-1, c}
-  T y0 = 0, y1 = 0;
-  for (int c = 0; c < nb; ++c) {
-    const T bc = b[c];
-    const T *col = Wc + c * nb - (c * (c - 1)) / 2 - c;  // col[r] = W_rc for r >= c
-    if (r0 >= c && r0 < nb) y0 += col[r0] * bc;
-    if (r1 >= c && r1 < nb) y1 += col[r1] * bc;
+  T v[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    const int g = ix[r];
+    v[r] = g >= 0 ? rt[g] : T(0);
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  b[r0] = y0;
-  b[r1] = y1;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // z = W^T y: z_r = sum_{c >= r} W_cr y_c, row c holds W_{c, 0..c}
-  T z0 = 0, z1 = 0;
-  for (int c = 0; c < nb; ++c) {
-    const T yc = b[c];
-    const T *row = Wr + (c * (c + 1)) / 2;  // row[r] = W_cr for r <= c
-    if (r0 <= c) z0 += row[r0] * yc;
-    if (r1 <= c) z1 += row[r1] * yc;
-  }
+  edge_block_solve<T, N>(sW, v);
   T *zo = zb + (size_t)patch * E.nslot + s0;
-  if (r0 < nb) zo[r0] = z0;
-  if (r1 < nb) zo[r1] = z1;
+#pragma unroll
+  for (int r = 0; r < N; ++r) zo[r] = v[r];
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_edge_solve(EdgeDev E, const T *__restrict__ fac, const T *__restrict__ rt,
+                                                    T *__restrict__ zb) {
+  constexpr int N0 = 4 * P - 3, N1 = 8 * P - 3;
+  __shared__ T sW[N1 * (N1 + 1) / 2];
+  const int blk = blockIdx.y;
+  if (blk == 0) edge_chunk<T, N0>(E, fac, rt, zb, sW, 0);
+  else if constexpr (P > 1) edge_chunk<T, N1>(E, fac, rt, zb, sW, blk);
 }
 
 // y = M x for a dense m x m matrix (row-major), one wavefront per row, FP64 sums
@@ -280,8 +289,20 @@ void launch_csr(int n, const int *rows, const int *ptr, const int *col, const TV
 
 template <typename T>
 void launch_edge_solve(const EdgeDev &E, const T *fac, const T *rt, T *zb, hipStream_t s) {
-  const long nw = (long)E.npatch * E.p;
-  if (nw > 0) k_edge_solve<T><<<(unsigned)((nw + 3) / 4), kBS, 0, s>>>(E, fac, rt, zb);
+  if (E.nchunk <= 0) return;
+  const dim3 grid((unsigned)E.nchunk, (unsigned)E.p);
+  switch (E.p) {
+    case 1: k_edge_solve<T, 1><<<grid, 256, 0, s>>>(E, fac, rt, zb); break;
+    case 2: k_edge_solve<T, 2><<<grid, 256, 0, s>>>(E, fac, rt, zb); break;
+    case 3: k_edge_solve<T, 3><<<grid, 256, 0, s>>>(E, fac, rt, zb); break;
+    case 4: k_edge_solve<T, 4><<<grid, 256, 0, s>>>(E, fac, rt, zb); break;
+    case 5: k_edge_solve<T, 5><<<grid, 256, 0, s>>>(E, fac, rt, zb); break;
+    case 6: k_edge_solve<T, 6><<<grid, 256, 0, s>>>(E, fac, rt, zb); break;
+    case 7: k_edge_solve<T, 7><<<grid, 256, 0, s>>>(E, fac, rt, zb); break;
+    case 8: k_edge_solve<T, 8><<<grid, 256, 0, s>>>(E, fac, rt, zb); break;
+    case 9: k_edge_solve<T, 9><<<grid, 256, 0, s>>>(E, fac, rt, zb); break;
+    default: break;
+  }
 }
 
 template <typename TM>

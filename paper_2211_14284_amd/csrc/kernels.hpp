@@ -50,6 +50,9 @@ struct EdgeDev {
   int blk_n[9], blk_slot[9], blk_fac[9];
   const int *idx;   // npatch * nslot global DoFs (-1: absent slot)
   const int *type;  // npatch: factor set of each patch
+  int nchunk;       // groups of at most 256 patches of one type
+  const int *chunk; // nchunk x 3: first and end position in plist, type
+  const int *plist; // npatch: the patches ordered by type
 };
 
 // Symbolic patch data on the device.

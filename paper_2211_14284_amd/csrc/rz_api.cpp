@@ -1684,6 +1684,25 @@ rz_status upload_edges(rz_problem *h, const EdgePatches &ep, EdgeDev &ed, double
   }
   ed.idx = idx;
   ed.type = typ;
+  // the patches grouped by type, in chunks of at most 256 (one block of the solve
+  // kernel each: one factor set in LDS for all its patches)
+  const int np = ed.npatch;
+  std::vector<int> plist(np), chunk;
+  for (int i = 0; i < np; ++i) plist[i] = i;
+  std::stable_sort(plist.begin(), plist.end(), [&](int a, int b) { return ep.type[a] < ep.type[b]; });
+  for (int i = 0; i < np;) {
+    int j = i;
+    while (j < np && ep.type[plist[j]] == ep.type[plist[i]] && j - i < 256) ++j;
+    chunk.push_back(i);
+    chunk.push_back(j);
+    chunk.push_back(ep.type[plist[i]]);
+    i = j;
+  }
+  int *dpl = nullptr, *dch = nullptr;
+  if ((e = upload(h, &dpl, plist)) || (e = upload(h, &dch, chunk))) return e;
+  ed.nchunk = (int)chunk.size() / 3;
+  ed.chunk = dch;
+  ed.plist = dpl;
   return RZ_OK;
 }
 
