@@ -167,6 +167,25 @@ __global__ void k_csr(int n, const int *__restrict__ rows, const int *__restrict
   y[g] = add ? (TY)((TV)y[g] + acc) : (TY)acc;
 }
 
+// The same product with one wavefront per row (rows of hundreds of entries: the
+// restriction to the p = 1 space): lanes stride over the row, then a fixed-order
+// shuffle reduction.
+template <typename TV, typename TX, typename TY>
+__global__ void __launch_bounds__(kBS) k_csr_wave(int n, const int *__restrict__ rows, const int *__restrict__ ptr,
+                                                  const int *__restrict__ col, const TV *__restrict__ val,
+                                                  const TX *__restrict__ x, TY *__restrict__ y, int add) {
+  const int lane = threadIdx.x & 63;
+  const long t = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (t >= n) return;
+  TV acc = 0;
+  for (int k = ptr[t] + lane; k < ptr[t + 1]; k += 64) acc += val[k] * (TV)x[col[k]];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (lane == 0) {
+    const int g = rows ? rows[t] : (int)t;
+    y[g] = add ? (TY)((TV)y[g] + acc) : (TY)acc;
+  }
+}
+
 // Edge-star patch solves, z = W^T (W b) per (patch, mode block) with W = L^{-1} of the
 // block's Cholesky factor (the patch type's, computed at setup in FP64).  A block of
 // the kernel takes one mode block of up to 256 patches of one type: W goes to LDS once
@@ -231,6 +250,73 @@ __global__ void __launch_bounds__(256) k_edge_solve(EdgeDev E, const T *__restri
   else if constexpr (P > 1) edge_chunk<T, N1>(E, fac, rt, zb, sW, blk);
 }
 
+// y = M x for a dense symmetric m x m matrix (row-major) reading only its lower
+// triangle: one block per 64 x 64 tile (ti, tj), ti >= tj, adds M_ij x_j to row block
+// ti and, below the diagonal, M_ij^T x_i to row block tj, each as a partial vector in
+// part[(row block) * nt + (other tile index)] (one partial per pair, no atomics);
+// k_symv_reduce sums the nt partials of every row in a fixed order.  FP64 sums.
+template <typename TM>
+__global__ void __launch_bounds__(256) k_symv_tile(int m, int nt, const TM *__restrict__ M,
+                                                   const double *__restrict__ x, double *__restrict__ part) {
+  // the tile in LDS, rows padded by one entry so that a lane-per-row read of one
+  // column touches distinct banks
+  __shared__ TM tile[64][65];
+  __shared__ double xi[64], xj[64], red[4][64];
+  const long b = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+  while ((long)(ti + 1) * (ti + 2) / 2 <= b) ++ti;
+  while ((long)ti * (ti + 1) / 2 > b) --ti;
+  const int tj = (int)(b - (long)ti * (ti + 1) / 2);
+  const int r0 = 64 * ti, c0 = 64 * tj, tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  if (tid < 64) {
+    xi[tid] = r0 + tid < m ? x[r0 + tid] : 0.0;
+    xj[tid] = c0 + tid < m ? x[c0 + tid] : 0.0;
+  }
+  // wave wv loads rows 16 wv .. 16 wv + 15, lane = column (one contiguous row segment
+  // per load); column partial sums of M^T x_i over those rows stay in the lane
+  TM v[16];
+  const int c = c0 + lane;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int row = r0 + 16 * wv + k;
+    v[k] = row < m && c < m ? M[(long)row * m + c] : TM(0);
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) tile[16 * wv + k][lane] = v[k];
+  __syncthreads();
+  if (ti != tj) {  // uniform over the block
+    double cs = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) cs += (double)v[k] * xi[16 * wv + k];
+    red[wv][lane] = cs;
+  }
+  __syncthreads();
+  if (ti != tj && tid < 64) part[((long)tj * nt + ti) * 64 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  // row partial sums of M x_j: lane = row, wave wv takes columns 16 wv .. 16 wv + 15
+  double rs = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) rs += (double)tile[lane][16 * wv + k] * xj[16 * wv + k];
+  __syncthreads();
+  red[wv][lane] = rs;
+  __syncthreads();
+  if (tid < 64) part[((long)ti * nt + tj) * 64 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+}
+
+// one block per row block: y = sum over the nt partials, four waves over a quarter of
+// them each, combined in a fixed order
+__global__ void __launch_bounds__(256) k_symv_reduce(int m, int nt, const double *__restrict__ part,
+                                                     double *__restrict__ y) {
+  __shared__ double red[4][64];
+  const int bi = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double acc = 0.0;
+  for (int k = wv; k < nt; k += 4) acc += part[((long)bi * nt + k) * 64 + lane];
+  red[wv][lane] = acc;
+  __syncthreads();
+  const int i = 64 * bi + threadIdx.x;
+  if (threadIdx.x < 64 && i < m) y[i] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
 // y = M x for a dense m x m matrix (row-major), one wavefront per row, FP64 sums
 template <typename TM>
 __global__ void __launch_bounds__(kBS) k_gemv(int m, const TM *__restrict__ M, const double *__restrict__ x,
@@ -287,6 +373,14 @@ void launch_csr(int n, const int *rows, const int *ptr, const int *col, const TV
   if (n > 0) k_csr<TV, TX, TY><<<nblk(n), kBS, 0, s>>>(n, rows, ptr, col, val, x, y, add);
 }
 
+template <typename TV, typename TX, typename TY>
+void launch_csr_wave(int n, const int *rows, const int *ptr, const int *col, const TV *val, const TX *x, TY *y,
+                     int add, hipStream_t s) {
+  if (n > 0) k_csr_wave<TV, TX, TY><<<(unsigned)((n + 3) / 4), kBS, 0, s>>>(n, rows, ptr, col, val, x, y, add);
+}
+template void launch_csr_wave<double, double, double>(int, const int *, const int *, const int *, const double *,
+                                                      const double *, double *, int, hipStream_t);
+
 template <typename T>
 void launch_edge_solve(const EdgeDev &E, const T *fac, const T *rt, T *zb, hipStream_t s) {
   if (E.nchunk <= 0) return;
@@ -304,6 +398,16 @@ void launch_edge_solve(const EdgeDev &E, const T *fac, const T *rt, T *zb, hipSt
     default: break;
   }
 }
+
+template <typename TM>
+void launch_symv(int m, const TM *M, const double *x, double *y, double *work, hipStream_t s) {
+  if (m <= 0) return;
+  const int nt = (m + 63) / 64;
+  k_symv_tile<TM><<<(unsigned)((long)nt * (nt + 1) / 2), 256, 0, s>>>(m, nt, M, x, work);
+  k_symv_reduce<<<nt, 256, 0, s>>>(m, nt, work, y);
+}
+template void launch_symv<double>(int, const double *, const double *, double *, double *, hipStream_t);
+template void launch_symv<float>(int, const float *, const double *, double *, double *, hipStream_t);
 
 template <typename TM>
 void launch_gemv(int m, const TM *M, const double *x, double *y, hipStream_t s) {

@@ -213,12 +213,20 @@ void launch_rows_scale(int n, const int *rows, const T *d, const T *x, T *y, hip
 template <typename TV, typename TX, typename TY>
 void launch_csr(int n, const int *rows, const int *ptr, const int *col, const TV *val, const TX *x, TY *y, int add,
                 hipStream_t s);
+// the same with one wavefront per row (long rows)
+template <typename TV, typename TX, typename TY>
+void launch_csr_wave(int n, const int *rows, const int *ptr, const int *col, const TV *val, const TX *x, TY *y,
+                     int add, hipStream_t s);
 // edge-star Cholesky solves: zb (npatch * nslot) from rt
 template <typename T>
 void launch_edge_solve(const EdgeDev &E, const T *fac, const T *rt, T *zb, hipStream_t s);
 // y = M x, dense m x m row-major matrix in TM, FP64 vectors
 template <typename TM>
 void launch_gemv(int m, const TM *M, const double *x, double *y, hipStream_t s);
+// y = M x for a dense symmetric m x m matrix (row-major) from its lower triangle;
+// work: ceil(m/64)^2 * 64 doubles
+template <typename TM>
+void launch_symv(int m, const TM *M, const double *x, double *y, double *work, hipStream_t s);
 // z[list[t]] = r ? r[list[t]] : 0
 template <typename T>
 void launch_list_copy(int n, const int *list, const T *r, T *z, hipStream_t s);

@@ -166,6 +166,7 @@ struct rz_problem {
   int ncf = 0;                              // free DoFs of the p = 1 space
   double *cinv64 = nullptr;
   float *cinv32 = nullptr;                  // dense A_0^{-1}
+  double *csym = nullptr;                   // partial products of the symmetric product
   int *pr_ptr = nullptr, *pr_col = nullptr; // restriction (rows: coarse free, compact)
   double *pr_val = nullptr;
   int npf = 0;
@@ -608,12 +609,12 @@ void coarse_correction_vec(rz_problem *h, const double *r1, T *z, bool f32) {
   if (h->ncf == 0) return;
   {
     Timed tm(h, RZ_K_TRANSFER);
-    launch_csr<double, double, double>(h->ncf, nullptr, h->pr_ptr, h->pr_col, h->pr_val, r1, h->vcr, 0, s);
+    launch_csr_wave<double, double, double>(h->ncf, nullptr, h->pr_ptr, h->pr_col, h->pr_val, r1, h->vcr, 0, s);
   }
   {
     Timed tm(h, RZ_K_COARSE);
-    if (f32 && h->cinv32) launch_gemv<float>(h->ncf, h->cinv32, h->vcr, h->vcx, s);
-    else launch_gemv<double>(h->ncf, h->cinv64, h->vcr, h->vcx, s);
+    if (f32 && h->cinv32) launch_symv<float>(h->ncf, h->cinv32, h->vcr, h->vcx, h->csym, s);
+    else launch_symv<double>(h->ncf, h->cinv64, h->vcr, h->vcx, h->csym, s);
   }
   {
     Timed tm(h, RZ_K_TRANSFER);
@@ -1999,6 +2000,8 @@ rz_status setup_vec_relax(rz_problem *h, const std::vector<double> &al, const st
       if ((e = dalloc(h, &h->cinv32, (size_t)ncf * ncf))) return e;
       launch_cast_d2f(h->cinv64, h->cinv32, (int64_t)ncf * ncf, s);
     }
+    const size_t nt = ((size_t)ncf + 63) / 64;
+    if ((e = dalloc(h, &h->csym, nt * nt * 64))) return e;
     // prolongation (the embedding of the p = 1 space, per axis: hats on continuous
     // axes, the constant r_0 on broken ones) and restriction = its transpose
     std::vector<int> prow, pptr(1, 0), pcol;
