@@ -190,10 +190,11 @@ rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t, int32_t nr
  * allocations (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  The call allocates nothing: the apply's workspace (the
  * face-line buffer of the Cartesian H(grad) path, the per-cell outputs of the
- * quadrature and H(curl)/H(div) paths) is a static device array of 64 MiB per GPU,
- * its address taken once per device by rz_create.  RZ_ERR_ARG if the problem needs
- * more workspace than that (ny*nz*4p*Nx elements on the Cartesian H(grad) path,
- * ncells*(p+1)^3 on the quadrature path, ncells*3p(p+1)^2 for H(curl)/H(div)).
+ * quadrature path, the contributions to shared entries of the H(curl)/H(div) paths)
+ * is a static device array of 64 MiB per GPU, its address taken once per device by
+ * rz_create.  RZ_ERR_ARG if the problem needs more workspace than that (ny*nz*4p*Nx
+ * elements on the Cartesian H(grad) path, ncells*(p+1)^3 on the quadrature path,
+ * 3*ndofs for H(curl), ndofs for H(div)).
  * Every call on one GPU shares that array and it keeps the last call's contents:
  * calls that overlap in time on one GPU (other streams, other contexts or
  * threads) race and give wrong results; calls ordered on one stream are safe. */

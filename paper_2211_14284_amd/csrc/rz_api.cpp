@@ -2147,6 +2147,10 @@ rz_status setup_vector(rz_problem *h, const rz_coef *cf, rz_problem **out) {
   Vd.off[3] = off;
   h->ndofs = off;
   h->nfree = off - ndir;
+  if (off > 0x7fffffffL) {
+    delete h;
+    return fail(ctx, RZ_ERR_ARG, "H(curl)/H(div) vectors are limited to 2^31 - 1 entries");
+  }
   if (ctx->device < 0) {
     *out = h;
     return RZ_OK;
@@ -2161,7 +2165,7 @@ rz_status setup_vector(rz_problem *h, const rz_coef *cf, rz_problem **out) {
   };
   std::vector<float> c32(h->coef.begin(), h->coef.end()), B32(h->t.B.begin(), h->t.B.end()),
       D32(h->t.D.begin(), h->t.D.end());
-  const size_t neb = (size_t)h->ncells * Vd.cell_dofs;
+  const size_t neb = (size_t)h->ndofs * (h->space == RZ_CURL ? 3 : 1);
   if ((e = upload(h, &h->coef64, h->coef)) || (e = upload(h, &h->coef32, c32)) || (e = upload(h, &h->B64, h->t.B)) ||
       (e = upload(h, &h->B32, B32)) || (e = upload(h, &h->D64, h->t.D)) || (e = upload(h, &h->D32, D32)) ||
       (e = dalloc(h, &h->eb64, neb)) || (e = dalloc(h, &h->eb32, neb)) || (e = dalloc(h, &h->status, 1)))
@@ -2764,9 +2768,11 @@ rz_status rz_apply(rz_problem *h, const void *x, void *y, rz_dtype t, int32_t nr
 }
 
 // Bytes of the apply's workspace (face-line buffer of the Cartesian H(grad) path,
-// per-cell outputs of the quadrature and vector-space paths) for element size sz.
+// per-cell outputs of the quadrature path, per-entry contributions of the other
+// cells sharing an entry in the vector-space paths: three per entry for H(curl),
+// one for H(div)) for element size sz.
 static size_t apply_workspace_bytes(const rz_problem *h, size_t sz) {
-  if (h->space != RZ_GRAD) return (size_t)h->ncells * h->V.cell_dofs * sz;
+  if (h->space != RZ_GRAD) return (size_t)h->ndofs * (h->space == RZ_CURL ? 3 : 1) * sz;
   const size_t n1 = (size_t)h->p + 1;
   if (h->quad) return (size_t)h->ncells * n1 * n1 * n1 * sz;
   return (size_t)h->ny * h->nz * 4 * h->p * h->Nx * sz;

@@ -72,8 +72,8 @@ def test_noalloc_matches_apply_twice(rz, ctx, kind, big, small):
 
 
 def test_noalloc_rejects_oversized_workspace(rz, ctx):
-    # NCE_9 on 15^3 cells: 3375 cells x 2700 DoFs x 8 B = 72.9 MB > 64 MiB
-    pb = rz.Problem(ctx, 15, 9, 1.0, 1.0, space="curl")
+    # NCE_9 on 12^3 cells: 3 contributions x 3,849,444 DoFs x 8 B = 92.4 MB > 64 MiB
+    pb = rz.Problem(ctx, 12, 9, 1.0, 1.0, space="curl")
     x = torch.zeros(pb.ndofs, dtype=torch.float64, device="cuda:0")
     y = torch.empty_like(x)
     with pytest.raises(rz.RzError) as ei:
