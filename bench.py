@@ -39,7 +39,10 @@ FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0, WRITE_SIZE
 # x 1.0; factors from a plain 1 GiB copy in the same run), valid for the kernel
 # version they were taken on (profiles/pmc_patch_solve_hgrad_q7_n32.md)
-MEASURED_TRAFFIC = {"patch": 2.281e9}
+# HBM traffic per launch from FETCH_SIZE / WRITE_SIZE (calibrated against a plain copy), at
+# the standard sizes only: C2 (Q_7, 32^3) and C3 (NCE_6, 16^3); apply = both of its kernels
+MEASURED_TRAFFIC = {"patch": 2.281e9, "apply_c2_f64": 341.8e6, "apply_c2_f32": 179.0e6,
+                    "apply_c3_f64": 156.6e6, "apply_c3_f32": 107.7e6}
 METRIC = "GDoF/s sum-factorized apply; PCG time-to-1e-8, FP64 vs mixed, H(grad) p=7"
 
 
@@ -164,6 +167,9 @@ def bench_c2(torch, rz, ctx, args, out):
         "apply_c2_f32": hbm_roof(2 * nd * 4 + 6 * nc * 4, a32, "k_apply_pencil+k_apply_faces",
                                  "x in, y out, 6 weights per cell (FP32)"),
     }
+    std = args.p == 7 and args.n == 32
+    out["rooflines"]["apply_c2_f64"]["traffic"] = MEASURED_TRAFFIC["apply_c2_f64"] if std else None
+    out["rooflines"]["apply_c2_f32"]["traffic"] = MEASURED_TRAFFIC["apply_c2_f32"] if std else None
     if args.nrhs > 1:
         out["multi_rhs_f64"] = bench_multi_rhs(torch, rz, pb, args.nrhs, per_launch["patch"], ms, infos[-1].iters)
     pb.close()
@@ -259,8 +265,11 @@ def bench_c3(torch, rz, ctx, steps, warmup, n=16, p=6):
                 a = time_apply(torch, pb, dt, code)
                 out[f"apply_ms_{nm}"] = round(a, 4)
                 out[f"apply_gdofs_{nm}"] = round(pb.ndofs / (a * 1e-3) / 1e9, 2)
-                out[f"roofline_apply_{nm}"] = hbm_roof(2 * pb.ndofs * sz + 6 * pb.ncells * sz, a, "k_apply_vec",
+                out[f"roofline_apply_{nm}"] = hbm_roof(2 * pb.ndofs * sz + 6 * pb.ncells * sz, a,
+                                                       "k_apply_vec_p+k_apply_vec_gather",
                                                        "x in, y out, 6 weights per cell")
+                out[f"roofline_apply_{nm}"]["traffic"] = MEASURED_TRAFFIC[f"apply_c3_{nm}"] if (n, p) == (16, 6) \
+                    else None
         pb.close()
     out["speedup_mixed_vs_f64"] = round(out["pcg_ms_f64"] / out["pcg_ms_mixed"], 3)
     out["speedup_defect_vs_f64"] = round(out["pcg_ms_f64"] / out["pcg_ms_defect"], 3)
