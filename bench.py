@@ -79,6 +79,22 @@ def time_solves(torch, pb, bt, x, steps, warmup):
     return (t1 - t0) * 1e3 / steps, infos, kt
 
 
+def time_graph(torch, pb, bt, x, steps, warmup=2):
+    """Wall time per solve with the CG iterations run from captured HIP graphs
+    (captured during the warm-up solves), and the capture/replay counts."""
+    pb.set_graph(True)
+    for _ in range(warmup):
+        pb.solve(bt, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [pb.solve(bt, x) for _ in range(steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    stats = pb.graph_stats()
+    pb.set_graph(False)
+    return ms, infos, {"captures": stats[0], "iterations_replayed": stats[1], "segments": stats[2]}
+
+
 def time_apply(torch, pb, dtype_t, code, reps=50, warm=10):
     """Median device time (ms) of one apply, HIP events on the library's stream."""
     x = torch.rand(pb.ndofs, dtype=dtype_t, device="cuda:0")
@@ -123,6 +139,8 @@ def bench_c2(torch, rz, ctx, args, out):
     bt = torch.as_tensor(b, device="cuda:0")
     x = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
     ms, infos, kt = time_solves(torch, pb, bt, x, args.steps, args.warmup)
+    log("FP64 solves from captured HIP graphs")
+    mg, ig, gs = time_graph(torch, pb, bt, x, args.steps)
     st = pb.stats()
     nd = pb.ndofs
     # the patch solve, the dominant kernel: its own bytes per launch as the scope
@@ -152,6 +170,7 @@ def bench_c2(torch, rz, ctx, args, out):
                    "ndofs": nd, "nfree": pb.nfree, "cells": nc, "p": args.p},
         "pcg_ms_f64": round(ms, 4), "iters_f64": infos[-1].iters, "rel_res_f64": max(i.rel_res for i in infos),
         "iters_natural_f64": infos[-1].iters_natural,
+        "pcg_ms_f64_graph": round(mg, 4), "iters_f64_graph": ig[-1].iters, "graph": gs,
         "setup_s_f64": round(setup_s, 3), "omega": pb.omega(),
         "apply_ms_f64": round(a64, 4), "apply_ms_f32": round(a32, 4), "apply_bf16": bf,
         "apply_gdofs_f64": round(nd / (a64 * 1e-3) / 1e9, 2), "apply_gdofs_f32": round(nd / (a32 * 1e-3) / 1e9, 2),
@@ -227,10 +246,12 @@ def bench_c1(torch, rz, ctx, steps=20):
     b = torch.as_tensor(synth.rhs_values(pb.ndofs, 0), device="cuda:0")
     x = torch.empty_like(b)
     ms, infos, _ = time_solves(torch, pb, b, x, steps, 2)
+    mg, ig, gs = time_graph(torch, pb, b, x, steps)
     a = time_apply(torch, pb, torch.float64, rz.F64)
     out = {"workload": "C1: H(grad) Q_4 on 4^3, alpha=beta=1", "ndofs": pb.ndofs, "nfree": pb.nfree,
            "apply_us_f64": round(a * 1e3, 2), "pcg_ms_f64": round(ms, 4), "iters_f64": infos[-1].iters,
-           "rel_res_f64": infos[-1].rel_res}
+           "rel_res_f64": infos[-1].rel_res, "pcg_ms_f64_graph": round(mg, 4), "iters_f64_graph": ig[-1].iters,
+           "graph": gs, "speedup_graph": round(ms / mg, 3)}
     sol = x.cpu().numpy()
     pb.close()
     return out, sol
@@ -261,6 +282,8 @@ def bench_c3(torch, rz, ctx, steps, warmup, n=16, p=6):
         out[f"kernel_ms_per_step_{name}"] = {k: round(v[0] / steps, 4) for k, v in kt.items()}
         if prec == rz.PREC_F64:
             out["gdofs_f64"] = round(pb.ndofs / (ms * 1e-3) / 1e9, 5)
+            mg, ig, gs = time_graph(torch, pb, b, x, steps)
+            out["pcg_ms_f64_graph"], out["iters_f64_graph"], out["graph"] = round(mg, 4), ig[-1].iters, gs
             for nm, dt, code, sz in (("f64", torch.float64, rz.F64, 8), ("f32", torch.float32, rz.F32, 4)):
                 a = time_apply(torch, pb, dt, code)
                 out[f"apply_ms_{nm}"] = round(a, 4)
@@ -462,6 +485,22 @@ def bench_batched(torch, rz, nrhs=4, nctx=2, count=64):
     torch.cuda.synchronize()
     t_con = time.perf_counter() - t0
     iters = [inf.iters for row in con for inf in row]
+    log("batched: the same with the CG iterations from captured HIP graphs")
+    for pb in probs:
+        pb.set_graph(True)
+    rz.solve_batched(probs, bs, xs)   # captures
+    sequential()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sequential()
+    t_seq_g = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    cong = rz.solve_batched(probs, bs, xs)
+    torch.cuda.synchronize()
+    t_con_g = time.perf_counter() - t0
+    same_iters = [inf.iters for row in cong for inf in row] == iters
+    for pb in probs:
+        pb.set_graph(False)
     out = {"workload": f"C4: {count} Riesz maps, space in grad/curl/div, n in 4..16, p in 3..9 (drawn per "
                        f"problem), {nrhs} RHS each, alpha=beta=1, FP64",
            "problems": count, "rhs_per_problem": nrhs, "total_dofs_x_rhs": dofs_rhs,
@@ -470,6 +509,9 @@ def bench_batched(torch, rz, nrhs=4, nctx=2, count=64):
            "contexts": nctx, "gdofs_rhs_per_s_sequential": round(dofs_rhs / t_seq / 1e9, 4),
            "gdofs_rhs_per_s_batched": round(dofs_rhs / t_con / 1e9, 4),
            "speedup": round(t_seq / t_con, 3), "iters_min_max": [min(iters), max(iters)],
+           "sequential_graph_s": round(t_seq_g, 4), "batched_graph_s": round(t_con_g, 4),
+           "gdofs_rhs_per_s_batched_graph": round(dofs_rhs / t_con_g / 1e9, 4),
+           "speedup_graph_vs_sequential": round(t_seq / t_con_g, 3), "graph_iters_equal": same_iters,
            "max_rel_res": max(inf.rel_res for row in con for inf in row)}
     for pb in probs:
         pb.close()

@@ -116,6 +116,12 @@ typedef struct {
                         * curl-curl potential problem (remark of Sec. 4.3); 0 = 1e-3 */
   int32_t aux;         /* auxiliary operator of the relaxation on trilinear cells     *
                         * (H(grad)): RZ_AUX_CELL_AVG (default) or RZ_AUX_PAPER_DIAG    */
+  int32_t graph;       /* 1: rz_solve / rz_solve_batched run each CG iteration (all    *
+                        * right-hand sides of the call active, iteration >= 1) from    *
+                        * HIP graphs captured on first use (per parity of the count,   *
+                        * vector count and set of x vectors), the cooperative Q_1      *
+                        * coarse solve launched between their segments; same kernels,  *
+                        * same results as 0 (default).  Not with per-kernel timing.    */
 } rz_opts;
 
 /* Auxiliary operators P of the relaxation (Sec. 3.2).  On Cartesian cells with
@@ -286,6 +292,9 @@ rz_status rz_sync(rz_problem *h);
  *                        RZ_AUX_PAPER_DIAG, (p+1)^3 (beta-mass, x fastest) then
  *                        3 blocks of p (p+1)^2 (alpha-mass of NCE component m, its
  *                        DP index along axis m)
+ *   RZ_EXPORT_GRAPHS     int64 triple: CG iterations captured as HIP graphs, iterations
+ *                        run from them, segments per captured iteration (last capture)
+ *                        of this problem (rz_opts.graph)
  *   RZ_EXPORT_EDGE_PATCH int64: edge id, then the DoFs (ascending) of non-empty
  *                        edge-star patch `index` of H(curl) (or of the NCE_p
  *                        potential problem of H(div)); edge ids run over the axis
@@ -295,7 +304,7 @@ enum {
   RZ_EXPORT_DOFMAP = 0, RZ_EXPORT_PATCH = 1, RZ_EXPORT_IC_PATTERN = 2,
   RZ_EXPORT_IC_FACTOR = 3, RZ_EXPORT_TABLES1D = 4, RZ_EXPORT_AUXCOEF = 5,
   RZ_EXPORT_OMEGA = 6, RZ_EXPORT_PATCH_KERNEL = 7, RZ_EXPORT_EDGE_PATCH = 8, RZ_EXPORT_STATS = 9,
-  RZ_EXPORT_PAPER_DIAG = 10, RZ_EXPORT_AUTOTUNE = 11
+  RZ_EXPORT_PAPER_DIAG = 10, RZ_EXPORT_AUTOTUNE = 11, RZ_EXPORT_GRAPHS = 12
 };
 rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *bytes);
 
@@ -315,6 +324,11 @@ enum {
 };
 rz_status rz_timing_enable(rz_problem *h, int on);
 rz_status rz_timing_read(rz_problem *h, double ms[RZ_NKERNELS], int64_t count[RZ_NKERNELS]);
+
+/* Set rz_opts.graph of a problem after setup (1: CG iterations from captured HIP
+ * graphs, 0: launches one by one; turning it off releases the graphs).  Results do
+ * not depend on it. */
+rz_status rz_set_graph(rz_problem *h, int on);
 
 /* ---- learned auxiliary weights (trilinear cells) ----------------------------------
  * The separable auxiliary of the relaxation uses per-cell weights c = (sigma_1..3,

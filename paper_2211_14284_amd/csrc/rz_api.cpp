@@ -26,6 +26,7 @@
 struct rz_ctx {
   int device = -1;
   hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream on which PCG iterations are captured
   std::string err;
   int nlive = 0;  // problems and MLPs created on this context and not yet freed
 };
@@ -196,6 +197,21 @@ struct rz_problem {
   std::vector<std::pair<int, double>> tune[2];
   // per-kernel timing
   bool timing = false;
+  // PCG iterations captured as HIP graphs (opts.graph), one set per parity of the
+  // iteration count (the CG scalars alternate between two slots): the segments
+  // between the cooperative Q_1 coarse solves, which run between their replays, and
+  // the vectors and buffer generation they were captured for
+  struct IterGraph {
+    std::vector<hipGraphExec_t> seg;
+    std::vector<double *> xs;
+    int nv = 0;
+    uint64_t gen = 0;
+    bool f32 = false, ok = false;
+  } ig[2];
+  uint64_t graph_gen = 1;                  // bumped when buffers named by the graphs change
+  int64_t graph_stat[3] = {0, 0, 0};       // captures, replayed iterations, segments
+  std::vector<hipGraph_t> *cap = nullptr;  // capture in progress: the closed segments
+  bool cap_bad = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   std::vector<std::pair<int, size_t>> ev_used;  // (kernel id, pool index)
 };
@@ -258,6 +274,7 @@ rz_status ensure_multi(rz_problem *h, int nv) {
   if (nv <= h->mcap) return RZ_OK;
   HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
   free_multi(h);
+  ++h->graph_gen;  // captured iterations name the buffers being replaced
   const size_t n = (size_t)h->ndofs, extra = (size_t)nv - 1;
   const size_t nzb = h->space == RZ_GRAD ? (size_t)h->nvert * h->ps.nrows : 0;
   auto al = [&](auto **ptr, size_t count) -> rz_status {
@@ -583,6 +600,15 @@ rz_status do_relax_prec(rz_problem *h, const double *r, double *z, double scale,
   return do_relax64(h, r, z, scale, w, acc);
 }
 
+// The cooperative launch of the Q_1 coarse solve on the gathered right-hand side.
+int coarse_coop(rz_problem *h, bool f32) {
+  const int m = h->cm, nb = h->cmz;
+  hipStream_t s = h->ctx->stream;
+  return f32 && h->cW32
+             ? launch_coarse_solve_f(m, nb, h->cq, h->cW32, h->cM32, h->cN32, h->cr, h->cu, h->cv, h->cx, h->status, s)
+             : launch_coarse_solve(m, nb, h->cq, h->cW, h->cM, h->cN, h->cr, h->cu, h->cv, h->cx, h->status, s);
+}
+
 // Coarse solve; f32 selects the FP32 copies of the dense blocks (V-cycles of the
 // mixed protocols), otherwise FP64 throughout.
 rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv, bool f32 = false) {
@@ -591,11 +617,20 @@ rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv, bool f32 = fa
   const int m = h->cm, nb = h->cmz;
   launch_coarse_gather(m * nb, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cNX, h->cNY, rcv, h->cr, h->cv, h->cx,
                        s);
-  const int rc = f32 && h->cW32
-                     ? launch_coarse_solve_f(m, nb, h->cq, h->cW32, h->cM32, h->cN32, h->cr, h->cu, h->cv, h->cx,
-                                             h->status, s)
-                     : launch_coarse_solve(m, nb, h->cq, h->cW, h->cM, h->cN, h->cr, h->cu, h->cv, h->cx, h->status, s);
-  if (rc) return fail(h->ctx, RZ_ERR_HIP, "cooperative launch of the coarse solve failed");
+  if (h->cap) {
+    // capturing a PCG iteration: the cooperative launch stays outside the graphs, so
+    // the segment closes here and the next one starts; the replay runs the solve
+    // between the two segments
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(s, &g) != hipSuccess || !g) h->cap_bad = true;
+    else h->cap->push_back(g);
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      h->cap_bad = true;
+      return fail(h->ctx, RZ_ERR_HIP, "capture of the PCG iteration failed at the coarse solve");
+    }
+  } else if (coarse_coop(h, f32)) {
+    return fail(h->ctx, RZ_ERR_HIP, "cooperative launch of the coarse solve failed");
+  }
   launch_coarse_scatter((int)h->ncoarse, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cmz, h->cNX, h->cNY,
                         h->cx, xcv, s);
   return RZ_OK;
@@ -1277,7 +1312,16 @@ rz_status setup_coarse(rz_problem *h) {
   return RZ_OK;
 }
 
+void graphs_release(rz_problem *h) {
+  for (auto &G : h->ig) {
+    for (hipGraphExec_t e : G.seg) hipGraphExecDestroy(e);
+    G.seg.clear();
+    G.ok = false;
+  }
+}
+
 void release(rz_problem *h) {
+  graphs_release(h);
   if (h->pot) {
     release(h->pot);
     delete h->pot;
@@ -2339,6 +2383,79 @@ void block_decide(rz_problem *h, int i, BlockRun::Rhs &R) {
   R.enq = BlockRun::NONE;
 }
 
+// One CG iteration of the right-hand sides ids (all of the run's, at one iteration
+// count it >= 1) from captured HIP graphs: on first use for this parity, vector count,
+// set of x vectors and buffer generation, the V-cycle and the iteration tails are
+// captured on the context's private stream (nothing runs while capturing), the
+// segments are instantiated, and the host counters are put back; then the segments
+// are launched on the problem's stream with the cooperative coarse solves between
+// them.  done = false (and nothing enqueued) if the capture cannot start.
+rz_status graph_iteration(rz_problem *h, BlockRun &B, const std::vector<int> &ids,
+                          const std::vector<const double *> &rs, const std::vector<double *> &zs, bool &done) {
+  done = false;
+  const int nv = (int)ids.size();
+  const int par = B.s[ids[0]].it & 1;
+  rz_problem::IterGraph &G = h->ig[par];
+  std::vector<double *> xs;
+  for (int i : ids) xs.push_back(B.s[i].x);
+  if (!(G.ok && G.gen == h->graph_gen && G.nv == nv && G.xs == xs)) {
+    for (hipGraphExec_t e : G.seg) hipGraphExecDestroy(e);
+    G.seg.clear();
+    G.ok = false;
+    rz_ctx *c = h->ctx;
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      c->cap_stream = nullptr;
+      return RZ_OK;
+    }
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return RZ_OK;
+    const hipStream_t user = c->stream;
+    std::vector<int> its;
+    for (int i : ids) its.push_back(B.s[i].it);
+    std::vector<hipGraph_t> graphs;
+    c->stream = c->cap_stream;
+    h->cap = &graphs;
+    h->cap_bad = false;
+    rz_status e = vcycle_multi(h, nv, ids.data(), rs.data(), zs.data());
+    for (size_t k = 0; k < ids.size() && !e; ++k) e = block_iteration_tail(h, ids[k], B.s[ids[k]]);
+    hipGraph_t last = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->cap_stream, &last);
+    c->stream = user;
+    h->cap = nullptr;
+    for (size_t k = 0; k < ids.size(); ++k) B.s[ids[k]].it = its[k];
+    bool ok = !e && ee == hipSuccess && last && !h->cap_bad;
+    if (last) graphs.push_back(last);
+    for (hipGraph_t g : graphs) {
+      hipGraphExec_t x = nullptr;
+      if (ok && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess) G.seg.push_back(x);
+      else ok = false;
+      hipGraphDestroy(g);
+    }
+    if (!ok) {
+      for (hipGraphExec_t x : G.seg) hipGraphExecDestroy(x);
+      G.seg.clear();
+      if (e) return e;
+      return fail(h->ctx, RZ_ERR_HIP, "capture of the PCG iteration failed");
+    }
+    G.xs = xs;
+    G.nv = nv;
+    G.gen = h->graph_gen;
+    G.f32 = h->opts.precision != RZ_PREC_F64;
+    G.ok = true;
+    ++h->graph_stat[0];
+    h->graph_stat[2] = (int64_t)G.seg.size();
+  }
+  hipStream_t s = h->ctx->stream;
+  for (size_t k = 0; k < G.seg.size(); ++k) {
+    HIPCALL(h, hipGraphLaunch(G.seg[k], s));
+    if (k + 1 < G.seg.size() && coarse_coop(h, G.f32))
+      return fail(h->ctx, RZ_ERR_HIP, "cooperative launch of the coarse solve failed");
+  }
+  for (int i : ids) ++B.s[i].it;
+  ++h->graph_stat[1];
+  done = true;
+  return RZ_OK;
+}
+
 // Advance every right-hand side by one step (the caller has waited for the
 // previous step's work).
 rz_status block_step(BlockRun &B) {
@@ -2387,11 +2504,18 @@ rz_status block_step(BlockRun &B) {
       zs.push_back(Bi.z);
     }
     if (!ids.empty()) {
-      if (rz_status e = vcycle_multi(h, (int)ids.size(), ids.data(), rs.data(), zs.data())) return e;
-      for (int i : ids) {
-        if (rz_status e = block_iteration_tail(h, i, B.s[i])) return e;
-        B.s[i].enq = BlockRun::ITER;
+      // captured iterations: every right-hand side of the run at one count it >= 1
+      bool graph = h->opts.graph && !h->timing && (int)ids.size() == nv && B.s[ids[0]].it >= 1;
+      for (int i : ids) graph = graph && B.s[i].it == B.s[ids[0]].it;
+      bool done = false;
+      if (graph)
+        if (rz_status e = graph_iteration(h, B, ids, rs, zs, done)) return e;
+      if (!done) {
+        if (rz_status e = vcycle_multi(h, (int)ids.size(), ids.data(), rs.data(), zs.data())) return e;
+        for (int i : ids)
+          if (rz_status e = block_iteration_tail(h, i, B.s[i])) return e;
       }
+      for (int i : ids) B.s[i].enq = BlockRun::ITER;
     }
     for (int i = 0; i < nv; ++i) {
       BlockRun::Rhs &R = B.s[i];
@@ -2492,6 +2616,7 @@ rz_status rz_destroy(rz_ctx *ctx) {
     return RZ_ERR_ARG;
   }
   if (ctx->device >= 0) hipStreamSynchronize(ctx->stream);
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return RZ_OK;
 }
@@ -3058,6 +3183,7 @@ rz_status refactor_patches(rz_problem *h, int *breakdown) {
 }  // namespace
 
 rz_status rz_set_aux(rz_problem *h, const double *coef6) {
+  if (h) ++h->graph_gen;  // the graphs of captured iterations may name replaced buffers
   if (h && h->pd) return fail(h->ctx, RZ_ERR_ARG, "rz_set_aux: the problem uses the paper's auxiliary (RZ_AUX_PAPER_DIAG)");
   rz_status e = require_device(h);
   if (e) return e;
@@ -3100,6 +3226,9 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
     std::memcpy(out.data() + o, src, nb);
   };
   switch (what) {
+    case RZ_EXPORT_GRAPHS:
+      put(h->graph_stat, sizeof h->graph_stat);
+      break;
     case RZ_EXPORT_AUTOTUNE: {
       for (int w = 0; w < 2; ++w) {
         const double n = (double)h->tune[w].size();
@@ -3300,6 +3429,17 @@ rz_status rz_timing_enable(rz_problem *h, int on) {
   rz_status e = require_device(h);
   if (e) return e;
   h->timing = on != 0;
+  return RZ_OK;
+}
+
+rz_status rz_set_graph(rz_problem *h, int on) {
+  rz_status e = require_device(h);
+  if (e) return e;
+  h->opts.graph = on != 0;
+  if (!on) {
+    HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+    graphs_release(h);
+  }
   return RZ_OK;
 }
 

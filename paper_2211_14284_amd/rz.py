@@ -27,7 +27,7 @@ COEF_CONST, COEF_CELL, COEF_SAMPLES = 0, 1, 2
 PREC_F64, PREC_MIXED, PREC_DEFECT = 0, 1, 2
 EXPORT_DOFMAP, EXPORT_PATCH, EXPORT_IC_PATTERN, EXPORT_IC_FACTOR = 0, 1, 2, 3
 EXPORT_TABLES1D, EXPORT_AUXCOEF, EXPORT_OMEGA, EXPORT_PATCH_KERNEL = 4, 5, 6, 7
-EXPORT_EDGE_PATCH, EXPORT_STATS, EXPORT_PAPER_DIAG, EXPORT_AUTOTUNE = 8, 9, 10, 11
+EXPORT_EDGE_PATCH, EXPORT_STATS, EXPORT_PAPER_DIAG, EXPORT_AUTOTUNE, EXPORT_GRAPHS = 8, 9, 10, 11, 12
 AUX_CELL_AVG, AUX_PAPER_DIAG = 0, 1
 KERNELS = ("apply", "condense", "patch", "expand", "transfer", "coarse", "krylov")
 STATUS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_OOM", -3: "RZ_ERR_BREAKDOWN",
@@ -53,7 +53,8 @@ class Coef(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("space", ctypes.c_int32), ("p", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double), ("omega", ctypes.c_double),
-                ("lanczos_seed", ctypes.c_uint64), ("hdiv_eps", ctypes.c_double), ("aux", ctypes.c_int32)]
+                ("lanczos_seed", ctypes.c_uint64), ("hdiv_eps", ctypes.c_double), ("aux", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -82,6 +83,7 @@ _proto = {
     "rz_export": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "rz_sync": (ctypes.c_int, [_vp]),
     "rz_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "rz_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
     "rz_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "rz_aux_data": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "rz_solve_batched": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_vp),
@@ -203,7 +205,8 @@ class Problem:
 
     n: cells per axis (int or 3-tuple); alpha, beta: scalars (constant), arrays of
     one value per cell, or (ncells, 27) arrays of reference samples; vertices:
-    optional (n_vertices, 3) array (any trilinear mesh).
+    optional (n_vertices, 3) array (any trilinear mesh).  Further keywords set the
+    fields of rz_opts (precision, maxit, rtol, omega, hdiv_eps, aux, graph, ...).
     """
 
     def __init__(self, ctx, n, p, alpha=1.0, beta=1.0, space="grad", vertices=None,
@@ -288,6 +291,10 @@ class Problem:
             return infos[0]
         return [infos[r] for r in range(k)]
 
+    def set_graph(self, on=True):
+        """Run CG iterations from captured HIP graphs (rz_opts.graph) or not."""
+        self.ctx.check(lib.rz_set_graph(self.handle, 1 if on else 0))
+
     # ---- per-kernel device timing --------------------------------------------------
     def timing(self, on=True):
         self.ctx.check(lib.rz_timing_enable(self.handle, 1 if on else 0))
@@ -362,6 +369,11 @@ class Problem:
             out[name] = {"candidates": cand, "chosen": int(v[o + 1 + 2 * n])}
             o += 2 + 2 * n
         return out
+
+    def graph_stats(self):
+        """(captures, iterations replayed, segments per captured iteration) of the
+        captured CG iterations (graph=1)."""
+        return tuple(int(v) for v in self._export(EXPORT_GRAPHS, dtype=np.int64))
 
     def aux_coefficients(self):
         return self._export(EXPORT_AUXCOEF).reshape(self.ncells, 6)
