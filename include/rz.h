@@ -122,7 +122,17 @@ typedef struct {
                         * vector count and set of x vectors), the cooperative Q_1      *
                         * coarse solve launched between their segments; same kernels,  *
                         * same results as 0 (default).  Not with per-kernel timing.    */
+  int32_t patch_solver; /* H(grad) vertex-star solves on the statically condensed       *
+                        * patches (Sec. 4.5): RZ_PATCH_IC (default) incomplete Cholesky *
+                        * on the static-condensation pattern, or RZ_PATCH_CHOLESKY the  *
+                        * exact Cholesky factor (the SC-chol column of Table           *
+                        * hgrad-iter), applied as W = L^{-1} dense per patch: memory    *
+                        * grows as p^4 per vertex, meant for small meshes (RZ_ERR_ARG   *
+                        * past 16 GiB of factors)                                       */
 } rz_opts;
+
+/* Vertex-star solvers of the H(grad) relaxation (rz_opts.patch_solver). */
+enum { RZ_PATCH_IC = 0, RZ_PATCH_CHOLESKY = 1 };
 
 /* Auxiliary operators P of the relaxation (Sec. 3.2).  On Cartesian cells with
  * cellwise-constant coefficients both equal A exactly (and the library uses its

@@ -1333,7 +1333,7 @@ __global__ void __launch_bounds__(256) k_patch_factor(LatDev L, PatchDev P, cons
                                                        const double *__restrict__ Bg, const double *__restrict__ Ag,
                                                        const double *__restrict__ lamg, PdDev pd,
                                                        double *__restrict__ f64, float *__restrict__ f32,
-                                                       int *status) {
+                                                       int *status, int ic) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *S = reinterpret_cast<double *>(smem_raw);
   const int p = L.p, n1 = p + 1;
@@ -1396,7 +1396,8 @@ __global__ void __launch_bounds__(256) k_patch_factor(LatDev L, PatchDev P, cons
     allowed[k] = ok ? 1 : 0;
   }
   __syncthreads();
-  for (int lv = 0; lv < P.nflev; ++lv) {
+  // ic = 0: store the assembled S_v on its pattern, unfactored
+  for (int lv = 0; ic && lv < P.nflev; ++lv) {
     const int b = P.flev_ptr[lv], e = P.flev_ptr[lv + 1];
     for (int t = b + threadIdx.x; t < e; t += blockDim.x) {
       int i = P.flev_rows[t];
@@ -2059,13 +2060,68 @@ void launch_expand_grad(const LatDev &L, const PatchDev &P, const T *coef, const
 
 void launch_patch_factor(const LatDev &L, const PatchDev &P, const double *coef, const double *B,
                          const double *A, const double *lam, const PdDev &pd, double *f64, float *f32, int *status,
-                         hipStream_t s) {
+                         hipStream_t s, int ic) {
   long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
   const int n1 = L.p + 1;
   size_t shm = sizeof(double) * (P.nnz + 2 * n1 * n1 + n1) + P.nnz;
   if (shm > 65536) hipFuncSetAttribute((const void *)k_patch_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  k_patch_factor<<<(unsigned)nv, 256, shm, s>>>(L, P, P.erow, coef, B, A, lam, pd, f64, f32, status);
+  k_patch_factor<<<(unsigned)nv, 256, shm, s>>>(L, P, P.erow, coef, B, A, lam, pd, f64, f32, status, ic);
 }
+
+namespace {
+
+// Vertex-patch solves with exact Cholesky factors (eq. sc-asm-afw with
+// S_v^{-1} = L_v^{-T} L_v^{-1}): z_v = W_v^T (W_v b_v) with W_v = L_v^{-1} stored dense,
+// lower, packed by rows (row i at i (i + 1) / 2).  One block per vertex slot: the
+// right-hand side gathered as by the IC solve (rows outside the domain or on a
+// Dirichlet face read 0; their W rows are those of the identity); y = W b with one
+// wavefront per row; z = W^T y with one thread per column reading the rows in order
+// (coalesced); z to the slot's rows of zb.
+template <typename T>
+__global__ void __launch_bounds__(256) k_patch_chol_solve(LatDev L, const int *__restrict__ off, int nr,
+                                                           const T *__restrict__ W, const T *__restrict__ rt,
+                                                           T *__restrict__ zb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *sb = reinterpret_cast<double *>(smem_raw), *sy = sb + nr;
+  const long slot = blockIdx.x;
+  const int nvx = L.nx + 1, nvy = L.ny + 1, p = L.p;
+  const int V[3] = {(int)(slot % nvx), (int)((slot / nvx) % nvy), (int)(slot / ((long)nvx * nvy))};
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = tid; i < nr; i += blockDim.x) {
+    const int X = V[0] * p + off[3 * i], Y = V[1] * p + off[3 * i + 1], Z = V[2] * p + off[3 * i + 2];
+    const bool in = X >= 0 && X < L.Nx && Y >= 0 && Y < L.Ny && Z >= 0 && Z < L.Nz;
+    sb[i] = in && !lat_dirichlet(L, X, Y, Z) ? (double)rt[lat_index(L, X, Y, Z)] : 0.0;
+  }
+  __syncthreads();
+  const T *Ws = W + slot * ((long)nr * (nr + 1) / 2);
+  for (int i = wv; i < nr; i += blockDim.x >> 6) {
+    const T *row = Ws + (long)i * (i + 1) / 2;
+    double acc = 0.0;
+    for (int j = lane; j <= i; j += 64) acc += (double)row[j] * sb[j];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) sy[i] = acc;
+  }
+  __syncthreads();
+  for (int j0 = 0; j0 < nr; j0 += blockDim.x) {
+    const int j = j0 + tid;
+    double acc = 0.0;
+    for (int i = j0; i < nr; ++i)
+      if (j <= i) acc += (double)Ws[(long)i * (i + 1) / 2 + j] * sy[i];
+    if (j < nr) zb[slot * nr + j] = (T)acc;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_patch_chol_solve(const LatDev &L, const PatchDev &P, const T *W, const T *rt, T *zb, hipStream_t s) {
+  const long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);
+  k_patch_chol_solve<T><<<(unsigned)nv, 256, 2 * sizeof(double) * P.nrows, s>>>(L, P.off, P.nrows, W, rt, zb);
+}
+template void launch_patch_chol_solve<double>(const LatDev &, const PatchDev &, const double *, const double *,
+                                              double *, hipStream_t);
+template void launch_patch_chol_solve<float>(const LatDev &, const PatchDev &, const float *, const float *, float *,
+                                             hipStream_t);
 
 static long max_face_points(const LatDev &L) {
   return std::max({(long)L.Ny * L.Nz, (long)L.Nx * L.Nz, (long)L.Nx * L.Ny});

@@ -267,7 +267,11 @@ void launch_expand_plane_grad(const LatDev &L, const T *r, const T *zbuf, T *z, 
 // failing patch + 1 (pivot <= 0).
 void launch_patch_factor(const LatDev &L, const PatchDev &P, const double *coef, const double *B,
                          const double *A, const double *lam, const PdDev &pd, double *f64, float *f32, int *status,
-                         hipStream_t s);
+                         hipStream_t s, int ic = 1);
+// Vertex-patch solves with exact Cholesky factors: z_v = W_v^T (W_v b_v), W_v = L_v^{-1}
+// dense lower packed by rows, nrows (nrows + 1) / 2 values per slot
+template <typename T>
+void launch_patch_chol_solve(const LatDev &L, const PatchDev &P, const T *W, const T *rt, T *zb, hipStream_t s);
 
 // z_D = r_D on Dirichlet rows of the Q_p lattice (r == nullptr: z_D = 0).
 void launch_dirichlet_copy_f(const LatDev &L, const float *r, float *z, hipStream_t s);

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -210,6 +211,10 @@ struct rz_problem {
   } ig[2];
   uint64_t graph_gen = 1;                  // bumped when buffers named by the graphs change
   int64_t graph_stat[3] = {0, 0, 0};       // captures, replayed iterations, segments
+  // exact Cholesky vertex-star solves (opts.patch_solver): W = L^{-1} per slot,
+  // dense lower packed by rows
+  double *cw64 = nullptr;
+  float *cw32 = nullptr;
   std::vector<hipGraph_t> *cap = nullptr;  // capture in progress: the closed segments
   bool cap_bad = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -543,6 +548,22 @@ void expand_any(rz_problem *h, const T *coef, const T *A, const T *lam, const T 
   }
 }
 
+// The vertex-patch solves of the H(grad) relaxation: incomplete factors through the
+// compiled pass schedule, or the exact factors (RZ_PATCH_CHOLESKY) as dense W = L^{-1}
+const double *chol_w(rz_problem *h, const double *) { return h->cw64; }
+const float *chol_w(rz_problem *h, const float *) { return h->cw32; }
+
+template <typename T>
+rz_status patch_solve_any(rz_problem *h, const T *f, const T *rt, T *zb) {
+  if (h->cw64) {
+    launch_patch_chol_solve<T>(h->L, h->P, chol_w(h, (const T *)nullptr), rt, zb, h->ctx->stream);
+    return RZ_OK;
+  }
+  if (launch_patch_solve<T>(h->L, h->PE, f, rt, zb, h->ctx->stream))
+    return fail(h->ctx, RZ_ERR_HIP, "patch solve launch failed");
+  return RZ_OK;
+}
+
 template <typename T>
 rz_status relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T *f, T *rt, T *zb,
                       const T *r, T *z, T scale = T(1), T w = T(0), T *acc = nullptr) {
@@ -553,7 +574,7 @@ rz_status relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, co
   }
   {
     Timed t(h, RZ_K_PATCH);
-    if (launch_patch_solve<T>(h->L, h->PE, f, rt, zb, s)) return fail(h->ctx, RZ_ERR_HIP, "patch solve launch failed");
+    if (rz_status e = patch_solve_any<T>(h, f, rt, zb)) return e;
   }
   {
     Timed t(h, RZ_K_EXPAND);
@@ -841,8 +862,12 @@ rz_status relax_multi(rz_problem *h, int nv, const int *ids, const T *const *r, 
   }
   {
     Timed t(h, RZ_K_PATCH);
-    if (launch_patch_solve_multi<T>(h->L, h->PE, f, nv, rt.data(), zb.data(), s))
+    if (h->cw64) {
+      for (int j = 0; j < nv; ++j)
+        if (rz_status e = patch_solve_any<T>(h, f, rt[j], zb[j])) return e;
+    } else if (launch_patch_solve_multi<T>(h->L, h->PE, f, nv, rt.data(), zb.data(), s)) {
       return fail(h->ctx, RZ_ERR_HIP, "patch solve launch failed");
+    }
   }
   {
     Timed t(h, RZ_K_EXPAND);
@@ -1542,6 +1567,93 @@ rz_status grad_patch_device(rz_problem *h) {
     std::snprintf(msg, sizeof msg, "incomplete Cholesky breakdown in vertex patch %d", stv - 1);
     return fail(ctx, RZ_ERR_BREAKDOWN, msg);
   }
+  return RZ_OK;
+}
+
+// Exact Cholesky factors of the statically condensed vertex-star matrices S_v
+// (rz_opts.patch_solver = RZ_PATCH_CHOLESKY): S_v assembled on the device on its
+// pattern (the setup kernel without its incomplete factorisation), then per slot on
+// host threads: S_v dense, S_v = L L^T, W = L^{-1} (column by column), W packed by
+// rows; W uploaded in FP64 and FP32; the incomplete factors are formed again so that
+// their export is unchanged.
+rz_status setup_patch_cholesky(rz_problem *h) {
+  const PatchSymbolic &ps = h->ps;
+  const int nr = ps.nrows;
+  const size_t tri = (size_t)nr * (nr + 1) / 2, nslot = (size_t)h->nvert;
+  if ((double)nslot * tri * 12.0 > 16.0 * (1ull << 30))
+    return fail(h->ctx, RZ_ERR_ARG, "RZ_PATCH_CHOLESKY: the dense patch factors would exceed 16 GiB (small meshes only)");
+  hipStream_t s = h->ctx->stream;
+  const size_t nf = nslot * ps.stride;
+  HIPCALL(h, hipMemsetAsync(h->f64, 0, nf * sizeof(double), s));
+  launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, pd_dev(h), h->f64, h->f32, h->status, s, 0);
+  std::vector<double> fh(nf);
+  HIPCALL(h, hipMemcpyAsync(fh.data(), h->f64, nf * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCALL(h, hipStreamSynchronize(s));
+  std::vector<double> W(nslot * tri);
+  std::atomic<long> bad(-1);
+  auto work = [&](size_t s0, size_t s1) {
+    std::vector<double> A((size_t)nr * nr), Wc((size_t)nr * nr);
+    for (size_t sl = s0; sl < s1; ++sl) {
+      std::fill(A.begin(), A.end(), 0.0);
+      const double *f = fh.data() + sl * ps.stride;
+      for (int r = 0; r < nr; ++r)
+        for (int k = ps.rowptr[r]; k < ps.rowptr[r + 1]; ++k) A[(size_t)r * nr + ps.col[k]] = f[ps.pos1[k]];
+      // S = L L^T in place (lower; row-oriented)
+      bool ok = true;
+      for (int j = 0; j < nr && ok; ++j) {
+        double d = A[(size_t)j * nr + j];
+        for (int k = 0; k < j; ++k) d -= A[(size_t)j * nr + k] * A[(size_t)j * nr + k];
+        if (!(d > 0.0)) {
+          ok = false;
+          break;
+        }
+        d = std::sqrt(d);
+        A[(size_t)j * nr + j] = d;
+        for (int i = j + 1; i < nr; ++i) {
+          double v = A[(size_t)i * nr + j];
+          const double *ri = &A[(size_t)i * nr], *rj = &A[(size_t)j * nr];
+          for (int k = 0; k < j; ++k) v -= ri[k] * rj[k];
+          A[(size_t)i * nr + j] = v / d;
+        }
+      }
+      if (!ok) {
+        long exp = -1;
+        bad.compare_exchange_strong(exp, (long)sl);
+        continue;
+      }
+      // W = L^{-1}, column c: W[c][c] = 1 / L[c][c], W[i][c] = -(sum_{c<=k<i} L[i][k] W[k][c]) / L[i][i]
+      for (int c = 0; c < nr; ++c) {
+        Wc[(size_t)c * nr + c] = 1.0 / A[(size_t)c * nr + c];
+        for (int i = c + 1; i < nr; ++i) {
+          double v = 0.0;
+          const double *ri = &A[(size_t)i * nr];
+          for (int k = c; k < i; ++k) v += ri[k] * Wc[(size_t)k * nr + c];
+          Wc[(size_t)i * nr + c] = -v / ri[i];
+        }
+      }
+      double *w = W.data() + sl * tri;
+      for (int i = 0; i < nr; ++i)
+        for (int j = 0; j <= i; ++j) w[(size_t)i * (i + 1) / 2 + j] = Wc[(size_t)i * nr + j];
+    }
+  };
+  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t) th.emplace_back(work, nslot * t / nt, nslot * (t + 1) / nt);
+  for (auto &t : th) t.join();
+  if (bad.load() >= 0) {
+    char msg[128];
+    std::snprintf(msg, sizeof msg, "Cholesky breakdown in vertex patch %ld", bad.load());
+    return fail(h->ctx, RZ_ERR_BREAKDOWN, msg);
+  }
+  rz_status e;
+  if (!h->cw64 && ((e = dalloc(h, &h->cw64, nslot * tri)) || (e = dalloc(h, &h->cw32, nslot * tri)))) return e;
+  HIPCALL(h, hipMemcpyAsync(h->cw64, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_cast_d2f(h->cw64, h->cw32, (int64_t)W.size(), s);
+  // the incomplete factors again (their export and the ELL padding as before)
+  HIPCALL(h, hipMemsetAsync(h->f64, 0, nf * sizeof(double), s));
+  HIPCALL(h, hipMemsetAsync(h->f32, 0, nf * sizeof(float), s));
+  launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, pd_dev(h), h->f64, h->f32, h->status, s);
+  HIPCALL(h, hipStreamSynchronize(s));
   return RZ_OK;
 }
 
@@ -2638,6 +2750,10 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
   if (opts->precision != RZ_PREC_F64 && opts->precision != RZ_PREC_MIXED && opts->precision != RZ_PREC_DEFECT)
     return fail(ctx, RZ_ERR_ARG, "bad precision");
   if (opts->aux != RZ_AUX_CELL_AVG && opts->aux != RZ_AUX_PAPER_DIAG) return fail(ctx, RZ_ERR_ARG, "bad aux");
+  if (opts->patch_solver != RZ_PATCH_IC && opts->patch_solver != RZ_PATCH_CHOLESKY)
+    return fail(ctx, RZ_ERR_ARG, "bad patch_solver");
+  if (opts->patch_solver == RZ_PATCH_CHOLESKY && opts->space != RZ_GRAD)
+    return fail(ctx, RZ_ERR_ARG, "RZ_PATCH_CHOLESKY: H(grad) vertex stars only");
   rz_problem *h = new rz_problem();
   h->ctx = ctx;
   h->opts = *opts;
@@ -2759,6 +2875,7 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
   };
   if (h->pd && (e = upload_paper_diagonals(h))) return bail(e);
   if ((e = grad_patch_device(h))) return bail(e);
+  if (h->opts.patch_solver == RZ_PATCH_CHOLESKY && (e = setup_patch_cholesky(h))) return bail(e);
   const int n1 = p + 1;
   if ((e = upload(h, &h->E64, h->t.E))) return bail(e);
   if (!h->quad) {  // A E and B E for the fused coarse correction and residual
@@ -3178,6 +3295,7 @@ rz_status refactor_patches(rz_problem *h, int *breakdown) {
   launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, pd_dev(h), h->f64, h->f32, h->status, s);
   HIPCALL(h, hipMemcpyAsync(breakdown, h->status, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCALL(h, hipStreamSynchronize(s));
+  if (!*breakdown && h->cw64) return setup_patch_cholesky(h);
   return RZ_OK;
 }
 }  // namespace
