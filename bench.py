@@ -257,6 +257,44 @@ def bench_c1(torch, rz, ctx, steps=20):
     return out, sol
 
 
+# Table hgrad-iter, Cartesian meshes, SC columns (SC-chol, SC-ICC) as the paper prints them
+PAPER_HGRAD_ITER = {(3, 0): (11, 11), (3, 1): (11, 11), (7, 0): (9, 10), (7, 1): (9, 10)}
+
+
+def bench_table_hgrad_iter(torch, rz, ctx):
+    """The paper's H(grad) iteration study on Cartesian meshes (Table hgrad-iter, SC
+    columns): alpha = 1, beta = 1e-8, homogeneous Dirichlet, the right-hand side the
+    Riesz representative of a random w (b = (M + K) w, w from U[-1,1) seed 7), CG to a
+    1e-8 reduction of the natural P^{-1}-norm; the statically condensed vertex stars
+    with exact Cholesky (RZ_PATCH_CHOLESKY) and with IC on the static-condensation
+    pattern.  The paper's coarse Cartesian mesh has six cells in the vertical (the
+    horizontal layout is in a figure): l = 0 is taken as 6^3 cells, l = 1 as 12^3."""
+    import synth
+    out = {"workload": "Table hgrad-iter, Cartesian: alpha=1, beta=1e-8, b = (M+K) w, natural-norm criterion",
+           "rows": []}
+    for p, l in ((3, 0), (3, 1), (7, 0), (7, 1)):
+        n = 6 * 2 ** l
+        riesz = rz.Problem(ctx, n, p, 1.0, 1.0)
+        w = torch.as_tensor(synth.rhs_values(riesz.ndofs, 7), device="cuda:0")
+        b = torch.empty_like(w)
+        riesz.apply(w, b)
+        riesz.close()
+        row = {"p": p, "l": l, "cells": n ** 3}
+        for name, ps in (("sc_chol", rz.PATCH_CHOLESKY), ("sc_icc", rz.PATCH_IC)):
+            if ps == rz.PATCH_CHOLESKY and (p, l) == (7, 1):
+                row[name] = None   # 2,197 dense 469 x 469 factors: host setup of minutes, skipped
+                continue
+            pb = rz.Problem(ctx, n, p, 1.0, 1e-8, patch_solver=ps, norm=rz.NORM_NATURAL)
+            x = torch.empty_like(b)
+            info = pb.solve(b, x)
+            row[name] = {"iters_natural": info.iters_natural, "rel_res_2norm_at_exit": info.rel_res}
+            pb.close()
+        row["paper_sc_chol_sc_icc"] = list(PAPER_HGRAD_ITER[(p, l)])
+        out["rows"].append(row)
+        log(f"table hgrad-iter p={p} l={l}: {row}")
+    return out
+
+
 def bench_c3(torch, rz, ctx, steps, warmup, n=16, p=6):
     """C3: H(curl) NCE_6 on a uniform 16^3 mesh, alpha = beta = 1: applies and PCG in
     the three precision protocols (FP64, FP32 relaxation, FP32 operator)."""
@@ -643,12 +681,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--p", type=int, default=7)
-    ap.add_argument("--only", choices=["c2", "c2-apply", "c2-relax", "c3", "c3-apply", "c5-apply"], default=None)
+    ap.add_argument("--only", choices=["c2", "c2-apply", "c2-relax", "c3", "c3-apply", "c5-apply", "table"],
+                    default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--no-table", action="store_true", help="skip the Table hgrad-iter iteration study")
     ap.add_argument("--nrhs", type=int, default=4, help="right-hand sides of the C2 multi-vector solve (1: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB once before the solves (outside the timed region), a plain copy "
@@ -703,6 +743,8 @@ def main():
             pb.close()
         elif piece == "c3":
             res = bench_c3(torch, rz, ctx, args.steps, args.warmup)
+        elif piece == "table":
+            res = bench_table_hgrad_iter(torch, rz, ctx)
         elif piece == "c3-apply":
             pb = rz.Problem(ctx, 16, 6, 1.0, 1.0, space="curl", omega=0.3)
             res["apply_ms_f64"] = time_apply(torch, pb, torch.float64, rz.F64, reps=args.steps)
@@ -729,6 +771,8 @@ def main():
     out["c1"], gpu["c1"] = bench_c1(torch, rz, ctx)
     if not args.no_c3:
         out["c3"] = bench_c3(torch, rz, ctx, max(1, args.steps // 2), 1)
+    if not args.no_table:
+        out["table_hgrad_iter"] = bench_table_hgrad_iter(torch, rz, ctx)
     if not args.no_c5:
         out["c5"] = bench_c5(torch, rz, ctx, max(1, args.steps // 2), 1)
     if not args.no_batched:

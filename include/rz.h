@@ -129,7 +129,17 @@ typedef struct {
                         * hgrad-iter), applied as W = L^{-1} dense per patch: memory    *
                         * grows as p^4 per vertex, meant for small meshes (RZ_ERR_ARG   *
                         * past 16 GiB of factors)                                       */
+  int32_t norm;        /* stopping rule of rz_solve / rz_solve_batched (FP64 and mixed  *
+                        * protocols): RZ_NORM_2 (default) the true 2-norm residual      *
+                        * <= rtol ||b||, confirmed by a residual from x; RZ_NORM_NATURAL *
+                        * the paper's criterion (Sec. 5.1): CG stops once the natural    *
+                        * norm (r^T M^{-1} r)^{1/2} of a residual has dropped by rtol    *
+                        * against the first (iters_natural then counts the iterations,   *
+                        * rel_res reports the true 2-norm residual at exit)              */
 } rz_opts;
+
+/* Stopping rules (rz_opts.norm). */
+enum { RZ_NORM_2 = 0, RZ_NORM_NATURAL = 1 };
 
 /* Vertex-star solvers of the H(grad) relaxation (rz_opts.patch_solver). */
 enum { RZ_PATCH_IC = 0, RZ_PATCH_CHOLESKY = 1 };

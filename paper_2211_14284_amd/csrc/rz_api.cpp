@@ -2460,7 +2460,10 @@ void block_decide(rz_problem *h, int i, BlockRun::Rhs &R) {
       if (!(pAp > 0)) {
         R.result = fail(h->ctx, RZ_ERR_BREAKDOWN, "CG breakdown: p.Ap <= 0");
         R.next = BlockRun::FINAL;
-      } else if (std::sqrt(rr) <= R.tol) {  // recurrence converged: check the true residual
+      } else if (h->opts.norm == RZ_NORM_NATURAL && R.it_natural >= 0) {  // the paper's criterion
+        R.result = RZ_OK;
+        R.next = BlockRun::FINAL;
+      } else if (h->opts.norm != RZ_NORM_NATURAL && std::sqrt(rr) <= R.tol) {  // check the true residual
         R.next = BlockRun::TRUE_RES;
       } else if (R.it >= h->opts.maxit) {
         R.result = RZ_ERR_NOT_CONVERGED;
@@ -2752,6 +2755,7 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
   if (opts->aux != RZ_AUX_CELL_AVG && opts->aux != RZ_AUX_PAPER_DIAG) return fail(ctx, RZ_ERR_ARG, "bad aux");
   if (opts->patch_solver != RZ_PATCH_IC && opts->patch_solver != RZ_PATCH_CHOLESKY)
     return fail(ctx, RZ_ERR_ARG, "bad patch_solver");
+  if (opts->norm != RZ_NORM_2 && opts->norm != RZ_NORM_NATURAL) return fail(ctx, RZ_ERR_ARG, "bad norm");
   if (opts->patch_solver == RZ_PATCH_CHOLESKY && opts->space != RZ_GRAD)
     return fail(ctx, RZ_ERR_ARG, "RZ_PATCH_CHOLESKY: H(grad) vertex stars only");
   rz_problem *h = new rz_problem();

@@ -156,3 +156,27 @@ def test_cholesky_rejected_outside_hgrad(rz, ctx):
         rz.Problem(ctx, 2, 3, 1.0, 1.0, space="curl", patch_solver=rz.PATCH_CHOLESKY)
     with pytest.raises(rz.RzError):
         rz.Problem(ctx, 2, 3, 1.0, 1.0, patch_solver=7)
+
+
+@pytest.mark.parametrize("patch_solver", [0, 1])
+def test_natural_norm_stopping_rule(rz, ctx, patch_solver):
+    """rz_opts.norm = RZ_NORM_NATURAL stops CG one iteration after the natural norm
+    has dropped by rtol (the count the 2-norm solve reports as iters_natural on the
+    same iterates), with the true residual reported at exit."""
+    n, p = (3, 3, 3), 4
+    al, be = coefs(n, 5)
+    b = None
+    res = {}
+    for norm in (rz.NORM_2, rz.NORM_NATURAL):
+        pb = rz.Problem(ctx, n, p, al, be, patch_solver=patch_solver, norm=norm)
+        try:
+            if b is None:
+                b = T(synth.rhs_values(pb.ndofs, 4))
+            x = torch.empty_like(b)
+            res[norm] = pb.solve(b, x)
+        finally:
+            pb.close()
+    i2, inat = res[rz.NORM_2], res[rz.NORM_NATURAL]
+    assert inat.iters_natural == i2.iters_natural >= 1
+    assert inat.iters == inat.iters_natural + 1
+    assert 0 < inat.rel_res < 1e-5
