@@ -227,3 +227,56 @@ class SCRelaxGrad:
         z[self.dmask] = r[self.dmask]
         return z
 
+
+
+def full_star_patches_grad(lat: Lattice):
+    """List of (vertex_id, dof array) of the vertex stars without static
+    condensation (Sec. 4.3, eq. pafw): every free DoF strictly inside the cells around
+    the vertex (|X - vx p| < p on every axis), ordered lexicographically by its offset
+    from the vertex with x fastest (a reading: the paper does not fix an order; it
+    matters for the incomplete factorisation only)."""
+    mesh, p = lat.mesh, lat.p
+    co = lat.coords()
+    free = ~lat.dirichlet_mask()
+    X, Y, Z = co[:, 1], co[:, 2], co[:, 3]
+    out = []
+    nvx, nvy, nvz = mesh.nx + 1, mesh.ny + 1, mesh.nz + 1
+    for vz in range(nvz):
+        for vy in range(nvy):
+            for vx in range(nvx):
+                dX, dY, dZ = X - vx * p, Y - vy * p, Z - vz * p
+                sel = np.where((np.abs(dX) < p) & (np.abs(dY) < p) & (np.abs(dZ) < p) & free)[0]
+                if sel.size == 0:
+                    continue
+                order = np.lexsort((dX[sel], dY[sel], dZ[sel]))
+                out.append((vx + nvx * (vy + nvy * vz), sel[order]))
+    return out
+
+
+class PAFWRelaxGrad:
+    """z = M^{-1} r for PAFW without static condensation (H(grad); Sec. 4.3 eq. pafw,
+    the additive fine part of eq. asm-afw): z = sum_v R_v^T P_v^{-1} R_v r over the full
+    vertex stars, P_v = R_v P R_v^T, factored exactly (factor="chol") or by incomplete
+    Cholesky on the pattern of P_v (factor="ic"); Dirichlet rows copy r."""
+
+    def __init__(self, lat: Lattice, P, factor="chol"):
+        self.lat = lat
+        P = sp.csr_matrix(P)
+        self.dmask = lat.dirichlet_mask()
+        self.patches = full_star_patches_grad(lat)
+        self.factors = []
+        for vid, dofs in self.patches:
+            Pv = P[dofs][:, dofs].toarray()
+            if factor == "ic":
+                self.factors.append(ic_on_pattern(Pv, Pv != 0))
+            else:
+                self.factors.append(np.linalg.cholesky(Pv))
+
+    def apply(self, r):
+        r = np.asarray(r, dtype=np.float64)
+        z = np.zeros_like(r)
+        for (vid, dofs), L in zip(self.patches, self.factors):
+            y = scipy.linalg.solve_triangular(L, r[dofs], lower=True)
+            z[dofs] += scipy.linalg.solve_triangular(L.T, y, lower=False)
+        z[self.dmask] = r[self.dmask]
+        return z

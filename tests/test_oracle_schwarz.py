@@ -216,3 +216,57 @@ def test_vcycle_symmetric_positive_definite():
     S = Skewed(lat, A, R, Pr, cs, pmg.omega_from_lambda(lam))
     a, b = us[0] @ S(us[1]), us[1] @ S(us[0])
     assert abs(a - b) > 1e-8 * abs(a)
+
+
+def test_full_star_single_patch_exact_inverse():
+    # n = 2, all faces Dirichlet: the centre vertex's full star holds every free DoF,
+    # so with exact factors its solve alone is A^{-1} (P = A on Cartesian cells)
+    m = Mesh(2, 2, 2)
+    lat = Lattice(m, "grad", 3)
+    A = asm.with_dirichlet(lat, asm.cartesian_operator(lat, 0.6, 2.5))
+    P = auxop.separable_operator(lat, auxop.cartesian_coefficient_array(lat, 0.6, 2.5))
+    R = schwarz.PAFWRelaxGrad(lat, P, factor="chol")
+    free = np.where(~lat.dirichlet_mask())[0]
+    keep = [i for i, (v, d) in enumerate(R.patches) if v == 13]
+    assert len(keep) == 1 and np.array_equal(np.sort(R.patches[keep[0]][1]), free)
+    R.patches = [R.patches[keep[0]]]
+    R.factors = [R.factors[keep[0]]]
+    b = np.where(lat.dirichlet_mask(), 0.0, np.random.default_rng(4).standard_normal(lat.ndofs))
+    x = spla.spsolve(A.tocsc(), b)
+    assert np.abs(R.apply(b) - x).max() < 1e-11 * np.abs(x).max()
+
+
+def test_full_star_sizes_and_order():
+    # an interior vertex's full star is the (2p-1)^3 box around it, x fastest
+    m = Mesh(3, 3, 3)
+    p = 2
+    lat = Lattice(m, "grad", p)
+    pts = dict(schwarz.full_star_patches_grad(lat))
+    v = 1 + 4 * (1 + 4 * 1)
+    co = lat.coords()
+    d = co[pts[v], 1:] - np.array([p, p, p])
+    assert len(pts[v]) == (2 * p - 1) ** 3
+    assert d[:3].tolist() == [[-1, -1, -1], [0, -1, -1], [1, -1, -1]]
+    assert d[3].tolist() == [-1, 0, -1]
+    # a corner vertex with Dirichlet faces: only the free points of its one cell
+    assert len(pts[0]) == (p - 1) ** 3
+
+
+def test_full_star_relax_spd_and_ic_differs():
+    m = Mesh(2, 2, 2)
+    lat = Lattice(m, "grad", 3)
+    co = np.random.default_rng(8).uniform(0.3, 3.0, (m.ncells, 6))
+    P = auxop.separable_operator(lat, co)
+    Rc = schwarz.PAFWRelaxGrad(lat, P, factor="chol")
+    Ri = schwarz.PAFWRelaxGrad(lat, P, factor="ic")
+    free = np.where(~lat.dirichlet_mask())[0]
+    for R in (Rc, Ri):
+        Mi = np.zeros((free.size, free.size))
+        for k, g in enumerate(free):
+            e = np.zeros(lat.ndofs)
+            e[g] = 1.0
+            Mi[:, k] = R.apply(e)[free]
+        assert np.abs(Mi - Mi.T).max() < 1e-12 * np.abs(Mi).max()
+        assert np.linalg.eigvalsh(0.5 * (Mi + Mi.T)).min() > 0
+    r = np.where(lat.dirichlet_mask(), 0.0, np.random.default_rng(9).standard_normal(lat.ndofs))
+    assert np.linalg.norm(Rc.apply(r) - Ri.apply(r)) > 1e-6 * np.linalg.norm(Rc.apply(r))
