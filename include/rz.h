@@ -129,6 +129,15 @@ typedef struct {
                         * hgrad-iter), applied as W = L^{-1} dense per patch: memory    *
                         * grows as p^4 per vertex, meant for small meshes (RZ_ERR_ARG   *
                         * past 16 GiB of factors)                                       */
+  int32_t decomposition; /* H(grad) relaxation (Sec. 4.3-4.4): RZ_DECOMP_SC (default)  *
+                        * SC-PAFW, vertex stars on the statically condensed interface; *
+                        * RZ_DECOMP_FULL PAFW without static condensation (eq. pafw):  *
+                        * every DoF strictly inside the cells around a vertex, the star *
+                        * matrix factored exactly (patch_solver RZ_PATCH_CHOLESKY) or   *
+                        * by IC on its pattern (RZ_PATCH_IC), both applied as dense     *
+                        * W = L^{-1} (the chol / ICC columns of Table hgrad-iter);      *
+                        * (2p-1)^3 rows per star, for small meshes and degrees          *
+                        * (RZ_ERR_ARG past 16 GiB of factors or about 5e11 host flops)  */
   int32_t norm;        /* stopping rule of rz_solve / rz_solve_batched (FP64 and mixed  *
                         * protocols): RZ_NORM_2 (default) the true 2-norm residual      *
                         * <= rtol ||b||, confirmed by a residual from x; RZ_NORM_NATURAL *
@@ -137,6 +146,9 @@ typedef struct {
                         * against the first (iters_natural then counts the iterations,   *
                         * rel_res reports the true 2-norm residual at exit)              */
 } rz_opts;
+
+/* Decompositions of the H(grad) relaxation (rz_opts.decomposition). */
+enum { RZ_DECOMP_SC = 0, RZ_DECOMP_FULL = 1 };
 
 /* Stopping rules (rz_opts.norm). */
 enum { RZ_NORM_2 = 0, RZ_NORM_NATURAL = 1 };

@@ -2113,6 +2113,59 @@ __global__ void __launch_bounds__(256) k_patch_chol_solve(LatDev L, const int *_
 
 }  // namespace
 
+namespace {
+
+// Sum over the full vertex stars holding each lattice point (vertex v holds X iff
+// |X - v p| < p on every axis: one vertex per axis on a vertex plane, two off it) of
+// their solutions, in a fixed order (z, y, x of the vertices); Dirichlet points take
+// r.  v = scale * (that); z = v, or with acc: acc += w v.
+template <typename T>
+__global__ void k_full_star_sum(LatDev L, int nrf, const T *__restrict__ zb, const T *__restrict__ r,
+                                T *__restrict__ z, T scale, T w, T *__restrict__ acc, long n) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int p = L.p, q = 2 * p - 1;
+  const int X[3] = {(int)(g % L.Nx), (int)((g / L.Nx) % L.Ny), (int)(g / ((long)L.Nx * L.Ny))};
+  T v;
+  if (lat_dirichlet(L, X[0], X[1], X[2])) {
+    v = r[g];
+  } else {
+    int v0[3], nv[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      v0[d] = X[d] / p;
+      nv[d] = X[d] - v0[d] * p == 0 ? 1 : 2;
+    }
+    const int nvx = L.nx + 1, nvy = L.ny + 1;
+    T sum = 0;
+    for (int k = 0; k < nv[2]; ++k)
+      for (int j = 0; j < nv[1]; ++j)
+        for (int i = 0; i < nv[0]; ++i) {
+          const int V[3] = {v0[0] + i, v0[1] + j, v0[2] + k};
+          const long slot = V[0] + (long)nvx * (V[1] + (long)nvy * V[2]);
+          const int o = (X[0] - V[0] * p + p - 1) + q * ((X[1] - V[1] * p + p - 1) + q * (X[2] - V[2] * p + p - 1));
+          sum += zb[slot * nrf + o];
+        }
+    v = sum;
+  }
+  v *= scale;
+  if (acc) acc[g] += w * v;
+  else z[g] = v;
+}
+
+}  // namespace
+
+template <typename T>
+void launch_full_star_sum(const LatDev &L, int nrf, const T *zb, const T *r, T *z, T scale, T w, T *acc,
+                          hipStream_t s) {
+  const long n = (long)L.Nx * L.Ny * L.Nz;
+  k_full_star_sum<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(L, nrf, zb, r, z, scale, w, acc, n);
+}
+template void launch_full_star_sum<double>(const LatDev &, int, const double *, const double *, double *, double,
+                                           double, double *, hipStream_t);
+template void launch_full_star_sum<float>(const LatDev &, int, const float *, const float *, float *, float, float,
+                                          float *, hipStream_t);
+
 template <typename T>
 void launch_patch_chol_solve(const LatDev &L, const PatchDev &P, const T *W, const T *rt, T *zb, hipStream_t s) {
   const long nv = (long)(L.nx + 1) * (L.ny + 1) * (L.nz + 1);

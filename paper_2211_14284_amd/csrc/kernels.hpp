@@ -272,6 +272,11 @@ void launch_patch_factor(const LatDev &L, const PatchDev &P, const double *coef,
 // dense lower packed by rows, nrows (nrows + 1) / 2 values per slot
 template <typename T>
 void launch_patch_chol_solve(const LatDev &L, const PatchDev &P, const T *W, const T *rt, T *zb, hipStream_t s);
+// Sum of the full vertex stars' solutions at every lattice point (Dirichlet points take
+// r), times scale, to z, or with acc: acc += w times that
+template <typename T>
+void launch_full_star_sum(const LatDev &L, int nrf, const T *zb, const T *r, T *z, T scale, T w, T *acc,
+                          hipStream_t s);
 
 // z_D = r_D on Dirichlet rows of the Q_p lattice (r == nullptr: z_D = 0).
 void launch_dirichlet_copy_f(const LatDev &L, const float *r, float *z, hipStream_t s);

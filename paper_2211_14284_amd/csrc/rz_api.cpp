@@ -215,6 +215,12 @@ struct rz_problem {
   // dense lower packed by rows
   double *cw64 = nullptr;
   float *cw32 = nullptr;
+  // full vertex stars (opts.decomposition): rows per star, the star's offsets (in PF),
+  // and the per-slot solutions
+  int nrf = 0;
+  PatchDev PF{};
+  double *fzb64 = nullptr;
+  float *fzb32 = nullptr;
   std::vector<hipGraph_t> *cap = nullptr;  // capture in progress: the closed segments
   bool cap_bad = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -564,10 +570,27 @@ rz_status patch_solve_any(rz_problem *h, const T *f, const T *rt, T *zb) {
   return RZ_OK;
 }
 
+double *full_zb(rz_problem *h, double *) { return h->fzb64; }
+float *full_zb(rz_problem *h, float *) { return h->fzb32; }
+
+// The relaxation with full vertex stars (no static condensation): the star solves on
+// r, then their sum at every point
+template <typename T>
+void relax_full(rz_problem *h, const T *r, T *z, T scale, T w, T *acc) {
+  Timed t(h, RZ_K_PATCH);
+  T *zb = full_zb(h, (T *)nullptr);
+  launch_patch_chol_solve<T>(h->L, h->PF, chol_w(h, (const T *)nullptr), r, zb, h->ctx->stream);
+  launch_full_star_sum<T>(h->L, h->nrf, zb, r, z, scale, w, acc, h->ctx->stream);
+}
+
 template <typename T>
 rz_status relax_steps(rz_problem *h, const T *coef, const T *A, const T *lam, const T *f, T *rt, T *zb,
                       const T *r, T *z, T scale = T(1), T w = T(0), T *acc = nullptr) {
   hipStream_t s = h->ctx->stream;
+  if (h->nrf) {
+    relax_full<T>(h, r, z, scale, w, acc);
+    return RZ_OK;
+  }
   {
     Timed t(h, RZ_K_CONDENSE);
     condense_any<T>(h, coef, A, lam, r, rt);
@@ -836,6 +859,13 @@ rz_status relax_multi(rz_problem *h, int nv, const int *ids, const T *const *r, 
       if (rz_status e = relax_vec<T>(h, vec_ptrs(h, (T *)nullptr), r[j], z[j])) return e;
       if (acc) axpy_t(w, z[j], acc[j], h->ndofs, s);
       else if (scale != T(1)) scale_copy_t(scale, z[j], z[j], h->ndofs, s);
+      post(j);
+    }
+    return RZ_OK;
+  }
+  if (h->nrf) {
+    for (int j = 0; j < nv; ++j) {
+      relax_full<T>(h, r[j], z[j], scale, w, acc ? acc[j] : nullptr);
       post(j);
     }
     return RZ_OK;
@@ -1570,12 +1600,104 @@ rz_status grad_patch_device(rz_problem *h) {
   return RZ_OK;
 }
 
+// Dense lower factor of a symmetric matrix A (n x n, row-major; overwritten by L),
+// row-oriented: for each row i the entries j < i in ascending order, then the pivot;
+// with pat (n x n flags) the entries off the pattern are dropped (incomplete
+// Cholesky on the pattern), without it the factor is exact.  False on a pivot <= 0.
+bool dense_factor(std::vector<double> &A, int n, const std::vector<unsigned char> *pat) {
+  for (int i = 0; i < n; ++i) {
+    double *ri = &A[(size_t)i * n];
+    for (int j = 0; j < i; ++j) {
+      if (pat && !(*pat)[(size_t)i * n + j]) {
+        ri[j] = 0.0;
+        continue;
+      }
+      const double *rj = &A[(size_t)j * n];
+      double v = ri[j];
+      for (int k = 0; k < j; ++k) v -= ri[k] * rj[k];
+      ri[j] = v / rj[j];
+    }
+    double d = ri[i];
+    for (int k = 0; k < i; ++k) d -= ri[k] * ri[k];
+    if (!(d > 0.0)) return false;
+    ri[i] = std::sqrt(d);
+    for (int j = i + 1; j < n; ++j) ri[j] = 0.0;
+  }
+  return true;
+}
+
+// W = L^{-1} of a dense lower L (n x n, row-major), column by column:
+// W[c][c] = 1 / L[c][c], W[i][c] = -(sum_{c<=k<i} L[i][k] W[k][c]) / L[i][i]; written
+// packed by rows (row i at i (i + 1) / 2) to out.
+void dense_inverse_packed(const std::vector<double> &L, int n, std::vector<double> &Wc, double *out) {
+  Wc.assign((size_t)n * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    Wc[(size_t)c * n + c] = 1.0 / L[(size_t)c * n + c];
+    for (int i = c + 1; i < n; ++i) {
+      double v = 0.0;
+      const double *ri = &L[(size_t)i * n];
+      for (int k = c; k < i; ++k) v += ri[k] * Wc[(size_t)k * n + c];
+      Wc[(size_t)i * n + c] = -v / ri[i];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) out[(size_t)i * (i + 1) / 2 + j] = Wc[(size_t)i * n + j];
+}
+
+// Per slot on host threads: fill(slot, A) builds the dense patch matrix, then the
+// exact (pat == nullptr) or incomplete factor and W = L^{-1}, packed by rows, into W;
+// the first slot with a pivot <= 0, or -1.
+template <typename Fill>
+long factor_slots(size_t nslot, int n, const std::vector<unsigned char> *(*patf)(size_t, const std::vector<double> &,
+                                                                                 std::vector<unsigned char> &),
+                  Fill fill, std::vector<double> &W) {
+  const size_t tri = (size_t)n * (n + 1) / 2;
+  W.assign(nslot * tri, 0.0);
+  std::atomic<long> bad(-1);
+  auto work = [&](size_t s0, size_t s1) {
+    std::vector<double> A((size_t)n * n), Wc;
+    std::vector<unsigned char> pat;
+    for (size_t sl = s0; sl < s1; ++sl) {
+      std::fill(A.begin(), A.end(), 0.0);
+      fill(sl, A);
+      const std::vector<unsigned char> *pp = patf ? patf(sl, A, pat) : nullptr;
+      if (!dense_factor(A, n, pp)) {
+        long exp = -1;
+        bad.compare_exchange_strong(exp, (long)sl);
+        continue;
+      }
+      dense_inverse_packed(A, n, Wc, W.data() + sl * tri);
+    }
+  };
+  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t) th.emplace_back(work, nslot * t / nt, nslot * (t + 1) / nt);
+  for (auto &t : th) t.join();
+  return bad.load();
+}
+
+// the pattern of a dense patch matrix: its nonzero entries
+const std::vector<unsigned char> *nonzero_pattern(size_t, const std::vector<double> &A,
+                                                  std::vector<unsigned char> &pat) {
+  pat.resize(A.size());
+  for (size_t k = 0; k < A.size(); ++k) pat[k] = A[k] != 0.0;
+  return &pat;
+}
+
+rz_status upload_patch_inverse(rz_problem *h, const std::vector<double> &W) {
+  rz_status e;
+  if (!h->cw64 && ((e = dalloc(h, &h->cw64, W.size())) || (e = dalloc(h, &h->cw32, W.size())))) return e;
+  HIPCALL(h, hipMemcpyAsync(h->cw64, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice, h->ctx->stream));
+  launch_cast_d2f(h->cw64, h->cw32, (int64_t)W.size(), h->ctx->stream);
+  HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+  return RZ_OK;
+}
+
 // Exact Cholesky factors of the statically condensed vertex-star matrices S_v
 // (rz_opts.patch_solver = RZ_PATCH_CHOLESKY): S_v assembled on the device on its
 // pattern (the setup kernel without its incomplete factorisation), then per slot on
-// host threads: S_v dense, S_v = L L^T, W = L^{-1} (column by column), W packed by
-// rows; W uploaded in FP64 and FP32; the incomplete factors are formed again so that
-// their export is unchanged.
+// host threads: S_v dense, S_v = L L^T, W = L^{-1}, packed by rows; W uploaded in FP64
+// and FP32; the incomplete factors are formed again so that their export is unchanged.
 rz_status setup_patch_cholesky(rz_problem *h) {
   const PatchSymbolic &ps = h->ps;
   const int nr = ps.nrows;
@@ -1589,72 +1711,118 @@ rz_status setup_patch_cholesky(rz_problem *h) {
   std::vector<double> fh(nf);
   HIPCALL(h, hipMemcpyAsync(fh.data(), h->f64, nf * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCALL(h, hipStreamSynchronize(s));
-  std::vector<double> W(nslot * tri);
-  std::atomic<long> bad(-1);
-  auto work = [&](size_t s0, size_t s1) {
-    std::vector<double> A((size_t)nr * nr), Wc((size_t)nr * nr);
-    for (size_t sl = s0; sl < s1; ++sl) {
-      std::fill(A.begin(), A.end(), 0.0);
-      const double *f = fh.data() + sl * ps.stride;
-      for (int r = 0; r < nr; ++r)
-        for (int k = ps.rowptr[r]; k < ps.rowptr[r + 1]; ++k) A[(size_t)r * nr + ps.col[k]] = f[ps.pos1[k]];
-      // S = L L^T in place (lower; row-oriented)
-      bool ok = true;
-      for (int j = 0; j < nr && ok; ++j) {
-        double d = A[(size_t)j * nr + j];
-        for (int k = 0; k < j; ++k) d -= A[(size_t)j * nr + k] * A[(size_t)j * nr + k];
-        if (!(d > 0.0)) {
-          ok = false;
-          break;
-        }
-        d = std::sqrt(d);
-        A[(size_t)j * nr + j] = d;
-        for (int i = j + 1; i < nr; ++i) {
-          double v = A[(size_t)i * nr + j];
-          const double *ri = &A[(size_t)i * nr], *rj = &A[(size_t)j * nr];
-          for (int k = 0; k < j; ++k) v -= ri[k] * rj[k];
-          A[(size_t)i * nr + j] = v / d;
-        }
-      }
-      if (!ok) {
-        long exp = -1;
-        bad.compare_exchange_strong(exp, (long)sl);
-        continue;
-      }
-      // W = L^{-1}, column c: W[c][c] = 1 / L[c][c], W[i][c] = -(sum_{c<=k<i} L[i][k] W[k][c]) / L[i][i]
-      for (int c = 0; c < nr; ++c) {
-        Wc[(size_t)c * nr + c] = 1.0 / A[(size_t)c * nr + c];
-        for (int i = c + 1; i < nr; ++i) {
-          double v = 0.0;
-          const double *ri = &A[(size_t)i * nr];
-          for (int k = c; k < i; ++k) v += ri[k] * Wc[(size_t)k * nr + c];
-          Wc[(size_t)i * nr + c] = -v / ri[i];
-        }
-      }
-      double *w = W.data() + sl * tri;
-      for (int i = 0; i < nr; ++i)
-        for (int j = 0; j <= i; ++j) w[(size_t)i * (i + 1) / 2 + j] = Wc[(size_t)i * nr + j];
-    }
-  };
-  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  std::vector<std::thread> th;
-  for (unsigned t = 0; t < nt; ++t) th.emplace_back(work, nslot * t / nt, nslot * (t + 1) / nt);
-  for (auto &t : th) t.join();
-  if (bad.load() >= 0) {
+  std::vector<double> W;
+  const long bad = factor_slots(nslot, nr, nullptr, [&](size_t sl, std::vector<double> &A) {
+    const double *f = fh.data() + sl * ps.stride;
+    for (int r = 0; r < nr; ++r)
+      for (int k = ps.rowptr[r]; k < ps.rowptr[r + 1]; ++k) A[(size_t)r * nr + ps.col[k]] = f[ps.pos1[k]];
+    for (int r = 0; r < nr; ++r)  // symmetric: the upper triangle from the lower
+      for (int c = 0; c < r; ++c) A[(size_t)c * nr + r] = A[(size_t)r * nr + c];
+  }, W);
+  if (bad >= 0) {
     char msg[128];
-    std::snprintf(msg, sizeof msg, "Cholesky breakdown in vertex patch %ld", bad.load());
+    std::snprintf(msg, sizeof msg, "Cholesky breakdown in vertex patch %ld", bad);
     return fail(h->ctx, RZ_ERR_BREAKDOWN, msg);
   }
-  rz_status e;
-  if (!h->cw64 && ((e = dalloc(h, &h->cw64, nslot * tri)) || (e = dalloc(h, &h->cw32, nslot * tri)))) return e;
-  HIPCALL(h, hipMemcpyAsync(h->cw64, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  launch_cast_d2f(h->cw64, h->cw32, (int64_t)W.size(), s);
+  if (rz_status e = upload_patch_inverse(h, W)) return e;
   // the incomplete factors again (their export and the ELL padding as before)
   HIPCALL(h, hipMemsetAsync(h->f64, 0, nf * sizeof(double), s));
   HIPCALL(h, hipMemsetAsync(h->f32, 0, nf * sizeof(float), s));
   launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, pd_dev(h), h->f64, h->f32, h->status, s);
   HIPCALL(h, hipStreamSynchronize(s));
   return RZ_OK;
+}
+
+// Full vertex stars (rz_opts.decomposition = RZ_DECOMP_FULL, PAFW without static
+// condensation, eq. pafw): every lattice point strictly inside the 8 cells around a
+// vertex, rows in the (2p-1)^3 box of offsets with x fastest (points outside the
+// domain or on a Dirichlet face are identity rows).  P_v assembled on host threads
+// from the separable cell weights and the 1-D tables (P_K(u, w) = s_0 A B B + s_1 B A B
+// + s_2 B B A + mu B B B over the cells holding both points), factored exactly or by IC
+// on its pattern, W = L^{-1} uploaded.
+rz_status setup_full_stars(rz_problem *h) {
+  const int p = h->p, q = 2 * p - 1, n1 = p + 1;
+  const int nrf = q * q * q;
+  const size_t tri = (size_t)nrf * (nrf + 1) / 2, nslot = (size_t)h->nvert;
+  if ((double)nslot * tri * 12.0 > 16.0 * (1ull << 30) || (double)nslot * nrf * nrf * (double)nrf > 5e11)
+    return fail(h->ctx, RZ_ERR_ARG, "RZ_DECOMP_FULL: the dense full-star factors are for small meshes and degrees");
+  std::vector<int> off(3 * (size_t)nrf);
+  for (int i = 0; i < nrf; ++i) {
+    off[3 * i] = i % q - (p - 1);
+    off[3 * i + 1] = (i / q) % q - (p - 1);
+    off[3 * i + 2] = i / (q * q) - (p - 1);
+  }
+  const int nvx = h->nx + 1, nvy = h->ny + 1;
+  const int N[3] = {h->nx * p + 1, h->ny * p + 1, h->nz * p + 1}, nc[3] = {h->nx, h->ny, h->nz};
+  const std::vector<double> &B = h->t.B, &A = h->t.A;
+  auto dir = [&](const int X[3]) {
+    for (int d = 0; d < 3; ++d) {
+      if (((h->dir >> (2 * d)) & 1u) && X[d] == 0) return true;
+      if (((h->dir >> (2 * d + 1)) & 1u) && X[d] == N[d] - 1) return true;
+    }
+    return false;
+  };
+  std::vector<double> W;
+  const bool ic = h->opts.patch_solver == RZ_PATCH_IC;
+  const long bad = factor_slots(nslot, nrf, ic ? nonzero_pattern : nullptr, [&](size_t sl, std::vector<double> &M) {
+    const int V[3] = {(int)(sl % nvx), (int)((sl / nvx) % nvy), (int)(sl / ((size_t)nvx * nvy))};
+    std::vector<char> live(nrf);
+    for (int i = 0; i < nrf; ++i) {
+      int X[3];
+      bool in = true;
+      for (int d = 0; d < 3; ++d) {
+        X[d] = V[d] * p + off[3 * i + d];
+        in = in && X[d] >= 0 && X[d] < N[d];
+      }
+      live[i] = in && !dir(X);
+    }
+    for (int i = 0; i < nrf; ++i) {
+      if (!live[i]) {
+        M[(size_t)i * nrf + i] = 1.0;
+        continue;
+      }
+      for (int j = 0; j < nrf; ++j) {
+        if (!live[j]) continue;
+        double v = 0.0;
+        for (int cell = 0; cell < 8; ++cell) {
+          int cc[3], u[3], w[3];
+          bool ok = true;
+          for (int d = 0; d < 3; ++d) {
+            cc[d] = V[d] - 1 + ((cell >> d) & 1);
+            u[d] = V[d] * p + off[3 * i + d] - cc[d] * p;
+            w[d] = V[d] * p + off[3 * j + d] - cc[d] * p;
+            ok = ok && cc[d] >= 0 && cc[d] < nc[d] && u[d] >= 0 && u[d] <= p && w[d] >= 0 && w[d] <= p;
+          }
+          if (!ok) continue;
+          const double *cf = &h->coef[6 * ((size_t)cc[0] + (size_t)h->nx * (cc[1] + (size_t)h->ny * cc[2]))];
+          double Bv[3], Av[3];
+          for (int d = 0; d < 3; ++d) {
+            Bv[d] = B[u[d] * n1 + w[d]];
+            Av[d] = A[u[d] * n1 + w[d]];
+          }
+          v += cf[0] * Av[0] * Bv[1] * Bv[2] + cf[1] * Bv[0] * Av[1] * Bv[2] + cf[2] * Bv[0] * Bv[1] * Av[2] +
+               cf[3] * Bv[0] * Bv[1] * Bv[2];
+        }
+        M[(size_t)i * nrf + j] = v;
+      }
+    }
+  }, W);
+  if (bad >= 0) {
+    char msg[128];
+    std::snprintf(msg, sizeof msg, "%s breakdown in full vertex star %ld", ic ? "incomplete Cholesky" : "Cholesky", bad);
+    return fail(h->ctx, RZ_ERR_BREAKDOWN, msg);
+  }
+  if (!h->nrf) {
+    rz_status e;
+    int *doff = nullptr;
+    if ((e = upload(h, &doff, off))) return e;
+    if ((e = dalloc(h, &h->fzb64, nslot * nrf)) || (e = dalloc(h, &h->fzb32, nslot * nrf))) return e;
+    h->PF = h->P;
+    h->PF.nrows = nrf;
+    h->PF.off = doff;
+    h->nrf = nrf;
+  }
+  return upload_patch_inverse(h, W);
 }
 
 // vectors of the V-cycle and of the Krylov methods (ndofs each), dot-product
@@ -2756,6 +2924,10 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
   if (opts->patch_solver != RZ_PATCH_IC && opts->patch_solver != RZ_PATCH_CHOLESKY)
     return fail(ctx, RZ_ERR_ARG, "bad patch_solver");
   if (opts->norm != RZ_NORM_2 && opts->norm != RZ_NORM_NATURAL) return fail(ctx, RZ_ERR_ARG, "bad norm");
+  if (opts->decomposition != RZ_DECOMP_SC && opts->decomposition != RZ_DECOMP_FULL)
+    return fail(ctx, RZ_ERR_ARG, "bad decomposition");
+  if (opts->decomposition == RZ_DECOMP_FULL && (opts->space != RZ_GRAD || opts->aux == RZ_AUX_PAPER_DIAG))
+    return fail(ctx, RZ_ERR_ARG, "RZ_DECOMP_FULL: H(grad) with the separable auxiliary only");
   if (opts->patch_solver == RZ_PATCH_CHOLESKY && opts->space != RZ_GRAD)
     return fail(ctx, RZ_ERR_ARG, "RZ_PATCH_CHOLESKY: H(grad) vertex stars only");
   rz_problem *h = new rz_problem();
@@ -2879,7 +3051,11 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
   };
   if (h->pd && (e = upload_paper_diagonals(h))) return bail(e);
   if ((e = grad_patch_device(h))) return bail(e);
-  if (h->opts.patch_solver == RZ_PATCH_CHOLESKY && (e = setup_patch_cholesky(h))) return bail(e);
+  if (h->opts.decomposition == RZ_DECOMP_FULL) {
+    if ((e = setup_full_stars(h))) return bail(e);
+  } else if (h->opts.patch_solver == RZ_PATCH_CHOLESKY && (e = setup_patch_cholesky(h))) {
+    return bail(e);
+  }
   const int n1 = p + 1;
   if ((e = upload(h, &h->E64, h->t.E))) return bail(e);
   if (!h->quad) {  // A E and B E for the fused coarse correction and residual
@@ -3299,6 +3475,7 @@ rz_status refactor_patches(rz_problem *h, int *breakdown) {
   launch_patch_factor(h->L, h->P, h->coef64, h->B64, h->A64, h->lam64, pd_dev(h), h->f64, h->f32, h->status, s);
   HIPCALL(h, hipMemcpyAsync(breakdown, h->status, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCALL(h, hipStreamSynchronize(s));
+  if (!*breakdown && h->nrf) return setup_full_stars(h);
   if (!*breakdown && h->cw64) return setup_patch_cholesky(h);
   return RZ_OK;
 }

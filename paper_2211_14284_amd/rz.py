@@ -31,6 +31,7 @@ EXPORT_EDGE_PATCH, EXPORT_STATS, EXPORT_PAPER_DIAG, EXPORT_AUTOTUNE, EXPORT_GRAP
 AUX_CELL_AVG, AUX_PAPER_DIAG = 0, 1
 PATCH_IC, PATCH_CHOLESKY = 0, 1
 NORM_2, NORM_NATURAL = 0, 1
+DECOMP_SC, DECOMP_FULL = 0, 1
 KERNELS = ("apply", "condense", "patch", "expand", "transfer", "coarse", "krylov")
 STATUS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_OOM", -3: "RZ_ERR_BREAKDOWN",
           -4: "RZ_ERR_NOT_CONVERGED", -5: "RZ_ERR_HIP", -6: "RZ_ERR_SINGULAR", -7: "RZ_ERR_NODEVICE"}
@@ -57,7 +58,7 @@ class Opts(ctypes.Structure):
                 ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double), ("omega", ctypes.c_double),
                 ("lanczos_seed", ctypes.c_uint64), ("hdiv_eps", ctypes.c_double), ("aux", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("patch_solver", ctypes.c_int32),
-                ("norm", ctypes.c_int32)]
+                ("decomposition", ctypes.c_int32), ("norm", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -180,3 +180,64 @@ def test_natural_norm_stopping_rule(rz, ctx, patch_solver):
     assert inat.iters_natural == i2.iters_natural >= 1
     assert inat.iters == inat.iters_natural + 1
     assert 0 < inat.rel_res < 1e-5
+
+
+FULL = [((2, 2, 2), 2, 1), ((3, 2, 2), 3, 1), ((2, 2, 3), 3, 0), ((2, 2, 2), 4, 1), ((2, 2, 2), 4, 0)]
+
+
+@pytest.mark.parametrize("n,p,chol", FULL)
+def test_full_star_relax_parity(rz, ctx, n, p, chol):
+    """RZ_DECOMP_FULL (PAFW without static condensation) against the oracle's
+    PAFWRelaxGrad, exact (chol = 1) and incomplete (chol = 0) star factors."""
+    print(f"full stars n={n} p={p} chol={chol}", flush=True)
+    al, be = coefs(n, 2)
+    lat = Lattice(Mesh(*n), "grad", p)
+    co = auxop.cartesian_coefficient_array(lat, al, be)
+    R = schwarz.PAFWRelaxGrad(lat, auxop.separable_operator(lat, co), factor="chol" if chol else "ic")
+    pb = rz.Problem(ctx, n, p, al, be, omega=0.3, decomposition=rz.DECOMP_FULL,
+                    patch_solver=rz.PATCH_CHOLESKY if chol else rz.PATCH_IC)
+    try:
+        r = np.where(lat.dirichlet_mask(), 0.0, synth.uniform_pm1(13, lat.ndofs))
+        z_ref = R.apply(r)
+        z = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
+        pb.relax(T(r), z)
+        assert rel(H(z), z_ref) < 1e-11
+        z32 = torch.empty(pb.ndofs, dtype=torch.float32, device="cuda:0")
+        pb.relax(T(r, torch.float32), z32, rz.F32)
+        assert rel(H(z32), z_ref) < 1e-4
+    finally:
+        pb.close()
+
+
+def test_full_star_solve(rz, ctx):
+    n, p = (3, 3, 3), 3
+    al, be = coefs(n, 4)
+    m = Mesh(*n)
+    lat, latc = Lattice(m, "grad", p), Lattice(m, "grad", 1)
+    A = asm.with_dirichlet(lat, asm.cartesian_operator(lat, al, be))
+    co = auxop.cartesian_coefficient_array(lat, al, be)
+    R = schwarz.PAFWRelaxGrad(lat, auxop.separable_operator(lat, co), factor="chol")
+    mask = lat.dirichlet_mask()
+    v0 = np.where(mask, 0.0, synth.uniform_pm1(99, lat.ndofs))
+    om = pmg.omega_from_lambda(pmg.lanczos_lambda_max(A, lambda r: np.where(mask, 0.0, R.apply(r)), v0))
+    A0 = asm.with_dirichlet(latc, asm.cartesian_operator(latc, al, be))
+    b = np.where(mask, 0.0, synth.rhs_values(lat.ndofs, 1))
+    _, it_ref, _ = pmg.pcg(A, b, pmg.VCycle(lat, A, R, pmg.prolongation(lat, latc), pmg.CoarseSolver(latc, A0), om))
+    pb = rz.Problem(ctx, n, p, al, be, decomposition=rz.DECOMP_FULL, patch_solver=rz.PATCH_CHOLESKY)
+    try:
+        assert abs(pb.omega() - om) < 1e-6 * om
+        x = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
+        info = pb.solve(T(b), x)
+        xg = H(x)
+        assert info.rel_res <= 1e-8
+        assert np.linalg.norm(b - A @ xg) <= 1e-8 * np.linalg.norm(b)
+        assert abs(info.iters - it_ref) <= 1, (info.iters, it_ref)
+    finally:
+        pb.close()
+
+
+def test_full_star_rejections(rz, ctx):
+    with pytest.raises(rz.RzError):
+        rz.Problem(ctx, 2, 3, 1.0, 1.0, space="div", decomposition=rz.DECOMP_FULL)
+    with pytest.raises(rz.RzError):   # (2p-1)^3 = 4913 rows per star: past the host-work limit
+        rz.Problem(ctx, 4, 9, 1.0, 1.0, decomposition=rz.DECOMP_FULL)
