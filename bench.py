@@ -257,6 +257,9 @@ def bench_c1(torch, rz, ctx, steps=20):
     return out, sol
 
 
+# Tables hcurl-iter and hdiv-iter, Cartesian meshes, SC-PH column as the paper prints it
+PAPER_SCPH_ITER = {("curl", 3, 0): 14, ("curl", 3, 1): 16, ("curl", 7, 0): 15, ("curl", 7, 1): 16,
+                   ("div", 3, 0): 11, ("div", 3, 1): 13, ("div", 7, 0): 13, ("div", 7, 1): 13}
 # Table hgrad-iter, Cartesian meshes, as the paper prints them: (chol, SC-chol, ICC, SC-ICC)
 PAPER_HGRAD_ITER = {(3, 0): (14, 11, 14, 11), (3, 1): (15, 11, 15, 11), (7, 0): (12, 9, 13, 10),
                     (7, 1): (12, 9, 13, 10)}
@@ -270,7 +273,8 @@ def bench_table_hgrad_iter(torch, rz, ctx):
     with static condensation, each with exact Cholesky and with IC on the pattern.  The paper's coarse Cartesian mesh has six cells in the vertical (the
     horizontal layout is in a figure): l = 0 is taken as 6^3 cells, l = 1 as 12^3."""
     import synth
-    out = {"workload": "Table hgrad-iter, Cartesian: alpha=1, beta=1e-8, b = (M+K) w, natural-norm criterion",
+    out = {"workload": "Tables hgrad-iter (four columns), hcurl-iter and hdiv-iter (SC-PH), Cartesian: alpha=1, "
+                       "beta=1e-8, b = (M+K) w, natural-norm criterion",
            "rows": []}
     for p, l in ((3, 0), (3, 1), (7, 0), (7, 1)):
         n = 6 * 2 ** l
@@ -295,6 +299,24 @@ def bench_table_hgrad_iter(torch, rz, ctx):
         row["paper_chol_scchol_icc_scicc"] = list(PAPER_HGRAD_ITER[(p, l)])
         out["rows"].append(row)
         log(f"table hgrad-iter p={p} l={l}: {row}")
+    # H(curl) and H(div): the SC-PH column (the library's relaxation for these spaces)
+    out["sc_ph"] = []
+    for space in ("curl", "div"):
+        for p, l in ((3, 0), (3, 1), (7, 0), (7, 1)):
+            n = 6 * 2 ** l
+            riesz = rz.Problem(ctx, n, p, 1.0, 1.0, space=space, omega=0.3)
+            w = torch.as_tensor(synth.rhs_values(riesz.ndofs, 7), device="cuda:0")
+            b = torch.empty_like(w)
+            riesz.apply(w, b)
+            riesz.close()
+            pb = rz.Problem(ctx, n, p, 1.0, 1e-8, space=space, norm=rz.NORM_NATURAL)
+            x = torch.empty_like(b)
+            info = pb.solve(b, x)
+            pb.close()
+            row = {"space": space, "p": p, "l": l, "cells": n ** 3, "iters_natural": info.iters_natural,
+                   "rel_res_2norm_at_exit": info.rel_res, "paper_sc_ph": PAPER_SCPH_ITER[(space, p, l)]}
+            out["sc_ph"].append(row)
+            log(f"table {space}-iter SC-PH p={p} l={l}: {row}")
     return out
 
 
