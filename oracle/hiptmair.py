@@ -287,3 +287,61 @@ class SCRelaxPH:
         z[c.G] = zG
         z[c.mask] = r[c.mask]
         return z
+
+
+# ----------------------------------------------------------------------------------
+# PAFW without static condensation for H(curl) / H(div) (Sec. 4.3, eq. pafw): the
+# vertex stars of the k-forms, every DoF whose support lies in the cells around a
+# vertex, with exact patch solves (the PAFW column of Tables hcurl-iter / hdiv-iter).
+# ----------------------------------------------------------------------------------
+def vertex_star_patches_vec(lat: Lattice):
+    """List of (vertex_id, dof array, ascending) of the non-empty vertex stars: a free
+    DoF belongs to the star of vertex v when every cell holding it (along each axis:
+    the cell of a DP coordinate, the one or two existing cells of a continuous
+    coordinate, two on an interior vertex plane) is among the cells v_a - 1, v_a."""
+    mesh, p = lat.mesh, lat.p
+    nc = (mesh.nx, mesh.ny, mesh.nz)
+    co = lat.coords()
+    free = ~lat.dirichlet_mask()
+    comp = co[:, 0]
+    lo = np.zeros((lat.ndofs, 3), dtype=np.int64)
+    hi = np.zeros((lat.ndofs, 3), dtype=np.int64)
+    for a in range(3):
+        C = co[:, 1 + a]
+        cont = np.array([lat.kinds[m][a] == "P" for m in range(len(lat.kinds))])[comp]
+        c = C // p
+        on = cont & (C % p == 0)
+        lo[:, a] = np.where(on, np.maximum(c - 1, 0), np.minimum(c, nc[a] - 1))
+        hi[:, a] = np.where(on, np.minimum(c, nc[a] - 1), np.minimum(c, nc[a] - 1))
+    out = []
+    nvx, nvy, nvz = nc[0] + 1, nc[1] + 1, nc[2] + 1
+    for vz in range(nvz):
+        for vy in range(nvy):
+            for vx in range(nvx):
+                v = np.array([vx, vy, vz])
+                inside = np.all((lo >= v - 1) & (hi <= v), axis=1) & free
+                sel = np.where(inside)[0]
+                if sel.size:
+                    out.append((vx + nvx * (vy + nvy * vz), sel))
+    return out
+
+
+class PAFWRelaxVec:
+    """z = M^{-1} r for PAFW on H(curl) / H(div) without static condensation:
+    z = sum_v R_v^T P_v^{-1} R_v r over the vertex stars (exact Cholesky of each
+    P_v = R_v P R_v^T); Dirichlet rows copy r."""
+
+    def __init__(self, lat: Lattice, P):
+        P = sp.csr_matrix(P)
+        self.dmask = lat.dirichlet_mask()
+        self.patches = vertex_star_patches_vec(lat)
+        self.factors = [np.linalg.cholesky(P[d][:, d].toarray()) for _, d in self.patches]
+
+    def apply(self, r):
+        r = np.asarray(r, dtype=np.float64)
+        z = np.zeros_like(r)
+        for (vid, dofs), L in zip(self.patches, self.factors):
+            y = scipy.linalg.solve_triangular(L, r[dofs], lower=True)
+            z[dofs] += scipy.linalg.solve_triangular(L.T, y, lower=False)
+        z[self.dmask] = r[self.dmask]
+        return z

@@ -215,3 +215,49 @@ def test_potential_term_matters():
     _, err_full = _solve("curl", 3, 3, 1.0, 1e-8)
     _, err_drop = _solve("curl", 3, 3, 1.0, 1e-8, potential=False)
     assert err_full < 1e-4 < 1e-3 < err_drop
+
+
+def test_pafw_vec_star_membership_brute_force():
+    # a free DoF is in the star of v iff every cell whose local DoFs include it is one
+    # of the cells around v (checked from the cell-to-DoF map)
+    from oracle import hiptmair as hp2
+    for space in ("curl", "div"):
+        m = Mesh(3, 2, 2, dirichlet=0x15)
+        lat = Lattice(m, space, 2)
+        cd = lat.cell_dofs()
+        nx, ny, nz = m.nx, m.ny, m.nz
+        support = [set() for _ in range(lat.ndofs)]
+        for c in range(m.ncells):
+            for g in cd[c]:
+                support[g].add(c)
+        free = ~lat.dirichlet_mask()
+        got = dict(hp2.vertex_star_patches_vec(lat))
+        for vz in range(nz + 1):
+            for vy in range(ny + 1):
+                for vx in range(nx + 1):
+                    cells = {cx + nx * (cy + ny * cz) for cx in (vx - 1, vx) for cy in (vy - 1, vy)
+                             for cz in (vz - 1, vz) if 0 <= cx < nx and 0 <= cy < ny and 0 <= cz < nz}
+                    want = [g for g in range(lat.ndofs) if free[g] and support[g] <= cells]
+                    vid = vx + (nx + 1) * (vy + (ny + 1) * vz)
+                    assert list(got.get(vid, [])) == want, (space, vid)
+
+
+@pytest.mark.parametrize("space", ["curl", "div"])
+def test_pafw_vec_single_star_exact_and_spd(space):
+    from oracle import hiptmair as hp2
+    lat = Lattice(Mesh(2, 2, 2), space, 2)
+    A = asm.with_dirichlet(lat, asm.cartesian_operator(lat, 1.3, 0.4))
+    R = hp2.PAFWRelaxVec(lat, A)
+    free = np.where(~lat.dirichlet_mask())[0]
+    Mi = np.zeros((free.size, free.size))
+    for k, g in enumerate(free):
+        e = np.zeros(lat.ndofs)
+        e[g] = 1.0
+        Mi[:, k] = R.apply(e)[free]
+    assert np.abs(Mi - Mi.T).max() < 1e-12 * np.abs(Mi).max()
+    assert np.linalg.eigvalsh(0.5 * (Mi + Mi.T)).min() > 0
+    keep = [i for i, (v, d) in enumerate(R.patches) if v == 13]
+    R.patches, R.factors = [R.patches[keep[0]]], [R.factors[keep[0]]]
+    b = np.where(lat.dirichlet_mask(), 0.0, np.random.default_rng(6).standard_normal(lat.ndofs))
+    x = spla.spsolve(A.tocsc(), b)
+    assert np.abs(R.apply(b) - x).max() < 1e-11 * np.abs(x).max()
