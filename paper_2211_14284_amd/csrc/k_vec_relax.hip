@@ -340,6 +340,41 @@ __global__ void k_list_copy(int n, const int *__restrict__ list, const T *__rest
   z[g] = r ? r[g] : T(0);
 }
 
+// Dense patch solves z_v = W_v^T (W_v b_v), W_v = L_v^{-1} packed by rows, on patches
+// given by index lists (nr entries per patch, -1 for the padding rows, whose W rows
+// are those of the identity): one block per patch; y = W b with one wavefront per
+// row, z = W^T y with one thread per column reading the rows in order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dense_patch_solve(int nr, const int *__restrict__ idx,
+                                                            const T *__restrict__ W, const T *__restrict__ r,
+                                                            T *__restrict__ zb) {
+  extern __shared__ __align__(16) unsigned char dps_smem[];
+  double *sb = reinterpret_cast<double *>(dps_smem), *sy = sb + nr;
+  const long pt = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = tid; i < nr; i += blockDim.x) {
+    const int g = idx[pt * nr + i];
+    sb[i] = g >= 0 ? (double)r[g] : 0.0;
+  }
+  __syncthreads();
+  const T *Ws = W + pt * ((long)nr * (nr + 1) / 2);
+  for (int i = wv; i < nr; i += blockDim.x >> 6) {
+    const T *row = Ws + (long)i * (i + 1) / 2;
+    double acc = 0.0;
+    for (int j = lane; j <= i; j += 64) acc += (double)row[j] * sb[j];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) sy[i] = acc;
+  }
+  __syncthreads();
+  for (int j0 = 0; j0 < nr; j0 += blockDim.x) {
+    const int j = j0 + tid;
+    double acc = 0.0;
+    for (int i = j0; i < nr; ++i)
+      if (j <= i) acc += (double)Ws[(long)i * (i + 1) / 2 + j] * sy[i];
+    if (j < nr) zb[pt * nr + j] = (T)acc;
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -445,5 +480,15 @@ template void launch_gemv<double>(int, const double *, const double *, double *,
 template void launch_gemv<float>(int, const float *, const double *, double *, hipStream_t);
 template void launch_list_copy<double>(int, const int *, const double *, double *, hipStream_t);
 template void launch_list_copy<float>(int, const int *, const float *, float *, hipStream_t);
+
+template <typename T>
+void launch_dense_patch_solve(int npatch, int nr, const int *idx, const T *W, const T *r, T *zb, hipStream_t s) {
+  if (npatch <= 0) return;
+  k_dense_patch_solve<T><<<(unsigned)npatch, 256, 2 * sizeof(double) * nr, s>>>(nr, idx, W, r, zb);
+}
+template void launch_dense_patch_solve<double>(int, int, const int *, const double *, const double *, double *,
+                                               hipStream_t);
+template void launch_dense_patch_solve<float>(int, int, const int *, const float *, const float *, float *,
+                                              hipStream_t);
 
 }  // namespace rz

@@ -274,6 +274,10 @@ template <typename T>
 void launch_patch_chol_solve(const LatDev &L, const PatchDev &P, const T *W, const T *rt, T *zb, hipStream_t s);
 // Sum of the full vertex stars' solutions at every lattice point (Dirichlet points take
 // r), times scale, to z, or with acc: acc += w times that
+// Dense patch solves z_v = W_v^T (W_v b_v) on npatch patches given by index lists (nr
+// entries each, -1 padding), W_v packed by rows
+template <typename T>
+void launch_dense_patch_solve(int npatch, int nr, const int *idx, const T *W, const T *r, T *zb, hipStream_t s);
 template <typename T>
 void launch_full_star_sum(const LatDev &L, int nrf, const T *zb, const T *r, T *z, T scale, T w, T *acc,
                           hipStream_t s);

@@ -219,6 +219,10 @@ struct rz_problem {
   // and the per-slot solutions
   int nrf = 0;
   PatchDev PF{};
+  // H(curl)/H(div) vertex stars (opts.decomposition): patches, their index lists
+  // (nrf entries each), and per free DoF the positions of its star solutions
+  int nvs = 0, nvfree = 0;
+  int *vs_idx = nullptr, *vs_rows = nullptr, *vs_ptr = nullptr, *vs_pos = nullptr;
   double *fzb64 = nullptr;
   float *fzb32 = nullptr;
   std::vector<hipGraph_t> *cap = nullptr;  // capture in progress: the closed segments
@@ -463,9 +467,22 @@ VecRelaxPtrs<float> vec_ptrs32(rz_problem *h) {
           q ? q->A32 : nullptr, q ? q->lam32 : nullptr, q ? q->zb32 : nullptr};
 }
 
+double *full_zb(rz_problem *h, double *);
+float *full_zb(rz_problem *h, float *);
+const double *chol_w(rz_problem *h, const double *);
+const float *chol_w(rz_problem *h, const float *);
+
 template <typename T>
 rz_status relax_vec(rz_problem *h, const VecRelaxPtrs<T> &X, const T *r, T *z) {
   hipStream_t s = h->ctx->stream;
+  if (h->nvs) {  // vertex stars without static condensation (PAFW)
+    Timed t(h, RZ_K_PATCH);
+    T *zb = full_zb(h, (T *)nullptr);
+    launch_dense_patch_solve<T>(h->nvs, h->nrf, h->vs_idx, chol_w(h, (const T *)nullptr), r, zb, s);
+    launch_list_gather<T>(h->nvfree, h->vs_rows, h->vs_ptr, h->vs_pos, zb, (const T *)nullptr, z, T(1), s);
+    launch_list_copy<T>(h->nDir, h->dlist, r, z, s);
+    return RZ_OK;
+  }
   {
     Timed t(h, RZ_K_CONDENSE);
     launch_vc_condense<T>(h->V, *X.vc, r, z, X.veb, s);
@@ -1825,6 +1842,133 @@ rz_status setup_full_stars(rz_problem *h) {
   return upload_patch_inverse(h, W);
 }
 
+// Vertex stars of H(curl) / H(div) without static condensation (rz_opts.decomposition
+// = RZ_DECOMP_FULL, PAFW, eq. pafw): a free DoF belongs to the star of vertex v when
+// every cell holding it is one of the cells around v.  Per non-empty star on host
+// threads: its DoFs ascending, P_v assembled dense from the cells' six weighted basis
+// matrices, exact Cholesky and W = L^{-1}; the stars padded to one size with identity
+// rows; per free DoF the positions of its star solutions, in ascending star order.
+rz_status setup_vertex_stars_vec(rz_problem *h) {
+  const int p = h->p, space = h->space == RZ_CURL ? 1 : 2;
+  VecLocal VL;
+  vec_local_layout(space, p, VL);
+  SpRows basis[6];
+  vec_basis_matrices(h->t, VL, basis);
+  const VecDev &V = h->V;
+  const int nc[3] = {h->nx, h->ny, h->nz};
+  const int nvx = nc[0] + 1, nvy = nc[1] + 1, nvz = nc[2] + 1;
+  const size_t nvert = (size_t)nvx * nvy * nvz;
+  std::vector<char> dirm((size_t)h->ndofs, 0);
+  {
+    std::vector<int> dl(h->nDir);
+    HIPCALL(h, hipMemcpy(dl.data(), h->dlist, sizeof(int) * dl.size(), hipMemcpyDeviceToHost));
+    for (int g : dl) dirm[g] = 1;
+  }
+  auto global = [&](int cx, int cy, int cz, int l, int &m, int C[3]) {
+    m = VL.comp[l];
+    const int cc[3] = {cx, cy, cz};
+    for (int a = 0; a < 3; ++a) C[a] = cc[a] * p + VL.crd[3 * l + a];
+    return V.off[m] + C[0] + (int64_t)V.ext[m][0] * (C[1] + (int64_t)V.ext[m][1] * C[2]);
+  };
+  // star membership: along every axis the cells holding the DoF lie in {v - 1, v}
+  auto in_star = [&](int m, const int C[3], const int v[3]) {
+    for (int a = 0; a < 3; ++a) {
+      const int c = C[a] / p;
+      int lo = std::min(c, nc[a] - 1), hi = lo;
+      if (vec_is_P(space, m, a) && C[a] % p == 0) {
+        lo = std::max(c - 1, 0);
+        hi = std::min(c, nc[a] - 1);
+      }
+      if (lo < v[a] - 1 || hi > v[a]) return false;
+    }
+    return true;
+  };
+  std::vector<std::vector<int64_t>> stars(nvert);
+  for (size_t vid = 0; vid < nvert; ++vid) {
+    const int v[3] = {(int)(vid % nvx), (int)((vid / nvx) % nvy), (int)(vid / ((size_t)nvx * nvy))};
+    std::vector<int64_t> &S = stars[vid];
+    for (int cz = v[2] - 1; cz <= v[2]; ++cz)
+      for (int cy = v[1] - 1; cy <= v[1]; ++cy)
+        for (int cx = v[0] - 1; cx <= v[0]; ++cx) {
+          if (cx < 0 || cy < 0 || cz < 0 || cx >= nc[0] || cy >= nc[1] || cz >= nc[2]) continue;
+          for (int l = 0; l < VL.nloc; ++l) {
+            int m, C[3];
+            const int64_t g = global(cx, cy, cz, l, m, C);
+            if (!dirm[g] && in_star(m, C, v)) S.push_back(g);
+          }
+        }
+    std::sort(S.begin(), S.end());
+    S.erase(std::unique(S.begin(), S.end()), S.end());
+  }
+  std::vector<size_t> live;
+  int nr = 0;
+  for (size_t vid = 0; vid < nvert; ++vid)
+    if (!stars[vid].empty()) {
+      live.push_back(vid);
+      nr = std::max(nr, (int)stars[vid].size());
+    }
+  const size_t np = live.size(), tri = (size_t)nr * (nr + 1) / 2;
+  if ((double)np * tri * 12.0 > 16.0 * (1ull << 30) || (double)np * nr * nr * (double)nr > 5e11)
+    return fail(h->ctx, RZ_ERR_ARG, "RZ_DECOMP_FULL: the dense vertex-star factors are for small meshes and degrees");
+  std::vector<double> W;
+  const long bad = factor_slots(np, nr, nullptr, [&](size_t k, std::vector<double> &M) {
+    const size_t vid = live[k];
+    const int v[3] = {(int)(vid % nvx), (int)((vid / nvx) % nvy), (int)(vid / ((size_t)nvx * nvy))};
+    const std::vector<int64_t> &S = stars[vid];
+    const int ns = (int)S.size();
+    for (int i = ns; i < nr; ++i) M[(size_t)i * nr + i] = 1.0;
+    std::vector<int> pos(VL.nloc);
+    for (int cz = v[2] - 1; cz <= v[2]; ++cz)
+      for (int cy = v[1] - 1; cy <= v[1]; ++cy)
+        for (int cx = v[0] - 1; cx <= v[0]; ++cx) {
+          if (cx < 0 || cy < 0 || cz < 0 || cx >= nc[0] || cy >= nc[1] || cz >= nc[2]) continue;
+          for (int l = 0; l < VL.nloc; ++l) {
+            int m, C[3];
+            const int64_t g = global(cx, cy, cz, l, m, C);
+            const auto it = std::lower_bound(S.begin(), S.end(), g);
+            pos[l] = (it != S.end() && *it == g) ? (int)(it - S.begin()) : -1;
+          }
+          const double *w = &h->coef[6 * ((size_t)cx + (size_t)nc[0] * (cy + (size_t)nc[1] * cz))];
+          for (int kb = 0; kb < 6; ++kb)
+            for (int l1 = 0; l1 < VL.nloc; ++l1) {
+              if (pos[l1] < 0) continue;
+              for (const auto &e : basis[kb][l1])
+                if (pos[e.first] >= 0) M[(size_t)pos[l1] * nr + pos[e.first]] += w[kb] * e.second;
+            }
+        }
+  }, W);
+  if (bad >= 0) {
+    char msg[128];
+    std::snprintf(msg, sizeof msg, "Cholesky breakdown in vertex star %ld", bad);
+    return fail(h->ctx, RZ_ERR_BREAKDOWN, msg);
+  }
+  // index lists and, per free DoF, its star positions (ascending star order)
+  std::vector<int> idx(np * nr, -1);
+  std::vector<std::vector<int>> where((size_t)h->ndofs);
+  for (size_t k = 0; k < np; ++k) {
+    const std::vector<int64_t> &S = stars[live[k]];
+    for (size_t i = 0; i < S.size(); ++i) {
+      idx[k * nr + i] = (int)S[i];
+      where[S[i]].push_back((int)(k * nr + i));
+    }
+  }
+  std::vector<int> rows, ptr{0}, pos;
+  for (int64_t g = 0; g < h->ndofs; ++g)
+    if (!where[g].empty()) {
+      rows.push_back((int)g);
+      pos.insert(pos.end(), where[g].begin(), where[g].end());
+      ptr.push_back((int)pos.size());
+    }
+  rz_status e;
+  if ((e = upload(h, &h->vs_idx, idx)) || (e = upload(h, &h->vs_rows, rows)) || (e = upload(h, &h->vs_ptr, ptr)) ||
+      (e = upload(h, &h->vs_pos, pos)) || (e = dalloc(h, &h->fzb64, np * nr)) || (e = dalloc(h, &h->fzb32, np * nr)))
+    return e;
+  h->nvs = (int)np;
+  h->nvfree = (int)rows.size();
+  h->nrf = nr;
+  return upload_patch_inverse(h, W);
+}
+
 // vectors of the V-cycle and of the Krylov methods (ndofs each), dot-product
 // scratch and the pinned host copy of the scalars
 rz_status alloc_krylov(rz_problem *h) {
@@ -2497,6 +2641,7 @@ rz_status setup_vector(rz_problem *h, const rz_coef *cf, rz_problem **out) {
   if (hipMemsetAsync(h->status, 0, sizeof(int), s) != hipSuccess) return bail(fail(ctx, RZ_ERR_HIP, "memset"));
   // the relaxation, coarse problem and transfers of the solver
   if ((e = setup_vec_relax(h, alc, bec, hsc)) || (e = alloc_krylov(h))) return bail(e);
+  if (h->opts.decomposition == RZ_DECOMP_FULL && (e = setup_vertex_stars_vec(h))) return bail(e);
   if (h->opts.omega > 0) {
     h->omega = h->opts.omega;
   } else {
@@ -2926,10 +3071,12 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
   if (opts->norm != RZ_NORM_2 && opts->norm != RZ_NORM_NATURAL) return fail(ctx, RZ_ERR_ARG, "bad norm");
   if (opts->decomposition != RZ_DECOMP_SC && opts->decomposition != RZ_DECOMP_FULL)
     return fail(ctx, RZ_ERR_ARG, "bad decomposition");
-  if (opts->decomposition == RZ_DECOMP_FULL && (opts->space != RZ_GRAD || opts->aux == RZ_AUX_PAPER_DIAG))
+  if (opts->decomposition == RZ_DECOMP_FULL && opts->space == RZ_GRAD && opts->aux == RZ_AUX_PAPER_DIAG)
     return fail(ctx, RZ_ERR_ARG, "RZ_DECOMP_FULL: H(grad) with the separable auxiliary only");
-  if (opts->patch_solver == RZ_PATCH_CHOLESKY && opts->space != RZ_GRAD)
-    return fail(ctx, RZ_ERR_ARG, "RZ_PATCH_CHOLESKY: H(grad) vertex stars only");
+  if (opts->decomposition == RZ_DECOMP_FULL && opts->space != RZ_GRAD && opts->patch_solver != RZ_PATCH_CHOLESKY)
+    return fail(ctx, RZ_ERR_ARG, "RZ_DECOMP_FULL on H(curl)/H(div): exact vertex-star solves (RZ_PATCH_CHOLESKY) only");
+  if (opts->patch_solver == RZ_PATCH_CHOLESKY && opts->space != RZ_GRAD && opts->decomposition != RZ_DECOMP_FULL)
+    return fail(ctx, RZ_ERR_ARG, "RZ_PATCH_CHOLESKY: H(grad) vertex stars, or the H(curl)/H(div) full vertex stars");
   rz_problem *h = new rz_problem();
   h->ctx = ctx;
   h->opts = *opts;

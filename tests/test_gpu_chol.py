@@ -241,3 +241,52 @@ def test_full_star_rejections(rz, ctx):
         rz.Problem(ctx, 2, 3, 1.0, 1.0, space="div", decomposition=rz.DECOMP_FULL)
     with pytest.raises(rz.RzError):   # (2p-1)^3 = 4913 rows per star: past the host-work limit
         rz.Problem(ctx, 4, 9, 1.0, 1.0, decomposition=rz.DECOMP_FULL)
+
+
+VEC_FULL = [("curl", (2, 2, 2), 1), ("curl", (3, 2, 2), 2), ("curl", (2, 2, 2), 3), ("div", (2, 2, 3), 2),
+            ("div", (2, 2, 2), 3)]
+
+
+@pytest.mark.parametrize("space,n,p", VEC_FULL)
+def test_vertex_stars_vec_relax_parity(rz, ctx, space, n, p):
+    """H(curl)/H(div) PAFW without static condensation (RZ_DECOMP_FULL, exact vertex
+    stars) against the oracle's PAFWRelaxVec."""
+    from oracle import hiptmair as hp
+    print(f"vertex stars {space} n={n} p={p}", flush=True)
+    nc = int(np.prod(n))
+    al = synth.cell_coefficients(nc, 3, 0.5, 2.0)
+    be = synth.cell_coefficients(nc, 4, 0.5, 2.0)
+    lat = Lattice(Mesh(*n), space, p)
+    A = asm.with_dirichlet(lat, asm.cartesian_operator(lat, al, be))
+    R = hp.PAFWRelaxVec(lat, A)
+    pb = rz.Problem(ctx, n, p, al, be, space=space, omega=0.3, decomposition=rz.DECOMP_FULL,
+                    patch_solver=rz.PATCH_CHOLESKY)
+    try:
+        r = np.where(lat.dirichlet_mask(), 0.0, synth.uniform_pm1(17, lat.ndofs))
+        z_ref = R.apply(r)
+        z = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
+        pb.relax(T(r), z)
+        assert rel(H(z), z_ref) < 1e-11
+        z32 = torch.empty(pb.ndofs, dtype=torch.float32, device="cuda:0")
+        pb.relax(T(r, torch.float32), z32, rz.F32)
+        assert rel(H(z32), z_ref) < 1e-4
+    finally:
+        pb.close()
+
+
+@pytest.mark.parametrize("space", ["curl", "div"])
+def test_vertex_stars_vec_solve(rz, ctx, space):
+    n, p = (3, 3, 3), 2
+    pb = rz.Problem(ctx, n, p, 1.0, 1.0, space=space, decomposition=rz.DECOMP_FULL, patch_solver=rz.PATCH_CHOLESKY)
+    try:
+        lat = Lattice(Mesh(*n), space, p)
+        A = asm.with_dirichlet(lat, asm.cartesian_operator(lat, 1.0, 1.0))
+        b = np.where(lat.dirichlet_mask(), 0.0, synth.rhs_values(lat.ndofs, 2))
+        x = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
+        info = pb.solve(T(b), x)
+        xg = H(x)
+        assert info.rel_res <= 1e-8
+        assert np.linalg.norm(b - A @ xg) <= 1e-8 * np.linalg.norm(b)
+        print(f"  {space}: {info.iters} iterations", flush=True)
+    finally:
+        pb.close()
