@@ -81,6 +81,71 @@ class CoarseSolver:
         return out
 
 
+def interp_1d(nf, lo_f, hi_f, lo_c, hi_c):
+    """Linear interpolation on one axis from the coarse vertices c (at fine vertex 2c)
+    to the fine vertices f: 1 where f = 2c, 1/2 where |f - 2c| = 1; rows the free
+    fine range lo_f..hi_f, columns the free coarse range lo_c..hi_c."""
+    rows, cols, vals = [], [], []
+    for f in range(lo_f, hi_f + 1):
+        for c in range(lo_c, hi_c + 1):
+            d = abs(f - 2 * c)
+            if d <= 1:
+                rows.append(f - lo_f)
+                cols.append(c - lo_c)
+                vals.append(1.0 if d == 0 else 0.5)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(hi_f - lo_f + 1, hi_c - lo_c + 1))
+
+
+class HMGCoarse:
+    """Geometric h-multigrid on the p = 1 space as the coarse solver (the h-hierarchy
+    below p = 1 of Sec. 5.1): the free Q_1 DoFs form a box; while every cell count is
+    even and the level holds more than min_free DoFs, the next level is the mesh with
+    half the cells per axis, with trilinear interpolation P (the Kronecker product of
+    the 1-D linear interpolations on the free coordinates) and the Galerkin operator
+    P^T A P; the coarsest level is solved exactly.  solve(r) is one V(1,1) cycle from a
+    zero guess with damped point Jacobi (weight omega_j) before and after the coarse
+    correction (a symmetric positive definite approximation of A_0^{-1})."""
+
+    def __init__(self, lat_c: Lattice, A0, omega_j=2.0 / 3.0, min_free=1000):
+        mesh = lat_c.mesh
+        self.omega_j = omega_j
+        mask = lat_c.dirichlet_mask()
+        self.free = np.where(~mask)[0]
+        self.n = lat_c.ndofs
+        n = [mesh.nx, mesh.ny, mesh.nz]
+        d = mesh.dirichlet
+        lo = [1 if d & (1 << (2 * a)) else 0 for a in range(3)]
+        hi = [n[a] - 1 if d & (1 << (2 * a + 1)) else n[a] for a in range(3)]
+        A = sp.csr_matrix(A0)[self.free][:, self.free]
+        self.A, self.P, self.dinv = [A], [], [1.0 / A.diagonal()]
+        while all(k % 2 == 0 for k in n) and A.shape[0] > min_free:
+            nc = [k // 2 for k in n]
+            loc = [1 if d & (1 << (2 * a)) else 0 for a in range(3)]
+            hic = [nc[a] - 1 if d & (1 << (2 * a + 1)) else nc[a] for a in range(3)]
+            Ps = [interp_1d(n[a] + 1, lo[a], hi[a], loc[a], hic[a]) for a in range(3)]
+            P = sp.csr_matrix(sp.kron(Ps[2], sp.kron(Ps[1], Ps[0])))
+            A = sp.csr_matrix(P.T @ A @ P)
+            self.P.append(P)
+            self.A.append(A)
+            self.dinv.append(1.0 / A.diagonal())
+            n, lo, hi = nc, loc, hic
+        self.chol = scipy.linalg.cho_factor(self.A[-1].toarray(), lower=True)
+
+    def cycle(self, level, b):
+        if level == len(self.A) - 1:
+            return scipy.linalg.cho_solve(self.chol, b)
+        A, w, dinv = self.A[level], self.omega_j, self.dinv[level]
+        x = w * dinv * b
+        xc = self.cycle(level + 1, self.P[level].T @ (b - A @ x))
+        x = x + self.P[level] @ xc
+        return x + w * dinv * (b - A @ x)
+
+    def solve(self, r):
+        out = np.zeros(self.n)
+        out[self.free] = self.cycle(0, r[self.free])
+        return out
+
+
 class VCycle:
     """Hybrid V(1,1): z = w M r; z += P A0^{-1} P^T (r - A z); z += w M (r - A z)."""
 
