@@ -239,6 +239,46 @@ def bench_multi_rhs(torch, rz, pb, nrhs, patch_ms_1, solve_ms_1, iters_1, reps=3
             "kernel_ms_per_call": {k: round(v[0], 3) for k, v in kt.items()}}
 
 
+def bench_hmg(torch, rz, ctx, steps=3, warmup=1):
+    """The p = 1 solve of the p-multigrid cycle by geometric h-multigrid (one V(1,1)
+    cycle, point Jacobi, coarsest level dense) against the exact solve: iterations,
+    time per PCG solve and the coarse solver's share, on the C2 workload (Q_7 on 32^3,
+    log-uniform cell coefficients), on the same mesh with alpha = beta = 1, and on a
+    64^3 mesh (Q_3, alpha = beta = 1; 4 levels) where the exact solver's dense plane
+    blocks would take about 24 GB and minutes of setup, so only h-MG runs."""
+    import synth
+    res = {}
+    cases = [("c2_q7_n32_loguniform", 32, 7, True, (rz.COARSE_DIRECT, rz.COARSE_HMG)),
+             ("q7_n32_const", 32, 7, False, (rz.COARSE_DIRECT, rz.COARSE_HMG)),
+             ("q3_n64_const", 64, 3, False, (rz.COARSE_HMG,))]
+    for name, n, p, logu, coarses in cases:
+        al, be = (synth.cell_coefficients(n ** 3, 1), synth.cell_coefficients(n ** 3, 2)) if logu else (1.0, 1.0)
+        bt = torch.as_tensor(synth.rhs_values((n * p + 1) ** 3, 0), device="cuda:0")
+        x = torch.zeros_like(bt)
+        row = {"ndofs": (n * p + 1) ** 3}
+        for co in coarses:
+            key = "hmg" if co == rz.COARSE_HMG else "direct"
+            log(f"h-MG study: {name} {key}")
+            t0 = time.perf_counter()
+            pb = rz.Problem(ctx, n, p, al, be, coarse=co)
+            torch.cuda.synchronize()
+            setup = time.perf_counter() - t0
+            ms, infos, kt = time_solves(torch, pb, bt, x, steps, warmup)
+            r = {"setup_s": round(setup, 3), "pcg_ms": round(ms, 3), "iters": infos[-1].iters,
+                 "rel_res": max(i.rel_res for i in infos),
+                 "coarse_ms_per_step": round(kt["coarse"][0] / steps, 4),
+                 "coarse_ms_per_call": round(kt["coarse"][0] / max(kt["coarse"][1], 1), 4)}
+            if co == rz.COARSE_HMG:
+                r["levels"] = pb.hmg_levels()
+                gms, ginf, gst = time_graph(torch, pb, bt, x, steps)
+                r["pcg_ms_graph"] = round(gms, 3)
+                r["graph_segments"] = gst["segments"]
+            row[key] = r
+            pb.close()
+        res[name] = row
+    return res
+
+
 def bench_c1(torch, rz, ctx, steps=20):
     """C1: Q_4 on 4^3, alpha = beta = 1; apply latency and PCG time (FP64)."""
     import synth
@@ -730,7 +770,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--p", type=int, default=7)
-    ap.add_argument("--only", choices=["c2", "c2-apply", "c2-relax", "c3", "c3-apply", "c5-apply", "table"],
+    ap.add_argument("--only", choices=["c2", "c2-apply", "c2-relax", "c3", "c3-apply", "c5-apply", "table", "hmg"],
                     default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -738,6 +778,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-table", action="store_true", help="skip the Table hgrad-iter iteration study")
+    ap.add_argument("--no-hmg", action="store_true", help="skip the h-multigrid coarse-solver study")
     ap.add_argument("--nrhs", type=int, default=4, help="right-hand sides of the C2 multi-vector solve (1: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB once before the solves (outside the timed region), a plain copy "
@@ -794,6 +835,8 @@ def main():
             res = bench_c3(torch, rz, ctx, args.steps, args.warmup)
         elif piece == "table":
             res = bench_table_hgrad_iter(torch, rz, ctx)
+        elif piece == "hmg":
+            res = bench_hmg(torch, rz, ctx, args.steps, args.warmup)
         elif piece == "c3-apply":
             pb = rz.Problem(ctx, 16, 6, 1.0, 1.0, space="curl", omega=0.3)
             res["apply_ms_f64"] = time_apply(torch, pb, torch.float64, rz.F64, reps=args.steps)
@@ -822,6 +865,8 @@ def main():
         out["c3"] = bench_c3(torch, rz, ctx, max(1, args.steps // 2), 1)
     if not args.no_table:
         out["table_hgrad_iter"] = bench_table_hgrad_iter(torch, rz, ctx)
+    if not args.no_hmg:
+        out["hmg_coarse"] = bench_hmg(torch, rz, ctx, max(1, args.steps // 3), 1)
     if not args.no_c5:
         out["c5"] = bench_c5(torch, rz, ctx, max(1, args.steps // 2), 1)
     if not args.no_batched:

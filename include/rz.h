@@ -145,7 +145,21 @@ typedef struct {
                         * norm (r^T M^{-1} r)^{1/2} of a residual has dropped by rtol    *
                         * against the first (iters_natural then counts the iterations,   *
                         * rel_res reports the true 2-norm residual at exit)              */
+  int32_t coarse;      /* H(grad) solver of the p = 1 problem inside the p-multigrid    *
+                        * cycle: RZ_COARSE_DIRECT (default) the exact solve, or          *
+                        * RZ_COARSE_HMG geometric h-multigrid on the Q_1 space (the      *
+                        * h-hierarchy of Sec. 5.1): meshes with half the cells per axis  *
+                        * while every count is even and a level holds more than 512 free *
+                        * vertices, trilinear interpolation, Galerkin operators, one     *
+                        * V(1,1) cycle with point Jacobi (weight 2/3) from a zero guess, *
+                        * the coarsest level solved exactly (dense inverse, at most 4096 *
+                        * free vertices, else RZ_ERR_ARG).  The cycle is symmetric       *
+                        * positive definite, so CG stays valid; iteration counts may     *
+                        * grow slightly against the exact solve.                         */
 } rz_opts;
+
+/* Solvers of the p = 1 problem (rz_opts.coarse). */
+enum { RZ_COARSE_DIRECT = 0, RZ_COARSE_HMG = 1 };
 
 /* Decompositions of the H(grad) relaxation (rz_opts.decomposition). */
 enum { RZ_DECOMP_SC = 0, RZ_DECOMP_FULL = 1 };
@@ -327,6 +341,8 @@ rz_status rz_sync(rz_problem *h);
  *   RZ_EXPORT_GRAPHS     int64 triple: CG iterations captured as HIP graphs, iterations
  *                        run from them, segments per captured iteration (last capture)
  *                        of this problem (rz_opts.graph)
+ *   RZ_EXPORT_HMG        int64 per level of the h-multigrid coarse solver (rz_opts.coarse =
+ *                        RZ_COARSE_HMG), finest first: its free vertices (rows)
  *   RZ_EXPORT_EDGE_PATCH int64: edge id, then the DoFs (ascending) of non-empty
  *                        edge-star patch `index` of H(curl) (or of the NCE_p
  *                        potential problem of H(div)); edge ids run over the axis
@@ -336,7 +352,7 @@ enum {
   RZ_EXPORT_DOFMAP = 0, RZ_EXPORT_PATCH = 1, RZ_EXPORT_IC_PATTERN = 2,
   RZ_EXPORT_IC_FACTOR = 3, RZ_EXPORT_TABLES1D = 4, RZ_EXPORT_AUXCOEF = 5,
   RZ_EXPORT_OMEGA = 6, RZ_EXPORT_PATCH_KERNEL = 7, RZ_EXPORT_EDGE_PATCH = 8, RZ_EXPORT_STATS = 9,
-  RZ_EXPORT_PAPER_DIAG = 10, RZ_EXPORT_AUTOTUNE = 11, RZ_EXPORT_GRAPHS = 12
+  RZ_EXPORT_PAPER_DIAG = 10, RZ_EXPORT_AUTOTUNE = 11, RZ_EXPORT_GRAPHS = 12, RZ_EXPORT_HMG = 13
 };
 rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *bytes);
 

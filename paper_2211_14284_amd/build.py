@@ -12,8 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librz.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["tables1d.cpp", "patch.cpp", "geom.cpp", "vec_local.cpp", "rz_api.cpp", "k_grad.hip", "k_grad_pd.hip", "k_common.hip",
-           "k_quad.hip", "k_quad_mfma.hip", "k_vec.hip", "k_vec_relax.hip", "mlp.hip"]
+SOURCES = ["tables1d.cpp", "patch.cpp", "geom.cpp", "vec_local.cpp", "hmg.cpp", "rz_api.cpp", "k_grad.hip", "k_grad_pd.hip", "k_common.hip",
+           "k_quad.hip", "k_quad_mfma.hip", "k_vec.hip", "k_vec_relax.hip", "mlp.hip", "k_hmg.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950", "-munsafe-fp-atomics",

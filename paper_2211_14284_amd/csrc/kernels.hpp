@@ -225,6 +225,13 @@ template <typename TM>
 void launch_gemv(int m, const TM *M, const double *x, double *y, hipStream_t s);
 // y = M x for a dense symmetric m x m matrix (row-major) from its lower triangle;
 // work: ceil(m/64)^2 * 64 doubles
+// One matrix row per lane of the h-multigrid cycle on the Q_1 space (FP64), the
+// matrix in ELL form (n rows, width entries each, entry k of row i at k * n + i):
+// HMG_RES0 out = b - A (w D^{-1} b); HMG_PROD out = M x; HMG_PROL out = w D^{-1} b + P x;
+// HMG_POST out = x + w D^{-1} (b - A x).  out aliases none of the inputs.
+enum { HMG_RES0 = 0, HMG_PROD = 1, HMG_PROL = 2, HMG_POST = 3 };
+void launch_hmg_row(int mode, int n, int width, const int *col, const double *val, const double *x,
+                    const double *b, const double *dinv, double w, double *out, hipStream_t s);
 template <typename TM>
 void launch_symv(int m, const TM *M, const double *x, double *y, double *work, hipStream_t s);
 // z[list[t]] = r ? r[list[t]] : 0

@@ -20,6 +20,7 @@
 #include "kernels.hpp"
 #include "lattice.hpp"
 #include "geom.hpp"
+#include "hmg.hpp"
 #include "patch.hpp"
 #include "tables1d.hpp"
 #include "vec_local.hpp"
@@ -211,6 +212,21 @@ struct rz_problem {
   } ig[2];
   uint64_t graph_gen = 1;                  // bumped when buffers named by the graphs change
   int64_t graph_stat[3] = {0, 0, 0};       // captures, replayed iterations, segments
+  // geometric h-multigrid on the Q_1 space (rz_opts.coarse = RZ_COARSE_HMG): levels
+  // with a coarser one below (n rows; A, D^{-1}, P to and R from the next level; the
+  // level's input b and output o, unused on level 0; residual t and iterate x), then
+  // the coarsest level's dense inverse
+  struct HmgLevel {
+    int n = 0, nnext = 0, aw = 0, pw = 0, rw = 0;  // rows; ELL widths of A, P, R
+    int *a_col = nullptr, *p_col = nullptr, *r_col = nullptr;
+    double *a_val = nullptr, *dinv = nullptr, *p_val = nullptr, *r_val = nullptr;
+    double *b = nullptr, *o = nullptr, *t = nullptr, *x = nullptr;
+  };
+  bool hmg_on = false;
+  std::vector<HmgLevel> hmg;
+  std::vector<int64_t> hmg_sizes;           // rows of levels 0..L
+  int hmg_nc = 0;
+  double *hmg_cinv = nullptr, *hmg_cb = nullptr, *hmg_co = nullptr, *hmg_work = nullptr;
   // exact Cholesky vertex-star solves (opts.patch_solver): W = L^{-1} per slot,
   // dense lower packed by rows
   double *cw64 = nullptr;
@@ -670,6 +686,8 @@ int coarse_coop(rz_problem *h, bool f32) {
              : launch_coarse_solve(m, nb, h->cq, h->cW, h->cM, h->cN, h->cr, h->cu, h->cv, h->cx, h->status, s);
 }
 
+void hmg_cycle(rz_problem *h, const double *b0, double *o0);
+
 // Coarse solve; f32 selects the FP32 copies of the dense blocks (V-cycles of the
 // mixed protocols), otherwise FP64 throughout.
 rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv, bool f32 = false) {
@@ -678,7 +696,9 @@ rz_status do_coarse(rz_problem *h, const double *rcv, double *xcv, bool f32 = fa
   const int m = h->cm, nb = h->cmz;
   launch_coarse_gather(m * nb, h->cbx0, h->cby0, h->cbz0, h->cmx, h->cmy, h->cNX, h->cNY, rcv, h->cr, h->cv, h->cx,
                        s);
-  if (h->cap) {
+  if (h->hmg_on) {
+    hmg_cycle(h, h->cr, h->cx);  // ordinary launches: captured with the rest of the iteration
+  } else if (h->cap) {
     // capturing a PCG iteration: the cooperative launch stays outside the graphs, so
     // the segment closes here and the next one starts; the replay runs the solve
     // between the two segments
@@ -1246,6 +1266,125 @@ rz_status estimate_lambda(rz_problem *h, double *lam_out) {
 // coarse problem: Q_1 rediscretisation with the same per-cell weights; plane-wise
 // block-tridiagonal LDL^T with dense inverse diagonal blocks.
 // ---------------------------------------------------------------------------------------
+// Geometric h-multigrid on the Q_1 space: the level-0 operator is the 27-point
+// stencil st of the free box (neighbours outside the box dropped: Dirichlet
+// vertices), the hierarchy and its Galerkin operators are built on the host, the
+// coarsest level is inverted densely on the device.
+constexpr int64_t kHmgMinFree = 512, kHmgMaxCoarsest = 4096;
+constexpr double kHmgJacobi = 2.0 / 3.0;
+
+rz_status setup_hmg(rz_problem *h, const std::vector<double> &st) {
+  hipStream_t s = h->ctx->stream;
+  const int mx = h->cmx, my = h->cmy, mz = h->cmz;
+  HostCsr A0;
+  A0.n = A0.m = mx * my * mz;
+  A0.ptr.assign(A0.n + 1, 0);
+  for (int z = 0; z < mz; ++z)
+    for (int y = 0; y < my; ++y)
+      for (int x = 0; x < mx; ++x) {
+        const int64_t row = x + (int64_t)mx * (y + (int64_t)my * z);
+        for (int off = 0; off < 27; ++off) {  // ascending column order: z, then y, then x offset
+          const int X = x + off % 3 - 1, Y = y + (off / 3) % 3 - 1, Z = z + off / 9 - 1;
+          if (X < 0 || X >= mx || Y < 0 || Y >= my || Z < 0 || Z >= mz) continue;
+          A0.col.push_back(X + mx * (Y + my * Z));
+          A0.val.push_back(st[row * 27 + off]);
+        }
+        A0.ptr[row + 1] = (int)A0.col.size();
+      }
+  const int n[3] = {h->nx, h->ny, h->nz};
+  std::vector<HostCsr> A, P, R;
+  hmg_hierarchy(std::move(A0), n, h->dir, kHmgMinFree, A, P, R);
+  const int L = (int)P.size();
+  h->hmg_sizes.clear();
+  for (auto &M : A) h->hmg_sizes.push_back(M.n);
+  if (A[L].n > kHmgMaxCoarsest)
+    return fail(h->ctx, RZ_ERR_ARG,
+                "h-multigrid coarse solver: the coarsest level (cell counts halved while all even) exceeds 4096 "
+                "free vertices");
+  rz_status e;
+  h->hmg.assign(L, rz_problem::HmgLevel());
+  for (int l = 0; l < L; ++l) {
+    auto &V = h->hmg[l];
+    V.n = A[l].n;
+    V.nnext = A[l + 1].n;
+    std::vector<double> dinv(V.n);
+    for (int i = 0; i < V.n; ++i) {
+      double d = 0.0;
+      for (int k = A[l].ptr[i]; k < A[l].ptr[i + 1]; ++k)
+        if (A[l].col[k] == i) d = A[l].val[k];
+      if (!(d > 0.0)) return fail(h->ctx, RZ_ERR_SINGULAR, "h-multigrid: non-positive diagonal");
+      dinv[i] = 1.0 / d;
+    }
+    // ELL form: entry k of row i at k * n + i, short rows padded with (i, 0)
+    auto ell = [&](const HostCsr &M, int &width, int **dcol, double **dval) -> rz_status {
+      width = 0;
+      for (int i = 0; i < M.n; ++i) width = std::max(width, M.ptr[i + 1] - M.ptr[i]);
+      std::vector<int> c((size_t)width * M.n);
+      std::vector<double> v((size_t)width * M.n, 0.0);
+      for (int i = 0; i < M.n; ++i)
+        for (int k = 0; k < width; ++k) {
+          const int q = M.ptr[i] + k;
+          const bool in = q < M.ptr[i + 1];
+          c[(size_t)k * M.n + i] = in ? M.col[q] : std::min(i, M.m - 1);
+          v[(size_t)k * M.n + i] = in ? M.val[q] : 0.0;
+        }
+      rz_status r;
+      if ((r = upload(h, dcol, c)) || (r = upload(h, dval, v))) return r;
+      return RZ_OK;
+    };
+    if ((e = ell(A[l], V.aw, &V.a_col, &V.a_val)) || (e = ell(P[l], V.pw, &V.p_col, &V.p_val)) ||
+        (e = ell(R[l], V.rw, &V.r_col, &V.r_val)) || (e = upload(h, &V.dinv, dinv)) || (e = dalloc(h, &V.t, V.n)) ||
+        (e = dalloc(h, &V.x, V.n)))
+      return e;
+    if (l > 0 && ((e = dalloc(h, &V.b, V.n)) || (e = dalloc(h, &V.o, V.n)))) return e;
+  }
+  const int nc = A[L].n;
+  h->hmg_nc = nc;
+  std::vector<double> D((size_t)nc * nc, 0.0);
+  for (int i = 0; i < nc; ++i)
+    for (int k = A[L].ptr[i]; k < A[L].ptr[i + 1]; ++k) D[(size_t)i * nc + A[L].col[k]] = A[L].val[k];
+  if ((e = upload(h, &h->hmg_cinv, D))) return e;
+  double *tmp = nullptr;
+  if (hipMalloc(&tmp, sizeof(double) * (size_t)nc * nc) != hipSuccess)
+    return fail(h->ctx, RZ_ERR_OOM, "h-multigrid coarsest inverse workspace");
+  launch_sweep_inverse(nc, h->hmg_cinv, tmp, h->status, s);
+  const hipError_t se = hipStreamSynchronize(s);
+  hipFree(tmp);
+  if (se != hipSuccess) return fail(h->ctx, RZ_ERR_HIP, "h-multigrid coarsest inverse failed");
+  int stv = 0;
+  HIPCALL(h, hipMemcpy(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost));
+  if (stv) return fail(h->ctx, RZ_ERR_SINGULAR, "h-multigrid coarsest level: non-positive pivot");
+  const size_t nt = ((size_t)nc + 63) / 64;
+  if ((e = dalloc(h, &h->hmg_work, nt * nt * 64))) return e;
+  if (L > 0 && ((e = dalloc(h, &h->hmg_cb, nc)) || (e = dalloc(h, &h->hmg_co, nc)))) return e;
+  h->hmg_on = true;
+  return RZ_OK;
+}
+
+// One V(1,1) cycle of the h-multigrid from a zero guess on the free-box vectors:
+// o0 = B b0 (levels: residual after the pre-relaxation, restriction; the coarsest
+// dense solve; then the prolonged correction plus the pre-relaxed iterate, and the
+// post-relaxation)
+void hmg_cycle(rz_problem *h, const double *b0, double *o0) {
+  hipStream_t s = h->ctx->stream;
+  const int L = (int)h->hmg.size();
+  const double w = kHmgJacobi;
+  auto bin = [&](int l) -> const double * { return l == 0 ? b0 : l < L ? h->hmg[l].b : h->hmg_cb; };
+  auto bout = [&](int l) -> double * { return l == 0 ? o0 : l < L ? h->hmg[l].o : h->hmg_co; };
+  for (int l = 0; l < L; ++l) {
+    auto &V = h->hmg[l];
+    launch_hmg_row(HMG_RES0, V.n, V.aw, V.a_col, V.a_val, nullptr, bin(l), V.dinv, w, V.t, s);
+    launch_hmg_row(HMG_PROD, V.nnext, V.rw, V.r_col, V.r_val, V.t, nullptr, nullptr, 0.0,
+                   const_cast<double *>(bin(l + 1)), s);
+  }
+  launch_symv<double>(h->hmg_nc, h->hmg_cinv, bin(L), bout(L), h->hmg_work, s);
+  for (int l = L - 1; l >= 0; --l) {
+    auto &V = h->hmg[l];
+    launch_hmg_row(HMG_PROL, V.n, V.pw, V.p_col, V.p_val, bout(l + 1), bin(l), V.dinv, w, V.x, s);
+    launch_hmg_row(HMG_POST, V.n, V.aw, V.a_col, V.a_val, V.x, bin(l), V.dinv, w, bout(l), s);
+  }
+}
+
 rz_status setup_coarse(rz_problem *h) {
   hipStream_t s = h->ctx->stream;
   const int NX = h->nx + 1, NY = h->ny + 1, NZ = h->nz + 1;
@@ -1268,7 +1407,6 @@ rz_status setup_coarse(rz_problem *h) {
   h->cmz = hi[2] - lo[2] + 1;
   const int m = h->cmx * h->cmy, nb = h->cmz;
   h->cm = m;
-  if (m > 4096) return fail(h->ctx, RZ_ERR_ARG, "coarse plane too large for the dense-block coarse solver");
   // 27-point stencil of every free coarse DoF from the p=1 cell matrices
   const Tables1D &t1 = h->t1;
   auto B1 = [&](int a, int b) { return t1.B[a * 2 + b]; };
@@ -1297,8 +1435,13 @@ rz_status setup_coarse(rz_problem *h) {
       }
     }
   }
-  // device blocks
   rz_status e;
+  if (h->opts.coarse == RZ_COARSE_HMG) {
+    if ((e = dalloc(h, &h->cr, nfree)) || (e = dalloc(h, &h->cv, nfree)) || (e = dalloc(h, &h->cx, nfree))) return e;
+    return setup_hmg(h, st);
+  }
+  if (m > 4096) return fail(h->ctx, RZ_ERR_ARG, "coarse plane too large for the dense-block coarse solver");
+  // device blocks
   if ((e = dalloc(h, &h->cW, (size_t)nb * m * m))) return e;
   std::vector<double> C((size_t)nb * m * 9, 0.0), Ct((size_t)nb * m * 9, 0.0);
   for (int k = 0; k < nb; ++k)
@@ -3069,6 +3212,9 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
   if (opts->patch_solver != RZ_PATCH_IC && opts->patch_solver != RZ_PATCH_CHOLESKY)
     return fail(ctx, RZ_ERR_ARG, "bad patch_solver");
   if (opts->norm != RZ_NORM_2 && opts->norm != RZ_NORM_NATURAL) return fail(ctx, RZ_ERR_ARG, "bad norm");
+  if (opts->coarse != RZ_COARSE_DIRECT && opts->coarse != RZ_COARSE_HMG) return fail(ctx, RZ_ERR_ARG, "bad coarse");
+  if (opts->coarse == RZ_COARSE_HMG && opts->space != RZ_GRAD)
+    return fail(ctx, RZ_ERR_ARG, "the h-multigrid coarse solver is built for H(grad) only");
   if (opts->decomposition != RZ_DECOMP_SC && opts->decomposition != RZ_DECOMP_FULL)
     return fail(ctx, RZ_ERR_ARG, "bad decomposition");
   if (opts->decomposition == RZ_DECOMP_FULL && opts->space == RZ_GRAD && opts->aux == RZ_AUX_PAPER_DIAG)
@@ -3674,6 +3820,10 @@ rz_status rz_export(rz_problem *h, int what, int64_t index, void *buf, int64_t *
   switch (what) {
     case RZ_EXPORT_GRAPHS:
       put(h->graph_stat, sizeof h->graph_stat);
+      break;
+    case RZ_EXPORT_HMG:
+      if (!h->hmg_on) return fail(h->ctx, RZ_ERR_ARG, "no h-multigrid coarse solver on this problem");
+      put(h->hmg_sizes.data(), sizeof(int64_t) * h->hmg_sizes.size());
       break;
     case RZ_EXPORT_AUTOTUNE: {
       for (int w = 0; w < 2; ++w) {

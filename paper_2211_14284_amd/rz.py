@@ -27,11 +27,12 @@ COEF_CONST, COEF_CELL, COEF_SAMPLES = 0, 1, 2
 PREC_F64, PREC_MIXED, PREC_DEFECT = 0, 1, 2
 EXPORT_DOFMAP, EXPORT_PATCH, EXPORT_IC_PATTERN, EXPORT_IC_FACTOR = 0, 1, 2, 3
 EXPORT_TABLES1D, EXPORT_AUXCOEF, EXPORT_OMEGA, EXPORT_PATCH_KERNEL = 4, 5, 6, 7
-EXPORT_EDGE_PATCH, EXPORT_STATS, EXPORT_PAPER_DIAG, EXPORT_AUTOTUNE, EXPORT_GRAPHS = 8, 9, 10, 11, 12
+EXPORT_EDGE_PATCH, EXPORT_STATS, EXPORT_PAPER_DIAG, EXPORT_AUTOTUNE, EXPORT_GRAPHS, EXPORT_HMG = 8, 9, 10, 11, 12, 13
 AUX_CELL_AVG, AUX_PAPER_DIAG = 0, 1
 PATCH_IC, PATCH_CHOLESKY = 0, 1
 NORM_2, NORM_NATURAL = 0, 1
 DECOMP_SC, DECOMP_FULL = 0, 1
+COARSE_DIRECT, COARSE_HMG = 0, 1
 KERNELS = ("apply", "condense", "patch", "expand", "transfer", "coarse", "krylov")
 STATUS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_OOM", -3: "RZ_ERR_BREAKDOWN",
           -4: "RZ_ERR_NOT_CONVERGED", -5: "RZ_ERR_HIP", -6: "RZ_ERR_SINGULAR", -7: "RZ_ERR_NODEVICE"}
@@ -58,7 +59,7 @@ class Opts(ctypes.Structure):
                 ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double), ("omega", ctypes.c_double),
                 ("lanczos_seed", ctypes.c_uint64), ("hdiv_eps", ctypes.c_double), ("aux", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("patch_solver", ctypes.c_int32),
-                ("decomposition", ctypes.c_int32), ("norm", ctypes.c_int32)]
+                ("decomposition", ctypes.c_int32), ("norm", ctypes.c_int32), ("coarse", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -378,6 +379,11 @@ class Problem:
         """(captures, iterations replayed, segments per captured iteration) of the
         captured CG iterations (graph=1)."""
         return tuple(int(v) for v in self._export(EXPORT_GRAPHS, dtype=np.int64))
+
+    def hmg_levels(self):
+        """Free vertices per level of the h-multigrid coarse solver (coarse=COARSE_HMG),
+        finest first."""
+        return [int(v) for v in self._export(EXPORT_HMG, dtype=np.int64)]
 
     def aux_coefficients(self):
         return self._export(EXPORT_AUXCOEF).reshape(self.ncells, 6)
