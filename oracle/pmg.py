@@ -81,6 +81,20 @@ class CoarseSolver:
         return out
 
 
+JACOBI_C = 1.5
+
+
+def jacobi_weight(M):
+    """Damping of point Jacobi on the SPD matrix M: JACOBI_C over the largest row sum
+    of |D^{-1/2} M D^{-1/2}| (Gershgorin), an upper bound of the spectrum of D^{-1} M,
+    so that the weighted spectrum stays in (0, JACOBI_C] and the relaxation contracts
+    on any mesh (anisotropic cells included) and for any positive coefficients."""
+    M = sp.csr_matrix(M)
+    d = M.diagonal()
+    S = sp.diags(1.0 / np.sqrt(d)) @ abs(M) @ sp.diags(1.0 / np.sqrt(d))
+    return JACOBI_C / np.asarray(S.sum(axis=1)).max()
+
+
 def interp_1d(nf, lo_f, hi_f, lo_c, hi_c):
     """Linear interpolation on one axis from the coarse vertices c (at fine vertex 2c)
     to the fine vertices f: 1 where f = 2c, 1/2 where |f - 2c| = 1; rows the free
@@ -103,12 +117,11 @@ class HMGCoarse:
     half the cells per axis, with trilinear interpolation P (the Kronecker product of
     the 1-D linear interpolations on the free coordinates) and the Galerkin operator
     P^T A P; the coarsest level is solved exactly.  solve(r) is one V(1,1) cycle from a
-    zero guess with damped point Jacobi (weight omega_j) before and after the coarse
-    correction (a symmetric positive definite approximation of A_0^{-1})."""
+    zero guess with damped point Jacobi (the level's jacobi_weight) before and after the
+    coarse correction (a symmetric positive definite approximation of A_0^{-1})."""
 
-    def __init__(self, lat_c: Lattice, A0, omega_j=2.0 / 3.0, min_free=1000):
+    def __init__(self, lat_c: Lattice, A0, min_free=1000):
         mesh = lat_c.mesh
-        self.omega_j = omega_j
         mask = lat_c.dirichlet_mask()
         self.free = np.where(~mask)[0]
         self.n = lat_c.ndofs
@@ -129,16 +142,111 @@ class HMGCoarse:
             self.A.append(A)
             self.dinv.append(1.0 / A.diagonal())
             n, lo, hi = nc, loc, hic
+        self.w = [jacobi_weight(M) for M in self.A]
         self.chol = scipy.linalg.cho_factor(self.A[-1].toarray(), lower=True)
 
     def cycle(self, level, b):
         if level == len(self.A) - 1:
             return scipy.linalg.cho_solve(self.chol, b)
-        A, w, dinv = self.A[level], self.omega_j, self.dinv[level]
+        A, w, dinv = self.A[level], self.w[level], self.dinv[level]
         x = w * dinv * b
         xc = self.cycle(level + 1, self.P[level].T @ (b - A @ x))
         x = x + self.P[level] @ xc
         return x + w * dinv * (b - A @ x)
+
+    def solve(self, r):
+        out = np.zeros(self.n)
+        out[self.free] = self.cycle(0, r[self.free])
+        return out
+
+
+def halve_1d(nf, nc, continuous):
+    """One axis of the interpolation between nested lowest-order spaces on meshes of
+    nf = 2 nc and nc cells (all vertices or cells, before Dirichlet rows are taken
+    out).  Continuous axis: the hats, linear interpolation (interp_1d).  Broken axis:
+    a coarse cell's constant r_0 is, in the reference coefficients of the Piola-mapped
+    fine functions, one half of r_0 on each of its two halves (the Piola factor of
+    that axis scales with the cell size)."""
+    if continuous:
+        return interp_1d(nf + 1, 0, nf, 0, nc)
+    return sp.csr_matrix((np.full(nf, 0.5), (np.arange(nf), np.arange(nf) // 2)), shape=(nf, nc))
+
+
+class HiptmairHMG:
+    """Geometric h-multigrid on the lowest-order space NCE_1 (H(curl)) or NCF_1
+    (H(div)) as the p-coarse solver, with Hiptmair-Jacobi relaxation (the h-hierarchy
+    of Sec. 5.1 in the solver diagram of Fig. hcurl_solver_diagram).
+
+    Levels: the mesh with half the cells per axis while every count is even and the
+    level holds more than min_free free DoFs; P the per-component Kronecker product
+    of halve_1d on the free DoFs, A_{l+1} = P^T A_l P.  Potential space of each level:
+    Q_1 (H(curl)) or NCE_1 (H(div)) on that level's mesh with the same Dirichlet faces,
+    G the exterior derivative between the two lowest-order spaces on the free DoFs
+    (exterior_derivative), its operator G^T A_l G.  Relaxation: damped Jacobi on A_l
+    and damped Jacobi on G^T A_l G (each with its jacobi_weight), pre-smoothing in that
+    order and post-smoothing in the reverse order, so one V(1,1) cycle from a zero
+    guess is symmetric; the coarsest level is solved exactly."""
+
+    def __init__(self, lat_c: Lattice, A0, min_free=512):
+        from .lattice import Mesh
+        from .hiptmair import exterior_derivative
+        space = lat_c.space
+        pot = {"curl": "grad", "div": "curl"}[space]
+        mesh = lat_c.mesh
+        d = mesh.dirichlet
+        n = [mesh.nx, mesh.ny, mesh.nz]
+        lat = lat_c
+        self.free = np.where(~lat.dirichlet_mask())[0]
+        self.n = lat.ndofs
+        A = sp.csr_matrix(A0)[self.free][:, self.free]
+        self.A, self.P, self.G, self.dinv, self.dpinv, self.w, self.wp = [], [], [], [], [], [], []
+
+        def add_level(lat, A):
+            f = np.where(~lat.dirichlet_mask())[0]
+            latp = Lattice(lat.mesh, pot, 1)
+            fp = np.where(~latp.dirichlet_mask())[0]
+            G = sp.csr_matrix(exterior_derivative(latp, lat))[f][:, fp]
+            Ap = sp.csr_matrix(G.T @ A @ G)
+            self.A.append(A)
+            self.G.append(G)
+            self.dinv.append(1.0 / A.diagonal())
+            self.dpinv.append(1.0 / Ap.diagonal())
+            self.w.append(jacobi_weight(A))
+            self.wp.append(jacobi_weight(Ap))
+            return f
+
+        f = add_level(lat, A)
+        while all(k % 2 == 0 for k in n) and A.shape[0] > min_free:
+            nc = [k // 2 for k in n]
+            latn = Lattice(Mesh(*nc, dirichlet=d), space, 1)
+            blocks = []
+            for m, kind in enumerate(lat.kinds):
+                Ps = [halve_1d(n[a], nc[a], kind[a] == "P") for a in range(3)]
+                blocks.append(sp.kron(Ps[2], sp.kron(Ps[1], Ps[0])))
+            fn = np.where(~latn.dirichlet_mask())[0]
+            P = sp.csr_matrix(sp.block_diag(blocks, format="csr")[f][:, fn])
+            A = sp.csr_matrix(P.T @ A @ P)
+            self.P.append(P)
+            lat, n = latn, nc
+            f = add_level(lat, A)
+        self.chol = scipy.linalg.cho_factor(self.A[-1].toarray(), lower=True)
+
+    def _space_jacobi(self, l, b, x):
+        return x + self.w[l] * self.dinv[l] * (b - self.A[l] @ x)
+
+    def _pot_jacobi(self, l, b, x, wp=None):
+        G = self.G[l]
+        wp = self.wp[l] if wp is None else wp
+        return x + G @ (wp * self.dpinv[l] * (G.T @ (b - self.A[l] @ x)))
+
+    def cycle(self, level, b):
+        if level == len(self.A) - 1:
+            return scipy.linalg.cho_solve(self.chol, b)
+        x = self._space_jacobi(level, b, np.zeros_like(b))
+        x = self._pot_jacobi(level, b, x)
+        x = x + self.P[level] @ self.cycle(level + 1, self.P[level].T @ (b - self.A[level] @ x))
+        x = self._pot_jacobi(level, b, x)
+        return self._space_jacobi(level, b, x)
 
     def solve(self, r):
         out = np.zeros(self.n)

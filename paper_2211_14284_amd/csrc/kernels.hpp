@@ -226,10 +226,19 @@ void launch_gemv(int m, const TM *M, const double *x, double *y, hipStream_t s);
 // y = M x for a dense symmetric m x m matrix (row-major) from its lower triangle;
 // work: ceil(m/64)^2 * 64 doubles
 // One matrix row per lane of the h-multigrid cycle on the Q_1 space (FP64), the
-// matrix in ELL form (n rows, width entries each, entry k of row i at k * n + i):
+// matrix in ELL form (n rows, width entries each, entry k of row i at k * n + i;
+// hmg_ell_width lists the widths compiled for):
 // HMG_RES0 out = b - A (w D^{-1} b); HMG_PROD out = M x; HMG_PROL out = w D^{-1} b + P x;
-// HMG_POST out = x + w D^{-1} (b - A x).  out aliases none of the inputs.
-enum { HMG_RES0 = 0, HMG_PROD = 1, HMG_PROL = 2, HMG_POST = 3 };
+// HMG_POST out = x + w D^{-1} (b - A x); HMG_RES out = b - A x; HMG_ADD out = b + M x;
+// HMG_JPROD out = w D^{-1} (M x).  out aliases none of the inputs.
+enum { HMG_RES0 = 0, HMG_PROD = 1, HMG_PROL = 2, HMG_POST = 3, HMG_RES = 4, HMG_ADD = 5, HMG_JPROD = 6 };
+// the smallest compiled ELL width >= w (w itself past 64: a loop without a fixed count)
+inline int hmg_ell_width(int w) {
+  static const int kW[] = {2, 4, 6, 8, 12, 16, 18, 20, 24, 27, 28, 32, 36, 40, 48, 64};
+  for (int v : kW)
+    if (v >= w) return v;
+  return w;
+}
 void launch_hmg_row(int mode, int n, int width, const int *col, const double *val, const double *x,
                     const double *b, const double *dinv, double w, double *out, hipStream_t s);
 template <typename TM>

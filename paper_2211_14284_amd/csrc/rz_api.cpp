@@ -221,6 +221,12 @@ struct rz_problem {
     int *a_col = nullptr, *p_col = nullptr, *r_col = nullptr;
     double *a_val = nullptr, *dinv = nullptr, *p_val = nullptr, *r_val = nullptr;
     double *b = nullptr, *o = nullptr, *t = nullptr, *x = nullptr;
+    double w = 0.0;                               // Jacobi weight on A
+    // H(curl)/H(div): potential space (np DoFs), G and G^T in ELL, its Jacobi data
+    int np = 0, gw = 0, gtw = 0;
+    int *g_col = nullptr, *gt_col = nullptr;
+    double *g_val = nullptr, *gt_val = nullptr, *dpinv = nullptr, *x2 = nullptr, *y = nullptr;
+    double wp = 0.0;
   };
   bool hmg_on = false;
   std::vector<HmgLevel> hmg;
@@ -729,7 +735,8 @@ void coarse_correction_vec(rz_problem *h, const double *r1, T *z, bool f32) {
   }
   {
     Timed tm(h, RZ_K_COARSE);
-    if (f32 && h->cinv32) launch_symv<float>(h->ncf, h->cinv32, h->vcr, h->vcx, h->csym, s);
+    if (h->hmg_on) hmg_cycle(h, h->vcr, h->vcx);
+    else if (f32 && h->cinv32) launch_symv<float>(h->ncf, h->cinv32, h->vcr, h->vcx, h->csym, s);
     else launch_symv<double>(h->ncf, h->cinv64, h->vcr, h->vcx, h->csym, s);
   }
   {
@@ -1271,72 +1278,86 @@ rz_status estimate_lambda(rz_problem *h, double *lam_out) {
 // vertices), the hierarchy and its Galerkin operators are built on the host, the
 // coarsest level is inverted densely on the device.
 constexpr int64_t kHmgMinFree = 512, kHmgMaxCoarsest = 4096;
-constexpr double kHmgJacobi = 2.0 / 3.0;
+constexpr double kHmgJacobiC = 1.5;
 
-rz_status setup_hmg(rz_problem *h, const std::vector<double> &st) {
+// Damping of point Jacobi on the SPD matrix M: 1.5 over the largest row sum of
+// |D^{-1/2} M D^{-1/2}| (Gershgorin), an upper bound of the spectrum of D^{-1} M, so
+// the weighted spectrum stays in (0, 1.5] and the relaxation contracts on any mesh
+// and for any positive coefficients.  Also D^{-1} into dinv; false on a non-positive
+// diagonal.
+bool jacobi_weight(const HostCsr &M, std::vector<double> &dinv, double &w) {
+  std::vector<double> d(M.n, 0.0);
+  for (int i = 0; i < M.n; ++i)
+    for (int k = M.ptr[i]; k < M.ptr[i + 1]; ++k)
+      if (M.col[k] == i) d[i] = M.val[k];
+  dinv.resize(M.n);
+  double g = 0.0;
+  for (int i = 0; i < M.n; ++i) {
+    if (!(d[i] > 0.0)) return false;
+    dinv[i] = 1.0 / d[i];
+    double r = 0.0;
+    for (int k = M.ptr[i]; k < M.ptr[i + 1]; ++k) r += std::fabs(M.val[k]) / std::sqrt(d[i] * d[M.col[k]]);
+    g = std::max(g, r);
+  }
+  w = kHmgJacobiC / g;
+  return true;
+}
+
+// Device copies of the hierarchy: operators A[l], interpolations P[l] and
+// restrictions R[l] = P[l]^T; for H(curl)/H(div) also the exterior derivative G[l]
+// from the potential space and the potential operators Ap[l] = G^T A G (empty for
+// H(grad)).  Matrices in ELL form, the coarsest level inverted densely.
+rz_status hmg_upload(rz_problem *h, const std::vector<HostCsr> &A, const std::vector<HostCsr> &P,
+                     const std::vector<HostCsr> &R, const std::vector<HostCsr> &G, const std::vector<HostCsr> &Ap) {
   hipStream_t s = h->ctx->stream;
-  const int mx = h->cmx, my = h->cmy, mz = h->cmz;
-  HostCsr A0;
-  A0.n = A0.m = mx * my * mz;
-  A0.ptr.assign(A0.n + 1, 0);
-  for (int z = 0; z < mz; ++z)
-    for (int y = 0; y < my; ++y)
-      for (int x = 0; x < mx; ++x) {
-        const int64_t row = x + (int64_t)mx * (y + (int64_t)my * z);
-        for (int off = 0; off < 27; ++off) {  // ascending column order: z, then y, then x offset
-          const int X = x + off % 3 - 1, Y = y + (off / 3) % 3 - 1, Z = z + off / 9 - 1;
-          if (X < 0 || X >= mx || Y < 0 || Y >= my || Z < 0 || Z >= mz) continue;
-          A0.col.push_back(X + mx * (Y + my * Z));
-          A0.val.push_back(st[row * 27 + off]);
-        }
-        A0.ptr[row + 1] = (int)A0.col.size();
-      }
-  const int n[3] = {h->nx, h->ny, h->nz};
-  std::vector<HostCsr> A, P, R;
-  hmg_hierarchy(std::move(A0), n, h->dir, kHmgMinFree, A, P, R);
   const int L = (int)P.size();
   h->hmg_sizes.clear();
   for (auto &M : A) h->hmg_sizes.push_back(M.n);
   if (A[L].n > kHmgMaxCoarsest)
     return fail(h->ctx, RZ_ERR_ARG,
                 "h-multigrid coarse solver: the coarsest level (cell counts halved while all even) exceeds 4096 "
-                "free vertices");
+                "free DoFs");
+  // ELL form: entry k of row i at k * n + i, short rows padded with (min(i, m-1), 0)
+  auto ell = [&](const HostCsr &M, int &width, int **dcol, double **dval) -> rz_status {
+    width = 1;
+    for (int i = 0; i < M.n; ++i) width = std::max(width, M.ptr[i + 1] - M.ptr[i]);
+    width = hmg_ell_width(width);
+    std::vector<int> cc((size_t)width * M.n);
+    std::vector<double> v((size_t)width * M.n, 0.0);
+    for (int i = 0; i < M.n; ++i)
+      for (int k = 0; k < width; ++k) {
+        const int q = M.ptr[i] + k;
+        const bool in = q < M.ptr[i + 1];
+        cc[(size_t)k * M.n + i] = in ? M.col[q] : std::min(i, M.m - 1);
+        v[(size_t)k * M.n + i] = in ? M.val[q] : 0.0;
+      }
+    rz_status r;
+    if ((r = upload(h, dcol, cc)) || (r = upload(h, dval, v))) return r;
+    return RZ_OK;
+  };
   rz_status e;
   h->hmg.assign(L, rz_problem::HmgLevel());
   for (int l = 0; l < L; ++l) {
     auto &V = h->hmg[l];
     V.n = A[l].n;
     V.nnext = A[l + 1].n;
-    std::vector<double> dinv(V.n);
-    for (int i = 0; i < V.n; ++i) {
-      double d = 0.0;
-      for (int k = A[l].ptr[i]; k < A[l].ptr[i + 1]; ++k)
-        if (A[l].col[k] == i) d = A[l].val[k];
-      if (!(d > 0.0)) return fail(h->ctx, RZ_ERR_SINGULAR, "h-multigrid: non-positive diagonal");
-      dinv[i] = 1.0 / d;
-    }
-    // ELL form: entry k of row i at k * n + i, short rows padded with (i, 0)
-    auto ell = [&](const HostCsr &M, int &width, int **dcol, double **dval) -> rz_status {
-      width = 0;
-      for (int i = 0; i < M.n; ++i) width = std::max(width, M.ptr[i + 1] - M.ptr[i]);
-      std::vector<int> c((size_t)width * M.n);
-      std::vector<double> v((size_t)width * M.n, 0.0);
-      for (int i = 0; i < M.n; ++i)
-        for (int k = 0; k < width; ++k) {
-          const int q = M.ptr[i] + k;
-          const bool in = q < M.ptr[i + 1];
-          c[(size_t)k * M.n + i] = in ? M.col[q] : std::min(i, M.m - 1);
-          v[(size_t)k * M.n + i] = in ? M.val[q] : 0.0;
-        }
-      rz_status r;
-      if ((r = upload(h, dcol, c)) || (r = upload(h, dval, v))) return r;
-      return RZ_OK;
-    };
+    std::vector<double> dinv;
+    if (!jacobi_weight(A[l], dinv, V.w)) return fail(h->ctx, RZ_ERR_SINGULAR, "h-multigrid: non-positive diagonal");
     if ((e = ell(A[l], V.aw, &V.a_col, &V.a_val)) || (e = ell(P[l], V.pw, &V.p_col, &V.p_val)) ||
         (e = ell(R[l], V.rw, &V.r_col, &V.r_val)) || (e = upload(h, &V.dinv, dinv)) || (e = dalloc(h, &V.t, V.n)) ||
         (e = dalloc(h, &V.x, V.n)))
       return e;
     if (l > 0 && ((e = dalloc(h, &V.b, V.n)) || (e = dalloc(h, &V.o, V.n)))) return e;
+    if (!G.empty()) {
+      V.np = G[l].m;
+      std::vector<double> dpinv;
+      if (!jacobi_weight(Ap[l], dpinv, V.wp))
+        return fail(h->ctx, RZ_ERR_SINGULAR, "h-multigrid: non-positive diagonal of the potential operator");
+      const HostCsr GT = csr_transpose(G[l]);
+      if ((e = ell(G[l], V.gw, &V.g_col, &V.g_val)) || (e = ell(GT, V.gtw, &V.gt_col, &V.gt_val)) ||
+          (e = upload(h, &V.dpinv, dpinv)) || (e = dalloc(h, &V.x2, V.n)) || (e = dalloc(h, &V.y, std::max(V.np, 1))))
+        return e;
+    }
   }
   const int nc = A[L].n;
   h->hmg_nc = nc;
@@ -1361,27 +1382,68 @@ rz_status setup_hmg(rz_problem *h, const std::vector<double> &st) {
   return RZ_OK;
 }
 
-// One V(1,1) cycle of the h-multigrid from a zero guess on the free-box vectors:
-// o0 = B b0 (levels: residual after the pre-relaxation, restriction; the coarsest
-// dense solve; then the prolonged correction plus the pre-relaxed iterate, and the
-// post-relaxation)
+// H(grad): the level-0 operator is the 27-point stencil st of the free box
+// (neighbours outside the box dropped: Dirichlet vertices), the hierarchy of
+// hmg_hierarchy.
+rz_status setup_hmg(rz_problem *h, const std::vector<double> &st) {
+  const int mx = h->cmx, my = h->cmy, mz = h->cmz;
+  HostCsr A0;
+  A0.n = A0.m = mx * my * mz;
+  A0.ptr.assign(A0.n + 1, 0);
+  for (int z = 0; z < mz; ++z)
+    for (int y = 0; y < my; ++y)
+      for (int x = 0; x < mx; ++x) {
+        const int64_t row = x + (int64_t)mx * (y + (int64_t)my * z);
+        for (int off = 0; off < 27; ++off) {  // ascending column order: z, then y, then x offset
+          const int X = x + off % 3 - 1, Y = y + (off / 3) % 3 - 1, Z = z + off / 9 - 1;
+          if (X < 0 || X >= mx || Y < 0 || Y >= my || Z < 0 || Z >= mz) continue;
+          A0.col.push_back(X + mx * (Y + my * Z));
+          A0.val.push_back(st[row * 27 + off]);
+        }
+        A0.ptr[row + 1] = (int)A0.col.size();
+      }
+  const int n[3] = {h->nx, h->ny, h->nz};
+  std::vector<HostCsr> A, P, R;
+  hmg_hierarchy(std::move(A0), n, h->dir, kHmgMinFree, A, P, R);
+  return hmg_upload(h, A, P, R, {}, {});
+}
+
+// One V(1,1) cycle of the h-multigrid from a zero guess on the free-DoF vectors,
+// o0 = B b0.  H(grad), per level: the residual after the pre-relaxation, its
+// restriction; after the coarser level, the pre-relaxed iterate plus the
+// interpolated correction, and the post-relaxation.  H(curl)/H(div) (Hiptmair): the
+// pre-relaxation is Jacobi on A, then Jacobi on the potential operator through G;
+// the post-relaxation the same two steps in the reverse order.
 void hmg_cycle(rz_problem *h, const double *b0, double *o0) {
   hipStream_t s = h->ctx->stream;
   const int L = (int)h->hmg.size();
-  const double w = kHmgJacobi;
   auto bin = [&](int l) -> const double * { return l == 0 ? b0 : l < L ? h->hmg[l].b : h->hmg_cb; };
   auto bout = [&](int l) -> double * { return l == 0 ? o0 : l < L ? h->hmg[l].o : h->hmg_co; };
   for (int l = 0; l < L; ++l) {
     auto &V = h->hmg[l];
-    launch_hmg_row(HMG_RES0, V.n, V.aw, V.a_col, V.a_val, nullptr, bin(l), V.dinv, w, V.t, s);
+    const double *b = bin(l);
+    launch_hmg_row(HMG_RES0, V.n, V.aw, V.a_col, V.a_val, nullptr, b, V.dinv, V.w, V.t, s);  // t = b - A x0
+    if (V.np) {
+      launch_hmg_row(HMG_JPROD, V.np, V.gtw, V.gt_col, V.gt_val, V.t, nullptr, V.dpinv, V.wp, V.y, s);
+      launch_hmg_row(HMG_PROL, V.n, V.gw, V.g_col, V.g_val, V.y, b, V.dinv, V.w, V.x, s);  // x1 = x0 + G y
+      launch_hmg_row(HMG_RES, V.n, V.aw, V.a_col, V.a_val, V.x, b, nullptr, 0.0, V.t, s);  // t = b - A x1
+    }
     launch_hmg_row(HMG_PROD, V.nnext, V.rw, V.r_col, V.r_val, V.t, nullptr, nullptr, 0.0,
                    const_cast<double *>(bin(l + 1)), s);
   }
   launch_symv<double>(h->hmg_nc, h->hmg_cinv, bin(L), bout(L), h->hmg_work, s);
   for (int l = L - 1; l >= 0; --l) {
     auto &V = h->hmg[l];
-    launch_hmg_row(HMG_PROL, V.n, V.pw, V.p_col, V.p_val, bout(l + 1), bin(l), V.dinv, w, V.x, s);
-    launch_hmg_row(HMG_POST, V.n, V.aw, V.a_col, V.a_val, V.x, bin(l), V.dinv, w, bout(l), s);
+    const double *b = bin(l);
+    if (V.np) {
+      launch_hmg_row(HMG_ADD, V.n, V.pw, V.p_col, V.p_val, bout(l + 1), V.x, nullptr, 0.0, V.x2, s);  // x2 = x1 + P xc
+      launch_hmg_row(HMG_RES, V.n, V.aw, V.a_col, V.a_val, V.x2, b, nullptr, 0.0, V.t, s);
+      launch_hmg_row(HMG_JPROD, V.np, V.gtw, V.gt_col, V.gt_val, V.t, nullptr, V.dpinv, V.wp, V.y, s);
+      launch_hmg_row(HMG_ADD, V.n, V.gw, V.g_col, V.g_val, V.y, V.x2, nullptr, 0.0, V.x, s);  // x3 = x2 + G y
+    } else {
+      launch_hmg_row(HMG_PROL, V.n, V.pw, V.p_col, V.p_val, bout(l + 1), b, V.dinv, V.w, V.x, s);
+    }
+    launch_hmg_row(HMG_POST, V.n, V.aw, V.a_col, V.a_val, V.x, b, V.dinv, V.w, bout(l), s);
   }
 }
 
@@ -2185,6 +2247,151 @@ bool vec_interior(int space, int p, int m, const int X[3]) {
   return true;
 }
 
+// Free numbering of the lowest-order lattice of `space` (RZ_GRAD: the Q_1 vertices)
+// on a mesh of n cells: map[g] = free index or -1.
+int p1_free_map(int space, const int n[3], unsigned dir, int ext[3][3], int64_t off[4], std::vector<int> &map) {
+  if (space == RZ_GRAD) {
+    off[0] = 0;
+    off[1] = off[2] = off[3] = (int64_t)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
+    for (int m = 0; m < 3; ++m)
+      for (int a = 0; a < 3; ++a) ext[m][a] = n[a] + 1;
+  } else {
+    vec_lattice(space, 1, n, ext, off);
+  }
+  map.assign(off[3], -1);
+  int nf = 0;
+  for (int64_t g = 0; g < off[3]; ++g) {
+    int m, X[3];
+    vec_coords(off, ext, g, m, X);
+    bool d = false;
+    if (space == RZ_GRAD) {
+      for (int a = 0; a < 3; ++a)
+        d = d || ((dir & (1u << (2 * a))) && X[a] == 0) || ((dir & (1u << (2 * a + 1))) && X[a] == n[a]);
+    } else {
+      d = vec_dirichlet(space, dir, ext, m, X);
+    }
+    if (!d) map[g] = nf++;
+  }
+  return nf;
+}
+
+// Geometric h-multigrid with Hiptmair relaxation on the lowest-order H(curl) / H(div)
+// space (Sec. 5.1, the p-coarse solver of Fig. hcurl_solver_diagram).  Levels: the
+// mesh with half the cells per axis while every count is even and the level holds
+// more than 512 free DoFs.  Interpolation per component and axis: the hats
+// (weights 1 and 1/2) along a continuous axis; along a broken axis each fine half of
+// a coarse cell gets 1/2 of its r_0 (in reference coefficients the Piola factor of
+// that axis scales with the cell size).  A_{l+1} = P^T A_l P.  Potential space:
+// Q_1 (H(curl)) or NCE_1 (H(div)) on the level's mesh with the same Dirichlet faces,
+// G the exterior derivative from the 1-D derivative table of degree 1 (the rule of
+// the relaxation's potential term at p = 1), its operator G^T A_l G.
+rz_status setup_hmg_vec(rz_problem *h, HostCsr A0) {
+  const int space = h->space, pspace = space == RZ_CURL ? RZ_GRAD : RZ_CURL;
+  const double *D1 = h->t1.D.data();  // 1 x 2: derivative of the two hats in r_0
+  const unsigned dir = h->dir;
+  int n[3] = {h->nx, h->ny, h->nz};
+  std::vector<HostCsr> A, P, R, G, Ap;
+  A.push_back(std::move(A0));
+  int ext[3][3], pext[3][3];
+  int64_t off[4], poff[4];
+  std::vector<int> map, pmap;
+  for (;;) {
+    const int nf = p1_free_map(space, n, dir, ext, off, map);
+    const int npf = p1_free_map(pspace, n, dir, pext, poff, pmap);
+    if (nf != A.back().n) return fail(h->ctx, RZ_ERR_ARG, "h-multigrid: level numbering mismatch");
+    // exterior derivative, rows the free DoFs of the space, columns the free potential DoFs
+    HostCsr Gl;
+    Gl.n = nf;
+    Gl.m = npf;
+    Gl.ptr.assign(nf + 1, 0);
+    for (int64_t g = 0; g < off[3]; ++g) {
+      if (map[g] < 0) continue;
+      int m, X[3];
+      vec_coords(off, ext, g, m, X);
+      std::vector<std::pair<int, double>> row;
+      // (sign, potential component, derivative axis): grad of Q_1 along m for NCE
+      // component m; curl of NCE for NCF component k
+      int terms[2][3], nt = 0;
+      if (space == RZ_CURL) {
+        terms[nt][0] = 1, terms[nt][1] = 0, terms[nt][2] = m, ++nt;
+      } else {
+        const int a1 = (m + 1) % 3, a2 = (m + 2) % 3;
+        terms[nt][0] = 1, terms[nt][1] = a2, terms[nt][2] = a1, ++nt;
+        terms[nt][0] = -1, terms[nt][1] = a1, terms[nt][2] = a2, ++nt;
+      }
+      for (int q = 0; q < nt; ++q)
+        for (int a = 0; a <= 1; ++a) {
+          int Y[3] = {X[0], X[1], X[2]};
+          Y[terms[q][2]] += a;
+          const int col = pmap[vec_index(poff, pext, terms[q][1], Y)];
+          if (col >= 0 && D1[a] != 0.0) row.push_back({col, terms[q][0] * D1[a]});
+        }
+      std::sort(row.begin(), row.end());
+      for (auto &cv : row) {
+        Gl.col.push_back(cv.first);
+        Gl.val.push_back(cv.second);
+      }
+      Gl.ptr[map[g] + 1] = (int)Gl.col.size();
+    }
+    for (int i = 0; i < nf; ++i) Gl.ptr[i + 1] = std::max(Gl.ptr[i + 1], Gl.ptr[i]);
+    Ap.push_back(csr_product(csr_transpose(Gl), csr_product(A.back(), Gl)));
+    G.push_back(std::move(Gl));
+    if (!(n[0] % 2 == 0 && n[1] % 2 == 0 && n[2] % 2 == 0) || nf <= kHmgMinFree) break;
+    const int nc[3] = {n[0] / 2, n[1] / 2, n[2] / 2};
+    int cext[3][3];
+    int64_t coff[4];
+    std::vector<int> cmap;
+    const int ncf = p1_free_map(space, nc, dir, cext, coff, cmap);
+    if (ncf == 0) break;
+    HostCsr Pl;
+    Pl.n = nf;
+    Pl.m = ncf;
+    Pl.ptr.assign(nf + 1, 0);
+    for (int64_t g = 0; g < off[3]; ++g) {
+      if (map[g] < 0) continue;
+      int m, X[3];
+      vec_coords(off, ext, g, m, X);
+      int cnt[3], ci[3][2];
+      double cw[3][2];
+      for (int a = 0; a < 3; ++a) {
+        cnt[a] = 0;
+        if (vec_is_P(space, m, a)) {
+          for (int d = -1; d <= 1; ++d) {
+            const int t = X[a] + d;
+            if (t < 0 || t % 2 != 0 || t / 2 > nc[a]) continue;
+            ci[a][cnt[a]] = t / 2;
+            cw[a][cnt[a]++] = d == 0 ? 1.0 : 0.5;
+          }
+        } else {
+          ci[a][0] = X[a] / 2;
+          cw[a][0] = 0.5;
+          cnt[a] = 1;
+        }
+      }
+      std::vector<std::pair<int, double>> row;
+      for (int k = 0; k < cnt[2]; ++k)
+        for (int j = 0; j < cnt[1]; ++j)
+          for (int i = 0; i < cnt[0]; ++i) {
+            const int Y[3] = {ci[0][i], ci[1][j], ci[2][k]};
+            const int col = cmap[vec_index(coff, cext, m, Y)];
+            if (col >= 0) row.push_back({col, cw[0][i] * cw[1][j] * cw[2][k]});
+          }
+      std::sort(row.begin(), row.end());
+      for (auto &cv : row) {
+        Pl.col.push_back(cv.first);
+        Pl.val.push_back(cv.second);
+      }
+      Pl.ptr[map[g] + 1] = (int)Pl.col.size();
+    }
+    for (int i = 0; i < nf; ++i) Pl.ptr[i + 1] = std::max(Pl.ptr[i + 1], Pl.ptr[i]);
+    R.push_back(csr_transpose(Pl));
+    A.push_back(csr_product(R.back(), csr_product(A.back(), Pl)));
+    P.push_back(std::move(Pl));
+    for (int a = 0; a < 3; ++a) n[a] = nc[a];
+  }
+  return hmg_upload(h, A, P, R, G, Ap);
+}
+
 // keys: cells with bitwise equal weights share one
 void cell_keys(const std::vector<double> &w6, int64_t ncells, std::vector<int> &key,
                std::vector<std::array<double, 6>> &keyw) {
@@ -2577,42 +2784,63 @@ rz_status setup_vec_relax(rz_problem *h, const std::vector<double> &al, const st
     vec_local_layout(space, 1, L1);
     SpRows basis1[6];
     vec_basis_matrices(h->t1, L1, basis1);
-    std::vector<double> A0((size_t)ncf * ncf, 0.0);
     std::vector<int> lg(L1.nloc);
-    for (int64_t c = 0; c < nc; ++c) {
-      const int cc[3] = {(int)(c % n[0]), (int)((c / n[0]) % n[1]), (int)(c / ((int64_t)n[0] * n[1]))};
-      for (int l = 0; l < L1.nloc; ++l) {
-        int X[3];
-        for (int a = 0; a < 3; ++a) X[a] = cc[a] + L1.crd[3 * l + a];
-        lg[l] = cmap[vec_index(off1, ext1, L1.comp[l], X)];
-      }
-      for (int k = 0; k < 6; ++k) {
-        const double w = h->coef[6 * c + k];
-        for (int r = 0; r < L1.nloc; ++r) {
-          if (lg[r] < 0) continue;
-          for (auto &ev : basis1[k][r])
-            if (lg[ev.first] >= 0) A0[(size_t)lg[r] * ncf + lg[ev.first]] += w * ev.second;
+    // the cells' entries in a fixed order (cell, weight, row, column) into per-row maps
+    auto for_entries = [&](auto &&add) {
+      for (int64_t c = 0; c < nc; ++c) {
+        const int cc[3] = {(int)(c % n[0]), (int)((c / n[0]) % n[1]), (int)(c / ((int64_t)n[0] * n[1]))};
+        for (int l = 0; l < L1.nloc; ++l) {
+          int X[3];
+          for (int a = 0; a < 3; ++a) X[a] = cc[a] + L1.crd[3 * l + a];
+          lg[l] = cmap[vec_index(off1, ext1, L1.comp[l], X)];
+        }
+        for (int k = 0; k < 6; ++k) {
+          const double w = h->coef[6 * c + k];
+          for (int r = 0; r < L1.nloc; ++r) {
+            if (lg[r] < 0) continue;
+            for (auto &ev : basis1[k][r])
+              if (lg[ev.first] >= 0) add(lg[r], lg[ev.first], w * ev.second);
+          }
         }
       }
+    };
+    if (h->opts.coarse == RZ_COARSE_HMG) {
+      std::vector<std::map<int, double>> rows(ncf);
+      for_entries([&](int r, int c, double v) { rows[r][c] += v; });
+      HostCsr A0;
+      A0.n = A0.m = ncf;
+      A0.ptr.assign(ncf + 1, 0);
+      for (int r = 0; r < ncf; ++r) {
+        for (auto &cv : rows[r]) {
+          A0.col.push_back(cv.first);
+          A0.val.push_back(cv.second);
+        }
+        A0.ptr[r + 1] = (int)A0.col.size();
+      }
+      std::vector<std::map<int, double>>().swap(rows);
+      if ((e = setup_hmg_vec(h, std::move(A0)))) return e;
+    } else {
+      std::vector<double> A0((size_t)ncf * ncf, 0.0);
+      for_entries([&](int r, int c, double v) { A0[(size_t)r * ncf + c] += v; });
+      if ((e = upload(h, &h->cinv64, A0))) return e;
+      std::vector<double>().swap(A0);
+      double *tmp = nullptr;
+      if (hipMalloc(&tmp, sizeof(double) * (size_t)ncf * ncf) != hipSuccess)
+        return fail(ctx, RZ_ERR_OOM, "coarse inverse workspace");
+      launch_sweep_inverse(ncf, h->cinv64, tmp, h->status, s);
+      const hipError_t se = hipStreamSynchronize(s);
+      hipFree(tmp);
+      if (se != hipSuccess) return fail(ctx, RZ_ERR_HIP, "coarse inverse failed");
+      int stv = 0;
+      HIPCALL(h, hipMemcpy(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost));
+      if (stv) return fail(ctx, RZ_ERR_SINGULAR, "coarse factorisation: non-positive pivot");
+      if (h->opts.precision != RZ_PREC_F64) {
+        if ((e = dalloc(h, &h->cinv32, (size_t)ncf * ncf))) return e;
+        launch_cast_d2f(h->cinv64, h->cinv32, (int64_t)ncf * ncf, s);
+      }
+      const size_t nt = ((size_t)ncf + 63) / 64;
+      if ((e = dalloc(h, &h->csym, nt * nt * 64))) return e;
     }
-    if ((e = upload(h, &h->cinv64, A0))) return e;
-    std::vector<double>().swap(A0);
-    double *tmp = nullptr;
-    if (hipMalloc(&tmp, sizeof(double) * (size_t)ncf * ncf) != hipSuccess)
-      return fail(ctx, RZ_ERR_OOM, "coarse inverse workspace");
-    launch_sweep_inverse(ncf, h->cinv64, tmp, h->status, s);
-    const hipError_t se = hipStreamSynchronize(s);
-    hipFree(tmp);
-    if (se != hipSuccess) return fail(ctx, RZ_ERR_HIP, "coarse inverse failed");
-    int stv = 0;
-    HIPCALL(h, hipMemcpy(&stv, h->status, sizeof(int), hipMemcpyDeviceToHost));
-    if (stv) return fail(ctx, RZ_ERR_SINGULAR, "coarse factorisation: non-positive pivot");
-    if (h->opts.precision != RZ_PREC_F64) {
-      if ((e = dalloc(h, &h->cinv32, (size_t)ncf * ncf))) return e;
-      launch_cast_d2f(h->cinv64, h->cinv32, (int64_t)ncf * ncf, s);
-    }
-    const size_t nt = ((size_t)ncf + 63) / 64;
-    if ((e = dalloc(h, &h->csym, nt * nt * 64))) return e;
     // prolongation (the embedding of the p = 1 space, per axis: hats on continuous
     // axes, the constant r_0 on broken ones) and restriction = its transpose
     std::vector<int> prow, pptr(1, 0), pcol;
@@ -3213,8 +3441,8 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
     return fail(ctx, RZ_ERR_ARG, "bad patch_solver");
   if (opts->norm != RZ_NORM_2 && opts->norm != RZ_NORM_NATURAL) return fail(ctx, RZ_ERR_ARG, "bad norm");
   if (opts->coarse != RZ_COARSE_DIRECT && opts->coarse != RZ_COARSE_HMG) return fail(ctx, RZ_ERR_ARG, "bad coarse");
-  if (opts->coarse == RZ_COARSE_HMG && opts->space != RZ_GRAD)
-    return fail(ctx, RZ_ERR_ARG, "the h-multigrid coarse solver is built for H(grad) only");
+  if (opts->coarse == RZ_COARSE_HMG && opts->space != RZ_GRAD && opts->decomposition == RZ_DECOMP_FULL)
+    return fail(ctx, RZ_ERR_ARG, "the h-multigrid coarse solver goes with the statically condensed relaxation");
   if (opts->decomposition != RZ_DECOMP_SC && opts->decomposition != RZ_DECOMP_FULL)
     return fail(ctx, RZ_ERR_ARG, "bad decomposition");
   if (opts->decomposition == RZ_DECOMP_FULL && opts->space == RZ_GRAD && opts->aux == RZ_AUX_PAPER_DIAG)
