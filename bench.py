@@ -241,28 +241,37 @@ def bench_multi_rhs(torch, rz, pb, nrhs, patch_ms_1, solve_ms_1, iters_1, reps=3
 
 def bench_hmg(torch, rz, ctx, steps=3, warmup=1):
     """The p = 1 solve of the p-multigrid cycle by geometric h-multigrid (one V(1,1)
-    cycle, point Jacobi, coarsest level dense) against the exact solve: iterations,
-    time per PCG solve and the coarse solver's share, on the C2 workload (Q_7 on 32^3,
-    log-uniform cell coefficients), on the same mesh with alpha = beta = 1, and on a
-    64^3 mesh (Q_3, alpha = beta = 1; 4 levels) where the exact solver's dense plane
-    blocks would take about 24 GB and minutes of setup, so only h-MG runs."""
+    cycle, point Jacobi, Hiptmair relaxation on the vector spaces, coarsest level
+    dense) against the exact solve: iterations, time per PCG solve and the coarse
+    solver's share.  H(grad): the C2 workload (Q_7 on 32^3, log-uniform cell
+    coefficients), the same mesh with alpha = beta = 1, and a 64^3 mesh (Q_3, alpha =
+    beta = 1; 4 levels) where the exact solver's dense plane blocks would take about
+    24 GB and minutes of setup, so only h-MG runs.  H(curl)/H(div): NCE_6 and NCF_6 on
+    16^3 (the C3 layout, alpha = beta = 1), and NCE_3 on 32^3, where the dense NCE_1
+    inverse would take 68 GB, so only h-MG runs."""
     import synth
     res = {}
-    cases = [("c2_q7_n32_loguniform", 32, 7, True, (rz.COARSE_DIRECT, rz.COARSE_HMG)),
-             ("q7_n32_const", 32, 7, False, (rz.COARSE_DIRECT, rz.COARSE_HMG)),
-             ("q3_n64_const", 64, 3, False, (rz.COARSE_HMG,))]
-    for name, n, p, logu, coarses in cases:
+    cases = [("c2_q7_n32_loguniform", "grad", 32, 7, True, (rz.COARSE_DIRECT, rz.COARSE_HMG)),
+             ("q7_n32_const", "grad", 32, 7, False, (rz.COARSE_DIRECT, rz.COARSE_HMG)),
+             ("q3_n64_const", "grad", 64, 3, False, (rz.COARSE_HMG,)),
+             ("c3_nce6_n16", "curl", 16, 6, False, (rz.COARSE_DIRECT, rz.COARSE_HMG)),
+             ("ncf6_n16", "div", 16, 6, False, (rz.COARSE_DIRECT, rz.COARSE_HMG)),
+             ("nce3_n32", "curl", 32, 3, False, (rz.COARSE_HMG,))]
+    for name, space, n, p, logu, coarses in cases:
         al, be = (synth.cell_coefficients(n ** 3, 1), synth.cell_coefficients(n ** 3, 2)) if logu else (1.0, 1.0)
-        bt = torch.as_tensor(synth.rhs_values((n * p + 1) ** 3, 0), device="cuda:0")
-        x = torch.zeros_like(bt)
-        row = {"ndofs": (n * p + 1) ** 3}
+        row = {}
+        bt = x = None
         for co in coarses:
             key = "hmg" if co == rz.COARSE_HMG else "direct"
             log(f"h-MG study: {name} {key}")
             t0 = time.perf_counter()
-            pb = rz.Problem(ctx, n, p, al, be, coarse=co)
+            pb = rz.Problem(ctx, n, p, al, be, space=space, coarse=co)
             torch.cuda.synchronize()
             setup = time.perf_counter() - t0
+            if bt is None:
+                bt = torch.as_tensor(synth.rhs_values(pb.ndofs, 0), device="cuda:0")
+                x = torch.zeros_like(bt)
+                row["ndofs"] = pb.ndofs
             ms, infos, kt = time_solves(torch, pb, bt, x, steps, warmup)
             r = {"setup_s": round(setup, 3), "pcg_ms": round(ms, 3), "iters": infos[-1].iters,
                  "rel_res": max(i.rel_res for i in infos),
