@@ -137,7 +137,14 @@ typedef struct {
                         * by IC on its pattern (RZ_PATCH_IC), both applied as dense     *
                         * W = L^{-1} (the chol / ICC columns of Table hgrad-iter);      *
                         * (2p-1)^3 rows per star, for small meshes and degrees          *
-                        * (RZ_ERR_ARG past 16 GiB of factors or about 5e11 host flops)  */
+                        * (RZ_ERR_ARG past 16 GiB of factors or about 5e11 host flops). *
+                        * H(curl)/H(div): RZ_DECOMP_SC (default) SC-PH; RZ_DECOMP_FULL   *
+                        * PAFW, the vertex stars of the k-forms without condensation;    *
+                        * RZ_DECOMP_SC_VERTEX SC-PAFW (Sec. 4.4), those stars restricted *
+                        * to the condensed interface, each solved exactly on the         *
+                        * assembled interface Schur complement (the PAFW and SC-PAFW     *
+                        * columns of Tables hcurl-iter / hdiv-iter; both with            *
+                        * RZ_PATCH_CHOLESKY, dense W = L^{-1} per star, small meshes)    */
   int32_t norm;        /* stopping rule of rz_solve / rz_solve_batched (FP64 and mixed  *
                         * protocols): RZ_NORM_2 (default) the true 2-norm residual      *
                         * <= rtol ||b||, confirmed by a residual from x; RZ_NORM_NATURAL *
@@ -161,8 +168,8 @@ typedef struct {
 /* Solvers of the p = 1 problem (rz_opts.coarse). */
 enum { RZ_COARSE_DIRECT = 0, RZ_COARSE_HMG = 1 };
 
-/* Decompositions of the H(grad) relaxation (rz_opts.decomposition). */
-enum { RZ_DECOMP_SC = 0, RZ_DECOMP_FULL = 1 };
+/* Decompositions of the relaxation (rz_opts.decomposition). */
+enum { RZ_DECOMP_SC = 0, RZ_DECOMP_FULL = 1, RZ_DECOMP_SC_VERTEX = 2 };
 
 /* Stopping rules (rz_opts.norm). */
 enum { RZ_NORM_2 = 0, RZ_NORM_NATURAL = 1 };

@@ -345,3 +345,24 @@ class PAFWRelaxVec:
             z[dofs] += scipy.linalg.solve_triangular(L.T, y, lower=False)
         z[self.dmask] = r[self.dmask]
         return z
+
+
+# ----------------------------------------------------------------------------------
+# SC-PAFW for H(curl) / H(div) (Sec. 4.4, eq. sc-asm-afw on the k-forms): the vertex
+# stars of the non-condensed PAFW restricted to the free interface DoFs, each solved
+# exactly on the interface Schur complement; no potential term (the vertex stars
+# already hold the kernel of the derivative).  The SC-PAFW column of Tables
+# hcurl-iter / hdiv-iter.
+# ----------------------------------------------------------------------------------
+class SCPAFWRelaxVec(SCRelaxPH):
+    """z = M^{-1} r for SC-PAFW: P_II solved exactly per cell, the interface by
+    sum_v R_v^T S_v^{-1} R_v over the vertex stars of the interface DoFs, then the
+    interior back-substitution; Dirichlet rows copy r."""
+
+    def __init__(self, lat: Lattice, P):
+        self.lat = lat
+        self.cond = cond = Condensed(lat, P)
+        self.potential = False
+        inner = interior_mask(lat)
+        self.patches = [(vid, d[~inner[d]]) for vid, d in vertex_star_patches_vec(lat) if (~inner[d]).any()]
+        self.local = PatchSolves(cond, self.patches)

@@ -244,6 +244,7 @@ struct rz_problem {
   // H(curl)/H(div) vertex stars (opts.decomposition): patches, their index lists
   // (nrf entries each), and per free DoF the positions of its star solutions
   int nvs = 0, nvfree = 0;
+  bool vs_sc = false;                       // vertex stars on the condensed interface (SC-PAFW)
   int *vs_idx = nullptr, *vs_rows = nullptr, *vs_ptr = nullptr, *vs_pos = nullptr;
   double *fzb64 = nullptr;
   float *fzb32 = nullptr;
@@ -497,6 +498,25 @@ const float *chol_w(rz_problem *h, const float *);
 template <typename T>
 rz_status relax_vec(rz_problem *h, const VecRelaxPtrs<T> &X, const T *r, T *z) {
   hipStream_t s = h->ctx->stream;
+  if (h->nvs && h->vs_sc) {  // SC-PAFW: condense, vertex stars on the interface, expand
+    {
+      Timed t(h, RZ_K_CONDENSE);
+      launch_vc_condense<T>(h->V, *X.vc, r, z, X.veb, s);
+      launch_list_gather<T>(h->nGam, h->gam, h->cg_ptr, h->cg_pos, X.veb, r, X.vrt, T(-1), s);
+    }
+    {
+      Timed t(h, RZ_K_PATCH);
+      T *zb = full_zb(h, (T *)nullptr);
+      launch_dense_patch_solve<T>(h->nvs, h->nrf, h->vs_idx, chol_w(h, (const T *)nullptr), X.vrt, zb, s);
+      launch_list_gather<T>(h->nvfree, h->vs_rows, h->vs_ptr, h->vs_pos, zb, (const T *)nullptr, z, T(1), s);
+    }
+    {
+      Timed t(h, RZ_K_EXPAND);
+      launch_vc_expand<T>(h->V, *X.vc, z, s);
+      launch_list_copy<T>(h->nDir, h->dlist, r, z, s);
+    }
+    return RZ_OK;
+  }
   if (h->nvs) {  // vertex stars without static condensation (PAFW)
     Timed t(h, RZ_K_PATCH);
     T *zb = full_zb(h, (T *)nullptr);
@@ -2053,12 +2073,27 @@ rz_status setup_full_stars(rz_problem *h) {
 // threads: its DoFs ascending, P_v assembled dense from the cells' six weighted basis
 // matrices, exact Cholesky and W = L^{-1}; the stars padded to one size with identity
 // rows; per free DoF the positions of its star solutions, in ascending star order.
-rz_status setup_vertex_stars_vec(rz_problem *h) {
+void cell_keys(const std::vector<double> &w6, int64_t ncells, std::vector<int> &key,
+               std::vector<std::array<double, 6>> &keyw);
+bool condense_keys(const VecLocal &L, const SpRows basis[6], const std::vector<std::array<double, 6>> &keyw,
+                   bool want_S, std::vector<CellCondensed> &conds, std::string &err);
+
+rz_status setup_vertex_stars_vec(rz_problem *h, bool sc) {
   const int p = h->p, space = h->space == RZ_CURL ? 1 : 2;
   VecLocal VL;
   vec_local_layout(space, p, VL);
   SpRows basis[6];
   vec_basis_matrices(h->t, VL, basis);
+  // SC-PAFW: the star matrices are assembled from the cells' interface Schur
+  // complements (the interior DoFs of a cell belong to that cell alone)
+  std::vector<int> key;
+  std::vector<std::array<double, 6>> keyw;
+  std::vector<CellCondensed> conds;
+  if (sc) {
+    std::string err;
+    cell_keys(h->coef, h->ncells, key, keyw);
+    if (!condense_keys(VL, basis, keyw, true, conds, err)) return fail(h->ctx, RZ_ERR_BREAKDOWN, err);
+  }
   const VecDev &V = h->V;
   const int nc[3] = {h->nx, h->ny, h->nz};
   const int nvx = nc[0] + 1, nvy = nc[1] + 1, nvz = nc[2] + 1;
@@ -2099,7 +2134,7 @@ rz_status setup_vertex_stars_vec(rz_problem *h) {
           for (int l = 0; l < VL.nloc; ++l) {
             int m, C[3];
             const int64_t g = global(cx, cy, cz, l, m, C);
-            if (!dirm[g] && in_star(m, C, v)) S.push_back(g);
+            if (!dirm[g] && in_star(m, C, v) && !(sc && VL.interior[l])) S.push_back(g);
           }
         }
     std::sort(S.begin(), S.end());
@@ -2114,7 +2149,8 @@ rz_status setup_vertex_stars_vec(rz_problem *h) {
     }
   const size_t np = live.size(), tri = (size_t)nr * (nr + 1) / 2;
   if ((double)np * tri * 12.0 > 16.0 * (1ull << 30) || (double)np * nr * nr * (double)nr > 5e11)
-    return fail(h->ctx, RZ_ERR_ARG, "RZ_DECOMP_FULL: the dense vertex-star factors are for small meshes and degrees");
+    return fail(h->ctx, RZ_ERR_ARG, "RZ_DECOMP_FULL / RZ_DECOMP_SC_VERTEX: the dense vertex-star factors are for small "
+                                    "meshes and degrees");
   std::vector<double> W;
   const long bad = factor_slots(np, nr, nullptr, [&](size_t k, std::vector<double> &M) {
     const size_t vid = live[k];
@@ -2133,7 +2169,21 @@ rz_status setup_vertex_stars_vec(rz_problem *h) {
             const auto it = std::lower_bound(S.begin(), S.end(), g);
             pos[l] = (it != S.end() && *it == g) ? (int)(it - S.begin()) : -1;
           }
-          const double *w = &h->coef[6 * ((size_t)cx + (size_t)nc[0] * (cy + (size_t)nc[1] * cz))];
+          const size_t cell = (size_t)cx + (size_t)nc[0] * (cy + (size_t)nc[1] * cz);
+          if (sc) {
+            const CellCondensed &cd = conds[key[cell]];
+            const int nG = (int)cd.G.size();
+            for (int i = 0; i < nG; ++i) {
+              const int pi = pos[cd.G[i]];
+              if (pi < 0) continue;
+              for (int j = 0; j < nG; ++j) {
+                const int pj = pos[cd.G[j]];
+                if (pj >= 0) M[(size_t)pi * nr + pj] += cd.S[(size_t)i * nG + j];
+              }
+            }
+            continue;
+          }
+          const double *w = &h->coef[6 * cell];
           for (int kb = 0; kb < 6; ++kb)
             for (int l1 = 0; l1 < VL.nloc; ++l1) {
               if (pos[l1] < 0) continue;
@@ -2169,6 +2219,7 @@ rz_status setup_vertex_stars_vec(rz_problem *h) {
       (e = upload(h, &h->vs_pos, pos)) || (e = dalloc(h, &h->fzb64, np * nr)) || (e = dalloc(h, &h->fzb32, np * nr)))
     return e;
   h->nvs = (int)np;
+  h->vs_sc = sc;
   h->nvfree = (int)rows.size();
   h->nrf = nr;
   return upload_patch_inverse(h, W);
@@ -3012,7 +3063,9 @@ rz_status setup_vector(rz_problem *h, const rz_coef *cf, rz_problem **out) {
   if (hipMemsetAsync(h->status, 0, sizeof(int), s) != hipSuccess) return bail(fail(ctx, RZ_ERR_HIP, "memset"));
   // the relaxation, coarse problem and transfers of the solver
   if ((e = setup_vec_relax(h, alc, bec, hsc)) || (e = alloc_krylov(h))) return bail(e);
-  if (h->opts.decomposition == RZ_DECOMP_FULL && (e = setup_vertex_stars_vec(h))) return bail(e);
+  if ((h->opts.decomposition == RZ_DECOMP_FULL || h->opts.decomposition == RZ_DECOMP_SC_VERTEX) &&
+      (e = setup_vertex_stars_vec(h, h->opts.decomposition == RZ_DECOMP_SC_VERTEX)))
+    return bail(e);
   if (h->opts.omega > 0) {
     h->omega = h->opts.omega;
   } else {
@@ -3443,14 +3496,22 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
   if (opts->coarse != RZ_COARSE_DIRECT && opts->coarse != RZ_COARSE_HMG) return fail(ctx, RZ_ERR_ARG, "bad coarse");
   if (opts->coarse == RZ_COARSE_HMG && opts->space != RZ_GRAD && opts->decomposition == RZ_DECOMP_FULL)
     return fail(ctx, RZ_ERR_ARG, "the h-multigrid coarse solver goes with the statically condensed relaxation");
-  if (opts->decomposition != RZ_DECOMP_SC && opts->decomposition != RZ_DECOMP_FULL)
+  if (opts->decomposition != RZ_DECOMP_SC && opts->decomposition != RZ_DECOMP_FULL &&
+      opts->decomposition != RZ_DECOMP_SC_VERTEX)
     return fail(ctx, RZ_ERR_ARG, "bad decomposition");
+  if (opts->decomposition == RZ_DECOMP_SC_VERTEX &&
+      (opts->space == RZ_GRAD || opts->patch_solver != RZ_PATCH_CHOLESKY))
+    return fail(ctx, RZ_ERR_ARG,
+                "RZ_DECOMP_SC_VERTEX: H(curl)/H(div) with exact vertex-star solves (RZ_PATCH_CHOLESKY); for H(grad) "
+                "RZ_DECOMP_SC is already the condensed vertex-star decomposition");
   if (opts->decomposition == RZ_DECOMP_FULL && opts->space == RZ_GRAD && opts->aux == RZ_AUX_PAPER_DIAG)
     return fail(ctx, RZ_ERR_ARG, "RZ_DECOMP_FULL: H(grad) with the separable auxiliary only");
   if (opts->decomposition == RZ_DECOMP_FULL && opts->space != RZ_GRAD && opts->patch_solver != RZ_PATCH_CHOLESKY)
     return fail(ctx, RZ_ERR_ARG, "RZ_DECOMP_FULL on H(curl)/H(div): exact vertex-star solves (RZ_PATCH_CHOLESKY) only");
-  if (opts->patch_solver == RZ_PATCH_CHOLESKY && opts->space != RZ_GRAD && opts->decomposition != RZ_DECOMP_FULL)
-    return fail(ctx, RZ_ERR_ARG, "RZ_PATCH_CHOLESKY: H(grad) vertex stars, or the H(curl)/H(div) full vertex stars");
+  if (opts->patch_solver == RZ_PATCH_CHOLESKY && opts->space != RZ_GRAD && opts->decomposition == RZ_DECOMP_SC)
+    return fail(ctx, RZ_ERR_ARG,
+                "RZ_PATCH_CHOLESKY: H(grad) vertex stars, or the H(curl)/H(div) vertex stars (RZ_DECOMP_FULL, "
+                "RZ_DECOMP_SC_VERTEX)");
   rz_problem *h = new rz_problem();
   h->ctx = ctx;
   h->opts = *opts;

@@ -290,3 +290,82 @@ def test_vertex_stars_vec_solve(rz, ctx, space):
         print(f"  {space}: {info.iters} iterations", flush=True)
     finally:
         pb.close()
+
+
+VEC_SC = [("curl", (2, 2, 2), 1), ("curl", (3, 2, 2), 2), ("curl", (2, 2, 2), 3), ("div", (2, 2, 3), 2),
+          ("div", (2, 2, 2), 3), ("curl", (3, 3, 3), 4)]
+
+
+@pytest.mark.parametrize("space,n,p", VEC_SC)
+def test_sc_vertex_stars_vec_relax_parity(rz, ctx, space, n, p):
+    """H(curl)/H(div) SC-PAFW (RZ_DECOMP_SC_VERTEX: the vertex stars on the condensed
+    interface, exact solves on the assembled Schur complement) against the oracle's
+    SCPAFWRelaxVec."""
+    from oracle import hiptmair as hp
+    print(f"SC vertex stars {space} n={n} p={p}", flush=True)
+    nc = int(np.prod(n))
+    al = synth.cell_coefficients(nc, 3, 0.5, 2.0)
+    be = synth.cell_coefficients(nc, 4, 0.5, 2.0)
+    lat = Lattice(Mesh(*n), space, p)
+    R = hp.SCPAFWRelaxVec(lat, asm.cartesian_operator(lat, al, be))
+    pb = rz.Problem(ctx, n, p, al, be, space=space, omega=0.3, decomposition=rz.DECOMP_SC_VERTEX,
+                    patch_solver=rz.PATCH_CHOLESKY)
+    try:
+        r = np.where(lat.dirichlet_mask(), 0.0, synth.uniform_pm1(17, lat.ndofs))
+        z_ref = R.apply(r)
+        z = torch.empty(pb.ndofs, dtype=torch.float64, device="cuda:0")
+        pb.relax(T(r), z)
+        assert rel(H(z), z_ref) < 1e-11
+        z32 = torch.empty(pb.ndofs, dtype=torch.float32, device="cuda:0")
+        pb.relax(T(r, torch.float32), z32, rz.F32)
+        assert rel(H(z32), z_ref) < 1e-4
+    finally:
+        pb.close()
+
+
+@pytest.mark.parametrize("space", ["curl", "div"])
+@pytest.mark.parametrize("beta", [1.0, 1e-2])
+def test_sc_vertex_stars_vec_solve_iterations(rz, ctx, space, beta):
+    """SC-PAFW on 6^3 cells, p = 3, alpha = 1 (the natural-norm criterion of the
+    tables): the iteration count is the oracle's within one (oracle: 12 / 12 for
+    H(curl), 10 / 9 for H(div) at beta = 1 / 1e-2), with the exact coarse solve and
+    within two with the h-multigrid one.  At beta <= 1e-4 the condensed vertex-star
+    Schur complements have near-kernel eigenvalues at the rounding level of the
+    condensation, and the count depends on rounding order (relative noise of 1e-5 in
+    the oracle's relaxation alone turns its 8 iterations at beta = 1e-8 into 44), so
+    no count is compared there."""
+    from oracle import hiptmair as hp
+    print(f"SC vertex stars solve {space} beta={beta}", flush=True)
+    n, p = (6, 6, 6), 3
+    lat, latc = Lattice(Mesh(*n), space, p), Lattice(Mesh(*n), space, 1)
+    Araw = asm.cartesian_operator(lat, 1.0, beta)
+    A = asm.with_dirichlet(lat, Araw)
+    R = hp.SCPAFWRelaxVec(lat, Araw)
+    Pr = pmg.prolongation(lat, latc)
+    cs = pmg.CoarseSolver(latc, asm.with_dirichlet(latc, asm.cartesian_operator(latc, 1.0, beta)))
+    mask = lat.dirichlet_mask()
+    v0 = np.where(mask, 0.0, synth.uniform_pm1(99, lat.ndofs))
+    om = pmg.omega_from_lambda(pmg.lanczos_lambda_max(A, lambda r: np.where(mask, 0.0, R.apply(r)), v0))
+    b = np.where(mask, 0.0, synth.rhs_values(lat.ndofs, 0))
+    _, it_ref, _ = pmg.pcg(A, b, pmg.VCycle(lat, A, R, Pr, cs, om), norm="natural")
+    for coarse in (rz.COARSE_DIRECT, rz.COARSE_HMG):
+        pb = rz.Problem(ctx, n, p, 1.0, beta, space=space, decomposition=rz.DECOMP_SC_VERTEX,
+                        patch_solver=rz.PATCH_CHOLESKY, norm=rz.NORM_NATURAL, coarse=coarse)
+        try:
+            if coarse == rz.COARSE_DIRECT:
+                assert abs(pb.omega() - om) < 1e-6 * om
+            x = torch.zeros(pb.ndofs, dtype=torch.float64, device="cuda:0")
+            info = pb.solve(T(b), x)
+            print(f"  {space} beta={beta} coarse={coarse}: {info.iters_natural} iterations (oracle {it_ref})",
+                  flush=True)
+            assert abs(info.iters_natural - it_ref) <= (1 if coarse == rz.COARSE_DIRECT else 2), \
+                (info.iters_natural, it_ref)
+        finally:
+            pb.close()
+
+
+def test_sc_vertex_stars_rejections(rz, ctx):
+    with pytest.raises(rz.RzError):   # H(grad): RZ_DECOMP_SC is already the condensed vertex stars
+        rz.Problem(ctx, 2, 3, 1.0, 1.0, decomposition=rz.DECOMP_SC_VERTEX, patch_solver=rz.PATCH_CHOLESKY)
+    with pytest.raises(rz.RzError):   # exact star solves only
+        rz.Problem(ctx, 2, 3, 1.0, 1.0, space="curl", decomposition=rz.DECOMP_SC_VERTEX)

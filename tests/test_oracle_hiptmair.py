@@ -261,3 +261,39 @@ def test_pafw_vec_single_star_exact_and_spd(space):
     b = np.where(lat.dirichlet_mask(), 0.0, np.random.default_rng(6).standard_normal(lat.ndofs))
     x = spla.spsolve(A.tocsc(), b)
     assert np.abs(R.apply(b) - x).max() < 1e-11 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("space", ["curl", "div"])
+def test_sc_pafw_one_cell_is_eight_exact_solves(space):
+    # one cell, no Dirichlet face: each of the 8 vertex stars holds every interface
+    # DoF, so the interface part of SC-PAFW is 8 S^{-1} rt, i.e. 8 times the
+    # interface values of the exact solve A^{-1} r (a dense solve)
+    lat = Lattice(Mesh(1, 1, 1, dirichlet=0), space, 3)
+    A = asm.cartesian_operator(lat, 1.7, 0.6)
+    R = hp.SCPAFWRelaxVec(lat, A)
+    assert len(R.patches) == 8
+    r = synth.uniform_pm1(7, lat.ndofs)
+    z = R.apply(r)
+    x = np.linalg.solve(A.toarray(), r)
+    G = R.cond.G
+    assert np.abs(z[G] - 8.0 * x[G]).max() < 1e-10 * np.abs(x[G]).max()
+    # the interior follows from the interface by the exact back-substitution
+    I = R.cond.I
+    zI = np.linalg.solve(A.toarray()[np.ix_(I, I)], r[I] - A.toarray()[np.ix_(I, G)] @ z[G])
+    assert np.abs(z[I] - zI).max() < 1e-10 * np.abs(zI).max()
+
+
+@pytest.mark.parametrize("space", ["curl", "div"])
+def test_sc_pafw_spd_and_stars_on_the_interface(space):
+    lat = Lattice(Mesh(2, 2, 2), space, 2)
+    nc = 8
+    al, be = synth.cell_coefficients(nc, 1), synth.cell_coefficients(nc, 2)
+    A = asm.with_dirichlet(lat, asm.cartesian_operator(lat, al, be))
+    R = hp.SCPAFWRelaxVec(lat, asm.cartesian_operator(lat, al, be))
+    inner = hp.interior_mask(lat)
+    for _, d in R.patches:
+        assert not inner[d].any()
+    free = np.where(~lat.dirichlet_mask())[0]
+    M = np.column_stack([R.apply(np.eye(lat.ndofs)[k])[free] for k in free])
+    assert np.abs(M - M.T).max() < 1e-10 * np.abs(M).max()
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
