@@ -163,6 +163,11 @@ typedef struct {
                         * free vertices, else RZ_ERR_ARG).  The cycle is symmetric       *
                         * positive definite, so CG stays valid; iteration counts may     *
                         * grow slightly against the exact solve.                         */
+  int32_t lanczos_steps; /* preconditioned CG steps of the Lanczos estimate behind the   *
+                        * default damping (omega = 0); 0 = 10, at most 200.  More steps  *
+                        * for relaxations whose spectrum has an outlying top (SC-PAFW at *
+                        * small beta: 10 steps underestimate lambda_max by 30 %, and the *
+                        * V(1,1) cycle then loses definiteness)                          */
 } rz_opts;
 
 /* Solvers of the p = 1 problem (rz_opts.coarse). */

@@ -318,7 +318,8 @@ def pcg(A, b, M, rtol=1e-8, maxit=500, norm="l2"):
     norm="l2": stop when the 2-norm of the residual has dropped by rtol (the true
     residual is checked at exit); norm="natural": stop when the natural norm
     (r^T M^{-1} r)^{1/2} has dropped by rtol, the criterion of the paper's
-    experiments (Sec. 5.1)."""
+    experiments (Sec. 5.1).  CG needs a positive definite preconditioner: a negative
+    r^T M^{-1} r is a breakdown, reported as iterations = -1."""
     if norm == "natural":
         return _pcg_natural(A, b, M, rtol, maxit)
     A = sp.csr_matrix(A)
@@ -346,6 +347,8 @@ def pcg(A, b, M, rtol=1e-8, maxit=500, norm="l2"):
             r = rtrue
         z = M(r)
         rz_new = r @ z
+        if rz_new < 0:          # breakdown: M is not positive definite
+            return x, -1, hist
         p = z + (rz_new / rz) * p
         rz = rz_new
     return x, it, hist
@@ -358,6 +361,8 @@ def _pcg_natural(A, b, M, rtol, maxit):
     hist = [np.linalg.norm(r)]
     z = M(r)
     rz = r @ z
+    if rz < 0:
+        return x, -1, hist
     if not rz > 0:
         return x, 0, hist
     tol = rtol * np.sqrt(rz)
@@ -372,7 +377,9 @@ def _pcg_natural(A, b, M, rtol, maxit):
         hist.append(np.linalg.norm(r))
         z = M(r)
         rz_new = r @ z
-        if np.sqrt(max(rz_new, 0.0)) <= tol:
+        if rz_new < 0:          # breakdown: M is not positive definite
+            return x, -1, hist
+        if np.sqrt(rz_new) <= tol:
             break
         p = z + (rz_new / rz) * p
         rz = rz_new

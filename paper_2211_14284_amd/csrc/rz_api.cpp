@@ -1229,8 +1229,9 @@ rz_status autotune_patch_solve(rz_problem *h, const T *f, T *rt, T *zb, int whic
   return RZ_OK;
 }
 
-// 10 preconditioned CG steps on A x = v0 with M = the FP64 fine relaxation (for every
-// precision protocol, so the damping does not depend on it); Lanczos estimate
+// rz_opts.lanczos_steps (default 10) preconditioned CG steps on A x = v0 with M = the
+// FP64 fine relaxation (for every precision protocol, so the damping does not depend
+// on it); Lanczos estimate
 rz_status estimate_lambda(rz_problem *h, double *lam_out) {
   hipStream_t s = h->ctx->stream;
   const int64_t n = h->ndofs;
@@ -1257,7 +1258,8 @@ rz_status estimate_lambda(rz_problem *h, double *lam_out) {
     if (e) return e;
   }
   std::vector<double> al, be;
-  for (int it = 0; it < 10; ++it) {
+  const int steps = h->opts.lanczos_steps > 0 ? h->opts.lanczos_steps : 10;
+  for (int it = 0; it < steps; ++it) {
     do_apply64(h, h->kp, h->kAp);
     double pAp;
     const double *xs[1] = {h->kp}, *ys[1] = {h->kAp};
@@ -3197,6 +3199,9 @@ void block_decide(rz_problem *h, int i, BlockRun::Rhs &R) {
       if (!(pAp > 0)) {
         R.result = fail(h->ctx, RZ_ERR_BREAKDOWN, "CG breakdown: p.Ap <= 0");
         R.next = BlockRun::FINAL;
+      } else if (rzv < 0) {  // CG needs a positive definite preconditioner
+        R.result = fail(h->ctx, RZ_ERR_BREAKDOWN, "CG breakdown: r.Mr < 0 (the preconditioner is not positive definite)");
+        R.next = BlockRun::FINAL;
       } else if (h->opts.norm == RZ_NORM_NATURAL && R.it_natural >= 0) {  // the paper's criterion
         R.result = RZ_OK;
         R.next = BlockRun::FINAL;
@@ -3494,6 +3499,7 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
     return fail(ctx, RZ_ERR_ARG, "bad patch_solver");
   if (opts->norm != RZ_NORM_2 && opts->norm != RZ_NORM_NATURAL) return fail(ctx, RZ_ERR_ARG, "bad norm");
   if (opts->coarse != RZ_COARSE_DIRECT && opts->coarse != RZ_COARSE_HMG) return fail(ctx, RZ_ERR_ARG, "bad coarse");
+  if (opts->lanczos_steps < 0 || opts->lanczos_steps > 200) return fail(ctx, RZ_ERR_ARG, "bad lanczos_steps");
   if (opts->coarse == RZ_COARSE_HMG && opts->space != RZ_GRAD && opts->decomposition == RZ_DECOMP_FULL)
     return fail(ctx, RZ_ERR_ARG, "the h-multigrid coarse solver goes with the statically condensed relaxation");
   if (opts->decomposition != RZ_DECOMP_SC && opts->decomposition != RZ_DECOMP_FULL &&

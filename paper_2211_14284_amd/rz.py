@@ -59,7 +59,8 @@ class Opts(ctypes.Structure):
                 ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double), ("omega", ctypes.c_double),
                 ("lanczos_seed", ctypes.c_uint64), ("hdiv_eps", ctypes.c_double), ("aux", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("patch_solver", ctypes.c_int32),
-                ("decomposition", ctypes.c_int32), ("norm", ctypes.c_int32), ("coarse", ctypes.c_int32)]
+                ("decomposition", ctypes.c_int32), ("norm", ctypes.c_int32), ("coarse", ctypes.c_int32),
+                ("lanczos_steps", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

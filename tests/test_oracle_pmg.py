@@ -150,3 +150,14 @@ def test_jacobi_weight_bounds_the_spectrum_on_anisotropic_cells():
         assert lam.min() > 0 and w * lam.max() <= pmg.JACOBI_C + 1e-12
         if space == "grad":
             assert (2.0 / 3.0) * lam.max() > 2.0
+
+
+def test_pcg_reports_breakdown_of_an_indefinite_preconditioner():
+    # r^T M r < 0 is a CG breakdown, never a converged natural norm
+    A = sp.diags(np.arange(1.0, 11.0)).tocsr()
+    b = np.ones(10)
+    for norm in ("natural", "l2"):
+        _, it, _ = pmg.pcg(A, b, lambda r: -r, norm=norm)
+        assert it == -1
+    _, it, _ = pmg.pcg(A, b, lambda r: r / A.diagonal(), norm="natural")
+    assert it >= 1
