@@ -143,6 +143,26 @@ def test_quad_coarse_parity(rz, ctx):
     assert rel(H(xc), ref.coarse().solve(rc)) < 1e-12
 
 
+def test_quad_hmg_coarse_parity(rz, ctx):
+    """The h-multigrid coarse solver (rz_opts.coarse = RZ_COARSE_HMG) on trilinear cells
+    with sampled coefficients: level 0 is the quadrature Q_1 operator, the hierarchy
+    and one V(1,1) cycle equal the oracle's HMGCoarse on the same operator to 1e-12."""
+    n = (16, 8, 8)
+    ref = Ref(n, 2, perturbed(n))
+    pb = rz.Problem(ctx, n, 2, ref.a, ref.b, vertices=ref.m.vertices, omega=0.3, coarse=rz.COARSE_HMG)
+    try:
+        A0 = asm.with_dirichlet(ref.latc, asm.quadrature_operator(ref.latc, ref.a, ref.b, default_points(1),
+                                                                 kind="gll"))
+        hm = pmg.HMGCoarse(ref.latc, A0, min_free=512)
+        assert pb.hmg_levels() == [a.shape[0] for a in hm.A] == [735, 63]
+        rc = np.where(ref.latc.dirichlet_mask(), 0.0, synth.uniform_pm1(31, ref.latc.ndofs))
+        xc = torch.empty(pb.ncoarse, dtype=torch.float64, device="cuda:0")
+        pb.coarse_solve(T(rc), xc)
+        assert rel(H(xc), hm.solve(rc)) < 1e-12
+    finally:
+        pb.close()
+
+
 @pytest.mark.parametrize("n,p,prec", [((3, 3, 3), 4, 0), ((3, 3, 3), 4, 1), ((3, 2, 2), 5, 0)])
 def test_quad_solve_parity(rz, ctx, n, p, prec):
     ref = Ref(n, p, perturbed(n))
