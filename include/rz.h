@@ -164,10 +164,10 @@ typedef struct {
                         * positive definite, so CG stays valid; iteration counts may     *
                         * grow slightly against the exact solve.                         */
   int32_t lanczos_steps; /* preconditioned CG steps of the Lanczos estimate behind the   *
-                        * default damping (omega = 0); 0 = 10, at most 200.  More steps  *
-                        * for relaxations whose spectrum has an outlying top (SC-PAFW at *
-                        * small beta: 10 steps underestimate lambda_max by 30 %, and the *
-                        * V(1,1) cycle then loses definiteness)                          */
+                        * default damping (omega = 0), at most 200; 0 = 10, or 40 with   *
+                        * RZ_DECOMP_SC_VERTEX, whose spectrum has an outlying top at     *
+                        * small beta (10 steps underestimate lambda_max by 30 %, and the *
+                        * V(1,1) cycle then loses definiteness: CG reports the breakdown)*/
 } rz_opts;
 
 /* Solvers of the p = 1 problem (rz_opts.coarse). */

@@ -350,7 +350,7 @@ def test_sc_vertex_stars_vec_solve_iterations(rz, ctx, space, beta):
     _, it_ref, _ = pmg.pcg(A, b, pmg.VCycle(lat, A, R, Pr, cs, om), norm="natural")
     for coarse in (rz.COARSE_DIRECT, rz.COARSE_HMG):
         pb = rz.Problem(ctx, n, p, 1.0, beta, space=space, decomposition=rz.DECOMP_SC_VERTEX,
-                        patch_solver=rz.PATCH_CHOLESKY, norm=rz.NORM_NATURAL, coarse=coarse)
+                        patch_solver=rz.PATCH_CHOLESKY, norm=rz.NORM_NATURAL, coarse=coarse, lanczos_steps=10)
         try:
             if coarse == rz.COARSE_DIRECT:
                 assert abs(pb.omega() - om) < 1e-6 * om
@@ -396,12 +396,19 @@ def test_sc_vertex_stars_vec_table_setting(rz, ctx, space):
         info = pb.solve(T(b), x)
         print(f"  {space}: {info.iters_natural} iterations (oracle {it_ref})", flush=True)
         assert abs(info.iters_natural - it_ref) <= 1, (info.iters_natural, it_ref)
+        om40 = pb.omega()
     finally:
         pb.close()
+    pd = rz.Problem(ctx, n, p, 1.0, 1e-8, space=space, decomposition=rz.DECOMP_SC_VERTEX,
+                    patch_solver=rz.PATCH_CHOLESKY, norm=rz.NORM_NATURAL)
+    try:       # 40 steps are this decomposition's default
+        assert pd.omega() == om40
+    finally:
+        pd.close()
 
 
 def test_sc_vertex_stars_default_damping_breakdown(rz, ctx):
-    """H(curl) SC-PAFW at beta = 1e-4 with the default 10-step estimate: the oracle's CG
+    """H(curl) SC-PAFW at beta = 1e-4 with a 10-step damping estimate: the oracle's CG
     meets r^T M r < 0 at its sixth iteration; the library reports the breakdown instead
     of iterating on."""
     print("SC vertex stars breakdown", flush=True)
@@ -409,7 +416,7 @@ def test_sc_vertex_stars_default_damping_breakdown(rz, ctx):
     lat = Lattice(Mesh(*n), "curl", p)
     b = np.where(lat.dirichlet_mask(), 0.0, synth.rhs_values(lat.ndofs, 0))
     pb = rz.Problem(ctx, n, p, 1.0, 1e-4, space="curl", decomposition=rz.DECOMP_SC_VERTEX,
-                    patch_solver=rz.PATCH_CHOLESKY, norm=rz.NORM_NATURAL)
+                    patch_solver=rz.PATCH_CHOLESKY, norm=rz.NORM_NATURAL, lanczos_steps=10)
     try:
         x = torch.zeros(pb.ndofs, dtype=torch.float64, device="cuda:0")
         info = pb.solve(T(b), x, check=False)
