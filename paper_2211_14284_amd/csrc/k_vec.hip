@@ -227,7 +227,8 @@ __device__ __forceinline__ void curl_out_line_int(const T *Uc, const T *Gc, cons
 template <int P, typename T, int CPB, bool CURL>
 __global__ void __launch_bounds__(256) k_apply_vec_p(VecDev V, const T *__restrict__ coef, const T *__restrict__ Bg,
                                                       const T *__restrict__ Dg, const T *__restrict__ x,
-                                                      T *__restrict__ y, T *__restrict__ ebuf, long ncells) {
+                                                      T *__restrict__ y, T *__restrict__ ebuf, long ncells,
+                                                      const T *__restrict__ bsub) {
   using S = VT<P, CURL>;
   constexpr int n1 = P + 1, TS = S::TS, TF = S::TF, NF = S::NF;
   extern __shared__ unsigned char vsm[];
@@ -303,11 +304,12 @@ __global__ void __launch_bounds__(256) k_apply_vec_p(VecDev V, const T *__restri
     // the line's points: l[m] = q, the other two axes (in increasing order) la, lb
     int cl, m, la, lb;
     T out[n1];
+    bool inner = false;  // curl: both other coordinates inside the cell (no shared entry)
     if constexpr (CURL) {
       // the (P-1)^2 lines of a component with both other coordinates inside the
       // cell first (cheap, and whole wavefronts of them), then the 4P others
       constexpr int NI = (P - 1) * (P - 1), NE = 4 * P;
-      const bool inner = t < 3 * NI * nc;
+      inner = t < 3 * NI * nc;
       if (inner) {
         cl = t / (3 * NI);
         const int r = t % (3 * NI), w = r % NI;
@@ -358,16 +360,25 @@ __global__ void __launch_bounds__(256) k_apply_vec_p(VecDev V, const T *__restri
     const long gbase = sO[cl][4 + m] + l[0] + V.ext[m][0] * (l[1] + V.ext[m][1] * l[2]);
     const long gstr = m == 0 ? 1 : (m == 1 ? (long)V.ext[m][0] : (long)V.ext[m][0] * V.ext[m][1]);
     const long n = V.off[3];
+    // with bsub (the residual b - A x): an entry held by this cell alone is complete
+    // here and stores b - value; shared entries store their partial sums, and the
+    // gather subtracts their totals
     if constexpr (CURL) {
       // continuous along the two other axes: slot (la == P) + 2 (lb == P) of every point
       const int sl = (la == P) + 2 * (lb == P);
       T *dst = sl == 0 ? y + gbase : ebuf + (sl - 1) * n + gbase;
+      if (bsub && inner) {
 #pragma unroll
-      for (int q = 0; q < P; ++q) dst[q * gstr] = out[q];
+        for (int q = 0; q < P; ++q) y[gbase + q * gstr] = bsub[gbase + q * gstr] - out[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < P; ++q) dst[q * gstr] = out[q];
+      }
     } else {
       // continuous along m only: the end q = P of the line goes to slot 1
 #pragma unroll
-      for (int q = 0; q < P; ++q) y[gbase + q * gstr] = out[q];
+      for (int q = 0; q < P; ++q)
+        y[gbase + q * gstr] = (bsub && q > 0) ? bsub[gbase + q * gstr] - out[q] : out[q];
       ebuf[gbase + P * gstr] = out[P];
     }
   }
@@ -380,13 +391,14 @@ __global__ void __launch_bounds__(256) k_apply_vec_p(VecDev V, const T *__restri
 // contribution in y, the others in ebuf[(s - 1) n + g].  The gather sums the
 // existing contributions in the order of s; Dirichlet rows copy x.  One block per
 // (GL consecutive x lines of the components, chunk of 128 entries), one thread per
-// entry of each of its lines, all loads issued before the stores.
+// entry of each of its lines, all loads issued before the stores.  With bsub the
+// stores are b - sum (b - x on Dirichlet rows).
 constexpr int GL = 4;
 
 template <int P, typename T, bool CURL>
 __global__ void __launch_bounds__(128) k_apply_vec_gather(VecDev V, const T *__restrict__ x,
                                                           const T *__restrict__ ebuf, T *__restrict__ y,
-                                                          int chunks) {
+                                                          int chunks, const T *__restrict__ bsub) {
   using S = VT<P, CURL>;
   int line = (blockIdx.x / chunks) * GL;
   const int ch = blockIdx.x % chunks, C0 = ch * 128 + (int)threadIdx.x;
@@ -448,14 +460,14 @@ __global__ void __launch_bounds__(128) k_apply_vec_gather(VecDev V, const T *__r
   }
 #pragma unroll
   for (int q = 0; q < GL; ++q)
-    if (what[q]) y[g[q]] = acc[q];
+    if (what[q]) y[g[q]] = bsub ? bsub[g[q]] - acc[q] : acc[q];
 }
 
 }  // namespace
 
 template <int P, typename T, bool CURL>
 void apply_vec_pc(const VecDev &V, const T *coef, const T *B, const T *D, const T *x, T *y, T *ebuf, long nc,
-                  hipStream_t s) {
+                  hipStream_t s, const T *bsub) {
   using S = VT<P, CURL>;
   constexpr size_t per_cell = (3 * (size_t)S::TS + (size_t)S::NF * S::TF + 6) * sizeof(T) + 8 * sizeof(int);
   // about 2048 tile points per block of 256 threads, at most 48 KB of LDS
@@ -463,7 +475,7 @@ void apply_vec_pc(const VecDev &V, const T *coef, const T *B, const T *D, const 
   constexpr int fit = (int)(48 * 1024 / per_cell) > 0 ? (int)(48 * 1024 / per_cell) : 1;
   constexpr int CPB = want < fit ? want : fit;
   const size_t shm = CPB * per_cell + ((P + 1) * (P + 1) + P * (P + 1)) * sizeof(T);
-  k_apply_vec_p<P, T, CPB, CURL><<<(unsigned)((nc + CPB - 1) / CPB), 256, shm, s>>>(V, coef, B, D, x, y, ebuf, nc);
+  k_apply_vec_p<P, T, CPB, CURL><<<(unsigned)((nc + CPB - 1) / CPB), 256, shm, s>>>(V, coef, B, D, x, y, ebuf, nc, bsub);
   long lines = 0;
   int emax = 0;
   for (int m = 0; m < 3; ++m) {
@@ -471,38 +483,38 @@ void apply_vec_pc(const VecDev &V, const T *coef, const T *B, const T *D, const 
     emax = std::max(emax, V.ext[m][0]);
   }
   const int chunks = (emax + 127) / 128;
-  k_apply_vec_gather<P, T, CURL><<<(unsigned)((lines + GL - 1) / GL * chunks), 128, 0, s>>>(V, x, ebuf, y, chunks);
+  k_apply_vec_gather<P, T, CURL><<<(unsigned)((lines + GL - 1) / GL * chunks), 128, 0, s>>>(V, x, ebuf, y, chunks, bsub);
 }
 
 template <int P, typename T>
 void apply_vec_p(const VecDev &V, const T *coef, const T *B, const T *D, const T *x, T *y, T *ebuf, long nc,
-                 hipStream_t s) {
-  if (V.space == 1) apply_vec_pc<P, T, true>(V, coef, B, D, x, y, ebuf, nc, s);
-  else apply_vec_pc<P, T, false>(V, coef, B, D, x, y, ebuf, nc, s);
+                 hipStream_t s, const T *bsub) {
+  if (V.space == 1) apply_vec_pc<P, T, true>(V, coef, B, D, x, y, ebuf, nc, s, bsub);
+  else apply_vec_pc<P, T, false>(V, coef, B, D, x, y, ebuf, nc, s, bsub);
 }
 
 template <typename T>
 int launch_apply_vec(const VecDev &V, const T *coef, const T *B, const T *D, const T *x, T *y, T *ebuf,
-                     hipStream_t s) {
+                     hipStream_t s, const T *bsub) {
   if (V.p < 1 || V.p > kMaxP) return -1;
   const long nc = (long)V.nx * V.ny * V.nz;
   switch (V.p) {
-    case 1: apply_vec_p<1, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
-    case 2: apply_vec_p<2, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
-    case 3: apply_vec_p<3, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
-    case 4: apply_vec_p<4, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
-    case 5: apply_vec_p<5, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
-    case 6: apply_vec_p<6, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
-    case 7: apply_vec_p<7, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
-    case 8: apply_vec_p<8, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
-    default: apply_vec_p<9, T>(V, coef, B, D, x, y, ebuf, nc, s); break;
+    case 1: apply_vec_p<1, T>(V, coef, B, D, x, y, ebuf, nc, s, bsub); break;
+    case 2: apply_vec_p<2, T>(V, coef, B, D, x, y, ebuf, nc, s, bsub); break;
+    case 3: apply_vec_p<3, T>(V, coef, B, D, x, y, ebuf, nc, s, bsub); break;
+    case 4: apply_vec_p<4, T>(V, coef, B, D, x, y, ebuf, nc, s, bsub); break;
+    case 5: apply_vec_p<5, T>(V, coef, B, D, x, y, ebuf, nc, s, bsub); break;
+    case 6: apply_vec_p<6, T>(V, coef, B, D, x, y, ebuf, nc, s, bsub); break;
+    case 7: apply_vec_p<7, T>(V, coef, B, D, x, y, ebuf, nc, s, bsub); break;
+    case 8: apply_vec_p<8, T>(V, coef, B, D, x, y, ebuf, nc, s, bsub); break;
+    default: apply_vec_p<9, T>(V, coef, B, D, x, y, ebuf, nc, s, bsub); break;
   }
   return 0;
 }
 
 template int launch_apply_vec<double>(const VecDev &, const double *, const double *, const double *,
-                                      const double *, double *, double *, hipStream_t);
+                                      const double *, double *, double *, hipStream_t, const double *);
 template int launch_apply_vec<float>(const VecDev &, const float *, const float *, const float *, const float *,
-                                     float *, float *, hipStream_t);
+                                     float *, float *, hipStream_t, const float *);
 
 }  // namespace rz

@@ -194,7 +194,7 @@ void launch_apply_gather(const LatDev &L, const T *x, const T *ebuf, T *y, hipSt
 // part 0..2, mass part 3..5); ebuf: ncells * cell_dofs.  Non-zero for unsupported p.
 template <typename T>
 int launch_apply_vec(const VecDev &V, const T *coef, const T *B, const T *D, const T *x, T *y, T *ebuf,
-                     hipStream_t s);
+                     hipStream_t s, const T *bsub = nullptr);  // bsub: y = bsub - A x
 // ---- H(curl) / H(div) relaxation ---------------------------------------------------
 // z_I = P_II^{-1} r_I at the interior DoFs; eb (ncells * nG) = P_GI z_I per cell
 template <typename T>

@@ -584,6 +584,12 @@ rz_status do_residual64(rz_problem *h, const double *b, const double *x, double 
     launch_apply_grad<double>(h->L, h->coef64, h->t.B.data(), h->t.A.data(), x, b, out, h->eb64, h->ctx->stream);
     return RZ_OK;
   }
+  if (h->space != RZ_GRAD) {  // b - A x fused into the apply's stores
+    Timed t(h, RZ_K_APPLY);
+    if (launch_apply_vec<double>(h->V, h->coef64, h->B64, h->D64, x, out, h->eb64, h->ctx->stream, b))
+      return fail(h->ctx, RZ_ERR_ARG, "unsupported degree");
+    return RZ_OK;
+  }
   rz_status e = do_apply64(h, x, h->vaz);
   if (e) return e;
   v_sub(h, b, h->vaz, out);
@@ -842,6 +848,12 @@ rz_status do_residual32(rz_problem *h, const float *b, const float *x, float *ou
   if (h->space == RZ_GRAD && !h->quad) {
     Timed t(h, RZ_K_APPLY);
     launch_apply_grad<float>(h->L, h->coef32, h->t.B.data(), h->t.A.data(), x, b, out, h->eb32, h->ctx->stream);
+    return RZ_OK;
+  }
+  if (h->space != RZ_GRAD) {  // b - A x fused into the apply's stores
+    Timed t(h, RZ_K_APPLY);
+    if (launch_apply_vec<float>(h->V, h->coef32, h->B32, h->D32, x, out, h->eb32, h->ctx->stream, b))
+      return fail(h->ctx, RZ_ERR_ARG, "unsupported degree");
     return RZ_OK;
   }
   rz_status e = do_apply32(h, x, h->az32);
