@@ -321,14 +321,14 @@ __global__ void __launch_bounds__(256) k_apply_faces(LatDev L, const S *__restri
 // Dirichlet rows copy x.  Rows interior to a cell were written by the cell kernel.
 template <typename S, typename T>
 __global__ void k_apply_gather(LatDev L, const S *__restrict__ x, const T *__restrict__ ebuf, S *__restrict__ y,
-                               long n) {
+                               long n, const S *__restrict__ bsub) {
   long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const int p = L.p, n1 = p + 1, n3 = n1 * n1 * n1;
   const int C[3] = {(int)(g % L.Nx), (int)((g / L.Nx) % L.Ny), (int)(g / ((long)L.Nx * L.Ny))};
   if (C[0] % p != 0 && C[1] % p != 0 && C[2] % p != 0) return;
   if (lat_dirichlet(L, C[0], C[1], C[2])) {
-    y[g] = x[g];
+    y[g] = bsub ? st_store<S, T>(st_load<T, S>(bsub[g]) - st_load<T, S>(x[g])) : x[g];
     return;
   }
   // per axis the (1 or 2) cells holding the coordinate: candidate 0 is the cell below
@@ -365,7 +365,7 @@ __global__ void k_apply_gather(LatDev L, const S *__restrict__ x, const T *__res
   T acc = 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc += v[q];
-  y[g] = st_store<S, T>(acc);
+  y[g] = st_store<S, T>(bsub ? st_load<T, S>(bsub[g]) - acc : acc);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1821,15 +1821,15 @@ void launch_apply_grad_bf16(const LatDev &L, const float *coef, const double *Bh
 }
 
 template <typename T>
-void launch_apply_gather(const LatDev &L, const T *x, const T *ebuf, T *y, hipStream_t s) {
+void launch_apply_gather(const LatDev &L, const T *x, const T *ebuf, T *y, hipStream_t s, const T *bsub) {
   long n = (long)L.Nx * L.Ny * L.Nz;
-  k_apply_gather<T, T><<<nblocks(n, 256), 256, 0, s>>>(L, x, ebuf, y, n);
+  k_apply_gather<T, T><<<nblocks(n, 256), 256, 0, s>>>(L, x, ebuf, y, n, bsub);
 }
 
 // BF16 vectors, FP32 per-cell buffer (the matrix-core apply)
 void launch_apply_gather_bf16(const LatDev &L, const bf16_t *x, const float *ebuf, bf16_t *y, hipStream_t s) {
   long n = (long)L.Nx * L.Ny * L.Nz;
-  k_apply_gather<bf16_t, float><<<nblocks(n, 256), 256, 0, s>>>(L, x, ebuf, y, n);
+  k_apply_gather<bf16_t, float><<<nblocks(n, 256), 256, 0, s>>>(L, x, ebuf, y, n, nullptr);
 }
 
 template <int P, typename T>
@@ -2247,8 +2247,10 @@ template void launch_apply_grad<double>(const LatDev &, const double *, const do
                                         const double *, const double *, double *, double *, hipStream_t);
 template void launch_apply_grad<float>(const LatDev &, const float *, const double *, const double *,
                                        const float *, const float *, float *, float *, hipStream_t);
-template void launch_apply_gather<double>(const LatDev &, const double *, const double *, double *, hipStream_t);
-template void launch_apply_gather<float>(const LatDev &, const float *, const float *, float *, hipStream_t);
+template void launch_apply_gather<double>(const LatDev &, const double *, const double *, double *, hipStream_t,
+                                          const double *);
+template void launch_apply_gather<float>(const LatDev &, const float *, const float *, float *, hipStream_t,
+                                         const float *);
 template void launch_condense_grad<double>(const LatDev &, const double *, const double *, const double *,
                                            const double *, double *, hipStream_t);
 template void launch_condense_grad<float>(const LatDev &, const float *, const float *, const float *,

@@ -31,7 +31,8 @@ __device__ __forceinline__ long qlat_index(const LatDev &L, int X, int Y, int Z)
 
 template <int P, int Q, typename T>
 __global__ void __launch_bounds__(Q *Q) k_apply_quad(LatDev L, QuadDev<T> G, const T *__restrict__ x,
-                                                     T *__restrict__ y, T *__restrict__ ebuf) {
+                                                     T *__restrict__ y, T *__restrict__ ebuf,
+                                                     const T *__restrict__ bsub) {
   constexpr int N1 = P + 1, N2 = N1 * N1, N3 = N2 * N1, QQ = Q * Q;
   __shared__ T tile[N3];
   __shared__ T XB[N2 * Q], XD[N2 * Q];
@@ -243,41 +244,44 @@ __global__ void __launch_bounds__(Q *Q) k_apply_quad(LatDev L, QuadDev<T> G, con
   for (int k = tid; k < N3; k += QQ) {
     const int a = k % N1, b = (k / N1) % N1, c = k / N2;
     const T val = tile[k];
-    if (a != 0 && a != P && b != 0 && b != P && c != 0 && c != P)
-      y[qlat_index(L, cx * P + a, cy * P + b, cz * P + c)] = val;
-    else
+    if (a != 0 && a != P && b != 0 && b != P && c != 0 && c != P) {  // held by this cell alone
+      const long g = qlat_index(L, cx * P + a, cy * P + b, cz * P + c);
+      y[g] = bsub ? bsub[g] - val : val;
+    } else {
       ebuf[cell * N3 + k] = val;
+    }
   }
 }
 
 template <int P, int Q, typename T>
-void apply_quad_pq(const LatDev &L, const QuadDev<T> &G, const T *x, T *y, T *ebuf, hipStream_t s) {
+void apply_quad_pq(const LatDev &L, const QuadDev<T> &G, const T *x, T *y, T *ebuf, hipStream_t s, const T *bsub) {
   const long nc = (long)L.nx * L.ny * L.nz;
-  k_apply_quad<P, Q, T><<<(unsigned)nc, Q * Q, 0, s>>>(L, G, x, y, ebuf);
+  k_apply_quad<P, Q, T><<<(unsigned)nc, Q * Q, 0, s>>>(L, G, x, y, ebuf, bsub);
 }
 
 }  // namespace
 
 template <typename T>
-int launch_apply_quad_cells(const LatDev &L, const QuadDev<T> &G, const T *x, T *y, T *ebuf, hipStream_t s) {
+int launch_apply_quad_cells(const LatDev &L, const QuadDev<T> &G, const T *x, T *y, T *ebuf, hipStream_t s,
+                            const T *bsub) {
   switch (L.p) {
-    case 1: apply_quad_pq<1, 3, T>(L, G, x, y, ebuf, s); break;
-    case 2: apply_quad_pq<2, 5, T>(L, G, x, y, ebuf, s); break;
-    case 3: apply_quad_pq<3, 6, T>(L, G, x, y, ebuf, s); break;
-    case 4: apply_quad_pq<4, 8, T>(L, G, x, y, ebuf, s); break;
-    case 5: apply_quad_pq<5, 9, T>(L, G, x, y, ebuf, s); break;
-    case 6: apply_quad_pq<6, 11, T>(L, G, x, y, ebuf, s); break;
-    case 7: apply_quad_pq<7, 12, T>(L, G, x, y, ebuf, s); break;
-    case 8: apply_quad_pq<8, 14, T>(L, G, x, y, ebuf, s); break;
-    case 9: apply_quad_pq<9, 15, T>(L, G, x, y, ebuf, s); break;
+    case 1: apply_quad_pq<1, 3, T>(L, G, x, y, ebuf, s, bsub); break;
+    case 2: apply_quad_pq<2, 5, T>(L, G, x, y, ebuf, s, bsub); break;
+    case 3: apply_quad_pq<3, 6, T>(L, G, x, y, ebuf, s, bsub); break;
+    case 4: apply_quad_pq<4, 8, T>(L, G, x, y, ebuf, s, bsub); break;
+    case 5: apply_quad_pq<5, 9, T>(L, G, x, y, ebuf, s, bsub); break;
+    case 6: apply_quad_pq<6, 11, T>(L, G, x, y, ebuf, s, bsub); break;
+    case 7: apply_quad_pq<7, 12, T>(L, G, x, y, ebuf, s, bsub); break;
+    case 8: apply_quad_pq<8, 14, T>(L, G, x, y, ebuf, s, bsub); break;
+    case 9: apply_quad_pq<9, 15, T>(L, G, x, y, ebuf, s, bsub); break;
     default: return -1;
   }
   return 0;
 }
 
 template int launch_apply_quad_cells<double>(const LatDev &, const QuadDev<double> &, const double *, double *,
-                                             double *, hipStream_t);
+                                             double *, hipStream_t, const double *);
 template int launch_apply_quad_cells<float>(const LatDev &, const QuadDev<float> &, const float *, float *,
-                                            float *, hipStream_t);
+                                            float *, hipStream_t, const float *);
 
 }  // namespace rz

@@ -187,9 +187,11 @@ void launch_apply_gather_bf16(const LatDev &L, const unsigned short *x, const fl
 // ebuf); the interface rows are then summed by launch_apply_gather.  Returns
 // non-zero for an unsupported degree.
 template <typename T>
-int launch_apply_quad_cells(const LatDev &L, const QuadDev<T> &G, const T *x, T *y, T *ebuf, hipStream_t s);
+int launch_apply_quad_cells(const LatDev &L, const QuadDev<T> &G, const T *x, T *y, T *ebuf, hipStream_t s,
+                            const T *bsub = nullptr);  // bsub: interior rows store bsub - A x
 template <typename T>
-void launch_apply_gather(const LatDev &L, const T *x, const T *ebuf, T *y, hipStream_t s);
+void launch_apply_gather(const LatDev &L, const T *x, const T *ebuf, T *y, hipStream_t s,
+                         const T *bsub = nullptr);  // bsub: y = bsub - A x (bsub - x on Dirichlet rows)
 // y = A x in H(curl) / H(div) on axis-aligned cells (weights: 6 per cell, stiffness
 // part 0..2, mass part 3..5); ebuf: ncells * cell_dofs.  Non-zero for unsupported p.
 template <typename T>

@@ -590,6 +590,12 @@ rz_status do_residual64(rz_problem *h, const double *b, const double *x, double 
       return fail(h->ctx, RZ_ERR_ARG, "unsupported degree");
     return RZ_OK;
   }
+  if (h->quad) {  // trilinear cells: the same fusion in the cell kernel and the gather
+    Timed t(h, RZ_K_APPLY);
+    launch_apply_quad_cells<double>(h->L, h->Q64, x, out, h->eb64, h->ctx->stream, b);
+    launch_apply_gather<double>(h->L, x, h->eb64, out, h->ctx->stream, b);
+    return RZ_OK;
+  }
   rz_status e = do_apply64(h, x, h->vaz);
   if (e) return e;
   v_sub(h, b, h->vaz, out);
@@ -854,6 +860,12 @@ rz_status do_residual32(rz_problem *h, const float *b, const float *x, float *ou
     Timed t(h, RZ_K_APPLY);
     if (launch_apply_vec<float>(h->V, h->coef32, h->B32, h->D32, x, out, h->eb32, h->ctx->stream, b))
       return fail(h->ctx, RZ_ERR_ARG, "unsupported degree");
+    return RZ_OK;
+  }
+  if (h->quad) {
+    Timed t(h, RZ_K_APPLY);
+    launch_apply_quad_cells<float>(h->L, h->Q32, x, out, h->eb32, h->ctx->stream, b);
+    launch_apply_gather<float>(h->L, x, h->eb32, out, h->ctx->stream, b);
     return RZ_OK;
   }
   rz_status e = do_apply32(h, x, h->az32);
