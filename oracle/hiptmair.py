@@ -44,7 +44,7 @@ from .tables1d import Element1D
 from .lattice import Lattice
 from .assemble import ref_grad, ref_curl, cartesian_operator
 from .auxop import separable_operator, cartesian_coefficient_array
-from .schwarz import interior_mask, SCRelaxGrad
+from .schwarz import interior_mask, SCRelaxGrad, full_star_patches_grad
 
 EPS_HDIV = 1e-3
 
@@ -366,3 +366,112 @@ class SCPAFWRelaxVec(SCRelaxPH):
         inner = interior_mask(lat)
         self.patches = [(vid, d[~inner[d]]) for vid, d in vertex_star_patches_vec(lat) if (~inner[d]).any()]
         self.local = PatchSolves(cond, self.patches)
+
+
+# ----------------------------------------------------------------------------------
+# PH without static condensation for H(curl) / H(div) (Sec. 4.3, eq. ph with eq.
+# asm-hiptmair): the stars of the k-dimensional entities (edges for H(curl), faces for
+# H(div)) holding every free DoF whose cells all contain the entity, solved exactly,
+# plus the potential term through the full stars of the potential space (vertex stars
+# of Q_p, resp. edge stars of NCE_p) and the full exterior derivative.  The PH column
+# of Tables hcurl-iter / hdiv-iter.
+# ----------------------------------------------------------------------------------
+def _holding_cells(lat: Lattice):
+    """Per free DoF and axis, the range lo..hi of the cells holding it (as in
+    vertex_star_patches_vec)."""
+    mesh, p = lat.mesh, lat.p
+    nc = (mesh.nx, mesh.ny, mesh.nz)
+    co = lat.coords()
+    comp = co[:, 0]
+    lo = np.zeros((lat.ndofs, 3), dtype=np.int64)
+    hi = np.zeros((lat.ndofs, 3), dtype=np.int64)
+    for a in range(3):
+        C = co[:, 1 + a]
+        cont = np.array([lat.kinds[m][a] == "P" for m in range(len(lat.kinds))])[comp]
+        c = C // p
+        on = cont & (C % p == 0)
+        lo[:, a] = np.where(on, np.maximum(c - 1, 0), np.minimum(c, nc[a] - 1))
+        hi[:, a] = np.minimum(c, nc[a] - 1)
+    return lo, hi
+
+
+def entity_star_patches(lat: Lattice, dim):
+    """List of (entity id, dof array, ascending) of the non-empty stars of the entities
+    of dimension dim (1: edges, 2: faces) without static condensation.  The cells
+    containing an edge along m are its cell along m and the (up to) two cells on
+    either side of each of its vertex coordinates; those containing a face normal to
+    m are the (up to) two cells on either side of its vertex plane.  A free DoF belongs
+    to the star when every cell holding it is among them.  Entity ids run over the
+    axis (of the edge, of the face normal), then lattice order, x fastest."""
+    mesh = lat.mesh
+    n = (mesh.nx, mesh.ny, mesh.nz)
+    lo, hi = _holding_cells(lat)
+    free = ~lat.dirichlet_mask()
+    out, base = [], 0
+    for m in range(3):
+        # entity coordinates: a cell index along the entity's own axes, a vertex index
+        # along the others (edge along m: cell along m; face normal to m: vertex along m)
+        cell_axes = [m] if dim == 1 else [a for a in range(3) if a != m]
+        ext = [n[a] if a in cell_axes else n[a] + 1 for a in range(3)]
+        for k2 in range(ext[2]):
+            for k1 in range(ext[1]):
+                for k0 in range(ext[0]):
+                    c = (k0, k1, k2)
+                    inside = free.copy()
+                    for a in range(3):
+                        blo, bhi = (c[a], c[a]) if a in cell_axes else (c[a] - 1, c[a])
+                        inside &= (lo[:, a] >= blo) & (hi[:, a] <= bhi)
+                    sel = np.where(inside)[0]
+                    if sel.size:
+                        out.append((base + k0 + ext[0] * (k1 + ext[1] * k2), sel))
+        base += ext[0] * ext[1] * ext[2]
+    return out
+
+
+class PHRelaxVec:
+    """z = M^{-1} r for PH without static condensation on H(curl) / H(div):
+    z = sum_E R_E^T P_E^{-1} R_E r + D (sum_j R_j^T B_j^{-1} R_j) D^T r, the first sum
+    over the edge (H(curl)) or face (H(div)) stars with exact Cholesky of
+    P_E = R_E P R_E^T, the second over the full stars of the potential problem B
+    (H(curl): Q_p with (grad phi, beta grad psi), vertex stars; H(div): NCE_p with
+    (curl phi, beta curl psi) + eps (phi, beta psi), edge stars), exact, and D the
+    exterior derivative between the free DoFs; Dirichlet rows copy r."""
+
+    def __init__(self, lat: Lattice, P, beta, eps=EPS_HDIV):
+        P = sp.csr_matrix(P)
+        mesh, p = lat.mesh, lat.p
+        self.dmask = lat.dirichlet_mask()
+        dim = 1 if lat.space == "curl" else 2
+        self.patches = entity_star_patches(lat, dim)
+        self.factors = [np.linalg.cholesky(P[d][:, d].toarray()) for _, d in self.patches]
+        be = np.broadcast_to(np.asarray(beta, dtype=np.float64), (mesh.ncells,))
+        if lat.space == "curl":
+            latp = Lattice(mesh, "grad", p)
+            B = separable_operator(latp, cartesian_coefficient_array(latp, be, 0.0))
+            self.pot_patches = full_star_patches_grad(latp)
+        else:
+            latp = Lattice(mesh, "curl", p)
+            B = cartesian_operator(latp, be, eps * be)
+            self.pot_patches = entity_star_patches(latp, 1)
+        B = sp.csr_matrix(B)
+        self.pot_factors = [np.linalg.cholesky(B[d][:, d].toarray()) for _, d in self.pot_patches]
+        keep = sp.diags((~self.dmask).astype(np.float64))
+        keepp = sp.diags((~latp.dirichlet_mask()).astype(np.float64))
+        self.D = sp.csr_matrix(keep @ exterior_derivative(latp, lat) @ keepp)
+        self.npot = latp.ndofs
+
+    @staticmethod
+    def _stars(patches, factors, r, n):
+        z = np.zeros(n)
+        for (_, d), L in zip(patches, factors):
+            y = scipy.linalg.solve_triangular(L, r[d], lower=True)
+            z[d] += scipy.linalg.solve_triangular(L.T, y, lower=False)
+        return z
+
+    def apply(self, r, potential=True):
+        r = np.asarray(r, dtype=np.float64)
+        z = self._stars(self.patches, self.factors, r, r.size)
+        if potential:
+            z = z + self.D @ self._stars(self.pot_patches, self.pot_factors, self.D.T @ r, self.npot)
+        z[self.dmask] = r[self.dmask]
+        return z

@@ -297,3 +297,56 @@ def test_sc_pafw_spd_and_stars_on_the_interface(space):
     M = np.column_stack([R.apply(np.eye(lat.ndofs)[k])[free] for k in free])
     assert np.abs(M - M.T).max() < 1e-10 * np.abs(M).max()
     assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+
+
+@pytest.mark.parametrize("space,count", [("curl", 12), ("div", 6)])
+def test_ph_one_cell_stars_are_exact_solves(space, count):
+    # one cell, no Dirichlet face: each of the cell's 12 edges (6 faces) has the whole
+    # cell as its star, so without the potential term PH is count times A^{-1}
+    lat = Lattice(Mesh(1, 1, 1, dirichlet=0), space, 2)
+    A = asm.cartesian_operator(lat, 1.7, 0.6)
+    R = hp.PHRelaxVec(lat, A, 0.6)
+    assert len(R.patches) == count and all(d.size == lat.ndofs for _, d in R.patches)
+    r = synth.uniform_pm1(9, lat.ndofs)
+    x = np.linalg.solve(A.toarray(), r)
+    assert np.abs(R.apply(r, potential=False) - count * x).max() < 1e-10 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("space,dim", [("curl", 1), ("div", 2), ("curl", 2)])
+def test_entity_stars_by_brute_force(space, dim):
+    # a DoF lies in the star of an entity exactly when every cell whose closure holds
+    # the DoF's support point contains the entity (checked cell by cell)
+    lat = Lattice(Mesh(3, 2, 2), space, 2)
+    pl = hp.entity_star_patches(lat, dim)
+    co = lat.coords()
+    cd = lat.cell_dofs()
+    holders = [set() for _ in range(lat.ndofs)]
+    for c in range(cd.shape[0]):
+        for g in cd[c]:
+            holders[g].add(c)
+    n = (3, 2, 2)
+
+    def cells_of(eid):
+        base = 0
+        for m in range(3):
+            cell_axes = [m] if dim == 1 else [a for a in range(3) if a != m]
+            ext = [n[a] if a in cell_axes else n[a] + 1 for a in range(3)]
+            cnt = ext[0] * ext[1] * ext[2]
+            if eid < base + cnt:
+                k = eid - base
+                c = (k % ext[0], (k // ext[0]) % ext[1], k // (ext[0] * ext[1]))
+                out = set()
+                for cz in range(n[2]):
+                    for cy in range(n[1]):
+                        for cx in range(n[0]):
+                            cc = (cx, cy, cz)
+                            if all((cc[a] == c[a]) if a in cell_axes else (cc[a] in (c[a] - 1, c[a]))
+                                   for a in range(3)):
+                                out.add(cx + n[0] * (cy + n[1] * cz))
+                return out
+            base += cnt
+    free = ~lat.dirichlet_mask()
+    for eid, d in pl:
+        cells = cells_of(eid)
+        want = [g for g in range(lat.ndofs) if free[g] and holders[g] <= cells]
+        assert sorted(want) == list(d)
