@@ -142,9 +142,14 @@ typedef struct {
                         * PAFW, the vertex stars of the k-forms without condensation;    *
                         * RZ_DECOMP_SC_VERTEX SC-PAFW (Sec. 4.4), those stars restricted *
                         * to the condensed interface, each solved exactly on the         *
-                        * assembled interface Schur complement (the PAFW and SC-PAFW     *
-                        * columns of Tables hcurl-iter / hdiv-iter; both with            *
-                        * RZ_PATCH_CHOLESKY, dense W = L^{-1} per star, small meshes)    */
+                        * assembled interface Schur complement; RZ_DECOMP_FULL_PH PH     *
+                        * without condensation (Sec. 4.3 eq. ph): edge (H(curl)) or face *
+                        * (H(div)) stars holding every DoF of their cells, plus the      *
+                        * potential term through the full vertex stars of Q_p (resp. the *
+                        * edge stars of NCE_p) and the full exterior derivative (the     *
+                        * PAFW, SC-PAFW and PH columns of Tables hcurl-iter / hdiv-iter; *
+                        * all with RZ_PATCH_CHOLESKY, dense W = L^{-1} per star, small   *
+                        * meshes)                                                        */
   int32_t norm;        /* stopping rule of rz_solve / rz_solve_batched (FP64 and mixed  *
                         * protocols): RZ_NORM_2 (default) the true 2-norm residual      *
                         * <= rtol ||b||, confirmed by a residual from x; RZ_NORM_NATURAL *
@@ -174,7 +179,7 @@ typedef struct {
 enum { RZ_COARSE_DIRECT = 0, RZ_COARSE_HMG = 1 };
 
 /* Decompositions of the relaxation (rz_opts.decomposition). */
-enum { RZ_DECOMP_SC = 0, RZ_DECOMP_FULL = 1, RZ_DECOMP_SC_VERTEX = 2 };
+enum { RZ_DECOMP_SC = 0, RZ_DECOMP_FULL = 1, RZ_DECOMP_SC_VERTEX = 2, RZ_DECOMP_FULL_PH = 3 };
 
 /* Stopping rules (rz_opts.norm). */
 enum { RZ_NORM_2 = 0, RZ_NORM_NATURAL = 1 };

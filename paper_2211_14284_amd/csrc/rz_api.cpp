@@ -245,6 +245,21 @@ struct rz_problem {
   // (nrf entries each), and per free DoF the positions of its star solutions
   int nvs = 0, nvfree = 0;
   bool vs_sc = false;                       // vertex stars on the condensed interface (SC-PAFW)
+  // PH without static condensation (RZ_DECOMP_FULL_PH): the edge / face stars of the
+  // space, the NCE_p edge stars of the H(div) potential (the H(curl) potential uses the
+  // full vertex stars of its Q_p problem), the full exterior derivative D and D^T
+  struct StarSet {
+    int np = 0, nr = 0, nfree = 0;
+    int *idx = nullptr, *rows = nullptr, *ptr = nullptr, *pos = nullptr;
+    double *w64 = nullptr, *zb64 = nullptr;
+    float *w32 = nullptr, *zb32 = nullptr;
+  };
+  StarSet ph_s, ph_p;
+  int nphd = 0, nphdt = 0;
+  int *phd_rows = nullptr, *phd_ptr = nullptr, *phd_col = nullptr;
+  int *phdt_rows = nullptr, *phdt_ptr = nullptr, *phdt_col = nullptr;
+  double *phd_val64 = nullptr, *phdt_val64 = nullptr;
+  float *phd_val32 = nullptr, *phdt_val32 = nullptr;
   int *vs_idx = nullptr, *vs_rows = nullptr, *vs_ptr = nullptr, *vs_pos = nullptr;
   double *fzb64 = nullptr;
   float *fzb32 = nullptr;
@@ -494,10 +509,43 @@ double *full_zb(rz_problem *h, double *);
 float *full_zb(rz_problem *h, float *);
 const double *chol_w(rz_problem *h, const double *);
 const float *chol_w(rz_problem *h, const float *);
+const double *ph_w(const rz_problem::StarSet &S, const double *) { return S.w64; }
+const float *ph_w(const rz_problem::StarSet &S, const float *) { return S.w32; }
+double *ph_zb(const rz_problem::StarSet &S, double *) { return S.zb64; }
+float *ph_zb(const rz_problem::StarSet &S, float *) { return S.zb32; }
+const double *ph_d(const rz_problem *h, const double *) { return h->phd_val64; }
+const float *ph_d(const rz_problem *h, const float *) { return h->phd_val32; }
+const double *ph_dt(const rz_problem *h, const double *) { return h->phdt_val64; }
+const float *ph_dt(const rz_problem *h, const float *) { return h->phdt_val32; }
+void fill_any(double *y, int64_t n, hipStream_t s) { launch_fill(y, 0.0, n, s); }
+void fill_any(float *y, int64_t n, hipStream_t s) { launch_fill_f(y, 0.0f, n, s); }
+template <typename T>
+void relax_full(rz_problem *h, const T *r, T *z, T scale, T w, T *acc);
 
 template <typename T>
 rz_status relax_vec(rz_problem *h, const VecRelaxPtrs<T> &X, const T *r, T *z) {
   hipStream_t s = h->ctx->stream;
+  if (h->ph_s.np) {  // PH without condensation: the space's stars + D (potential stars) D^T
+    Timed t(h, RZ_K_PATCH);
+    const rz_problem::StarSet &S = h->ph_s;
+    T *zb = ph_zb(S, (T *)nullptr);
+    launch_dense_patch_solve<T>(S.np, S.nr, S.idx, ph_w(S, (const T *)nullptr), r, zb, s);
+    launch_list_gather<T>(S.nfree, S.rows, S.ptr, S.pos, zb, (const T *)nullptr, z, T(1), s);
+    fill_any(X.vq, h->pndofs, s);
+    launch_csr<T, T, T>(h->nphdt, h->phdt_rows, h->phdt_ptr, h->phdt_col, ph_dt(h, (const T *)nullptr), r, X.vq, 0,
+                        s);
+    if (h->space == RZ_CURL) {
+      relax_full<T>(h->pot, X.vq, X.vy, T(1), T(0), (T *)nullptr);
+    } else {
+      const rz_problem::StarSet &Q = h->ph_p;
+      T *zq = ph_zb(Q, (T *)nullptr);
+      launch_dense_patch_solve<T>(Q.np, Q.nr, Q.idx, ph_w(Q, (const T *)nullptr), X.vq, zq, s);
+      launch_list_gather<T>(Q.nfree, Q.rows, Q.ptr, Q.pos, zq, (const T *)nullptr, X.vy, T(1), s);
+    }
+    launch_csr<T, T, T>(h->nphd, h->phd_rows, h->phd_ptr, h->phd_col, ph_d(h, (const T *)nullptr), X.vy, z, 1, s);
+    launch_list_copy<T>(h->nDir, h->dlist, r, z, s);
+    return RZ_OK;
+  }
   if (h->nvs && h->vs_sc) {  // SC-PAFW: condense, vertex stars on the interface, expand
     {
       Timed t(h, RZ_K_CONDENSE);
@@ -725,6 +773,7 @@ int coarse_coop(rz_problem *h, bool f32) {
 }
 
 void hmg_cycle(rz_problem *h, const double *b0, double *o0);
+rz_status setup_ph_full(rz_problem *h, const std::vector<double> &coefe);
 
 // Coarse solve; f32 selects the FP32 copies of the dense blocks (V-cycles of the
 // mixed protocols), otherwise FP64 throughout.
@@ -2724,6 +2773,7 @@ rz_status setup_vec_relax(rz_problem *h, const std::vector<double> &al, const st
   std::vector<int> drow, dptr(1, 0), dcol;
   std::vector<double> dval;
   int64_t pndofs = 0;
+  std::vector<double> coefe_pot;  // H(div): the NCE_p potential's weights
   if (space == RZ_CURL) {
     std::vector<double> coefq(6 * nc, 0.0);
     for (int64_t c = 0; c < nc; ++c) {
@@ -2763,6 +2813,7 @@ rz_status setup_vec_relax(rz_problem *h, const std::vector<double> &al, const st
         coefe[6 * c + 3 + d] = eps * be[c] * V / (2.0 * hs[c][d] * hs[c][d]);
       }
     }
+    coefe_pot = coefe;
     int exte[3][3];
     int64_t offe[4];
     vec_lattice(RZ_CURL, p, n, exte, offe);
@@ -2834,6 +2885,7 @@ rz_status setup_vec_relax(rz_problem *h, const std::vector<double> &al, const st
   launch_fill_f(h->vq32, 0.0f, pndofs, s);
   launch_fill(h->vy64, 0.0, pndofs, s);
   launch_fill_f(h->vy32, 0.0f, pndofs, s);
+  if (h->opts.decomposition == RZ_DECOMP_FULL_PH && (e = setup_ph_full(h, coefe_pot))) return e;
   // ---- Dirichlet rows --------------------------------------------------------------------
   std::vector<int> dl;
   h->dmask.assign(h->ndofs, 0);
@@ -2993,6 +3045,228 @@ rz_status setup_vec_relax(rz_problem *h, const std::vector<double> &al, const st
 // public API
 // =========================================================================================
 namespace {
+
+// Stars of the k-dimensional entities of NCE_p (space 1) or NCF_p (space 2) without
+// static condensation (PH, Sec. 4.3 eq. ph): kind 1 the edges (the cell along the edge,
+// up to two cells across each of its vertex coordinates), kind 2 the faces (up to two
+// cells across the face's vertex plane).  A free DoF belongs to a star when every
+// cell holding it is among the entity's cells.  Entities by axis (of the edge, of the
+// face normal), then lattice order; empty stars dropped.  Each star matrix is
+// assembled from the cells' weighted basis matrices (weights coef6, six per cell),
+// factored exactly on host threads and applied as W = L^{-1} (FP64 and FP32).
+rz_status build_entity_stars(rz_problem *h, int space, const double *coef6, int kind, rz_problem::StarSet &S) {
+  const int p = h->p;
+  VecLocal VL;
+  vec_local_layout(space, p, VL);
+  SpRows basis[6];
+  vec_basis_matrices(h->t, VL, basis);
+  const int n[3] = {h->nx, h->ny, h->nz};
+  int ext[3][3];
+  int64_t off[4];
+  vec_lattice(space, p, n, ext, off);
+  auto global = [&](const int cc[3], int l, int &m, int C[3]) {
+    m = VL.comp[l];
+    for (int a = 0; a < 3; ++a) C[a] = cc[a] * p + VL.crd[3 * l + a];
+    return vec_index(off, ext, m, C);
+  };
+  struct Ent {
+    int lo[3], hi[3];
+  };
+  std::vector<Ent> ents;
+  for (int m = 0; m < 3; ++m) {
+    bool cell_axis[3];
+    int ee[3];
+    for (int a = 0; a < 3; ++a) {
+      cell_axis[a] = kind == 1 ? a == m : a != m;
+      ee[a] = cell_axis[a] ? n[a] : n[a] + 1;
+    }
+    for (int k2 = 0; k2 < ee[2]; ++k2)
+      for (int k1 = 0; k1 < ee[1]; ++k1)
+        for (int k0 = 0; k0 < ee[0]; ++k0) {
+          const int c[3] = {k0, k1, k2};
+          Ent E;
+          for (int a = 0; a < 3; ++a) {
+            E.lo[a] = cell_axis[a] ? c[a] : c[a] - 1;
+            E.hi[a] = c[a];
+          }
+          ents.push_back(E);
+        }
+  }
+  auto inside = [&](int m, const int C[3], const Ent &E) {
+    for (int a = 0; a < 3; ++a) {
+      const int c = C[a] / p;
+      int lo = std::min(c, n[a] - 1), hi = lo;
+      if (vec_is_P(space, m, a) && C[a] % p == 0) {
+        lo = std::max(c - 1, 0);
+        hi = std::min(c, n[a] - 1);
+      }
+      if (lo < E.lo[a] || hi > E.hi[a]) return false;
+    }
+    return true;
+  };
+  auto for_cells = [&](const Ent &E, auto &&f) {
+    for (int cz = std::max(E.lo[2], 0); cz <= std::min(E.hi[2], n[2] - 1); ++cz)
+      for (int cy = std::max(E.lo[1], 0); cy <= std::min(E.hi[1], n[1] - 1); ++cy)
+        for (int cx = std::max(E.lo[0], 0); cx <= std::min(E.hi[0], n[0] - 1); ++cx) {
+          const int cc[3] = {cx, cy, cz};
+          f(cc);
+        }
+  };
+  std::vector<std::vector<int64_t>> stars(ents.size());
+  for (size_t k = 0; k < ents.size(); ++k) {
+    std::vector<int64_t> &St = stars[k];
+    for_cells(ents[k], [&](const int cc[3]) {
+      for (int l = 0; l < VL.nloc; ++l) {
+        int m, C[3];
+        const int64_t g = global(cc, l, m, C);
+        if (!vec_dirichlet(space, h->dir, ext, m, C) && inside(m, C, ents[k])) St.push_back(g);
+      }
+    });
+    std::sort(St.begin(), St.end());
+    St.erase(std::unique(St.begin(), St.end()), St.end());
+  }
+  std::vector<size_t> live;
+  int nr = 0;
+  for (size_t k = 0; k < ents.size(); ++k)
+    if (!stars[k].empty()) {
+      live.push_back(k);
+      nr = std::max(nr, (int)stars[k].size());
+    }
+  const size_t np = live.size(), tri = (size_t)nr * (nr + 1) / 2;
+  if ((double)np * tri * 12.0 > 16.0 * (1ull << 30) || (double)np * nr * nr * (double)nr > 5e11)
+    return fail(h->ctx, RZ_ERR_ARG, "RZ_DECOMP_FULL_PH: the dense star factors are for small meshes and degrees");
+  std::vector<double> W;
+  const long bad = factor_slots(np, nr, nullptr, [&](size_t k, std::vector<double> &M) {
+    const std::vector<int64_t> &St = stars[live[k]];
+    const int ns = (int)St.size();
+    for (int i = ns; i < nr; ++i) M[(size_t)i * nr + i] = 1.0;
+    std::vector<int> pos(VL.nloc);
+    for_cells(ents[live[k]], [&](const int cc[3]) {
+      for (int l = 0; l < VL.nloc; ++l) {
+        int m, C[3];
+        const int64_t g = global(cc, l, m, C);
+        const auto it = std::lower_bound(St.begin(), St.end(), g);
+        pos[l] = (it != St.end() && *it == g) ? (int)(it - St.begin()) : -1;
+      }
+      const double *w = coef6 + 6 * ((size_t)cc[0] + (size_t)n[0] * (cc[1] + (size_t)n[1] * cc[2]));
+      for (int kb = 0; kb < 6; ++kb)
+        for (int l1 = 0; l1 < VL.nloc; ++l1) {
+          if (pos[l1] < 0) continue;
+          for (const auto &ev : basis[kb][l1])
+            if (pos[ev.first] >= 0) M[(size_t)pos[l1] * nr + pos[ev.first]] += w[kb] * ev.second;
+        }
+    });
+  }, W);
+  if (bad >= 0) {
+    char msg[128];
+    std::snprintf(msg, sizeof msg, "Cholesky breakdown in star %ld", bad);
+    return fail(h->ctx, RZ_ERR_BREAKDOWN, msg);
+  }
+  std::vector<int> idx(np * nr, -1);
+  std::vector<std::vector<int>> where((size_t)off[3]);
+  for (size_t k = 0; k < np; ++k) {
+    const std::vector<int64_t> &St = stars[live[k]];
+    for (size_t i = 0; i < St.size(); ++i) {
+      idx[k * nr + i] = (int)St[i];
+      where[St[i]].push_back((int)(k * nr + i));
+    }
+  }
+  std::vector<int> rows, ptr{0}, pos;
+  for (int64_t g = 0; g < off[3]; ++g)
+    if (!where[g].empty()) {
+      rows.push_back((int)g);
+      pos.insert(pos.end(), where[g].begin(), where[g].end());
+      ptr.push_back((int)pos.size());
+    }
+  rz_status e;
+  if ((e = upload(h, &S.idx, idx)) || (e = upload(h, &S.rows, rows)) || (e = upload(h, &S.ptr, ptr)) ||
+      (e = upload(h, &S.pos, pos)) || (e = upload(h, &S.w64, W)) || (e = dalloc(h, &S.w32, W.size())) ||
+      (e = dalloc(h, &S.zb64, np * nr)) || (e = dalloc(h, &S.zb32, np * nr)))
+    return e;
+  launch_cast_d2f(S.w64, S.w32, (int64_t)W.size(), h->ctx->stream);
+  S.np = (int)np;
+  S.nr = nr;
+  S.nfree = (int)rows.size();
+  return RZ_OK;
+}
+
+// PH without static condensation: the stars of the space, the potential's stars (H(curl):
+// the full vertex stars of the Q_p problem h->pot; H(div): NCE_p edge stars with the
+// weights coefe), and the full exterior derivative between the free DoFs of the
+// potential space and of the space (the 1-D derivative table of degree p), with its
+// transpose.
+rz_status setup_ph_full(rz_problem *h, const std::vector<double> &coefe) {
+  const int p = h->p, space = h->space, n1 = p + 1;
+  const int n[3] = {h->nx, h->ny, h->nz};
+  rz_status e;
+  if ((e = build_entity_stars(h, space, h->coef.data(), space == RZ_CURL ? 1 : 2, h->ph_s))) return e;
+  if (space == RZ_CURL) {
+    if ((e = setup_full_stars(h->pot))) return e;
+  } else if ((e = build_entity_stars(h, RZ_CURL, coefe.data(), 1, h->ph_p))) {
+    return e;
+  }
+  int ext[3][3], exte[3][3];
+  int64_t off[4], offe[4];
+  vec_lattice(space, p, n, ext, off);
+  vec_lattice(RZ_CURL, p, n, exte, offe);
+  const rz_problem *q = h->pot;
+  const Tables1D &t = h->t;
+  std::vector<int> drow, dptr(1, 0), dcol;
+  std::vector<double> dval;
+  for (int64_t g = 0; g < off[3]; ++g) {
+    int m, X[3];
+    vec_coords(off, ext, g, m, X);
+    if (vec_dirichlet(space, h->dir, ext, m, X)) continue;
+    std::vector<std::pair<int, double>> row;
+    if (space == RZ_CURL) {  // NCE component m at X <- Q_p points along m
+      const int c = X[m] / p, j = X[m] % p;
+      for (int a = 0; a <= p; ++a) {
+        const double v = t.D[j * n1 + a];
+        if (v == 0.0) continue;
+        int Y[3] = {X[0], X[1], X[2]};
+        Y[m] = c * p + a;
+        if (lat_dirichlet_h(q, Y[0], Y[1], Y[2])) continue;
+        row.push_back({(int)(Y[0] + (int64_t)q->Nx * (Y[1] + (int64_t)q->Ny * Y[2])), v});
+      }
+    } else {  // NCF component m at X <- NCE d_{a1} u_{a2} - d_{a2} u_{a1}
+      const int a1 = (m + 1) % 3, a2 = (m + 2) % 3;
+      const int terms[2][3] = {{1, a2, a1}, {-1, a1, a2}};
+      for (auto &tm : terms) {
+        const int c = tm[1], d = tm[2];
+        const int cd = X[d] / p, j = X[d] % p;
+        for (int a = 0; a <= p; ++a) {
+          const double v = tm[0] * t.D[j * n1 + a];
+          if (v == 0.0) continue;
+          int Y[3] = {X[0], X[1], X[2]};
+          Y[d] = cd * p + a;
+          if (vec_dirichlet(RZ_CURL, h->dir, exte, c, Y)) continue;
+          row.push_back({(int)vec_index(offe, exte, c, Y), v});
+        }
+      }
+    }
+    if (row.empty()) continue;
+    std::sort(row.begin(), row.end());
+    drow.push_back((int)g);
+    for (auto &cv : row) {
+      dcol.push_back(cv.first);
+      dval.push_back(cv.second);
+    }
+    dptr.push_back((int)dcol.size());
+  }
+  std::vector<int> trid, tptr, tcol;
+  std::vector<double> tval;
+  csr_transpose(drow, dptr, dcol, dval, h->pndofs, trid, tptr, tcol, tval);
+  h->nphd = (int)drow.size();
+  h->nphdt = (int)trid.size();
+  if ((e = upload(h, &h->phd_rows, drow)) || (e = upload(h, &h->phd_ptr, dptr)) || (e = upload(h, &h->phd_col, dcol)) ||
+      (e = upload(h, &h->phd_val64, dval)) || (e = upload(h, &h->phd_val32, as_type<float>(dval))) ||
+      (e = upload(h, &h->phdt_rows, trid)) || (e = upload(h, &h->phdt_ptr, tptr)) ||
+      (e = upload(h, &h->phdt_col, tcol)) || (e = upload(h, &h->phdt_val64, tval)) ||
+      (e = upload(h, &h->phdt_val32, as_type<float>(tval))))
+    return e;
+  HIPCALL(h, hipStreamSynchronize(h->ctx->stream));
+  return RZ_OK;
+}
 
 // H(curl) / H(div) problems: the cellwise-constant Cartesian cell matrices of the
 // closed form (Sec. 3.2 with the pullbacks of Sec. 3.1 on boxes), apply only.
@@ -3530,8 +3804,10 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
   if (opts->coarse == RZ_COARSE_HMG && opts->space != RZ_GRAD && opts->decomposition == RZ_DECOMP_FULL)
     return fail(ctx, RZ_ERR_ARG, "the h-multigrid coarse solver goes with the statically condensed relaxation");
   if (opts->decomposition != RZ_DECOMP_SC && opts->decomposition != RZ_DECOMP_FULL &&
-      opts->decomposition != RZ_DECOMP_SC_VERTEX)
+      opts->decomposition != RZ_DECOMP_SC_VERTEX && opts->decomposition != RZ_DECOMP_FULL_PH)
     return fail(ctx, RZ_ERR_ARG, "bad decomposition");
+  if (opts->decomposition == RZ_DECOMP_FULL_PH && (opts->space == RZ_GRAD || opts->patch_solver != RZ_PATCH_CHOLESKY))
+    return fail(ctx, RZ_ERR_ARG, "RZ_DECOMP_FULL_PH: H(curl)/H(div) with exact star solves (RZ_PATCH_CHOLESKY)");
   if (opts->decomposition == RZ_DECOMP_SC_VERTEX &&
       (opts->space == RZ_GRAD || opts->patch_solver != RZ_PATCH_CHOLESKY))
     return fail(ctx, RZ_ERR_ARG,
@@ -3543,8 +3819,8 @@ static rz_status setup_impl(rz_ctx *ctx, const rz_mesh *mesh, const rz_coef *cf,
     return fail(ctx, RZ_ERR_ARG, "RZ_DECOMP_FULL on H(curl)/H(div): exact vertex-star solves (RZ_PATCH_CHOLESKY) only");
   if (opts->patch_solver == RZ_PATCH_CHOLESKY && opts->space != RZ_GRAD && opts->decomposition == RZ_DECOMP_SC)
     return fail(ctx, RZ_ERR_ARG,
-                "RZ_PATCH_CHOLESKY: H(grad) vertex stars, or the H(curl)/H(div) vertex stars (RZ_DECOMP_FULL, "
-                "RZ_DECOMP_SC_VERTEX)");
+                "RZ_PATCH_CHOLESKY: H(grad) vertex stars, or the H(curl)/H(div) stars (RZ_DECOMP_FULL, "
+                "RZ_DECOMP_SC_VERTEX, RZ_DECOMP_FULL_PH)");
   rz_problem *h = new rz_problem();
   h->ctx = ctx;
   h->opts = *opts;

@@ -31,7 +31,7 @@ EXPORT_EDGE_PATCH, EXPORT_STATS, EXPORT_PAPER_DIAG, EXPORT_AUTOTUNE, EXPORT_GRAP
 AUX_CELL_AVG, AUX_PAPER_DIAG = 0, 1
 PATCH_IC, PATCH_CHOLESKY = 0, 1
 NORM_2, NORM_NATURAL = 0, 1
-DECOMP_SC, DECOMP_FULL, DECOMP_SC_VERTEX = 0, 1, 2
+DECOMP_SC, DECOMP_FULL, DECOMP_SC_VERTEX, DECOMP_FULL_PH = 0, 1, 2, 3
 COARSE_DIRECT, COARSE_HMG = 0, 1
 KERNELS = ("apply", "condense", "patch", "expand", "transfer", "coarse", "krylov")
 STATUS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_OOM", -3: "RZ_ERR_BREAKDOWN",
