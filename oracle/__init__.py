@@ -20,6 +20,8 @@ Modules
   pmg       -- p-transfer, coarse problem, V(1,1) cycle and PCG (Sec. 4.3, 5)
   learned   -- least-squares separable fit to the broken diagonals, per-cell
                features, a hand-written NumPy MLP (forward, backward, Adam)
+  hodge     -- mixed Hodge Laplacians k = 1, 2, 3: block system, Chebyshev-accelerated
+               Riesz-map block preconditioner, preconditioned MINRES (Sec. 5.3)
   quadrature-- Gauss-Lobatto rules, sampled (triquadratic) coefficients and the
                cell-averaged separable auxiliary weights for trilinear cells
 
