@@ -320,6 +320,50 @@ rz_status rz_solve(rz_problem *h, const double *b, double *x, int32_t nrhs, rz_s
 rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const *b, double *const *x,
                            int32_t nrhs, rz_solve_info *infos);
 
+/* ---- Mixed Hodge Laplacians (Sec. 5.3) -------------------------------------------
+ * With no essential boundary, find (sigma, u) in V^{k-1} x V^k (k = 1: Q_p x NCE_p,
+ * k = 2: NCE_p x NCF_p, k = 3: NCF_p x DQ_{p-1}) with
+ *   -(tau, sigma) + (d tau, u) = 0,  (v, d sigma) + (d v, d u) = F(v),
+ * i.e. in FDM coefficients K [sigma; u] = [0; f] with
+ *   K = [ -M_{k-1}  D^T M_k ; M_k D  S_k ],
+ * M_j the beta-weighted mass of V^j, S_k the alpha-weighted (d v, d u) (zero for
+ * k = 3), D = d^{k-1} (grad, curl, div; exact in the FDM bases), and the L^2 mass of
+ * DQ_{p-1} diagonal (8 / V per value on a box of volume V).  The solver is MINRES
+ * (Paige & Saunders) preconditioned by blockdiag(C_{k-1}, C_k): C_j is cheb_steps
+ * Chebyshev iterations (the paper uses 4) on the Riesz map of problem j,
+ * preconditioned by that problem's p-multigrid V-cycle, over [0.9 lambda_min,
+ * 1.1 lambda_max] of the extreme eigenvalues of the Lanczos tridiagonal of 10
+ * V-cycle-preconditioned CG steps (start vector: SplitMix64 of the problem's
+ * lanczos_seed); for DQ_{p-1} the preconditioner is point Jacobi of the diagonal
+ * mass, whose Chebyshev interval is [0.9, 1.1].
+ * Vectors are [sigma (ndofs of lo); u (ndofs of hi, or ncells p^3 for k = 3)],
+ * FP64 device arrays; DQ_{p-1} numbering: X + n_x p (Y + n_y p Z), x fastest.
+ * The object borrows lo and hi (set up with rz_setup for the spaces of form degree
+ * k-1 and k, on the same Cartesian mesh and degree, dirichlet = 0, cellwise
+ * coefficients, FP64 protocol, the default decomposition); free it first.  Calls on
+ * one object, and on its problems, must not overlap.  The paper's setting is
+ * alpha = beta = 1 for both problems. */
+typedef struct rz_hodge rz_hodge;
+
+/* Build D and D^T (CSR on the device), the mass/stiffness weights, and the Chebyshev
+ * intervals (synchronous).  hi must be NULL exactly for k = 3.  RZ_ERR_ARG on a
+ * mismatch, RZ_ERR_OOM, RZ_ERR_BREAKDOWN if the Lanczos estimate fails. */
+rz_status rz_hodge_create(int32_t k, rz_problem *lo, rz_problem *hi, int32_t cheb_steps, rz_hodge **out);
+rz_status rz_hodge_free(rz_hodge *g);
+/* sizes[0] = ndofs of V^{k-1}, sizes[1] = of V^k; eig (may be NULL): the Ritz
+ * extremes (lo min, lo max, hi min, hi max) behind the Chebyshev intervals. */
+rz_status rz_hodge_sizes(const rz_hodge *g, int64_t sizes[2], double eig[4]);
+/* y = K x (asynchronous on the problems' stream). */
+rz_status rz_hodge_apply(rz_hodge *g, const double *x, double *y);
+/* z = blockdiag(C_{k-1}, C_k) r (asynchronous). */
+rz_status rz_hodge_precond(rz_hodge *g, const double *r, double *z);
+/* MINRES from x = 0 until the natural norm (r^T P^{-1} r)^{1/2} of the residual
+ * has dropped by rtol (the paper's criterion, 1e-8).  info (may be NULL): iters =
+ * iters_natural = MINRES iterations, rel_res = ||b - K x||_2 / ||b||_2 at exit,
+ * t_solve_ms = device time.  Synchronous; RZ_ERR_NOT_CONVERGED after maxit,
+ * RZ_ERR_BREAKDOWN if the preconditioner is not positive definite. */
+rz_status rz_hodge_solve(rz_hodge *g, const double *b, double *x, double rtol, int32_t maxit, rz_solve_info *info);
+
 /* Wait for the problem's queued work and report a coarse-solve wait that gave up.
  * The coarse solve (inside rz_coarse_solve, rz_vcycle and rz_solve) synchronises
  * its planes through bounded waits on data written in the same launch; a wait that

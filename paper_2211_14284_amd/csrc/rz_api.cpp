@@ -4656,3 +4656,509 @@ rz_status rz_timing_read(rz_problem *h, double ms[RZ_NKERNELS], int64_t count[RZ
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Mixed Hodge Laplacians (Sec. 5.3): find (sigma, u) in V^{k-1} x V^k, no essential
+// boundary, with the block operator
+//   K = [ -M_{k-1}  D^T M_k ; M_k D  S_k ]
+// (M_j the beta-weighted mass of V^j, S_k the alpha-weighted (d v, d u), D = d^{k-1}
+// in FDM coefficients), preconditioned by blockdiag(C_{k-1}, C_k), C_j a fixed number
+// of Chebyshev steps on the Riesz map A_j = M_j + S_j preconditioned by its V-cycle
+// (for V^3 = DQ_{p-1}: by point Jacobi of its diagonal mass), and solved by MINRES.
+// ---------------------------------------------------------------------------------------
+struct rz_hodge {
+  rz_ctx *ctx = nullptr;
+  int k = 0, steps = 4;
+  rz_problem *lo = nullptr, *hi = nullptr;  // hi == nullptr for k = 3
+  int64_t nlo = 0, nhi = 0;
+  double eig_lo[2] = {0, 0}, eig_hi[2] = {1, 1};
+  std::vector<void *> allocs;
+  // mass-only and stiffness-only cell weights of the two problems
+  double *cm_lo = nullptr, *cm_hi = nullptr, *cs_hi = nullptr;
+  // D and D^T in CSR (int32 offsets)
+  int *d_ptr = nullptr, *d_col = nullptr, *dt_ptr = nullptr, *dt_col = nullptr;
+  double *d_val = nullptr, *dt_val = nullptr;
+  // DQ_{p-1}: mass diagonal, Chebyshev-scaled inverse, identity row list
+  double *m3 = nullptr, *m3c = nullptr;
+  int *rows3 = nullptr;
+  double *partials = nullptr, *dots = nullptr;
+  // block temporaries and the MINRES vectors (length nlo + nhi)
+  double *tlo = nullptr, *thi = nullptr, *shi = nullptr;
+  double *cr = nullptr, *cd = nullptr, *ct = nullptr, *cz = nullptr;  // Chebyshev (max block length)
+  double *mv[10] = {};
+};
+
+namespace {
+
+template <typename T>
+rz_status hg_alloc(rz_hodge *g, T **ptr, size_t count) {
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, sizeof(T) * (count ? count : 1));
+  if (e != hipSuccess) return fail(g->ctx, RZ_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  g->allocs.push_back(p);
+  *ptr = static_cast<T *>(p);
+  return RZ_OK;
+}
+
+template <typename T>
+rz_status hg_upload(rz_hodge *g, T **ptr, const std::vector<T> &v) {
+  if (rz_status e = hg_alloc(g, ptr, v.size())) return e;
+  hipError_t e = hipMemcpyAsync(*ptr, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, g->ctx->stream);
+  if (e != hipSuccess) return fail(g->ctx, RZ_ERR_HIP, hipGetErrorString(e));
+  return RZ_OK;
+}
+
+// Per-axis kinds of component m of the space of form degree k (k = 3: DQ_{p-1}):
+// true = continuous (p n + 1 points), false = broken (p n values)
+bool hg_cont(int k, int m, int a) {
+  if (k == 0) return true;
+  if (k == 1) return a != m;
+  if (k == 2) return a == m;
+  return false;
+}
+int hg_ncomp(int k) { return (k == 0 || k == 3) ? 1 : 3; }
+
+struct HgLat {
+  int k, p, n[3];
+  int64_t off[3], ext[3][3];
+  int64_t ndofs;
+  HgLat(int k_, int p_, const int nn[3]) : k(k_), p(p_) {
+    for (int a = 0; a < 3; ++a) n[a] = nn[a];
+    int64_t o = 0;
+    for (int m = 0; m < hg_ncomp(k); ++m) {
+      off[m] = o;
+      int64_t sz = 1;
+      for (int a = 0; a < 3; ++a) {
+        ext[m][a] = (int64_t)n[a] * p + (hg_cont(k, m, a) ? 1 : 0);
+        sz *= ext[m][a];
+      }
+      o += sz;
+    }
+    ndofs = o;
+  }
+  int64_t index(int m, const int64_t X[3]) const { return off[m] + X[0] + ext[m][0] * (X[1] + ext[m][1] * X[2]); }
+};
+
+// d^{k-1}: V^{k-1} -> V^k on the lattice.  A derivative along axis a takes the
+// continuous index of the source to the broken index X_a = c p + i of the target
+// with the 1-D weights D[i][j] (the FDM derivative table); the other axes keep
+// their index.  grad: component m = d_m u; curl: component m = d_{m+1} u_{m+2} -
+// d_{m+2} u_{m+1} (indices mod 3); div: sum_m d_m u_m.
+void hg_derivative(int k, int p, const int nn[3], const std::vector<double> &Dt, std::vector<int> &ptr,
+                   std::vector<int> &col, std::vector<double> &val) {
+  HgLat src(k - 1, p, nn), dst(k, p, nn);
+  ptr.assign(1, 0);
+  col.clear();
+  val.clear();
+  for (int m = 0; m < hg_ncomp(k); ++m) {
+    // terms (sign, derivative axis, source component)
+    struct Term { double sign; int axis, comp; };
+    std::vector<Term> terms;
+    if (k == 1) terms = {{1.0, m, 0}};
+    else if (k == 2) terms = {{1.0, (m + 1) % 3, (m + 2) % 3}, {-1.0, (m + 2) % 3, (m + 1) % 3}};
+    else terms = {{1.0, 0, 0}, {1.0, 1, 1}, {1.0, 2, 2}};
+    int64_t X[3];
+    for (X[2] = 0; X[2] < dst.ext[m][2]; ++X[2])
+      for (X[1] = 0; X[1] < dst.ext[m][1]; ++X[1])
+        for (X[0] = 0; X[0] < dst.ext[m][0]; ++X[0]) {
+          for (const Term &t : terms) {
+            const int64_t c = X[t.axis] / p, i = X[t.axis] % p;
+            int64_t Y[3] = {X[0], X[1], X[2]};
+            for (int j = 0; j <= p; ++j) {
+              const double w = Dt[i * (p + 1) + j];
+              if (w == 0.0) continue;
+              Y[t.axis] = c * p + j;
+              col.push_back((int)src.index(t.comp, Y));
+              val.push_back(t.sign * w);
+            }
+          }
+          ptr.push_back((int)col.size());
+        }
+  }
+}
+
+void hg_transpose(int64_t nrows, int64_t ncols, const std::vector<int> &ptr, const std::vector<int> &col,
+                  const std::vector<double> &val, std::vector<int> &tp, std::vector<int> &tc, std::vector<double> &tv) {
+  tp.assign(ncols + 1, 0);
+  for (int c : col) tp[c + 1]++;
+  for (int64_t i = 0; i < ncols; ++i) tp[i + 1] += tp[i];
+  tc.resize(col.size());
+  tv.resize(val.size());
+  std::vector<int> pos(tp.begin(), tp.end() - 1);
+  for (int64_t r = 0; r < nrows; ++r)
+    for (int q = ptr[r]; q < ptr[r + 1]; ++q) {
+      tc[pos[col[q]]] = (int)r;
+      tv[pos[col[q]]++] = val[q];
+    }
+}
+
+// y = M x (mass) or S x (stiffness) of problem h with the weights w
+void hg_apply_w(rz_problem *h, const double *w, const double *x, double *y) {
+  Timed t(h, RZ_K_APPLY);
+  if (h->space != RZ_GRAD)
+    launch_apply_vec<double>(h->V, w, h->B64, h->D64, x, y, h->eb64, h->ctx->stream);
+  else
+    launch_apply_grad<double>(h->L, w, h->t.B.data(), h->t.A.data(), x, nullptr, y, h->eb64, h->ctx->stream);
+}
+
+rz_status hg_dot(rz_hodge *g, const double *x, const double *y, int64_t n, double *out) {
+  hipStream_t s = g->ctx->stream;
+  const double *xs[1] = {x}, *ys[1] = {y};
+  launch_dots(1, xs, ys, n, g->partials, g->dots, s);
+  hipError_t e = hipMemcpyAsync(out, g->dots, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(g->ctx, RZ_ERR_HIP, hipGetErrorString(e));
+  return RZ_OK;
+}
+
+// y = K x on [sigma; u]
+rz_status hg_apply(rz_hodge *g, const double *x, double *y) {
+  hipStream_t s = g->ctx->stream;
+  const double *xs = x, *xu = x + g->nlo;
+  double *ys = y, *yu = y + g->nlo;
+  const int nlo = (int)g->nlo, nhi = (int)g->nhi;
+  // t_hi = M_k u ; y_sigma = D^T t_hi - M_{k-1} sigma
+  if (g->hi) hg_apply_w(g->hi, g->cm_hi, xu, g->thi);
+  else launch_rows_scale<double>(nhi, g->rows3, g->m3, xu, g->thi, s);
+  launch_csr<double, double, double>(nlo, nullptr, g->dt_ptr, g->dt_col, g->dt_val, g->thi, ys, 0, s);
+  hg_apply_w(g->lo, g->cm_lo, xs, g->tlo);
+  launch_axpy(-1.0, g->tlo, ys, g->nlo, s);
+  // y_u = M_k D sigma + S_k u
+  launch_csr<double, double, double>(nhi, nullptr, g->d_ptr, g->d_col, g->d_val, xs, g->shi, 0, s);
+  if (g->hi) {
+    hg_apply_w(g->hi, g->cm_hi, g->shi, yu);
+    hg_apply_w(g->hi, g->cs_hi, xu, g->thi);
+    launch_axpy(1.0, g->thi, yu, g->nhi, s);
+  } else {
+    launch_rows_scale<double>(nhi, g->rows3, g->m3, g->shi, yu, s);
+  }
+  return RZ_OK;
+}
+
+// x = steps Chebyshev iterations on A x = f (problem h's Riesz map, its V-cycle as
+// the preconditioner) for the spectrum [lmin, lmax] of B A, from x = 0
+rz_status hg_cheb(rz_hodge *g, rz_problem *h, double lmin, double lmax, const double *f, double *x) {
+  hipStream_t s = g->ctx->stream;
+  const int64_t n = h->ndofs;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  if (rz_status e = do_vcycle(h, f, g->cz)) return e;
+  launch_scale_copy(1.0 / theta, g->cz, g->cd, n, s);  // d = B f / theta
+  hipError_t he = hipMemcpyAsync(g->cr, f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+  if (he != hipSuccess) return fail(g->ctx, RZ_ERR_HIP, hipGetErrorString(he));
+  for (int j = 0; j < g->steps; ++j) {
+    if (j == 0) launch_scale_copy(1.0, g->cd, x, n, s);
+    else launch_axpy(1.0, g->cd, x, n, s);
+    if (j + 1 == g->steps) break;
+    if (rz_status e = do_apply64(h, g->cd, g->ct)) return e;
+    launch_axpy(-1.0, g->ct, g->cr, n, s);  // r -= A d
+    const double rho_next = 1.0 / (2.0 * sigma - rho);
+    if (rz_status e = do_vcycle(h, g->cr, g->cz)) return e;
+    launch_scale_copy(rho_next * rho, g->cd, g->cd, n, s);
+    launch_axpy(2.0 * rho_next / delta, g->cz, g->cd, n, s);
+    rho = rho_next;
+  }
+  return RZ_OK;
+}
+
+// z = blockdiag(C_{k-1}, C_k) r
+rz_status hg_precond(rz_hodge *g, const double *r, double *z) {
+  if (rz_status e = hg_cheb(g, g->lo, 0.9 * g->eig_lo[0], 1.1 * g->eig_lo[1], r, z)) return e;
+  if (g->hi) return hg_cheb(g, g->hi, 0.9 * g->eig_hi[0], 1.1 * g->eig_hi[1], r + g->nlo, z + g->nlo);
+  // L^2: B A = I, so the steps reduce to z = q M^{-1} r with q = 1 - p(1) for the
+  // Chebyshev polynomial p of the interval [0.9, 1.1] (m3c holds q / diag)
+  launch_rows_scale<double>((int)g->nhi, g->rows3, g->m3c, r + g->nlo, z + g->nlo, g->ctx->stream);
+  return RZ_OK;
+}
+
+// extreme eigenvalues of (V-cycle) A from the Lanczos tridiagonal of 10 preconditioned CG
+// steps from the SplitMix64 start vector of the problem's lanczos_seed
+rz_status hg_extremes(rz_hodge *g, rz_problem *h, double out[2]) {
+  hipStream_t s = g->ctx->stream;
+  const int64_t n = h->ndofs;
+  std::vector<double> v0(n);
+  uint64_t st = h->opts.lanczos_seed;
+  for (int64_t i = 0; i < n; ++i) v0[i] = 2.0 * ((double)(splitmix_next(st) >> 11) * 0x1.0p-53) - 1.0;
+  double *r = g->cr, *z = g->cz, *d = g->cd, *Ad = g->ct;
+  hipError_t he = hipMemcpyAsync(r, v0.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
+  if (he != hipSuccess) return fail(g->ctx, RZ_ERR_HIP, hipGetErrorString(he));
+  if (rz_status e = do_vcycle(h, r, z)) return e;
+  launch_scale_copy(1.0, z, d, n, s);
+  double rz_;
+  if (rz_status e = hg_dot(g, r, z, n, &rz_)) return e;
+  std::vector<double> diag, off;
+  double a_prev = 0, b_prev = 0;
+  for (int it = 0; it < 10; ++it) {
+    if (rz_status e = do_apply64(h, d, Ad)) return e;
+    double dAd;
+    if (rz_status e = hg_dot(g, d, Ad, n, &dAd)) return e;
+    if (!(dAd > 0)) break;
+    const double a = rz_ / dAd;
+    launch_axpy(-a, Ad, r, n, s);
+    if (rz_status e = do_vcycle(h, r, z)) return e;
+    double rzn;
+    if (rz_status e = hg_dot(g, r, z, n, &rzn)) return e;
+    const double b = rzn / rz_;
+    diag.push_back(1.0 / a + (it > 0 ? b_prev / a_prev : 0.0));
+    off.push_back(std::sqrt(b) / a);
+    a_prev = a;
+    b_prev = b;
+    rz_ = rzn;
+    launch_xpby(z, b, d, n, s);
+    if (!(rzn > 0)) break;
+  }
+  if (diag.empty()) return fail(g->ctx, RZ_ERR_BREAKDOWN, "rz_hodge: Lanczos estimate failed");
+  off.resize(diag.size() > 1 ? diag.size() - 1 : 1, 0.0);
+  if (diag.size() == 1) off[0] = 0.0;
+  std::vector<double> neg(diag.size());
+  for (size_t i = 0; i < diag.size(); ++i) neg[i] = -diag[i];
+  out[1] = tridiag_max_eig(diag, off);
+  out[0] = -tridiag_max_eig(neg, off);
+  return RZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rz_status rz_hodge_create(int32_t k, rz_problem *lo, rz_problem *hi, int32_t cheb_steps, rz_hodge **out) {
+  if (!out) return RZ_ERR_ARG;
+  *out = nullptr;
+  rz_status e = require_device(lo);
+  if (e) return e;
+  rz_ctx *ctx = lo->ctx;
+  if (k < 1 || k > 3) return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: k must be 1, 2 or 3");
+  if (cheb_steps < 1 || cheb_steps > 64) return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: cheb_steps in 1..64");
+  if ((k == 3) != (hi == nullptr)) return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: hi is null exactly for k = 3");
+  if (lo->space != k - 1 || (hi && hi->space != k))
+    return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: lo must be the space of form degree k-1, hi of degree k");
+  for (rz_problem *h : {lo, hi}) {
+    if (!h) continue;
+    if (h->ctx != ctx) return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: problems on different contexts");
+    if (h->dir != 0) return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: no essential boundary (dirichlet = 0) expected");
+    if (h->quad) return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: Cartesian cells with cellwise coefficients only");
+    if (h->opts.precision != RZ_PREC_F64 || h->opts.decomposition != RZ_DECOMP_SC)
+      return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: FP64 problems with the condensed decomposition expected");
+    if (h->p != lo->p || h->nx != lo->nx || h->ny != lo->ny || h->nz != lo->nz)
+      return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: lo and hi on different meshes or degrees");
+  }
+  if (lo->p < 1) return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: degree");
+  auto *g = new rz_hodge;
+  g->ctx = ctx;
+  g->k = k;
+  g->steps = cheb_steps;
+  g->lo = lo;
+  g->hi = hi;
+  g->nlo = lo->ndofs;
+  const int nn[3] = {lo->nx, lo->ny, lo->nz};
+  g->nhi = hi ? hi->ndofs : (int64_t)lo->ncells * lo->p * lo->p * lo->p;
+  auto bail = [&](rz_status st) { rz_hodge_free(g); return st; };
+  if (g->nlo + g->nhi >= (int64_t)1 << 31) return bail(fail(ctx, RZ_ERR_ARG, "rz_hodge_create: too many DoFs"));
+  hipStream_t s = ctx->stream;
+  // cell weights: [alpha-part x3, beta-part x3] per cell; mass keeps beta, stiffness alpha
+  auto split = [&](rz_problem *h, bool mass) {
+    std::vector<double> w(h->coef);
+    for (size_t c = 0; c < w.size(); c += 6)
+      for (int d = 0; d < 3; ++d) w[c + (mass ? d : 3 + d)] = 0.0;
+    return w;
+  };
+  if ((e = hg_upload(g, &g->cm_lo, split(lo, true)))) return bail(e);
+  if (hi && ((e = hg_upload(g, &g->cm_hi, split(hi, true))) || (e = hg_upload(g, &g->cs_hi, split(hi, false)))))
+    return bail(e);
+  // D and D^T
+  std::vector<int> ptr, col, tp, tc;
+  std::vector<double> val, tv;
+  hg_derivative(k, lo->p, nn, lo->t.D, ptr, col, val);
+  if ((int64_t)ptr.size() != g->nhi + 1) return bail(fail(ctx, RZ_ERR_ARG, "rz_hodge_create: D rows"));
+  hg_transpose(g->nhi, g->nlo, ptr, col, val, tp, tc, tv);
+  if ((e = hg_upload(g, &g->d_ptr, ptr)) || (e = hg_upload(g, &g->d_col, col)) || (e = hg_upload(g, &g->d_val, val)) ||
+      (e = hg_upload(g, &g->dt_ptr, tp)) || (e = hg_upload(g, &g->dt_col, tc)) || (e = hg_upload(g, &g->dt_val, tv)))
+    return bail(e);
+  if (!hi) {
+    // DQ_{p-1} mass: 8 / V per value (3-form Piola map, L^2-orthonormal broken basis)
+    const int p = lo->p;
+    HgLat l3(3, p, nn);
+    std::vector<double> m3(g->nhi), m3c(g->nhi);
+    std::vector<int> rows(g->nhi);
+    const double th = 1.0, dl = 0.1, sg = th / dl;  // interval [0.9, 1.1]
+    // q = 1 - p(1) evaluated by running the scalar recurrence itself (A = B = 1)
+    {
+      double x = 0, r = 1, d = 1.0 / th, rh = 1.0 / sg;
+      for (int j = 0; j < g->steps; ++j) {
+        x += d;
+        if (j + 1 == g->steps) break;
+        r -= d;
+        const double rn = 1.0 / (2.0 * sg - rh);
+        d = rn * rh * d + (2.0 * rn / dl) * r;
+        rh = rn;
+      }
+      for (int64_t c = 0; c < lo->ncells; ++c) {
+        const int cx = c % lo->nx, cy = (c / lo->nx) % lo->ny, cz = c / ((int64_t)lo->nx * lo->ny);
+        const int nvx = lo->nx + 1, nvy = lo->ny + 1;
+        const double hs[3] = {lo->vert[3 * (cx + 1)] - lo->vert[3 * cx],
+                              lo->vert[3 * ((cy + 1) * nvx) + 1] - lo->vert[3 * (cy * nvx) + 1],
+                              lo->vert[3 * ((int64_t)(cz + 1) * nvx * nvy) + 2] -
+                                  lo->vert[3 * ((int64_t)cz * nvx * nvy) + 2]};
+        const double w = 8.0 / (hs[0] * hs[1] * hs[2]);
+        for (int zc = 0; zc < p; ++zc)
+          for (int yc = 0; yc < p; ++yc)
+            for (int xc = 0; xc < p; ++xc) {
+              const int64_t X[3] = {(int64_t)cx * p + xc, (int64_t)cy * p + yc, (int64_t)cz * p + zc};
+              const int64_t gi = l3.index(0, X);
+              m3[gi] = w;
+              m3c[gi] = x / w;
+            }
+      }
+    }
+    for (int64_t i = 0; i < g->nhi; ++i) rows[i] = (int)i;
+    if ((e = hg_upload(g, &g->m3, m3)) || (e = hg_upload(g, &g->m3c, m3c)) || (e = hg_upload(g, &g->rows3, rows)))
+      return bail(e);
+  }
+  const int64_t nmax = std::max(g->nlo, g->nhi), N = g->nlo + g->nhi;
+  if ((e = hg_alloc(g, &g->partials, dots_partials_size())) || (e = hg_alloc(g, &g->dots, 4)) ||
+      (e = hg_alloc(g, &g->tlo, g->nlo)) || (e = hg_alloc(g, &g->thi, g->nhi)) || (e = hg_alloc(g, &g->shi, g->nhi)) ||
+      (e = hg_alloc(g, &g->cr, nmax)) || (e = hg_alloc(g, &g->cd, nmax)) || (e = hg_alloc(g, &g->ct, nmax)) ||
+      (e = hg_alloc(g, &g->cz, nmax)))
+    return bail(e);
+  for (double *&v : g->mv)
+    if ((e = hg_alloc(g, &v, N))) return bail(e);
+  if ((e = hg_extremes(g, lo, g->eig_lo))) return bail(e);
+  if (hi && (e = hg_extremes(g, hi, g->eig_hi))) return bail(e);
+  if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(ctx, RZ_ERR_HIP, "rz_hodge_create: stream"));
+  *out = g;
+  return RZ_OK;
+}
+
+rz_status rz_hodge_free(rz_hodge *g) {
+  if (!g) return RZ_OK;
+  hipStreamSynchronize(g->ctx->stream);
+  for (void *p : g->allocs) hipFree(p);
+  delete g;
+  return RZ_OK;
+}
+
+rz_status rz_hodge_sizes(const rz_hodge *g, int64_t sizes[2], double eig[4]) {
+  if (!g || !sizes) return RZ_ERR_ARG;
+  sizes[0] = g->nlo;
+  sizes[1] = g->nhi;
+  if (eig) {
+    eig[0] = g->eig_lo[0];
+    eig[1] = g->eig_lo[1];
+    eig[2] = g->eig_hi[0];
+    eig[3] = g->eig_hi[1];
+  }
+  return RZ_OK;
+}
+
+rz_status rz_hodge_apply(rz_hodge *g, const double *x, double *y) {
+  if (!g || !x || !y || x == y) return g ? fail(g->ctx, RZ_ERR_ARG, "rz_hodge_apply: bad vectors") : RZ_ERR_ARG;
+  return hg_apply(g, x, y);
+}
+
+rz_status rz_hodge_precond(rz_hodge *g, const double *r, double *z) {
+  if (!g || !r || !z || r == z) return g ? fail(g->ctx, RZ_ERR_ARG, "rz_hodge_precond: bad vectors") : RZ_ERR_ARG;
+  return hg_precond(g, r, z);
+}
+
+rz_status rz_hodge_solve(rz_hodge *g, const double *b, double *x, double rtol, int32_t maxit, rz_solve_info *info) {
+  if (!g || !b || !x || b == x || !(rtol > 0) || maxit < 1)
+    return g ? fail(g->ctx, RZ_ERR_ARG, "rz_hodge_solve: bad arguments") : RZ_ERR_ARG;
+  rz_ctx *ctx = g->ctx;
+  hipStream_t s = ctx->stream;
+  const int64_t N = g->nlo + g->nhi;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  hipEventRecord(e0, s);
+  double *v_prev = g->mv[0], *v = g->mv[1], *kz = g->mv[2], *z = g->mv[3], *z_next = g->mv[4];
+  double *w_prev = g->mv[5], *w = g->mv[6], *tmp = g->mv[7];
+  rz_status st = RZ_OK;
+  int it = 0;
+  double eta = 0, phi0 = 0;
+  auto run = [&]() -> rz_status {
+    hipError_t he;
+    if ((he = hipMemsetAsync(x, 0, sizeof(double) * N, s)) != hipSuccess ||
+        (he = hipMemsetAsync(v_prev, 0, sizeof(double) * N, s)) != hipSuccess ||
+        (he = hipMemsetAsync(w_prev, 0, sizeof(double) * N, s)) != hipSuccess ||
+        (he = hipMemsetAsync(w, 0, sizeof(double) * N, s)) != hipSuccess ||
+        (he = hipMemcpyAsync(v, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return fail(ctx, RZ_ERR_HIP, hipGetErrorString(he));
+    rz_status e;
+    if ((e = hg_precond(g, v, z))) return e;
+    double g2;
+    if ((e = hg_dot(g, v, z, N, &g2))) return e;
+    if (!(g2 > 0)) return g2 == 0 ? RZ_OK : fail(ctx, RZ_ERR_BREAKDOWN, "rz_hodge_solve: indefinite preconditioner");
+    double gamma = std::sqrt(g2), gamma_prev = 1.0;
+    double c = 1, c_prev = 1, sn = 0, s_prev = 0;
+    eta = phi0 = gamma;
+    while (it < maxit && std::fabs(eta) > rtol * phi0) {
+      ++it;
+      launch_scale_copy(1.0 / gamma, z, z, N, s);
+      if ((e = hg_apply(g, z, kz))) return e;
+      double delta;
+      if ((e = hg_dot(g, kz, z, N, &delta))) return e;
+      launch_axpy(-delta / gamma, v, kz, N, s);
+      launch_axpy(-gamma / gamma_prev, v_prev, kz, N, s);  // kz now holds v_next
+      if ((e = hg_precond(g, kz, z_next))) return e;
+      double gn2;
+      if ((e = hg_dot(g, kz, z_next, N, &gn2))) return e;
+      if (gn2 < 0) return fail(ctx, RZ_ERR_BREAKDOWN, "rz_hodge_solve: indefinite preconditioner");
+      const double gamma_next = std::sqrt(gn2);
+      const double a0 = c * delta - c_prev * sn * gamma;
+      const double a1 = std::hypot(a0, gamma_next);
+      const double a2 = sn * delta + c_prev * c * gamma;
+      const double a3 = s_prev * gamma;
+      c_prev = c;
+      c = a0 / a1;
+      s_prev = sn;
+      sn = gamma_next / a1;
+      // w_next = (z - a3 w_prev - a2 w) / a1, written over w_prev
+      launch_scale_copy(-a3 / a1, w_prev, w_prev, N, s);
+      launch_axpy(1.0 / a1, z, w_prev, N, s);
+      launch_axpy(-a2 / a1, w, w_prev, N, s);
+      std::swap(w_prev, w);  // w = w_next, w_prev = old w
+      launch_axpy(c * eta, w, x, N, s);
+      eta = -sn * eta;
+      // rotate: v_prev <- v, v <- v_next (in kz); the old v_prev buffer takes the next A z
+      double *old = v_prev;
+      v_prev = v;
+      v = kz;
+      kz = old;
+      std::swap(z, z_next);
+      gamma_prev = gamma;
+      gamma = gamma_next;
+      if (gamma == 0) break;
+    }
+    return RZ_OK;
+  };
+  st = run();
+  double rel = -1;
+  if (st == RZ_OK) {
+    // true residual ||b - K x|| / ||b||
+    rz_status e = hg_apply(g, x, tmp);
+    if (!e) {
+      launch_axpy(-1.0, b, tmp, N, s);
+      double rr = 0, bb = 0;
+      if (!(e = hg_dot(g, tmp, tmp, N, &rr)) && !(e = hg_dot(g, b, b, N, &bb))) rel = bb > 0 ? std::sqrt(rr / bb) : 0;
+    }
+    st = e;
+  }
+  hipEventRecord(e1, s);
+  hipEventSynchronize(e1);
+  float ms = 0;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st == RZ_OK && std::fabs(eta) > rtol * phi0) st = RZ_ERR_NOT_CONVERGED;
+  if (info) {
+    info->iters = it;
+    info->status = st;
+    info->rel_res = rel;
+    info->omega = 0.0;
+    info->t_solve_ms = ms;
+    info->iters_natural = it;
+  }
+  return st;
+}
+
+}  // extern "C"

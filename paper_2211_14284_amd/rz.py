@@ -95,6 +95,12 @@ _proto = {
     "rz_solve_batched": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_vp),
                                         ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(SolveInfo)]),
     "rz_set_aux": (ctypes.c_int, [_vp, _vp]),
+    "rz_hodge_create": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)]),
+    "rz_hodge_free": (ctypes.c_int, [_vp]),
+    "rz_hodge_sizes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
+    "rz_hodge_apply": (ctypes.c_int, [_vp, _vp, _vp]),
+    "rz_hodge_precond": (ctypes.c_int, [_vp, _vp, _vp]),
+    "rz_hodge_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SolveInfo)]),
     "rz_mlp_create": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                      ctypes.POINTER(_vp)]),
     "rz_mlp_free": (ctypes.c_int, [_vp]),
@@ -121,11 +127,12 @@ _live = weakref.WeakSet()
 
 
 def close_all():
-    """Free every live problem and MLP, then every context (also run at exit)."""
+    """Free every live Hodge solver, then every problem and MLP, then every context
+    (also run at exit)."""
     objs = list(_live)
-    for last in (False, True):
+    for rank in (0, 1, 2):
         for o in objs:
-            if isinstance(o, Context) == last:
+            if (2 if isinstance(o, Context) else 0 if isinstance(o, Hodge) else 1) == rank:
                 try:
                     o.close()
                 except RzError:
@@ -417,6 +424,51 @@ class Problem:
 
     def __del__(self, _finalizing=sys.is_finalizing):
         # the default argument keeps the check usable when module globals are gone
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hodge:
+    """Mixed Hodge Laplacian k in {1, 2, 3} on two set-up problems (rz_hodge_*):
+    ``Hodge(k, lo, hi, cheb_steps=4)`` with lo of form degree k-1 and hi of degree k
+    (None for k = 3), both with dirichlet=0.  Vectors are [sigma; u] of length
+    n_lo + n_hi."""
+
+    def __init__(self, k, lo, hi=None, cheb_steps=4):
+        self.ctx, self.lo, self.hi = lo.ctx, lo, hi
+        self.handle = _vp()
+        self.ctx.check(lib.rz_hodge_create(k, lo.handle, hi.handle if hi is not None else None, cheb_steps,
+                                           ctypes.byref(self.handle)))
+        s = (ctypes.c_int64 * 2)()
+        e = (ctypes.c_double * 4)()
+        self.ctx.check(lib.rz_hodge_sizes(self.handle, s, e))
+        self.n_lo, self.n_hi = int(s[0]), int(s[1])
+        self.eig = list(e)
+        _live.add(self)
+
+    def apply(self, x, y):
+        self.ctx.check(lib.rz_hodge_apply(self.handle, _ptr(x), _ptr(y)))
+
+    def precond(self, r, z):
+        self.ctx.check(lib.rz_hodge_precond(self.handle, _ptr(r), _ptr(z)))
+
+    def solve(self, b, x, rtol=1e-8, maxit=500, check=True):
+        info = SolveInfo()
+        code = lib.rz_hodge_solve(self.handle, _ptr(b), _ptr(x), rtol, maxit, ctypes.byref(info))
+        if check:
+            self.ctx.check(code)
+        return info
+
+    def close(self):
+        if self.handle:
+            lib.rz_hodge_free(self.handle)
+            self.handle = _vp()
+
+    def __del__(self, _finalizing=sys.is_finalizing):
         if _finalizing():
             return
         try:
