@@ -437,6 +437,53 @@ def bench_table_hgrad_iter(torch, rz, ctx):
     return out
 
 
+# Table hodge-iter, Cartesian columns: (p, l) -> MINRES iterations for k = 1, 2, 3
+PAPER_HODGE_ITER = {(3, 0): (9, 8, 8), (3, 1): (9, 7, 8), (7, 0): (9, 8, 8), (7, 1): (9, 8, 8)}
+
+
+def bench_hodge(torch, rz, ctx, cases=((3, 0), (3, 1), (7, 0), (7, 1))):
+    """Mixed Hodge Laplacians (Sec. 5.3, Table hodge-iter, Cartesian columns): no
+    essential boundary, right-hand side [0; A_k w] (the Riesz representative of a
+    random w in V^k, w from U[-1,1) seed 7; for k = 3 A_3 = M_3 = 8 n^3 I on the unit
+    cube), MINRES with 4 Chebyshev steps per block preconditioned by each Riesz map's
+    V-cycle (alpha = beta = 1), natural-norm reduction 1e-8.  l = 0 is 6^3 cells, l = 1
+    12^3 (as for the other iteration tables).  Setup (two Riesz-map problems and the
+    Chebyshev intervals) is outside the timed solve."""
+    import synth
+    sp_ = ["grad", "curl", "div"]
+    out = {"workload": "Table hodge-iter (Cartesian): MINRES, blockdiag Riesz-map preconditioner, "
+                       "4 Chebyshev steps per block, natural-norm 1e-8", "rows": []}
+    for p, l in cases:
+        n = 6 * 2 ** l
+        row = {"p": p, "l": l, "cells": n ** 3}
+        for k in (1, 2, 3):
+            t0 = time.time()
+            lo = rz.Problem(ctx, n, p, 1.0, 1.0, space=sp_[k - 1], dirichlet=0)
+            hi = rz.Problem(ctx, n, p, 1.0, 1.0, space=sp_[k], dirichlet=0) if k < 3 else None
+            hg = rz.Hodge(k, lo, hi, 4)
+            setup_s = time.time() - t0
+            w = torch.as_tensor(synth.uniform_pm1(7, hg.n_hi), device="cuda:0")
+            b = torch.zeros(hg.n_lo + hg.n_hi, dtype=torch.float64, device="cuda:0")
+            if hi is not None:
+                hi.apply(w, b[hg.n_lo:])
+            else:
+                b[hg.n_lo:] = 8.0 * n ** 3 * w
+            x = torch.empty_like(b)
+            hg.solve(b, x)
+            info = hg.solve(b, x)
+            row[f"k{k}"] = {"ndofs": hg.n_lo + hg.n_hi, "iters": info.iters, "solve_ms": round(info.t_solve_ms, 3),
+                            "rel_res_2norm": info.rel_res, "setup_s": round(setup_s, 2),
+                            "ritz_lo_hi": [round(e, 4) for e in hg.eig]}
+            hg.close()
+            lo.close()
+            if hi is not None:
+                hi.close()
+        row["paper_k1_k2_k3"] = list(PAPER_HODGE_ITER[(p, l)])
+        out["rows"].append(row)
+        log(f"table hodge-iter p={p} l={l}: {row}")
+    return out
+
+
 def bench_c3(torch, rz, ctx, steps, warmup, n=16, p=6):
     """C3: H(curl) NCE_6 on a uniform 16^3 mesh, alpha = beta = 1: applies and PCG in
     the three precision protocols (FP64, FP32 relaxation, FP32 operator)."""
@@ -823,7 +870,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--p", type=int, default=7)
-    ap.add_argument("--only", choices=["c2", "c2-apply", "c2-relax", "c3", "c3-apply", "c5-apply", "table", "hmg"],
+    ap.add_argument("--only", choices=["c2", "c2-apply", "c2-relax", "c3", "c3-apply", "c5-apply", "table", "hmg", "hodge"],
                     default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -832,6 +879,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-table", action="store_true", help="skip the Table hgrad-iter iteration study")
     ap.add_argument("--no-hmg", action="store_true", help="skip the h-multigrid coarse-solver study")
+    ap.add_argument("--no-hodge", action="store_true", help="skip the Hodge-Laplacian MINRES study")
     ap.add_argument("--nrhs", type=int, default=4, help="right-hand sides of the C2 multi-vector solve (1: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB once before the solves (outside the timed region), a plain copy "
@@ -890,6 +938,8 @@ def main():
             res = bench_table_hgrad_iter(torch, rz, ctx)
         elif piece == "hmg":
             res = bench_hmg(torch, rz, ctx, args.steps, args.warmup)
+        elif piece == "hodge":
+            res = bench_hodge(torch, rz, ctx)
         elif piece == "c3-apply":
             pb = rz.Problem(ctx, 16, 6, 1.0, 1.0, space="curl", omega=0.3)
             res["apply_ms_f64"] = time_apply(torch, pb, torch.float64, rz.F64, reps=args.steps)
@@ -920,6 +970,8 @@ def main():
         out["table_hgrad_iter"] = bench_table_hgrad_iter(torch, rz, ctx)
     if not args.no_hmg:
         out["hmg_coarse"] = bench_hmg(torch, rz, ctx, max(1, args.steps // 3), 1)
+    if not args.no_hodge:
+        out["table_hodge_iter"] = bench_hodge(torch, rz, ctx)
     if not args.no_c5:
         out["c5"] = bench_c5(torch, rz, ctx, max(1, args.steps // 2), 1)
     if not args.no_batched:
