@@ -340,9 +340,13 @@ rz_status rz_solve_batched(rz_problem *const *hs, int32_t n, const double *const
  * FP64 device arrays; DQ_{p-1} numbering: X + n_x p (Y + n_y p Z), x fastest.
  * The object borrows lo and hi (set up with rz_setup for the spaces of form degree
  * k-1 and k, on the same Cartesian mesh and degree, dirichlet = 0, cellwise
- * coefficients, FP64 protocol, the default decomposition); free it first.  Calls on
- * one object, and on its problems, must not overlap.  The paper's setting is
- * alpha = beta = 1 for both problems. */
+ * coefficients, the default decomposition); free it first.  Calls on one object, and
+ * on its problems, must not overlap.  The paper's setting is alpha = beta = 1 for
+ * both problems.  A problem set up with RZ_PREC_MIXED relaxes in FP32 inside its
+ * V-cycles (and uses the FP32 copies of its coarse blocks); MINRES, the block
+ * operator, the Chebyshev recurrences and the Lanczos intervals stay FP64, and the
+ * preconditioner is then symmetric up to FP32 rounding.  RZ_PREC_DEFECT problems are
+ * rejected. */
 typedef struct rz_hodge rz_hodge;
 
 /* Build D and D^T (CSR on the device), the mass/stiffness weights, and the Chebyshev

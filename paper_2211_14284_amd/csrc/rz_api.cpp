@@ -4937,8 +4937,9 @@ rz_status rz_hodge_create(int32_t k, rz_problem *lo, rz_problem *hi, int32_t che
     if (h->ctx != ctx) return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: problems on different contexts");
     if (h->dir != 0) return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: no essential boundary (dirichlet = 0) expected");
     if (h->quad) return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: Cartesian cells with cellwise coefficients only");
-    if (h->opts.precision != RZ_PREC_F64 || h->opts.decomposition != RZ_DECOMP_SC)
-      return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: FP64 problems with the condensed decomposition expected");
+    if (h->opts.precision == RZ_PREC_DEFECT || h->opts.decomposition != RZ_DECOMP_SC)
+      return fail(ctx, RZ_ERR_ARG,
+                  "rz_hodge_create: FP64 or mixed-protocol problems with the condensed decomposition expected");
     if (h->p != lo->p || h->nx != lo->nx || h->ny != lo->ny || h->nz != lo->nz)
       return fail(ctx, RZ_ERR_ARG, "rz_hodge_create: lo and hi on different meshes or degrees");
   }

@@ -49,9 +49,10 @@ def close(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b), np.abs(a - b).max() / np.abs(b).max()
 
 
-def build(rz, ctx, k, n, p, vertices=None):
-    lo = rz.Problem(ctx, n, p, 1.0, 1.0, space=SPACE[k - 1], vertices=vertices, dirichlet=0)
-    hi = rz.Problem(ctx, n, p, 1.0, 1.0, space=SPACE[k], vertices=vertices, dirichlet=0) if k < 3 else None
+def build(rz, ctx, k, n, p, vertices=None, precision=0):
+    lo = rz.Problem(ctx, n, p, 1.0, 1.0, space=SPACE[k - 1], vertices=vertices, dirichlet=0, precision=precision)
+    hi = rz.Problem(ctx, n, p, 1.0, 1.0, space=SPACE[k], vertices=vertices, dirichlet=0,
+                    precision=precision) if k < 3 else None
     return lo, hi, rz.Hodge(k, lo, hi)
 
 
@@ -109,6 +110,23 @@ def test_hodge_solve_parity(rz, ctx, k, n, p):
     release(hg, lo, hi)
 
 
+@pytest.mark.parametrize("k,n,p", [(1, (3, 3, 3), 3), (2, (3, 2, 3), 4), (3, (3, 3, 3), 3)])
+def test_hodge_mixed_precision_solve(rz, ctx, k, n, p):
+    # FP32 relaxation inside the V-cycles: the same solution to the FP64 tolerance of
+    # the direct solve, at most two MINRES iterations more than the FP64 oracle
+    print(f"hodge mixed solve k={k} n={n} p={p}", flush=True)
+    sysm, P, b, x_ref, it_ref, hist = hodge.hodge_solve(Mesh(*n, dirichlet=0), k, p)
+    lo, hi, hg = build(rz, ctx, k, n, p, precision=1)
+    x = torch.empty(b.size, dtype=torch.float64, device="cuda:0")
+    info = hg.solve(T(b), x)
+    xg = H(x)
+    xs = spla.spsolve(sysm.K.tocsc(), b)
+    assert info.iters <= it_ref + 2
+    assert np.linalg.norm(xg - xs) <= 1e-6 * np.linalg.norm(xs)
+    assert np.linalg.norm(b - sysm.K @ xg) <= 1e-6 * np.linalg.norm(b)
+    release(hg, lo, hi)
+
+
 def test_hodge_rejects_bad_arguments(rz, ctx):
     lo = rz.Problem(ctx, 2, 2, 1.0, 1.0, space="div", dirichlet=0)
     hi = rz.Problem(ctx, 2, 2, 1.0, 1.0, space="curl", dirichlet=0)
@@ -119,6 +137,10 @@ def test_hodge_rejects_bad_arguments(rz, ctx):
     dd = rz.Problem(ctx, 2, 2, 1.0, 1.0, space="div")   # Dirichlet boundary
     with pytest.raises(rz.RzError):
         rz.Hodge(3, dd, None)
+    df = rz.Problem(ctx, 2, 2, 1.0, 1.0, space="div", dirichlet=0, precision=2)   # defect correction
+    with pytest.raises(rz.RzError):
+        rz.Hodge(3, df, None)
+    df.close()
     hg = rz.Hodge(3, lo, None)
     b = torch.zeros(hg.n_lo + hg.n_hi, dtype=torch.float64, device="cuda:0")
     b[-1] = 1.0
