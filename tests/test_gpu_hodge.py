@@ -90,6 +90,38 @@ def test_hodge_apply_and_precond_parity(rz, ctx, k, n, p):
     release(hg, lo, hi)
 
 
+@pytest.mark.parametrize("k,n,p", [(1, (6, 5, 4), 4), (2, (5, 4, 3), 4), (3, (6, 5, 4), 4), (3, (4, 3, 5), 6),
+                                   (2, (2, 3, 2), 7)])
+def test_hodge_apply_parity_larger(rz, ctx, k, n, p):
+    # several cells per axis, unequal counts, graded cells: the block operator entry by entry
+    print(f"hodge apply k={k} n={n} p={p}", flush=True)
+    v = graded(n)
+    sysm = hodge.HodgeSystem(Mesh(*n, vertices=v, dirichlet=0), k, p)
+    lo, hi, hg = build(rz, ctx, k, n, p, v)
+    N = sysm.n_lo + sysm.n_hi
+    x = synth.uniform_pm1(23, N)
+    y = torch.empty(N, dtype=torch.float64, device="cuda:0")
+    hg.apply(T(x), y)
+    e2, emax = close(H(y), sysm.K @ x)
+    assert e2 < 1e-12 and emax < 1e-12
+    release(hg, lo, hi)
+
+
+def test_hodge_precond_parity_medium(rz, ctx):
+    k, n, p = 2, (4, 3, 4), 3
+    print(f"hodge precond k={k} n={n} p={p}", flush=True)
+    sysm = hodge.HodgeSystem(Mesh(*n, dirichlet=0), k, p)
+    P = hodge.HodgePreconditioner(sysm, 4)
+    lo, hi, hg = build(rz, ctx, k, n, p)
+    N = sysm.n_lo + sysm.n_hi
+    r = synth.uniform_pm1(24, N)
+    z = torch.empty(N, dtype=torch.float64, device="cuda:0")
+    hg.precond(T(r), z)
+    e2, emax = close(H(z), P(r))
+    assert e2 < 1e-10 and emax < 1e-10
+    release(hg, lo, hi)
+
+
 @pytest.mark.parametrize("k,n,p", [(1, (3, 3, 3), 3), (2, (3, 3, 3), 3), (3, (3, 3, 3), 3), (3, (2, 3, 2), 4)])
 def test_hodge_solve_parity(rz, ctx, k, n, p):
     print(f"hodge solve k={k} n={n} p={p}", flush=True)
