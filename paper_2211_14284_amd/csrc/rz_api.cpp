@@ -4850,8 +4850,9 @@ rz_status hg_cheb(rz_hodge *g, rz_problem *h, double lmin, double lmax, const do
     if (j == 0) launch_scale_copy(1.0, g->cd, x, n, s);
     else launch_axpy(1.0, g->cd, x, n, s);
     if (j + 1 == g->steps) break;
-    if (rz_status e = do_apply64(h, g->cd, g->ct)) return e;
-    launch_axpy(-1.0, g->ct, g->cr, n, s);  // r -= A d
+    // r <- r - A d, fused into the apply's stores (into the spare buffer, then swapped)
+    if (rz_status e = do_residual64(h, g->cr, g->cd, g->ct)) return e;
+    std::swap(g->cr, g->ct);
     const double rho_next = 1.0 / (2.0 * sigma - rho);
     if (rz_status e = do_vcycle(h, g->cr, g->cz)) return e;
     launch_scale_copy(rho_next * rho, g->cd, g->cd, n, s);
