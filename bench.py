@@ -438,10 +438,15 @@ def bench_table_hgrad_iter(torch, rz, ctx):
 
 
 # Table hodge-iter, Cartesian columns: (p, l) -> MINRES iterations for k = 1, 2, 3
-PAPER_HODGE_ITER = {(3, 0): (9, 8, 8), (3, 1): (9, 7, 8), (7, 0): (9, 8, 8), (7, 1): (9, 8, 8)}
+PAPER_HODGE_ITER = {(3, 0): (9, 8, 8), (3, 1): (9, 7, 8), (3, 2): (9, 7, 8), (7, 0): (9, 8, 8), (7, 1): (9, 8, 8),
+                    (7, 2): (8, 6, 8)}
+HODGE_CASES = ((3, 0, "direct"), (3, 1, "direct"), (7, 0, "direct"), (7, 1, "direct"))
+# l = 2 (24^3 cells): the dense NCE_1 / NCF_1 inverse would not fit, so the p = 1 problems
+# are solved by the h-multigrid; l = 1 repeated with it for comparison
+HODGE_CASES_HMG = ((3, 1, "hmg"), (3, 2, "hmg"), (7, 2, "hmg"))
 
 
-def bench_hodge(torch, rz, ctx, cases=((3, 0), (3, 1), (7, 0), (7, 1))):
+def bench_hodge(torch, rz, ctx, cases=HODGE_CASES):
     """Mixed Hodge Laplacians (Sec. 5.3, Table hodge-iter, Cartesian columns): no
     essential boundary, right-hand side [0; A_k w] (the Riesz representative of a
     random w in V^k, w from U[-1,1) seed 7; for k = 3 A_3 = M_3 = 8 n^3 I on the unit
@@ -453,13 +458,14 @@ def bench_hodge(torch, rz, ctx, cases=((3, 0), (3, 1), (7, 0), (7, 1))):
     sp_ = ["grad", "curl", "div"]
     out = {"workload": "Table hodge-iter (Cartesian): MINRES, blockdiag Riesz-map preconditioner, "
                        "4 Chebyshev steps per block, natural-norm 1e-8", "rows": []}
-    for p, l in cases:
+    for p, l, coarse in cases:
         n = 6 * 2 ** l
-        row = {"p": p, "l": l, "cells": n ** 3}
+        co = rz.COARSE_HMG if coarse == "hmg" else rz.COARSE_DIRECT
+        row = {"p": p, "l": l, "cells": n ** 3, "coarse": coarse}
         for k in (1, 2, 3):
             t0 = time.time()
-            lo = rz.Problem(ctx, n, p, 1.0, 1.0, space=sp_[k - 1], dirichlet=0)
-            hi = rz.Problem(ctx, n, p, 1.0, 1.0, space=sp_[k], dirichlet=0) if k < 3 else None
+            lo = rz.Problem(ctx, n, p, 1.0, 1.0, space=sp_[k - 1], dirichlet=0, coarse=co)
+            hi = rz.Problem(ctx, n, p, 1.0, 1.0, space=sp_[k], dirichlet=0, coarse=co) if k < 3 else None
             hg = rz.Hodge(k, lo, hi, 4)
             setup_s = time.time() - t0
             w = torch.as_tensor(synth.uniform_pm1(7, hg.n_hi), device="cuda:0")
@@ -479,8 +485,8 @@ def bench_hodge(torch, rz, ctx, cases=((3, 0), (3, 1), (7, 0), (7, 1))):
             if hi is not None:
                 hi.close()
             # the mixed protocol: FP32 relaxation inside the V-cycles, FP64 MINRES
-            lo = rz.Problem(ctx, n, p, 1.0, 1.0, space=sp_[k - 1], dirichlet=0, precision=1)
-            hi = rz.Problem(ctx, n, p, 1.0, 1.0, space=sp_[k], dirichlet=0, precision=1) if k < 3 else None
+            lo = rz.Problem(ctx, n, p, 1.0, 1.0, space=sp_[k - 1], dirichlet=0, precision=1, coarse=co)
+            hi = rz.Problem(ctx, n, p, 1.0, 1.0, space=sp_[k], dirichlet=0, precision=1, coarse=co) if k < 3 else None
             hg = rz.Hodge(k, lo, hi, 4)
             hg.solve(b, x, check=False)
             info = hg.solve(b, x, check=False)
@@ -493,7 +499,7 @@ def bench_hodge(torch, rz, ctx, cases=((3, 0), (3, 1), (7, 0), (7, 1))):
                 hi.close()
         row["paper_k1_k2_k3"] = list(PAPER_HODGE_ITER[(p, l)])
         out["rows"].append(row)
-        log(f"table hodge-iter p={p} l={l}: {row}")
+        log(f"table hodge-iter p={p} l={l} coarse={coarse}: {row}")
     return out
 
 
@@ -952,7 +958,7 @@ def main():
         elif piece == "hmg":
             res = bench_hmg(torch, rz, ctx, args.steps, args.warmup)
         elif piece == "hodge":
-            res = bench_hodge(torch, rz, ctx)
+            res = bench_hodge(torch, rz, ctx, HODGE_CASES + HODGE_CASES_HMG)
         elif piece == "c3-apply":
             pb = rz.Problem(ctx, 16, 6, 1.0, 1.0, space="curl", omega=0.3)
             res["apply_ms_f64"] = time_apply(torch, pb, torch.float64, rz.F64, reps=args.steps)

@@ -159,6 +159,32 @@ def test_hodge_mixed_precision_solve(rz, ctx, k, n, p):
     release(hg, lo, hi)
 
 
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_hodge_hmg_coarse_solve(rz, ctx, k):
+    # the p = 1 problems solved by the h-multigrid (one coarsening at 8^3 without
+    # essential boundary): the solution of the direct solve, and MINRES iterations
+    # within three of the exact coarse solve
+    n, p = (8, 8, 8), 2
+    print(f"hodge hmg k={k} n={n} p={p}", flush=True)
+    sysm = hodge.HodgeSystem(Mesh(*n, dirichlet=0), k, p)
+    b = sysm.rhs()
+    xs = spla.spsolve(sysm.K.tocsc(), b)
+    its = {}
+    for coarse in (rz.COARSE_DIRECT, rz.COARSE_HMG):
+        lo = rz.Problem(ctx, n, p, 1.0, 1.0, space=SPACE[k - 1], dirichlet=0, coarse=coarse)
+        hi = rz.Problem(ctx, n, p, 1.0, 1.0, space=SPACE[k], dirichlet=0, coarse=coarse) if k < 3 else None
+        if coarse == rz.COARSE_HMG:
+            assert len(lo.hmg_levels()) >= 2
+        hg = rz.Hodge(k, lo, hi)
+        x = torch.empty(b.size, dtype=torch.float64, device="cuda:0")
+        info = hg.solve(T(b), x)
+        xg = H(x)
+        assert np.linalg.norm(xg - xs) <= 1e-6 * np.linalg.norm(xs)
+        its[coarse] = info.iters
+        release(hg, lo, hi)
+    assert its[rz.COARSE_HMG] <= its[rz.COARSE_DIRECT] + 3
+
+
 def test_hodge_rejects_bad_arguments(rz, ctx):
     lo = rz.Problem(ctx, 2, 2, 1.0, 1.0, space="div", dirichlet=0)
     hi = rz.Problem(ctx, 2, 2, 1.0, 1.0, space="curl", dirichlet=0)
